@@ -1,0 +1,321 @@
+"""FP64 CPU oracle for the merged-index ε-join (ctypes wrapper of oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may use it; the library under
+``paper_2603_16360_amd`` never does, and shares no code with it.
+
+Every function states the passage of the paper it follows; see oracle.c for
+the readings of the points the paper leaves open.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+METRICS = {"l2": 0, "ip": 1}
+WS = {"self": 0, "soft": 1, "hard": 2}
+HYB = {"off": 0, "force": 1, "adapt": 2, "budget": 3}
+STAT_FIELDS = ("pairs", "n_dist", "n_expanded", "h_pops", "ood", "hybrid",
+               "visited_data", "fragile")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain -O2, no fast-math)."""
+    from .build import build_oracle
+    return build_oracle(verbose=verbose)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        _lib = C.CDLL(_LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+_f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_i64, _int, _dbl = C.c_int64, C.c_int, C.c_double
+
+
+class _Cfg(C.Structure):
+    _fields_ = [("work_sharing", C.c_int32), ("hybrid", C.c_int32),
+                ("hybrid_beam", C.c_int32), ("conv_threshold", C.c_int32),
+                ("ood_ratio", C.c_double), ("uncertain_policy", C.c_int32),
+                ("uncertain_rel", C.c_double), ("shuffle_seed", C.c_uint64),
+                ("fragile_rel", C.c_double)]
+
+
+def _declare(L):
+    L.or_nlj.restype = _i64
+    L.or_nlj.argtypes = [_f32p, _i64, _f32p, _i64, _int, _int, _dbl, _i64, _i32p, _i32p, _f64p]
+    L.or_nlj_counts.restype = None
+    L.or_nlj_counts.argtypes = [_f32p, _i64, _f32p, _i64, _int, _int, _dbl, _i64p]
+    L.or_pair_dists.restype = None
+    L.or_pair_dists.argtypes = [_f32p, _f32p, _int, _int, _i64, _i32p, _i32p, _f64p]
+    L.or_dist_matrix.restype = None
+    L.or_dist_matrix.argtypes = [_f32p, _i64, _f32p, _i64, _int, _int, _f64p]
+    L.or_pooled_kth.restype = _int
+    L.or_pooled_kth.argtypes = [_f32p, _i64, _f32p, _i64, _int, _int, _i64, _i64,
+                                C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.or_knn.restype = None
+    L.or_knn.argtypes = [_f32p, _i64, _int, _int, _i32p, _f64p]
+    L.or_rng_prune.restype = _int
+    L.or_rng_prune.argtypes = [_f32p, _int, _i64, _i32p, _f64p, _int, _int, _i32p]
+    L.or_build_merged.restype = _i64
+    L.or_build_merged.argtypes = [_f32p, _i64, _int, _int, _int, _i32p, _f64p,
+                                  C.POINTER(C.c_int32)]
+    L.or_mst_parents.restype = _dbl
+    L.or_mst_parents.argtypes = [_f32p, _i64, _i64, _int, _i32p, _int, C.c_int32,
+                                 _i32p, _i32p]
+    L.or_join.restype = _i64
+    L.or_join.argtypes = [_f32p, _i64, _i64, _int, _int, _i32p, _int, C.c_int32,
+                          C.c_void_p, _i32p, _i64, _dbl, C.POINTER(_Cfg), C.c_void_p,
+                          _i64, _i32p, _i32p, _f64p, _i32p]
+    L.or_join_self_counts.restype = None
+    L.or_join_self_counts.argtypes = [_f32p, _i64, _i64, _int, _int, _i32p, _int,
+                                      C.c_int32, _i32p, _i64, _dbl, _i64p]
+    L.or_mlp_forward.restype = None
+    L.or_mlp_forward.argtypes = [_int] * 5 + [_f64p] * 7 + [_f64p]
+    L.or_mlp_bce_backward.restype = _dbl
+    L.or_mlp_bce_backward.argtypes = ([_int] * 5 + [_f64p] * 7 + [_f64p, C.c_void_p]
+                                      + [_f64p] * 6)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+# ---------------------------------------------------------------------------
+# O1: Definition 1, the exact join
+# ---------------------------------------------------------------------------
+
+def nlj(Q, X, eps: float, metric: str = "l2"):
+    """Exact join {(i, j): dist(Q_i, X_j) < eps} in (i, j) order.
+
+    Returns (qi int32, xj int32, dist float64)."""
+    Q, X = _f32(Q), _f32(X)
+    L = lib()
+    e = np.empty(0, np.int32)
+    cnt = L.or_nlj(Q, Q.shape[0], X, X.shape[0], Q.shape[1], METRICS[metric], eps,
+                   0, e, e, np.empty(0, np.float64))
+    oq = np.empty(cnt, np.int32)
+    ox = np.empty(cnt, np.int32)
+    od = np.empty(cnt, np.float64)
+    L.or_nlj(Q, Q.shape[0], X, X.shape[0], Q.shape[1], METRICS[metric], eps, cnt,
+             oq, ox, od)
+    return oq, ox, od
+
+
+def nlj_counts(Q, X, eps: float, metric: str = "l2") -> np.ndarray:
+    Q, X = _f32(Q), _f32(X)
+    out = np.empty(Q.shape[0], np.int64)
+    lib().or_nlj_counts(Q, Q.shape[0], X, X.shape[0], Q.shape[1], METRICS[metric],
+                        eps, out)
+    return out
+
+
+def pair_dists(Q, X, qi, xj, metric: str = "l2") -> np.ndarray:
+    """Exact fp64 distance of each listed pair."""
+    Q, X = _f32(Q), _f32(X)
+    qi = np.ascontiguousarray(qi, np.int32)
+    xj = np.ascontiguousarray(xj, np.int32)
+    out = np.empty(qi.shape[0], np.float64)
+    lib().or_pair_dists(Q, X, Q.shape[1], METRICS[metric], qi.shape[0], qi, xj, out)
+    return out
+
+
+def dist_matrix(A, B, metric: str = "l2") -> np.ndarray:
+    A, B = _f32(A), _f32(B)
+    out = np.empty((A.shape[0], B.shape[0]), np.float64)
+    lib().or_dist_matrix(A, A.shape[0], B, B.shape[0], A.shape[1], METRICS[metric], out)
+    return out
+
+
+def pooled_kth(Q, X, k: int, metric: str = "l2", M: int | None = None):
+    """k-th and (k+1)-th smallest of all pooled pair distances (1-based)."""
+    Q, X = _f32(Q), _f32(X)
+    M = M or max(64, min(X.shape[0], 8 * (k // max(1, Q.shape[0]) + 1)))
+    L = lib()
+    while True:
+        vk, vk1 = C.c_double(), C.c_double()
+        rc = L.or_pooled_kth(Q, Q.shape[0], X, X.shape[0], Q.shape[1], METRICS[metric],
+                             k, M, C.byref(vk), C.byref(vk1))
+        if rc == 0 or M >= X.shape[0]:
+            return vk.value, vk1.value
+        if rc == 2:
+            raise MemoryError("or_pooled_kth")
+        M = min(X.shape[0], M * 4)
+
+
+def calibrate_eps(Q, X, target_mean: float, metric: str = "l2",
+                  integer: bool = False) -> float:
+    """ε for a target mean match count over the queries Q (a sample).
+
+    Real-valued data: the midpoint of the k-th and (k+1)-th smallest pooled
+    distances, k = round(target * |Q|).  Integer data (L2): with D_k the k-th
+    smallest squared distance (an integer), ε = sqrt(D_k + 0.5), so that no
+    squared distance ever equals ε².
+    """
+    k = int(round(target_mean * Q.shape[0]))
+    vk, vk1 = pooled_kth(Q, X, k, metric)
+    if integer and metric == "l2":
+        dk = round(vk * vk)
+        return float(np.sqrt(dk + 0.5))
+    return 0.5 * (vk + vk1)
+
+
+# ---------------------------------------------------------------------------
+# O2: merged-graph build (Section 4.3, Appendix C)
+# ---------------------------------------------------------------------------
+
+def knn(V, K: int):
+    V = _f32(V)
+    ids = np.empty((V.shape[0], K), np.int32)
+    dd = np.empty((V.shape[0], K), np.float64)
+    lib().or_knn(V, V.shape[0], V.shape[1], K, ids, dd)
+    return ids, dd
+
+
+def rng_prune(V, u: int, cand, cd, R: int):
+    V = _f32(V)
+    cand = np.ascontiguousarray(cand, np.int32)
+    cd = np.ascontiguousarray(cd, np.float64)
+    out = np.full(R, -1, np.int32)
+    k = lib().or_rng_prune(V, V.shape[1], u, cand, cd, cand.shape[0], R, out)
+    return out[:k]
+
+
+@dataclass
+class Graph:
+    adj: np.ndarray        # [N][R] int32, -1 padded; data ids [0, nx), queries after
+    elen: np.ndarray       # [N][R] float64 edge lengths
+    entry: int
+    repairs: int           # connectivity-repair edges added
+
+
+def build_merged(Q, X, R: int, Kc: int | None = None) -> Graph:
+    """Merged graph over V = [X; Q]: data ids 0..nx-1, query i is node nx+i."""
+    V = np.ascontiguousarray(np.concatenate([_f32(X), _f32(Q)], axis=0))
+    Kc = Kc or 2 * R
+    n = V.shape[0]
+    adj = np.empty((n, R), np.int32)
+    elen = np.empty((n, R), np.float64)
+    ent = C.c_int32()
+    rep = lib().or_build_merged(V, n, V.shape[1], R, Kc, adj, elen, C.byref(ent))
+    return Graph(adj, elen, int(ent.value), int(rep))
+
+
+def mst_parents(Q, X, adj, entry: int):
+    """MST parents of the query nodes (node id, or -1 for the root s), BFS
+    order of query indices, and the total tree weight."""
+    V = np.ascontiguousarray(np.concatenate([_f32(X), _f32(Q)], axis=0))
+    nq, nx = Q.shape[0], X.shape[0]
+    adj = np.ascontiguousarray(adj, np.int32)
+    parent = np.empty(nq, np.int32)
+    order = np.empty(nq, np.int32)
+    w = lib().or_mst_parents(V, nx, nq, V.shape[1], adj, adj.shape[1], entry, parent, order)
+    return parent, order, w
+
+
+# ---------------------------------------------------------------------------
+# O3: the merged-index join (Algorithms 1-8)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class JoinResult:
+    qi: np.ndarray
+    xj: np.ndarray
+    dist: np.ndarray
+    stats: np.ndarray  # [n][8], columns STAT_FIELDS, row i = query_ids[i]
+
+    def pairs(self) -> set:
+        return set(zip(self.qi.tolist(), self.xj.tolist()))
+
+
+def join(Q, X, adj, entry: int, eps: float, metric: str = "l2", query_ids=None,
+         work_sharing: str = "self", hybrid: str = "off", hybrid_beam: int = 256,
+         conv_threshold: int = 10, ood_ratio: float = 1.5, parent=None,
+         budget=None, uncertain: str = "plain", uncertain_rel: float = 1e-5,
+         shuffle_seed: int = 0, fragile_rel: float | None = None) -> JoinResult:
+    V = np.ascontiguousarray(np.concatenate([_f32(X), _f32(Q)], axis=0))
+    nq, nx, d = Q.shape[0], X.shape[0], Q.shape[1]
+    adj = np.ascontiguousarray(adj, np.int32)
+    R = adj.shape[1]
+    qids = np.arange(nq, dtype=np.int32) if query_ids is None else np.ascontiguousarray(query_ids, np.int32)
+    n = qids.shape[0]
+    cfg = _Cfg(WS[work_sharing], HYB[hybrid], hybrid_beam, conv_threshold, ood_ratio,
+               {"plain": 0, "out": 1, "in": 2}[uncertain], uncertain_rel, shuffle_seed,
+               4.0 * d * 2.0 ** -24 if fragile_rel is None else fragile_rel)
+    par = None
+    if work_sharing != "self":
+        if parent is None:
+            raise ValueError("work sharing needs MST parents")
+        par = np.ascontiguousarray(parent, np.int32)
+    bud = None
+    if hybrid == "budget":
+        bud = np.ascontiguousarray(budget, np.int32)
+        assert bud.shape[0] == n
+    stats = np.zeros((n, len(STAT_FIELDS)), np.int32)
+    L = lib()
+    args = (V, nx, nq, d, METRICS[metric], adj, R, entry,
+            par.ctypes.data if par is not None else None, qids, n, eps, C.byref(cfg),
+            bud.ctypes.data if bud is not None else None)
+    e32, e64 = np.empty(0, np.int32), np.empty(0, np.float64)
+    cnt = L.or_join(*args, 0, e32, e32, e64, stats)
+    oq, ox, od = np.empty(cnt, np.int32), np.empty(cnt, np.int32), np.empty(cnt, np.float64)
+    L.or_join(*args, cnt, oq, ox, od, stats)
+    return JoinResult(oq, ox, od, stats)
+
+
+def join_self_counts(Q, X, adj, entry: int, eps: float, metric: str = "l2",
+                     query_ids=None) -> np.ndarray:
+    """Per-query match counts of the self-mode BFS join, OpenMP over queries
+    (the same steps as ``join`` in self/off mode; used for CPU timing)."""
+    V = np.ascontiguousarray(np.concatenate([_f32(X), _f32(Q)], axis=0))
+    nq, nx, d = Q.shape[0], X.shape[0], Q.shape[1]
+    adj = np.ascontiguousarray(adj, np.int32)
+    qids = np.arange(nq, dtype=np.int32) if query_ids is None else np.ascontiguousarray(query_ids, np.int32)
+    out = np.empty(qids.shape[0], np.int64)
+    lib().or_join_self_counts(V, nx, nq, d, METRICS[metric], adj, adj.shape[1], entry,
+                              qids, qids.shape[0], eps, out)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# O5: the difficulty MLP in fp64
+# ---------------------------------------------------------------------------
+
+def mlp_forward(params, Xin):
+    W1, b1, W2, b2, W3, b3 = [np.ascontiguousarray(p, np.float64) for p in params]
+    Xin = np.ascontiguousarray(Xin, np.float64)
+    n, din = Xin.shape
+    out = np.empty((n, W3.shape[0]), np.float64)
+    lib().or_mlp_forward(n, din, W1.shape[0], W2.shape[0], W3.shape[0], Xin,
+                         W1, b1, W2, b2, W3, b3, out)
+    return out
+
+
+def mlp_bce_backward(params, Xin, Y, mask=None):
+    """(loss, [gW1, gb1, gW2, gb2, gW3, gb3]) of mean BCE-with-logits."""
+    W1, b1, W2, b2, W3, b3 = [np.ascontiguousarray(p, np.float64) for p in params]
+    Xin = np.ascontiguousarray(Xin, np.float64)
+    Y = np.ascontiguousarray(Y, np.float64)
+    n, din = Xin.shape
+    m = None if mask is None else np.ascontiguousarray(mask, np.float64)
+    grads = [np.empty_like(p) for p in (W1, b1, W2, b2, W3, b3)]
+    loss = lib().or_mlp_bce_backward(n, din, W1.shape[0], W2.shape[0], W3.shape[0], Xin,
+                                     W1, b1, W2, b2, W3, b3, Y,
+                                     m.ctypes.data if m is not None else None, *grads)
+    return loss, grads
