@@ -1,0 +1,186 @@
+/*
+ * vj.h -- C ABI of the MI355X merged-index vector-join library (libvj.so).
+ *
+ * Problem (paper, Definition 1): given a query set Q, a data set X, a
+ * distance dist and a threshold eps, the vector join is the set of pairs
+ * (q, x) with dist(q, x) < eps.  The approximate join of the paper (Section
+ * 4) indexes Q and X together in ONE proximity graph (the merged index,
+ * Section 4.3) and answers every query by probing its own neighbourhood and
+ * expanding in-range neighbours (Algorithms 1-8).
+ *
+ * Conventions for every call:
+ *  - Array arguments are DEVICE pointers (HIP device memory of the current
+ *    device, e.g. torch CUDA tensors) unless the name ends in _host.
+ *    Vectors are float32, row-major [rows][d].
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is queued
+ *    on it; calls that must return a size to the host (the pair count)
+ *    synchronise that stream before returning.
+ *  - Node ids of an index: data rows are 0..nx-1, query rows nx..nx+nq-1.
+ *    Pairs are reported as (query index 0..nq-1, data index 0..nx-1).
+ *  - Metrics: VJ_L2 is the unsquared Euclidean distance ||q - x||;
+ *    VJ_IP is 1 - <q, x>.  The predicate is strict: dist < eps.
+ *  - Errors: every call returns a vj_status; on error nothing is written to
+ *    the outputs and vj_last_error() (per thread) describes the failure.
+ *    No C++ exception crosses this boundary.
+ *  - Ownership: objects returned through vj_index ** / vj_pairs ** belong
+ *    to the caller and are released with vj_index_free / vj_pairs_free.
+ *    Indexes copy their inputs; the caller may free them on return.
+ *  - Every call works on the device that is current on the calling thread.
+ */
+#ifndef VJ_H
+#define VJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VJ_OK = 0,
+    VJ_ERR_INVALID_ARG = 1,     /* null pointer, negative size, d <= 0, eps NaN, ids out of range */
+    VJ_ERR_METRIC_MISMATCH = 2, /* join metric differs from the index metric */
+    VJ_ERR_OOM = 3,             /* device allocation failed */
+    VJ_ERR_HIP = 4,             /* a HIP runtime call failed */
+    VJ_ERR_INTERNAL = 5,        /* a kernel reported an inconsistency */
+    VJ_ERR_UNSUPPORTED = 6      /* shape outside the supported range (see each call) */
+} vj_status;
+
+typedef enum { VJ_L2 = 0, VJ_IP = 1 } vj_metric;
+
+/* Work-sharing mode (cfg.work_sharing, Algorithms 3 and 8). */
+typedef enum {
+    VJ_WS_SELF = 0, /* seeds {s, q}: the merged-index default (MI) */
+    VJ_WS_SOFT = 1, /* + the parent query's closest visited data node (SWS) */
+    VJ_WS_HARD = 2  /* + every in-range node the parent found (HWS) */
+} vj_work_sharing;
+
+/* Expansion mode (cfg.force_hybrid / cfg.adapt_hybrid, Algorithms 6-7). */
+typedef enum {
+    VJ_HYB_OFF = 0,    /* BFS over in-range data nodes only */
+    VJ_HYB_FORCE = 1,  /* hybrid search for every query */
+    VJ_HYB_ADAPT = 2,  /* hybrid only for queries predicted OOD (d1/d2 > ratio) */
+    VJ_HYB_BUDGET = 3, /* hybrid with a per-query cap on out-range pops (budget[]) */
+    VJ_HYB_LEARNED = 4 /* budgets chosen by the index's attached predictor */
+} vj_hybrid;
+
+/* Arithmetic of the distance evaluations. */
+typedef enum {
+    VJ_PREC_FP32 = 0, /* fp32 inputs, fp32 accumulation */
+    VJ_PREC_BF16 = 1, /* bf16 copy, fp32 accumulation, fp32 re-check near eps */
+    VJ_PREC_FP8 = 2,  /* e4m3 copy (per-row scale), fp32 re-check near eps */
+    VJ_PREC_U8 = 3,   /* exact u8 copy (integer data in [0, 255] only) */
+    VJ_PREC_AUTO = 4  /* u8 if the index data is exactly u8, else fp32 */
+} vj_precision;
+
+typedef struct vj_index vj_index;
+typedef struct vj_pairs vj_pairs;
+
+typedef struct {
+    int32_t R;           /* max out-degree, 1..64 */
+    int32_t K_cand;      /* exact-kNN candidates per node before pruning (0: 2R) */
+    int32_t build_mst;   /* 1: compute the query MST (needed for SOFT/HARD) */
+    int32_t copies;      /* bit mask of low-precision copies: 1 bf16, 2 fp8, 4 u8 */
+} vj_build_params;
+
+typedef struct {
+    int32_t work_sharing;   /* vj_work_sharing */
+    int32_t hybrid;         /* vj_hybrid */
+    int32_t hybrid_beam;    /* bound on the out-range queue (default 256) */
+    int32_t conv_threshold; /* stop after this many unproductive out-range pops (10; <=0: none) */
+    float ood_ratio;        /* d1/d2 threshold of VJ_HYB_ADAPT (1.5) */
+    int32_t precision;      /* vj_precision */
+    const int32_t *budget;  /* device [n]: out-range pops allowed (VJ_HYB_BUDGET); <0: brute force */
+    int32_t hash_log2;      /* per-query visited-set slots = 2^hash_log2 (0: auto) */
+    int32_t waves_per_cu;   /* persistent waves per compute unit (0: auto) */
+    int64_t pair_capacity;  /* initial result capacity hint (0: auto) */
+} vj_join_params;
+
+void vj_default_build_params(vj_build_params *p);
+void vj_default_join_params(vj_join_params *p);
+
+/*
+ * Build the merged index over Q and X (Section 4.3: one graph over both
+ * sets, per-node set label = id < nx).  Q: [nq][d], X: [nx][d] float32.
+ * Graph: exact kNN candidates (MFMA tiles) -> RNG edge rule (Appendix C) ->
+ * reverse edges -> entry nearest the centroid -> connectivity repair ->
+ * edge lengths -> query MST (Section 3.2).  The graph is always built on L2
+ * geometry; `metric` is the metric joins must use (for VJ_IP the rows
+ * should be unit-norm, where L2 and IP orders coincide).
+ * Limits: 1 <= d <= 1024, nq + nx < 2^31, 1 <= R <= 64.
+ */
+vj_status vj_build_merged_index(const float *Q, int64_t nq, const float *X, int64_t nx,
+                                int32_t d, vj_metric metric, const vj_build_params *p,
+                                void *stream, vj_index **out);
+
+/*
+ * Wrap a graph built elsewhere (the paper treats the index as a black box,
+ * e.g. NSG or HNSW) as a merged index.  adj: [nq+nx][R] int32 node ids,
+ * -1 padded; entry: entry node id.  parent: [nq] MST parent node ids (-1 =
+ * the entry is the parent) or NULL to compute the MST here.  Edge lengths
+ * are computed here.  Same limits as vj_build_merged_index.
+ */
+vj_status vj_index_from_graph(const float *Q, int64_t nq, const float *X, int64_t nx,
+                              int32_t d, vj_metric metric, const int32_t *adj, int32_t R,
+                              int32_t entry, const int32_t *parent, void *stream,
+                              vj_index **out);
+
+/* Copy the graph out: adj [N][R] int32, elen [N][R] float32 (either may be
+ * NULL), parent [nq] int32 (may be NULL; -1 = entry).  Device pointers. */
+vj_status vj_index_export_graph(const vj_index *idx, int32_t *adj, float *elen,
+                                int32_t *parent, void *stream);
+
+/* Scalar facts of an index (any pointer may be NULL). */
+vj_status vj_index_info(const vj_index *idx, int64_t *nq, int64_t *nx, int32_t *d,
+                        int32_t *R, int32_t *entry, int32_t *metric);
+
+void vj_index_free(vj_index *idx);
+
+/*
+ * The merged-index join (Algorithm 1 with cfg.merged = true) of the queries
+ * query_ids[0..n) (indices into Q; NULL = all nq queries in order) at
+ * threshold eps.  In SOFT/HARD mode queries are processed parents-first
+ * along the MST; a query whose MST parent is not in this call gets no
+ * cached seed.  eps <= 0 (L2) returns an empty result.  Each query runs on
+ * one wavefront of a persistent kernel.
+ */
+vj_status vj_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
+                  vj_metric metric, const vj_join_params *p, void *stream,
+                  vj_pairs **out);
+
+/*
+ * Exact nested-loop join (the NLJ of Section 2.2) on MFMA tiles: every
+ * pair with dist < eps.  Distances are evaluated in bf16 (one term, or a
+ * three-term hi/lo split for prec = VJ_PREC_FP32) with fp32 accumulation;
+ * every pair whose tile value lies within a proven error bound of eps is
+ * re-decided from the fp32 inputs in fp64, so the result equals the exact
+ * fp64 decision.  Limits: 1 <= d <= 1024.
+ */
+vj_status vj_bruteforce_join(const float *Q, int64_t nq, const float *X, int64_t nx,
+                             int32_t d, float eps, vj_metric metric, vj_precision prec,
+                             void *stream, vj_pairs **out);
+
+/* Number of pairs held by a result. */
+int64_t vj_pairs_count(const vj_pairs *r);
+
+/* Write the pairs: qx [count][2] int32 (query index, data index), dist
+ * [count] float32 (may be NULL).  sorted != 0 orders by (query, data). */
+vj_status vj_pairs_export(const vj_pairs *r, int32_t *qx, float *dist, int sorted,
+                          void *stream);
+
+/* Per-query counters of a vj_join result, [n][8] int32 in the order of
+ * query_ids: pairs, distance evaluations, expanded nodes, out-range pops,
+ * predicted OOD, hybrid used, distinct data nodes visited, flags
+ * (bit 0: re-run on the spill path, bit 1: routed to brute force). */
+vj_status vj_pairs_stats(const vj_pairs *r, int32_t *stats, void *stream);
+
+void vj_pairs_free(vj_pairs *r);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *vj_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VJ_H */

@@ -1,0 +1,250 @@
+// Small device helpers of the index and the result: padded copies, exact u8
+// and bf16 copies, edge lengths, id bookkeeping and the pair export.
+#include <cstring>
+
+#include <rocprim/rocprim.hpp>
+
+#include "vj_internal.h"
+#include "util.h"
+
+namespace vj {
+
+namespace {
+
+__global__ void k_pad_rows(const float *src, int64_t rows, int d, float *dst, int dp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = rows * (int64_t)dp;
+    if (i >= total) return;
+    const int64_t r = i / dp;
+    const int c = (int)(i - r * dp);
+    dst[i] = c < d ? src[r * d + c] : 0.0f;
+}
+
+// bf16 by round-to-nearest-even of the fp32 bits
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ void k_quantize(const float *vec, int64_t n, uint8_t *u8, uint16_t *bf, int32_t *flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float f = vec[i];
+    if (u8) {
+        const float r = rintf(f);
+        const bool ok = r == f && f >= 0.0f && f <= 255.0f;
+        if (!ok) atomicOr(flag, 1);
+        u8[i] = ok ? (uint8_t)r : 0;
+    }
+    if (bf) bf[i] = to_bf16(f);
+}
+
+// one 64-thread block per node; thread j handles edge j (R <= 64)
+__global__ void k_edge_lengths(const float *vec, int dp, const int32_t *adj, int64_t N, int R,
+                               float *elen) {
+    const int64_t u = blockIdx.x;
+    const int j = threadIdx.x;
+    if (u >= N || j >= R) return;
+    const int32_t v = adj[u * R + j];
+    if (v < 0 || v >= N) { elen[u * R + j] = INFINITY; return; }
+    const float4 *a = reinterpret_cast<const float4 *>(vec + u * dp);
+    const float4 *b = reinterpret_cast<const float4 *>(vec + (int64_t)v * dp);
+    float acc = 0.f;
+    for (int c = 0; c < dp / 4; ++c) {
+        const float4 x = a[c], y = b[c];
+        float t;
+        t = x.x - y.x; acc = fmaf(t, t, acc);
+        t = x.y - y.y; acc = fmaf(t, t, acc);
+        t = x.z - y.z; acc = fmaf(t, t, acc);
+        t = x.w - y.w; acc = fmaf(t, t, acc);
+    }
+    elen[u * R + j] = sqrtf(acc);
+}
+
+// L2 distance of rows [first, first+n) to row `node`
+__global__ void k_dist_to_node(const float *vec, int dp, int64_t first, int64_t n, int32_t node,
+                               float *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 *a = reinterpret_cast<const float4 *>(vec + (first + i) * dp);
+    const float4 *b = reinterpret_cast<const float4 *>(vec + (int64_t)node * dp);
+    float acc = 0.f;
+    for (int c = 0; c < dp / 4; ++c) {
+        const float4 x = a[c], y = b[c];
+        float t;
+        t = x.x - y.x; acc = fmaf(t, t, acc);
+        t = x.y - y.y; acc = fmaf(t, t, acc);
+        t = x.z - y.z; acc = fmaf(t, t, acc);
+        t = x.w - y.w; acc = fmaf(t, t, acc);
+    }
+    out[i] = sqrtf(acc);
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_iota(int32_t *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
+}
+
+__global__ void k_stamp(int32_t *inb, int64_t nq, const int32_t *ids, int64_t n, int32_t gen,
+                        int32_t *err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t q = ids ? ids[i] : (int32_t)i;
+    if (q < 0 || q >= nq) { atomicOr(err, 8); return; }
+    inb[q] = gen;
+}
+
+__global__ void k_depth_keys(const int32_t *depth, int64_t nq, const int32_t *ids, int64_t n,
+                             int32_t *keys, int32_t *pos) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t q = ids ? ids[i] : (int32_t)i;
+    keys[i] = (q >= 0 && q < nq) ? depth[q] : 0;
+    pos[i] = (int32_t)i;
+}
+
+__global__ void k_gather_ids(const int32_t *ids, const int32_t *pos, int64_t n, int32_t *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = ids ? ids[pos[i]] : pos[i];
+}
+
+__global__ void k_gather_slots(const int32_t *qlist, const int32_t *qpos, const int32_t *slots,
+                               int64_t n, int32_t *q2, int32_t *p2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    q2[i] = qlist[slots[i]];
+    p2[i] = qpos[slots[i]];
+}
+
+__global__ void k_pack_keys(const int32_t *q, const int32_t *x, int64_t n, uint64_t *key) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) key[i] = ((uint64_t)(uint32_t)q[i] << 32) | (uint32_t)x[i];
+}
+
+__global__ void k_unpack_keys(const uint64_t *key, int64_t n, int32_t *qx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    qx[2 * i] = (int32_t)(key[i] >> 32);
+    qx[2 * i + 1] = (int32_t)(uint32_t)key[i];
+}
+
+__global__ void k_interleave(const int32_t *q, const int32_t *x, int64_t n, int32_t *qx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    qx[2 * i] = q[i];
+    qx[2 * i + 1] = x[i];
+}
+
+inline unsigned grid1(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+int num_cus() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) != hipSuccess) return 256;
+        cached[dev] = p.multiProcessorCount;
+    }
+    return cached[dev];
+}
+
+void launch_pad_rows(const float *src, int64_t rows, int d, float *dst, int dp, hipStream_t s) {
+    const int64_t n = rows * (int64_t)dp;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_pad_rows, dim3(grid1(n)), dim3(256), 0, s, src, rows, d, dst, dp);
+}
+
+void launch_quantize(const float *vec, int64_t rows, int dp, uint8_t *u8, uint16_t *bf16,
+                     int32_t *flag, hipStream_t s) {
+    const int64_t n = rows * (int64_t)dp;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_quantize, dim3(grid1(n)), dim3(256), 0, s, vec, n, u8, bf16, flag);
+}
+
+void launch_edge_lengths(const float *vec, int dp, const int32_t *adj, int64_t N, int R,
+                         float *elen, hipStream_t s) {
+    if (N == 0) return;
+    hipLaunchKernelGGL(k_edge_lengths, dim3((unsigned)N), dim3(64), 0, s, vec, dp, adj, N, R, elen);
+}
+
+void launch_dist_to_node(const float *vec, int dp, int64_t first, int64_t n, int32_t node,
+                         float *out, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_dist_to_node, dim3(grid1(n)), dim3(256), 0, s, vec, dp, first, n, node, out);
+}
+
+void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid1(n)), dim3(256), 0, s, p, n, v);
+}
+
+void iota_i32(int32_t *p, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_iota, dim3(grid1(n)), dim3(256), 0, s, p, n);
+}
+
+void stamp_batch(int32_t *inb, int64_t nq, const int32_t *ids, int64_t n, int32_t gen,
+                 int32_t *err, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_stamp, dim3(grid1(n)), dim3(256), 0, s, inb, nq, ids, n, gen, err);
+}
+
+void gather_slots(const int32_t *qlist, const int32_t *qpos, const int32_t *slots, int64_t n,
+                  int32_t *q2, int32_t *p2, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gather_slots, dim3(grid1(n)), dim3(256), 0, s, qlist, qpos, slots, n, q2, p2);
+}
+
+// processing order parents-first: stable sort of caller positions by MST depth
+void order_by_depth(const int32_t *depth, int64_t nq, const int32_t *ids, int64_t n,
+                    int32_t *qlist, int32_t *qpos, DevBuf &tmp, hipStream_t s) {
+    if (n == 0) return;
+    DevBuf keys(n * sizeof(int32_t)), keys2(n * sizeof(int32_t)), pos(n * sizeof(int32_t));
+    hipLaunchKernelGGL(k_depth_keys, dim3(grid1(n)), dim3(256), 0, s, depth, nq, ids, n,
+                       keys.as<int32_t>(), pos.as<int32_t>());
+    size_t bytes = 0;
+    VJ_HIP(rocprim::radix_sort_pairs(nullptr, bytes, keys.as<int32_t>(), keys2.as<int32_t>(),
+                                     pos.as<int32_t>(), qpos, (size_t)n, 0, 31, s));
+    tmp.reserve(bytes);
+    VJ_HIP(rocprim::radix_sort_pairs(tmp.p, bytes, keys.as<int32_t>(), keys2.as<int32_t>(),
+                                     pos.as<int32_t>(), qpos, (size_t)n, 0, 31, s));
+    hipLaunchKernelGGL(k_gather_ids, dim3(grid1(n)), dim3(256), 0, s, ids, qpos, n, qlist);
+    VJ_HIP(hipStreamSynchronize(s));  // the temporaries above are freed on return
+}
+
+void export_pairs(const Pairs &r, int32_t *qx, float *dist, bool sorted, hipStream_t s) {
+    const int64_t n = r.count;
+    if (n == 0) return;
+    if (!sorted) {
+        hipLaunchKernelGGL(k_interleave, dim3(grid1(n)), dim3(256), 0, s, r.q.as<int32_t>(),
+                           r.x.as<int32_t>(), n, qx);
+        if (dist) VJ_HIP(hipMemcpyAsync(dist, r.dist.p, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+        return;
+    }
+    DevBuf k1(n * 8), k2(n * 8), v2(n * sizeof(float)), tmp;
+    hipLaunchKernelGGL(k_pack_keys, dim3(grid1(n)), dim3(256), 0, s, r.q.as<int32_t>(),
+                       r.x.as<int32_t>(), n, k1.as<uint64_t>());
+    size_t bytes = 0;
+    VJ_HIP(rocprim::radix_sort_pairs(nullptr, bytes, k1.as<uint64_t>(), k2.as<uint64_t>(),
+                                     r.dist.as<float>(), v2.as<float>(), (size_t)n, 0, 64, s));
+    tmp.alloc(bytes);
+    VJ_HIP(rocprim::radix_sort_pairs(tmp.p, bytes, k1.as<uint64_t>(), k2.as<uint64_t>(),
+                                     r.dist.as<float>(), v2.as<float>(), (size_t)n, 0, 64, s));
+    hipLaunchKernelGGL(k_unpack_keys, dim3(grid1(n)), dim3(256), 0, s, k2.as<uint64_t>(), n, qx);
+    if (dist) VJ_HIP(hipMemcpyAsync(dist, v2.p, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    VJ_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
+}
+
+}  // namespace vj

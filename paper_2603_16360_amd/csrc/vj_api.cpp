@@ -1,0 +1,604 @@
+// C ABI of libvj: argument checks, index objects, the join driver and the
+// result objects.  Every entry point converts internal errors to vj_status.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "build.h"
+#include "tiles.h"
+#include "util.h"
+#include "vj_internal.h"
+
+struct vj_index { vj::Index impl; };
+struct vj_pairs { vj::Pairs impl; };
+
+namespace vj {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+const char *last_error() { return g_err.c_str(); }
+
+int padded_dim(int d) {
+    static const int dims[] = {32, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
+    for (int x : dims)
+        if (d <= x) return x;
+    return -1;
+}
+
+static int ceil_log2(int64_t v) {
+    int l = 0;
+    while ((int64_t(1) << l) < v) ++l;
+    return l;
+}
+
+// ----------------------------------------------------------------- index --
+
+// copy + pad the vectors, exact low-precision copies, join state
+static void init_vectors(Index &ix, const float *Q, const float *X, hipStream_t s) {
+    ix.vec.alloc((size_t)ix.N * ix.dp * sizeof(float));
+    launch_pad_rows(X, ix.nx, ix.d, ix.vec.as<float>(), ix.dp, s);
+    launch_pad_rows(Q, ix.nq, ix.d, ix.vec.as<float>() + (size_t)ix.nx * ix.dp, ix.dp, s);
+    DevBuf flag(sizeof(int32_t));
+    VJ_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+    ix.vec_u8.alloc((size_t)ix.N * ix.dp);
+    launch_quantize(ix.vec.as<float>(), ix.N, ix.dp, ix.vec_u8.as<uint8_t>(), nullptr,
+                    flag.as<int32_t>(), s);
+    int32_t h = 0;
+    VJ_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    ix.integer_u8 = (h == 0);
+    if (!ix.integer_u8) ix.vec_u8.release();
+    const size_t nq = (size_t)std::max<int64_t>(ix.nq, 1);
+    ix.pub.alloc(nq * sizeof(unsigned long long));
+    ix.inb.alloc(nq * sizeof(int32_t));
+    ix.seg.alloc(nq * sizeof(int64_t));
+    ix.segn.alloc(nq * sizeof(int32_t));
+    VJ_HIP(hipMemsetAsync(ix.pub.p, 0, ix.pub.bytes, s));
+    VJ_HIP(hipMemsetAsync(ix.inb.p, 0, ix.inb.bytes, s));
+    VJ_HIP(hipMemsetAsync(ix.seg.p, 0, ix.seg.bytes, s));
+    VJ_HIP(hipMemsetAsync(ix.segn.p, 0, ix.segn.bytes, s));
+}
+
+void ensure_bf16(Index &ix, hipStream_t s) {
+    if (ix.vec_bf16.p) return;
+    ix.vec_bf16.alloc((size_t)ix.N * ix.dp * sizeof(uint16_t));
+    launch_quantize(ix.vec.as<float>(), ix.N, ix.dp, nullptr, ix.vec_bf16.as<uint16_t>(),
+                    nullptr, s);
+}
+
+// MST over the query nodes plus (s, q) edges, rooted at s (Section 3.2);
+// Kruskal with ties on (w, min id, max id); weights are fp32 L2 lengths.
+void compute_mst(Index &ix, hipStream_t s) {
+    const int64_t nq = ix.nq, nx = ix.nx;
+    const int R = ix.R;
+    std::vector<int32_t> adjq((size_t)nq * R);
+    std::vector<float> elq((size_t)nq * R), ds((size_t)nq);
+    if (nq > 0) {
+        VJ_HIP(hipMemcpyAsync(adjq.data(), ix.adj.as<int32_t>() + (size_t)nx * R,
+                              adjq.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipMemcpyAsync(elq.data(), ix.elen.as<float>() + (size_t)nx * R,
+                              elq.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+        DevBuf dd((size_t)nq * sizeof(float));
+        launch_dist_to_node(ix.vec.as<float>(), ix.dp, nx, nq, ix.entry, dd.as<float>(), s);
+        VJ_HIP(hipMemcpyAsync(ds.data(), dd.p, ds.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipStreamSynchronize(s));
+    }
+    struct E { float w; int32_t a, b; };
+    std::vector<E> es;
+    es.reserve((size_t)nq * (R + 1));
+    const int32_t sn = ix.entry;
+    for (int64_t i = 0; i < nq; ++i) {
+        const int32_t u = (int32_t)(nx + i);
+        for (int j = 0; j < R; ++j) {
+            const int32_t v = adjq[(size_t)i * R + j];
+            if (v < nx || v == u) continue;
+            es.push_back({elq[(size_t)i * R + j], std::min(u, v), std::max(u, v)});
+        }
+        if (u != sn) es.push_back({ds[i], std::min(u, sn), std::max(u, sn)});
+    }
+    std::sort(es.begin(), es.end(), [](const E &x, const E &y) {
+        if (x.w != y.w) return x.w < y.w;
+        if (x.a != y.a) return x.a < y.a;
+        return x.b < y.b;
+    });
+    // vertices: query indices 0..nq-1, plus slot nq for s when s is a data node
+    auto vid = [&](int32_t node) -> int64_t { return node >= nx ? node - nx : nq; };
+    std::vector<int64_t> uf((size_t)nq + 1);
+    std::iota(uf.begin(), uf.end(), 0);
+    auto find = [&](int64_t x) {
+        while (uf[x] != x) { uf[x] = uf[uf[x]]; x = uf[x]; }
+        return x;
+    };
+    std::vector<std::vector<int32_t>> tree((size_t)nq + 1);
+    for (const E &e : es) {
+        int64_t ra = find(vid(e.a)), rb = find(vid(e.b));
+        if (ra == rb) continue;
+        uf[std::max(ra, rb)] = std::min(ra, rb);
+        tree[vid(e.a)].push_back(e.b);
+        tree[vid(e.b)].push_back(e.a);
+    }
+    std::vector<int32_t> parent((size_t)std::max<int64_t>(nq, 1), -1), depth((size_t)std::max<int64_t>(nq, 1), 0);
+    std::vector<uint8_t> seen((size_t)nq + 1, 0);
+    std::vector<int32_t> queue;
+    queue.reserve((size_t)nq + 1);
+    queue.push_back(sn);
+    seen[vid(sn)] = 1;
+    for (size_t h = 0; h < queue.size(); ++h) {
+        const int32_t u = queue[h];
+        auto &kids = tree[vid(u)];
+        std::sort(kids.begin(), kids.end());
+        for (int32_t v : kids) {
+            if (seen[vid(v)]) continue;
+            seen[vid(v)] = 1;
+            const int64_t qi = v - nx;
+            parent[qi] = (u == sn) ? -1 : u;
+            depth[qi] = (u == sn) ? 0 : depth[u - nx] + 1;
+            queue.push_back(v);
+        }
+    }
+    ix.parent.alloc((size_t)std::max<int64_t>(nq, 1) * sizeof(int32_t));
+    ix.depth.alloc((size_t)std::max<int64_t>(nq, 1) * sizeof(int32_t));
+    VJ_HIP(hipMemcpyAsync(ix.parent.p, parent.data(), (size_t)nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    VJ_HIP(hipMemcpyAsync(ix.depth.p, depth.data(), (size_t)nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    ix.has_mst = true;
+}
+
+static void set_parents(Index &ix, const int32_t *parent, hipStream_t s) {
+    const int64_t nq = ix.nq;
+    std::vector<int32_t> par((size_t)std::max<int64_t>(nq, 1), -1), depth((size_t)std::max<int64_t>(nq, 1), -1);
+    if (nq > 0) {
+        VJ_HIP(hipMemcpyAsync(par.data(), parent, (size_t)nq * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipStreamSynchronize(s));
+    }
+    for (int64_t i = 0; i < nq; ++i) {
+        const int32_t p = par[i];
+        VJ_CHECK(p == -1 || (p >= ix.nx && p < ix.N && p != ix.nx + i), VJ_ERR_INVALID_ARG,
+                 "parent ids must be query node ids or -1");
+    }
+    // depth by walking up (the parents must form a forest rooted at the entry)
+    for (int64_t i = 0; i < nq; ++i) {
+        std::vector<int64_t> chain;
+        int64_t c = i;
+        while (c >= 0 && depth[c] < 0) {
+            chain.push_back(c);
+            VJ_CHECK((int64_t)chain.size() <= nq, VJ_ERR_INVALID_ARG, "parent ids contain a cycle");
+            c = par[c] >= 0 ? par[c] - ix.nx : -1;
+        }
+        int32_t d0 = c >= 0 ? depth[c] : -1;
+        for (auto it = chain.rbegin(); it != chain.rend(); ++it) depth[*it] = ++d0;
+    }
+    ix.parent.alloc((size_t)std::max<int64_t>(nq, 1) * sizeof(int32_t));
+    ix.depth.alloc((size_t)std::max<int64_t>(nq, 1) * sizeof(int32_t));
+    VJ_HIP(hipMemcpyAsync(ix.parent.p, par.data(), (size_t)nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    VJ_HIP(hipMemcpyAsync(ix.depth.p, depth.data(), (size_t)nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    ix.has_mst = true;
+}
+
+static void check_shape(const float *Q, int64_t nq, const float *X, int64_t nx, int32_t d) {
+    VJ_CHECK(nq >= 0 && nx >= 1, VJ_ERR_INVALID_ARG, "need nq >= 0 and nx >= 1");
+    VJ_CHECK(X != nullptr && (nq == 0 || Q != nullptr), VJ_ERR_INVALID_ARG, "null vector pointer");
+    VJ_CHECK(d >= 1, VJ_ERR_INVALID_ARG, "d must be >= 1");
+    VJ_CHECK(d <= 1024, VJ_ERR_UNSUPPORTED, "d must be <= 1024");
+    VJ_CHECK(nq + nx < ((int64_t)1 << 31) - 1, VJ_ERR_UNSUPPORTED, "nq + nx must be < 2^31 - 1");
+}
+
+// ------------------------------------------------------------------ join --
+
+struct JoinScratch {
+    DevBuf qlist, qpos, q2, p2, sorttmp;
+    DevBuf il_id, il_d, ghash, gstamp, ovf, counters;
+    DevBuf out_q, out_x, out_d;
+};
+
+static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const vj_join_params &p,
+                     const int32_t *budget, hipStream_t s, Pairs &r) {
+    const int ws = p.work_sharing, hyb = p.hybrid;
+    int prec = p.precision;
+    if (prec == VJ_PREC_AUTO) prec = ix.integer_u8 ? VJ_PREC_U8 : VJ_PREC_FP32;
+    VJ_CHECK(prec != VJ_PREC_U8 || ix.integer_u8, VJ_ERR_INVALID_ARG,
+             "u8 precision needs integer data in [0, 255]");
+    VJ_CHECK(prec == VJ_PREC_FP32 || prec == VJ_PREC_U8, VJ_ERR_UNSUPPORTED,
+             "precision not supported by the traversal");
+
+    JoinScratch sc;
+    const int wpb = 4;
+    const int hl = p.hash_log2 > 0 ? p.hash_log2 : 11;
+    VJ_CHECK(hl >= 6 && hl <= 14, VJ_ERR_INVALID_ARG, "hash_log2 must be in [6, 14]");
+    const int wpc = p.waves_per_cu > 0 ? p.waves_per_cu : 16;
+    const int max_blocks0 = std::max(1, num_cus() * std::max(1, wpc / wpb));
+    const int beam = (hyb != VJ_HYB_OFF) ? p.hybrid_beam : 0;
+
+    sc.qlist.alloc(n * sizeof(int32_t));
+    sc.qpos.alloc(n * sizeof(int32_t));
+    if (ws == VJ_WS_SELF) {
+        if (ids) VJ_HIP(hipMemcpyAsync(sc.qlist.p, ids, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        else iota_i32(sc.qlist.as<int32_t>(), n, s);
+        iota_i32(sc.qpos.as<int32_t>(), n, s);
+    } else {
+        order_by_depth(ix.depth.as<int32_t>(), ix.nq, ids, n, sc.qlist.as<int32_t>(),
+                       sc.qpos.as<int32_t>(), sc.sorttmp, s);
+    }
+    // counters: [0] out_count (u64), [2] work, [3] ovf_count, [4] err
+    sc.counters.alloc(64);
+    r.stats.alloc((size_t)std::max<int64_t>(n, 1) * 8 * sizeof(int32_t));
+    sc.ovf.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
+
+    int64_t cap = p.pair_capacity > 0 ? p.pair_capacity : std::max<int64_t>(1 << 16, n * 64);
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        sc.out_q.reserve((size_t)cap * sizeof(int32_t));
+        sc.out_x.reserve((size_t)cap * sizeof(int32_t));
+        sc.out_d.reserve((size_t)cap * sizeof(float));
+        ix.gen += 8;
+        const uint32_t G = ix.gen;
+        VJ_HIP(hipMemsetAsync(sc.counters.p, 0, 64, s));
+        int32_t *ctr = sc.counters.as<int32_t>();
+        if (ws != VJ_WS_SELF)
+            stamp_batch(ix.inb.as<int32_t>(), ix.nq, ids, n, (int32_t)G, ctr + 4, s);
+
+        TraverseLaunch a{};
+        a.vec = prec == VJ_PREC_U8 ? ix.vec_u8.p : prec == VJ_PREC_BF16 ? ix.vec_bf16.p : ix.vec.p;
+        a.vec32 = ix.vec.as<float>();
+        a.adj = ix.adj.as<int32_t>();
+        a.elen = ix.elen.as<float>();
+        a.nx = ix.nx;
+        a.nq = ix.nq;
+        a.R = ix.R;
+        a.dp = ix.dp;
+        a.entry = ix.entry;
+        a.metric = ix.metric;
+        a.prec = prec;
+        a.eps = eps;
+        a.eps2 = (float)((double)eps * (double)eps);
+        a.ws = ws;
+        a.parent = ix.has_mst ? ix.parent.as<int32_t>() : nullptr;
+        a.pub = ix.pub.as<unsigned long long>();
+        a.inb = ix.inb.as<int32_t>();
+        a.seg = ix.seg.as<int64_t>();
+        a.segn = ix.segn.as<int32_t>();
+        a.gen_first = G;
+        a.hyb = hyb;
+        a.beam = beam;
+        a.conv = p.conv_threshold;
+        a.ood_ratio = p.ood_ratio;
+        a.budget = budget;
+        a.out_q = sc.out_q.as<int32_t>();
+        a.out_x = sc.out_x.as<int32_t>();
+        a.out_d = sc.out_d.as<float>();
+        a.cap = cap;
+        a.out_count = reinterpret_cast<unsigned long long *>(ctr);
+        a.work = ctr + 2;
+        a.ovf_count = ctr + 3;
+        a.err = ctr + 4;
+        a.stats = r.stats.as<int32_t>();
+        a.ovf = sc.ovf.as<int32_t>();
+
+        // level 0: LDS visited set; levels >= 1: per-wave global tables
+        int64_t pending = n;
+        const int32_t *lq = sc.qlist.as<int32_t>(), *lp = sc.qpos.as<int32_t>();
+        int32_t hctr[5] = {0, 0, 0, 0, 0};
+        for (int level = 0; pending > 0; ++level) {
+            VJ_CHECK(level <= 2, VJ_ERR_INTERNAL, "spill levels exhausted");
+            const bool spill = level > 0;
+            int hlog, ilcap, max_blocks;
+            if (!spill) {
+                hlog = hl;
+                ilcap = (int)std::min<int64_t>(ix.nx, 16384);
+                max_blocks = max_blocks0;
+            } else if (level == 1) {
+                hlog = std::min(18, ceil_log2(2 * ix.nx) + 1);
+                ilcap = (int)std::min<int64_t>(ix.nx, 1 << 17);
+                max_blocks = std::max(1, std::min<int>(num_cus(), (int)((pending + wpb - 1) / wpb)));
+            } else {
+                hlog = ceil_log2(2 * ix.nx) + 1;
+                ilcap = (int)ix.nx;
+                max_blocks = std::max(1, std::min<int>(4, (int)((pending + wpb - 1) / wpb)));
+            }
+            const int slots = max_blocks * wpb;
+            sc.il_id.reserve((size_t)slots * ilcap * sizeof(int32_t));
+            sc.il_d.reserve((size_t)slots * ilcap * sizeof(float));
+            if (spill) {
+                const size_t gb = (size_t)slots * ((size_t)1 << hlog) * 8;
+                if (sc.ghash.bytes < gb) {
+                    sc.ghash.alloc(gb);
+                    VJ_HIP(hipMemsetAsync(sc.ghash.p, 0, gb, s));
+                    sc.gstamp.alloc((size_t)slots * sizeof(uint32_t));
+                    VJ_HIP(hipMemsetAsync(sc.gstamp.p, 0, sc.gstamp.bytes, s));
+                }
+            }
+            a.qlist = lq;
+            a.qpos = lp;
+            a.n = (int32_t)pending;
+            a.gen = G + (uint32_t)level;
+            a.il_id = sc.il_id.as<int32_t>();
+            a.il_d = sc.il_d.as<float>();
+            a.il_cap = ilcap;
+            a.ghash = spill ? sc.ghash.as<int32_t>() : nullptr;
+            a.gstamp = spill ? sc.gstamp.as<uint32_t>() : nullptr;
+            a.hash_log2 = hlog;
+            a.hash_limit = spill ? (1 << hlog) / 2 : ((1 << hlog) * 3) / 4;
+            a.lds_ints_per_wave = (spill ? 0 : (1 << hlog)) + 64 + (beam > 0 ? 2 * (beam + 64) : 0);
+            VJ_HIP(hipMemsetAsync(ctr + 2, 0, 2 * sizeof(int32_t), s));  // work, ovf_count
+            const int got = launch_traverse(a, spill, max_blocks, wpb, s);
+            VJ_CHECK(got > 0, VJ_ERR_UNSUPPORTED, "no traversal kernel for this row width");
+            VJ_CHECK(got <= slots, VJ_ERR_INTERNAL, "traversal launched more waves than scratch");
+            VJ_HIP(hipGetLastError());
+            VJ_HIP(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s));
+            VJ_HIP(hipStreamSynchronize(s));
+            VJ_CHECK(!(hctr[4] & 8), VJ_ERR_INVALID_ARG, "query id out of range");
+            VJ_CHECK(!(hctr[4] & 2), VJ_ERR_INTERNAL, "a query waited too long for its parent");
+            pending = hctr[3];
+            if (pending > 0) {
+                // re-run the overflowed slots, in processing order (parents first)
+                std::vector<int32_t> slots_h((size_t)pending);
+                VJ_HIP(hipMemcpyAsync(slots_h.data(), sc.ovf.p, pending * sizeof(int32_t),
+                                      hipMemcpyDeviceToHost, s));
+                VJ_HIP(hipStreamSynchronize(s));
+                std::sort(slots_h.begin(), slots_h.end());
+                DevBuf sl(pending * sizeof(int32_t));
+                VJ_HIP(hipMemcpyAsync(sl.p, slots_h.data(), pending * sizeof(int32_t),
+                                      hipMemcpyHostToDevice, s));
+                DevBuf q2(pending * sizeof(int32_t)), p2(pending * sizeof(int32_t));
+                gather_slots(lq, lp, sl.as<int32_t>(), pending, q2.as<int32_t>(), p2.as<int32_t>(), s);
+                VJ_HIP(hipStreamSynchronize(s));
+                sc.q2 = std::move(q2);
+                sc.p2 = std::move(p2);
+                lq = sc.q2.as<int32_t>();
+                lp = sc.p2.as<int32_t>();
+            }
+        }
+        const int64_t total = (int64_t)(((uint64_t)(uint32_t)hctr[1] << 32) | (uint32_t)hctr[0]);
+        if (total <= cap) {
+            r.count = total;
+            r.n_queries = n;
+            r.q = std::move(sc.out_q);
+            r.x = std::move(sc.out_x);
+            r.dist = std::move(sc.out_d);
+            return;
+        }
+        cap = total + total / 16 + 1024;
+    }
+    VJ_CHECK(false, VJ_ERR_INTERNAL, "result capacity did not converge");
+}
+
+}  // namespace vj
+
+// =================================================================== C ABI ==
+
+using namespace vj;
+
+#define API_BEGIN try {
+#define API_END                                                                    \
+    }                                                                              \
+    catch (const vj::Error &e) {                                                   \
+        vj::set_error(e.msg);                                                      \
+        return e.st;                                                               \
+    }                                                                              \
+    catch (const std::bad_alloc &) {                                               \
+        vj::set_error("host allocation failed");                                   \
+        return VJ_ERR_OOM;                                                         \
+    }                                                                              \
+    catch (...) {                                                                  \
+        vj::set_error("unexpected exception");                                     \
+        return VJ_ERR_INTERNAL;                                                    \
+    }                                                                              \
+    vj::set_error("");                                                             \
+    return VJ_OK;
+
+extern "C" {
+
+void vj_default_build_params(vj_build_params *p) {
+    if (!p) return;
+    p->R = 32;
+    p->K_cand = 0;
+    p->build_mst = 1;
+    p->copies = 0;
+}
+
+void vj_default_join_params(vj_join_params *p) {
+    if (!p) return;
+    p->work_sharing = VJ_WS_SELF;
+    p->hybrid = VJ_HYB_OFF;
+    p->hybrid_beam = 256;
+    p->conv_threshold = 10;
+    p->ood_ratio = 1.5f;
+    p->precision = VJ_PREC_FP32;
+    p->budget = nullptr;
+    p->hash_log2 = 0;
+    p->waves_per_cu = 0;
+    p->pair_capacity = 0;
+}
+
+const char *vj_last_error(void) { return vj::last_error(); }
+
+vj_status vj_index_from_graph(const float *Q, int64_t nq, const float *X, int64_t nx, int32_t d,
+                              vj_metric metric, const int32_t *adj, int32_t R, int32_t entry,
+                              const int32_t *parent, void *stream, vj_index **out) {
+    API_BEGIN
+    VJ_CHECK(out != nullptr && adj != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    check_shape(Q, nq, X, nx, d);
+    VJ_CHECK(metric == VJ_L2 || metric == VJ_IP, VJ_ERR_INVALID_ARG, "unknown metric");
+    VJ_CHECK(R >= 1 && R <= 64, VJ_ERR_UNSUPPORTED, "R must be in [1, 64]");
+    VJ_CHECK(entry >= 0 && entry < nq + nx, VJ_ERR_INVALID_ARG, "entry out of range");
+    hipStream_t s = (hipStream_t)stream;
+    auto h = std::make_unique<vj_index>();
+    Index &ix = h->impl;
+    ix.nq = nq; ix.nx = nx; ix.N = nq + nx; ix.d = d; ix.dp = padded_dim(d); ix.R = R;
+    ix.entry = entry; ix.metric = metric;
+    VJ_HIP(hipGetDevice(&ix.device));
+    init_vectors(ix, Q, X, s);
+    ix.adj.alloc((size_t)ix.N * R * sizeof(int32_t));
+    VJ_HIP(hipMemcpyAsync(ix.adj.p, adj, ix.adj.bytes, hipMemcpyDeviceToDevice, s));
+    // every id must be -1 or a node id
+    std::vector<int32_t> ah((size_t)ix.N * R);
+    VJ_HIP(hipMemcpyAsync(ah.data(), adj, ah.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    for (int32_t v : ah) VJ_CHECK(v >= -1 && v < ix.N, VJ_ERR_INVALID_ARG, "adjacency id out of range");
+    ix.elen.alloc((size_t)ix.N * R * sizeof(float));
+    launch_edge_lengths(ix.vec.as<float>(), ix.dp, ix.adj.as<int32_t>(), ix.N, R, ix.elen.as<float>(), s);
+    if (parent) set_parents(ix, parent, s);
+    else compute_mst(ix, s);
+    VJ_HIP(hipStreamSynchronize(s));
+    *out = h.release();
+    API_END
+}
+
+vj_status vj_build_merged_index(const float *Q, int64_t nq, const float *X, int64_t nx, int32_t d,
+                                vj_metric metric, const vj_build_params *bp, void *stream,
+                                vj_index **out) {
+    API_BEGIN
+    VJ_CHECK(out != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    check_shape(Q, nq, X, nx, d);
+    VJ_CHECK(metric == VJ_L2 || metric == VJ_IP, VJ_ERR_INVALID_ARG, "unknown metric");
+    vj_build_params p;
+    vj_default_build_params(&p);
+    if (bp) p = *bp;
+    VJ_CHECK(p.R >= 1 && p.R <= 64, VJ_ERR_UNSUPPORTED, "R must be in [1, 64]");
+    const int kc = p.K_cand > 0 ? p.K_cand : 2 * p.R;
+    VJ_CHECK(kc >= p.R && kc <= 256, VJ_ERR_UNSUPPORTED, "K_cand must be in [R, 256]");
+    hipStream_t s = (hipStream_t)stream;
+    auto h = std::make_unique<vj_index>();
+    Index &ix = h->impl;
+    ix.nq = nq; ix.nx = nx; ix.N = nq + nx; ix.d = d; ix.dp = padded_dim(d); ix.R = p.R;
+    ix.metric = metric;
+    VJ_HIP(hipGetDevice(&ix.device));
+    init_vectors(ix, Q, X, s);
+    build_graph(ix, (int)std::min<int64_t>(kc, ix.N - 1), s);
+    if (p.copies & 1) ensure_bf16(ix, s);
+    if (p.build_mst) compute_mst(ix, s);
+    VJ_HIP(hipStreamSynchronize(s));
+    *out = h.release();
+    API_END
+}
+
+vj_status vj_index_export_graph(const vj_index *idx, int32_t *adj, float *elen, int32_t *parent,
+                                void *stream) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr, VJ_ERR_INVALID_ARG, "null index");
+    const Index &ix = idx->impl;
+    hipStream_t s = (hipStream_t)stream;
+    if (adj) VJ_HIP(hipMemcpyAsync(adj, ix.adj.p, (size_t)ix.N * ix.R * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (elen) VJ_HIP(hipMemcpyAsync(elen, ix.elen.p, (size_t)ix.N * ix.R * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (parent) {
+        VJ_CHECK(ix.has_mst, VJ_ERR_INVALID_ARG, "index has no MST");
+        VJ_HIP(hipMemcpyAsync(parent, ix.parent.p, (size_t)ix.nq * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    VJ_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
+vj_status vj_index_info(const vj_index *idx, int64_t *nq, int64_t *nx, int32_t *d, int32_t *R,
+                        int32_t *entry, int32_t *metric) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr, VJ_ERR_INVALID_ARG, "null index");
+    const Index &ix = idx->impl;
+    if (nq) *nq = ix.nq;
+    if (nx) *nx = ix.nx;
+    if (d) *d = ix.d;
+    if (R) *R = ix.R;
+    if (entry) *entry = ix.entry;
+    if (metric) *metric = ix.metric;
+    API_END
+}
+
+void vj_index_free(vj_index *idx) { delete idx; }
+
+vj_status vj_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps, vj_metric metric,
+                  const vj_join_params *pp, void *stream, vj_pairs **out) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr && out != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    Index &ix = idx->impl;
+    VJ_CHECK(n >= 0, VJ_ERR_INVALID_ARG, "n must be >= 0");
+    VJ_CHECK(query_ids != nullptr || n == ix.nq, VJ_ERR_INVALID_ARG,
+             "query_ids may be NULL only with n == nq");
+    VJ_CHECK(n < ((int64_t)1 << 31), VJ_ERR_UNSUPPORTED, "n must be < 2^31");
+    VJ_CHECK(std::isfinite(eps), VJ_ERR_INVALID_ARG, "eps must be finite");
+    VJ_CHECK(metric == ix.metric, VJ_ERR_METRIC_MISMATCH, "join metric differs from the index metric");
+    vj_join_params p;
+    vj_default_join_params(&p);
+    if (pp) p = *pp;
+    VJ_CHECK(p.work_sharing >= VJ_WS_SELF && p.work_sharing <= VJ_WS_HARD, VJ_ERR_INVALID_ARG, "work_sharing");
+    VJ_CHECK(p.hybrid >= VJ_HYB_OFF && p.hybrid <= VJ_HYB_LEARNED, VJ_ERR_INVALID_ARG, "hybrid");
+    VJ_CHECK(p.hybrid_beam >= 0 && p.hybrid_beam <= 4096, VJ_ERR_INVALID_ARG, "hybrid_beam in [0, 4096]");
+    VJ_CHECK(p.work_sharing == VJ_WS_SELF || ix.has_mst, VJ_ERR_INVALID_ARG, "work sharing needs the MST");
+    VJ_CHECK(p.hybrid != VJ_HYB_BUDGET || p.budget != nullptr, VJ_ERR_INVALID_ARG, "budget mode needs budget[]");
+    VJ_CHECK(p.hybrid != VJ_HYB_LEARNED, VJ_ERR_UNSUPPORTED, "no predictor attached");
+    hipStream_t s = (hipStream_t)stream;
+    auto h = std::make_unique<vj_pairs>();
+    Pairs &r = h->impl;
+    r.n_queries = n;
+    if (n == 0 || (metric == VJ_L2 && eps <= 0.0f)) {
+        r.stats.alloc((size_t)std::max<int64_t>(n, 1) * 8 * sizeof(int32_t));
+        VJ_HIP(hipMemsetAsync(r.stats.p, 0, r.stats.bytes, s));
+        VJ_HIP(hipStreamSynchronize(s));
+        r.count = 0;
+        *out = h.release();
+        vj::set_error("");
+        return VJ_OK;
+    }
+    run_join(ix, query_ids, n, eps, p, p.budget, s, r);
+    *out = h.release();
+    API_END
+}
+
+vj_status vj_bruteforce_join(const float *Q, int64_t nq, const float *X, int64_t nx, int32_t d,
+                             float eps, vj_metric metric, vj_precision prec, void *stream,
+                             vj_pairs **out) {
+    API_BEGIN
+    VJ_CHECK(out != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    check_shape(Q, nq, X, nx, d);
+    VJ_CHECK(std::isfinite(eps), VJ_ERR_INVALID_ARG, "eps must be finite");
+    VJ_CHECK(metric == VJ_L2 || metric == VJ_IP, VJ_ERR_INVALID_ARG, "unknown metric");
+    VJ_CHECK(prec == VJ_PREC_FP32 || prec == VJ_PREC_BF16, VJ_ERR_UNSUPPORTED,
+             "brute force supports FP32 (split bf16) and BF16 tiles");
+    hipStream_t s = (hipStream_t)stream;
+    auto h = std::make_unique<vj_pairs>();
+    bruteforce_join(Q, nq, X, nx, d, eps, metric, prec, s, h->impl);
+    *out = h.release();
+    API_END
+}
+
+int64_t vj_pairs_count(const vj_pairs *r) { return r ? r->impl.count : -1; }
+
+vj_status vj_pairs_export(const vj_pairs *r, int32_t *qx, float *dist, int sorted, void *stream) {
+    API_BEGIN
+    VJ_CHECK(r != nullptr, VJ_ERR_INVALID_ARG, "null result");
+    VJ_CHECK(qx != nullptr || r->impl.count == 0, VJ_ERR_INVALID_ARG, "null qx");
+    hipStream_t s = (hipStream_t)stream;
+    export_pairs(r->impl, qx, dist, sorted != 0, s);
+    VJ_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
+vj_status vj_pairs_stats(const vj_pairs *r, int32_t *stats, void *stream) {
+    API_BEGIN
+    VJ_CHECK(r != nullptr && stats != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    VJ_CHECK(r->impl.n_queries > 0 && r->impl.stats.p, VJ_ERR_INVALID_ARG, "result has no per-query counters");
+    hipStream_t s = (hipStream_t)stream;
+    VJ_HIP(hipMemcpyAsync(stats, r->impl.stats.p, (size_t)r->impl.n_queries * 8 * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
+void vj_pairs_free(vj_pairs *r) { delete r; }
+
+}  // extern "C"
+
+namespace vj {
+int launch_traverse(const TraverseLaunch &a, bool spill, int max_blocks, int wpb, hipStream_t s) {
+    switch (a.prec) {
+    case VJ_PREC_FP32: return launch_traverse_f32(a, spill, max_blocks, wpb, s);
+    case VJ_PREC_U8: return launch_traverse_u8(a, spill, max_blocks, wpb, s);
+    case VJ_PREC_BF16: return launch_traverse_bf16(a, spill, max_blocks, wpb, s);
+    default: return 0;
+    }
+}
+}  // namespace vj

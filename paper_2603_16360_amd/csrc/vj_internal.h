@@ -1,0 +1,168 @@
+// Internal declarations of libvj (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/vj.h"
+
+namespace vj {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const std::string &msg);
+const char *last_error();
+
+struct Error {
+    vj_status st;
+    std::string msg;
+};
+
+#define VJ_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            throw ::vj::Error{e_ == hipErrorOutOfMemory ? VJ_ERR_OOM : VJ_ERR_HIP,     \
+                              std::string(#call) + ": " + hipGetErrorString(e_)};      \
+    } while (0)
+
+#define VJ_CHECK(cond, status, msg)                                                   \
+    do {                                                                               \
+        if (!(cond)) throw ::vj::Error{status, msg};                                  \
+    } while (0)
+
+// Device buffer that frees itself.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t n) { alloc(n); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t n) {
+        release();
+        if (n == 0) n = 16;
+        VJ_HIP(hipMalloc(&p, n));
+        bytes = n;
+    }
+    // grow (contents not kept)
+    void reserve(size_t n) { if (n > bytes) alloc(n); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Padded row widths the kernels are compiled for (elements).
+int padded_dim(int d);
+
+// ----------------------------------------------------------------- index --
+struct Index {
+    int64_t nq = 0, nx = 0, N = 0;
+    int32_t d = 0, dp = 0, R = 0, entry = 0;
+    vj_metric metric = VJ_L2;
+    int device = 0;
+    bool integer_u8 = false;  // every value an integer in [0, 255]
+    DevBuf vec;      // float [N][dp], zero padded
+    DevBuf vec_u8;   // uint8 [N][dp] (integer_u8 only)
+    DevBuf vec_bf16; // bf16 [N][dp] (optional)
+    DevBuf adj;      // int32 [N][R], -1 padded
+    DevBuf elen;     // float [N][R] L2 edge lengths, +inf padded
+    DevBuf parent;   // int32 [nq] MST parent node id (-1: entry)
+    DevBuf depth;    // int32 [nq] depth in the MST (root children: 0)
+    bool has_mst = false;
+    // join state shared by calls on this index (calls on one index must not overlap)
+    DevBuf pub;      // uint64 [nq] (generation << 32 | cache node) published by each query
+    DevBuf inb;      // int32 [nq] generation stamp: query is part of the current call
+    DevBuf seg;      // int64 [nq] offset of the query's pairs in the call's output
+    DevBuf segn;     // int32 [nq] number of pairs of the query
+    uint32_t gen = 0;
+};
+
+// ----------------------------------------------------------------- pairs --
+struct Pairs {
+    int64_t count = 0;
+    int64_t n_queries = 0;   // rows of stats (0 for brute force)
+    DevBuf q, x, dist;       // int32, int32, float [count]
+    DevBuf stats;            // int32 [n_queries][8]
+};
+
+// --------------------------------------------------------------- kernels --
+struct TraverseLaunch {
+    // index
+    const void *vec;          // element type per `prec`
+    const float *vec32;       // fp32 rows (query slices, re-checks)
+    const int32_t *adj;
+    const float *elen;
+    int64_t nx, nq;
+    int32_t R, dp, entry, metric, prec;
+    float eps, eps2;          // L2: compare squared distance with eps2
+    // work
+    const int32_t *qlist;     // [n] query index per processing slot
+    const int32_t *qpos;      // [n] caller position per processing slot
+    int32_t n;
+    int32_t *work;            // next processing slot
+    // work sharing
+    int32_t ws;
+    const int32_t *parent;
+    unsigned long long *pub;
+    const int32_t *inb;
+    int64_t *seg;
+    int32_t *segn;
+    uint32_t gen;             // this pass publishes with gen (first pass) or gen+1 (spill)
+    uint32_t gen_first;       // generation of the first pass of the call
+    // hybrid
+    int32_t hyb, beam, conv;
+    float ood_ratio;
+    const int32_t *budget;    // by caller position
+    // scratch
+    int32_t *il_id;           // [slots][il_cap]
+    float *il_d;
+    int32_t il_cap;
+    int32_t *ghash;           // [slots][1 << hash_log2] uint64 (spill pass only)
+    uint32_t *gstamp;         // [slots] per-slot query counter of the spill tables
+    int32_t hash_log2, hash_limit;
+    int32_t lds_ints_per_wave;
+    // output
+    int32_t *out_q, *out_x;
+    float *out_d;
+    int64_t cap;
+    unsigned long long *out_count;
+    int32_t *stats;           // [n_caller][8]
+    int32_t *ovf;             // processing slots that must be re-run on the spill path
+    int32_t *ovf_count;
+    int32_t *err;
+};
+
+// launch the persistent traversal; spill = global visited hash.  Returns the
+// number of wave slots launched (<= max_slots), 0 if the shape is unsupported.
+int launch_traverse(const TraverseLaunch &a, bool spill, int max_blocks, int waves_per_block,
+                    hipStream_t s);
+int launch_traverse_f32(const TraverseLaunch &a, bool spill, int max_blocks, int wpb, hipStream_t s);
+int launch_traverse_u8(const TraverseLaunch &a, bool spill, int max_blocks, int wpb, hipStream_t s);
+int launch_traverse_bf16(const TraverseLaunch &a, bool spill, int max_blocks, int wpb, hipStream_t s);
+int num_cus();
+
+// edge lengths of every adjacency entry (L2)
+void launch_edge_lengths(const float *vec, int dp, const int32_t *adj, int64_t N, int R,
+                         float *elen, hipStream_t s);
+// copy rows into a zero-padded layout
+void launch_pad_rows(const float *src, int64_t rows, int d, float *dst, int dp,
+                     hipStream_t s);
+// u8 / bf16 copies; flag[0] |= 1 if some value is not an integer in [0,255]
+void launch_quantize(const float *vec, int64_t rows, int dp, uint8_t *u8, uint16_t *bf16,
+                     int32_t *flag, hipStream_t s);
+
+// pairs export
+void export_pairs(const Pairs &r, int32_t *qx, float *dist, bool sorted, hipStream_t s);
+
+}  // namespace vj

@@ -1,0 +1,242 @@
+"""ctypes binding of libvj (include/vj.h): argument marshalling only.
+
+Every function here calls the C ABI of the same name; all computation runs
+in the library's HIP kernels.  PyTorch provides device memory and streams.
+If libvj.so is missing the import fails loudly: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvj.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -c 'import __graft_entry__ as g; g.build()'`")
+
+_lib = C.CDLL(LIB_PATH)
+
+VJ_OK = 0
+STATUS = {0: "VJ_OK", 1: "VJ_ERR_INVALID_ARG", 2: "VJ_ERR_METRIC_MISMATCH", 3: "VJ_ERR_OOM",
+          4: "VJ_ERR_HIP", 5: "VJ_ERR_INTERNAL", 6: "VJ_ERR_UNSUPPORTED"}
+METRIC = {"l2": 0, "ip": 1}
+WORK_SHARING = {"self": 0, "soft": 1, "hard": 2}
+HYBRID = {"off": 0, "force": 1, "adapt": 2, "budget": 3, "learned": 4}
+PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2, "u8": 3, "auto": 4}
+STAT_FIELDS = ("pairs", "n_dist", "n_expanded", "h_pops", "ood", "hybrid",
+               "visited_data", "flags")
+
+
+class VJError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class vj_build_params(C.Structure):
+    _fields_ = [("R", C.c_int32), ("K_cand", C.c_int32), ("build_mst", C.c_int32),
+                ("copies", C.c_int32)]
+
+
+class vj_join_params(C.Structure):
+    _fields_ = [("work_sharing", C.c_int32), ("hybrid", C.c_int32),
+                ("hybrid_beam", C.c_int32), ("conv_threshold", C.c_int32),
+                ("ood_ratio", C.c_float), ("precision", C.c_int32),
+                ("budget", C.c_void_p), ("hash_log2", C.c_int32),
+                ("waves_per_cu", C.c_int32), ("pair_capacity", C.c_int64)]
+
+
+_vp, _i64, _i32, _f32 = C.c_void_p, C.c_int64, C.c_int32, C.c_float
+_PP = C.POINTER(C.c_void_p)
+
+_SIGS = {
+    "vj_default_build_params": (None, [C.POINTER(vj_build_params)]),
+    "vj_default_join_params": (None, [C.POINTER(vj_join_params)]),
+    "vj_build_merged_index": (C.c_int, [_vp, _i64, _vp, _i64, _i32, C.c_int,
+                                        C.POINTER(vj_build_params), _vp, _PP]),
+    "vj_index_from_graph": (C.c_int, [_vp, _i64, _vp, _i64, _i32, C.c_int, _vp, _i32, _i32,
+                                      _vp, _vp, _PP]),
+    "vj_index_export_graph": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "vj_index_info": (C.c_int, [_vp] + [_vp] * 6),
+    "vj_index_free": (None, [_vp]),
+    "vj_join": (C.c_int, [_vp, _vp, _i64, _f32, C.c_int, C.POINTER(vj_join_params), _vp, _PP]),
+    "vj_bruteforce_join": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _f32, C.c_int, C.c_int,
+                                     _vp, _PP]),
+    "vj_pairs_count": (_i64, [_vp]),
+    "vj_pairs_export": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
+    "vj_pairs_stats": (C.c_int, [_vp, _vp, _vp]),
+    "vj_pairs_free": (None, [_vp]),
+    "vj_last_error": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+def _check(status: int):
+    if status != VJ_OK:
+        raise VJError(status, _lib.vj_last_error().decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    return t.contiguous()
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(0)
+
+
+# ------------------------------------------------------------------ objects --
+
+class Pairs:
+    """A join result held by the library (vj_pairs)."""
+
+    def __init__(self, handle: int, n_queries: int):
+        self._h = C.c_void_p(handle)
+        self.n_queries = n_queries
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.vj_pairs_free(self._h)
+            self._h = C.c_void_p(0)
+
+    def count(self) -> int:
+        return int(_lib.vj_pairs_count(self._h))
+
+    def export(self, sorted: bool = True):
+        """(qx int32 [count, 2], dist float32 [count]) as CUDA tensors."""
+        n = self.count()
+        qx = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+        dist = torch.empty(n, dtype=torch.float32, device="cuda")
+        _check(_lib.vj_pairs_export(self._h, _ptr(qx), _ptr(dist), int(sorted), _stream()))
+        return qx, dist
+
+    def stats(self) -> torch.Tensor:
+        """Per-query counters [n, 8] int32 (columns STAT_FIELDS)."""
+        st = torch.empty((self.n_queries, 8), dtype=torch.int32, device="cuda")
+        if self.n_queries:
+            _check(_lib.vj_pairs_stats(self._h, _ptr(st), _stream()))
+        return st
+
+
+class Index:
+    """A merged index (vj_index) over Q (queries) and X (data)."""
+
+    def __init__(self, handle: int):
+        self._h = C.c_void_p(handle)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.vj_index_free(self._h)
+            self._h = C.c_void_p(0)
+
+    def info(self) -> dict:
+        nq, nx = C.c_int64(), C.c_int64()
+        d, R, e, m = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(_lib.vj_index_info(self._h, C.byref(nq), C.byref(nx), C.byref(d), C.byref(R),
+                                  C.byref(e), C.byref(m)))
+        return {"nq": nq.value, "nx": nx.value, "d": d.value, "R": R.value,
+                "entry": e.value, "metric": m.value}
+
+    def export_graph(self):
+        """(adj int32 [N, R], elen float32 [N, R], parent int32 [nq]) on the GPU."""
+        i = self.info()
+        N = i["nq"] + i["nx"]
+        adj = torch.empty((N, i["R"]), dtype=torch.int32, device="cuda")
+        elen = torch.empty((N, i["R"]), dtype=torch.float32, device="cuda")
+        parent = torch.empty(i["nq"], dtype=torch.int32, device="cuda")
+        _check(_lib.vj_index_export_graph(self._h, _ptr(adj), _ptr(elen), _ptr(parent), _stream()))
+        return adj, elen, parent
+
+
+# ---------------------------------------------------------------- functions --
+
+def join_params(work_sharing="self", hybrid="off", hybrid_beam=256, conv_threshold=10,
+                ood_ratio=1.5, precision="fp32", budget=None, hash_log2=0, waves_per_cu=0,
+                pair_capacity=0):
+    p = vj_join_params()
+    _lib.vj_default_join_params(C.byref(p))
+    p.work_sharing = WORK_SHARING[work_sharing]
+    p.hybrid = HYBRID[hybrid]
+    p.hybrid_beam = hybrid_beam
+    p.conv_threshold = conv_threshold
+    p.ood_ratio = ood_ratio
+    p.precision = PRECISION[precision]
+    p.budget = budget.data_ptr() if budget is not None else None
+    p.hash_log2 = hash_log2
+    p.waves_per_cu = waves_per_cu
+    p.pair_capacity = pair_capacity
+    return p
+
+
+def vj_build_merged_index(Q: torch.Tensor, X: torch.Tensor, metric: str = "l2", R: int = 32,
+                          K_cand: int = 0, build_mst: bool = True, copies: int = 0) -> Index:
+    Q = _dev(Q, torch.float32, "Q")
+    X = _dev(X, torch.float32, "X")
+    bp = vj_build_params()
+    _lib.vj_default_build_params(C.byref(bp))
+    bp.R, bp.K_cand, bp.build_mst, bp.copies = R, K_cand, int(build_mst), copies
+    h = C.c_void_p()
+    _check(_lib.vj_build_merged_index(_ptr(Q), Q.shape[0], _ptr(X), X.shape[0], X.shape[1],
+                                      METRIC[metric], C.byref(bp), _stream(), C.byref(h)))
+    return Index(h.value)
+
+
+def vj_index_from_graph(Q: torch.Tensor, X: torch.Tensor, adj: torch.Tensor, entry: int,
+                        metric: str = "l2", parent: torch.Tensor | None = None) -> Index:
+    Q = _dev(Q, torch.float32, "Q")
+    X = _dev(X, torch.float32, "X")
+    adj = _dev(adj, torch.int32, "adj")
+    if parent is not None:
+        parent = _dev(parent, torch.int32, "parent")
+    h = C.c_void_p()
+    _check(_lib.vj_index_from_graph(_ptr(Q), Q.shape[0], _ptr(X), X.shape[0], X.shape[1],
+                                    METRIC[metric], _ptr(adj), adj.shape[1], entry,
+                                    _ptr(parent) if parent is not None else C.c_void_p(0),
+                                    _stream(), C.byref(h)))
+    return Index(h.value)
+
+
+def vj_join(index: Index, eps: float, metric: str = "l2", query_ids: torch.Tensor | None = None,
+            params: vj_join_params | None = None, **kw) -> Pairs:
+    if params is None:
+        params = join_params(**kw)
+    n = index.info()["nq"] if query_ids is None else int(query_ids.numel())
+    qp = C.c_void_p(0)
+    if query_ids is not None:
+        query_ids = _dev(query_ids, torch.int32, "query_ids")
+        qp = _ptr(query_ids)
+    h = C.c_void_p()
+    _check(_lib.vj_join(index._h, qp, n, float(eps), METRIC[metric], C.byref(params),
+                        _stream(), C.byref(h)))
+    return Pairs(h.value, n)
+
+
+def vj_bruteforce_join(Q: torch.Tensor, X: torch.Tensor, eps: float, metric: str = "l2",
+                       precision: str = "fp32") -> Pairs:
+    Q = _dev(Q, torch.float32, "Q")
+    X = _dev(X, torch.float32, "X")
+    h = C.c_void_p()
+    _check(_lib.vj_bruteforce_join(_ptr(Q), Q.shape[0], _ptr(X), X.shape[0], X.shape[1],
+                                   float(eps), METRIC[metric], PRECISION[precision],
+                                   _stream(), C.byref(h)))
+    return Pairs(h.value, 0)
+
+
+def vj_last_error() -> str:
+    return _lib.vj_last_error().decode()
