@@ -1,0 +1,570 @@
+// Merged-index join kernel: the online path of Algorithm 1 with cfg.merged =
+// true (Sections 4.1-4.4).  Included by one translation unit per row type.
+//
+// Shape: one wavefront (64 lanes) per query; a launch covers a contiguous
+// range of a processing list, four waves per workgroup.  Per query:
+//   seeds    {s} (+ the parent's cached node, soft mode; its in-range
+//            nodes, hard mode)                                  Algorithm 3
+//   probe    the neighbours of the query node q                 Algorithms 4-5
+//   check    d1/d2 OOD test or a per-query budget               Algorithm 6
+//   expand   in-range data nodes to closure; in hybrid mode the closest
+//            out-range node of a bounded queue is expanded whenever the
+//            in-range worklist is empty                         Algorithm 7
+//   cache    closest visited data node (soft)                   Algorithm 8
+// All per-query state lives in LDS: the visited hash, the in-range worklist
+// (which is also the query's pair buffer) and the out-range queue.  A query
+// that outgrows them is re-run on the spill variant (SPILL = true), whose
+// visited set and worklist are per-wave regions of global memory.
+//
+// Rows are gathered LPR lanes per row, 16 bytes per lane per load (a row
+// group's load covers whole 128-byte lines), and reduced with xor shuffles
+// inside the lane group.  Every loop has a static bound; ids read back from
+// memory are range-checked before they index anything.
+#pragma once
+
+#include "vj_internal.h"
+
+namespace vj {
+namespace wj {
+
+constexpr int kWaves = 4;      // waves per workgroup
+constexpr int kHash = 1024;    // LDS visited-set slots per wave
+constexpr int kList = 512;     // LDS in-range worklist entries per wave
+constexpr int kBeamMax = 256;  // largest out-range queue the LDS variant holds
+constexpr int kHeap = kBeamMax + 64;
+
+template <typename T> struct Elem;
+template <> struct Elem<float> { static constexpr int CE = 4; };
+template <> struct Elem<uint8_t> { static constexpr int CE = 16; };
+
+// lanes per row: a power of two with at most 8 16-byte chunks per lane
+constexpr int pick_lpr(int cpr) {
+    int l = 8;
+    while (l > 1 && cpr % l) l >>= 1;
+    if (cpr / l > 8) {
+        l = 16;
+        while ((l < 64) && (cpr % l || cpr / l > 8)) l <<= 1;
+    }
+    return l;
+}
+
+__device__ __forceinline__ void to_float(const uint4 &r, float *f, float) {
+    f[0] = __uint_as_float(r.x); f[1] = __uint_as_float(r.y);
+    f[2] = __uint_as_float(r.z); f[3] = __uint_as_float(r.w);
+}
+__device__ __forceinline__ void to_float(const uint4 &r, float *f, uint8_t) {
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f[4 * i + 0] = (float)(w[i] & 0xffu);
+        f[4 * i + 1] = (float)((w[i] >> 8) & 0xffu);
+        f[4 * i + 2] = (float)((w[i] >> 16) & 0xffu);
+        f[4 * i + 3] = (float)(w[i] >> 24);
+    }
+}
+
+// lanes of one wave exchange data through LDS / their own global stores
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint32_t slot_of(int32_t v, int log2n) {
+    return ((uint32_t)v * 0x9E3779B1u) >> (32 - log2n);
+}
+
+// wave-wide (key, id, index) reduction keeping the min or the max by (key, id)
+__device__ __forceinline__ void wave_best(float &k, int &id, int &ix, bool want_max) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float ok = __shfl_xor(k, off);
+        const int oid = __shfl_xor(id, off);
+        const int oix = __shfl_xor(ix, off);
+        const bool take = want_max ? (ok > k || (ok == k && oid > id))
+                                   : (ok < k || (ok == k && oid < id));
+        if (take) { k = ok; id = oid; ix = oix; }
+    }
+}
+
+// Per-wave query state.  Uniform fields are kept identical in every lane.
+struct QState {
+    int tail, head, hc, nvis, ndist, nexp, hpops;
+    bool abort, hyb_active;
+    float best_k;
+    int best_id;
+    float d1sum;
+    int c1;
+};
+
+// Everything one wave needs to touch: LDS or spill regions, plus the query.
+struct WaveMem {
+    int32_t *hash;   // visited set (LDS or global)
+    int hash_log2, hash_limit;
+    int32_t *il;     // in-range worklist ids
+    float *ild;      // their distance keys
+    int il_cap;
+    int32_t *stage;  // 64 candidate ids (LDS)
+    float *hk;       // out-range queue keys (LDS)
+    int32_t *hi;     // out-range queue ids
+};
+
+// Insert each active lane's id; returns true where the id was new.  A lane
+// probes at most the table size before giving up (error flag + abort).
+__device__ __forceinline__ bool visit(const JoinArgs &a, const WaveMem &m, QState &s, int32_t v,
+                                      bool active) {
+    bool isnew = false;
+    const int n = 1 << m.hash_log2;
+    uint32_t h = slot_of(v, m.hash_log2);
+    int probes = 0;
+    for (int it = 0; it <= n; ++it) {
+        if (__ballot(active) == 0) break;
+        if (active) {
+            if (++probes > n) {
+                active = false;
+                atomicOr(a.err, 16);
+            } else {
+                const int old = atomicCAS(&m.hash[h], -1, v);
+                if (old == -1) { isnew = true; active = false; }
+                else if (old == v) active = false;
+                else h = (h + 1) & (uint32_t)(n - 1);
+            }
+        }
+    }
+    if (__ballot(probes > n)) s.abort = true;
+    return isnew;
+}
+
+template <int LPR, int VPL, int CE, typename T>
+__device__ __forceinline__ float row_partial(const uint4 *buf, const float *qf, bool l2) {
+    float acc = 0.f;
+#pragma unroll
+    for (int w = 0; w < VPL; ++w) {
+        float f[CE];
+        to_float(buf[w], f, T());
+#pragma unroll
+        for (int e = 0; e < CE; ++e) {
+            if (l2) { const float t = f[e] - qf[w * CE + e]; acc = fmaf(t, t, acc); }
+            else acc = fmaf(f[e], qf[w * CE + e], acc);
+        }
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    return acc;
+}
+
+// drop the largest (key, id) entries until the queue holds `beam`
+__device__ __forceinline__ void heap_trim(const WaveMem &m, QState &s, int beam, int lane) {
+    for (int guard = 0; guard < 64 && s.hc > beam; ++guard) {
+        float bk = -INFINITY;
+        int bid = -1, bx = 0;
+        for (int i = lane; i < s.hc; i += 64) {
+            const float kk = m.hk[i];
+            const int id = m.hi[i];
+            if (kk > bk || (kk == bk && id > bid)) { bk = kk; bid = id; bx = i; }
+        }
+        wave_best(bk, bid, bx, true);
+        bx = uni(bx);
+        if (lane == 0) { m.hk[bx] = m.hk[s.hc - 1]; m.hi[bx] = m.hi[s.hc - 1]; }
+        s.hc -= 1;
+        wave_sync();
+    }
+}
+
+// One candidate batch (<= 1 id per lane): visited check, compaction, row
+// gathers, distances, classification.  probe: distances for every valid
+// data candidate (the d1 feature needs them), not only new ones.
+template <typename T, int DP>
+__device__ __forceinline__ void run_batch(const JoinArgs &a, const WaveMem &m, QState &s,
+                                          const float *qf, int32_t v, bool probe, int lane) {
+    constexpr int CE = Elem<T>::CE;
+    constexpr int CPR = DP / CE;
+    constexpr int LPR = pick_lpr(CPR);
+    constexpr int VPL = CPR / LPR;
+    constexpr int RPP = 64 / LPR;
+    constexpr int PG = VPL >= 4 ? 1 : 4 / VPL;
+    const bool l2 = a.metric == VJ_L2;
+    const int p = lane % LPR, rr = lane / LPR;
+    const uint64_t ltmask = (1ull << lane) - 1ull;
+    const T *vbase = reinterpret_cast<const T *>(a.rows);
+
+    const bool valid = v >= 0 && v < a.nx;
+    const bool isnew = visit(a, m, s, v, valid);
+    s.nvis += __popcll(__ballot(isnew));
+    if (s.nvis > m.hash_limit) s.abort = true;
+    if (s.abort) return;
+    const bool need = probe ? valid : isnew;
+    const uint64_t mneed = __ballot(need);
+    const int cnt = __popcll(mneed);
+    if (need) m.stage[__popcll(mneed & ltmask)] = isnew ? v : ~v;
+    wave_sync();
+    s.ndist += cnt;
+    for (int base = 0; base < cnt; base += RPP * PG) {
+        uint4 buf[PG][VPL];
+        int sid[PG];
+#pragma unroll
+        for (int g = 0; g < PG; ++g) {
+            const int c = base + g * RPP + rr;
+            sid[g] = c < cnt ? m.stage[c] : 0;
+            const int id = sid[g] >= 0 ? sid[g] : ~sid[g];
+            const uint4 *row = reinterpret_cast<const uint4 *>(vbase + (size_t)id * DP);
+#pragma unroll
+            for (int w = 0; w < VPL; ++w)
+                buf[g][w] = c < cnt ? row[p + w * LPR] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int g = 0; g < PG; ++g) {
+            const float acc = row_partial<LPR, VPL, CE, T>(buf[g], qf, l2);
+            const int c = base + g * RPP + rr;
+            const bool lead = p == 0 && c < cnt;
+            const bool nw = sid[g] >= 0;
+            const int id = nw ? sid[g] : ~sid[g];
+            const float key = l2 ? acc : 1.0f - acc;
+            const bool inr = l2 ? (acc < a.eps2) : (key < a.eps);
+            if (lead && nw && (key < s.best_k || (key == s.best_k && id < s.best_id))) {
+                s.best_k = key;
+                s.best_id = id;
+            }
+            if (probe && lead) {
+                s.d1sum += l2 ? sqrtf(key) : sqrtf(fmaxf(0.f, 2.f * key));
+                s.c1 += 1;
+            }
+            const bool ap = lead && nw && inr;
+            const uint64_t ma = __ballot(ap);
+            const int na = __popcll(ma);
+            if (s.tail + na > m.il_cap) {
+                s.abort = true;
+            } else {
+                if (ap) {
+                    const int o = s.tail + __popcll(ma & ltmask);
+                    m.il[o] = id;
+                    m.ild[o] = key;
+                }
+                s.tail += na;
+            }
+            if (s.hyb_active) {
+                const bool hp = lead && nw && !inr;
+                const uint64_t mh = __ballot(hp);
+                if (hp) {
+                    const int o = s.hc + __popcll(mh & ltmask);
+                    m.hk[o] = key;
+                    m.hi[o] = id;
+                }
+                s.hc += __popcll(mh);
+                if (s.hc > a.beam) { wave_sync(); heap_trim(m, s, a.beam, lane); }
+            }
+        }
+    }
+    wave_sync();
+}
+
+template <typename T, int DP>
+__device__ __forceinline__ void run_query(const JoinArgs &a, const WaveMem &m, int k,
+                                          const int32_t *qlist, const int32_t *qpos,
+                                          int32_t *ovf, int32_t *ovf_count, bool spill, int lane) {
+    constexpr int CE = Elem<T>::CE;
+    constexpr int CPR = DP / CE;
+    constexpr int LPR = pick_lpr(CPR);
+    constexpr int VPL = CPR / LPR;
+    constexpr int QF = VPL * CE;
+    const int R = a.R;
+    const int qi = uni(qlist[k]);
+    const int pos = uni(qpos[k]);
+    int32_t *st = a.stats + (size_t)pos * 8;
+    if (qi < 0 || qi >= a.nq) {
+        if (lane < 8) st[lane] = 0;
+        if (lane == 0) atomicOr(a.err, 8);
+        return;
+    }
+    const int32_t q = (int32_t)(a.nx + qi);
+    if (a.hyb == VJ_HYB_BUDGET && a.budget[pos] < 0) {  // routed to brute force
+        if (lane < 8) st[lane] = lane == 7 ? 2 : 0;
+        if (lane == 0 && a.ws != VJ_WS_SELF) a.cache[qi] = -1;
+        return;
+    }
+
+    // the query's slice of dimensions, fp32
+    float qf[QF];
+    {
+        const int p = lane % LPR;
+        const float *qrow = a.rows32 + (size_t)q * DP;
+#pragma unroll
+        for (int w = 0; w < VPL; ++w) {
+            const float4 *src = reinterpret_cast<const float4 *>(qrow + (p + w * LPR) * CE);
+#pragma unroll
+            for (int e = 0; e < CE / 4; ++e) {
+                const float4 t = src[e];
+                qf[w * CE + 4 * e + 0] = t.x; qf[w * CE + 4 * e + 1] = t.y;
+                qf[w * CE + 4 * e + 2] = t.z; qf[w * CE + 4 * e + 3] = t.w;
+            }
+        }
+    }
+    for (int i = lane; i < (1 << m.hash_log2); i += 64) m.hash[i] = -1;
+    wave_sync();
+
+    QState s{};
+    s.best_k = INFINITY;
+    s.best_id = 0x7fffffff;
+
+    // ---- SeedPhase: s, plus the parent's cache (parents ran in an earlier launch)
+    int pcache = -1;
+    int64_t pseg = 0;
+    int pcnt = 0;
+    if (a.ws != VJ_WS_SELF) {
+        const int32_t par = a.parent[qi];
+        if (par >= a.nx && par < a.nx + a.nq && a.inb[par - a.nx] == (int32_t)a.gen) {
+            const int pq = par - (int32_t)a.nx;
+            if (a.ws == VJ_WS_SOFT) {
+                pcache = uni(a.cache[pq]);
+            } else {
+                pseg = a.seg[pq];
+                pcnt = uni(a.segn[pq]);
+                if (pseg < 0 || pseg + pcnt > a.cap) pcnt = 0;
+            }
+        }
+    }
+    {
+        int32_t v = -1;
+        if (lane == 0) v = a.entry;
+        if (lane == 1) v = pcache;
+        run_batch<T, DP>(a, m, s, qf, v, false, lane);
+        for (int t = 0; !s.abort && t < pcnt && t < a.nx + 64; t += 64) {
+            const int32_t u = t + lane < pcnt ? a.out_x[pseg + t + lane] : -1;
+            run_batch<T, DP>(a, m, s, qf, u, false, lane);
+        }
+    }
+
+    // ---- GreedySearchPhase on the merged index: probe N(q), then stop
+    const int32_t nbq = lane < R ? a.adj[(size_t)q * R + lane] : -1;
+    if (!s.abort) run_batch<T, DP>(a, m, s, qf, nbq, a.hyb == VJ_HYB_ADAPT, lane);
+
+    // ---- CheckHybrid
+    bool hyb = false;
+    int ood = 0;
+    if (!s.abort) {
+        if (a.hyb == VJ_HYB_FORCE) {
+            hyb = true;
+        } else if (a.hyb == VJ_HYB_BUDGET) {
+            hyb = a.budget[pos] > 0;
+        } else if (a.hyb == VJ_HYB_ADAPT) {
+            float s1 = s.d1sum;
+            int n1 = s.c1;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) { s1 += __shfl_xor(s1, off); n1 += __shfl_xor(n1, off); }
+            float s2 = 0.f;
+            int n2 = 0;
+            const int NB = 64 / R;
+            for (int j0 = 0; j0 < R; j0 += NB) {
+                const int b = lane / R, j = lane - b * R;
+                const int yj = j0 + b;
+                const bool ok = b < NB && yj < R;
+                const int32_t y = __shfl(nbq, ok ? yj : 0);
+                if (ok && y >= 0 && y < a.nx) {
+                    const int32_t z = a.adj[(size_t)y * R + j];
+                    if (z >= 0 && z < a.nx) { s2 += a.elen[(size_t)y * R + j]; n2 += 1; }
+                }
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) { s2 += __shfl_xor(s2, off); n2 += __shfl_xor(n2, off); }
+            if (n1 == 0) hyb = true;
+            else if (n2 == 0) hyb = false;
+            else hyb = (s1 / (float)n1) / (s2 / (float)n2) > a.ood_ratio;
+            ood = hyb ? 1 : 0;
+        }
+    }
+    s.hyb_active = hyb && a.beam > 0;
+
+    // ---- ExpansionPhase: in-range closure, then one out-range pop at a time
+    const int NB = 64 / R;
+    int unprod = 0, before = 0;
+    bool pending = false;
+    const int budget = a.hyb == VJ_HYB_BUDGET ? a.budget[pos] : 0;
+    for (int round = 0; round <= m.hash_limit + 1 && !s.abort; ++round) {
+        for (int it = 0; it <= m.il_cap && !s.abort && s.head < s.tail; ++it) {
+            const int nb = min(NB, s.tail - s.head);
+            const int b = lane / R, j = lane - b * R;
+            int32_t v = -1;
+            if (b < nb) {
+                const int32_t u = m.il[s.head + b];
+                if (u >= 0 && u < a.nx) v = a.adj[(size_t)u * R + j];
+                else atomicOr(a.err, 32);
+            }
+            s.head += nb;
+            s.nexp += nb;
+            run_batch<T, DP>(a, m, s, qf, v, false, lane);
+        }
+        if (s.abort) break;
+        if (pending) { unprod = (s.tail == before) ? unprod + 1 : 0; pending = false; }
+        if (!s.hyb_active || s.hc == 0) break;
+        if (a.hyb == VJ_HYB_BUDGET) { if (s.hpops >= budget) break; }
+        else if (a.conv > 0 && unprod >= a.conv) break;
+        float bk = INFINITY;
+        int bid = 0x7fffffff, bx = 0;
+        for (int i = lane; i < s.hc; i += 64) {
+            const float kk = m.hk[i];
+            const int id = m.hi[i];
+            if (kk < bk || (kk == bk && id < bid)) { bk = kk; bid = id; bx = i; }
+        }
+        wave_best(bk, bid, bx, false);
+        bid = uni(bid);
+        bx = uni(bx);
+        if (lane == 0) { m.hk[bx] = m.hk[s.hc - 1]; m.hi[bx] = m.hi[s.hc - 1]; }
+        s.hc -= 1;
+        wave_sync();
+        s.hpops += 1;
+        s.nexp += 1;
+        before = s.tail;
+        pending = true;
+        if (bid < 0 || bid >= a.nx) { if (lane == 0) atomicOr(a.err, 32); s.abort = true; break; }
+        const int32_t v = lane < R ? a.adj[(size_t)bid * R + lane] : -1;
+        run_batch<T, DP>(a, m, s, qf, v, false, lane);
+    }
+
+    if (s.abort) {
+        // not written: re-run on the spill variant (or reported if this is it)
+        if (lane == 0) ovf[atomicAdd(ovf_count, 1)] = k;
+        if (lane < 8) st[lane] = lane == 7 ? 4 : 0;
+        return;
+    }
+
+    // ---- emit pairs
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(a.out_count, (unsigned long long)s.tail);
+    const uint32_t blo = __shfl((uint32_t)base, 0), bhi = __shfl((uint32_t)(base >> 32), 0);
+    base = ((unsigned long long)bhi << 32) | blo;
+    const bool fits = base + (unsigned long long)s.tail <= (unsigned long long)a.cap;
+    const bool l2 = a.metric == VJ_L2;
+    if (fits) {
+        for (int i = lane; i < s.tail; i += 64) {
+            a.out_q[base + i] = qi;
+            a.out_x[base + i] = m.il[i];
+            const float kk = m.ild[i];
+            a.out_d[base + i] = l2 ? sqrtf(kk) : kk;
+        }
+    }
+
+    // ---- UpdateCache (read by children in a later launch)
+    if (a.ws == VJ_WS_SOFT) {
+        float bk = s.best_k;
+        int bid = s.best_id, bx = 0;
+        wave_best(bk, bid, bx, false);
+        if (lane == 0) a.cache[qi] = bid == 0x7fffffff ? -1 : bid;
+    } else if (a.ws == VJ_WS_HARD && lane == 0) {
+        a.seg[qi] = (int64_t)base;
+        a.segn[qi] = fits ? s.tail : 0;
+    }
+
+    if (lane == 0) {
+        st[0] = s.tail;
+        st[1] = s.ndist;
+        st[2] = s.nexp;
+        st[3] = s.hpops;
+        st[4] = ood;
+        st[5] = hyb ? 1 : 0;
+        st[6] = s.nvis;
+        st[7] = spill ? 1 : 0;
+    }
+}
+
+// LDS variant: everything per query in static LDS
+template <typename T, int DP, bool HYB>
+__global__ void __launch_bounds__(64 * kWaves)
+k_join_lds(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos, int k0,
+           int k1, int32_t *ovf, int32_t *ovf_count) {
+    __shared__ int32_t sh_hash[kWaves][kHash];
+    __shared__ int32_t sh_il[kWaves][kList];
+    __shared__ float sh_ild[kWaves][kList];
+    __shared__ int32_t sh_stage[kWaves][64];
+    __shared__ float sh_hk[kWaves][HYB ? kHeap : 1];
+    __shared__ int32_t sh_hi[kWaves][HYB ? kHeap : 1];
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    const int k = k0 + (int)blockIdx.x * kWaves + wib;
+    if (k >= k1) return;
+    const JoinArgs &a = *pa;
+    WaveMem m;
+    m.hash = sh_hash[wib];
+    m.hash_log2 = 10;
+    m.hash_limit = kHash * 3 / 4 - 64;
+    m.il = sh_il[wib];
+    m.ild = sh_ild[wib];
+    m.il_cap = kList;
+    m.stage = sh_stage[wib];
+    m.hk = sh_hk[wib];
+    m.hi = sh_hi[wib];
+    run_query<T, DP>(a, m, k, qlist, qpos, ovf, ovf_count, false, lane);
+}
+
+// spill variant: visited set and worklist in per-wave global regions
+template <typename T, int DP, bool HYB>
+__global__ void __launch_bounds__(64 * kWaves)
+k_join_spill(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos, int k0,
+             int k1, int32_t *gh, int hash_log2, int32_t *gil, float *gild, int il_cap,
+             int32_t *ovf, int32_t *ovf_count) {
+    __shared__ int32_t sh_stage[kWaves][64];
+    __shared__ float sh_hk[kWaves][HYB ? kHeap : 1];
+    __shared__ int32_t sh_hi[kWaves][HYB ? kHeap : 1];
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    const int k = k0 + (int)blockIdx.x * kWaves + wib;
+    if (k >= k1) return;
+    const JoinArgs &a = *pa;
+    const size_t w = (size_t)(k - k0);  // scratch region of this wave
+    WaveMem m;
+    m.hash = gh + (w << hash_log2);
+    m.hash_log2 = hash_log2;
+    m.hash_limit = (1 << hash_log2) / 2;
+    m.il = gil + w * il_cap;
+    m.ild = gild + w * il_cap;
+    m.il_cap = il_cap;
+    m.stage = sh_stage[wib];
+    m.hk = sh_hk[wib];
+    m.hi = sh_hi[wib];
+    run_query<T, DP>(a, m, k, qlist, qpos, ovf, ovf_count, true, lane);
+}
+
+template <typename T, int DP>
+bool launch_dp(const JoinLaunch &L, hipStream_t s) {
+    const unsigned blocks = (unsigned)((L.count + kWaves - 1) / kWaves);
+    if (blocks == 0) return true;
+    const int k0 = L.first, k1 = L.first + L.count;
+    if (!L.spill) {
+        if (L.hyb)
+            hipLaunchKernelGGL((k_join_lds<T, DP, true>), dim3(blocks), dim3(64 * kWaves), 0, s,
+                               L.args, L.qlist, L.qpos, k0, k1, L.ovf, L.ovf_count);
+        else
+            hipLaunchKernelGGL((k_join_lds<T, DP, false>), dim3(blocks), dim3(64 * kWaves), 0, s,
+                               L.args, L.qlist, L.qpos, k0, k1, L.ovf, L.ovf_count);
+    } else {
+        if (L.hyb)
+            hipLaunchKernelGGL((k_join_spill<T, DP, true>), dim3(blocks), dim3(64 * kWaves), 0, s,
+                               L.args, L.qlist, L.qpos, k0, k1, L.gh, L.hash_log2, L.gil, L.gild,
+                               L.il_cap, L.ovf, L.ovf_count);
+        else
+            hipLaunchKernelGGL((k_join_spill<T, DP, false>), dim3(blocks), dim3(64 * kWaves), 0, s,
+                               L.args, L.qlist, L.qpos, k0, k1, L.gh, L.hash_log2, L.gil, L.gild,
+                               L.il_cap, L.ovf, L.ovf_count);
+    }
+    return true;
+}
+
+template <typename T>
+bool launch_elem(const JoinLaunch &L, hipStream_t s) {
+    switch (L.dp) {
+    case 32: return launch_dp<T, 32>(L, s);
+    case 64: return launch_dp<T, 64>(L, s);
+    case 96: return launch_dp<T, 96>(L, s);
+    case 128: return launch_dp<T, 128>(L, s);
+    case 192: return launch_dp<T, 192>(L, s);
+    case 256: return launch_dp<T, 256>(L, s);
+    case 384: return launch_dp<T, 384>(L, s);
+    case 512: return launch_dp<T, 512>(L, s);
+    case 768: return launch_dp<T, 768>(L, s);
+    case 1024: return launch_dp<T, 1024>(L, s);
+    default: return false;
+    }
+}
+
+}  // namespace wj
+}  // namespace vj

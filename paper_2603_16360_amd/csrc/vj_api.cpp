@@ -55,11 +55,11 @@ static void init_vectors(Index &ix, const float *Q, const float *X, hipStream_t 
     ix.integer_u8 = (h == 0);
     if (!ix.integer_u8) ix.vec_u8.release();
     const size_t nq = (size_t)std::max<int64_t>(ix.nq, 1);
-    ix.pub.alloc(nq * sizeof(unsigned long long));
+    ix.cache.alloc(nq * sizeof(int32_t));
     ix.inb.alloc(nq * sizeof(int32_t));
     ix.seg.alloc(nq * sizeof(int64_t));
     ix.segn.alloc(nq * sizeof(int32_t));
-    VJ_HIP(hipMemsetAsync(ix.pub.p, 0, ix.pub.bytes, s));
+    VJ_HIP(hipMemsetAsync(ix.cache.p, 0xff, ix.cache.bytes, s));
     VJ_HIP(hipMemsetAsync(ix.inb.p, 0, ix.inb.bytes, s));
     VJ_HIP(hipMemsetAsync(ix.seg.p, 0, ix.seg.bytes, s));
     VJ_HIP(hipMemsetAsync(ix.segn.p, 0, ix.segn.bytes, s));
@@ -192,11 +192,41 @@ static void check_shape(const float *Q, int64_t nq, const float *X, int64_t nx, 
 
 // ------------------------------------------------------------------ join --
 
-struct JoinScratch {
-    DevBuf qlist, qpos, q2, p2, sorttmp;
-    DevBuf il_id, il_d, ghash, gstamp, ovf, counters;
-    DevBuf out_q, out_x, out_d;
+// Processing order: the caller's order in self mode; in soft / hard mode the
+// queries sorted by MST depth, one launch per depth so that every parent
+// finished in an earlier launch (any parent-before-child order gives the
+// same result, Algorithm 3 reads only the parent's cache).
+struct Order {
+    DevBuf qlist, qpos;
+    std::vector<int64_t> level_start;  // boundaries of the launches, last = n
 };
+
+static void make_order(Index &ix, const int32_t *ids, int64_t n, int ws, hipStream_t s, Order &o) {
+    o.qlist.alloc(n * sizeof(int32_t));
+    o.qpos.alloc(n * sizeof(int32_t));
+    o.level_start.clear();
+    if (ws == VJ_WS_SELF) {
+        if (ids) VJ_HIP(hipMemcpyAsync(o.qlist.p, ids, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        else iota_i32(o.qlist.as<int32_t>(), n, s);
+        iota_i32(o.qpos.as<int32_t>(), n, s);
+        o.level_start = {0, n};
+        return;
+    }
+    DevBuf tmp;
+    order_by_depth(ix.depth.as<int32_t>(), ix.nq, ids, n, o.qlist.as<int32_t>(), o.qpos.as<int32_t>(), tmp, s);
+    // depth of every processing slot, to cut the list into levels
+    std::vector<int32_t> ql((size_t)n), dep((size_t)ix.nq);
+    VJ_HIP(hipMemcpyAsync(ql.data(), o.qlist.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipMemcpyAsync(dep.data(), ix.depth.p, ix.nq * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    o.level_start.push_back(0);
+    for (int64_t i = 1; i < n; ++i) {
+        const int32_t a = ql[i - 1], b = ql[i];
+        VJ_CHECK(a >= 0 && a < ix.nq && b >= 0 && b < ix.nq, VJ_ERR_INVALID_ARG, "query id out of range");
+        if (dep[b] != dep[a]) o.level_start.push_back(i);
+    }
+    o.level_start.push_back(n);
+}
 
 static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const vj_join_params &p,
                      const int32_t *budget, hipStream_t s, Pairs &r) {
@@ -207,45 +237,31 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
              "u8 precision needs integer data in [0, 255]");
     VJ_CHECK(prec == VJ_PREC_FP32 || prec == VJ_PREC_U8, VJ_ERR_UNSUPPORTED,
              "precision not supported by the traversal");
-
-    JoinScratch sc;
-    const int wpb = 4;
-    const int hl = p.hash_log2 > 0 ? p.hash_log2 : 11;
-    VJ_CHECK(hl >= 6 && hl <= 14, VJ_ERR_INVALID_ARG, "hash_log2 must be in [6, 14]");
-    const int wpc = p.waves_per_cu > 0 ? p.waves_per_cu : 16;
-    const int max_blocks0 = std::max(1, num_cus() * std::max(1, wpc / wpb));
     const int beam = (hyb != VJ_HYB_OFF) ? p.hybrid_beam : 0;
+    VJ_CHECK(beam <= 256, VJ_ERR_UNSUPPORTED, "hybrid_beam must be <= 256");
 
-    sc.qlist.alloc(n * sizeof(int32_t));
-    sc.qpos.alloc(n * sizeof(int32_t));
-    if (ws == VJ_WS_SELF) {
-        if (ids) VJ_HIP(hipMemcpyAsync(sc.qlist.p, ids, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        else iota_i32(sc.qlist.as<int32_t>(), n, s);
-        iota_i32(sc.qpos.as<int32_t>(), n, s);
-    } else {
-        order_by_depth(ix.depth.as<int32_t>(), ix.nq, ids, n, sc.qlist.as<int32_t>(),
-                       sc.qpos.as<int32_t>(), sc.sorttmp, s);
-    }
-    // counters: [0] out_count (u64), [2] work, [3] ovf_count, [4] err
-    sc.counters.alloc(64);
+    Order ord;
+    make_order(ix, ids, n, ws, s, ord);
+    const int32_t *qlist = ord.qlist.as<int32_t>(), *qpos = ord.qpos.as<int32_t>();
+
+    // counters: [0..1] out_count (u64), [2] ovf_count, [3] err
+    DevBuf counters(64), argsbuf(sizeof(JoinArgs)), ovf((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
+    DevBuf out_q, out_x, out_d, gh, gil, gild, q2, p2, sl;
     r.stats.alloc((size_t)std::max<int64_t>(n, 1) * 8 * sizeof(int32_t));
-    sc.ovf.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
+    int32_t *ctr = counters.as<int32_t>();
 
     int64_t cap = p.pair_capacity > 0 ? p.pair_capacity : std::max<int64_t>(1 << 16, n * 64);
     for (int attempt = 0; attempt < 4; ++attempt) {
-        sc.out_q.reserve((size_t)cap * sizeof(int32_t));
-        sc.out_x.reserve((size_t)cap * sizeof(int32_t));
-        sc.out_d.reserve((size_t)cap * sizeof(float));
-        ix.gen += 8;
-        const uint32_t G = ix.gen;
-        VJ_HIP(hipMemsetAsync(sc.counters.p, 0, 64, s));
-        int32_t *ctr = sc.counters.as<int32_t>();
-        if (ws != VJ_WS_SELF)
-            stamp_batch(ix.inb.as<int32_t>(), ix.nq, ids, n, (int32_t)G, ctr + 4, s);
+        out_q.reserve((size_t)cap * sizeof(int32_t));
+        out_x.reserve((size_t)cap * sizeof(int32_t));
+        out_d.reserve((size_t)cap * sizeof(float));
+        ix.gen += 1;
+        VJ_HIP(hipMemsetAsync(counters.p, 0, 64, s));
+        if (ws != VJ_WS_SELF) stamp_batch(ix.inb.as<int32_t>(), ix.nq, ids, n, ix.gen, ctr + 3, s);
 
-        TraverseLaunch a{};
-        a.vec = prec == VJ_PREC_U8 ? ix.vec_u8.p : prec == VJ_PREC_BF16 ? ix.vec_bf16.p : ix.vec.p;
-        a.vec32 = ix.vec.as<float>();
+        JoinArgs a{};
+        a.rows = prec == VJ_PREC_U8 ? ix.vec_u8.p : ix.vec.p;
+        a.rows32 = ix.vec.as<float>();
         a.adj = ix.adj.as<int32_t>();
         a.elen = ix.elen.as<float>();
         a.nx = ix.nx;
@@ -254,113 +270,105 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
         a.dp = ix.dp;
         a.entry = ix.entry;
         a.metric = ix.metric;
-        a.prec = prec;
         a.eps = eps;
         a.eps2 = (float)((double)eps * (double)eps);
         a.ws = ws;
-        a.parent = ix.has_mst ? ix.parent.as<int32_t>() : nullptr;
-        a.pub = ix.pub.as<unsigned long long>();
-        a.inb = ix.inb.as<int32_t>();
-        a.seg = ix.seg.as<int64_t>();
-        a.segn = ix.segn.as<int32_t>();
-        a.gen_first = G;
         a.hyb = hyb;
         a.beam = beam;
         a.conv = p.conv_threshold;
         a.ood_ratio = p.ood_ratio;
+        a.gen = ix.gen;
+        a.parent = ix.has_mst ? ix.parent.as<int32_t>() : nullptr;
+        a.inb = ix.inb.as<int32_t>();
+        a.cache = ix.cache.as<int32_t>();
+        a.seg = ix.seg.as<int64_t>();
+        a.segn = ix.segn.as<int32_t>();
         a.budget = budget;
-        a.out_q = sc.out_q.as<int32_t>();
-        a.out_x = sc.out_x.as<int32_t>();
-        a.out_d = sc.out_d.as<float>();
+        a.out_q = out_q.as<int32_t>();
+        a.out_x = out_x.as<int32_t>();
+        a.out_d = out_d.as<float>();
         a.cap = cap;
         a.out_count = reinterpret_cast<unsigned long long *>(ctr);
-        a.work = ctr + 2;
-        a.ovf_count = ctr + 3;
-        a.err = ctr + 4;
         a.stats = r.stats.as<int32_t>();
-        a.ovf = sc.ovf.as<int32_t>();
+        a.err = ctr + 3;
+        VJ_HIP(hipMemcpyAsync(argsbuf.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
 
-        // level 0: LDS visited set; levels >= 1: per-wave global tables
-        int64_t pending = n;
-        const int32_t *lq = sc.qlist.as<int32_t>(), *lp = sc.qpos.as<int32_t>();
-        int32_t hctr[5] = {0, 0, 0, 0, 0};
-        for (int level = 0; pending > 0; ++level) {
-            VJ_CHECK(level <= 2, VJ_ERR_INTERNAL, "spill levels exhausted");
-            const bool spill = level > 0;
-            int hlog, ilcap, max_blocks;
-            if (!spill) {
-                hlog = hl;
-                ilcap = (int)std::min<int64_t>(ix.nx, 16384);
-                max_blocks = max_blocks0;
-            } else if (level == 1) {
-                hlog = std::min(18, ceil_log2(2 * ix.nx) + 1);
-                ilcap = (int)std::min<int64_t>(ix.nx, 1 << 17);
-                max_blocks = std::max(1, std::min<int>(num_cus(), (int)((pending + wpb - 1) / wpb)));
-            } else {
-                hlog = ceil_log2(2 * ix.nx) + 1;
-                ilcap = (int)ix.nx;
-                max_blocks = std::max(1, std::min<int>(4, (int)((pending + wpb - 1) / wpb)));
-            }
-            const int slots = max_blocks * wpb;
-            sc.il_id.reserve((size_t)slots * ilcap * sizeof(int32_t));
-            sc.il_d.reserve((size_t)slots * ilcap * sizeof(float));
-            if (spill) {
-                const size_t gb = (size_t)slots * ((size_t)1 << hlog) * 8;
-                if (sc.ghash.bytes < gb) {
-                    sc.ghash.alloc(gb);
-                    VJ_HIP(hipMemsetAsync(sc.ghash.p, 0, gb, s));
-                    sc.gstamp.alloc((size_t)slots * sizeof(uint32_t));
-                    VJ_HIP(hipMemsetAsync(sc.gstamp.p, 0, sc.gstamp.bytes, s));
-                }
-            }
-            a.qlist = lq;
-            a.qpos = lp;
-            a.n = (int32_t)pending;
-            a.gen = G + (uint32_t)level;
-            a.il_id = sc.il_id.as<int32_t>();
-            a.il_d = sc.il_d.as<float>();
-            a.il_cap = ilcap;
-            a.ghash = spill ? sc.ghash.as<int32_t>() : nullptr;
-            a.gstamp = spill ? sc.gstamp.as<uint32_t>() : nullptr;
-            a.hash_log2 = hlog;
-            a.hash_limit = spill ? (1 << hlog) / 2 : ((1 << hlog) * 3) / 4;
-            a.lds_ints_per_wave = (spill ? 0 : (1 << hlog)) + 64 + (beam > 0 ? 2 * (beam + 64) : 0);
-            VJ_HIP(hipMemsetAsync(ctr + 2, 0, 2 * sizeof(int32_t), s));  // work, ovf_count
-            const int got = launch_traverse(a, spill, max_blocks, wpb, s);
-            VJ_CHECK(got > 0, VJ_ERR_UNSUPPORTED, "no traversal kernel for this row width");
-            VJ_CHECK(got <= slots, VJ_ERR_INTERNAL, "traversal launched more waves than scratch");
+        int32_t hctr[4] = {0, 0, 0, 0};
+        for (size_t lv = 0; lv + 1 < ord.level_start.size(); ++lv) {
+            JoinLaunch L{};
+            L.args = argsbuf.as<JoinArgs>();
+            L.qlist = qlist;
+            L.qpos = qpos;
+            L.first = (int)ord.level_start[lv];
+            L.count = (int)(ord.level_start[lv + 1] - ord.level_start[lv]);
+            L.dp = ix.dp;
+            L.prec = prec;
+            L.spill = false;
+            L.hyb = beam > 0;
+            L.ovf = ovf.as<int32_t>();
+            L.ovf_count = ctr + 2;
+            VJ_HIP(hipMemsetAsync(ctr + 2, 0, sizeof(int32_t), s));
+            VJ_CHECK(launch_join(L, s), VJ_ERR_UNSUPPORTED, "no join kernel for this row width");
             VJ_HIP(hipGetLastError());
             VJ_HIP(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s));
             VJ_HIP(hipStreamSynchronize(s));
-            VJ_CHECK(!(hctr[4] & 8), VJ_ERR_INVALID_ARG, "query id out of range");
-            VJ_CHECK(!(hctr[4] & 2), VJ_ERR_INTERNAL, "a query waited too long for its parent");
-            pending = hctr[3];
-            if (pending > 0) {
-                // re-run the overflowed slots, in processing order (parents first)
+            VJ_CHECK(!(hctr[3] & 8), VJ_ERR_INVALID_ARG, "query id out of range");
+            // queries that outgrew LDS: re-run on global visited sets, in
+            // processing order, with larger tables at each spill level
+            int64_t pending = hctr[2];
+            const int32_t *lq = qlist, *lp = qpos;
+            for (int level = 1; pending > 0; ++level) {
+                VJ_CHECK(level <= 2, VJ_ERR_INTERNAL, "spill levels exhausted");
                 std::vector<int32_t> slots_h((size_t)pending);
-                VJ_HIP(hipMemcpyAsync(slots_h.data(), sc.ovf.p, pending * sizeof(int32_t),
-                                      hipMemcpyDeviceToHost, s));
+                VJ_HIP(hipMemcpyAsync(slots_h.data(), ovf.p, pending * sizeof(int32_t), hipMemcpyDeviceToHost, s));
                 VJ_HIP(hipStreamSynchronize(s));
                 std::sort(slots_h.begin(), slots_h.end());
-                DevBuf sl(pending * sizeof(int32_t));
-                VJ_HIP(hipMemcpyAsync(sl.p, slots_h.data(), pending * sizeof(int32_t),
-                                      hipMemcpyHostToDevice, s));
-                DevBuf q2(pending * sizeof(int32_t)), p2(pending * sizeof(int32_t));
-                gather_slots(lq, lp, sl.as<int32_t>(), pending, q2.as<int32_t>(), p2.as<int32_t>(), s);
+                sl.alloc(pending * sizeof(int32_t));
+                VJ_HIP(hipMemcpyAsync(sl.p, slots_h.data(), pending * sizeof(int32_t), hipMemcpyHostToDevice, s));
+                DevBuf nq2(pending * sizeof(int32_t)), np2(pending * sizeof(int32_t));
+                gather_slots(lq, lp, sl.as<int32_t>(), pending, nq2.as<int32_t>(), np2.as<int32_t>(), s);
                 VJ_HIP(hipStreamSynchronize(s));
-                sc.q2 = std::move(q2);
-                sc.p2 = std::move(p2);
-                lq = sc.q2.as<int32_t>();
-                lp = sc.p2.as<int32_t>();
+                q2 = std::move(nq2);
+                p2 = std::move(np2);
+                lq = q2.as<int32_t>();
+                lp = p2.as<int32_t>();
+                const int hl = level == 1 ? std::min(18, ceil_log2(2 * ix.nx)) : ceil_log2(2 * ix.nx);
+                const int ilc = (int)(level == 1 ? std::min<int64_t>(ix.nx, 1 << 16) : ix.nx);
+                const int64_t chunk = level == 1 ? 128 : 4;
+                gh.reserve((size_t)chunk * ((size_t)1 << hl) * sizeof(int32_t));
+                gil.reserve((size_t)chunk * ilc * sizeof(int32_t));
+                gild.reserve((size_t)chunk * ilc * sizeof(float));
+                VJ_HIP(hipMemsetAsync(ctr + 2, 0, sizeof(int32_t), s));
+                for (int64_t c0 = 0; c0 < pending; c0 += chunk) {
+                    JoinLaunch S = L;
+                    S.qlist = lq;
+                    S.qpos = lp;
+                    S.first = (int)c0;
+                    S.count = (int)std::min<int64_t>(chunk, pending - c0);
+                    S.spill = true;
+                    S.gh = gh.as<int32_t>();
+                    S.hash_log2 = hl;
+                    S.gil = gil.as<int32_t>();
+                    S.gild = gild.as<float>();
+                    S.il_cap = ilc;
+                    VJ_CHECK(launch_join(S, s), VJ_ERR_UNSUPPORTED, "no join kernel for this row width");
+                    VJ_HIP(hipGetLastError());
+                    VJ_HIP(hipStreamSynchronize(s));  // the next chunk reuses the scratch
+                }
+                VJ_HIP(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s));
+                VJ_HIP(hipStreamSynchronize(s));
+                pending = hctr[2];
             }
+            VJ_CHECK(!(hctr[3] & 16), VJ_ERR_INTERNAL, "visited-set probe exceeded the table size");
+            VJ_CHECK(!(hctr[3] & 32), VJ_ERR_INTERNAL, "a worklist entry is not a data node id");
         }
         const int64_t total = (int64_t)(((uint64_t)(uint32_t)hctr[1] << 32) | (uint32_t)hctr[0]);
         if (total <= cap) {
             r.count = total;
             r.n_queries = n;
-            r.q = std::move(sc.out_q);
-            r.x = std::move(sc.out_x);
-            r.dist = std::move(sc.out_d);
+            r.q = std::move(out_q);
+            r.x = std::move(out_x);
+            r.dist = std::move(out_d);
             return;
         }
         cap = total + total / 16 + 1024;
@@ -593,12 +601,11 @@ void vj_pairs_free(vj_pairs *r) { delete r; }
 }  // extern "C"
 
 namespace vj {
-int launch_traverse(const TraverseLaunch &a, bool spill, int max_blocks, int wpb, hipStream_t s) {
-    switch (a.prec) {
-    case VJ_PREC_FP32: return launch_traverse_f32(a, spill, max_blocks, wpb, s);
-    case VJ_PREC_U8: return launch_traverse_u8(a, spill, max_blocks, wpb, s);
-    case VJ_PREC_BF16: return launch_traverse_bf16(a, spill, max_blocks, wpb, s);
-    default: return 0;
+bool launch_join(const JoinLaunch &L, hipStream_t s) {
+    switch (L.prec) {
+    case VJ_PREC_FP32: return launch_join_f32(L, s);
+    case VJ_PREC_U8: return launch_join_u8(L, s);
+    default: return false;
     }
 }
 }  // namespace vj

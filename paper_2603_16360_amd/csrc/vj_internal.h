@@ -81,11 +81,11 @@ struct Index {
     DevBuf depth;    // int32 [nq] depth in the MST (root children: 0)
     bool has_mst = false;
     // join state shared by calls on this index (calls on one index must not overlap)
-    DevBuf pub;      // uint64 [nq] (generation << 32 | cache node) published by each query
+    DevBuf cache;    // int32 [nq] soft work sharing: closest visited data node
     DevBuf inb;      // int32 [nq] generation stamp: query is part of the current call
     DevBuf seg;      // int64 [nq] offset of the query's pairs in the call's output
     DevBuf segn;     // int32 [nq] number of pairs of the query
-    uint32_t gen = 0;
+    int32_t gen = 0;
 };
 
 // ----------------------------------------------------------------- pairs --
@@ -97,59 +97,50 @@ struct Pairs {
 };
 
 // --------------------------------------------------------------- kernels --
-struct TraverseLaunch {
-    // index
-    const void *vec;          // element type per `prec`
-    const float *vec32;       // fp32 rows (query slices, re-checks)
-    const int32_t *adj;
-    const float *elen;
+// Join parameters, resident in device memory for the duration of a call.
+struct JoinArgs {
+    const void *rows;         // rows the distances read: float or uint8 [N][dp]
+    const float *rows32;      // fp32 rows (query slices)
+    const int32_t *adj;       // [N][R]
+    const float *elen;        // [N][R]
     int64_t nx, nq;
-    int32_t R, dp, entry, metric, prec;
-    float eps, eps2;          // L2: compare squared distance with eps2
-    // work
-    const int32_t *qlist;     // [n] query index per processing slot
-    const int32_t *qpos;      // [n] caller position per processing slot
-    int32_t n;
-    int32_t *work;            // next processing slot
-    // work sharing
-    int32_t ws;
-    const int32_t *parent;
-    unsigned long long *pub;
-    const int32_t *inb;
-    int64_t *seg;
-    int32_t *segn;
-    uint32_t gen;             // this pass publishes with gen (first pass) or gen+1 (spill)
-    uint32_t gen_first;       // generation of the first pass of the call
-    // hybrid
-    int32_t hyb, beam, conv;
+    int32_t R, dp, entry, metric;
+    float eps, eps2;          // L2 compares the squared distance with eps2
+    int32_t ws, hyb, beam, conv;
     float ood_ratio;
-    const int32_t *budget;    // by caller position
-    // scratch
-    int32_t *il_id;           // [slots][il_cap]
-    float *il_d;
-    int32_t il_cap;
-    int32_t *ghash;           // [slots][1 << hash_log2] uint64 (spill pass only)
-    uint32_t *gstamp;         // [slots] per-slot query counter of the spill tables
-    int32_t hash_log2, hash_limit;
-    int32_t lds_ints_per_wave;
-    // output
+    int32_t gen;              // stamp of this call in inb[]
+    const int32_t *parent;    // [nq] MST parent node id (-1: entry)
+    const int32_t *inb;       // [nq] == gen: query is part of this call
+    int32_t *cache;           // [nq] soft: closest visited data node
+    int64_t *seg;             // [nq] hard: offset of the query's pairs
+    int32_t *segn;            // [nq] hard: number of them
+    const int32_t *budget;    // [n] by caller position (VJ_HYB_BUDGET)
     int32_t *out_q, *out_x;
     float *out_d;
     int64_t cap;
     unsigned long long *out_count;
-    int32_t *stats;           // [n_caller][8]
-    int32_t *ovf;             // processing slots that must be re-run on the spill path
-    int32_t *ovf_count;
-    int32_t *err;
+    int32_t *stats;           // [n][8] by caller position
+    int32_t *err;             // bit flags
 };
 
-// launch the persistent traversal; spill = global visited hash.  Returns the
-// number of wave slots launched (<= max_slots), 0 if the shape is unsupported.
-int launch_traverse(const TraverseLaunch &a, bool spill, int max_blocks, int waves_per_block,
-                    hipStream_t s);
-int launch_traverse_f32(const TraverseLaunch &a, bool spill, int max_blocks, int wpb, hipStream_t s);
-int launch_traverse_u8(const TraverseLaunch &a, bool spill, int max_blocks, int wpb, hipStream_t s);
-int launch_traverse_bf16(const TraverseLaunch &a, bool spill, int max_blocks, int wpb, hipStream_t s);
+// One launch over a contiguous piece of the processing list.
+struct JoinLaunch {
+    const JoinArgs *args;     // device pointer
+    const int32_t *qlist;     // query index per processing slot
+    const int32_t *qpos;      // caller position per processing slot
+    int first, count, dp, prec;  // slots [first, first + count) of qlist
+    bool spill, hyb;
+    int32_t *gh;              // spill: [count][1 << hash_log2] visited sets, by slot - first
+    int hash_log2;
+    int32_t *gil;             // spill: [count][il_cap] worklists
+    float *gild;
+    int il_cap;
+    int32_t *ovf, *ovf_count; // slots (indices into qlist) that must be re-run
+};
+
+bool launch_join(const JoinLaunch &L, hipStream_t s);
+bool launch_join_f32(const JoinLaunch &L, hipStream_t s);
+bool launch_join_u8(const JoinLaunch &L, hipStream_t s);
 int num_cus();
 
 // edge lengths of every adjacency entry (L2)
