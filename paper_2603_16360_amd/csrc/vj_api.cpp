@@ -524,8 +524,8 @@ vj_status vj_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
     VJ_CHECK(idx != nullptr && out != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
     Index &ix = idx->impl;
     VJ_CHECK(n >= 0, VJ_ERR_INVALID_ARG, "n must be >= 0");
-    VJ_CHECK(query_ids != nullptr || n == ix.nq, VJ_ERR_INVALID_ARG,
-             "query_ids may be NULL only with n == nq");
+    VJ_CHECK(query_ids != nullptr || n == ix.nq || n == 0, VJ_ERR_INVALID_ARG,
+             "query_ids may be NULL only with n == nq or n == 0");
     VJ_CHECK(n < ((int64_t)1 << 31), VJ_ERR_UNSUPPORTED, "n must be < 2^31");
     VJ_CHECK(std::isfinite(eps), VJ_ERR_INVALID_ARG, "eps must be finite");
     VJ_CHECK(metric == ix.metric, VJ_ERR_METRIC_MISMATCH, "join metric differs from the index metric");

@@ -119,18 +119,29 @@ def beta_mixture(n: int, a: np.ndarray, b: np.ndarray, seed: int,
     return out
 
 
+def _bessel_ratio(nu: float, x: float, terms: int = 4000) -> float:
+    """I_nu(x) / I_{nu-1}(x) from the recurrence R_nu = 1 / (2 nu / x + R_{nu+1})
+    evaluated backwards (a continued fraction; no overflow or underflow)."""
+    r = 0.0
+    for k in range(terms, -1, -1):
+        r = 1.0 / (2.0 * (nu + k) / x + r)
+    return r
+
+
 def vmf_kappa_for_mean_cosine(p: int, target: float) -> float:
     """κ of a von Mises-Fisher law on S^{p-1} whose E[cos(x, mu)] = target.
 
-    E[cos] = A_p(κ) = I_{p/2}(κ) / I_{p/2-1}(κ) (Mardia & Jupp, 9.3).
+    E[cos] = A_p(κ) = I_{p/2}(κ) / I_{p/2-1}(κ) (Mardia & Jupp, 9.3),
+    increasing in κ; solved by bisection.
     """
-    from scipy.optimize import brentq
-    from scipy.special import ive
-
-    def f(k: float) -> float:
-        return ive(p / 2.0, k) / ive(p / 2.0 - 1.0, k) - target
-
-    return float(brentq(f, 1e-3, 1e6))
+    lo, hi = 1e-6, 1e7
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if _bessel_ratio(p / 2.0, mid) < target:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
 
 
 def _vmf_cosines(rng: np.random.Generator, n: int, p: int, kappa: float) -> np.ndarray:
