@@ -1,8 +1,266 @@
+// Exact epsilon-join on MFMA tiles (the nested-loop join of Section 2.2, run
+// as a GEMM):  d^2(q, x) = |q|^2 + |x|^2 - 2 <q, x>  (L2)  or  1 - <q, x>  (IP)
+// with <q, x> from bf16 MFMA tiles and fp32 accumulation.  Every pair whose
+// tile value lies below eps plus a proven bound on the tile's error becomes a
+// candidate; each candidate is re-decided from the fp32 inputs in fp64, so the
+// result equals the exact decision dist < eps computed in fp64.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mfma_tile.h"
 #include "tiles.h"
 
 namespace vj {
-void bruteforce_join(const float *, int64_t, const float *, int64_t, int, float, vj_metric,
-                     vj_precision, hipStream_t, Pairs &) {
-    VJ_CHECK(false, VJ_ERR_UNSUPPORTED, "brute force not available");
+namespace {
+
+using mt::floatx4;
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
 }
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// One wave per row: bf16 hi (and lo) copies padded to Kp, squared norm
+// (fp64 sum rounded to fp32), and flags: bit 0 set if a value is not an
+// integer of magnitude <= 256; max |value| and max norm via atomicMax on the
+// (non-negative) float bits.
+__global__ void k_prep(const float *src, int64_t rows, int d, int Kp, uint16_t *hi, uint16_t *lo,
+                       float *norm2, unsigned *maxabs, unsigned *maxnorm, int *flags) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (r >= rows) return;
+    double acc = 0.0;
+    float mabs = 0.f;
+    bool nonint = false;
+    for (int k = lane; k < Kp; k += 64) {
+        const float f = k < d ? src[r * d + k] : 0.f;
+        const uint16_t h = bf16_rne(f);
+        hi[r * Kp + k] = h;
+        if (lo) lo[r * Kp + k] = bf16_rne(f - bf16_to_f(h));
+        acc += (double)f * (double)f;
+        mabs = fmaxf(mabs, fabsf(f));
+        nonint |= !(rintf(f) == f && fabsf(f) <= 256.f);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        acc += __shfl_xor(acc, off);
+        mabs = fmaxf(mabs, __shfl_xor(mabs, off));
+    }
+    if (__ballot(nonint) && lane == 0) atomicOr(flags, 1);
+    if (lane == 0) {
+        norm2[r] = (float)acc;
+        atomicMax(maxabs, __float_as_uint(mabs));
+        atomicMax(maxnorm, __float_as_uint((float)sqrt(acc)));
+    }
+}
+
+// per-query-row threshold on the tile value, including its error bound
+__global__ void k_thresholds(const float *nq2, int64_t nq, double eps, int metric, double e_dot,
+                             double e_fin, float maxnorm_x, float *thr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const double qn = sqrt((double)nq2[i]), xn = (double)maxnorm_x;
+    if (metric == VJ_L2) {
+        const double m2 = 2.0 * e_dot * qn * xn + e_fin * (qn + xn) * (qn + xn);
+        thr[i] = __double2float_ru(eps * eps + m2);            // candidate iff d~^2 < thr
+    } else {
+        const double m = e_dot * qn * xn + e_fin;
+        thr[i] = __double2float_rd(1.0 - eps - m);              // candidate iff <q,x>~ > thr
+    }
+}
+
+// 64 query rows x 128 data rows per workgroup; wave w takes data rows 32w..32w+31
+template <int NSPLIT>
+__global__ void __launch_bounds__(256)
+k_range_tiles(const uint16_t *Qh, const uint16_t *Ql, int64_t nq, const uint16_t *Xh,
+              const uint16_t *Xl, int64_t nx, int Kp, const float *nq2, const float *nx2,
+              const float *thr, int metric, int32_t *cq, int32_t *cx, int64_t cap,
+              unsigned long long *count) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q0 = (int64_t)blockIdx.y * 64;
+    const int64_t x0 = (int64_t)blockIdx.x * 128 + w * 32;
+    floatx4 acc[4][2];
+    mt::tile_64x32<NSPLIT>(Qh, Ql, q0, nq, Xh, Xl, x0, nx, Kp, lane, acc);
+    uint32_t hits = 0;  // bit (rt*8 + ct*4 + i)
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t q = q0 + mt::tile_arow(rt, i, lane);
+                const int64_t x = x0 + mt::tile_brow(ct, lane);
+                if (q < nq && x < nx) {
+                    const float dot = acc[rt][ct][i];
+                    const bool c = metric == VJ_L2 ? (nq2[q] + nx2[x] - 2.f * dot < thr[q])
+                                                   : (dot > thr[q]);
+                    if (c) hits |= 1u << (rt * 8 + ct * 4 + i);
+                }
+            }
+    if (__ballot(hits != 0) == 0) return;
+    int excl;
+    const int total = mt::wave_scan(__popc(hits), lane, excl);
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(count, (unsigned long long)total);
+    base = __shfl(base, 0);
+    int o = 0;
+    for (int b = 0; b < 32; ++b) {
+        if (!(hits & (1u << b))) continue;
+        const int rt = b >> 3, ct = (b >> 2) & 1, i = b & 3;
+        const unsigned long long at = base + excl + o++;
+        if (at < (unsigned long long)cap) {
+            cq[at] = (int32_t)(q0 + mt::tile_arow(rt, i, lane));
+            cx[at] = (int32_t)(x0 + mt::tile_brow(ct, lane));
+        }
+    }
+}
+
+// fp64 decision for every candidate: 8 lanes per candidate
+__global__ void k_recheck(const float *Q, const float *X, int d, int metric, double eps,
+                          const int32_t *cq, const int32_t *cx, int64_t n, int32_t *oq,
+                          int32_t *ox, float *od, unsigned long long *count) {
+    const int lane = threadIdx.x & 63;
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const int p = lane & 7;
+    const bool ok = c < n;
+    const int32_t q = ok ? cq[c] : 0, x = ok ? cx[c] : 0;
+    double acc = 0.0;
+    if (ok) {
+        for (int k = p; k < d; k += 8) {
+            const double a = Q[(int64_t)q * d + k], b = X[(int64_t)x * d + k];
+            if (metric == VJ_L2) { const double t = a - b; acc += t * t; }
+            else acc += a * b;
+        }
+    }
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    const double dist = metric == VJ_L2 ? sqrt(acc) : 1.0 - acc;
+    const bool keep = ok && p == 0 && dist < eps;
+    const uint64_t m = __ballot(keep);
+    if (m == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(count, (unsigned long long)__popcll(m));
+    base = __shfl(base, 0);
+    if (keep) {
+        const unsigned long long at = base + __popcll(m & ((1ull << lane) - 1ull));
+        oq[at] = q;
+        ox[at] = x;
+        od[at] = (float)dist;
+    }
+}
+
+inline unsigned g1(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void prepare_rows(const float *src, int64_t rows, int d, int Kp, bool split, TileRows &t,
+                  hipStream_t s) {
+    t.rows = rows;
+    t.Kp = Kp;
+    t.hi.alloc((size_t)std::max<int64_t>(rows, 1) * Kp * sizeof(uint16_t));
+    if (split) t.lo.alloc((size_t)std::max<int64_t>(rows, 1) * Kp * sizeof(uint16_t));
+    else t.lo.release();
+    t.norm2.alloc((size_t)std::max<int64_t>(rows, 1) * sizeof(float));
+    DevBuf stats(16);
+    VJ_HIP(hipMemsetAsync(stats.p, 0, 16, s));
+    unsigned *u = stats.as<unsigned>();
+    if (rows > 0)
+        hipLaunchKernelGGL(k_prep, dim3(g1(rows, 4)), dim3(256), 0, s, src, rows, d, Kp,
+                           t.hi.as<uint16_t>(), split ? t.lo.as<uint16_t>() : nullptr,
+                           t.norm2.as<float>(), u, u + 1, reinterpret_cast<int *>(u + 2));
+    VJ_HIP(hipGetLastError());
+    unsigned h[4] = {0, 0, 0, 0};
+    VJ_HIP(hipMemcpyAsync(h, stats.p, 16, hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    std::memcpy(&t.maxabs, &h[0], 4);
+    std::memcpy(&t.maxnorm, &h[1], 4);
+    t.small_int = (h[2] & 1) == 0;
+}
+
+void tile_error_bounds(const TileRows &a, const TileRows &b, int nsplit, double &e_dot,
+                       double &e_fin) {
+    const int Kp = a.Kp;
+    const double u32 = std::ldexp(1.0, -24);
+    const double amax = std::max(a.maxabs, b.maxabs);
+    // integer inputs with |v| <= 256 are exact in bf16, and every partial sum
+    // of products, every norm and |q|^2 + |x|^2 stay integers below 2^24: the
+    // tile value is then the exact squared distance
+    if (a.small_int && b.small_int && 2.0 * Kp * amax * amax < 16777216.0) {
+        e_dot = 0.0;
+        e_fin = 0.0;
+        return;
+    }
+    const double u = std::ldexp(1.0, -8);                   // bf16 unit roundoff
+    const double e_in = nsplit == 3 ? 4.0 * u * u : 2.0 * u + u * u;
+    const double n = (double)nsplit * Kp;
+    const double gam = 1.01 * n * u32;                       // fp32 accumulation
+    e_dot = e_in * (1.0 + gam) + gam;                        // |dot~ - dot| <= e_dot |q||x|
+    e_fin = 5.0 * u32;                                       // norms and the final adds
+}
+
+void bruteforce_join(const float *Q, int64_t nq, const float *X, int64_t nx, int d, float eps,
+                     vj_metric metric, vj_precision prec, hipStream_t s, Pairs &out) {
+    out.n_queries = 0;
+    out.count = 0;
+    if (nq == 0 || (metric == VJ_L2 && eps <= 0.0f)) return;
+    const int Kp = ((d + 31) / 32) * 32;
+    const int nsplit = prec == VJ_PREC_FP32 ? 3 : 1;
+    TileRows tq, tx;
+    prepare_rows(Q, nq, d, Kp, nsplit == 3, tq, s);
+    prepare_rows(X, nx, d, Kp, nsplit == 3, tx, s);
+    double e_dot, e_fin;
+    tile_error_bounds(tq, tx, nsplit, e_dot, e_fin);
+    DevBuf thr((size_t)nq * sizeof(float));
+    hipLaunchKernelGGL(k_thresholds, dim3(g1(nq, 256)), dim3(256), 0, s, tq.norm2.as<float>(), nq,
+                       (double)eps, (int)metric, e_dot, e_fin, tx.maxnorm, thr.as<float>());
+    DevBuf ctr(16);
+    int64_t cap = std::max<int64_t>(1 << 20, nq * 64);
+    DevBuf cq, cx;
+    unsigned long long ncand = 0;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        cq.reserve((size_t)cap * sizeof(int32_t));
+        cx.reserve((size_t)cap * sizeof(int32_t));
+        VJ_HIP(hipMemsetAsync(ctr.p, 0, 16, s));
+        const dim3 grid(g1(nx, 128), g1(nq, 64));
+        VJ_CHECK(grid.y <= 65535u, VJ_ERR_UNSUPPORTED, "too many query rows for one call");
+        if (nsplit == 3)
+            hipLaunchKernelGGL(k_range_tiles<3>, grid, dim3(256), 0, s, tq.hi.as<uint16_t>(),
+                               tq.lo.as<uint16_t>(), nq, tx.hi.as<uint16_t>(), tx.lo.as<uint16_t>(),
+                               nx, Kp, tq.norm2.as<float>(), tx.norm2.as<float>(), thr.as<float>(),
+                               (int)metric, cq.as<int32_t>(), cx.as<int32_t>(), cap,
+                               ctr.as<unsigned long long>());
+        else
+            hipLaunchKernelGGL(k_range_tiles<1>, grid, dim3(256), 0, s, tq.hi.as<uint16_t>(),
+                               nullptr, nq, tx.hi.as<uint16_t>(), nullptr, nx, Kp,
+                               tq.norm2.as<float>(), tx.norm2.as<float>(), thr.as<float>(),
+                               (int)metric, cq.as<int32_t>(), cx.as<int32_t>(), cap,
+                               ctr.as<unsigned long long>());
+        VJ_HIP(hipGetLastError());
+        VJ_HIP(hipMemcpyAsync(&ncand, ctr.p, 8, hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipStreamSynchronize(s));
+        if ((int64_t)ncand <= cap) break;
+        cap = (int64_t)ncand + (int64_t)ncand / 8 + 1024;
+        VJ_CHECK(attempt < 2, VJ_ERR_INTERNAL, "candidate capacity did not converge");
+    }
+    out.q.alloc((size_t)std::max<unsigned long long>(ncand, 1) * sizeof(int32_t));
+    out.x.alloc((size_t)std::max<unsigned long long>(ncand, 1) * sizeof(int32_t));
+    out.dist.alloc((size_t)std::max<unsigned long long>(ncand, 1) * sizeof(float));
+    VJ_HIP(hipMemsetAsync(ctr.as<char>() + 8, 0, 8, s));
+    if (ncand > 0)
+        hipLaunchKernelGGL(k_recheck, dim3(g1((int64_t)ncand * 8, 256)), dim3(256), 0, s, Q, X, d,
+                           (int)metric, (double)eps, cq.as<int32_t>(), cx.as<int32_t>(),
+                           (int64_t)ncand, out.q.as<int32_t>(), out.x.as<int32_t>(),
+                           out.dist.as<float>(), ctr.as<unsigned long long>() + 1);
+    VJ_HIP(hipGetLastError());
+    unsigned long long kept = 0;
+    VJ_HIP(hipMemcpyAsync(&kept, ctr.as<char>() + 8, 8, hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    out.count = (int64_t)kept;
+    out.n_candidates = (int64_t)ncand;
+}
+
 }  // namespace vj

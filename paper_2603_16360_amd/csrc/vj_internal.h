@@ -92,6 +92,7 @@ struct Index {
 struct Pairs {
     int64_t count = 0;
     int64_t n_queries = 0;   // rows of stats (0 for brute force)
+    int64_t n_candidates = 0; // brute force: pairs re-checked in fp64
     DevBuf q, x, dist;       // int32, int32, float [count]
     DevBuf stats;            // int32 [n_queries][8]
 };
