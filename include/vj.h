@@ -78,7 +78,7 @@ typedef struct vj_pairs vj_pairs;
 
 typedef struct {
     int32_t R;           /* max out-degree, 1..64 */
-    int32_t K_cand;      /* exact-kNN candidates per node before pruning (0: 2R) */
+    int32_t K_cand;      /* exact-kNN candidates per node before pruning, <= 112 (0: min(2R, 112)) */
     int32_t build_mst;   /* 1: compute the query MST (needed for SOFT/HARD) */
     int32_t copies;      /* bit mask of low-precision copies: 1 bf16, 2 fp8, 4 u8 */
 } vj_build_params;

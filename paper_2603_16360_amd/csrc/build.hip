@@ -1,7 +1,588 @@
+// Merged-graph construction on the GPU (Section 4.3: one graph over Q and X;
+// Appendix C: the RNG edge rule).  The paper treats the graph index as a
+// black box; this build makes it deterministic, ties broken by smaller id:
+//   1. exact K nearest neighbours of every node (MFMA tiles + a running
+//      top-K per row), re-ranked by direct fp32 distances;
+//   2. RNG prune of each list: scan by (distance, id), keep v unless an
+//      already-kept w is closer to v than the owner is; at most R kept;
+//   3. reverse edges: the candidates of v are its pruned list plus every u
+//      whose pruned list holds v; all of them if they fit in R, otherwise
+//      the RNG prune of them;
+//   4. entry = node nearest to the fp64 centroid;
+//   5. connectivity repair from the entry: the smallest unreachable node
+//      gets an edge from its nearest reachable node with a free slot (else
+//      it replaces that node's longest edge), until all are reachable.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "build.h"
+#include "mfma_tile.h"
+#include "tiles.h"
+#include "util.h"
 
 namespace vj {
-void build_graph(Index &, int, hipStream_t) {
-    VJ_CHECK(false, VJ_ERR_UNSUPPORTED, "graph build not available");
+namespace {
+
+using mt::floatx4;
+constexpr int kKnnCap = 384;   // per-row candidate buffer of the top-K sweep
+constexpr int kCandMax = 1024; // candidates a reverse-edge prune considers
+
+// ------------------------------------------------------------------ kNN --
+// A wave owns 16 rows and sweeps all N rows as columns, 128 per step.  Each
+// row keeps a buffer [K best | pending] in global memory; an element enters
+// the buffer when its key (|x|^2 - 2<u,x>, same order as |u-x|^2) is <= the
+// row's current K-th key.  After a step, rows with > K + 128 entries are
+// sorted and cut back to K.
+template <int NSPLIT>
+__global__ void __launch_bounds__(256)
+k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2, int K,
+      float *bkey, int32_t *bid) {
+    __shared__ float s_tau[4][16];
+    __shared__ int s_cnt[4][16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * 64 + w * 16;
+    if (lane < 16) { s_tau[w][lane] = INFINITY; s_cnt[w][lane] = 0; }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+
+    auto merge_row = [&](int r) {
+        const int64_t row = r0 + r;
+        const int c = min(s_cnt[w][r], kKnnCap);
+        float key[8];
+        int id[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = j * 64 + lane;
+            const bool ok = e < c && row < N;
+            key[j] = ok ? bkey[row * kKnnCap + e] : INFINITY;
+            id[j] = ok ? bid[row * kKnnCap + e] : 0x7fffffff;
+        }
+        mt::wave_sort<8>(key, id, lane);
+        const int keep = min(c, K);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = j * 64 + lane;
+            if (e < K && row < N) {
+                bkey[row * kKnnCap + e] = e < keep ? key[j] : INFINITY;
+                bid[row * kKnnCap + e] = e < keep ? id[j] : -1;
+            }
+        }
+        // K-th key (element K-1) is register (K-1)/64 of lane (K-1)%64
+        float kth = INFINITY;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (j == (K - 1) / 64) kth = __shfl(key[j], (K - 1) & 63);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        if (lane == 0) {
+            s_cnt[w][r] = keep;
+            s_tau[w][r] = keep >= K ? kth : INFINITY;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    };
+
+    for (int64_t c0 = 0; c0 < N; c0 += 128) {
+        floatx4 acc[8];
+        mt::tile_16x128<NSPLIT>(Ah, Al, r0, N, Ah, Al, c0, N, Kp, lane, acc);
+#pragma unroll
+        for (int ct = 0; ct < 8; ++ct)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = (lane >> 4) * 4 + i;
+                const int64_t row = r0 + r;
+                const int64_t col = c0 + ct * 16 + (lane & 15);
+                if (row < N && col < N && col != row) {
+                    const float key = n2[col] - 2.f * acc[ct][i];
+                    if (key <= s_tau[w][r]) {
+                        const int at = atomicAdd(&s_cnt[w][r], 1);
+                        if (at < kKnnCap) {
+                            bkey[row * kKnnCap + at] = key;
+                            bid[row * kKnnCap + at] = (int32_t)col;
+                        }
+                    }
+                }
+            }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        for (int r = 0; r < 16; ++r)
+            if (s_cnt[w][r] > K + 128) merge_row(r);
+    }
+    for (int r = 0; r < 16; ++r) merge_row(r);
 }
+
+// --------------------------------------------------- row distance helper --
+// squared L2 distances from row `u` to up to 8 rows at once: lane group g
+// (8 lanes) handles ids[g]; returns the group's total in every lane of it.
+template <int DP>
+__device__ __forceinline__ float dist8(const float *vec, int32_t u, int32_t v, int lane) {
+    constexpr int CH = DP / 4;             // float4 chunks per row
+    constexpr int PER = (CH + 7) / 8;       // chunks per lane
+    const int p = lane & 7;
+    const float4 *a = reinterpret_cast<const float4 *>(vec + (size_t)u * DP);
+    const float4 *b = reinterpret_cast<const float4 *>(vec + (size_t)v * DP);
+    float acc = 0.f;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int c = p + 8 * t;
+        if (c < CH) {
+            const float4 x = a[c], y = b[c];
+            float q;
+            q = x.x - y.x; acc = fmaf(q, q, acc);
+            q = x.y - y.y; acc = fmaf(q, q, acc);
+            q = x.z - y.z; acc = fmaf(q, q, acc);
+            q = x.w - y.w; acc = fmaf(q, q, acc);
+        }
+    }
+    acc += __shfl_xor(acc, 4);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 1);
+    return acc;
+}
+
+// Exact re-rank of the K buffered neighbours of every row: direct fp32 squared
+// distances, sorted by (distance, id); the first Kc are written out.
+template <int DP>
+__global__ void __launch_bounds__(256)
+k_rerank(const float *vec, int64_t N, const int32_t *bid, int K, int Kc, int32_t *out_id,
+         float *out_d2) {
+    const int lane = threadIdx.x & 63;
+    const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (u >= N) return;
+    float key[2];
+    int id[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) { key[j] = INFINITY; id[j] = 0x7fffffff; }
+    for (int base = 0; base < K; base += 8) {
+        const int e = base + (lane >> 3);
+        const int32_t v = e < K ? bid[u * kKnnCap + e] : -1;
+        const bool ok = e < K && v >= 0 && v < N && v != u;
+        const float d2 = dist8<DP>(vec, (int32_t)u, ok ? v : (int32_t)u, lane);
+        // element e goes to register e / 64 of lane e % 64
+        for (int g = 0; g < 8; ++g) {
+            const int ee = base + g;
+            const float dd = __shfl(d2, g * 8);
+            const int vv = __shfl(v, g * 8);
+            const bool okk = __shfl((int)ok, g * 8) != 0;
+            if (ee < 128 && (ee & 63) == lane) {
+                const float kk = okk ? dd : INFINITY;
+                const int ii = okk ? vv : 0x7fffffff;
+                if (ee < 64) { key[0] = kk; id[0] = ii; }
+                else { key[1] = kk; id[1] = ii; }
+            }
+        }
+    }
+    mt::wave_sort<2>(key, id, lane);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int e = j * 64 + lane;
+        if (e < Kc) {
+            const bool ok = key[j] < INFINITY;
+            out_id[u * Kc + e] = ok ? id[j] : -1;
+            out_d2[u * Kc + e] = key[j];
+        }
+    }
+}
+
+// RNG prune of one wave's candidate list (sorted by (d2, id), m entries, in
+// LDS).  keep v unless a kept w has d2(w, v) < d2(u, v); at most R kept.
+template <int DP>
+__device__ __forceinline__ int rng_prune(const float *vec, const int32_t *cid, const float *cd2,
+                                         int m, int R, int32_t *kept, int lane) {
+    int nk = 0;
+    for (int i = 0; i < m && nk < R; ++i) {
+        const int32_t v = cid[i];
+        const float dv = cd2[i];
+        if (v < 0) continue;
+        bool blocked = false;
+        for (int b0 = 0; b0 < nk && !blocked; b0 += 8) {
+            const int b = b0 + (lane >> 3);
+            const int32_t wv = b < nk ? kept[b] : v;
+            const float d2 = dist8<DP>(vec, wv, v, lane);
+            blocked = __ballot(b < nk && d2 < dv) != 0;
+        }
+        if (!blocked) {
+            if (lane == 0) kept[nk] = v;
+            ++nk;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    return nk;
+}
+
+// forward prune of every node's re-ranked kNN list
+template <int DP>
+__global__ void __launch_bounds__(256)
+k_prune_fwd(const float *vec, int64_t N, const int32_t *kid, const float *kd2, int Kc, int R,
+            int32_t *fwd, float *fwd_d2, int32_t *fdeg, int32_t *indeg) {
+    __shared__ int32_t s_kept[4][64];
+    __shared__ int32_t s_cid[4][256];
+    __shared__ float s_cd[4][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t u = (int64_t)blockIdx.x * 4 + w;
+    if (u >= N) return;
+    for (int e = lane; e < Kc; e += 64) { s_cid[w][e] = kid[u * Kc + e]; s_cd[w][e] = kd2[u * Kc + e]; }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    const int nk = rng_prune<DP>(vec, s_cid[w], s_cd[w], Kc, R, s_kept[w], lane);
+    for (int e = lane; e < R; e += 64) {
+        const int32_t v = e < nk ? s_kept[w][e] : -1;
+        fwd[u * R + e] = v;
+        float dv = INFINITY;
+        for (int t = 0; t < Kc; ++t)
+            if (s_cid[w][t] == v) { dv = s_cd[w][t]; break; }
+        fwd_d2[u * R + e] = e < nk ? dv : INFINITY;
+        if (e < nk) atomicAdd(&indeg[v], 1);
+    }
+    if (lane == 0) fdeg[u] = nk;
+}
+
+__global__ void k_scatter_rev(int64_t N, int R, const int32_t *fwd, const float *fwd_d2,
+                              const int64_t *roff, int32_t *rpos, int32_t *rid, float *rd2) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= N * R) return;
+    const int32_t v = fwd[e];
+    if (v < 0) return;
+    const int64_t u = e / R;
+    const int at = atomicAdd(&rpos[v], 1);
+    rid[roff[v] + at] = (int32_t)u;
+    rd2[roff[v] + at] = fwd_d2[e];
+}
+
+// final rows: fwd(v) + rev(v), sorted by (d2, id), deduplicated; kept whole
+// if <= R, else RNG-pruned to R.  Reverse lists longer than the buffer keep
+// their smallest (d2, id) entries (streamed through a sorted 1024 buffer).
+template <int DP>
+__global__ void __launch_bounds__(256)
+k_prune_rev(const float *vec, int64_t N, int R, const int32_t *fwd, const float *fwd_d2,
+            const int32_t *fdeg, const int64_t *roff, const int32_t *rid, const float *rd2,
+            int32_t *adj) {
+    __shared__ int32_t s_kept[4][64];
+    __shared__ int32_t s_cid[4][kCandMax];
+    __shared__ float s_cd[4][kCandMax];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t v = (int64_t)blockIdx.x * 4 + w;
+    if (v >= N) return;
+    float key[16];
+    int id[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) { key[j] = INFINITY; id[j] = 0x7fffffff; }
+    const int nf = fdeg[v];
+    const int64_t r0 = roff[v], nr = roff[v + 1] - r0;
+    const int64_t total = nf + nr;
+    // stream all candidates through the sorted buffer, 256 new ones at a time
+    for (int64_t base = 0; base < total; base += 256) {
+#pragma unroll
+        for (int j = 12; j < 16; ++j) {
+            const int64_t e = base + (j - 12) * 64 + lane;
+            float k = INFINITY;
+            int i = 0x7fffffff;
+            if (e < total) {
+                if (e < nf) { i = fwd[v * R + e]; k = fwd_d2[v * R + e]; }
+                else { i = rid[r0 + (e - nf)]; k = rd2[r0 + (e - nf)]; }
+            }
+            key[j] = k;
+            id[j] = i;
+        }
+        mt::wave_sort<16>(key, id, lane);
+    }
+    // dedup (equal ids are adjacent: same id, same squared distance); when
+    // more than 1024 candidates were streamed only the first 768 of the
+    // sorted buffer are exact ranks, so only those are used
+    const int limit = total > kCandMax ? 768 : kCandMax;
+    int m = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int up = __shfl_up(id[j], 1);
+        const int last = j > 0 ? __shfl(id[j > 0 ? j - 1 : 0], 63) : -2;
+        const int prev = lane == 0 ? last : up;
+        const bool keep = (j * 64 + lane) < limit && key[j] < INFINITY && id[j] != 0x7fffffff &&
+                          id[j] != prev;
+        const uint64_t mk = __ballot(keep);
+        if (keep) {
+            const int at = m + __popcll(mk & ((1ull << lane) - 1ull));
+            s_cid[w][at] = id[j];
+            s_cd[w][at] = key[j];
+        }
+        m += __popcll(mk);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    int nk;
+    if (m <= R) {
+        for (int e = lane; e < m; e += 64) s_kept[w][e] = s_cid[w][e];
+        nk = m;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        nk = rng_prune<DP>(vec, s_cid[w], s_cd[w], m, R, s_kept[w], lane);
+    }
+    for (int e = lane; e < R; e += 64) adj[v * R + e] = e < nk ? s_kept[w][e] : -1;
+}
+
+// ------------------------------------------------------- entry point --
+__global__ void k_centroid(const float *vec, int64_t N, int dp, double *sum) {
+    const int c = blockIdx.y * blockDim.x + threadIdx.x;
+    if (c >= dp) return;
+    double acc = 0.0;
+    for (int64_t r = blockIdx.x; r < N; r += gridDim.x) acc += (double)vec[r * dp + c];
+    atomicAdd(&sum[c], acc);
+}
+
+__global__ void k_centroid_dist(const float *vec, int64_t N, int dp, const double *sum,
+                                double *dist, unsigned long long *best) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    double acc = 0.0;
+    for (int c = 0; c < dp; ++c) {
+        const double t = (double)vec[r * dp + c] - sum[c] / (double)N;
+        acc += t * t;
+    }
+    dist[r] = acc;
+    atomicMin(best, (unsigned long long)__double_as_longlong(acc));
+}
+
+__global__ void k_argmin_id(const double *dist, int64_t N, const unsigned long long *best,
+                            int *id) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    if ((unsigned long long)__double_as_longlong(dist[r]) == *best) atomicMin(id, (int)r);
+}
+
+// ------------------------------------------------------ connectivity --
+__global__ void k_bfs_step(const int32_t *adj, int R, const int32_t *front, int nf, int *seen,
+                           int32_t *next, int *nnext) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nf * R) return;
+    const int32_t u = front[t / R];
+    const int32_t v = adj[(int64_t)u * R + t % R];
+    if (v < 0) return;
+    if (atomicExch(&seen[v], 1) == 0) next[atomicAdd(nnext, 1)] = v;
+}
+
+__global__ void k_first_unseen(const int *seen, int64_t N, int *first) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < N && !seen[r]) atomicMin(first, (int)r);
+}
+
+// nearest reached node to w: overall and among nodes with a free slot;
+// results packed as (float bits << 32 | id) so atomicMin gives (d2, id) order
+__global__ void k_nearest_reached(const float *vec, int64_t N, int dp, int32_t w, const int *seen,
+                                  const int32_t *adj, int R, unsigned long long *best_any,
+                                  unsigned long long *best_free) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N || !seen[p]) return;
+    float acc = 0.f;
+    for (int c = 0; c < dp; ++c) {
+        const float t = vec[p * dp + c] - vec[(int64_t)w * dp + c];
+        acc = fmaf(t, t, acc);
+    }
+    const unsigned long long key = ((unsigned long long)__float_as_uint(acc) << 32) | (uint32_t)p;
+    atomicMin(best_any, key);
+    if (adj[p * R + R - 1] < 0) atomicMin(best_free, key);
+}
+
+// put w into row p (free slot, else the last = longest slot), then re-sort
+// the row by (d2, id); one wave
+__global__ void k_attach(const float *vec, int dp, int32_t *adj, int R, int32_t p, int32_t w) {
+    __shared__ float s_d[64];
+    __shared__ int32_t s_i[64];
+    const int lane = threadIdx.x;
+    int32_t *row = adj + (int64_t)p * R;
+    int deg = 0;
+    for (int j = 0; j < R; ++j) deg += row[j] >= 0;
+    const int slot = deg < R ? deg : R - 1;
+    int32_t v = lane < R ? row[lane] : -1;
+    if (lane == slot) v = w;
+    float acc = INFINITY;
+    if (v >= 0) {
+        acc = 0.f;
+        for (int c = 0; c < dp; ++c) {
+            const float t = vec[(int64_t)p * dp + c] - vec[(int64_t)v * dp + c];
+            acc = fmaf(t, t, acc);
+        }
+    }
+    float key[1] = {acc};
+    int id[1] = {v >= 0 ? v : 0x7fffffff};
+    mt::wave_sort<1>(key, id, lane);
+    if (lane < R) row[lane] = key[0] < INFINITY ? id[0] : -1;
+    (void)s_d;
+    (void)s_i;
+}
+
+inline unsigned g1b(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int DP>
+void launch_rows(const float *vec, int64_t N, int R, int K, int Kc, const int32_t *bid,
+                 int32_t *kid, float *kd2, int32_t *fwd, float *fwd_d2, int32_t *fdeg,
+                 int32_t *indeg, hipStream_t s) {
+    hipLaunchKernelGGL(k_rerank<DP>, dim3(g1b(N, 4)), dim3(256), 0, s, vec, N, bid, K, Kc, kid, kd2);
+    hipLaunchKernelGGL(k_prune_fwd<DP>, dim3(g1b(N, 4)), dim3(256), 0, s, vec, N, kid, kd2, Kc, R,
+                       fwd, fwd_d2, fdeg, indeg);
+}
+
+template <int DP>
+void launch_rev(const float *vec, int64_t N, int R, const int32_t *fwd, const float *fwd_d2,
+                const int32_t *fdeg, const int64_t *roff, const int32_t *rid, const float *rd2,
+                int32_t *adj, hipStream_t s) {
+    hipLaunchKernelGGL(k_prune_rev<DP>, dim3(g1b(N, 4)), dim3(256), 0, s, vec, N, R, fwd, fwd_d2,
+                       fdeg, roff, rid, rd2, adj);
+}
+
+#define VJ_DP_SWITCH(dp, CALL)                                                     \
+    switch (dp) {                                                                  \
+    case 32: { constexpr int DP = 32; CALL; } break;                               \
+    case 64: { constexpr int DP = 64; CALL; } break;                               \
+    case 96: { constexpr int DP = 96; CALL; } break;                               \
+    case 128: { constexpr int DP = 128; CALL; } break;                             \
+    case 192: { constexpr int DP = 192; CALL; } break;                             \
+    case 256: { constexpr int DP = 256; CALL; } break;                             \
+    case 384: { constexpr int DP = 384; CALL; } break;                             \
+    case 512: { constexpr int DP = 512; CALL; } break;                             \
+    case 768: { constexpr int DP = 768; CALL; } break;                             \
+    case 1024: { constexpr int DP = 1024; CALL; } break;                           \
+    default: VJ_CHECK(false, VJ_ERR_UNSUPPORTED, "row width");                     \
+    }
+
+}  // namespace
+
+void build_graph(Index &ix, int kc, hipStream_t s) {
+    const int64_t N = ix.N;
+    const int R = ix.R, dp = ix.dp;
+    VJ_CHECK(N >= 2, VJ_ERR_INVALID_ARG, "need at least two vectors");
+    kc = (int)std::min<int64_t>(kc, N - 1);
+    const int K = std::min(128, kc + 16);  // top-K of the tile sweep, re-ranked to kc
+    const float *vec = ix.vec.as<float>();
+
+    // 1. kNN on MFMA tiles over all nodes, then exact re-rank
+    TileRows t;
+    const int Kp = ((dp + 31) / 32) * 32;
+    prepare_rows(vec, N, dp, Kp, true, t, s);
+    double e_dot, e_fin;
+    tile_error_bounds(t, t, 1, e_dot, e_fin);
+    const int nsplit = (e_dot == 0.0) ? 1 : 3;
+    DevBuf bkey((size_t)N * kKnnCap * sizeof(float)), bidb((size_t)N * kKnnCap * sizeof(int32_t));
+    if (nsplit == 3)
+        hipLaunchKernelGGL(k_knn<3>, dim3(g1b(N, 64)), dim3(256), 0, s, t.hi.as<uint16_t>(),
+                           t.lo.as<uint16_t>(), N, Kp, t.norm2.as<float>(), K, bkey.as<float>(),
+                           bidb.as<int32_t>());
+    else
+        hipLaunchKernelGGL(k_knn<1>, dim3(g1b(N, 64)), dim3(256), 0, s, t.hi.as<uint16_t>(),
+                           nullptr, N, Kp, t.norm2.as<float>(), K, bkey.as<float>(),
+                           bidb.as<int32_t>());
+    VJ_HIP(hipGetLastError());
+    t.hi.release();
+    t.lo.release();
+    bkey.release();
+
+    // 2. re-rank + forward prune
+    DevBuf kid((size_t)N * kc * sizeof(int32_t)), kd2((size_t)N * kc * sizeof(float));
+    DevBuf fwd((size_t)N * R * sizeof(int32_t)), fwd_d2((size_t)N * R * sizeof(float));
+    DevBuf fdeg((size_t)N * sizeof(int32_t)), indeg((size_t)N * sizeof(int32_t));
+    VJ_HIP(hipMemsetAsync(indeg.p, 0, indeg.bytes, s));
+    VJ_DP_SWITCH(dp, (launch_rows<DP>(vec, N, R, K, kc, bidb.as<int32_t>(), kid.as<int32_t>(),
+                                      kd2.as<float>(), fwd.as<int32_t>(), fwd_d2.as<float>(),
+                                      fdeg.as<int32_t>(), indeg.as<int32_t>(), s)));
+    VJ_HIP(hipGetLastError());
+    bidb.release();
+
+    // 3. reverse lists (CSR by target), then the final rows
+    std::vector<int32_t> indeg_h((size_t)N);
+    VJ_HIP(hipMemcpyAsync(indeg_h.data(), indeg.p, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> roff_h((size_t)N + 1, 0);
+    for (int64_t v = 0; v < N; ++v) roff_h[v + 1] = roff_h[v] + indeg_h[v];
+    DevBuf roff((size_t)(N + 1) * sizeof(int64_t)), rpos((size_t)N * sizeof(int32_t));
+    DevBuf rid((size_t)std::max<int64_t>(roff_h[N], 1) * sizeof(int32_t));
+    DevBuf rd2((size_t)std::max<int64_t>(roff_h[N], 1) * sizeof(float));
+    VJ_HIP(hipMemcpyAsync(roff.p, roff_h.data(), (N + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    VJ_HIP(hipMemsetAsync(rpos.p, 0, rpos.bytes, s));
+    hipLaunchKernelGGL(k_scatter_rev, dim3(g1b(N * R, 256)), dim3(256), 0, s, N, R,
+                       fwd.as<int32_t>(), fwd_d2.as<float>(), roff.as<int64_t>(),
+                       rpos.as<int32_t>(), rid.as<int32_t>(), rd2.as<float>());
+    ix.adj.alloc((size_t)N * R * sizeof(int32_t));
+    VJ_DP_SWITCH(dp, (launch_rev<DP>(vec, N, R, fwd.as<int32_t>(), fwd_d2.as<float>(),
+                                     fdeg.as<int32_t>(), roff.as<int64_t>(), rid.as<int32_t>(),
+                                     rd2.as<float>(), ix.adj.as<int32_t>(), s)));
+    VJ_HIP(hipGetLastError());
+
+    // 4. entry = node nearest to the fp64 centroid (ties: smaller id)
+    {
+        DevBuf sum((size_t)dp * sizeof(double)), dist((size_t)N * sizeof(double)), best(16);
+        VJ_HIP(hipMemsetAsync(sum.p, 0, sum.bytes, s));
+        VJ_HIP(hipMemsetAsync(best.p, 0xff, 8, s));
+        VJ_HIP(hipMemsetAsync(best.as<char>() + 8, 0x7f, 4, s));
+        hipLaunchKernelGGL(k_centroid, dim3(std::min<int64_t>(N, 1024), g1b(dp, 128)), dim3(128), 0, s,
+                           vec, N, dp, sum.as<double>());
+        hipLaunchKernelGGL(k_centroid_dist, dim3(g1b(N, 256)), dim3(256), 0, s, vec, N, dp,
+                           sum.as<double>(), dist.as<double>(), best.as<unsigned long long>());
+        hipLaunchKernelGGL(k_argmin_id, dim3(g1b(N, 256)), dim3(256), 0, s, dist.as<double>(), N,
+                           best.as<unsigned long long>(), reinterpret_cast<int *>(best.as<char>() + 8));
+        int e = 0;
+        VJ_HIP(hipMemcpyAsync(&e, best.as<char>() + 8, 4, hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipStreamSynchronize(s));
+        VJ_CHECK(e >= 0 && e < N, VJ_ERR_INTERNAL, "entry point");
+        ix.entry = e;
+    }
+
+    // 5. connectivity repair from the entry
+    {
+        DevBuf seen((size_t)N * sizeof(int)), fa((size_t)N * sizeof(int32_t)),
+            fb((size_t)N * sizeof(int32_t)), misc(32);
+        int *seenp = seen.as<int>();
+        int32_t *misc_i = misc.as<int32_t>();
+        auto bfs_from = [&](int32_t start, bool reset) {
+            if (reset) VJ_HIP(hipMemsetAsync(seen.p, 0, seen.bytes, s));
+            int one = 1;
+            VJ_HIP(hipMemcpyAsync(seenp + start, &one, sizeof(int), hipMemcpyHostToDevice, s));
+            VJ_HIP(hipMemcpyAsync(fa.p, &start, sizeof(int32_t), hipMemcpyHostToDevice, s));
+            int nf = 1;
+            int32_t *cur = fa.as<int32_t>(), *nxt = fb.as<int32_t>();
+            for (int64_t level = 0; nf > 0 && level <= N; ++level) {
+                VJ_HIP(hipMemsetAsync(misc_i, 0, sizeof(int), s));
+                hipLaunchKernelGGL(k_bfs_step, dim3(g1b((int64_t)nf * R, 256)), dim3(256), 0, s,
+                                   ix.adj.as<int32_t>(), R, cur, nf, seenp, nxt, misc_i);
+                VJ_HIP(hipMemcpyAsync(&nf, misc_i, sizeof(int), hipMemcpyDeviceToHost, s));
+                VJ_HIP(hipStreamSynchronize(s));
+                std::swap(cur, nxt);
+            }
+        };
+        bfs_from(ix.entry, true);
+        const int64_t max_iter = std::min<int64_t>(N, 200000);
+        for (int64_t iter = 0;; ++iter) {
+            VJ_CHECK(iter <= max_iter, VJ_ERR_INTERNAL, "connectivity repair did not converge");
+            int first = 0x7fffffff;
+            VJ_HIP(hipMemcpyAsync(misc_i, &first, sizeof(int), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_first_unseen, dim3(g1b(N, 256)), dim3(256), 0, s, seenp, N, misc_i);
+            VJ_HIP(hipMemcpyAsync(&first, misc_i, sizeof(int), hipMemcpyDeviceToHost, s));
+            VJ_HIP(hipStreamSynchronize(s));
+            if (first == 0x7fffffff) break;
+            unsigned long long init[2] = {~0ull, ~0ull}, got[2];
+            VJ_HIP(hipMemcpyAsync(misc.as<char>() + 8, init, 16, hipMemcpyHostToDevice, s));
+            unsigned long long *bests = reinterpret_cast<unsigned long long *>(misc.as<char>() + 8);
+            hipLaunchKernelGGL(k_nearest_reached, dim3(g1b(N, 256)), dim3(256), 0, s, vec, N, dp,
+                               (int32_t)first, seenp, ix.adj.as<int32_t>(), R, bests, bests + 1);
+            VJ_HIP(hipMemcpyAsync(got, bests, 16, hipMemcpyDeviceToHost, s));
+            VJ_HIP(hipStreamSynchronize(s));
+            const bool has_free = got[1] != ~0ull;
+            const int32_t p = (int32_t)(uint32_t)(has_free ? got[1] : got[0]);
+            VJ_CHECK(p >= 0 && p < N, VJ_ERR_INTERNAL, "repair source");
+            hipLaunchKernelGGL(k_attach, dim3(1), dim3(64), 0, s, vec, dp, ix.adj.as<int32_t>(), R, p,
+                               (int32_t)first);
+            ix.repairs += 1;
+            // a new edge only adds reachability; an overwritten edge may remove some
+            if (has_free) bfs_from((int32_t)first, false);
+            else bfs_from(ix.entry, true);
+        }
+    }
+
+    // 6. edge lengths
+    ix.elen.alloc((size_t)N * R * sizeof(float));
+    launch_edge_lengths(vec, dp, ix.adj.as<int32_t>(), N, R, ix.elen.as<float>(), s);
+    VJ_HIP(hipGetLastError());
+    VJ_HIP(hipStreamSynchronize(s));
+}
+
 }  // namespace vj

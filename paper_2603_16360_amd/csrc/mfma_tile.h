@@ -67,9 +67,81 @@ __device__ __forceinline__ void tile_64x32(const uint16_t *Ah, const uint16_t *A
     }
 }
 
+// A wave's 16 x 128 block: 16 rows of A against 8 slices of 16 rows of B.
+template <int NSPLIT>
+__device__ __forceinline__ void tile_16x128(const uint16_t *Ah, const uint16_t *Al, int64_t a0,
+                                            int64_t na, const uint16_t *Bh, const uint16_t *Bl,
+                                            int64_t b0, int64_t nb, int Kp, int lane,
+                                            floatx4 acc[8]) {
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    for (int k0 = 0; k0 < Kp; k0 += 32) {
+        const bf16x8 a = load8(Ah, a0 + r16, na, Kp, k0 + kq);
+        bf16x8 b[8];
+#pragma unroll
+        for (int ct = 0; ct < 8; ++ct) b[ct] = load8(Bh, b0 + ct * 16 + r16, nb, Kp, k0 + kq);
+#pragma unroll
+        for (int ct = 0; ct < 8; ++ct)
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[ct], acc[ct], 0, 0, 0);
+        if (NSPLIT == 3) {
+            const bf16x8 al = load8(Al, a0 + r16, na, Kp, k0 + kq);
+#pragma unroll
+            for (int ct = 0; ct < 8; ++ct) {
+                const bf16x8 bl = load8(Bl, b0 + ct * 16 + r16, nb, Kp, k0 + kq);
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[ct], 0, 0, 0);
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b[ct], acc[ct], 0, 0, 0);
+            }
+        }
+    }
+}
+
 // row of A / row of B of accumulator element (rt, ct, i) for this lane
 __device__ __forceinline__ int tile_arow(int rt, int i, int lane) { return rt * 16 + (lane >> 4) * 4 + i; }
 __device__ __forceinline__ int tile_brow(int ct, int lane) { return ct * 16 + (lane & 15); }
+
+// (key, id) order: smaller key first, then smaller id
+__device__ __forceinline__ bool kless(float ka, int ia, float kb, int ib) {
+    return ka < kb || (ka == kb && ia < ib);
+}
+
+// Bitonic sort, ascending by (key, id), of 64*E elements held E per lane
+// (element e = j*64 + lane lives in register j of that lane).
+template <int E>
+__device__ __forceinline__ void wave_sort(float *key, int *id, int lane) {
+#pragma unroll
+    for (int size = 2; size <= 64 * E; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= 64) {
+                const int s = stride >> 6;
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    if (j & s) continue;
+                    const int j2 = j | s;
+                    const bool asc = (((j << 6) | lane) & size) == 0;
+                    const bool sw = asc ? kless(key[j2], id[j2], key[j], id[j])
+                                        : kless(key[j], id[j], key[j2], id[j2]);
+                    if (sw) {
+                        const float tk = key[j]; key[j] = key[j2]; key[j2] = tk;
+                        const int ti = id[j]; id[j] = id[j2]; id[j2] = ti;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    const float pk = __shfl_xor(key[j], stride);
+                    const int pi = __shfl_xor(id[j], stride);
+                    const bool lower = (lane & stride) == 0;
+                    const bool asc = (((j << 6) | lane) & size) == 0;
+                    const bool want_min = lower == asc;
+                    const bool take = want_min ? kless(pk, pi, key[j], id[j]) : kless(key[j], id[j], pk, pi);
+                    if (take) { key[j] = pk; id[j] = pi; }
+                }
+            }
+        }
+    }
+}
 
 // exclusive prefix sum of per-lane counts over the wave; returns the total
 __device__ __forceinline__ int wave_scan(int c, int lane, int &excl) {

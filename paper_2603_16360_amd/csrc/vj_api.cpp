@@ -469,8 +469,8 @@ vj_status vj_build_merged_index(const float *Q, int64_t nq, const float *X, int6
     vj_default_build_params(&p);
     if (bp) p = *bp;
     VJ_CHECK(p.R >= 1 && p.R <= 64, VJ_ERR_UNSUPPORTED, "R must be in [1, 64]");
-    const int kc = p.K_cand > 0 ? p.K_cand : 2 * p.R;
-    VJ_CHECK(kc >= p.R && kc <= 256, VJ_ERR_UNSUPPORTED, "K_cand must be in [R, 256]");
+    const int kc = p.K_cand > 0 ? p.K_cand : std::min(2 * p.R, 112);
+    VJ_CHECK(kc >= 1 && kc <= 112, VJ_ERR_UNSUPPORTED, "K_cand must be in [1, 112]");
     hipStream_t s = (hipStream_t)stream;
     auto h = std::make_unique<vj_index>();
     Index &ix = h->impl;

@@ -80,6 +80,7 @@ struct Index {
     DevBuf parent;   // int32 [nq] MST parent node id (-1: entry)
     DevBuf depth;    // int32 [nq] depth in the MST (root children: 0)
     bool has_mst = false;
+    int64_t repairs = 0;  // connectivity-repair edges added by the build
     // join state shared by calls on this index (calls on one index must not overlap)
     DevBuf cache;    // int32 [nq] soft work sharing: closest visited data node
     DevBuf inb;      // int32 [nq] generation stamp: query is part of the current call
