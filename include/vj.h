@@ -91,8 +91,8 @@ typedef struct {
     float ood_ratio;        /* d1/d2 threshold of VJ_HYB_ADAPT (1.5) */
     int32_t precision;      /* vj_precision */
     const int32_t *budget;  /* device [n]: out-range pops allowed (VJ_HYB_BUDGET); <0: brute force */
-    int32_t hash_log2;      /* per-query visited-set slots = 2^hash_log2 (0: auto) */
-    int32_t waves_per_cu;   /* persistent waves per compute unit (0: auto) */
+    int32_t hash_log2;      /* reserved, set 0 */
+    int32_t waves_per_cu;   /* reserved, set 0 */
     int64_t pair_capacity;  /* initial result capacity hint (0: auto) */
 } vj_join_params;
 
@@ -142,7 +142,10 @@ void vj_index_free(vj_index *idx);
  * threshold eps.  In SOFT/HARD mode queries are processed parents-first
  * along the MST; a query whose MST parent is not in this call gets no
  * cached seed.  eps <= 0 (L2) returns an empty result.  Each query runs on
- * one wavefront of a persistent kernel.
+ * one wavefront with its visited set, worklist and pairs in LDS; queries
+ * that outgrow LDS are re-run with per-wave global tables.  Calls on one
+ * index must not overlap (they share the index's per-query cache).
+ * Limits: hybrid_beam <= 256.
  */
 vj_status vj_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
                   vj_metric metric, const vj_join_params *p, void *stream,
@@ -173,6 +176,13 @@ vj_status vj_pairs_export(const vj_pairs *r, int32_t *qx, float *dist, int sorte
  * predicted OOD, hybrid used, distinct data nodes visited, flags
  * (bit 0: re-run on the spill path, bit 1: routed to brute force). */
 vj_status vj_pairs_stats(const vj_pairs *r, int32_t *stats, void *stream);
+
+/* Device time of a vj_join result's traversal launches, measured with HIP
+ * events recorded on the call's stream around them: kernel_ms for the
+ * LDS-resident launches, spill_ms for the re-runs of queries that outgrew
+ * LDS, n_spilled the number of such queries.  Any pointer may be NULL. */
+vj_status vj_pairs_timing(const vj_pairs *r, float *kernel_ms, float *spill_ms,
+                          int64_t *n_spilled);
 
 void vj_pairs_free(vj_pairs *r);
 

@@ -251,7 +251,17 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
     int32_t *ctr = counters.as<int32_t>();
 
     int64_t cap = p.pair_capacity > 0 ? p.pair_capacity : std::max<int64_t>(1 << 16, n * 64);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    VJ_HIP(hipEventCreate(&ev0));
+    VJ_HIP(hipEventCreate(&ev1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } evguard{ev0, ev1};
     for (int attempt = 0; attempt < 4; ++attempt) {
+        r.kernel_ms = 0.f;
+        r.spill_ms = 0.f;
+        r.n_spilled = 0;
         out_q.reserve((size_t)cap * sizeof(int32_t));
         out_x.reserve((size_t)cap * sizeof(int32_t));
         out_d.reserve((size_t)cap * sizeof(float));
@@ -308,14 +318,22 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
             L.ovf = ovf.as<int32_t>();
             L.ovf_count = ctr + 2;
             VJ_HIP(hipMemsetAsync(ctr + 2, 0, sizeof(int32_t), s));
+            VJ_HIP(hipEventRecord(ev0, s));
             VJ_CHECK(launch_join(L, s), VJ_ERR_UNSUPPORTED, "no join kernel for this row width");
             VJ_HIP(hipGetLastError());
+            VJ_HIP(hipEventRecord(ev1, s));
             VJ_HIP(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s));
             VJ_HIP(hipStreamSynchronize(s));
+            {
+                float ms = 0.f;
+                VJ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+                r.kernel_ms += ms;
+            }
             VJ_CHECK(!(hctr[3] & 8), VJ_ERR_INVALID_ARG, "query id out of range");
             // queries that outgrew LDS: re-run on global visited sets, in
             // processing order, with larger tables at each spill level
             int64_t pending = hctr[2];
+            r.n_spilled += pending;
             const int32_t *lq = qlist, *lp = qpos;
             for (int level = 1; pending > 0; ++level) {
                 VJ_CHECK(level <= 2, VJ_ERR_INTERNAL, "spill levels exhausted");
@@ -351,9 +369,14 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
                     S.gil = gil.as<int32_t>();
                     S.gild = gild.as<float>();
                     S.il_cap = ilc;
+                    VJ_HIP(hipEventRecord(ev0, s));
                     VJ_CHECK(launch_join(S, s), VJ_ERR_UNSUPPORTED, "no join kernel for this row width");
                     VJ_HIP(hipGetLastError());
+                    VJ_HIP(hipEventRecord(ev1, s));
                     VJ_HIP(hipStreamSynchronize(s));  // the next chunk reuses the scratch
+                    float ms = 0.f;
+                    VJ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+                    r.spill_ms += ms;
                 }
                 VJ_HIP(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s));
                 VJ_HIP(hipStreamSynchronize(s));
@@ -593,6 +616,16 @@ vj_status vj_pairs_stats(const vj_pairs *r, int32_t *stats, void *stream) {
     VJ_HIP(hipMemcpyAsync(stats, r->impl.stats.p, (size_t)r->impl.n_queries * 8 * sizeof(int32_t),
                           hipMemcpyDeviceToDevice, s));
     VJ_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
+vj_status vj_pairs_timing(const vj_pairs *r, float *kernel_ms, float *spill_ms,
+                          int64_t *n_spilled) {
+    API_BEGIN
+    VJ_CHECK(r != nullptr, VJ_ERR_INVALID_ARG, "null result");
+    if (kernel_ms) *kernel_ms = r->impl.kernel_ms;
+    if (spill_ms) *spill_ms = r->impl.spill_ms;
+    if (n_spilled) *n_spilled = r->impl.n_spilled;
     API_END
 }
 

@@ -94,6 +94,9 @@ struct Pairs {
     int64_t count = 0;
     int64_t n_queries = 0;   // rows of stats (0 for brute force)
     int64_t n_candidates = 0; // brute force: pairs re-checked in fp64
+    float kernel_ms = 0.f;    // join: LDS-variant launches, timed with events on the stream
+    float spill_ms = 0.f;     // join: spill-variant launches
+    int64_t n_spilled = 0;    // join: queries re-run on the spill variant
     DevBuf q, x, dist;       // int32, int32, float [count]
     DevBuf stats;            // int32 [n_queries][8]
 };

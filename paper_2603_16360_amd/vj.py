@@ -69,6 +69,7 @@ _SIGS = {
     "vj_pairs_count": (_i64, [_vp]),
     "vj_pairs_export": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
     "vj_pairs_stats": (C.c_int, [_vp, _vp, _vp]),
+    "vj_pairs_timing": (C.c_int, [_vp, _vp, _vp, _vp]),
     "vj_pairs_free": (None, [_vp]),
     "vj_last_error": (C.c_char_p, []),
 }
@@ -125,6 +126,12 @@ class Pairs:
         dist = torch.empty(n, dtype=torch.float32, device="cuda")
         _check(_lib.vj_pairs_export(self._h, _ptr(qx), _ptr(dist), int(sorted), _stream()))
         return qx, dist
+
+    def timing(self) -> dict:
+        """Device time of the traversal launches (HIP events on the stream)."""
+        k, sp, ns = C.c_float(), C.c_float(), C.c_int64()
+        _check(_lib.vj_pairs_timing(self._h, C.byref(k), C.byref(sp), C.byref(ns)))
+        return {"kernel_ms": k.value, "spill_ms": sp.value, "n_spilled": ns.value}
 
     def stats(self) -> torch.Tensor:
         """Per-query counters [n, 8] int32 (columns STAT_FIELDS)."""

@@ -1,0 +1,58 @@
+"""Write tests/golden/eps.json: the threshold of each named workload.
+
+eps is calibrated by the oracle alone (oracle.calibrate_eps) on the
+workload's seeded query sample, for the workload's target mean match count;
+a checksum of the generated vectors is stored beside it so a change of the
+generator is detected.  Run:  python tests/golden/make_eps.py [names...]
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import workloads  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "eps.json")
+
+MAKERS = {
+    "tiny": lambda: workloads.config_tiny(),
+    "mid": lambda: workloads.config_mid(),
+}
+
+
+def checksum(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()[:16]
+
+
+def sample(w):
+    r = np.random.default_rng(w.eps_sample_seed)
+    n = min(w.eps_sample, w.Q.shape[0])
+    return np.sort(r.choice(w.Q.shape[0], size=n, replace=False))
+
+
+def main(names):
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for name in names:
+        t = time.time()
+        w = MAKERS[name]()
+        idx = sample(w)
+        eps = oracle.calibrate_eps(w.Q[idx], w.X, w.target_matches, w.metric,
+                                   integer=bool(w.meta.get("integer")))
+        data[name] = {"eps": eps, "metric": w.metric, "target_mean_matches": w.target_matches,
+                      "sample_queries": int(idx.size), "sample_seed": w.eps_sample_seed,
+                      "Q_sha": checksum(w.Q), "X_sha": checksum(w.X),
+                      "nq": int(w.Q.shape[0]), "nx": int(w.X.shape[0]), "d": w.d}
+        print(f"{name}: eps={eps!r} ({time.time() - t:.1f}s)", flush=True)
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or list(MAKERS))
