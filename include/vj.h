@@ -91,7 +91,10 @@ typedef struct {
     float ood_ratio;        /* d1/d2 threshold of VJ_HYB_ADAPT (1.5) */
     int32_t precision;      /* vj_precision */
     const int32_t *budget;  /* device [n]: out-range pops allowed (VJ_HYB_BUDGET); <0: brute force */
-    int32_t hash_log2;      /* reserved, set 0 */
+    int32_t start_tier;     /* first storage tier of every query (0): 0 one wave per query,
+                               1 one workgroup per query, 2 per-wave global tables; a query
+                               that outgrows a tier re-runs on the next.  Callers that know
+                               their queries are large (high eps) skip the small tiers. */
     int32_t waves_per_cu;   /* reserved, set 0 */
     int64_t pair_capacity;  /* initial result capacity hint (0: auto) */
 } vj_join_params;
@@ -142,8 +145,10 @@ void vj_index_free(vj_index *idx);
  * threshold eps.  In SOFT/HARD mode queries are processed parents-first
  * along the MST; a query whose MST parent is not in this call gets no
  * cached seed.  eps <= 0 (L2) returns an empty result.  Each query runs on
- * one wavefront with its visited set, worklist and pairs in LDS; queries
- * that outgrow LDS are re-run with per-wave global tables.  Calls on one
+ * one wavefront with its visited set, worklist and pairs in LDS (1024-slot
+ * visited set, 512 pairs, four waves per workgroup); a query that outgrows
+ * them is re-run with 4096 slots and 2048 pairs (one wave per workgroup),
+ * then with per-wave tables in global memory.  Calls on one
  * index must not overlap (they share the index's per-query cache).
  * Limits: hybrid_beam <= 256.
  */
@@ -174,13 +179,14 @@ vj_status vj_pairs_export(const vj_pairs *r, int32_t *qx, float *dist, int sorte
 /* Per-query counters of a vj_join result, [n][8] int32 in the order of
  * query_ids: pairs, distance evaluations, expanded nodes, out-range pops,
  * predicted OOD, hybrid used, distinct data nodes visited, flags
- * (bit 0: re-run on the spill path, bit 1: routed to brute force). */
+ * (bit 0: re-run after outgrowing the small LDS tier, bit 1: routed to
+ * brute force, bit 3: re-run on per-wave global tables). */
 vj_status vj_pairs_stats(const vj_pairs *r, int32_t *stats, void *stream);
 
 /* Device time of a vj_join result's traversal launches, measured with HIP
  * events recorded on the call's stream around them: kernel_ms for the
- * LDS-resident launches, spill_ms for the re-runs of queries that outgrew
- * LDS, n_spilled the number of such queries.  Any pointer may be NULL. */
+ * small-LDS-tier launches, spill_ms for the re-runs of queries that outgrew
+ * that tier, n_spilled the number of such queries.  Any pointer may be NULL. */
 vj_status vj_pairs_timing(const vj_pairs *r, float *kernel_ms, float *spill_ms,
                           int64_t *n_spilled);
 

@@ -13,8 +13,8 @@
 //   cache    closest visited data node (soft)                   Algorithm 8
 // All per-query state lives in LDS: the visited hash, the in-range worklist
 // (which is also the query's pair buffer) and the out-range queue.  A query
-// that outgrows them is re-run on the spill variant (SPILL = true), whose
-// visited set and worklist are per-wave regions of global memory.
+// that outgrows them is re-run on a larger tier: a whole workgroup with 8x
+// the LDS visited slots, then per-wave regions of global memory.
 //
 // Rows are gathered LPR lanes per row, 16 bytes per lane per load (a row
 // group's load covers whole 128-byte lines), and reduced with xor shuffles
@@ -27,9 +27,10 @@
 namespace vj {
 namespace wj {
 
+// LDS tiers: one wave per query, four per workgroup, for most queries; the
+// queries that outgrow it run on all four waves of a workgroup with 8x the
+// visited slots.  Both keep every per-query structure in LDS.
 constexpr int kWaves = 4;      // waves per workgroup
-constexpr int kHash = 1024;    // LDS visited-set slots per wave
-constexpr int kList = 512;     // LDS in-range worklist entries per wave
 constexpr int kBeamMax = 256;  // largest out-range queue the LDS variant holds
 constexpr int kHeap = kBeamMax + 64;
 
@@ -112,7 +113,7 @@ struct WaveMem {
 
 // Insert each active lane's id; returns true where the id was new.  A lane
 // probes at most the table size before giving up (error flag + abort).
-__device__ __forceinline__ bool visit(const JoinArgs &a, const WaveMem &m, QState &s, int32_t v,
+__device__ __forceinline__ bool visit(const JoinArgs &a, const WaveMem &m, bool &abort, int32_t v,
                                       bool active) {
     bool isnew = false;
     const int n = 1 << m.hash_log2;
@@ -132,7 +133,7 @@ __device__ __forceinline__ bool visit(const JoinArgs &a, const WaveMem &m, QStat
             }
         }
     }
-    if (__ballot(probes > n)) s.abort = true;
+    if (__ballot(probes > n)) abort = true;
     return isnew;
 }
 
@@ -155,19 +156,19 @@ __device__ __forceinline__ float row_partial(const uint4 *buf, const float *qf, 
 }
 
 // drop the largest (key, id) entries until the queue holds `beam`
-__device__ __forceinline__ void heap_trim(const WaveMem &m, QState &s, int beam, int lane) {
-    for (int guard = 0; guard < 64 && s.hc > beam; ++guard) {
+__device__ __forceinline__ void heap_trim(const WaveMem &m, int &hc, int beam, int lane) {
+    for (int guard = 0; guard < 64 * kWaves && hc > beam; ++guard) {
         float bk = -INFINITY;
         int bid = -1, bx = 0;
-        for (int i = lane; i < s.hc; i += 64) {
+        for (int i = lane; i < hc; i += 64) {
             const float kk = m.hk[i];
             const int id = m.hi[i];
             if (kk > bk || (kk == bk && id > bid)) { bk = kk; bid = id; bx = i; }
         }
         wave_best(bk, bid, bx, true);
         bx = uni(bx);
-        if (lane == 0) { m.hk[bx] = m.hk[s.hc - 1]; m.hi[bx] = m.hi[s.hc - 1]; }
-        s.hc -= 1;
+        if (lane == 0) { m.hk[bx] = m.hk[hc - 1]; m.hi[bx] = m.hi[hc - 1]; }
+        hc -= 1;
         wave_sync();
     }
 }
@@ -183,14 +184,14 @@ __device__ __forceinline__ void run_batch(const JoinArgs &a, const WaveMem &m, Q
     constexpr int LPR = pick_lpr(CPR);
     constexpr int VPL = CPR / LPR;
     constexpr int RPP = 64 / LPR;
-    constexpr int PG = VPL >= 4 ? 1 : 4 / VPL;
+    constexpr int PG = (12 / VPL) < (64 / RPP) ? (12 / VPL) : (64 / RPP);
     const bool l2 = a.metric == VJ_L2;
     const int p = lane % LPR, rr = lane / LPR;
     const uint64_t ltmask = (1ull << lane) - 1ull;
     const T *vbase = reinterpret_cast<const T *>(a.rows);
 
     const bool valid = v >= 0 && v < a.nx;
-    const bool isnew = visit(a, m, s, v, valid);
+    const bool isnew = visit(a, m, s.abort, v, valid);
     s.nvis += __popcll(__ballot(isnew));
     if (s.nvis > m.hash_limit) s.abort = true;
     if (s.abort) return;
@@ -252,7 +253,7 @@ __device__ __forceinline__ void run_batch(const JoinArgs &a, const WaveMem &m, Q
                     m.hi[o] = id;
                 }
                 s.hc += __popcll(mh);
-                if (s.hc > a.beam) { wave_sync(); heap_trim(m, s, a.beam, lane); }
+                if (s.hc > a.beam) { wave_sync(); heap_trim(m, s.hc, a.beam, lane); }
             }
         }
     }
@@ -262,7 +263,7 @@ __device__ __forceinline__ void run_batch(const JoinArgs &a, const WaveMem &m, Q
 template <typename T, int DP>
 __device__ __forceinline__ void run_query(const JoinArgs &a, const WaveMem &m, int k,
                                           const int32_t *qlist, const int32_t *qpos,
-                                          int32_t *ovf, int32_t *ovf_count, bool spill, int lane) {
+                                          int32_t *ovf, int32_t *ovf_count, int tier, int lane) {
     constexpr int CE = Elem<T>::CE;
     constexpr int CPR = DP / CE;
     constexpr int LPR = pick_lpr(CPR);
@@ -422,7 +423,7 @@ __device__ __forceinline__ void run_query(const JoinArgs &a, const WaveMem &m, i
     }
 
     if (s.abort) {
-        // not written: re-run on the spill variant (or reported if this is it)
+        // not written: re-run on the next tier
         if (lane == 0) ovf[atomicAdd(ovf_count, 1)] = k;
         if (lane < 8) st[lane] = lane == 7 ? 4 : 0;
         return;
@@ -463,40 +464,41 @@ __device__ __forceinline__ void run_query(const JoinArgs &a, const WaveMem &m, i
         st[4] = ood;
         st[5] = hyb ? 1 : 0;
         st[6] = s.nvis;
-        st[7] = spill ? 1 : 0;
+        st[7] = (tier > 0 ? 1 : 0) | (tier > 1 ? 8 : 0);
     }
 }
 
-// LDS variant: everything per query in static LDS
-template <typename T, int DP, bool HYB>
-__global__ void __launch_bounds__(64 * kWaves)
+// LDS variant: everything per query in static LDS (2^HL visited slots and a
+// LIST-entry worklist per wave, W waves per workgroup)
+template <typename T, int DP, bool HYB, int HL, int LIST, int W>
+__global__ void __launch_bounds__(64 * W, 4)
 k_join_lds(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos, int k0,
            int k1, int32_t *ovf, int32_t *ovf_count) {
-    __shared__ int32_t sh_hash[kWaves][kHash];
-    __shared__ int32_t sh_il[kWaves][kList];
-    __shared__ float sh_ild[kWaves][kList];
-    __shared__ int32_t sh_stage[kWaves][64];
-    __shared__ float sh_hk[kWaves][HYB ? kHeap : 1];
-    __shared__ int32_t sh_hi[kWaves][HYB ? kHeap : 1];
+    __shared__ int32_t sh_hash[W][1 << HL];
+    __shared__ int32_t sh_il[W][LIST];
+    __shared__ float sh_ild[W][LIST];
+    __shared__ int32_t sh_stage[W][64];
+    __shared__ float sh_hk[W][HYB ? kHeap : 1];
+    __shared__ int32_t sh_hi[W][HYB ? kHeap : 1];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
-    const int k = k0 + (int)blockIdx.x * kWaves + wib;
+    const int k = k0 + (int)blockIdx.x * W + wib;
     if (k >= k1) return;
     const JoinArgs &a = *pa;
     WaveMem m;
     m.hash = sh_hash[wib];
-    m.hash_log2 = 10;
-    m.hash_limit = kHash * 3 / 4 - 64;
+    m.hash_log2 = HL;
+    m.hash_limit = (1 << HL) * 3 / 4 - 64;
     m.il = sh_il[wib];
     m.ild = sh_ild[wib];
-    m.il_cap = kList;
+    m.il_cap = LIST;
     m.stage = sh_stage[wib];
     m.hk = sh_hk[wib];
     m.hi = sh_hi[wib];
-    run_query<T, DP>(a, m, k, qlist, qpos, ovf, ovf_count, false, lane);
+    run_query<T, DP>(a, m, k, qlist, qpos, ovf, ovf_count, 0, lane);
 }
 
-// spill variant: visited set and worklist in per-wave global regions
+// global tier: visited set and worklist in per-wave regions of global memory
 template <typename T, int DP, bool HYB>
 __global__ void __launch_bounds__(64 * kWaves)
 k_join_spill(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos, int k0,
@@ -521,31 +523,459 @@ k_join_spill(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_
     m.stage = sh_stage[wib];
     m.hk = sh_hk[wib];
     m.hi = sh_hi[wib];
-    run_query<T, DP>(a, m, k, qlist, qpos, ovf, ovf_count, true, lane);
+    run_query<T, DP>(a, m, k, qlist, qpos, ovf, ovf_count, 2, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Cooperative tier: the W waves of one workgroup run ONE query on shared LDS
+// tables (for the queries that outgrow the one-wave tier).  The in-range
+// worklist is consumed in rounds: between two barriers wave 0 trims the
+// out-range queue and takes a snapshot of the counters; every wave then
+// takes its own NB nodes of the unprocessed part of the list.  The in-range
+// closure does not depend on the order in which nodes are expanded, and the
+// out-range queue holds the `beam` smallest (key, id) entries at every
+// closure point whatever the insertion order, so the closure points, the
+// queue at each of them and hence every pop and stop decision are those of
+// a one-wave run.
+
+template <int W> struct CoopShared {
+    int tail, hc, nvis, abort;  // live counters (LDS atomics)
+    int s_tail, s_hc, s_abort;  // snapshot written by wave 0 between barriers
+    int hyb, ood;               // CheckHybrid decision of wave 0
+    int ndist[W], nexp[W];
+    float bk[W];
+    int bi[W];
+    unsigned long long base;    // output offset of the query's pairs
+};
+
+// per-wave running values (per lane for best_k / best_id, like QState)
+struct CoopWave {
+    int ndist;
+    float best_k;
+    int best_id;
+    float d1sum;
+    int c1;
+};
+
+__device__ __forceinline__ int lds_load(const int *p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
+
+// One candidate batch of one wave against the shared tables (see run_batch).
+template <typename T, int DP, int W>
+__device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, CoopShared<W> &sh,
+                                           CoopWave &cw, const float *qf, int32_t v, bool probe,
+                                           bool hyb_active, int heap_cap, int lane) {
+    constexpr int CE = Elem<T>::CE;
+    constexpr int CPR = DP / CE;
+    constexpr int LPR = pick_lpr(CPR);
+    constexpr int VPL = CPR / LPR;
+    constexpr int RPP = 64 / LPR;
+    constexpr int PG = (12 / VPL) < (64 / RPP) ? (12 / VPL) : (64 / RPP);
+    const bool l2 = a.metric == VJ_L2;
+    const int p = lane % LPR, rr = lane / LPR;
+    const uint64_t ltmask = (1ull << lane) - 1ull;
+    const T *vbase = reinterpret_cast<const T *>(a.rows);
+
+    if (uni(lds_load(&sh.abort))) return;
+    const bool valid = v >= 0 && v < a.nx;
+    bool ovf = false;
+    const bool isnew = visit(a, m, ovf, v, valid);
+    const int nnew = __popcll(__ballot(isnew));
+    int old = 0;
+    if (lane == 0 && nnew) old = atomicAdd(&sh.nvis, nnew);
+    old = uni(old);
+    if (ovf || old + nnew > m.hash_limit) {
+        if (lane == 0) atomicOr(&sh.abort, 1);
+        return;
+    }
+    const bool need = probe ? valid : isnew;
+    const uint64_t mneed = __ballot(need);
+    const int cnt = __popcll(mneed);
+    if (need) m.stage[__popcll(mneed & ltmask)] = isnew ? v : ~v;
+    wave_sync();
+    cw.ndist += cnt;
+    for (int base = 0; base < cnt; base += RPP * PG) {
+        uint4 buf[PG][VPL];
+        int sid[PG];
+#pragma unroll
+        for (int g = 0; g < PG; ++g) {
+            const int c = base + g * RPP + rr;
+            sid[g] = c < cnt ? m.stage[c] : 0;
+            const int id = sid[g] >= 0 ? sid[g] : ~sid[g];
+            const uint4 *row = reinterpret_cast<const uint4 *>(vbase + (size_t)id * DP);
+#pragma unroll
+            for (int w = 0; w < VPL; ++w)
+                buf[g][w] = c < cnt ? row[p + w * LPR] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int g = 0; g < PG; ++g) {
+            const float acc = row_partial<LPR, VPL, CE, T>(buf[g], qf, l2);
+            const int c = base + g * RPP + rr;
+            const bool lead = p == 0 && c < cnt;
+            const bool nw = sid[g] >= 0;
+            const int id = nw ? sid[g] : ~sid[g];
+            const float key = l2 ? acc : 1.0f - acc;
+            const bool inr = l2 ? (acc < a.eps2) : (key < a.eps);
+            if (lead && nw && (key < cw.best_k || (key == cw.best_k && id < cw.best_id))) {
+                cw.best_k = key;
+                cw.best_id = id;
+            }
+            if (probe && lead) {
+                cw.d1sum += l2 ? sqrtf(key) : sqrtf(fmaxf(0.f, 2.f * key));
+                cw.c1 += 1;
+            }
+            const bool ap = lead && nw && inr;
+            const uint64_t ma = __ballot(ap);
+            const int na = __popcll(ma);
+            if (na) {
+                int b0 = 0;
+                if (lane == 0) b0 = atomicAdd(&sh.tail, na);
+                b0 = uni(b0);
+                if (b0 + na > m.il_cap) {
+                    if (lane == 0) atomicOr(&sh.abort, 1);
+                } else if (ap) {
+                    const int o = b0 + __popcll(ma & ltmask);
+                    m.il[o] = id;
+                    m.ild[o] = key;
+                }
+            }
+            if (hyb_active) {
+                const bool hp = lead && nw && !inr;
+                const uint64_t mh = __ballot(hp);
+                const int nh = __popcll(mh);
+                if (nh) {
+                    int b1 = 0;
+                    if (lane == 0) b1 = atomicAdd(&sh.hc, nh);
+                    b1 = uni(b1);
+                    if (b1 + nh > heap_cap) {
+                        if (lane == 0) atomicOr(&sh.abort, 1);
+                    } else if (hp) {
+                        const int o = b1 + __popcll(mh & ltmask);
+                        m.hk[o] = key;
+                        m.hi[o] = id;
+                    }
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
+template <typename T, int DP, int W>
+__device__ __forceinline__ void run_query_coop(const JoinArgs &a, const WaveMem &m,
+                                               CoopShared<W> &sh, int heap_cap, int k,
+                                               const int32_t *qlist, const int32_t *qpos,
+                                               int32_t *ovf, int32_t *ovf_count) {
+    constexpr int CE = Elem<T>::CE;
+    constexpr int CPR = DP / CE;
+    constexpr int LPR = pick_lpr(CPR);
+    constexpr int VPL = CPR / LPR;
+    constexpr int QF = VPL * CE;
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    const int R = a.R;
+    const int qi = uni(qlist[k]);
+    const int pos = uni(qpos[k]);
+    int32_t *st = a.stats + (size_t)pos * 8;
+    // whole-workgroup early exits (one query per workgroup: uniform)
+    if (qi < 0 || qi >= a.nq) {
+        if (threadIdx.x < 8) st[threadIdx.x] = 0;
+        if (threadIdx.x == 0) atomicOr(a.err, 8);
+        return;
+    }
+    const int32_t q = (int32_t)(a.nx + qi);
+    if (a.hyb == VJ_HYB_BUDGET && a.budget[pos] < 0) {
+        if (threadIdx.x < 8) st[threadIdx.x] = threadIdx.x == 7 ? 2 : 0;
+        if (threadIdx.x == 0 && a.ws != VJ_WS_SELF) a.cache[qi] = -1;
+        return;
+    }
+
+    float qf[QF];
+    {
+        const int p = lane % LPR;
+        const float *qrow = a.rows32 + (size_t)q * DP;
+#pragma unroll
+        for (int w = 0; w < VPL; ++w) {
+            const float4 *src = reinterpret_cast<const float4 *>(qrow + (p + w * LPR) * CE);
+#pragma unroll
+            for (int e = 0; e < CE / 4; ++e) {
+                const float4 t = src[e];
+                qf[w * CE + 4 * e + 0] = t.x; qf[w * CE + 4 * e + 1] = t.y;
+                qf[w * CE + 4 * e + 2] = t.z; qf[w * CE + 4 * e + 3] = t.w;
+            }
+        }
+    }
+    for (int i = threadIdx.x; i < (1 << m.hash_log2); i += 64 * W) m.hash[i] = -1;
+    if (threadIdx.x == 0) {
+        sh.tail = 0; sh.hc = 0; sh.nvis = 0; sh.abort = 0;
+        sh.hyb = 0; sh.ood = 0;
+    }
+    __syncthreads();
+
+    CoopWave cw{};
+    cw.best_k = INFINITY;
+    cw.best_id = 0x7fffffff;
+
+    // ---- SeedPhase: wave 0 the entry and the soft cache, all waves the
+    // parent's in-range list (hard), in chunks of 64
+    int pcache = -1;
+    int64_t pseg = 0;
+    int pcnt = 0;
+    if (a.ws != VJ_WS_SELF) {
+        const int32_t par = a.parent[qi];
+        if (par >= a.nx && par < a.nx + a.nq && a.inb[par - a.nx] == (int32_t)a.gen) {
+            const int pq = par - (int32_t)a.nx;
+            if (a.ws == VJ_WS_SOFT) {
+                pcache = uni(a.cache[pq]);
+            } else {
+                pseg = a.seg[pq];
+                pcnt = uni(a.segn[pq]);
+                if (pseg < 0 || pseg + pcnt > a.cap) pcnt = 0;
+            }
+        }
+    }
+    if (wib == 0) {
+        int32_t v = -1;
+        if (lane == 0) v = a.entry;
+        if (lane == 1) v = pcache;
+        coop_batch<T, DP, W>(a, m, sh, cw, qf, v, false, false, heap_cap, lane);
+    }
+    for (int t = wib * 64; t < pcnt && t < a.nx + 64; t += 64 * W) {
+        const int32_t u = t + lane < pcnt ? a.out_x[pseg + t + lane] : -1;
+        coop_batch<T, DP, W>(a, m, sh, cw, qf, u, false, false, heap_cap, lane);
+    }
+    __syncthreads();
+
+    // ---- probe N(q) and CheckHybrid (wave 0)
+    if (wib == 0) {
+        const int32_t nbq = lane < R ? a.adj[(size_t)q * R + lane] : -1;
+        coop_batch<T, DP, W>(a, m, sh, cw, qf, nbq, a.hyb == VJ_HYB_ADAPT, false, heap_cap, lane);
+        bool hyb = false;
+        if (a.hyb == VJ_HYB_FORCE) {
+            hyb = true;
+        } else if (a.hyb == VJ_HYB_BUDGET) {
+            hyb = a.budget[pos] > 0;
+        } else if (a.hyb == VJ_HYB_ADAPT) {
+            float s1 = cw.d1sum;
+            int n1 = cw.c1;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) { s1 += __shfl_xor(s1, off); n1 += __shfl_xor(n1, off); }
+            float s2 = 0.f;
+            int n2 = 0;
+            const int NB = 64 / R;
+            for (int j0 = 0; j0 < R; j0 += NB) {
+                const int b = lane / R, j = lane - b * R;
+                const int yj = j0 + b;
+                const bool ok = b < NB && yj < R;
+                const int32_t y = __shfl(nbq, ok ? yj : 0);
+                if (ok && y >= 0 && y < a.nx) {
+                    const int32_t z = a.adj[(size_t)y * R + j];
+                    if (z >= 0 && z < a.nx) { s2 += a.elen[(size_t)y * R + j]; n2 += 1; }
+                }
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) { s2 += __shfl_xor(s2, off); n2 += __shfl_xor(n2, off); }
+            if (n1 == 0) hyb = true;
+            else if (n2 == 0) hyb = false;
+            else hyb = (s1 / (float)n1) / (s2 / (float)n2) > a.ood_ratio;
+            if (lane == 0) sh.ood = hyb ? 1 : 0;
+        }
+        if (lane == 0) sh.hyb = hyb ? 1 : 0;
+    }
+    __syncthreads();
+    const bool hyb = sh.hyb != 0;
+    const bool hyb_active = hyb && a.beam > 0;
+
+    // ---- ExpansionPhase in rounds
+    const int NB = 64 / R;
+    int head = 0, unprod = 0, before = 0, hpops = 0, nexp = 0;
+    bool pending = false;
+    const int budget = a.hyb == VJ_HYB_BUDGET ? a.budget[pos] : 0;
+    const int bound = m.il_cap + (1 << m.hash_log2) + 4;
+    for (int round = 0; round < bound; ++round) {
+        __syncthreads();
+        if (wib == 0) {
+            if (hyb_active) {
+                int hc = uni(lds_load(&sh.hc));
+                if (hc > a.beam) {
+                    heap_trim(m, hc, a.beam, lane);
+                    if (lane == 0) sh.hc = hc;
+                }
+            }
+            if (lane == 0) {
+                sh.s_tail = lds_load(&sh.tail);
+                sh.s_hc = lds_load(&sh.hc);
+                sh.s_abort = lds_load(&sh.abort);
+            }
+        }
+        __syncthreads();
+        const int t = min(uni(sh.s_tail), m.il_cap);
+        const int hc = uni(sh.s_hc);
+        if (uni(sh.s_abort)) break;
+        if (head < t) {
+            const int take = min(W * NB, t - head);
+            const int my0 = head + wib * NB;
+            const int nmine = max(0, min(NB, head + take - my0));
+            if (nmine > 0) {
+                const int b = lane / R, j = lane - b * R;
+                int32_t v = -1;
+                if (b < nmine) {
+                    const int32_t u = m.il[my0 + b];
+                    if (u >= 0 && u < a.nx) v = a.adj[(size_t)u * R + j];
+                    else atomicOr(a.err, 32);
+                }
+                nexp += nmine;
+                coop_batch<T, DP, W>(a, m, sh, cw, qf, v, false, hyb_active, heap_cap, lane);
+            }
+            head += take;
+            continue;
+        }
+        // closure point: the same decision in every wave
+        if (pending) { unprod = (t == before) ? unprod + 1 : 0; pending = false; }
+        if (!hyb_active || hc == 0) break;
+        if (a.hyb == VJ_HYB_BUDGET) { if (hpops >= budget) break; }
+        else if (a.conv > 0 && unprod >= a.conv) break;
+        hpops += 1;
+        before = t;
+        pending = true;
+        if (wib == 0) {
+            float bk = INFINITY;
+            int bid = 0x7fffffff, bx = 0;
+            for (int i = lane; i < hc; i += 64) {
+                const float kk = m.hk[i];
+                const int id = m.hi[i];
+                if (kk < bk || (kk == bk && id < bid)) { bk = kk; bid = id; bx = i; }
+            }
+            wave_best(bk, bid, bx, false);
+            bid = uni(bid);
+            bx = uni(bx);
+            if (lane == 0) {
+                m.hk[bx] = m.hk[hc - 1];
+                m.hi[bx] = m.hi[hc - 1];
+                sh.hc = hc - 1;
+            }
+            wave_sync();
+            nexp += 1;
+            if (bid < 0 || bid >= a.nx) {
+                if (lane == 0) { atomicOr(a.err, 32); atomicOr(&sh.abort, 1); }
+            } else {
+                const int32_t v = lane < R ? a.adj[(size_t)bid * R + lane] : -1;
+                coop_batch<T, DP, W>(a, m, sh, cw, qf, v, false, hyb_active, heap_cap, lane);
+            }
+        }
+    }
+    {
+        float bk = cw.best_k;
+        int bid = cw.best_id, bx = 0;
+        wave_best(bk, bid, bx, false);
+        if (lane == 0) {
+            sh.ndist[wib] = cw.ndist;
+            sh.nexp[wib] = nexp;
+            sh.bk[wib] = bk;
+            sh.bi[wib] = bid;
+        }
+    }
+    __syncthreads();
+    const int tail = min(lds_load(&sh.tail), m.il_cap);
+    if (lds_load(&sh.abort)) {
+        if (threadIdx.x == 0) ovf[atomicAdd(ovf_count, 1)] = k;
+        if (threadIdx.x < 8) st[threadIdx.x] = threadIdx.x == 7 ? 4 : 0;
+        return;
+    }
+
+    // ---- emit pairs
+    if (threadIdx.x == 0) sh.base = atomicAdd(a.out_count, (unsigned long long)tail);
+    __syncthreads();
+    const unsigned long long base = sh.base;
+    const bool fits = base + (unsigned long long)tail <= (unsigned long long)a.cap;
+    const bool l2 = a.metric == VJ_L2;
+    if (fits) {
+        for (int i = threadIdx.x; i < tail; i += 64 * W) {
+            a.out_q[base + i] = qi;
+            a.out_x[base + i] = m.il[i];
+            const float kk = m.ild[i];
+            a.out_d[base + i] = l2 ? sqrtf(kk) : kk;
+        }
+    }
+    if (threadIdx.x == 0) {
+        float bk = INFINITY;
+        int bid = 0x7fffffff, nd = 0, ne = 0;
+        for (int w = 0; w < W; ++w) {
+            if (sh.bk[w] < bk || (sh.bk[w] == bk && sh.bi[w] < bid)) { bk = sh.bk[w]; bid = sh.bi[w]; }
+            nd += sh.ndist[w];
+            ne += sh.nexp[w];
+        }
+        // ---- UpdateCache
+        if (a.ws == VJ_WS_SOFT) a.cache[qi] = bid == 0x7fffffff ? -1 : bid;
+        else if (a.ws == VJ_WS_HARD) {
+            a.seg[qi] = (int64_t)base;
+            a.segn[qi] = fits ? tail : 0;
+        }
+        st[0] = tail;
+        st[1] = nd;
+        st[2] = ne;
+        st[3] = hpops;
+        st[4] = sh.ood;
+        st[5] = hyb ? 1 : 0;
+        st[6] = lds_load(&sh.nvis);
+        st[7] = 1;
+    }
+}
+
+// cooperative tier: one query per workgroup of W waves, 2^HL visited slots,
+// LIST in-range entries
+template <typename T, int DP, bool HYB, int HL, int LIST, int W>
+__global__ void __launch_bounds__(64 * W)
+k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos, int k0,
+            int k1, int32_t *ovf, int32_t *ovf_count) {
+    constexpr int HC = HYB ? kBeamMax + 64 * W : 1;
+    __shared__ int32_t sh_hash[1 << HL];
+    __shared__ int32_t sh_il[LIST];
+    __shared__ float sh_ild[LIST];
+    __shared__ int32_t sh_stage[W][64];
+    __shared__ float sh_hk[HC];
+    __shared__ int32_t sh_hi[HC];
+    __shared__ CoopShared<W> sh;
+    const int k = k0 + (int)blockIdx.x;
+    if (k >= k1) return;
+    const JoinArgs &a = *pa;
+    WaveMem m;
+    m.hash = sh_hash;
+    m.hash_log2 = HL;
+    m.hash_limit = (1 << HL) * 3 / 4 - 64 * W;
+    m.il = sh_il;
+    m.ild = sh_ild;
+    m.il_cap = LIST;
+    m.stage = sh_stage[threadIdx.x >> 6];
+    m.hk = sh_hk;
+    m.hi = sh_hi;
+    run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, ovf, ovf_count);
+}
+
+template <typename T, int DP, bool HYB>
+void launch_tier(const JoinLaunch &L, hipStream_t s) {
+    const int k0 = L.first, k1 = L.first + L.count;
+    if (L.tier == 0) {
+        const unsigned blocks = (unsigned)((L.count + kWaves - 1) / kWaves);
+        hipLaunchKernelGGL((k_join_lds<T, DP, HYB, 10, 512, kWaves>), dim3(blocks),
+                           dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, L.ovf,
+                           L.ovf_count);
+    } else if (L.tier == 1) {
+        hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 13, 1536, kWaves>), dim3((unsigned)L.count),
+                           dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, L.ovf,
+                           L.ovf_count);
+    } else {
+        const unsigned blocks = (unsigned)((L.count + kWaves - 1) / kWaves);
+        hipLaunchKernelGGL((k_join_spill<T, DP, HYB>), dim3(blocks), dim3(64 * kWaves), 0, s,
+                           L.args, L.qlist, L.qpos, k0, k1, L.gh, L.hash_log2, L.gil, L.gild,
+                           L.il_cap, L.ovf, L.ovf_count);
+    }
 }
 
 template <typename T, int DP>
 bool launch_dp(const JoinLaunch &L, hipStream_t s) {
-    const unsigned blocks = (unsigned)((L.count + kWaves - 1) / kWaves);
-    if (blocks == 0) return true;
-    const int k0 = L.first, k1 = L.first + L.count;
-    if (!L.spill) {
-        if (L.hyb)
-            hipLaunchKernelGGL((k_join_lds<T, DP, true>), dim3(blocks), dim3(64 * kWaves), 0, s,
-                               L.args, L.qlist, L.qpos, k0, k1, L.ovf, L.ovf_count);
-        else
-            hipLaunchKernelGGL((k_join_lds<T, DP, false>), dim3(blocks), dim3(64 * kWaves), 0, s,
-                               L.args, L.qlist, L.qpos, k0, k1, L.ovf, L.ovf_count);
-    } else {
-        if (L.hyb)
-            hipLaunchKernelGGL((k_join_spill<T, DP, true>), dim3(blocks), dim3(64 * kWaves), 0, s,
-                               L.args, L.qlist, L.qpos, k0, k1, L.gh, L.hash_log2, L.gil, L.gild,
-                               L.il_cap, L.ovf, L.ovf_count);
-        else
-            hipLaunchKernelGGL((k_join_spill<T, DP, false>), dim3(blocks), dim3(64 * kWaves), 0, s,
-                               L.args, L.qlist, L.qpos, k0, k1, L.gh, L.hash_log2, L.gil, L.gild,
-                               L.il_cap, L.ovf, L.ovf_count);
-    }
+    if (L.count <= 0) return true;
+    if (L.hyb) launch_tier<T, DP, true>(L, s);
+    else launch_tier<T, DP, false>(L, s);
     return true;
 }
 

@@ -304,39 +304,66 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
         VJ_HIP(hipMemcpyAsync(argsbuf.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
 
         int32_t hctr[4] = {0, 0, 0, 0};
-        for (size_t lv = 0; lv + 1 < ord.level_start.size(); ++lv) {
+        // One launch (or a sequence of chunks, global tiers) of `cnt` slots
+        // of the lists lq/lp on tier `tier`; returns the device time.
+        auto run_tier = [&](int tier, const int32_t *lq, const int32_t *lp, int64_t cnt) -> float {
             JoinLaunch L{};
             L.args = argsbuf.as<JoinArgs>();
-            L.qlist = qlist;
-            L.qpos = qpos;
-            L.first = (int)ord.level_start[lv];
-            L.count = (int)(ord.level_start[lv + 1] - ord.level_start[lv]);
+            L.qlist = lq;
+            L.qpos = lp;
             L.dp = ix.dp;
             L.prec = prec;
-            L.spill = false;
+            L.tier = std::min(tier, 2);
             L.hyb = beam > 0;
             L.ovf = ovf.as<int32_t>();
             L.ovf_count = ctr + 2;
-            VJ_HIP(hipMemsetAsync(ctr + 2, 0, sizeof(int32_t), s));
-            VJ_HIP(hipEventRecord(ev0, s));
-            VJ_CHECK(launch_join(L, s), VJ_ERR_UNSUPPORTED, "no join kernel for this row width");
-            VJ_HIP(hipGetLastError());
-            VJ_HIP(hipEventRecord(ev1, s));
-            VJ_HIP(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s));
-            VJ_HIP(hipStreamSynchronize(s));
-            {
+            int64_t chunk = cnt;
+            if (tier >= 2) {
+                // tier 2: 2^16-slot visited sets (32,768 nodes) and 32,768
+                // pairs per query; tier 3: tables as large as the data set
+                L.hash_log2 = tier == 2 ? std::min(16, ceil_log2(2 * ix.nx)) : ceil_log2(2 * ix.nx);
+                L.il_cap = (int)(tier == 2 ? std::min<int64_t>(ix.nx, 1 << 15) : ix.nx);
+                chunk = tier == 2 ? 1024 : 4;
+                gh.reserve((size_t)std::min(chunk, cnt) * ((size_t)1 << L.hash_log2) * sizeof(int32_t));
+                gil.reserve((size_t)std::min(chunk, cnt) * L.il_cap * sizeof(int32_t));
+                gild.reserve((size_t)std::min(chunk, cnt) * L.il_cap * sizeof(float));
+                L.gh = gh.as<int32_t>();
+                L.gil = gil.as<int32_t>();
+                L.gild = gild.as<float>();
+            }
+            float total_ms = 0.f;
+            for (int64_t c0 = 0; c0 < cnt; c0 += chunk) {
+                L.first = (int)c0;
+                L.count = (int)std::min<int64_t>(chunk, cnt - c0);
+                VJ_HIP(hipEventRecord(ev0, s));
+                VJ_CHECK(launch_join(L, s), VJ_ERR_UNSUPPORTED, "no join kernel for this row width");
+                VJ_HIP(hipGetLastError());
+                VJ_HIP(hipEventRecord(ev1, s));
+                VJ_HIP(hipStreamSynchronize(s));  // the next chunk reuses the scratch
                 float ms = 0.f;
                 VJ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-                r.kernel_ms += ms;
+                total_ms += ms;
             }
-            VJ_CHECK(!(hctr[3] & 8), VJ_ERR_INVALID_ARG, "query id out of range");
-            // queries that outgrew LDS: re-run on global visited sets, in
-            // processing order, with larger tables at each spill level
-            int64_t pending = hctr[2];
-            r.n_spilled += pending;
-            const int32_t *lq = qlist, *lp = qpos;
-            for (int level = 1; pending > 0; ++level) {
-                VJ_CHECK(level <= 2, VJ_ERR_INTERNAL, "spill levels exhausted");
+            return total_ms;
+        };
+        for (size_t lv = 0; lv + 1 < ord.level_start.size(); ++lv) {
+            // one MST level (all queries, self mode): the first tier, then the
+            // queries that outgrew it, in processing order, on the next tiers
+            const int64_t first = ord.level_start[lv];
+            int64_t pending = ord.level_start[lv + 1] - first;
+            const int32_t *lq = qlist + first, *lp = qpos + first;
+            for (int tier = p.start_tier; pending > 0; ++tier) {
+                VJ_CHECK(tier <= 3, VJ_ERR_INTERNAL, "join tiers exhausted");
+                VJ_HIP(hipMemsetAsync(ctr + 2, 0, sizeof(int32_t), s));
+                const float ms = run_tier(tier, lq, lp, pending);
+                if (tier == p.start_tier) r.kernel_ms += ms;
+                else r.spill_ms += ms;
+                VJ_HIP(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s));
+                VJ_HIP(hipStreamSynchronize(s));
+                VJ_CHECK(!(hctr[3] & 8), VJ_ERR_INVALID_ARG, "query id out of range");
+                pending = hctr[2];
+                if (pending == 0) break;
+                r.n_spilled += tier == p.start_tier ? pending : 0;
                 std::vector<int32_t> slots_h((size_t)pending);
                 VJ_HIP(hipMemcpyAsync(slots_h.data(), ovf.p, pending * sizeof(int32_t), hipMemcpyDeviceToHost, s));
                 VJ_HIP(hipStreamSynchronize(s));
@@ -350,37 +377,6 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
                 p2 = std::move(np2);
                 lq = q2.as<int32_t>();
                 lp = p2.as<int32_t>();
-                const int hl = level == 1 ? std::min(18, ceil_log2(2 * ix.nx)) : ceil_log2(2 * ix.nx);
-                const int ilc = (int)(level == 1 ? std::min<int64_t>(ix.nx, 1 << 16) : ix.nx);
-                const int64_t chunk = level == 1 ? 128 : 4;
-                gh.reserve((size_t)chunk * ((size_t)1 << hl) * sizeof(int32_t));
-                gil.reserve((size_t)chunk * ilc * sizeof(int32_t));
-                gild.reserve((size_t)chunk * ilc * sizeof(float));
-                VJ_HIP(hipMemsetAsync(ctr + 2, 0, sizeof(int32_t), s));
-                for (int64_t c0 = 0; c0 < pending; c0 += chunk) {
-                    JoinLaunch S = L;
-                    S.qlist = lq;
-                    S.qpos = lp;
-                    S.first = (int)c0;
-                    S.count = (int)std::min<int64_t>(chunk, pending - c0);
-                    S.spill = true;
-                    S.gh = gh.as<int32_t>();
-                    S.hash_log2 = hl;
-                    S.gil = gil.as<int32_t>();
-                    S.gild = gild.as<float>();
-                    S.il_cap = ilc;
-                    VJ_HIP(hipEventRecord(ev0, s));
-                    VJ_CHECK(launch_join(S, s), VJ_ERR_UNSUPPORTED, "no join kernel for this row width");
-                    VJ_HIP(hipGetLastError());
-                    VJ_HIP(hipEventRecord(ev1, s));
-                    VJ_HIP(hipStreamSynchronize(s));  // the next chunk reuses the scratch
-                    float ms = 0.f;
-                    VJ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-                    r.spill_ms += ms;
-                }
-                VJ_HIP(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s));
-                VJ_HIP(hipStreamSynchronize(s));
-                pending = hctr[2];
             }
             VJ_CHECK(!(hctr[3] & 16), VJ_ERR_INTERNAL, "visited-set probe exceeded the table size");
             VJ_CHECK(!(hctr[3] & 32), VJ_ERR_INTERNAL, "a worklist entry is not a data node id");
@@ -442,7 +438,7 @@ void vj_default_join_params(vj_join_params *p) {
     p->ood_ratio = 1.5f;
     p->precision = VJ_PREC_FP32;
     p->budget = nullptr;
-    p->hash_log2 = 0;
+    p->start_tier = 0;
     p->waves_per_cu = 0;
     p->pair_capacity = 0;
 }
@@ -560,6 +556,7 @@ vj_status vj_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
     VJ_CHECK(p.hybrid_beam >= 0 && p.hybrid_beam <= 4096, VJ_ERR_INVALID_ARG, "hybrid_beam in [0, 4096]");
     VJ_CHECK(p.work_sharing == VJ_WS_SELF || ix.has_mst, VJ_ERR_INVALID_ARG, "work sharing needs the MST");
     VJ_CHECK(p.hybrid != VJ_HYB_BUDGET || p.budget != nullptr, VJ_ERR_INVALID_ARG, "budget mode needs budget[]");
+    VJ_CHECK(p.start_tier >= 0 && p.start_tier <= 2, VJ_ERR_INVALID_ARG, "start_tier in [0, 2]");
     VJ_CHECK(p.hybrid != VJ_HYB_LEARNED, VJ_ERR_UNSUPPORTED, "no predictor attached");
     hipStream_t s = (hipStream_t)stream;
     auto h = std::make_unique<vj_pairs>();

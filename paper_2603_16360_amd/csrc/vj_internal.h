@@ -134,7 +134,8 @@ struct JoinLaunch {
     const int32_t *qlist;     // query index per processing slot
     const int32_t *qpos;      // caller position per processing slot
     int first, count, dp, prec;  // slots [first, first + count) of qlist
-    bool spill, hyb;
+    int tier;                    // 0 small LDS, 1 large LDS, 2 global tables
+    bool hyb;
     int32_t *gh;              // spill: [count][1 << hash_log2] visited sets, by slot - first
     int hash_log2;
     int32_t *gil;             // spill: [count][il_cap] worklists

@@ -46,7 +46,7 @@ class vj_join_params(C.Structure):
     _fields_ = [("work_sharing", C.c_int32), ("hybrid", C.c_int32),
                 ("hybrid_beam", C.c_int32), ("conv_threshold", C.c_int32),
                 ("ood_ratio", C.c_float), ("precision", C.c_int32),
-                ("budget", C.c_void_p), ("hash_log2", C.c_int32),
+                ("budget", C.c_void_p), ("start_tier", C.c_int32),
                 ("waves_per_cu", C.c_int32), ("pair_capacity", C.c_int64)]
 
 
@@ -174,7 +174,7 @@ class Index:
 # ---------------------------------------------------------------- functions --
 
 def join_params(work_sharing="self", hybrid="off", hybrid_beam=256, conv_threshold=10,
-                ood_ratio=1.5, precision="fp32", budget=None, hash_log2=0, waves_per_cu=0,
+                ood_ratio=1.5, precision="fp32", budget=None, start_tier=0, waves_per_cu=0,
                 pair_capacity=0):
     p = vj_join_params()
     _lib.vj_default_join_params(C.byref(p))
@@ -185,7 +185,7 @@ def join_params(work_sharing="self", hybrid="off", hybrid_beam=256, conv_thresho
     p.ood_ratio = ood_ratio
     p.precision = PRECISION[precision]
     p.budget = budget.data_ptr() if budget is not None else None
-    p.hash_log2 = hash_log2
+    p.start_tier = start_tier
     p.waves_per_cu = waves_per_cu
     p.pair_capacity = pair_capacity
     return p

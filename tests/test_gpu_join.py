@@ -119,9 +119,8 @@ def test_self_bfs_subset_and_duplicates(tiny):
 
 def test_spill_path_matches(tiny):
     base = qx_set(_gpu_pairs(vj.vj_join(tiny.idx, tiny.eps))[0])
-    # a 64-slot visited set overflows on most queries: they re-run on the
-    # global-table path and must give the same result
-    res = vj.vj_join(tiny.idx, tiny.eps, hash_log2=6)
+    # every query on the global-table path must give the same result
+    res = vj.vj_join(tiny.idx, tiny.eps, start_tier=2)
     st = res.stats().cpu().numpy()
     assert (st[:, 7] & 1).sum() > 0
     assert qx_set(_gpu_pairs(res)[0]) == base

@@ -134,12 +134,13 @@ def test_self_bfs_subset_and_duplicates(tiny):
 
 
 def test_spill_path_matches(tiny):
-    # at 2.6x eps some queries outgrow the per-wave LDS worklist / visited
-    # set and re-run on the global-table variant; all must match the oracle
+    # at 2.6x eps (oracle: up to 4,449 pairs and 5,135 visited nodes per
+    # query) queries outgrow the small LDS tier, some also the large one, and
+    # re-run on the global-table tier; all must match the oracle
     eps = tiny.eps * 2.6
     res = vj.vj_join(tiny.idx, eps)
     st = res.stats().cpu().numpy()
-    assert (st[:, 7] & 1).sum() > 0
+    assert (st[:, 7] & 1).sum() > (st[:, 7] & 8).sum() // 8 > 0
     ref = oracle.join(tiny.w.Q, tiny.w.X, tiny.g.adj, tiny.g.entry, eps, uncertain="out")
     refu = oracle.join(tiny.w.Q, tiny.w.X, tiny.g.adj, tiny.g.entry, eps, uncertain="in")
     assert ref.pairs() <= qx_set(_gpu_pairs(res)[0]) <= refu.pairs()
@@ -171,14 +172,17 @@ def test_invalid_arguments(tiny):
     with pytest.raises(vj.VJError) as e:
         vj.vj_join(tiny.idx, tiny.eps, query_ids=bad)
     assert e.value.status == 1
+    with pytest.raises(vj.VJError) as e:
+        vj.vj_join(tiny.idx, tiny.eps, start_tier=3)
+    assert e.value.status == 1
 
 
-def _mode_parity(case, **kw):
+def _mode_parity(case, start_tier=0, **kw):
     w = case.w
     par = case.parent if kw.get("work_sharing", "self") != "self" else None
     ref = oracle.join(w.Q, w.X, case.g.adj, case.g.entry, case.eps, metric=w.metric,
                       parent=par, **kw)
-    res = vj.vj_join(case.idx, case.eps, metric=w.metric, **kw)
+    res = vj.vj_join(case.idx, case.eps, metric=w.metric, start_tier=start_tier, **kw)
     qx, _ = _gpu_pairs(res)
     got, want = _by_query(qx), _by_query(zip(ref.qi, ref.xj))
     fragile = ref.stats[:, 7].astype(bool)
@@ -208,11 +212,43 @@ def test_modes_match_oracle(tiny, kw):
         assert np.array_equal(st[ok, 4], ref.stats[ok, 4])
 
 
+@pytest.mark.parametrize("start_tier", [1, 2])
+@pytest.mark.parametrize("kw", [
+    {},
+    {"hybrid": "force"},
+    {"hybrid": "adapt"},
+    {"hybrid": "force", "hybrid_beam": 16, "conv_threshold": 3},
+    {"work_sharing": "soft", "hybrid": "force"},
+    {"work_sharing": "hard"},
+], ids=lambda k: "-".join(f"{a}={b}" for a, b in k.items()) or "bfs")
+def test_larger_tiers_match_oracle(tiny, kw, start_tier):
+    # every query starts on the workgroup-per-query tier (1) or on the
+    # global-table tier (2); per-query results and counters as on tier 0
+    _say(f"vj_join tiny start_tier={start_tier} {kw}")
+    res, ref = _mode_parity(tiny, start_tier=start_tier, **kw)
+    st = res.stats().cpu().numpy()
+    assert np.all(st[:, 7] & 1)
+    assert np.all((st[:, 7] & 8) > 0) == (start_tier == 2)
+    ok = ~ref.stats[:, 7].astype(bool)
+    for col in (0, 2, 3, 6):  # pairs, expanded, out-range pops, visited data nodes
+        assert np.array_equal(st[ok, col], ref.stats[ok, col]), col
+
+
 def test_budget_mode(tiny):
+    _budget_mode(tiny, 0)
+
+
+@pytest.mark.parametrize("start_tier", [1, 2])
+def test_budget_mode_larger_tiers(tiny, start_tier):
+    _budget_mode(tiny, start_tier)
+
+
+def _budget_mode(tiny, start_tier):
     r = np.random.default_rng(11)
     b = r.integers(0, 8, size=tiny.w.Q.shape[0]).astype(np.int32)
     b[::7] = -1  # routed elsewhere: no traversal
-    res = vj.vj_join(tiny.idx, tiny.eps, hybrid="budget", budget=torch.from_numpy(b).cuda())
+    res = vj.vj_join(tiny.idx, tiny.eps, hybrid="budget", budget=torch.from_numpy(b).cuda(),
+                     start_tier=start_tier)
     ref = oracle.join(tiny.w.Q, tiny.w.X, tiny.g.adj, tiny.g.entry, tiny.eps, hybrid="budget",
                       budget=np.maximum(b, 0))
     qx, _ = _gpu_pairs(res)
@@ -235,10 +271,11 @@ def integer_case():
     return Case(w, eps)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "u8", "auto"])
-def test_integer_data_exact(integer_case, precision):
+@pytest.mark.parametrize("precision,start_tier", [("fp32", 0), ("u8", 0), ("auto", 0),
+                                                  ("u8", 1), ("fp32", 1), ("u8", 2)])
+def test_integer_data_exact(integer_case, precision, start_tier):
     c = integer_case
-    res = vj.vj_join(c.idx, c.eps, precision=precision)
+    res = vj.vj_join(c.idx, c.eps, precision=precision, start_tier=start_tier)
     ref = oracle.join(c.w.Q, c.w.X, c.g.adj, c.g.entry, c.eps)
     qx, dist = _gpu_pairs(res)
     assert qx_set(qx) == ref.pairs()  # squared distances are exact integers
