@@ -24,10 +24,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TIER_KERNELS = ("k_join_lds (one wave per query)", "k_join_coop (one workgroup per query)",
+                "k_join_spill (per-wave global tables)")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_join_mid_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_16360_amd", "csrc", f)
+                  for f in ("join_impl.h", "join_inst.hip")]
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tier):
+    """HBM bytes per launch of the tier's kernel from the committed rocprofv3
+    counter summary, or None when the kernel source changed since then."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line)
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("source_sha") != kernel_source_sha():
+        return None
+    key = f"tier{tier}_hbm_bytes_per_launch"
+    return float(kv[key]) if key in kv else None
 
 
 def algorithmic_bytes(stats, dp, elem_bytes, R, mask):
@@ -47,6 +72,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--variants", default="fp32,u8")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run a plain 1 GiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -69,6 +96,14 @@ def main():
     log(f"data {nq} x {nx} x {d} generated in {time.time() - t0:.1f}s, eps={eps}")
 
     dev = torch.device("cuda:0")
+    if args.copy_calib:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)  # reads and writes exactly 1 GiB
+        torch.cuda.synchronize()
+        del a, b
+        log("copy calibration: 1 GiB device-to-device copy done")
     Q = torch.from_numpy(w.Q).to(dev)
     X = torch.from_numpy(w.X).to(dev)
     torch.cuda.synchronize()
@@ -94,7 +129,7 @@ def main():
         for _ in range(args.warmup):
             vj.vj_join(idx, eps, precision=variant)
         torch.cuda.synchronize()
-        kernel_ms, spill_ms, walls = [], [], []
+        walls, tier_ms, tier_ln = [], np.zeros(4), np.zeros(4)
         res = None
         for _ in range(args.steps):
             torch.cuda.synchronize()
@@ -102,25 +137,40 @@ def main():
             res = vj.vj_join(idx, eps, precision=variant)
             torch.cuda.synchronize()
             walls.append(time.perf_counter() - ts)
-            tm = res.timing()
-            kernel_ms.append(tm["kernel_ms"])
-            spill_ms.append(tm["spill_ms"])
+            tiers = res.tiers()
+            tier_ms += [t["ms"] for t in tiers]
+            tier_ln += [t["launches"] for t in tiers]
+        tier_ms /= args.steps
+        tier_ln /= args.steps
+        tiers = res.tiers()
         qx, _ = res.export(sorted=True)
         keys = qx[:, 0].to(torch.int64) * nx + qx[:, 1].to(torch.int64)
         precise = bool(torch.isin(keys, gt_keys).all().item())
         recall = keys.numel() / max(1, n_gt)
         st = res.stats().cpu().numpy()
-        spilled = (st[:, 7] & 1).astype(bool)
+        fl = st[:, 7]
+        done_on = [(fl & 1) == 0, ((fl & 1) == 1) & ((fl & 8) == 0), (fl & 8) > 0]
         eb = 1 if variant == "u8" else 4
-        nbytes = algorithmic_bytes(st, 128, eb, R, ~spilled)
-        k_ms = float(np.mean(kernel_ms))
+        per_tier = []
+        for t in range(3):
+            ms = float(tier_ms[t] + (tier_ms[3] if t == 2 else 0.0))
+            ln = float(tier_ln[t] + (tier_ln[3] if t == 2 else 0.0))
+            nbytes = algorithmic_bytes(st, 128, eb, R, done_on[t])
+            per_tier.append({"kernel": TIER_KERNELS[t], "ms": ms, "launches": ln,
+                             "queries_launched": int(tiers[t]["queries"] + (tiers[3]["queries"] if t == 2 else 0)),
+                             "queries_completed": int(done_on[t].sum()),
+                             "algorithmic_bytes": nbytes,
+                             "achieved_gbs": nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0})
+        dom = int(np.argmax([pt["ms"] for pt in per_tier]))
+        all_bytes = algorithmic_bytes(st, 128, eb, R, np.ones(len(st), bool))
+        dev_ms = float(tier_ms.sum())
         results[variant] = {
             "qps": nq / float(np.mean(walls)),
             "ms_per_step": 1000.0 * float(np.mean(walls)),
-            "kernel_ms": k_ms, "spill_ms": float(np.mean(spill_ms)),
-            "n_spilled": int(spilled.sum()), "recall": recall, "precision_is_one": precise,
-            "pairs": int(keys.numel()), "bytes_per_launch": nbytes,
-            "achieved_gbs": nbytes / (k_ms * 1e-3) / 1e9,
+            "device_ms": dev_ms, "recall": recall, "precision_is_one": precise,
+            "pairs": int(keys.numel()), "tiers": per_tier, "dominant_tier": dom,
+            "algorithmic_bytes_all": all_bytes,
+            "traversal_gbs": all_bytes / (dev_ms * 1e-3) / 1e9,
             "mean_dist_evals": float(st[:, 1].mean()), "mean_expanded": float(st[:, 2].mean()),
         }
         log(f"{variant}: {results[variant]}")
@@ -132,17 +182,22 @@ def main():
         adj, _, _ = idx.export_graph()
         adj = adj.cpu().numpy()
         cores = len(os.sched_getaffinity(0))
-        sample = np.arange(0, nq, 5, dtype=np.int32)  # every 5th query: 20,000
-        t = time.time()
-        counts = oracle.join_self_counts(w.Q, w.X, adj, info["entry"], eps, query_ids=sample)
-        cpu_s = time.time() - t
-        cpu = {"value": sample.size / cpu_s, "unit": "queries/s", "cores": cores,
+        reps, cpu_s, npairs = 0, 0.0, 0
+        while cpu_s < 10.0 and reps < 30:  # the whole query set, repeated to >= 10 s
+            t = time.time()
+            counts = oracle.join_self_counts(w.Q, w.X, adj, info["entry"], eps)
+            cpu_s += time.time() - t
+            npairs = int(counts.sum())
+            reps += 1
+        cpu = {"value": reps * nq / cpu_s, "unit": "queries/s", "cores": cores,
                "kind": "oracle",
-               "sample": f"{sample.size} of the {nq} queries (every 5th), self-seeded BFS merged-"
-                         f"index join in fp64 with OpenMP over queries, same graph and eps; "
-                         f"{cpu_s:.1f}s; {int(counts.sum())} pairs"}
+               "sample": f"all {nq} queries x {reps} repetitions ({cpu_s:.1f}s): self-seeded BFS "
+                         f"merged-index join in fp64 with OpenMP over queries, same graph and eps; "
+                         f"{npairs} pairs per repetition"}
         log(f"cpu baseline: {cpu}")
 
+    dom = head["tiers"][head["dominant_tier"]]
+    traffic = measured_traffic(head["dominant_tier"])
     line = {
         "metric": "join queries/sec at recall>=0.95 (1Mx128 fp32); achieved HBM GB/s vs peak",
         "value": head["qps"],
@@ -160,9 +215,11 @@ def main():
                                "L2, eps for mean 50 matches, merged graph R=32, self-seeded BFS",
                    "eps": eps, "global_batch": nq},
         "recall": head["recall"],
-        "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": head["achieved_gbs"] / HBM_PEAK_GBS,
-                     "traffic": None},
+        "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["achieved_gbs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dom["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": dom["algorithmic_bytes"] / max(1.0, dom["launches"]),
+                     "avg_launch_ms": dom["ms"] / max(1.0, dom["launches"])},
         "cpu_baseline": cpu,
         "variants": results,
         "build_s": build_s,

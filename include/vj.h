@@ -92,7 +92,8 @@ typedef struct {
     int32_t precision;      /* vj_precision */
     const int32_t *budget;  /* device [n]: out-range pops allowed (VJ_HYB_BUDGET); <0: brute force */
     int32_t start_tier;     /* first storage tier of every query (0): 0 one wave per query,
-                               1 one workgroup per query, 2 per-wave global tables; a query
+                               1 one workgroup per query, 2 one workgroup per query with its
+                               tables in global memory; a query
                                that outgrows a tier re-runs on the next.  Callers that know
                                their queries are large (high eps) skip the small tiers. */
     int32_t waves_per_cu;   /* reserved, set 0 */
@@ -147,8 +148,9 @@ void vj_index_free(vj_index *idx);
  * cached seed.  eps <= 0 (L2) returns an empty result.  Each query runs on
  * one wavefront with its visited set, worklist and pairs in LDS (1024-slot
  * visited set, 512 pairs, four waves per workgroup); a query that outgrows
- * them is re-run with 4096 slots and 2048 pairs (one wave per workgroup),
- * then with per-wave tables in global memory.  Calls on one
+ * them is re-run by a whole workgroup of four waves on 8192 LDS slots and
+ * 1536 pairs, then on tables in global memory (2^16 slots and 32768 pairs,
+ * then as large as the data set).  Calls on one
  * index must not overlap (they share the index's per-query cache).
  * Limits: hybrid_beam <= 256.
  */
@@ -179,8 +181,8 @@ vj_status vj_pairs_export(const vj_pairs *r, int32_t *qx, float *dist, int sorte
 /* Per-query counters of a vj_join result, [n][8] int32 in the order of
  * query_ids: pairs, distance evaluations, expanded nodes, out-range pops,
  * predicted OOD, hybrid used, distinct data nodes visited, flags
- * (bit 0: re-run after outgrowing the small LDS tier, bit 1: routed to
- * brute force, bit 3: re-run on per-wave global tables). */
+ * (bit 0: re-run after outgrowing the one-wave LDS tier, bit 1: routed to
+ * brute force, bit 3: re-run on global tables). */
 vj_status vj_pairs_stats(const vj_pairs *r, int32_t *stats, void *stream);
 
 /* Device time of a vj_join result's traversal launches, measured with HIP
@@ -189,6 +191,14 @@ vj_status vj_pairs_stats(const vj_pairs *r, int32_t *stats, void *stream);
  * that tier, n_spilled the number of such queries.  Any pointer may be NULL. */
 vj_status vj_pairs_timing(const vj_pairs *r, float *kernel_ms, float *spill_ms,
                           int64_t *n_spilled);
+
+/* Per-tier breakdown of a vj_join result's traversal, for the storage tiers
+ * 0 (one wave per query, LDS), 1 (one workgroup per query, LDS), 2 (one
+ * workgroup per query, global tables of 2^16 slots) and 3 (the same with
+ * tables as large as the data set): ms[t] the device time of the tier's launches (HIP events on the
+ * call's stream), launches[t] their number and queries[t] the queries
+ * launched on the tier, re-runs included.  Arrays of 4; any may be NULL. */
+vj_status vj_pairs_tiers(const vj_pairs *r, float *ms, int32_t *launches, int64_t *queries);
 
 void vj_pairs_free(vj_pairs *r);
 

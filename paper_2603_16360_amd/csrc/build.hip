@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "build.h"
+#include "build_rows.h"
 #include "mfma_tile.h"
 #include "tiles.h"
 #include "util.h"
@@ -26,8 +27,8 @@ namespace vj {
 namespace {
 
 using mt::floatx4;
-constexpr int kKnnCap = 384;   // per-row candidate buffer of the top-K sweep
-constexpr int kCandMax = 1024; // candidates a reverse-edge prune considers
+using brow::kKnnCap;
+using brow::g1b;
 
 // ------------------------------------------------------------------ kNN --
 // A wave owns 16 rows and sweeps all N rows as columns, 128 per step.  Each
@@ -112,133 +113,6 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
     for (int r = 0; r < 16; ++r) merge_row(r);
 }
 
-// --------------------------------------------------- row distance helper --
-// squared L2 distances from row `u` to up to 8 rows at once: lane group g
-// (8 lanes) handles ids[g]; returns the group's total in every lane of it.
-template <int DP>
-__device__ __forceinline__ float dist8(const float *vec, int32_t u, int32_t v, int lane) {
-    constexpr int CH = DP / 4;             // float4 chunks per row
-    constexpr int PER = (CH + 7) / 8;       // chunks per lane
-    const int p = lane & 7;
-    const float4 *a = reinterpret_cast<const float4 *>(vec + (size_t)u * DP);
-    const float4 *b = reinterpret_cast<const float4 *>(vec + (size_t)v * DP);
-    float acc = 0.f;
-#pragma unroll
-    for (int t = 0; t < PER; ++t) {
-        const int c = p + 8 * t;
-        if (c < CH) {
-            const float4 x = a[c], y = b[c];
-            float q;
-            q = x.x - y.x; acc = fmaf(q, q, acc);
-            q = x.y - y.y; acc = fmaf(q, q, acc);
-            q = x.z - y.z; acc = fmaf(q, q, acc);
-            q = x.w - y.w; acc = fmaf(q, q, acc);
-        }
-    }
-    acc += __shfl_xor(acc, 4);
-    acc += __shfl_xor(acc, 2);
-    acc += __shfl_xor(acc, 1);
-    return acc;
-}
-
-// Exact re-rank of the K buffered neighbours of every row: direct fp32 squared
-// distances, sorted by (distance, id); the first Kc are written out.
-template <int DP>
-__global__ void __launch_bounds__(256)
-k_rerank(const float *vec, int64_t N, const int32_t *bid, int K, int Kc, int32_t *out_id,
-         float *out_d2) {
-    const int lane = threadIdx.x & 63;
-    const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (u >= N) return;
-    float key[2];
-    int id[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) { key[j] = INFINITY; id[j] = 0x7fffffff; }
-    for (int base = 0; base < K; base += 8) {
-        const int e = base + (lane >> 3);
-        const int32_t v = e < K ? bid[u * kKnnCap + e] : -1;
-        const bool ok = e < K && v >= 0 && v < N && v != u;
-        const float d2 = dist8<DP>(vec, (int32_t)u, ok ? v : (int32_t)u, lane);
-        // element e goes to register e / 64 of lane e % 64
-        for (int g = 0; g < 8; ++g) {
-            const int ee = base + g;
-            const float dd = __shfl(d2, g * 8);
-            const int vv = __shfl(v, g * 8);
-            const bool okk = __shfl((int)ok, g * 8) != 0;
-            if (ee < 128 && (ee & 63) == lane) {
-                const float kk = okk ? dd : INFINITY;
-                const int ii = okk ? vv : 0x7fffffff;
-                if (ee < 64) { key[0] = kk; id[0] = ii; }
-                else { key[1] = kk; id[1] = ii; }
-            }
-        }
-    }
-    mt::wave_sort<2>(key, id, lane);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int e = j * 64 + lane;
-        if (e < Kc) {
-            const bool ok = key[j] < INFINITY;
-            out_id[u * Kc + e] = ok ? id[j] : -1;
-            out_d2[u * Kc + e] = key[j];
-        }
-    }
-}
-
-// RNG prune of one wave's candidate list (sorted by (d2, id), m entries, in
-// LDS).  keep v unless a kept w has d2(w, v) < d2(u, v); at most R kept.
-template <int DP>
-__device__ __forceinline__ int rng_prune(const float *vec, const int32_t *cid, const float *cd2,
-                                         int m, int R, int32_t *kept, int lane) {
-    int nk = 0;
-    for (int i = 0; i < m && nk < R; ++i) {
-        const int32_t v = cid[i];
-        const float dv = cd2[i];
-        if (v < 0) continue;
-        bool blocked = false;
-        for (int b0 = 0; b0 < nk && !blocked; b0 += 8) {
-            const int b = b0 + (lane >> 3);
-            const int32_t wv = b < nk ? kept[b] : v;
-            const float d2 = dist8<DP>(vec, wv, v, lane);
-            blocked = __ballot(b < nk && d2 < dv) != 0;
-        }
-        if (!blocked) {
-            if (lane == 0) kept[nk] = v;
-            ++nk;
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-            __builtin_amdgcn_wave_barrier();
-        }
-    }
-    return nk;
-}
-
-// forward prune of every node's re-ranked kNN list
-template <int DP>
-__global__ void __launch_bounds__(256)
-k_prune_fwd(const float *vec, int64_t N, const int32_t *kid, const float *kd2, int Kc, int R,
-            int32_t *fwd, float *fwd_d2, int32_t *fdeg, int32_t *indeg) {
-    __shared__ int32_t s_kept[4][64];
-    __shared__ int32_t s_cid[4][256];
-    __shared__ float s_cd[4][256];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t u = (int64_t)blockIdx.x * 4 + w;
-    if (u >= N) return;
-    for (int e = lane; e < Kc; e += 64) { s_cid[w][e] = kid[u * Kc + e]; s_cd[w][e] = kd2[u * Kc + e]; }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    const int nk = rng_prune<DP>(vec, s_cid[w], s_cd[w], Kc, R, s_kept[w], lane);
-    for (int e = lane; e < R; e += 64) {
-        const int32_t v = e < nk ? s_kept[w][e] : -1;
-        fwd[u * R + e] = v;
-        float dv = INFINITY;
-        for (int t = 0; t < Kc; ++t)
-            if (s_cid[w][t] == v) { dv = s_cd[w][t]; break; }
-        fwd_d2[u * R + e] = e < nk ? dv : INFINITY;
-        if (e < nk) atomicAdd(&indeg[v], 1);
-    }
-    if (lane == 0) fdeg[u] = nk;
-}
-
 __global__ void k_scatter_rev(int64_t N, int R, const int32_t *fwd, const float *fwd_d2,
                               const int64_t *roff, int32_t *rpos, int32_t *rid, float *rd2) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -249,77 +123,6 @@ __global__ void k_scatter_rev(int64_t N, int R, const int32_t *fwd, const float 
     const int at = atomicAdd(&rpos[v], 1);
     rid[roff[v] + at] = (int32_t)u;
     rd2[roff[v] + at] = fwd_d2[e];
-}
-
-// final rows: fwd(v) + rev(v), sorted by (d2, id), deduplicated; kept whole
-// if <= R, else RNG-pruned to R.  Reverse lists longer than the buffer keep
-// their smallest (d2, id) entries (streamed through a sorted 1024 buffer).
-template <int DP>
-__global__ void __launch_bounds__(256)
-k_prune_rev(const float *vec, int64_t N, int R, const int32_t *fwd, const float *fwd_d2,
-            const int32_t *fdeg, const int64_t *roff, const int32_t *rid, const float *rd2,
-            int32_t *adj) {
-    __shared__ int32_t s_kept[4][64];
-    __shared__ int32_t s_cid[4][kCandMax];
-    __shared__ float s_cd[4][kCandMax];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t v = (int64_t)blockIdx.x * 4 + w;
-    if (v >= N) return;
-    float key[16];
-    int id[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) { key[j] = INFINITY; id[j] = 0x7fffffff; }
-    const int nf = fdeg[v];
-    const int64_t r0 = roff[v], nr = roff[v + 1] - r0;
-    const int64_t total = nf + nr;
-    // stream all candidates through the sorted buffer, 256 new ones at a time
-    for (int64_t base = 0; base < total; base += 256) {
-#pragma unroll
-        for (int j = 12; j < 16; ++j) {
-            const int64_t e = base + (j - 12) * 64 + lane;
-            float k = INFINITY;
-            int i = 0x7fffffff;
-            if (e < total) {
-                if (e < nf) { i = fwd[v * R + e]; k = fwd_d2[v * R + e]; }
-                else { i = rid[r0 + (e - nf)]; k = rd2[r0 + (e - nf)]; }
-            }
-            key[j] = k;
-            id[j] = i;
-        }
-        mt::wave_sort<16>(key, id, lane);
-    }
-    // dedup (equal ids are adjacent: same id, same squared distance); when
-    // more than 1024 candidates were streamed only the first 768 of the
-    // sorted buffer are exact ranks, so only those are used
-    const int limit = total > kCandMax ? 768 : kCandMax;
-    int m = 0;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int up = __shfl_up(id[j], 1);
-        const int last = j > 0 ? __shfl(id[j > 0 ? j - 1 : 0], 63) : -2;
-        const int prev = lane == 0 ? last : up;
-        const bool keep = (j * 64 + lane) < limit && key[j] < INFINITY && id[j] != 0x7fffffff &&
-                          id[j] != prev;
-        const uint64_t mk = __ballot(keep);
-        if (keep) {
-            const int at = m + __popcll(mk & ((1ull << lane) - 1ull));
-            s_cid[w][at] = id[j];
-            s_cd[w][at] = key[j];
-        }
-        m += __popcll(mk);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    int nk;
-    if (m <= R) {
-        for (int e = lane; e < m; e += 64) s_kept[w][e] = s_cid[w][e];
-        nk = m;
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-    } else {
-        nk = rng_prune<DP>(vec, s_cid[w], s_cd[w], m, R, s_kept[w], lane);
-    }
-    for (int e = lane; e < R; e += 64) adj[v * R + e] = e < nk ? s_kept[w][e] : -1;
 }
 
 // ------------------------------------------------------- entry point --
@@ -412,39 +215,43 @@ __global__ void k_attach(const float *vec, int dp, int32_t *adj, int R, int32_t 
     (void)s_i;
 }
 
-inline unsigned g1b(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-template <int DP>
-void launch_rows(const float *vec, int64_t N, int R, int K, int Kc, const int32_t *bid,
+}  // namespace
+
+// row-width instantiations of the row kernels (build_inst.hip)
+#define VJ_BUILD_WIDTHS(X) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+#define VJ_DECL(dp)                                                                         \
+    void build_rows_##dp(const float *, int64_t, int, int, int, const int32_t *, int32_t *,  \
+                         float *, int32_t *, float *, int32_t *, int32_t *, hipStream_t);    \
+    void build_rev_##dp(const float *, int64_t, int, const int32_t *, const float *,         \
+                        const int32_t *, const int64_t *, const int32_t *, const float *,    \
+                        int32_t *, hipStream_t);
+VJ_BUILD_WIDTHS(VJ_DECL)
+#undef VJ_DECL
+
+namespace {
+
+void launch_rows(int dp, const float *vec, int64_t N, int R, int K, int Kc, const int32_t *bid,
                  int32_t *kid, float *kd2, int32_t *fwd, float *fwd_d2, int32_t *fdeg,
                  int32_t *indeg, hipStream_t s) {
-    hipLaunchKernelGGL(k_rerank<DP>, dim3(g1b(N, 4)), dim3(256), 0, s, vec, N, bid, K, Kc, kid, kd2);
-    hipLaunchKernelGGL(k_prune_fwd<DP>, dim3(g1b(N, 4)), dim3(256), 0, s, vec, N, kid, kd2, Kc, R,
-                       fwd, fwd_d2, fdeg, indeg);
-}
-
-template <int DP>
-void launch_rev(const float *vec, int64_t N, int R, const int32_t *fwd, const float *fwd_d2,
-                const int32_t *fdeg, const int64_t *roff, const int32_t *rid, const float *rd2,
-                int32_t *adj, hipStream_t s) {
-    hipLaunchKernelGGL(k_prune_rev<DP>, dim3(g1b(N, 4)), dim3(256), 0, s, vec, N, R, fwd, fwd_d2,
-                       fdeg, roff, rid, rd2, adj);
-}
-
-#define VJ_DP_SWITCH(dp, CALL)                                                     \
-    switch (dp) {                                                                  \
-    case 32: { constexpr int DP = 32; CALL; } break;                               \
-    case 64: { constexpr int DP = 64; CALL; } break;                               \
-    case 96: { constexpr int DP = 96; CALL; } break;                               \
-    case 128: { constexpr int DP = 128; CALL; } break;                             \
-    case 192: { constexpr int DP = 192; CALL; } break;                             \
-    case 256: { constexpr int DP = 256; CALL; } break;                             \
-    case 384: { constexpr int DP = 384; CALL; } break;                             \
-    case 512: { constexpr int DP = 512; CALL; } break;                             \
-    case 768: { constexpr int DP = 768; CALL; } break;                             \
-    case 1024: { constexpr int DP = 1024; CALL; } break;                           \
-    default: VJ_CHECK(false, VJ_ERR_UNSUPPORTED, "row width");                     \
+    switch (dp) {
+#define VJ_CASE(w) case w: build_rows_##w(vec, N, R, K, Kc, bid, kid, kd2, fwd, fwd_d2, fdeg, indeg, s); return;
+        VJ_BUILD_WIDTHS(VJ_CASE)
+#undef VJ_CASE
+    default: VJ_CHECK(false, VJ_ERR_UNSUPPORTED, "row width");
     }
+}
+
+void launch_rev(int dp, const float *vec, int64_t N, int R, const int32_t *fwd,
+                const float *fwd_d2, const int32_t *fdeg, const int64_t *roff,
+                const int32_t *rid, const float *rd2, int32_t *adj, hipStream_t s) {
+    switch (dp) {
+#define VJ_CASE(w) case w: build_rev_##w(vec, N, R, fwd, fwd_d2, fdeg, roff, rid, rd2, adj, s); return;
+        VJ_BUILD_WIDTHS(VJ_CASE)
+#undef VJ_CASE
+    default: VJ_CHECK(false, VJ_ERR_UNSUPPORTED, "row width");
+    }
+}
 
 }  // namespace
 
@@ -482,9 +289,8 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
     DevBuf fwd((size_t)N * R * sizeof(int32_t)), fwd_d2((size_t)N * R * sizeof(float));
     DevBuf fdeg((size_t)N * sizeof(int32_t)), indeg((size_t)N * sizeof(int32_t));
     VJ_HIP(hipMemsetAsync(indeg.p, 0, indeg.bytes, s));
-    VJ_DP_SWITCH(dp, (launch_rows<DP>(vec, N, R, K, kc, bidb.as<int32_t>(), kid.as<int32_t>(),
-                                      kd2.as<float>(), fwd.as<int32_t>(), fwd_d2.as<float>(),
-                                      fdeg.as<int32_t>(), indeg.as<int32_t>(), s)));
+    launch_rows(dp, vec, N, R, K, kc, bidb.as<int32_t>(), kid.as<int32_t>(), kd2.as<float>(),
+                fwd.as<int32_t>(), fwd_d2.as<float>(), fdeg.as<int32_t>(), indeg.as<int32_t>(), s);
     VJ_HIP(hipGetLastError());
     bidb.release();
 
@@ -503,9 +309,8 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
                        fwd.as<int32_t>(), fwd_d2.as<float>(), roff.as<int64_t>(),
                        rpos.as<int32_t>(), rid.as<int32_t>(), rd2.as<float>());
     ix.adj.alloc((size_t)N * R * sizeof(int32_t));
-    VJ_DP_SWITCH(dp, (launch_rev<DP>(vec, N, R, fwd.as<int32_t>(), fwd_d2.as<float>(),
-                                     fdeg.as<int32_t>(), roff.as<int64_t>(), rid.as<int32_t>(),
-                                     rd2.as<float>(), ix.adj.as<int32_t>(), s)));
+    launch_rev(dp, vec, N, R, fwd.as<int32_t>(), fwd_d2.as<float>(), fdeg.as<int32_t>(),
+               roff.as<int64_t>(), rid.as<int32_t>(), rd2.as<float>(), ix.adj.as<int32_t>(), s);
     VJ_HIP(hipGetLastError());
 
     // 4. entry = node nearest to the fp64 centroid (ties: smaller id)

@@ -1,0 +1,234 @@
+// Row-wise graph-build kernels templated on the padded row width DP:
+// exact re-rank of the kNN candidates, the forward RNG prune and the prune
+// of forward + reverse candidates (Appendix C edge rule; ties by smaller
+// id).  Instantiated once per width by build_inst.hip.
+#pragma once
+
+#include "mfma_tile.h"
+#include "vj_internal.h"
+
+namespace vj {
+namespace brow {
+
+constexpr int kKnnCap = 384;   // per-row candidate buffer of the top-K sweep
+constexpr int kCandMax = 1024; // candidates a reverse-edge prune considers
+
+inline unsigned g1b(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+// --------------------------------------------------- row distance helper --
+// squared L2 distances from row `u` to up to 8 rows at once: lane group g
+// (8 lanes) handles ids[g]; returns the group's total in every lane of it.
+template <int DP>
+__device__ __forceinline__ float dist8(const float *vec, int32_t u, int32_t v, int lane) {
+    constexpr int CH = DP / 4;             // float4 chunks per row
+    constexpr int PER = (CH + 7) / 8;       // chunks per lane
+    const int p = lane & 7;
+    const float4 *a = reinterpret_cast<const float4 *>(vec + (size_t)u * DP);
+    const float4 *b = reinterpret_cast<const float4 *>(vec + (size_t)v * DP);
+    float acc = 0.f;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int c = p + 8 * t;
+        if (c < CH) {
+            const float4 x = a[c], y = b[c];
+            float q;
+            q = x.x - y.x; acc = fmaf(q, q, acc);
+            q = x.y - y.y; acc = fmaf(q, q, acc);
+            q = x.z - y.z; acc = fmaf(q, q, acc);
+            q = x.w - y.w; acc = fmaf(q, q, acc);
+        }
+    }
+    acc += __shfl_xor(acc, 4);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 1);
+    return acc;
+}
+
+// Exact re-rank of the K buffered neighbours of every row: direct fp32 squared
+// distances, sorted by (distance, id); the first Kc are written out.
+template <int DP>
+__global__ void __launch_bounds__(256)
+k_rerank(const float *vec, int64_t N, const int32_t *bid, int K, int Kc, int32_t *out_id,
+         float *out_d2) {
+    const int lane = threadIdx.x & 63;
+    const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (u >= N) return;
+    float key[2];
+    int id[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) { key[j] = INFINITY; id[j] = 0x7fffffff; }
+    for (int base = 0; base < K; base += 8) {
+        const int e = base + (lane >> 3);
+        const int32_t v = e < K ? bid[u * kKnnCap + e] : -1;
+        const bool ok = e < K && v >= 0 && v < N && v != u;
+        const float d2 = dist8<DP>(vec, (int32_t)u, ok ? v : (int32_t)u, lane);
+        // element e goes to register e / 64 of lane e % 64
+        for (int g = 0; g < 8; ++g) {
+            const int ee = base + g;
+            const float dd = __shfl(d2, g * 8);
+            const int vv = __shfl(v, g * 8);
+            const bool okk = __shfl((int)ok, g * 8) != 0;
+            if (ee < 128 && (ee & 63) == lane) {
+                const float kk = okk ? dd : INFINITY;
+                const int ii = okk ? vv : 0x7fffffff;
+                if (ee < 64) { key[0] = kk; id[0] = ii; }
+                else { key[1] = kk; id[1] = ii; }
+            }
+        }
+    }
+    mt::wave_sort<2>(key, id, lane);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int e = j * 64 + lane;
+        if (e < Kc) {
+            const bool ok = key[j] < INFINITY;
+            out_id[u * Kc + e] = ok ? id[j] : -1;
+            out_d2[u * Kc + e] = key[j];
+        }
+    }
+}
+
+// RNG prune of one wave's candidate list (sorted by (d2, id), m entries, in
+// LDS).  keep v unless a kept w has d2(w, v) < d2(u, v); at most R kept.
+template <int DP>
+__device__ __forceinline__ int rng_prune(const float *vec, const int32_t *cid, const float *cd2,
+                                         int m, int R, int32_t *kept, int lane) {
+    int nk = 0;
+    for (int i = 0; i < m && nk < R; ++i) {
+        const int32_t v = cid[i];
+        const float dv = cd2[i];
+        if (v < 0) continue;
+        bool blocked = false;
+        for (int b0 = 0; b0 < nk && !blocked; b0 += 8) {
+            const int b = b0 + (lane >> 3);
+            const int32_t wv = b < nk ? kept[b] : v;
+            const float d2 = dist8<DP>(vec, wv, v, lane);
+            blocked = __ballot(b < nk && d2 < dv) != 0;
+        }
+        if (!blocked) {
+            if (lane == 0) kept[nk] = v;
+            ++nk;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    return nk;
+}
+
+// forward prune of every node's re-ranked kNN list
+template <int DP>
+__global__ void __launch_bounds__(256)
+k_prune_fwd(const float *vec, int64_t N, const int32_t *kid, const float *kd2, int Kc, int R,
+            int32_t *fwd, float *fwd_d2, int32_t *fdeg, int32_t *indeg) {
+    __shared__ int32_t s_kept[4][64];
+    __shared__ int32_t s_cid[4][256];
+    __shared__ float s_cd[4][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t u = (int64_t)blockIdx.x * 4 + w;
+    if (u >= N) return;
+    for (int e = lane; e < Kc; e += 64) { s_cid[w][e] = kid[u * Kc + e]; s_cd[w][e] = kd2[u * Kc + e]; }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    const int nk = rng_prune<DP>(vec, s_cid[w], s_cd[w], Kc, R, s_kept[w], lane);
+    for (int e = lane; e < R; e += 64) {
+        const int32_t v = e < nk ? s_kept[w][e] : -1;
+        fwd[u * R + e] = v;
+        float dv = INFINITY;
+        for (int t = 0; t < Kc; ++t)
+            if (s_cid[w][t] == v) { dv = s_cd[w][t]; break; }
+        fwd_d2[u * R + e] = e < nk ? dv : INFINITY;
+        if (e < nk) atomicAdd(&indeg[v], 1);
+    }
+    if (lane == 0) fdeg[u] = nk;
+}
+
+
+// final rows: fwd(v) + rev(v), sorted by (d2, id), deduplicated; kept whole
+// if <= R, else RNG-pruned to R.  Reverse lists longer than the buffer keep
+// their smallest (d2, id) entries (streamed through a sorted 1024 buffer).
+template <int DP>
+__global__ void __launch_bounds__(256)
+k_prune_rev(const float *vec, int64_t N, int R, const int32_t *fwd, const float *fwd_d2,
+            const int32_t *fdeg, const int64_t *roff, const int32_t *rid, const float *rd2,
+            int32_t *adj) {
+    __shared__ int32_t s_kept[4][64];
+    __shared__ int32_t s_cid[4][kCandMax];
+    __shared__ float s_cd[4][kCandMax];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t v = (int64_t)blockIdx.x * 4 + w;
+    if (v >= N) return;
+    float key[16];
+    int id[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) { key[j] = INFINITY; id[j] = 0x7fffffff; }
+    const int nf = fdeg[v];
+    const int64_t r0 = roff[v], nr = roff[v + 1] - r0;
+    const int64_t total = nf + nr;
+    // stream all candidates through the sorted buffer, 256 new ones at a time
+    for (int64_t base = 0; base < total; base += 256) {
+#pragma unroll
+        for (int j = 12; j < 16; ++j) {
+            const int64_t e = base + (j - 12) * 64 + lane;
+            float k = INFINITY;
+            int i = 0x7fffffff;
+            if (e < total) {
+                if (e < nf) { i = fwd[v * R + e]; k = fwd_d2[v * R + e]; }
+                else { i = rid[r0 + (e - nf)]; k = rd2[r0 + (e - nf)]; }
+            }
+            key[j] = k;
+            id[j] = i;
+        }
+        mt::wave_sort<16>(key, id, lane);
+    }
+    // dedup (equal ids are adjacent: same id, same squared distance); when
+    // more than 1024 candidates were streamed only the first 768 of the
+    // sorted buffer are exact ranks, so only those are used
+    const int limit = total > kCandMax ? 768 : kCandMax;
+    int m = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int up = __shfl_up(id[j], 1);
+        const int last = j > 0 ? __shfl(id[j > 0 ? j - 1 : 0], 63) : -2;
+        const int prev = lane == 0 ? last : up;
+        const bool keep = (j * 64 + lane) < limit && key[j] < INFINITY && id[j] != 0x7fffffff &&
+                          id[j] != prev;
+        const uint64_t mk = __ballot(keep);
+        if (keep) {
+            const int at = m + __popcll(mk & ((1ull << lane) - 1ull));
+            s_cid[w][at] = id[j];
+            s_cd[w][at] = key[j];
+        }
+        m += __popcll(mk);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    int nk;
+    if (m <= R) {
+        for (int e = lane; e < m; e += 64) s_kept[w][e] = s_cid[w][e];
+        nk = m;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        nk = rng_prune<DP>(vec, s_cid[w], s_cd[w], m, R, s_kept[w], lane);
+    }
+    for (int e = lane; e < R; e += 64) adj[v * R + e] = e < nk ? s_kept[w][e] : -1;
+}
+
+template <int DP>
+void launch_rows(const float *vec, int64_t N, int R, int K, int Kc, const int32_t *bid,
+                 int32_t *kid, float *kd2, int32_t *fwd, float *fwd_d2, int32_t *fdeg,
+                 int32_t *indeg, hipStream_t s) {
+    hipLaunchKernelGGL(k_rerank<DP>, dim3(g1b(N, 4)), dim3(256), 0, s, vec, N, bid, K, Kc, kid, kd2);
+    hipLaunchKernelGGL(k_prune_fwd<DP>, dim3(g1b(N, 4)), dim3(256), 0, s, vec, N, kid, kd2, Kc, R,
+                       fwd, fwd_d2, fdeg, indeg);
+}
+
+template <int DP>
+void launch_rev(const float *vec, int64_t N, int R, const int32_t *fwd, const float *fwd_d2,
+                const int32_t *fdeg, const int64_t *roff, const int32_t *rid, const float *rd2,
+                int32_t *adj, hipStream_t s) {
+    hipLaunchKernelGGL(k_prune_rev<DP>, dim3(g1b(N, 4)), dim3(256), 0, s, vec, N, R, fwd, fwd_d2,
+                       fdeg, roff, rid, rd2, adj);
+}
+
+}  // namespace brow
+}  // namespace vj

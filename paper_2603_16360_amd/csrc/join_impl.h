@@ -14,7 +14,7 @@
 // All per-query state lives in LDS: the visited hash, the in-range worklist
 // (which is also the query's pair buffer) and the out-range queue.  A query
 // that outgrows them is re-run on a larger tier: a whole workgroup with 8x
-// the LDS visited slots, then per-wave regions of global memory.
+// the LDS visited slots, then a whole workgroup with tables in global memory.
 //
 // Rows are gathered LPR lanes per row, 16 bytes per lane per load (a row
 // group's load covers whole 128-byte lines), and reduced with xor shuffles
@@ -263,7 +263,7 @@ __device__ __forceinline__ void run_batch(const JoinArgs &a, const WaveMem &m, Q
 template <typename T, int DP>
 __device__ __forceinline__ void run_query(const JoinArgs &a, const WaveMem &m, int k,
                                           const int32_t *qlist, const int32_t *qpos,
-                                          int32_t *ovf, int32_t *ovf_count, int tier, int lane) {
+                                          int32_t *ovf, int32_t *ovf_count, int lane) {
     constexpr int CE = Elem<T>::CE;
     constexpr int CPR = DP / CE;
     constexpr int LPR = pick_lpr(CPR);
@@ -464,7 +464,7 @@ __device__ __forceinline__ void run_query(const JoinArgs &a, const WaveMem &m, i
         st[4] = ood;
         st[5] = hyb ? 1 : 0;
         st[6] = s.nvis;
-        st[7] = (tier > 0 ? 1 : 0) | (tier > 1 ? 8 : 0);
+        st[7] = 0;
     }
 }
 
@@ -495,35 +495,7 @@ k_join_lds(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t 
     m.stage = sh_stage[wib];
     m.hk = sh_hk[wib];
     m.hi = sh_hi[wib];
-    run_query<T, DP>(a, m, k, qlist, qpos, ovf, ovf_count, 0, lane);
-}
-
-// global tier: visited set and worklist in per-wave regions of global memory
-template <typename T, int DP, bool HYB>
-__global__ void __launch_bounds__(64 * kWaves)
-k_join_spill(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos, int k0,
-             int k1, int32_t *gh, int hash_log2, int32_t *gil, float *gild, int il_cap,
-             int32_t *ovf, int32_t *ovf_count) {
-    __shared__ int32_t sh_stage[kWaves][64];
-    __shared__ float sh_hk[kWaves][HYB ? kHeap : 1];
-    __shared__ int32_t sh_hi[kWaves][HYB ? kHeap : 1];
-    const int lane = threadIdx.x & 63;
-    const int wib = threadIdx.x >> 6;
-    const int k = k0 + (int)blockIdx.x * kWaves + wib;
-    if (k >= k1) return;
-    const JoinArgs &a = *pa;
-    const size_t w = (size_t)(k - k0);  // scratch region of this wave
-    WaveMem m;
-    m.hash = gh + (w << hash_log2);
-    m.hash_log2 = hash_log2;
-    m.hash_limit = (1 << hash_log2) / 2;
-    m.il = gil + w * il_cap;
-    m.ild = gild + w * il_cap;
-    m.il_cap = il_cap;
-    m.stage = sh_stage[wib];
-    m.hk = sh_hk[wib];
-    m.hi = sh_hi[wib];
-    run_query<T, DP>(a, m, k, qlist, qpos, ovf, ovf_count, 2, lane);
+    run_query<T, DP>(a, m, k, qlist, qpos, ovf, ovf_count, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -664,7 +636,7 @@ template <typename T, int DP, int W>
 __device__ __forceinline__ void run_query_coop(const JoinArgs &a, const WaveMem &m,
                                                CoopShared<W> &sh, int heap_cap, int k,
                                                const int32_t *qlist, const int32_t *qpos,
-                                               int32_t *ovf, int32_t *ovf_count) {
+                                               int32_t *ovf, int32_t *ovf_count, int flags) {
     constexpr int CE = Elem<T>::CE;
     constexpr int CPR = DP / CE;
     constexpr int LPR = pick_lpr(CPR);
@@ -917,7 +889,7 @@ __device__ __forceinline__ void run_query_coop(const JoinArgs &a, const WaveMem 
         st[4] = sh.ood;
         st[5] = hyb ? 1 : 0;
         st[6] = lds_load(&sh.nvis);
-        st[7] = 1;
+        st[7] = flags;
     }
 }
 
@@ -948,7 +920,37 @@ k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t
     m.stage = sh_stage[threadIdx.x >> 6];
     m.hk = sh_hk;
     m.hi = sh_hi;
-    run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, ovf, ovf_count);
+    run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, ovf, ovf_count, 1);
+}
+
+// cooperative tier on global tables: one query per workgroup of W waves,
+// its visited set (2^hash_log2 slots) and in-range list (il_cap entries) in
+// the workgroup's region of gh / gil / gild (region = block - first block)
+template <typename T, int DP, bool HYB, int W>
+__global__ void __launch_bounds__(64 * W)
+k_join_coop_global(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos,
+                   int k0, int k1, int32_t *gh, int hash_log2, int32_t *gil, float *gild,
+                   int il_cap, int32_t *ovf, int32_t *ovf_count) {
+    constexpr int HC = HYB ? kBeamMax + 64 * W : 1;
+    __shared__ int32_t sh_stage[W][64];
+    __shared__ float sh_hk[HC];
+    __shared__ int32_t sh_hi[HC];
+    __shared__ CoopShared<W> sh;
+    const int k = k0 + (int)blockIdx.x;
+    if (k >= k1) return;
+    const JoinArgs &a = *pa;
+    const size_t r = blockIdx.x;
+    WaveMem m;
+    m.hash = gh + (r << hash_log2);
+    m.hash_log2 = hash_log2;
+    m.hash_limit = (1 << hash_log2) / 2;
+    m.il = gil + r * (size_t)il_cap;
+    m.ild = gild + r * (size_t)il_cap;
+    m.il_cap = il_cap;
+    m.stage = sh_stage[threadIdx.x >> 6];
+    m.hk = sh_hk;
+    m.hi = sh_hi;
+    run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, ovf, ovf_count, 1 | 8);
 }
 
 template <typename T, int DP, bool HYB>
@@ -964,10 +966,9 @@ void launch_tier(const JoinLaunch &L, hipStream_t s) {
                            dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, L.ovf,
                            L.ovf_count);
     } else {
-        const unsigned blocks = (unsigned)((L.count + kWaves - 1) / kWaves);
-        hipLaunchKernelGGL((k_join_spill<T, DP, HYB>), dim3(blocks), dim3(64 * kWaves), 0, s,
-                           L.args, L.qlist, L.qpos, k0, k1, L.gh, L.hash_log2, L.gil, L.gild,
-                           L.il_cap, L.ovf, L.ovf_count);
+        hipLaunchKernelGGL((k_join_coop_global<T, DP, HYB, kWaves>), dim3((unsigned)L.count),
+                           dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, L.gh,
+                           L.hash_log2, L.gil, L.gild, L.il_cap, L.ovf, L.ovf_count);
     }
 }
 

@@ -262,6 +262,11 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
         r.kernel_ms = 0.f;
         r.spill_ms = 0.f;
         r.n_spilled = 0;
+        for (int t = 0; t < 4; ++t) {
+            r.tier_ms[t] = 0.f;
+            r.tier_launches[t] = 0;
+            r.tier_queries[t] = 0;
+        }
         out_q.reserve((size_t)cap * sizeof(int32_t));
         out_x.reserve((size_t)cap * sizeof(int32_t));
         out_d.reserve((size_t)cap * sizeof(float));
@@ -323,7 +328,7 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
                 // pairs per query; tier 3: tables as large as the data set
                 L.hash_log2 = tier == 2 ? std::min(16, ceil_log2(2 * ix.nx)) : ceil_log2(2 * ix.nx);
                 L.il_cap = (int)(tier == 2 ? std::min<int64_t>(ix.nx, 1 << 15) : ix.nx);
-                chunk = tier == 2 ? 1024 : 4;
+                chunk = tier == 2 ? 1024 : 16;
                 gh.reserve((size_t)std::min(chunk, cnt) * ((size_t)1 << L.hash_log2) * sizeof(int32_t));
                 gil.reserve((size_t)std::min(chunk, cnt) * L.il_cap * sizeof(int32_t));
                 gild.reserve((size_t)std::min(chunk, cnt) * L.il_cap * sizeof(float));
@@ -343,7 +348,10 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
                 float ms = 0.f;
                 VJ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
                 total_ms += ms;
+                r.tier_launches[tier] += 1;
             }
+            r.tier_ms[tier] += total_ms;
+            r.tier_queries[tier] += cnt;
             return total_ms;
         };
         for (size_t lv = 0; lv + 1 < ord.level_start.size(); ++lv) {
@@ -623,6 +631,17 @@ vj_status vj_pairs_timing(const vj_pairs *r, float *kernel_ms, float *spill_ms,
     if (kernel_ms) *kernel_ms = r->impl.kernel_ms;
     if (spill_ms) *spill_ms = r->impl.spill_ms;
     if (n_spilled) *n_spilled = r->impl.n_spilled;
+    API_END
+}
+
+vj_status vj_pairs_tiers(const vj_pairs *r, float *ms, int32_t *launches, int64_t *queries) {
+    API_BEGIN
+    VJ_CHECK(r != nullptr, VJ_ERR_INVALID_ARG, "null result");
+    for (int t = 0; t < 4; ++t) {
+        if (ms) ms[t] = r->impl.tier_ms[t];
+        if (launches) launches[t] = r->impl.tier_launches[t];
+        if (queries) queries[t] = r->impl.tier_queries[t];
+    }
     API_END
 }
 

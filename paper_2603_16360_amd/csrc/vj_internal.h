@@ -97,6 +97,9 @@ struct Pairs {
     float kernel_ms = 0.f;    // join: LDS-variant launches, timed with events on the stream
     float spill_ms = 0.f;     // join: spill-variant launches
     int64_t n_spilled = 0;    // join: queries re-run on the spill variant
+    float tier_ms[4] = {0.f, 0.f, 0.f, 0.f};  // join: device time per storage tier
+    int32_t tier_launches[4] = {0, 0, 0, 0};
+    int64_t tier_queries[4] = {0, 0, 0, 0};
     DevBuf q, x, dist;       // int32, int32, float [count]
     DevBuf stats;            // int32 [n_queries][8]
 };
@@ -134,11 +137,11 @@ struct JoinLaunch {
     const int32_t *qlist;     // query index per processing slot
     const int32_t *qpos;      // caller position per processing slot
     int first, count, dp, prec;  // slots [first, first + count) of qlist
-    int tier;                    // 0 small LDS, 1 large LDS, 2 global tables
+    int tier;                    // 0 one wave + LDS, 1 workgroup + LDS, 2 workgroup + global
     bool hyb;
-    int32_t *gh;              // spill: [count][1 << hash_log2] visited sets, by slot - first
+    int32_t *gh;              // tier 2: [count][1 << hash_log2] visited sets, by slot - first
     int hash_log2;
-    int32_t *gil;             // spill: [count][il_cap] worklists
+    int32_t *gil;             // tier 2: [count][il_cap] in-range lists
     float *gild;
     int il_cap;
     int32_t *ovf, *ovf_count; // slots (indices into qlist) that must be re-run

@@ -70,6 +70,7 @@ _SIGS = {
     "vj_pairs_export": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
     "vj_pairs_stats": (C.c_int, [_vp, _vp, _vp]),
     "vj_pairs_timing": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "vj_pairs_tiers": (C.c_int, [_vp, _vp, _vp, _vp]),
     "vj_pairs_free": (None, [_vp]),
     "vj_last_error": (C.c_char_p, []),
 }
@@ -112,7 +113,7 @@ class Pairs:
         self.n_queries = n_queries
 
     def __del__(self):
-        if getattr(self, "_h", None) and self._h.value:
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
             _lib.vj_pairs_free(self._h)
             self._h = C.c_void_p(0)
 
@@ -133,6 +134,12 @@ class Pairs:
         _check(_lib.vj_pairs_timing(self._h, C.byref(k), C.byref(sp), C.byref(ns)))
         return {"kernel_ms": k.value, "spill_ms": sp.value, "n_spilled": ns.value}
 
+    def tiers(self) -> list:
+        """Per storage tier 0..3: device ms, launches, queries launched."""
+        ms, ln, nq = (C.c_float * 4)(), (C.c_int32 * 4)(), (C.c_int64 * 4)()
+        _check(_lib.vj_pairs_tiers(self._h, ms, ln, nq))
+        return [{"ms": ms[t], "launches": ln[t], "queries": nq[t]} for t in range(4)]
+
     def stats(self) -> torch.Tensor:
         """Per-query counters [n, 8] int32 (columns STAT_FIELDS)."""
         st = torch.empty((self.n_queries, 8), dtype=torch.int32, device="cuda")
@@ -148,7 +155,7 @@ class Index:
         self._h = C.c_void_p(handle)
 
     def __del__(self):
-        if getattr(self, "_h", None) and self._h.value:
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
             _lib.vj_index_free(self._h)
             self._h = C.c_void_p(0)
 
