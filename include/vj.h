@@ -91,7 +91,7 @@ typedef struct {
     float ood_ratio;        /* d1/d2 threshold of VJ_HYB_ADAPT (1.5) */
     int32_t precision;      /* vj_precision */
     const int32_t *budget;  /* device [n]: out-range pops allowed (VJ_HYB_BUDGET); <0: brute force */
-    int32_t start_tier;     /* first storage tier of every query (0): 0 one wave per query,
+    int32_t start_tier;     /* first storage tier of every query (1): 0 one wave per query,
                                1 one workgroup per query, 2 one workgroup per query with its
                                tables in global memory; a query
                                that outgrows a tier re-runs on the next.  Callers that know

@@ -532,6 +532,10 @@ struct CoopWave {
 __device__ __forceinline__ int lds_load(const int *p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
 
 // One candidate batch of one wave against the shared tables (see run_batch).
+// probe: this lane's candidate is a neighbour of q in the probe of an ADAPT
+// query, whose distance is needed (d1) even when it was already visited.
+// Occupancy of the cooperative kernels is bound by LDS, so a pass keeps up
+// to 16 16-byte loads per lane in flight.
 template <typename T, int DP, int W>
 __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, CoopShared<W> &sh,
                                            CoopWave &cw, const float *qf, int32_t v, bool probe,
@@ -541,7 +545,7 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
     constexpr int LPR = pick_lpr(CPR);
     constexpr int VPL = CPR / LPR;
     constexpr int RPP = 64 / LPR;
-    constexpr int PG = (12 / VPL) < (64 / RPP) ? (12 / VPL) : (64 / RPP);
+    constexpr int PG = (16 / VPL) < (64 / RPP) ? (16 / VPL) : (64 / RPP);
     const bool l2 = a.metric == VJ_L2;
     const int p = lane % LPR, rr = lane / LPR;
     const uint64_t ltmask = (1ull << lane) - 1ull;
@@ -562,7 +566,9 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
     const bool need = probe ? valid : isnew;
     const uint64_t mneed = __ballot(need);
     const int cnt = __popcll(mneed);
-    if (need) m.stage[__popcll(mneed & ltmask)] = isnew ? v : ~v;
+    // staged entry: id, or ~id for a probe lane whose node was seen before;
+    // bit 30 marks a probe lane (ids < 2^30)
+    if (need) m.stage[__popcll(mneed & ltmask)] = (isnew ? v : ~v) ^ (probe ? (1 << 30) : 0);
     wave_sync();
     cw.ndist += cnt;
     for (int base = 0; base < cnt; base += RPP * PG) {
@@ -572,7 +578,8 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
         for (int g = 0; g < PG; ++g) {
             const int c = base + g * RPP + rr;
             sid[g] = c < cnt ? m.stage[c] : 0;
-            const int id = sid[g] >= 0 ? sid[g] : ~sid[g];
+            const int e = sid[g] >= 0 ? sid[g] : ~sid[g];
+            const int id = e & ((1 << 30) - 1);
             const uint4 *row = reinterpret_cast<const uint4 *>(vbase + (size_t)id * DP);
 #pragma unroll
             for (int w = 0; w < VPL; ++w)
@@ -584,14 +591,16 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
             const int c = base + g * RPP + rr;
             const bool lead = p == 0 && c < cnt;
             const bool nw = sid[g] >= 0;
-            const int id = nw ? sid[g] : ~sid[g];
+            const int e = nw ? sid[g] : ~sid[g];
+            const bool pl = (e >> 30) & 1;
+            const int id = e & ((1 << 30) - 1);
             const float key = l2 ? acc : 1.0f - acc;
             const bool inr = l2 ? (acc < a.eps2) : (key < a.eps);
             if (lead && nw && (key < cw.best_k || (key == cw.best_k && id < cw.best_id))) {
                 cw.best_k = key;
                 cw.best_id = id;
             }
-            if (probe && lead) {
+            if (pl && lead) {
                 cw.d1sum += l2 ? sqrtf(key) : sqrtf(fmaxf(0.f, 2.f * key));
                 cw.c1 += 1;
             }
@@ -705,22 +714,24 @@ __device__ __forceinline__ void run_query_coop(const JoinArgs &a, const WaveMem 
             }
         }
     }
-    if (wib == 0) {
-        int32_t v = -1;
-        if (lane == 0) v = a.entry;
-        if (lane == 1) v = pcache;
-        coop_batch<T, DP, W>(a, m, sh, cw, qf, v, false, false, heap_cap, lane);
-    }
-    for (int t = wib * 64; t < pcnt && t < a.nx + 64; t += 64 * W) {
-        const int32_t u = t + lane < pcnt ? a.out_x[pseg + t + lane] : -1;
-        coop_batch<T, DP, W>(a, m, sh, cw, qf, u, false, false, heap_cap, lane);
-    }
-    __syncthreads();
-
-    // ---- probe N(q) and CheckHybrid (wave 0)
+    // ---- seeds and the probe of N(q) in one batch of wave 0 (lanes 0..R-1
+    // the neighbours of q, lanes R and R+1 the entry and the soft cache); the
+    // other waves take the parent's in-range list (hard) meanwhile.  The
+    // visited set and the in-range set after this phase are the same as
+    // with seeds first, then the probe.  CheckHybrid follows on wave 0; the
+    // first round's barriers publish it.
     if (wib == 0) {
         const int32_t nbq = lane < R ? a.adj[(size_t)q * R + lane] : -1;
-        coop_batch<T, DP, W>(a, m, sh, cw, qf, nbq, a.hyb == VJ_HYB_ADAPT, false, heap_cap, lane);
+        int32_t v = nbq;
+        if (R <= 62) {
+            if (lane == R) v = a.entry;
+            if (lane == R + 1) v = pcache;
+        } else {
+            const int32_t sv = lane == 0 ? a.entry : lane == 1 ? pcache : -1;
+            coop_batch<T, DP, W>(a, m, sh, cw, qf, sv, false, false, heap_cap, lane);
+        }
+        coop_batch<T, DP, W>(a, m, sh, cw, qf, v, a.hyb == VJ_HYB_ADAPT && lane < R, false,
+                             heap_cap, lane);
         bool hyb = false;
         if (a.hyb == VJ_HYB_FORCE) {
             hyb = true;
@@ -753,6 +764,10 @@ __device__ __forceinline__ void run_query_coop(const JoinArgs &a, const WaveMem 
         }
         if (lane == 0) sh.hyb = hyb ? 1 : 0;
     }
+    for (int t = wib * 64; t < pcnt && t < a.nx + 64; t += 64 * W) {
+        const int32_t u = t + lane < pcnt ? a.out_x[pseg + t + lane] : -1;
+        coop_batch<T, DP, W>(a, m, sh, cw, qf, u, false, false, heap_cap, lane);
+    }
     __syncthreads();
     const bool hyb = sh.hyb != 0;
     const bool hyb_active = hyb && a.beam > 0;
@@ -763,6 +778,20 @@ __device__ __forceinline__ void run_query_coop(const JoinArgs &a, const WaveMem 
     bool pending = false;
     const int budget = a.hyb == VJ_HYB_BUDGET ? a.budget[pos] : 0;
     const int bound = m.il_cap + (1 << m.hash_log2) + 4;
+    // candidates of this wave's nodes in round `head`, from [h, h + n) of
+    // the list (lane b * R + j: neighbour j of node h + b)
+    auto candidates = [&](int h, int n) -> int32_t {
+        const int b = lane / R, j = lane - b * R;
+        int32_t v = -1;
+        if (b < n) {
+            const int32_t u = m.il[h + b];
+            if (u >= 0 && u < a.nx) v = a.adj[(size_t)u * R + j];
+            else atomicOr(a.err, 32);
+        }
+        return v;
+    };
+    int32_t pre_v = -1;  // candidates loaded one round ahead
+    int pre_head = -1;   // the round (list head) they belong to
     for (int round = 0; round < bound; ++round) {
         __syncthreads();
         if (wib == 0) {
@@ -787,14 +816,16 @@ __device__ __forceinline__ void run_query_coop(const JoinArgs &a, const WaveMem 
             const int take = min(W * NB, t - head);
             const int my0 = head + wib * NB;
             const int nmine = max(0, min(NB, head + take - my0));
+            // a prefetch is only made for a round whose nodes were all known
+            const int32_t v = pre_head == head ? pre_v : candidates(my0, nmine);
+            // the next round takes W * NB nodes whatever this round appends
+            // if that many are already listed: load their candidates now
+            const int h2 = head + take;
+            if (t - h2 >= W * NB) {
+                pre_v = candidates(h2 + wib * NB, NB);
+                pre_head = h2;
+            }
             if (nmine > 0) {
-                const int b = lane / R, j = lane - b * R;
-                int32_t v = -1;
-                if (b < nmine) {
-                    const int32_t u = m.il[my0 + b];
-                    if (u >= 0 && u < a.nx) v = a.adj[(size_t)u * R + j];
-                    else atomicOr(a.err, 32);
-                }
                 nexp += nmine;
                 coop_batch<T, DP, W>(a, m, sh, cw, qf, v, false, hyb_active, heap_cap, lane);
             }

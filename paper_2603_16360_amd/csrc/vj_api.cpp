@@ -446,7 +446,7 @@ void vj_default_join_params(vj_join_params *p) {
     p->ood_ratio = 1.5f;
     p->precision = VJ_PREC_FP32;
     p->budget = nullptr;
-    p->start_tier = 0;
+    p->start_tier = 1;
     p->waves_per_cu = 0;
     p->pair_capacity = 0;
 }

@@ -181,7 +181,7 @@ class Index:
 # ---------------------------------------------------------------- functions --
 
 def join_params(work_sharing="self", hybrid="off", hybrid_beam=256, conv_threshold=10,
-                ood_ratio=1.5, precision="fp32", budget=None, start_tier=0, waves_per_cu=0,
+                ood_ratio=1.5, precision="fp32", budget=None, start_tier=1, waves_per_cu=0,
                 pair_capacity=0):
     p = vj_join_params()
     _lib.vj_default_join_params(C.byref(p))

@@ -1,5 +1,6 @@
-"""GPU parity of the merged-index join (vj_join, one wavefront per query,
-per-query state in static LDS) against the CPU oracle.
+"""GPU parity of the merged-index join (vj_join: by default one workgroup
+per query with its tables in LDS; also the one-wave and global-table
+tiers) against the CPU oracle.
 
 Both sides run on the same graph (built by the oracle), the same queries,
 parents and eps.  BFS mode is compared with the sandwich rule: with L and U
@@ -133,17 +134,39 @@ def test_self_bfs_subset_and_duplicates(tiny):
     assert int(st[:, 0].sum()) == len(qx)
 
 
-def test_spill_path_matches(tiny):
-    # at 2.6x eps (oracle: up to 4,449 pairs and 5,135 visited nodes per
-    # query) queries outgrow the small LDS tier, some also the large one, and
-    # re-run on the global-table tier; all must match the oracle
-    eps = tiny.eps * 2.6
-    res = vj.vj_join(tiny.idx, eps)
+def _overflow_case(tiny, mult, start_tier):
+    eps = tiny.eps * mult
+    res = vj.vj_join(tiny.idx, eps, start_tier=start_tier)
     st = res.stats().cpu().numpy()
-    assert (st[:, 7] & 1).sum() > (st[:, 7] & 8).sum() // 8 > 0
     ref = oracle.join(tiny.w.Q, tiny.w.X, tiny.g.adj, tiny.g.entry, eps, uncertain="out")
     refu = oracle.join(tiny.w.Q, tiny.w.X, tiny.g.adj, tiny.g.entry, eps, uncertain="in")
     assert ref.pairs() <= qx_set(_gpu_pairs(res)[0]) <= refu.pairs()
+    exact = ref.stats[:, 0] == refu.stats[:, 0]
+    assert np.array_equal(st[exact, 0], ref.stats[exact, 0])
+    assert np.array_equal(st[exact, 6], ref.stats[exact, 6])
+    return st
+
+
+def test_tier_overflow_one_wave_tier(tiny):
+    # at 1.4x eps (oracle: 178 of 1,000 queries hold > 512 pairs) queries
+    # started on the one-wave tier outgrow its pair list and re-run on the
+    # workgroup tier
+    st = _overflow_case(tiny, 1.4, 0)
+    assert 0 < (st[:, 7] & 1).sum() < len(st)
+
+
+def test_tier_overflow_to_global_tables(tiny):
+    # at 2.6x eps (oracle: up to 4,449 pairs and 5,135 visited nodes; 301
+    # queries hold > 1,536 pairs) queries outgrow the workgroup tier's LDS
+    # tables and re-run on global tables
+    st = _overflow_case(tiny, 2.6, 1)
+    assert 0 < ((st[:, 7] & 8) > 0).sum() < len(st)
+
+
+def test_tier_overflow_chain(tiny):
+    # the same from the one-wave tier: every query re-runs, some twice
+    st = _overflow_case(tiny, 2.6, 0)
+    assert np.all(st[:, 7] & 1) and 0 < ((st[:, 7] & 8) > 0).sum() < len(st)
 
 
 def test_small_result_capacity_regrows(tiny):
@@ -177,7 +200,7 @@ def test_invalid_arguments(tiny):
     assert e.value.status == 1
 
 
-def _mode_parity(case, start_tier=0, **kw):
+def _mode_parity(case, start_tier=1, **kw):
     w = case.w
     par = case.parent if kw.get("work_sharing", "self") != "self" else None
     ref = oracle.join(w.Q, w.X, case.g.adj, case.g.entry, case.eps, metric=w.metric,
@@ -207,12 +230,15 @@ def _mode_parity(case, start_tier=0, **kw):
 def test_modes_match_oracle(tiny, kw):
     res, ref = _mode_parity(tiny, **kw)
     st = res.stats().cpu().numpy()
+    ok = ~ref.stats[:, 7].astype(bool)
+    for col in (0, 2, 3, 6):
+        assert np.array_equal(st[ok, col], ref.stats[ok, col]), col
     if kw.get("hybrid") == "adapt":
         ok = ~ref.stats[:, 7].astype(bool)
         assert np.array_equal(st[ok, 4], ref.stats[ok, 4])
 
 
-@pytest.mark.parametrize("start_tier", [1, 2])
+@pytest.mark.parametrize("start_tier", [0, 2])
 @pytest.mark.parametrize("kw", [
     {},
     {"hybrid": "force"},
@@ -221,25 +247,26 @@ def test_modes_match_oracle(tiny, kw):
     {"work_sharing": "soft", "hybrid": "force"},
     {"work_sharing": "hard"},
 ], ids=lambda k: "-".join(f"{a}={b}" for a, b in k.items()) or "bfs")
-def test_larger_tiers_match_oracle(tiny, kw, start_tier):
-    # every query starts on the workgroup-per-query tier (1) or on the
-    # global-table tier (2); per-query results and counters as on tier 0
+def test_other_tiers_match_oracle(tiny, kw, start_tier):
+    # every query starts on the one-wave tier (0) or on the global-table
+    # tier (2) instead of the default workgroup tier (1); per-query results
+    # and counters as with the default
     _say(f"vj_join tiny start_tier={start_tier} {kw}")
     res, ref = _mode_parity(tiny, start_tier=start_tier, **kw)
     st = res.stats().cpu().numpy()
-    assert np.all(st[:, 7] & 1)
-    assert np.all((st[:, 7] & 8) > 0) == (start_tier == 2)
+    if start_tier == 2:
+        assert np.all(st[:, 7] & 8)
     ok = ~ref.stats[:, 7].astype(bool)
     for col in (0, 2, 3, 6):  # pairs, expanded, out-range pops, visited data nodes
         assert np.array_equal(st[ok, col], ref.stats[ok, col]), col
 
 
 def test_budget_mode(tiny):
-    _budget_mode(tiny, 0)
+    _budget_mode(tiny, 1)
 
 
-@pytest.mark.parametrize("start_tier", [1, 2])
-def test_budget_mode_larger_tiers(tiny, start_tier):
+@pytest.mark.parametrize("start_tier", [0, 2])
+def test_budget_mode_other_tiers(tiny, start_tier):
     _budget_mode(tiny, start_tier)
 
 
@@ -271,8 +298,8 @@ def integer_case():
     return Case(w, eps)
 
 
-@pytest.mark.parametrize("precision,start_tier", [("fp32", 0), ("u8", 0), ("auto", 0),
-                                                  ("u8", 1), ("fp32", 1), ("u8", 2)])
+@pytest.mark.parametrize("precision,start_tier", [("fp32", 1), ("u8", 1), ("auto", 1),
+                                                  ("u8", 0), ("fp32", 0), ("u8", 2)])
 def test_integer_data_exact(integer_case, precision, start_tier):
     c = integer_case
     res = vj.vj_join(c.idx, c.eps, precision=precision, start_tier=start_tier)
