@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TIER_KERNELS = ("k_join_lds (one wave per query)", "k_join_coop (one workgroup per query)",
-                "k_join_spill (per-wave global tables)")
+                "k_join_coop_global (one workgroup per query, global tables)")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_join_mid_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_16360_amd", "csrc", f)
                   for f in ("join_impl.h", "join_inst.hip")]
