@@ -24,8 +24,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TIER_KERNELS = ("k_join_lds (one wave per query)", "k_join_coop (one workgroup per query)",
-                "k_join_coop_global (one workgroup per query, global tables)")
+TIER_KERNELS = ("k_join_lds (one wave per query)",
+                "k_join_coop (one workgroup per query; LDS, then global tables)",
+                "k_join_coop_global (re-run launch on global tables)")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_join_mid_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_16360_amd", "csrc", f)
                   for f in ("join_impl.h", "join_inst.hip")]
@@ -149,7 +150,9 @@ def main():
         recall = keys.numel() / max(1, n_gt)
         st = res.stats().cpu().numpy()
         fl = st[:, 7]
-        done_on = [(fl & 1) == 0, ((fl & 1) == 1) & ((fl & 8) == 0), (fl & 8) > 0]
+        # the launch that completed each query: one-wave tier, workgroup tier
+        # (LDS or, promoted within the launch, global tables), re-run launch
+        done_on = [(fl & 1) == 0, ((fl & 1) == 1) & ((fl & 16) == 0), (fl & 16) > 0]
         eb = 1 if variant == "u8" else 4
         per_tier = []
         for t in range(3):

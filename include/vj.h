@@ -149,8 +149,10 @@ void vj_index_free(vj_index *idx);
  * one wavefront with its visited set, worklist and pairs in LDS (1024-slot
  * visited set, 512 pairs, four waves per workgroup); a query that outgrows
  * them is re-run by a whole workgroup of four waves on 8192 LDS slots and
- * 1536 pairs, then on tables in global memory (2^16 slots and 32768 pairs,
- * then as large as the data set).  Calls on one
+ * 1536 pairs (the default first tier), then on tables in global memory
+ * (2^16 slots and 32768 pairs: within the same launch while the index's
+ * regions last, else in a re-run launch; then as large as the data set).
+ * Calls on one
  * index must not overlap (they share the index's per-query cache).
  * Limits: hybrid_beam <= 256.
  */
@@ -181,8 +183,8 @@ vj_status vj_pairs_export(const vj_pairs *r, int32_t *qx, float *dist, int sorte
 /* Per-query counters of a vj_join result, [n][8] int32 in the order of
  * query_ids: pairs, distance evaluations, expanded nodes, out-range pops,
  * predicted OOD, hybrid used, distinct data nodes visited, flags
- * (bit 0: re-run after outgrowing the one-wave LDS tier, bit 1: routed to
- * brute force, bit 3: re-run on global tables). */
+ * (bit 0: ran on the workgroup tier, bit 1: routed to brute force, bit 3:
+ * finished on global tables, bit 4: finished in a separate re-run launch). */
 vj_status vj_pairs_stats(const vj_pairs *r, int32_t *stats, void *stream);
 
 /* Device time of a vj_join result's traversal launches, measured with HIP

@@ -14,7 +14,8 @@
 // All per-query state lives in LDS: the visited hash, the in-range worklist
 // (which is also the query's pair buffer) and the out-range queue.  A query
 // that outgrows them is re-run on a larger tier: a whole workgroup with 8x
-// the LDS visited slots, then a whole workgroup with tables in global memory.
+// the LDS visited slots, then (in the same launch while free regions last) a
+// whole workgroup with tables in global memory.
 //
 // Rows are gathered LPR lanes per row, 16 bytes per lane per load (a row
 // group's load covers whole 128-byte lines), and reduced with xor shuffles
@@ -641,11 +642,14 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
     wave_sync();
 }
 
+// Runs slot k of the processing list on the tables of m.  Returns true
+// (in every thread) when the query outgrew them: nothing was written but
+// its stats row, and the caller re-runs it on larger tables.
 template <typename T, int DP, int W>
-__device__ __forceinline__ void run_query_coop(const JoinArgs &a, const WaveMem &m,
+__device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem &m,
                                                CoopShared<W> &sh, int heap_cap, int k,
                                                const int32_t *qlist, const int32_t *qpos,
-                                               int32_t *ovf, int32_t *ovf_count, int flags) {
+                                               int flags) {
     constexpr int CE = Elem<T>::CE;
     constexpr int CPR = DP / CE;
     constexpr int LPR = pick_lpr(CPR);
@@ -661,13 +665,13 @@ __device__ __forceinline__ void run_query_coop(const JoinArgs &a, const WaveMem 
     if (qi < 0 || qi >= a.nq) {
         if (threadIdx.x < 8) st[threadIdx.x] = 0;
         if (threadIdx.x == 0) atomicOr(a.err, 8);
-        return;
+        return false;
     }
     const int32_t q = (int32_t)(a.nx + qi);
     if (a.hyb == VJ_HYB_BUDGET && a.budget[pos] < 0) {
         if (threadIdx.x < 8) st[threadIdx.x] = threadIdx.x == 7 ? 2 : 0;
         if (threadIdx.x == 0 && a.ws != VJ_WS_SELF) a.cache[qi] = -1;
-        return;
+        return false;
     }
 
     float qf[QF];
@@ -880,9 +884,8 @@ __device__ __forceinline__ void run_query_coop(const JoinArgs &a, const WaveMem 
     __syncthreads();
     const int tail = min(lds_load(&sh.tail), m.il_cap);
     if (lds_load(&sh.abort)) {
-        if (threadIdx.x == 0) ovf[atomicAdd(ovf_count, 1)] = k;
         if (threadIdx.x < 8) st[threadIdx.x] = threadIdx.x == 7 ? 4 : 0;
-        return;
+        return true;
     }
 
     // ---- emit pairs
@@ -922,14 +925,37 @@ __device__ __forceinline__ void run_query_coop(const JoinArgs &a, const WaveMem 
         st[6] = lds_load(&sh.nvis);
         st[7] = flags;
     }
+    return false;
 }
 
-// cooperative tier: one query per workgroup of W waves, 2^HL visited slots,
-// LIST in-range entries
+// Global tables of one query: 2^hash_log2 visited slots and il_cap in-range
+// entries in region r of gh / gil / gild.
+struct GlobalTables {
+    int32_t *gh;
+    int32_t *gil;
+    float *gild;
+    int hash_log2, il_cap;
+    int32_t *next;  // slot counter of in-launch promotion
+    int cap;        // regions available to it
+};
+
+__device__ __forceinline__ void use_global(WaveMem &m, const GlobalTables &g, size_t r) {
+    m.hash = g.gh + (r << g.hash_log2);
+    m.hash_log2 = g.hash_log2;
+    m.hash_limit = (1 << g.hash_log2) / 2;
+    m.il = g.gil + r * (size_t)g.il_cap;
+    m.ild = g.gild + r * (size_t)g.il_cap;
+    m.il_cap = g.il_cap;
+}
+
+// cooperative tier: one query per workgroup of W waves, 2^HL visited slots
+// and LIST in-range entries in LDS.  A query that outgrows them takes a free
+// region of global tables (if any is left) and runs again in this launch;
+// otherwise, or if it outgrows those too, its slot goes to the overflow list.
 template <typename T, int DP, bool HYB, int HL, int LIST, int W>
 __global__ void __launch_bounds__(64 * W)
 k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos, int k0,
-            int k1, int32_t *ovf, int32_t *ovf_count) {
+            int k1, GlobalTables g, int32_t *ovf, int32_t *ovf_count) {
     constexpr int HC = HYB ? kBeamMax + 64 * W : 1;
     __shared__ int32_t sh_hash[1 << HL];
     __shared__ int32_t sh_il[LIST];
@@ -938,6 +964,7 @@ k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t
     __shared__ float sh_hk[HC];
     __shared__ int32_t sh_hi[HC];
     __shared__ CoopShared<W> sh;
+    __shared__ int sh_region;
     const int k = k0 + (int)blockIdx.x;
     if (k >= k1) return;
     const JoinArgs &a = *pa;
@@ -951,17 +978,24 @@ k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t
     m.stage = sh_stage[threadIdx.x >> 6];
     m.hk = sh_hk;
     m.hi = sh_hi;
-    run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, ovf, ovf_count, 1);
+    if (!run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, 1)) return;
+    if (threadIdx.x == 0) sh_region = g.cap > 0 ? atomicAdd(g.next, 1) : 0;
+    __syncthreads();
+    const int r = sh_region;
+    bool again = true;
+    if (r < g.cap) {
+        use_global(m, g, (size_t)r);
+        again = run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, 1 | 8);
+    }
+    if (again && threadIdx.x == 0) ovf[atomicAdd(ovf_count, 1)] = k;
 }
 
 // cooperative tier on global tables: one query per workgroup of W waves,
-// its visited set (2^hash_log2 slots) and in-range list (il_cap entries) in
-// the workgroup's region of gh / gil / gild (region = block - first block)
+// its tables in region (block index) of g; a re-run launch of the host
 template <typename T, int DP, bool HYB, int W>
 __global__ void __launch_bounds__(64 * W)
 k_join_coop_global(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos,
-                   int k0, int k1, int32_t *gh, int hash_log2, int32_t *gil, float *gild,
-                   int il_cap, int32_t *ovf, int32_t *ovf_count) {
+                   int k0, int k1, GlobalTables g, int32_t *ovf, int32_t *ovf_count) {
     constexpr int HC = HYB ? kBeamMax + 64 * W : 1;
     __shared__ int32_t sh_stage[W][64];
     __shared__ float sh_hk[HC];
@@ -970,18 +1004,13 @@ k_join_coop_global(const JoinArgs *__restrict__ pa, const int32_t *qlist, const 
     const int k = k0 + (int)blockIdx.x;
     if (k >= k1) return;
     const JoinArgs &a = *pa;
-    const size_t r = blockIdx.x;
     WaveMem m;
-    m.hash = gh + (r << hash_log2);
-    m.hash_log2 = hash_log2;
-    m.hash_limit = (1 << hash_log2) / 2;
-    m.il = gil + r * (size_t)il_cap;
-    m.ild = gild + r * (size_t)il_cap;
-    m.il_cap = il_cap;
+    use_global(m, g, blockIdx.x);
     m.stage = sh_stage[threadIdx.x >> 6];
     m.hk = sh_hk;
     m.hi = sh_hi;
-    run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, ovf, ovf_count, 1 | 8);
+    if (run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, 1 | 8 | 16) && threadIdx.x == 0)
+        ovf[atomicAdd(ovf_count, 1)] = k;
 }
 
 template <typename T, int DP, bool HYB>
@@ -992,14 +1021,23 @@ void launch_tier(const JoinLaunch &L, hipStream_t s) {
         hipLaunchKernelGGL((k_join_lds<T, DP, HYB, 10, 512, kWaves>), dim3(blocks),
                            dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, L.ovf,
                            L.ovf_count);
-    } else if (L.tier == 1) {
-        hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 13, 1536, kWaves>), dim3((unsigned)L.count),
-                           dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, L.ovf,
-                           L.ovf_count);
     } else {
-        hipLaunchKernelGGL((k_join_coop_global<T, DP, HYB, kWaves>), dim3((unsigned)L.count),
-                           dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, L.gh,
-                           L.hash_log2, L.gil, L.gild, L.il_cap, L.ovf, L.ovf_count);
+        GlobalTables g;
+        g.gh = L.gh;
+        g.gil = L.gil;
+        g.gild = L.gild;
+        g.hash_log2 = L.hash_log2;
+        g.il_cap = L.il_cap;
+        g.next = L.promo_next;
+        g.cap = L.promo_cap;
+        if (L.tier == 1)
+            hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 13, 1536, kWaves>), dim3((unsigned)L.count),
+                               dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, g, L.ovf,
+                               L.ovf_count);
+        else
+            hipLaunchKernelGGL((k_join_coop_global<T, DP, HYB, kWaves>), dim3((unsigned)L.count),
+                               dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, g, L.ovf,
+                               L.ovf_count);
     }
 }
 

@@ -244,7 +244,7 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
     make_order(ix, ids, n, ws, s, ord);
     const int32_t *qlist = ord.qlist.as<int32_t>(), *qpos = ord.qpos.as<int32_t>();
 
-    // counters: [0..1] out_count (u64), [2] ovf_count, [3] err
+    // counters: [0..1] out_count (u64), [2] ovf_count, [3] err, [4] global regions taken
     DevBuf counters(64), argsbuf(sizeof(JoinArgs)), ovf((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
     DevBuf out_q, out_x, out_d, gh, gil, gild, q2, p2, sl;
     r.stats.alloc((size_t)std::max<int64_t>(n, 1) * 8 * sizeof(int32_t));
@@ -323,12 +323,34 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
             L.ovf = ovf.as<int32_t>();
             L.ovf_count = ctr + 2;
             int64_t chunk = cnt;
-            if (tier >= 2) {
-                // tier 2: 2^16-slot visited sets (32,768 nodes) and 32,768
-                // pairs per query; tier 3: tables as large as the data set
-                L.hash_log2 = tier == 2 ? std::min(16, ceil_log2(2 * ix.nx)) : ceil_log2(2 * ix.nx);
-                L.il_cap = (int)(tier == 2 ? std::min<int64_t>(ix.nx, 1 << 15) : ix.nx);
-                chunk = tier == 2 ? 1024 : 16;
+            // global tables: 2^16 visited slots (32,768 nodes) and 32,768
+            // pairs per region (smaller for small data sets), kept in the
+            // index; tier 3 tables are as large as the data set
+            const int hl2 = std::min(16, ceil_log2(2 * ix.nx));
+            const int ilc2 = (int)std::min<int64_t>(ix.nx, 1 << 15);
+            auto global_regions = [&](int64_t regions) {
+                ix.ws_gh.reserve((size_t)regions * ((size_t)1 << hl2) * sizeof(int32_t));
+                ix.ws_gil.reserve((size_t)regions * ilc2 * sizeof(int32_t));
+                ix.ws_gild.reserve((size_t)regions * ilc2 * sizeof(float));
+                L.gh = ix.ws_gh.as<int32_t>();
+                L.gil = ix.ws_gil.as<int32_t>();
+                L.gild = ix.ws_gild.as<float>();
+                L.hash_log2 = hl2;
+                L.il_cap = ilc2;
+            };
+            if (tier == 1) {
+                // regions a query that outgrows LDS may take within the launch
+                L.promo_cap = (int)std::min<int64_t>(1024, std::max<int64_t>(64, cnt / 16));
+                global_regions(L.promo_cap);
+                L.promo_next = ctr + 4;
+                VJ_HIP(hipMemsetAsync(ctr + 4, 0, sizeof(int32_t), s));
+            } else if (tier == 2) {
+                chunk = 1024;
+                global_regions(std::min(chunk, cnt));
+            } else if (tier == 3) {
+                L.hash_log2 = ceil_log2(2 * ix.nx);
+                L.il_cap = (int)ix.nx;
+                chunk = 16;
                 gh.reserve((size_t)std::min(chunk, cnt) * ((size_t)1 << L.hash_log2) * sizeof(int32_t));
                 gil.reserve((size_t)std::min(chunk, cnt) * L.il_cap * sizeof(int32_t));
                 gild.reserve((size_t)std::min(chunk, cnt) * L.il_cap * sizeof(float));

@@ -86,6 +86,7 @@ struct Index {
     DevBuf inb;      // int32 [nq] generation stamp: query is part of the current call
     DevBuf seg;      // int64 [nq] offset of the query's pairs in the call's output
     DevBuf segn;     // int32 [nq] number of pairs of the query
+    DevBuf ws_gh, ws_gil, ws_gild;  // global tables of the join (kept between calls)
     int32_t gen = 0;
 };
 
@@ -139,11 +140,13 @@ struct JoinLaunch {
     int first, count, dp, prec;  // slots [first, first + count) of qlist
     int tier;                    // 0 one wave + LDS, 1 workgroup + LDS, 2 workgroup + global
     bool hyb;
-    int32_t *gh;              // tier 2: [count][1 << hash_log2] visited sets, by slot - first
+    int32_t *gh;              // global tables: [regions][1 << hash_log2] visited sets
     int hash_log2;
-    int32_t *gil;             // tier 2: [count][il_cap] in-range lists
+    int32_t *gil;             // [regions][il_cap] in-range lists
     float *gild;
     int il_cap;
+    int32_t *promo_next;      // tier 1: counter of the global regions taken in the launch
+    int promo_cap;            // tier 1: regions of gh / gil / gild it may take (0: none)
     int32_t *ovf, *ovf_count; // slots (indices into qlist) that must be re-run
 };
 

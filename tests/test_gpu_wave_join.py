@@ -158,9 +158,13 @@ def test_tier_overflow_one_wave_tier(tiny):
 def test_tier_overflow_to_global_tables(tiny):
     # at 2.6x eps (oracle: up to 4,449 pairs and 5,135 visited nodes; 301
     # queries hold > 1,536 pairs) queries outgrow the workgroup tier's LDS
-    # tables and re-run on global tables
+    # tables and re-run on global tables: 64 of them within the launch (the
+    # regions a 1,000-query call may take), the rest in a re-run launch
     st = _overflow_case(tiny, 2.6, 1)
-    assert 0 < ((st[:, 7] & 8) > 0).sum() < len(st)
+    on_global = (st[:, 7] & 8) > 0
+    rerun = (st[:, 7] & 16) > 0
+    assert 0 < on_global.sum() < len(st)
+    assert (on_global & ~rerun).sum() == 64 and rerun.sum() > 0
 
 
 def test_tier_overflow_chain(tiny):
