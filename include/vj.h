@@ -67,7 +67,10 @@ typedef enum {
 /* Arithmetic of the distance evaluations. */
 typedef enum {
     VJ_PREC_FP32 = 0, /* fp32 inputs, fp32 accumulation */
-    VJ_PREC_BF16 = 1, /* bf16 copy, fp32 accumulation, fp32 re-check near eps */
+    VJ_PREC_BF16 = 1, /* bf16 rows, fp32 query and accumulation; a candidate within the
+                         proven error margin of eps is re-decided from the fp32 rows in the
+                         fp32 kernels' arithmetic, so in/out decisions equal VJ_PREC_FP32's
+                         (join: workgroup tiers only) */
     VJ_PREC_FP8 = 2,  /* e4m3 copy (per-row scale), fp32 re-check near eps */
     VJ_PREC_U8 = 3,   /* exact u8 copy (integer data in [0, 255] only) */
     VJ_PREC_AUTO = 4  /* u8 if the index data is exactly u8, else fp32 */
@@ -193,6 +196,12 @@ vj_status vj_pairs_stats(const vj_pairs *r, int32_t *stats, void *stream);
  * that tier, n_spilled the number of such queries.  Any pointer may be NULL. */
 vj_status vj_pairs_timing(const vj_pairs *r, float *kernel_ms, float *spill_ms,
                           int64_t *n_spilled);
+
+/* Candidates whose low-precision value fell inside the proven error margin
+ * of eps and were re-decided at full precision: from the fp32 rows, in the
+ * fp32 kernels' arithmetic (vj_join with VJ_PREC_BF16), or in fp64
+ * (vj_bruteforce_join). */
+vj_status vj_pairs_rechecked(const vj_pairs *r, int64_t *n);
 
 /* Per-tier breakdown of a vj_join result's traversal, for the storage tiers
  * 0 (one wave per query, LDS), 1 (one workgroup per query, LDS), 2 (one

@@ -23,6 +23,8 @@
 // memory are range-checked before they index anything.
 #pragma once
 
+#include <type_traits>
+
 #include "vj_internal.h"
 
 namespace vj {
@@ -38,6 +40,10 @@ constexpr int kHeap = kBeamMax + 64;
 template <typename T> struct Elem;
 template <> struct Elem<float> { static constexpr int CE = 4; };
 template <> struct Elem<uint8_t> { static constexpr int CE = 16; };
+template <> struct Elem<uint16_t> { static constexpr int CE = 8; };  // bf16 bits
+
+// bf16 rows carry a rounding error that the kernels bound and re-check
+template <typename T> constexpr bool kIsBf16 = std::is_same<T, uint16_t>::value;
 
 // lanes per row: a power of two with at most 8 16-byte chunks per lane
 constexpr int pick_lpr(int cpr) {
@@ -62,6 +68,15 @@ __device__ __forceinline__ void to_float(const uint4 &r, float *f, uint8_t) {
         f[4 * i + 1] = (float)((w[i] >> 8) & 0xffu);
         f[4 * i + 2] = (float)((w[i] >> 16) & 0xffu);
         f[4 * i + 3] = (float)(w[i] >> 24);
+    }
+}
+
+__device__ __forceinline__ void to_float(const uint4 &r, float *f, uint16_t) {
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f[2 * i + 0] = __uint_as_float(w[i] << 16);
+        f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
     }
 }
 
@@ -110,6 +125,8 @@ struct WaveMem {
     int32_t *stage;  // 64 candidate ids (LDS)
     float *hk;       // out-range queue keys (LDS)
     int32_t *hi;     // out-range queue ids
+    int32_t *aux;    // 64 ids re-checked from fp32 rows (LDS, bf16 rows only)
+    float *auxf;     // their fp32 values
 };
 
 // Insert each active lane's id; returns true where the id was new.  A lane
@@ -154,6 +171,55 @@ __device__ __forceinline__ float row_partial(const uint4 *buf, const float *qf, 
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     return acc;
+}
+
+// as row_partial, plus the squared norm of the row (xn2)
+template <int LPR, int VPL, int CE, typename T>
+__device__ __forceinline__ float row_partial_n(const uint4 *buf, const float *qf, bool l2,
+                                               float &xn2) {
+    float acc = 0.f, nn = 0.f;
+#pragma unroll
+    for (int w = 0; w < VPL; ++w) {
+        float f[CE];
+        to_float(buf[w], f, T());
+#pragma unroll
+        for (int e = 0; e < CE; ++e) {
+            if (l2) { const float t = f[e] - qf[w * CE + e]; acc = fmaf(t, t, acc); }
+            else acc = fmaf(f[e], qf[w * CE + e], acc);
+            nn = fmaf(f[e], f[e], nn);
+        }
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+        acc += __shfl_xor(acc, off);
+        nn += __shfl_xor(nn, off);
+    }
+    xn2 = nn;
+    return acc;
+}
+
+// The fp32 kernels' value of candidate `id` (L2: squared distance, IP: dot
+// product), from the fp32 rows with exactly their lane layout and order of
+// operations, so that a decision taken on it is the fp32 kernels' decision.
+// Each group of pick_lpr(DP / 4) lanes evaluates its own id.
+template <int DP>
+__device__ __forceinline__ float fp32_value(const JoinArgs &a, int32_t q, int32_t id, bool l2,
+                                            int lane) {
+    constexpr int CPR = DP / 4;
+    constexpr int LPR = pick_lpr(CPR);
+    constexpr int VPL = CPR / LPR;
+    const int p = lane % LPR;
+    const uint4 *xrow = reinterpret_cast<const uint4 *>(a.rows32 + (size_t)id * DP);
+    const float4 *qrow = reinterpret_cast<const float4 *>(a.rows32 + (size_t)q * DP);
+    uint4 buf[VPL];
+    float qf[VPL * 4];
+#pragma unroll
+    for (int w = 0; w < VPL; ++w) {
+        buf[w] = xrow[p + w * LPR];
+        const float4 t = qrow[p + w * LPR];
+        qf[4 * w + 0] = t.x; qf[4 * w + 1] = t.y; qf[4 * w + 2] = t.z; qf[4 * w + 3] = t.w;
+    }
+    return row_partial<LPR, VPL, 4, float>(buf, qf, l2);
 }
 
 // drop the largest (key, id) entries until the queue holds `beam`
@@ -528,6 +594,8 @@ struct CoopWave {
     int best_id;
     float d1sum;
     int c1;
+    int32_t q;   // the query's node id
+    float qn;    // |q| (bf16 margin of the inner product)
 };
 
 __device__ __forceinline__ int lds_load(const int *p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
@@ -546,7 +614,8 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
     constexpr int LPR = pick_lpr(CPR);
     constexpr int VPL = CPR / LPR;
     constexpr int RPP = 64 / LPR;
-    constexpr int PG = (16 / VPL) < (64 / RPP) ? (16 / VPL) : (64 / RPP);
+    constexpr int LCAP = kIsBf16<T> ? 8 : 16;  // bf16: registers for the re-check path
+    constexpr int PG = (LCAP / VPL) < (64 / RPP) ? (LCAP / VPL) : (64 / RPP);
     const bool l2 = a.metric == VJ_L2;
     const int p = lane % LPR, rr = lane / LPR;
     const uint64_t ltmask = (1ull << lane) - 1ull;
@@ -586,17 +655,90 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
             for (int w = 0; w < VPL; ++w)
                 buf[g][w] = c < cnt ? row[p + w * LPR] : make_uint4(0, 0, 0, 0);
         }
+        float keyv[PG];
+        bool inrv[PG], uncv[PG];
+        uint64_t unc_any = 0;
 #pragma unroll
         for (int g = 0; g < PG; ++g) {
-            const float acc = row_partial<LPR, VPL, CE, T>(buf[g], qf, l2);
+            const int c = base + g * RPP + rr;
+            const bool lead = p == 0 && c < cnt;
+            float acc;
+            uncv[g] = false;
+            if constexpr (kIsBf16<T>) {
+                // |q - x~| differs from |q - x| by at most |x - x~| <= bf_u |x~|
+                // (triangle inequality; q is exact); GB bounds the relative
+                // error of the fp32 sums here and in the fp32 kernels
+                constexpr float GB = (float)(2 * (VPL * CE + 5 + 16)) * 5.9604645e-8f;
+                float xn2;
+                acc = row_partial_n<LPR, VPL, CE, T>(buf[g], qf, l2, xn2);
+                const float xn = sqrtf(xn2) * (1.f + GB);
+                bool sure;
+                if (l2) {
+                    const float dt = sqrtf(acc);
+                    const float ex = a.bf_u * xn;
+                    const float hi = (dt * (1.f + GB) + ex) * (1.f + GB);
+                    const float lo = fmaxf(0.f, dt * (1.f - GB) - ex) * (1.f - GB);
+                    sure = hi * hi * (1.f + GB) < a.eps2 || lo * lo * (1.f - GB) >= a.eps2;
+                } else {
+                    const float mrg = cw.qn * xn * (a.bf_u + 2.f * GB * (1.f + a.bf_u)) +
+                                      GB * (1.f + fabsf(acc));
+                    const float key = 1.0f - acc;
+                    sure = key + mrg < a.eps || key - mrg >= a.eps;
+                }
+                uncv[g] = lead && !sure;
+                unc_any |= __ballot(uncv[g]);
+            } else {
+                acc = row_partial<LPR, VPL, CE, T>(buf[g], qf, l2);
+            }
+            keyv[g] = l2 ? acc : 1.0f - acc;
+            inrv[g] = l2 ? (acc < a.eps2) : (keyv[g] < a.eps);
+        }
+        if constexpr (kIsBf16<T>) {
+            if (unc_any) {
+                // re-decide the candidates inside the margin from the fp32 rows
+                int nu = 0, pos[PG];
+#pragma unroll
+                for (int g = 0; g < PG; ++g) {
+                    const uint64_t mg = __ballot(uncv[g]);
+                    pos[g] = nu + __popcll(mg & ltmask);
+                    if (uncv[g]) {
+                        const int e = sid[g] >= 0 ? sid[g] : ~sid[g];
+                        m.aux[pos[g]] = e & ((1 << 30) - 1);
+                    }
+                    nu += __popcll(mg);
+                }
+                wave_sync();
+                constexpr int RPP32 = 64 / pick_lpr(DP / 4);
+                constexpr int LPR32 = pick_lpr(DP / 4);
+                for (int u0 = 0; u0 < nu; u0 += RPP32) {
+                    const int ui = u0 + lane / LPR32;
+                    const int32_t uid = ui < nu ? m.aux[ui] : 0;
+                    const float v32 = fp32_value<DP>(a, cw.q, uid, l2, lane);
+                    if (lane % LPR32 == 0 && ui < nu) m.auxf[ui] = v32;
+                }
+                wave_sync();
+#pragma unroll
+                for (int g = 0; g < PG; ++g) {
+                    if (uncv[g]) {
+                        const float v32 = m.auxf[pos[g]];
+                        keyv[g] = l2 ? v32 : 1.0f - v32;
+                        inrv[g] = l2 ? (v32 < a.eps2) : (keyv[g] < a.eps);
+                    }
+                }
+                if (lane == 0) atomicAdd(a.nrecheck, (unsigned long long)nu);
+                wave_sync();
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < PG; ++g) {
             const int c = base + g * RPP + rr;
             const bool lead = p == 0 && c < cnt;
             const bool nw = sid[g] >= 0;
             const int e = nw ? sid[g] : ~sid[g];
             const bool pl = (e >> 30) & 1;
             const int id = e & ((1 << 30) - 1);
-            const float key = l2 ? acc : 1.0f - acc;
-            const bool inr = l2 ? (acc < a.eps2) : (key < a.eps);
+            const float key = keyv[g];
+            const bool inr = inrv[g];
             if (lead && nw && (key < cw.best_k || (key == cw.best_k && id < cw.best_id))) {
                 cw.best_k = key;
                 cw.best_id = id;
@@ -699,6 +841,15 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
     CoopWave cw{};
     cw.best_k = INFINITY;
     cw.best_id = 0x7fffffff;
+    cw.q = q;
+    {
+        float qn2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < QF; ++i) qn2 = fmaf(qf[i], qf[i], qn2);
+#pragma unroll
+        for (int off = LPR / 2; off > 0; off >>= 1) qn2 += __shfl_xor(qn2, off);
+        cw.qn = sqrtf(qn2) * (1.f + 1e-6f);
+    }
 
     // ---- SeedPhase: wave 0 the entry and the soft cache, all waves the
     // parent's in-range list (hard), in chunks of 64
@@ -965,6 +1116,8 @@ k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t
     __shared__ int32_t sh_hi[HC];
     __shared__ CoopShared<W> sh;
     __shared__ int sh_region;
+    __shared__ int32_t sh_aux[kIsBf16<T> ? W : 1][64];
+    __shared__ float sh_auxf[kIsBf16<T> ? W : 1][64];
     const int k = k0 + (int)blockIdx.x;
     if (k >= k1) return;
     const JoinArgs &a = *pa;
@@ -978,6 +1131,8 @@ k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t
     m.stage = sh_stage[threadIdx.x >> 6];
     m.hk = sh_hk;
     m.hi = sh_hi;
+    m.aux = sh_aux[kIsBf16<T> ? threadIdx.x >> 6 : 0];
+    m.auxf = sh_auxf[kIsBf16<T> ? threadIdx.x >> 6 : 0];
     if (!run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, 1)) return;
     if (threadIdx.x == 0) sh_region = g.cap > 0 ? atomicAdd(g.next, 1) : 0;
     __syncthreads();
@@ -1001,6 +1156,8 @@ k_join_coop_global(const JoinArgs *__restrict__ pa, const int32_t *qlist, const 
     __shared__ float sh_hk[HC];
     __shared__ int32_t sh_hi[HC];
     __shared__ CoopShared<W> sh;
+    __shared__ int32_t sh_aux[kIsBf16<T> ? W : 1][64];
+    __shared__ float sh_auxf[kIsBf16<T> ? W : 1][64];
     const int k = k0 + (int)blockIdx.x;
     if (k >= k1) return;
     const JoinArgs &a = *pa;
@@ -1009,6 +1166,8 @@ k_join_coop_global(const JoinArgs *__restrict__ pa, const int32_t *qlist, const 
     m.stage = sh_stage[threadIdx.x >> 6];
     m.hk = sh_hk;
     m.hi = sh_hi;
+    m.aux = sh_aux[kIsBf16<T> ? threadIdx.x >> 6 : 0];
+    m.auxf = sh_auxf[kIsBf16<T> ? threadIdx.x >> 6 : 0];
     if (run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, 1 | 8 | 16) && threadIdx.x == 0)
         ovf[atomicAdd(ovf_count, 1)] = k;
 }
@@ -1017,10 +1176,13 @@ template <typename T, int DP, bool HYB>
 void launch_tier(const JoinLaunch &L, hipStream_t s) {
     const int k0 = L.first, k1 = L.first + L.count;
     if (L.tier == 0) {
-        const unsigned blocks = (unsigned)((L.count + kWaves - 1) / kWaves);
-        hipLaunchKernelGGL((k_join_lds<T, DP, HYB, 10, 512, kWaves>), dim3(blocks),
-                           dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, L.ovf,
-                           L.ovf_count);
+        // the one-wave tier reads fp32 or exact u8 rows only
+        if constexpr (!kIsBf16<T>) {
+            const unsigned blocks = (unsigned)((L.count + kWaves - 1) / kWaves);
+            hipLaunchKernelGGL((k_join_lds<T, DP, HYB, 10, 512, kWaves>), dim3(blocks),
+                               dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, L.ovf,
+                               L.ovf_count);
+        }
     } else {
         GlobalTables g;
         g.gh = L.gh;

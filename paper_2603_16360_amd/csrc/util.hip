@@ -32,13 +32,23 @@ __global__ void k_quantize(const float *vec, int64_t n, uint8_t *u8, uint16_t *b
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float f = vec[i];
+    bool bad_u8 = false, bad_bf = false;
     if (u8) {
         const float r = rintf(f);
         const bool ok = r == f && f >= 0.0f && f <= 255.0f;
-        if (!ok) atomicOr(flag, 1);
+        bad_u8 = !ok;
         u8[i] = ok ? (uint8_t)r : 0;
     }
-    if (bf) bf[i] = to_bf16(f);
+    if (bf) {
+        const uint16_t h = to_bf16(f);
+        bf[i] = h;
+        bad_bf = __uint_as_float((uint32_t)h << 16) != f;
+    }
+    // flag bit 0: a value is not an integer in [0, 255]; bit 1: a value is
+    // not exact in bf16 (one atomic per wave)
+    const int bits = (__ballot(bad_u8) ? 1 : 0) | (__ballot(bad_bf) ? 2 : 0);
+    if (flag && bits && (threadIdx.x & 63) == __builtin_amdgcn_readfirstlane(threadIdx.x & 63))
+        atomicOr(flag, bits);
 }
 
 // one 64-thread block per node; thread j handles edge j (R <= 64)

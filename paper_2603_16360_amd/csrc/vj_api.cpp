@@ -52,7 +52,7 @@ static void init_vectors(Index &ix, const float *Q, const float *X, hipStream_t 
     int32_t h = 0;
     VJ_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     VJ_HIP(hipStreamSynchronize(s));
-    ix.integer_u8 = (h == 0);
+    ix.integer_u8 = (h & 1) == 0;
     if (!ix.integer_u8) ix.vec_u8.release();
     const size_t nq = (size_t)std::max<int64_t>(ix.nq, 1);
     ix.cache.alloc(nq * sizeof(int32_t));
@@ -68,8 +68,14 @@ static void init_vectors(Index &ix, const float *Q, const float *X, hipStream_t 
 void ensure_bf16(Index &ix, hipStream_t s) {
     if (ix.vec_bf16.p) return;
     ix.vec_bf16.alloc((size_t)ix.N * ix.dp * sizeof(uint16_t));
+    DevBuf flag(sizeof(int32_t));
+    VJ_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
     launch_quantize(ix.vec.as<float>(), ix.N, ix.dp, nullptr, ix.vec_bf16.as<uint16_t>(),
-                    nullptr, s);
+                    flag.as<int32_t>(), s);
+    int32_t h = 0;
+    VJ_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    ix.bf16_exact = (h & 2) == 0;
 }
 
 // MST over the query nodes plus (s, q) edges, rooted at s (Section 3.2);
@@ -235,8 +241,11 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
     if (prec == VJ_PREC_AUTO) prec = ix.integer_u8 ? VJ_PREC_U8 : VJ_PREC_FP32;
     VJ_CHECK(prec != VJ_PREC_U8 || ix.integer_u8, VJ_ERR_INVALID_ARG,
              "u8 precision needs integer data in [0, 255]");
-    VJ_CHECK(prec == VJ_PREC_FP32 || prec == VJ_PREC_U8, VJ_ERR_UNSUPPORTED,
-             "precision not supported by the traversal");
+    VJ_CHECK(prec == VJ_PREC_FP32 || prec == VJ_PREC_U8 || prec == VJ_PREC_BF16,
+             VJ_ERR_UNSUPPORTED, "precision not supported by the traversal");
+    if (prec == VJ_PREC_BF16) ensure_bf16(ix, s);
+    // bf16 rows run on the workgroup tiers (they carry the margin re-check)
+    const int start_tier = prec == VJ_PREC_BF16 ? std::max(1, (int)p.start_tier) : (int)p.start_tier;
     const int beam = (hyb != VJ_HYB_OFF) ? p.hybrid_beam : 0;
     VJ_CHECK(beam <= 256, VJ_ERR_UNSUPPORTED, "hybrid_beam must be <= 256");
 
@@ -244,7 +253,8 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
     make_order(ix, ids, n, ws, s, ord);
     const int32_t *qlist = ord.qlist.as<int32_t>(), *qpos = ord.qpos.as<int32_t>();
 
-    // counters: [0..1] out_count (u64), [2] ovf_count, [3] err, [4] global regions taken
+    // counters: [0..1] out_count (u64), [2] ovf_count, [3] err, [4] global regions taken,
+    // [6..7] bf16 re-checks (u64)
     DevBuf counters(64), argsbuf(sizeof(JoinArgs)), ovf((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
     DevBuf out_q, out_x, out_d, gh, gil, gild, q2, p2, sl;
     r.stats.alloc((size_t)std::max<int64_t>(n, 1) * 8 * sizeof(int32_t));
@@ -275,7 +285,10 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
         if (ws != VJ_WS_SELF) stamp_batch(ix.inb.as<int32_t>(), ix.nq, ids, n, ix.gen, ctr + 3, s);
 
         JoinArgs a{};
-        a.rows = prec == VJ_PREC_U8 ? ix.vec_u8.p : ix.vec.p;
+        a.rows = prec == VJ_PREC_U8 ? ix.vec_u8.p : prec == VJ_PREC_BF16 ? ix.vec_bf16.p : ix.vec.p;
+        // RNE to bf16 has relative error <= 2^-8 of |x|, i.e. <= 2^-8 / (1 - 2^-8) of |bf16(x)|
+        a.bf_u = prec == VJ_PREC_BF16 && !ix.bf16_exact ? 0.00392157f : 0.f;
+        a.nrecheck = reinterpret_cast<unsigned long long *>(ctr + 6);
         a.rows32 = ix.vec.as<float>();
         a.adj = ix.adj.as<int32_t>();
         a.elen = ix.elen.as<float>();
@@ -382,18 +395,18 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
             const int64_t first = ord.level_start[lv];
             int64_t pending = ord.level_start[lv + 1] - first;
             const int32_t *lq = qlist + first, *lp = qpos + first;
-            for (int tier = p.start_tier; pending > 0; ++tier) {
+            for (int tier = start_tier; pending > 0; ++tier) {
                 VJ_CHECK(tier <= 3, VJ_ERR_INTERNAL, "join tiers exhausted");
                 VJ_HIP(hipMemsetAsync(ctr + 2, 0, sizeof(int32_t), s));
                 const float ms = run_tier(tier, lq, lp, pending);
-                if (tier == p.start_tier) r.kernel_ms += ms;
+                if (tier == start_tier) r.kernel_ms += ms;
                 else r.spill_ms += ms;
                 VJ_HIP(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s));
                 VJ_HIP(hipStreamSynchronize(s));
                 VJ_CHECK(!(hctr[3] & 8), VJ_ERR_INVALID_ARG, "query id out of range");
                 pending = hctr[2];
                 if (pending == 0) break;
-                r.n_spilled += tier == p.start_tier ? pending : 0;
+                r.n_spilled += tier == start_tier ? pending : 0;
                 std::vector<int32_t> slots_h((size_t)pending);
                 VJ_HIP(hipMemcpyAsync(slots_h.data(), ovf.p, pending * sizeof(int32_t), hipMemcpyDeviceToHost, s));
                 VJ_HIP(hipStreamSynchronize(s));
@@ -413,6 +426,10 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
         }
         const int64_t total = (int64_t)(((uint64_t)(uint32_t)hctr[1] << 32) | (uint32_t)hctr[0]);
         if (total <= cap) {
+            unsigned long long nre = 0;
+            VJ_HIP(hipMemcpyAsync(&nre, ctr + 6, sizeof(nre), hipMemcpyDeviceToHost, s));
+            VJ_HIP(hipStreamSynchronize(s));
+            r.n_candidates = (int64_t)nre;
             r.count = total;
             r.n_queries = n;
             r.q = std::move(out_q);
@@ -656,6 +673,13 @@ vj_status vj_pairs_timing(const vj_pairs *r, float *kernel_ms, float *spill_ms,
     API_END
 }
 
+vj_status vj_pairs_rechecked(const vj_pairs *r, int64_t *n) {
+    API_BEGIN
+    VJ_CHECK(r != nullptr && n != nullptr, VJ_ERR_INVALID_ARG, "null argument");
+    *n = r->impl.n_candidates;
+    API_END
+}
+
 vj_status vj_pairs_tiers(const vj_pairs *r, float *ms, int32_t *launches, int64_t *queries) {
     API_BEGIN
     VJ_CHECK(r != nullptr, VJ_ERR_INVALID_ARG, "null result");
@@ -676,6 +700,7 @@ bool launch_join(const JoinLaunch &L, hipStream_t s) {
     switch (L.prec) {
     case VJ_PREC_FP32: return launch_join_f32(L, s);
     case VJ_PREC_U8: return launch_join_u8(L, s);
+    case VJ_PREC_BF16: return launch_join_bf16(L, s);
     default: return false;
     }
 }

@@ -72,6 +72,7 @@ struct Index {
     vj_metric metric = VJ_L2;
     int device = 0;
     bool integer_u8 = false;  // every value an integer in [0, 255]
+    bool bf16_exact = false;  // every value exact in bf16 (valid once vec_bf16 exists)
     DevBuf vec;      // float [N][dp], zero padded
     DevBuf vec_u8;   // uint8 [N][dp] (integer_u8 only)
     DevBuf vec_bf16; // bf16 [N][dp] (optional)
@@ -115,6 +116,8 @@ struct JoinArgs {
     int64_t nx, nq;
     int32_t R, dp, entry, metric;
     float eps, eps2;          // L2 compares the squared distance with eps2
+    float bf_u;               // bf16 rows: bound on |x - bf16(x)| / |bf16(x)| (0: exact copy)
+    unsigned long long *nrecheck;  // bf16 rows: candidates re-decided from fp32 rows
     int32_t ws, hyb, beam, conv;
     float ood_ratio;
     int32_t gen;              // stamp of this call in inb[]
@@ -153,6 +156,7 @@ struct JoinLaunch {
 bool launch_join(const JoinLaunch &L, hipStream_t s);
 bool launch_join_f32(const JoinLaunch &L, hipStream_t s);
 bool launch_join_u8(const JoinLaunch &L, hipStream_t s);
+bool launch_join_bf16(const JoinLaunch &L, hipStream_t s);
 int num_cus();
 
 // edge lengths of every adjacency entry (L2)

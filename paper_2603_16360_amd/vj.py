@@ -71,6 +71,7 @@ _SIGS = {
     "vj_pairs_stats": (C.c_int, [_vp, _vp, _vp]),
     "vj_pairs_timing": (C.c_int, [_vp, _vp, _vp, _vp]),
     "vj_pairs_tiers": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "vj_pairs_rechecked": (C.c_int, [_vp, _vp]),
     "vj_pairs_free": (None, [_vp]),
     "vj_last_error": (C.c_char_p, []),
 }
@@ -133,6 +134,12 @@ class Pairs:
         k, sp, ns = C.c_float(), C.c_float(), C.c_int64()
         _check(_lib.vj_pairs_timing(self._h, C.byref(k), C.byref(sp), C.byref(ns)))
         return {"kernel_ms": k.value, "spill_ms": sp.value, "n_spilled": ns.value}
+
+    def rechecked(self) -> int:
+        """Candidates re-decided at full precision (see vj_pairs_rechecked)."""
+        n = C.c_int64()
+        _check(_lib.vj_pairs_rechecked(self._h, C.byref(n)))
+        return n.value
 
     def tiers(self) -> list:
         """Per storage tier 0..3: device ms, launches, queries launched."""
