@@ -86,6 +86,9 @@ def _declare(L):
     L.or_join_self_counts.restype = None
     L.or_join_self_counts.argtypes = [_f32p, _i64, _i64, _int, _int, _i32p, _int,
                                       C.c_int32, _i32p, _i64, _dbl, _i64p]
+    L.or_features.restype = None
+    L.or_features.argtypes = [_f32p, _i64, _i64, _int, _int, _i32p, _int, C.c_int32, _i32p,
+                              _i64, _dbl, _f64p]
     L.or_mlp_forward.restype = None
     L.or_mlp_forward.argtypes = [_int] * 5 + [_f64p] * 7 + [_f64p]
     L.or_mlp_bce_backward.restype = _dbl
@@ -296,6 +299,22 @@ def join_self_counts(Q, X, adj, entry: int, eps: float, metric: str = "l2",
 # ---------------------------------------------------------------------------
 # O5: the difficulty MLP in fp64
 # ---------------------------------------------------------------------------
+
+FEATURE_NAMES = ("eps", "dist_s", "min_dist_A", "d1", "d2", "d1_over_d2", "frac_A",
+                 "frac_A_in_range")
+
+
+def features(Q, X, adj, entry: int, eps: float, metric: str = "l2", query_ids=None):
+    """[n][d + 8]: each query's vector and the 8 post-probe features
+    (FEATURE_NAMES; see or_features)."""
+    V = np.ascontiguousarray(np.concatenate([_f32(X), _f32(Q)], axis=0))
+    nq, nx, d = Q.shape[0], X.shape[0], Q.shape[1]
+    adj = np.ascontiguousarray(adj, np.int32)
+    qids = np.arange(nq, dtype=np.int32) if query_ids is None else np.ascontiguousarray(query_ids, np.int32)
+    out = np.empty((qids.shape[0], d + 8), np.float64)
+    lib().or_features(V, nx, nq, d, METRICS[metric], adj, adj.shape[1], entry, qids,
+                      qids.shape[0], eps, out)
+    return out
 
 def mlp_forward(params, Xin):
     W1, b1, W2, b2, W3, b3 = [np.ascontiguousarray(p, np.float64) for p in params]

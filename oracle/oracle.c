@@ -13,7 +13,8 @@
  *   - Section 3.2 (work sharing, MST): or_mst_parents
  *   - Algorithms 1-8:                  or_join
  *   - difficulty MLP (not in the paper; fp64 reference):
- *                                      or_mlp_forward, or_mlp_bce_backward
+ *                                      or_features, or_mlp_forward,
+ *                                      or_mlp_bce_backward
  *
  * Readings of points the paper leaves open are marked "reading:".
  */
@@ -826,6 +827,65 @@ void or_join_self_counts(const float *V, int64_t nx, int64_t nq, int d, int metr
             counts[i] = nw;
         }
         free(stamp); free(W);
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * O5 input: per-query features known once the probe of Algorithm 4 is done
+ * (q, its neighbour list N(q), the entry s, eps), extending the d1/d2 signal
+ * of CheckHybrid (Section 4.4).  With A = N(q) restricted to data nodes:
+ *   f0 = eps
+ *   f1 = dist(q, s)
+ *   f2 = min over A of dist(q, y)                       (0 if A is empty)
+ *   f3 = d1 = mean over A of the L2 length |q - y|      (0 if A is empty)
+ *   f4 = d2 = mean L2 edge length |y - z| over y in A, z in N(y), z a data
+ *        node other than q                              (0 if none)
+ *   f5 = d1 / d2                                        (0 if d2 is 0)
+ *   f6 = |A| / R
+ *   f7 = |{y in A : dist(q, y) < eps}| / R
+ * dist is the join metric (L2, or 1 - <q, y> for IP); d1 and d2 are in L2
+ * units as in the OOD test (reading: for IP, |q - y| = sqrt(2 (1 - <q, y>))
+ * on unit vectors, computed here from the vectors directly).  Output row i:
+ * the query vector (d values) followed by f0..f7.
+ * ---------------------------------------------------------------------- */
+void or_features(const float *V, int64_t nx, int64_t nq, int d, int metric,
+                 const int32_t *adj, int R, int32_t entry, const int32_t *qidx,
+                 int64_t n, double eps, double *out)
+{
+    (void)nq;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t q = nx + qidx[i];
+        const float *qv = V + q * d;
+        double *o = out + i * (int64_t)(d + 8);
+        for (int k = 0; k < d; ++k) o[k] = (double)qv[k];
+        double f1 = dist64(qv, V + (int64_t)entry * d, d, metric);
+        double mn = 0.0, s1 = 0.0, s2 = 0.0;
+        int64_t na = 0, nin = 0, c2 = 0;
+        for (int j = 0; j < R; ++j) {
+            int32_t y = adj[q * R + j];
+            if (y < 0 || y >= nx) continue;
+            double dy = dist64(qv, V + (int64_t)y * d, d, metric);
+            if (na == 0 || dy < mn) mn = dy;
+            if (dy < eps) ++nin;
+            s1 += l2_64(qv, V + (int64_t)y * d, d);
+            ++na;
+            for (int k = 0; k < R; ++k) {
+                int32_t z = adj[(int64_t)y * R + k];
+                if (z < 0 || z >= nx || z == q) continue;
+                s2 += l2_64(V + (int64_t)y * d, V + (int64_t)z * d, d);
+                ++c2;
+            }
+        }
+        double d1 = na ? s1 / (double)na : 0.0;
+        double d2 = c2 ? s2 / (double)c2 : 0.0;
+        o[d + 0] = eps;
+        o[d + 1] = f1;
+        o[d + 2] = na ? mn : 0.0;
+        o[d + 3] = d1;
+        o[d + 4] = d2;
+        o[d + 5] = d2 > 0.0 ? d1 / d2 : 0.0;
+        o[d + 6] = (double)na / (double)R;
+        o[d + 7] = (double)nin / (double)R;
     }
 }
 

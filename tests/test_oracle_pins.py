@@ -293,6 +293,26 @@ def test_worked_examples(ex):
     if "parent" in ex:
         par, order, _ = oracle.mst_parents(Q, X, adj, ex["entry"])
         assert par.tolist() == ex["parent"]
+    if "features" in ex:
+        f = oracle.features(Q, X, adj, ex["entry"], ex["eps"])
+        assert np.allclose(f[0, :Q.shape[1]], Q[0])
+        np.testing.assert_allclose(f[0, Q.shape[1]:], ex["features"]["expect"], rtol=1e-6, atol=1e-12)
+
+
+def test_features_ip_single_neighbour_closed_form():
+    # unit vectors, one data neighbour y: for IP the feature distances are
+    # 1 - <q, y>, while d1 is the L2 length |q - y| = sqrt(2 (1 - <q, y>))
+    ang = np.array([0.0, 0.3, 1.2, 2.0])
+    X = np.stack([np.cos(ang), np.sin(ang)], 1).astype(np.float32)  # data 0..3
+    Q = np.array([[1.0, 0.0]], np.float32)                          # node 4
+    adj = np.array([[1, -1], [0, -1], [1, -1], [2, -1], [1, -1]], np.int32)
+    f = oracle.features(Q, X, adj, 3, 0.5, metric="ip")[0, 2:]
+    ip = float(np.cos(0.3))
+    assert f[1] == pytest.approx(1 - np.cos(2.0), rel=1e-6)        # dist(q, s), s = 3
+    assert f[2] == pytest.approx(1 - ip, rel=1e-5)                  # min over A = {1}
+    assert f[3] == pytest.approx(np.sqrt(2 * (1 - ip)), rel=1e-5)   # d1 in L2 units
+    assert f[4] == pytest.approx(np.sqrt(2 * (1 - ip)), rel=1e-5)   # d2: N(1) = {0}, |x1 - x0|
+    assert f[6] == 0.5 and f[7] == 0.5                              # |A| / R, in range / R
 
 
 @pytest.fixture(scope="module")
