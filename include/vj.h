@@ -61,7 +61,8 @@ typedef enum {
     VJ_HYB_FORCE = 1,  /* hybrid search for every query */
     VJ_HYB_ADAPT = 2,  /* hybrid only for queries predicted OOD (d1/d2 > ratio) */
     VJ_HYB_BUDGET = 3, /* hybrid with a per-query cap on out-range pops (budget[]) */
-    VJ_HYB_LEARNED = 4 /* budgets chosen by the index's attached predictor */
+    VJ_HYB_LEARNED = 4 /* budgets chosen by the index's attached predictor; queries no
+                          budget satisfies are joined exactly on MFMA tiles */
 } vj_hybrid;
 
 /* Arithmetic of the distance evaluations. */
@@ -78,6 +79,7 @@ typedef enum {
 
 typedef struct vj_index vj_index;
 typedef struct vj_pairs vj_pairs;
+typedef struct vj_predictor vj_predictor;
 
 typedef struct {
     int32_t R;           /* max out-degree, 1..64 */
@@ -212,6 +214,64 @@ vj_status vj_pairs_rechecked(const vj_pairs *r, int64_t *n);
 vj_status vj_pairs_tiers(const vj_pairs *r, float *ms, int32_t *launches, int64_t *queries);
 
 void vj_pairs_free(vj_pairs *r);
+
+/* ---------------------------------------------------------------------------
+ * Difficulty predictor (VJ_HYB_LEARNED).  The paper's OOD test (Section 4.4)
+ * predicts, from d1/d2 after the probe, whether a query needs hybrid
+ * search.  The learned form extends that signal: an MLP over the query
+ * vector and 8 post-probe features predicts the query's recall under k
+ * out-range pop budgets; the join gives each query the smallest budget whose
+ * predicted recall reaches a target and joins the rest exactly.
+ * ------------------------------------------------------------------------- */
+
+/* Features of the queries query_ids[0..n) (NULL = all, n == nq): row i,
+ * [d + 8] float32, is the query vector then f0..f7 = eps, dist(q, s),
+ * min over A of dist(q, y), d1, d2, d1 / d2, |A| / R, |{y in A: dist < eps}| / R
+ * with A = the data nodes among N(q), dist the join metric, d1 (mean |q - y|
+ * over A) and d2 (mean edge length |y - z|, z a data neighbour of y other
+ * than q) in L2 units; A-based values are 0 when A is empty. */
+vj_status vj_join_features(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
+                           vj_metric metric, float *features, void *stream);
+
+/* An MLP din -> h1 -> h2 -> k (ReLU hidden layers, k logits, sigmoid
+ * heads), He-uniform weights from `seed`, zero biases, identity input
+ * normalisation.  Weights are row-major W[out][in]; the input is normalised
+ * as (x - mu) * inv_sigma per column before the first layer. */
+vj_status vj_predictor_create(int32_t din, int32_t h1, int32_t h2, int32_t k, uint64_t seed,
+                              void *stream, vj_predictor **out);
+void vj_predictor_free(vj_predictor *p);
+/* Copy parameters in / out (device pointers of the shapes above; NULL
+ * skips that parameter). */
+vj_status vj_predictor_set_params(vj_predictor *p, const float *W1, const float *b1,
+                                  const float *W2, const float *b2, const float *W3,
+                                  const float *b3, const float *mu, const float *inv_sigma,
+                                  void *stream);
+vj_status vj_predictor_get_params(const vj_predictor *p, float *W1, float *b1, float *W2,
+                                  float *b2, float *W3, float *b3, float *mu, float *inv_sigma,
+                                  void *stream);
+/* mu / inv_sigma from the columns of X [n][din] (constant columns: 1). */
+vj_status vj_predictor_fit_normalization(vj_predictor *p, const float *X, int64_t n, void *stream);
+/* logits [n][k] of X [n][din]. */
+vj_status vj_predictor_forward(const vj_predictor *p, const float *X, int64_t n, float *logits,
+                               void *stream);
+/* Mean binary cross-entropy of sigmoid(logits) against Y [n][k] in [0, 1]
+ * over the entries with mask != 0 (mask NULL: all), into *loss (host), and
+ * its gradient for each parameter (device, parameter shapes; NULL skips). */
+vj_status vj_predictor_loss_grad(const vj_predictor *p, const float *X, const float *Y,
+                                 const float *mask, int64_t n, double *loss, float *gW1,
+                                 float *gb1, float *gW2, float *gb2, float *gW3, float *gb3,
+                                 void *stream);
+/* Adam (beta 0.9 / 0.999) on the mean BCE over minibatches of `batch` rows
+ * of a seeded shuffle, for `epochs` passes; the mean loss of each epoch goes
+ * to loss_per_epoch_host (may be NULL). */
+vj_status vj_predictor_train(vj_predictor *p, const float *X, const float *Y, int64_t n,
+                             int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                             float *loss_per_epoch_host, void *stream);
+/* Attach a predictor to an index for VJ_HYB_LEARNED joins (NULL detaches):
+ * head j predicts the recall under budgets_host[j] out-range pops (k values,
+ * ascending, >= 0).  The predictor must outlive its use by the index. */
+vj_status vj_index_attach_predictor(vj_index *idx, const vj_predictor *p, float recall_target,
+                                    const int32_t *budgets_host);
 
 /* Text of the last error on the calling thread ("" if none). */
 const char *vj_last_error(void);

@@ -11,12 +11,14 @@
 #include <vector>
 
 #include "build.h"
+#include "predictor.h"
 #include "tiles.h"
 #include "util.h"
 #include "vj_internal.h"
 
 struct vj_index { vj::Index impl; };
 struct vj_pairs { vj::Pairs impl; };
+struct vj_predictor { vj::Predictor impl; };
 
 namespace vj {
 
@@ -442,6 +444,67 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
     VJ_CHECK(false, VJ_ERR_INTERNAL, "result capacity did not converge");
 }
 
+// VJ_HYB_LEARNED: features after the probe -> the attached MLP -> the
+// smallest budget whose predicted recall reaches the target; the join then
+// runs in budget mode, and the queries no budget satisfies (budget -1) are
+// joined exactly on the MFMA tiles, their pairs appended.
+static void learned_join(Index &ix, const int32_t *ids, int64_t n, float eps, vj_join_params p,
+                         hipStream_t s, Pairs &r) {
+    const Predictor &P = *ix.pred;
+    VJ_CHECK(P.din == ix.d + kFeatures, VJ_ERR_INVALID_ARG, "predictor input width is not d + 8");
+    std::vector<int32_t> ids_h((size_t)n);
+    if (ids) {
+        VJ_HIP(hipMemcpyAsync(ids_h.data(), ids, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipStreamSynchronize(s));
+        for (int32_t q : ids_h) VJ_CHECK(q >= 0 && q < ix.nq, VJ_ERR_INVALID_ARG, "query id out of range");
+    } else {
+        for (int64_t i = 0; i < n; ++i) ids_h[(size_t)i] = (int32_t)i;
+    }
+    DevBuf ql((size_t)n * sizeof(int32_t));
+    VJ_HIP(hipMemcpyAsync(ql.p, ids_h.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    DevBuf feat((size_t)n * (ix.d + kFeatures) * sizeof(float)), logits((size_t)n * P.k * sizeof(float)),
+        bud((size_t)n * sizeof(int32_t));
+    compute_features(ix, ql.as<int32_t>(), n, eps, ix.d + kFeatures, feat.as<float>(), s);
+    predictor_forward(P, feat.as<float>(), n, logits.as<float>(), s);
+    select_budgets(logits.as<float>(), n, P.k, ix.pred_budgets.as<int32_t>(), ix.pred_target,
+                   bud.as<int32_t>(), s);
+    p.hybrid = VJ_HYB_BUDGET;
+    run_join(ix, ids, n, eps, p, bud.as<int32_t>(), s, r);
+    // queries routed to the exact join
+    std::vector<int32_t> bud_h((size_t)n), routed;
+    VJ_HIP(hipMemcpyAsync(bud_h.data(), bud.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n; ++i)
+        if (bud_h[(size_t)i] < 0) routed.push_back(ids_h[(size_t)i]);
+    if (routed.empty()) return;
+    const int64_t nr = (int64_t)routed.size();
+    DevBuf rl((size_t)nr * sizeof(int32_t)), rows((size_t)nr * ix.dp * sizeof(float));
+    VJ_HIP(hipMemcpyAsync(rl.p, routed.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    gather_rows(ix.vec.as<float>() + (size_t)ix.nx * ix.dp, ix.dp, rl.as<int32_t>(), nr,
+                rows.as<float>(), s);
+    Pairs bp;
+    bruteforce_join(rows.as<float>(), nr, ix.vec.as<float>(), ix.nx, ix.dp, eps, ix.metric,
+                    VJ_PREC_FP32, s, bp);
+    if (bp.count == 0) return;
+    remap_ids(bp.q.as<int32_t>(), bp.count, rl.as<int32_t>(), s);
+    const int64_t tot = r.count + bp.count;
+    DevBuf q2((size_t)tot * sizeof(int32_t)), x2((size_t)tot * sizeof(int32_t)),
+        d2((size_t)tot * sizeof(float));
+    auto cat = [&](DevBuf &dst, const DevBuf &a, const DevBuf &b, size_t el) {
+        if (r.count) VJ_HIP(hipMemcpyAsync(dst.p, a.p, (size_t)r.count * el, hipMemcpyDeviceToDevice, s));
+        VJ_HIP(hipMemcpyAsync(dst.as<char>() + (size_t)r.count * el, b.p, (size_t)bp.count * el,
+                              hipMemcpyDeviceToDevice, s));
+    };
+    cat(q2, r.q, bp.q, sizeof(int32_t));
+    cat(x2, r.x, bp.x, sizeof(int32_t));
+    cat(d2, r.dist, bp.dist, sizeof(float));
+    VJ_HIP(hipStreamSynchronize(s));
+    r.q = std::move(q2);
+    r.x = std::move(x2);
+    r.dist = std::move(d2);
+    r.count = tot;
+}
+
 }  // namespace vj
 
 // =================================================================== C ABI ==
@@ -604,7 +667,8 @@ vj_status vj_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
     VJ_CHECK(p.work_sharing == VJ_WS_SELF || ix.has_mst, VJ_ERR_INVALID_ARG, "work sharing needs the MST");
     VJ_CHECK(p.hybrid != VJ_HYB_BUDGET || p.budget != nullptr, VJ_ERR_INVALID_ARG, "budget mode needs budget[]");
     VJ_CHECK(p.start_tier >= 0 && p.start_tier <= 2, VJ_ERR_INVALID_ARG, "start_tier in [0, 2]");
-    VJ_CHECK(p.hybrid != VJ_HYB_LEARNED, VJ_ERR_UNSUPPORTED, "no predictor attached");
+    VJ_CHECK(p.hybrid != VJ_HYB_LEARNED || ix.pred != nullptr, VJ_ERR_INVALID_ARG,
+             "learned routing needs an attached predictor");
     hipStream_t s = (hipStream_t)stream;
     auto h = std::make_unique<vj_pairs>();
     Pairs &r = h->impl;
@@ -618,7 +682,8 @@ vj_status vj_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
         vj::set_error("");
         return VJ_OK;
     }
-    run_join(ix, query_ids, n, eps, p, p.budget, s, r);
+    if (p.hybrid != VJ_HYB_LEARNED) run_join(ix, query_ids, n, eps, p, p.budget, s, r);
+    else learned_join(ix, query_ids, n, eps, p, s, r);
     *out = h.release();
     API_END
 }
@@ -692,6 +757,150 @@ vj_status vj_pairs_tiers(const vj_pairs *r, float *ms, int32_t *launches, int64_
 }
 
 void vj_pairs_free(vj_pairs *r) { delete r; }
+
+// ------------------------------------------------------------ predictor --
+
+vj_status vj_join_features(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
+                           vj_metric metric, float *features, void *stream) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr && (features != nullptr || n == 0), VJ_ERR_INVALID_ARG, "null pointer");
+    Index &ix = idx->impl;
+    VJ_CHECK(n >= 0 && (query_ids != nullptr || n == ix.nq || n == 0), VJ_ERR_INVALID_ARG,
+             "query_ids may be NULL only with n == nq");
+    VJ_CHECK(std::isfinite(eps), VJ_ERR_INVALID_ARG, "eps must be finite");
+    VJ_CHECK(metric == ix.metric, VJ_ERR_METRIC_MISMATCH, "metric differs from the index metric");
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        vj::set_error("");
+        return VJ_OK;
+    }
+    std::vector<int32_t> ids_h((size_t)n);
+    if (query_ids) {
+        VJ_HIP(hipMemcpyAsync(ids_h.data(), query_ids, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipStreamSynchronize(s));
+        for (int32_t q : ids_h) VJ_CHECK(q >= 0 && q < ix.nq, VJ_ERR_INVALID_ARG, "query id out of range");
+    } else {
+        for (int64_t i = 0; i < n; ++i) ids_h[(size_t)i] = (int32_t)i;
+    }
+    DevBuf ql((size_t)n * sizeof(int32_t));
+    VJ_HIP(hipMemcpyAsync(ql.p, ids_h.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    compute_features(ix, ql.as<int32_t>(), n, eps, ix.d + kFeatures, features, s);
+    VJ_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
+vj_status vj_predictor_create(int32_t din, int32_t h1, int32_t h2, int32_t k, uint64_t seed,
+                              void *stream, vj_predictor **out) {
+    API_BEGIN
+    VJ_CHECK(out != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    VJ_CHECK(din >= 1 && h1 >= 1 && h2 >= 1 && k >= 1 && k <= 64, VJ_ERR_INVALID_ARG,
+             "layer widths must be >= 1 (k <= 64)");
+    auto h = std::make_unique<vj_predictor>();
+    predictor_init(h->impl, din, h1, h2, k, seed, (hipStream_t)stream);
+    *out = h.release();
+    API_END
+}
+
+void vj_predictor_free(vj_predictor *p) { delete p; }
+
+vj_status vj_predictor_set_params(vj_predictor *pr, const float *W1, const float *b1,
+                                  const float *W2, const float *b2, const float *W3,
+                                  const float *b3, const float *mu, const float *inv_sigma,
+                                  void *stream) {
+    API_BEGIN
+    VJ_CHECK(pr != nullptr, VJ_ERR_INVALID_ARG, "null predictor");
+    Predictor &p = pr->impl;
+    hipStream_t s = (hipStream_t)stream;
+    const float *src[8] = {W1, b1, W2, b2, W3, b3, mu, inv_sigma};
+    DevBuf *dst[8] = {&p.W1, &p.b1, &p.W2, &p.b2, &p.W3, &p.b3, &p.mu, &p.inv_sigma};
+    for (int i = 0; i < 8; ++i)
+        if (src[i]) VJ_HIP(hipMemcpyAsync(dst[i]->p, src[i], dst[i]->bytes, hipMemcpyDeviceToDevice, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
+vj_status vj_predictor_get_params(const vj_predictor *pr, float *W1, float *b1, float *W2,
+                                  float *b2, float *W3, float *b3, float *mu, float *inv_sigma,
+                                  void *stream) {
+    API_BEGIN
+    VJ_CHECK(pr != nullptr, VJ_ERR_INVALID_ARG, "null predictor");
+    const Predictor &p = pr->impl;
+    hipStream_t s = (hipStream_t)stream;
+    float *dst[8] = {W1, b1, W2, b2, W3, b3, mu, inv_sigma};
+    const DevBuf *src[8] = {&p.W1, &p.b1, &p.W2, &p.b2, &p.W3, &p.b3, &p.mu, &p.inv_sigma};
+    for (int i = 0; i < 8; ++i)
+        if (dst[i]) VJ_HIP(hipMemcpyAsync(dst[i], src[i]->p, src[i]->bytes, hipMemcpyDeviceToDevice, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
+vj_status vj_predictor_fit_normalization(vj_predictor *pr, const float *X, int64_t n, void *stream) {
+    API_BEGIN
+    VJ_CHECK(pr != nullptr && X != nullptr && n >= 1, VJ_ERR_INVALID_ARG, "bad arguments");
+    predictor_fit_normalization(pr->impl, X, n, (hipStream_t)stream);
+    API_END
+}
+
+vj_status vj_predictor_forward(const vj_predictor *pr, const float *X, int64_t n, float *logits,
+                               void *stream) {
+    API_BEGIN
+    VJ_CHECK(pr != nullptr && n >= 0 && (n == 0 || (X && logits)), VJ_ERR_INVALID_ARG, "bad arguments");
+    VJ_CHECK(n < ((int64_t)1 << 31), VJ_ERR_UNSUPPORTED, "n must be < 2^31");
+    predictor_forward(pr->impl, X, n, logits, (hipStream_t)stream);
+    API_END
+}
+
+vj_status vj_predictor_loss_grad(const vj_predictor *pr, const float *X, const float *Y,
+                                 const float *mask, int64_t n, double *loss, float *gW1,
+                                 float *gb1, float *gW2, float *gb2, float *gW3, float *gb3,
+                                 void *stream) {
+    API_BEGIN
+    VJ_CHECK(pr != nullptr && n >= 0 && (n == 0 || (X && Y)), VJ_ERR_INVALID_ARG, "bad arguments");
+    VJ_CHECK(n < ((int64_t)1 << 31), VJ_ERR_UNSUPPORTED, "n must be < 2^31");
+    const double l = predictor_loss_grad(pr->impl, X, Y, mask, n, gW1, gb1, gW2, gb2, gW3, gb3,
+                                         (hipStream_t)stream);
+    if (loss) *loss = l;
+    API_END
+}
+
+vj_status vj_predictor_train(vj_predictor *pr, const float *X, const float *Y, int64_t n,
+                             int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                             float *loss_per_epoch_host, void *stream) {
+    API_BEGIN
+    VJ_CHECK(pr != nullptr && X != nullptr && Y != nullptr && n >= 1, VJ_ERR_INVALID_ARG, "bad arguments");
+    VJ_CHECK(epochs >= 0 && batch >= 1 && std::isfinite(lr) && lr > 0.f, VJ_ERR_INVALID_ARG,
+             "epochs >= 0, batch >= 1, lr > 0");
+    predictor_train(pr->impl, X, Y, n, epochs, batch, lr, seed, loss_per_epoch_host,
+                    (hipStream_t)stream);
+    API_END
+}
+
+vj_status vj_index_attach_predictor(vj_index *idx, const vj_predictor *pr, float recall_target,
+                                    const int32_t *budgets_host) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr, VJ_ERR_INVALID_ARG, "null index");
+    Index &ix = idx->impl;
+    if (pr == nullptr) {
+        ix.pred = nullptr;
+        vj::set_error("");
+        return VJ_OK;
+    }
+    VJ_CHECK(budgets_host != nullptr, VJ_ERR_INVALID_ARG, "budgets needed");
+    VJ_CHECK(std::isfinite(recall_target) && recall_target > 0.f && recall_target <= 1.f,
+             VJ_ERR_INVALID_ARG, "recall_target in (0, 1]");
+    const Predictor &p = pr->impl;
+    VJ_CHECK(p.din == ix.d + kFeatures, VJ_ERR_INVALID_ARG, "predictor input width is not d + 8");
+    for (int j = 0; j < p.k; ++j) {
+        VJ_CHECK(budgets_host[j] >= 0, VJ_ERR_INVALID_ARG, "budgets must be >= 0");
+        VJ_CHECK(j == 0 || budgets_host[j] > budgets_host[j - 1], VJ_ERR_INVALID_ARG,
+                 "budgets must be ascending");
+    }
+    ix.pred_budgets.alloc((size_t)p.k * sizeof(int32_t));
+    VJ_HIP(hipMemcpy(ix.pred_budgets.p, budgets_host, p.k * sizeof(int32_t), hipMemcpyHostToDevice));
+    ix.pred = &p;
+    ix.pred_target = recall_target;
+    API_END
+}
 
 }  // extern "C"
 

@@ -88,6 +88,10 @@ struct Index {
     DevBuf seg;      // int64 [nq] offset of the query's pairs in the call's output
     DevBuf segn;     // int32 [nq] number of pairs of the query
     DevBuf ws_gh, ws_gil, ws_gild;  // global tables of the join (kept between calls)
+    // attached difficulty predictor (VJ_HYB_LEARNED); not owned
+    const struct Predictor *pred = nullptr;
+    float pred_target = 0.f;
+    DevBuf pred_budgets;  // int32 [k] out-range pop budget of each head, ascending
     int32_t gen = 0;
 };
 

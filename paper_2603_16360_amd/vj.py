@@ -73,6 +73,17 @@ _SIGS = {
     "vj_pairs_tiers": (C.c_int, [_vp, _vp, _vp, _vp]),
     "vj_pairs_rechecked": (C.c_int, [_vp, _vp]),
     "vj_pairs_free": (None, [_vp]),
+    "vj_join_features": (C.c_int, [_vp, _vp, _i64, _f32, C.c_int, _vp, _vp]),
+    "vj_predictor_create": (C.c_int, [_i32, _i32, _i32, _i32, C.c_uint64, _vp, _PP]),
+    "vj_predictor_free": (None, [_vp]),
+    "vj_predictor_set_params": (C.c_int, [_vp] + [_vp] * 8 + [_vp]),
+    "vj_predictor_get_params": (C.c_int, [_vp] + [_vp] * 8 + [_vp]),
+    "vj_predictor_fit_normalization": (C.c_int, [_vp, _vp, _i64, _vp]),
+    "vj_predictor_forward": (C.c_int, [_vp, _vp, _i64, _vp, _vp]),
+    "vj_predictor_loss_grad": (C.c_int, [_vp, _vp, _vp, _vp, _i64, C.POINTER(C.c_double)]
+                               + [_vp] * 6 + [_vp]),
+    "vj_predictor_train": (C.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _f32, C.c_uint64, _vp, _vp]),
+    "vj_index_attach_predictor": (C.c_int, [_vp, _vp, _f32, _vp]),
     "vj_last_error": (C.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -257,6 +268,90 @@ def vj_bruteforce_join(Q: torch.Tensor, X: torch.Tensor, eps: float, metric: str
                                    float(eps), METRIC[metric], PRECISION[precision],
                                    _stream(), C.byref(h)))
     return Pairs(h.value, 0)
+
+
+def vj_join_features(index: Index, eps: float, metric: str = "l2",
+                     query_ids: torch.Tensor | None = None) -> torch.Tensor:
+    """[n][d + 8] float32 post-probe features (see vj_join_features)."""
+    info = index.info()
+    n = info["nq"] if query_ids is None else int(query_ids.numel())
+    out = torch.empty((n, info["d"] + 8), dtype=torch.float32, device="cuda")
+    qp = C.c_void_p(0)
+    if query_ids is not None:
+        query_ids = _dev(query_ids, torch.int32, "query_ids")
+        qp = _ptr(query_ids)
+    _check(_lib.vj_join_features(index._h, qp, n, float(eps), METRIC[metric], _ptr(out), _stream()))
+    return out
+
+
+class Predictor:
+    """The difficulty MLP (vj_predictor): din -> h1 -> h2 -> k."""
+
+    def __init__(self, din: int, h1: int = 256, h2: int = 256, k: int = 4, seed: int = 0):
+        h = C.c_void_p()
+        _check(_lib.vj_predictor_create(din, h1, h2, k, seed, _stream(), C.byref(h)))
+        self._h = h
+        self.shapes = {"W1": (h1, din), "b1": (h1,), "W2": (h2, h1), "b2": (h2,),
+                       "W3": (k, h2), "b3": (k,), "mu": (din,), "inv_sigma": (din,)}
+        self.din, self.k = din, k
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.vj_predictor_free(self._h)
+            self._h = C.c_void_p(0)
+
+    NAMES = ("W1", "b1", "W2", "b2", "W3", "b3", "mu", "inv_sigma")
+
+    def get_params(self) -> dict:
+        out = {k: torch.empty(v, dtype=torch.float32, device="cuda") for k, v in self.shapes.items()}
+        _check(_lib.vj_predictor_get_params(self._h, *[_ptr(out[k]) for k in self.NAMES], _stream()))
+        return out
+
+    def set_params(self, **kw):
+        ts = {k: _dev(v, torch.float32, k) for k, v in kw.items()}
+        for k, v in ts.items():
+            if tuple(v.shape) != self.shapes[k]:
+                raise ValueError(f"{k} must have shape {self.shapes[k]}")
+        _check(_lib.vj_predictor_set_params(self._h, *[_ptr(ts[k]) if k in ts else C.c_void_p(0)
+                                                       for k in self.NAMES], _stream()))
+
+    def fit_normalization(self, X: torch.Tensor):
+        X = _dev(X, torch.float32, "X")
+        _check(_lib.vj_predictor_fit_normalization(self._h, _ptr(X), X.shape[0], _stream()))
+
+    def forward(self, X: torch.Tensor) -> torch.Tensor:
+        X = _dev(X, torch.float32, "X")
+        out = torch.empty((X.shape[0], self.k), dtype=torch.float32, device="cuda")
+        _check(_lib.vj_predictor_forward(self._h, _ptr(X), X.shape[0], _ptr(out), _stream()))
+        return out
+
+    def loss_grad(self, X: torch.Tensor, Y: torch.Tensor, mask: torch.Tensor | None = None):
+        X = _dev(X, torch.float32, "X")
+        Y = _dev(Y, torch.float32, "Y")
+        m = _dev(mask, torch.float32, "mask") if mask is not None else None
+        g = {k: torch.empty(self.shapes[k], dtype=torch.float32, device="cuda")
+             for k in ("W1", "b1", "W2", "b2", "W3", "b3")}
+        loss = C.c_double()
+        _check(_lib.vj_predictor_loss_grad(self._h, _ptr(X), _ptr(Y), _ptr(m), X.shape[0],
+                                           C.byref(loss), *[_ptr(g[k]) for k in g], _stream()))
+        return loss.value, g
+
+    def train(self, X: torch.Tensor, Y: torch.Tensor, epochs: int = 10, batch: int = 1024,
+              lr: float = 1e-3, seed: int = 0):
+        X = _dev(X, torch.float32, "X")
+        Y = _dev(Y, torch.float32, "Y")
+        losses = (C.c_float * max(1, epochs))()
+        _check(_lib.vj_predictor_train(self._h, _ptr(X), _ptr(Y), X.shape[0], epochs, batch,
+                                       float(lr), seed, losses, _stream()))
+        return list(losses)[:epochs]
+
+
+def vj_index_attach_predictor(index: Index, pred: Predictor | None, recall_target: float = 0.95,
+                              budgets=(0, 16, 64, 256)):
+    b = (C.c_int32 * len(budgets))(*budgets)
+    _check(_lib.vj_index_attach_predictor(index._h, pred._h if pred is not None else None,
+                                          float(recall_target), b))
+    index._pred = pred  # keep the predictor alive while attached
 
 
 def vj_last_error() -> str:
