@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--variants", default="fp32,u8")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration)")
+    ap.add_argument("--stream", action="store_true",
+                    help="instead of the headline: the batched stream workload at 1/10 scale "
+                         "(200 batches, p50/p99 batch latency)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -84,6 +87,9 @@ def main():
     import torch
     import workloads
     from paper_2603_16360_amd import vj
+
+    if args.stream:
+        return stream_main(args, torch, workloads, vj)
 
     t0 = time.time()
     w = workloads.config_mid()
@@ -228,6 +234,73 @@ def main():
         "build_s": build_s,
         "ground_truth_s": gt_s,
         "ground_truth_pairs": n_gt,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def stream_main(args, torch, workloads, vj):
+    """The batched stream: one merged index over X and every batch's queries,
+    then the batches joined one after the other (vj_join_batches), each at
+    its own eps (oracle-calibrated, tests/golden/eps.json)."""
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "eps.json")))["stream"]
+    t0 = time.time()
+    w = workloads.config_stream(scale=golden["scale"], n_batches=golden["n_batches"])
+    for key, arr in (("Q_sha", w.Q), ("X_sha", w.X)):
+        sha = hashlib.sha256(np.ascontiguousarray(arr).tobytes()).hexdigest()[:16]
+        if sha != golden[key]:
+            raise SystemExit(f"generated data differs from the calibrated data ({key})")
+    batches = workloads.stream_batches(w)
+    starts = [b[0] for b in batches]
+    counts = [b[1] for b in batches]
+    eps = golden["eps"]
+    log(f"stream: X {w.X.shape}, {len(batches)} batches, {w.Q.shape[0]} queries ({time.time() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    Q = torch.from_numpy(w.Q).to(dev)
+    X = torch.from_numpy(w.X).to(dev)
+    t = time.time()
+    idx = vj.vj_build_merged_index(Q, X, metric="l2", R=w.R)
+    torch.cuda.synchronize()
+    build_s = time.time() - t
+    log(f"merged index over {w.Q.shape[0] + w.X.shape[0]} nodes built in {build_s:.1f}s")
+    params, tuned_ms = vj.vj_autotune_join(idx, eps[0], query_ids=torch.arange(
+        starts[0], starts[0] + counts[0], dtype=torch.int32, device=dev))
+    log(f"autotuned on batch 0: start_tier={params.start_tier} precision={params.precision} "
+        f"({tuned_ms:.3f} ms)")
+    for _ in range(max(1, args.warmup)):
+        vj.vj_join_batches(idx, starts[:4], counts[:4], eps[:4], params=params)
+    torch.cuda.synchronize()
+    walls, lat = [], []
+    res = None
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        res, ms = vj.vj_join_batches(idx, starts, counts, eps, params=params)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - ts)
+        lat.extend(ms)
+    nq = int(sum(counts))
+    pairs = sum(r.count() for r in res)
+    # recall on every 20th batch against the exact join
+    found = exact = 0
+    for b in range(0, len(batches), 20):
+        qb = Q[starts[b]:starts[b] + counts[b]]
+        gt = vj.vj_bruteforce_join(qb, X, eps[b])
+        exact += gt.count()
+        found += res[b].count()
+    lat = np.array(lat)
+    line = {
+        "metric": "stream join queries/sec and batch latency (200 batches, X=1M x 96)",
+        "value": nq / float(np.mean(walls)), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * float(np.mean(walls)), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "stream at 1/10 scale: X=1,000,000 d=96 1,024-cluster Gaussian "
+                               "mixture; 200 batches of 100..10,000 queries (log-uniform), eps "
+                               "per batch for 5..200 mean matches", "queries": nq},
+        "batch_ms_p50": float(np.percentile(lat, 50)), "batch_ms_p99": float(np.percentile(lat, 99)),
+        "batch_ms_max": float(lat.max()), "pairs": int(pairs),
+        "recall_sampled_batches": found / max(1, exact), "build_s": build_s,
+        "tuned": {"start_tier": params.start_tier, "precision": params.precision},
     }
     print(json.dumps(line), flush=True)
 

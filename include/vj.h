@@ -177,6 +177,30 @@ vj_status vj_bruteforce_join(const float *Q, int64_t nq, const float *X, int64_t
                              int32_t d, float eps, vj_metric metric, vj_precision prec,
                              void *stream, vj_pairs **out);
 
+/*
+ * Batches (a stream of joins on one index): batch b joins the queries
+ * query_ids[start[b] .. start[b] + count[b]) (indices into Q; query_ids NULL:
+ * the ids start[b] .. start[b] + count[b] - 1 themselves) at eps_host[b],
+ * with the parameters p, one after the other on `stream`, reusing the
+ * index's join buffers.  out[n_batches] receives the results (on error none
+ * is kept); batch_ms_host[b] (may be NULL) the wall time of batch b, from
+ * its submission to its result being complete.
+ */
+vj_status vj_join_batches(vj_index *idx, const int32_t *query_ids, const int64_t *batch_start_host,
+                          const int64_t *batch_count_host, const float *eps_host,
+                          int32_t n_batches, vj_metric metric, const vj_join_params *p,
+                          void *stream, vj_pairs **out, float *batch_ms_host);
+
+/*
+ * Autotuning: time vj_join on the sample query_ids[0..n) at eps for each
+ * candidate launch configuration (first storage tier 0 or 1; fp32 rows, or
+ * exact u8 rows when the index data allows them -- every candidate gives
+ * the same decisions) and write the fastest into *p, keeping its other
+ * fields.  best_ms_host (may be NULL): the device time of the pick.
+ */
+vj_status vj_autotune_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
+                           vj_metric metric, vj_join_params *p, float *best_ms_host, void *stream);
+
 /* Number of pairs held by a result. */
 int64_t vj_pairs_count(const vj_pairs *r);
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -205,13 +206,13 @@ static void check_shape(const float *Q, int64_t nq, const float *X, int64_t nx, 
 // finished in an earlier launch (any parent-before-child order gives the
 // same result, Algorithm 3 reads only the parent's cache).
 struct Order {
-    DevBuf qlist, qpos;
+    DevBuf &qlist, &qpos;
     std::vector<int64_t> level_start;  // boundaries of the launches, last = n
 };
 
 static void make_order(Index &ix, const int32_t *ids, int64_t n, int ws, hipStream_t s, Order &o) {
-    o.qlist.alloc(n * sizeof(int32_t));
-    o.qpos.alloc(n * sizeof(int32_t));
+    o.qlist.reserve(n * sizeof(int32_t));
+    o.qpos.reserve(n * sizeof(int32_t));
     o.level_start.clear();
     if (ws == VJ_WS_SELF) {
         if (ids) VJ_HIP(hipMemcpyAsync(o.qlist.p, ids, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
@@ -251,25 +252,26 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
     const int beam = (hyb != VJ_HYB_OFF) ? p.hybrid_beam : 0;
     VJ_CHECK(beam <= 256, VJ_ERR_UNSUPPORTED, "hybrid_beam must be <= 256");
 
-    Order ord;
+    JoinWorkspace &jw = ix.jw;
+    Order ord{jw.qlist, jw.qpos, {}};
     make_order(ix, ids, n, ws, s, ord);
     const int32_t *qlist = ord.qlist.as<int32_t>(), *qpos = ord.qpos.as<int32_t>();
 
     // counters: [0..1] out_count (u64), [2] ovf_count, [3] err, [4] global regions taken,
     // [6..7] bf16 re-checks (u64)
-    DevBuf counters(64), argsbuf(sizeof(JoinArgs)), ovf((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
-    DevBuf out_q, out_x, out_d, gh, gil, gild, q2, p2, sl;
+    jw.counters.reserve(64);
+    jw.args.reserve(sizeof(JoinArgs));
+    jw.ovf.reserve((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
+    DevBuf &counters = jw.counters, &argsbuf = jw.args, &ovf = jw.ovf, &sl = jw.slots;
+    DevBuf &out_q = jw.out_q, &out_x = jw.out_x, &out_d = jw.out_d;
+    DevBuf gh, gil, gild, q2, p2;
     r.stats.alloc((size_t)std::max<int64_t>(n, 1) * 8 * sizeof(int32_t));
     int32_t *ctr = counters.as<int32_t>();
 
     int64_t cap = p.pair_capacity > 0 ? p.pair_capacity : std::max<int64_t>(1 << 16, n * 64);
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    VJ_HIP(hipEventCreate(&ev0));
-    VJ_HIP(hipEventCreate(&ev1));
-    struct EvGuard {
-        hipEvent_t a, b;
-        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
-    } evguard{ev0, ev1};
+    if (!jw.ev0) VJ_HIP(hipEventCreate(&jw.ev0));
+    if (!jw.ev1) VJ_HIP(hipEventCreate(&jw.ev1));
+    hipEvent_t ev0 = jw.ev0, ev1 = jw.ev1;
     for (int attempt = 0; attempt < 4; ++attempt) {
         r.kernel_ms = 0.f;
         r.spill_ms = 0.f;
@@ -413,7 +415,7 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
                 VJ_HIP(hipMemcpyAsync(slots_h.data(), ovf.p, pending * sizeof(int32_t), hipMemcpyDeviceToHost, s));
                 VJ_HIP(hipStreamSynchronize(s));
                 std::sort(slots_h.begin(), slots_h.end());
-                sl.alloc(pending * sizeof(int32_t));
+                sl.reserve(pending * sizeof(int32_t));
                 VJ_HIP(hipMemcpyAsync(sl.p, slots_h.data(), pending * sizeof(int32_t), hipMemcpyHostToDevice, s));
                 DevBuf nq2(pending * sizeof(int32_t)), np2(pending * sizeof(int32_t));
                 gather_slots(lq, lp, sl.as<int32_t>(), pending, nq2.as<int32_t>(), np2.as<int32_t>(), s);
@@ -430,13 +432,20 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
         if (total <= cap) {
             unsigned long long nre = 0;
             VJ_HIP(hipMemcpyAsync(&nre, ctr + 6, sizeof(nre), hipMemcpyDeviceToHost, s));
+            // the result owns exact-size copies; the workspace keeps its buffers
+            const size_t m = (size_t)std::max<int64_t>(total, 1);
+            r.q.alloc(m * sizeof(int32_t));
+            r.x.alloc(m * sizeof(int32_t));
+            r.dist.alloc(m * sizeof(float));
+            if (total > 0) {
+                VJ_HIP(hipMemcpyAsync(r.q.p, out_q.p, total * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+                VJ_HIP(hipMemcpyAsync(r.x.p, out_x.p, total * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+                VJ_HIP(hipMemcpyAsync(r.dist.p, out_d.p, total * sizeof(float), hipMemcpyDeviceToDevice, s));
+            }
             VJ_HIP(hipStreamSynchronize(s));
             r.n_candidates = (int64_t)nre;
             r.count = total;
             r.n_queries = n;
-            r.q = std::move(out_q);
-            r.x = std::move(out_x);
-            r.dist = std::move(out_d);
             return;
         }
         cap = total + total / 16 + 1024;
@@ -757,6 +766,100 @@ vj_status vj_pairs_tiers(const vj_pairs *r, float *ms, int32_t *launches, int64_
 }
 
 void vj_pairs_free(vj_pairs *r) { delete r; }
+
+// ------------------------------------------------------- batches, tuning --
+
+vj_status vj_join_batches(vj_index *idx, const int32_t *query_ids, const int64_t *batch_start_host,
+                          const int64_t *batch_count_host, const float *eps_host,
+                          int32_t n_batches, vj_metric metric, const vj_join_params *pp,
+                          void *stream, vj_pairs **out, float *batch_ms_host) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr && out != nullptr && batch_start_host != nullptr &&
+                 batch_count_host != nullptr && eps_host != nullptr && n_batches >= 0,
+             VJ_ERR_INVALID_ARG, "null pointer or negative batch count");
+    Index &ix = idx->impl;
+    for (int32_t b = 0; b < n_batches; ++b) {
+        const int64_t st = batch_start_host[b], ct = batch_count_host[b];
+        VJ_CHECK(st >= 0 && ct >= 0, VJ_ERR_INVALID_ARG, "batch ranges must be >= 0");
+        VJ_CHECK(query_ids != nullptr ? true : st + ct <= ix.nq, VJ_ERR_INVALID_ARG,
+                 "batch range beyond the queries");
+        VJ_CHECK(std::isfinite(eps_host[b]), VJ_ERR_INVALID_ARG, "eps must be finite");
+    }
+    std::vector<vj_pairs *> res((size_t)n_batches, nullptr);
+    struct Guard {
+        std::vector<vj_pairs *> &v;
+        bool done = false;
+        ~Guard() { if (!done) for (auto *r : v) delete r; }
+    } guard{res};
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int32_t> iota_h;
+    DevBuf ids_dev;
+    for (int32_t b = 0; b < n_batches; ++b) {
+        const auto t0 = std::chrono::steady_clock::now();
+        const int64_t st = batch_start_host[b], ct = batch_count_host[b];
+        const int32_t *ids = nullptr;
+        if (query_ids) {
+            ids = query_ids + st;
+        } else if (ct > 0) {
+            // the identity list of this range
+            iota_h.resize((size_t)ct);
+            for (int64_t i = 0; i < ct; ++i) iota_h[(size_t)i] = (int32_t)(st + i);
+            ids_dev.reserve((size_t)ct * sizeof(int32_t));
+            VJ_HIP(hipMemcpyAsync(ids_dev.p, iota_h.data(), ct * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            ids = ids_dev.as<int32_t>();
+        }
+        const vj_status rc = vj_join(idx, ids, ct, eps_host[b], metric, pp, stream, &res[(size_t)b]);
+        VJ_CHECK(rc == VJ_OK, rc, std::string("batch ") + std::to_string(b) + ": " + vj_last_error());
+        if (batch_ms_host)
+            batch_ms_host[b] = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    for (int32_t b = 0; b < n_batches; ++b) out[b] = res[(size_t)b];
+    guard.done = true;
+    API_END
+}
+
+vj_status vj_autotune_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
+                           vj_metric metric, vj_join_params *pp, float *best_ms_host, void *stream) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr && pp != nullptr && (query_ids != nullptr || n == idx->impl.nq) && n >= 1,
+             VJ_ERR_INVALID_ARG, "bad arguments");
+    const Index &ix = idx->impl;
+    vj_join_params base = *pp;
+    // candidates: the one-wave or the workgroup tier first; fp32 or (when the
+    // data is exactly u8) u8 rows -- all of them give the same decisions
+    std::vector<vj_join_params> cand;
+    for (int tier : {0, 1}) {
+        for (int prec : {(int)VJ_PREC_FP32, (int)VJ_PREC_U8}) {
+            if (prec == VJ_PREC_U8 && !ix.integer_u8) continue;
+            if (base.precision != VJ_PREC_FP32 && base.precision != VJ_PREC_U8 &&
+                base.precision != VJ_PREC_AUTO) prec = base.precision;
+            vj_join_params c = base;
+            c.start_tier = tier;
+            c.precision = prec;
+            cand.push_back(c);
+        }
+    }
+    float best = INFINITY;
+    vj_join_params pick = base;
+    for (const auto &c : cand) {
+        float t = INFINITY;
+        for (int rep = 0; rep < 3; ++rep) {  // first run warms the workspace
+            vj_pairs *r = nullptr;
+            const vj_status rc = vj_join(idx, query_ids, n, eps, metric, &c, stream, &r);
+            VJ_CHECK(rc == VJ_OK, rc, vj_last_error());
+            const float ms = r->impl.kernel_ms + r->impl.spill_ms;
+            delete r;
+            if (rep > 0) t = std::min(t, ms);
+        }
+        if (t < best) {
+            best = t;
+            pick = c;
+        }
+    }
+    *pp = pick;
+    if (best_ms_host) *best_ms_host = best;
+    API_END
+}
 
 // ------------------------------------------------------------ predictor --
 

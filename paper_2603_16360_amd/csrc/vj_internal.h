@@ -66,6 +66,19 @@ struct DevBuf {
 int padded_dim(int d);
 
 // ----------------------------------------------------------------- index --
+// Buffers of vj_join kept between calls on one index (grow only).
+struct JoinWorkspace {
+    DevBuf qlist, qpos, counters, args, ovf, slots, out_q, out_x, out_d;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    JoinWorkspace() = default;
+    JoinWorkspace(const JoinWorkspace &) = delete;
+    JoinWorkspace &operator=(const JoinWorkspace &) = delete;
+    ~JoinWorkspace() {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+};
+
 struct Index {
     int64_t nq = 0, nx = 0, N = 0;
     int32_t d = 0, dp = 0, R = 0, entry = 0;
@@ -88,6 +101,7 @@ struct Index {
     DevBuf seg;      // int64 [nq] offset of the query's pairs in the call's output
     DevBuf segn;     // int32 [nq] number of pairs of the query
     DevBuf ws_gh, ws_gil, ws_gild;  // global tables of the join (kept between calls)
+    JoinWorkspace jw;
     // attached difficulty predictor (VJ_HYB_LEARNED); not owned
     const struct Predictor *pred = nullptr;
     float pred_target = 0.f;

@@ -74,6 +74,10 @@ _SIGS = {
     "vj_pairs_rechecked": (C.c_int, [_vp, _vp]),
     "vj_pairs_free": (None, [_vp]),
     "vj_join_features": (C.c_int, [_vp, _vp, _i64, _f32, C.c_int, _vp, _vp]),
+    "vj_join_batches": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _i32, C.c_int, C.POINTER(vj_join_params),
+                                  _vp, _vp, _vp]),
+    "vj_autotune_join": (C.c_int, [_vp, _vp, _i64, _f32, C.c_int, C.POINTER(vj_join_params),
+                                   _vp, _vp]),
     "vj_predictor_create": (C.c_int, [_i32, _i32, _i32, _i32, C.c_uint64, _vp, _PP]),
     "vj_predictor_free": (None, [_vp]),
     "vj_predictor_set_params": (C.c_int, [_vp] + [_vp] * 8 + [_vp]),
@@ -268,6 +272,44 @@ def vj_bruteforce_join(Q: torch.Tensor, X: torch.Tensor, eps: float, metric: str
                                    float(eps), METRIC[metric], PRECISION[precision],
                                    _stream(), C.byref(h)))
     return Pairs(h.value, 0)
+
+
+def vj_join_batches(index: Index, starts, counts, eps_list, metric: str = "l2",
+                    query_ids: torch.Tensor | None = None, params: vj_join_params | None = None,
+                    **kw):
+    """Run the batches back to back; returns (list of Pairs, wall ms per batch)."""
+    if params is None:
+        params = join_params(**kw)
+    nb = len(starts)
+    st = (C.c_int64 * nb)(*[int(v) for v in starts])
+    ct = (C.c_int64 * nb)(*[int(v) for v in counts])
+    ep = (C.c_float * nb)(*[float(v) for v in eps_list])
+    out = (C.c_void_p * nb)()
+    ms = (C.c_float * nb)()
+    qp = C.c_void_p(0)
+    if query_ids is not None:
+        query_ids = _dev(query_ids, torch.int32, "query_ids")
+        qp = _ptr(query_ids)
+    _check(_lib.vj_join_batches(index._h, qp, st, ct, ep, nb, METRIC[metric], C.byref(params),
+                                _stream(), out, ms))
+    return [Pairs(out[b], int(counts[b])) for b in range(nb)], list(ms)
+
+
+def vj_autotune_join(index: Index, eps: float, metric: str = "l2",
+                     query_ids: torch.Tensor | None = None, params: vj_join_params | None = None,
+                     **kw):
+    """(tuned vj_join_params, best device ms) on the given sample."""
+    if params is None:
+        params = join_params(**kw)
+    n = index.info()["nq"] if query_ids is None else int(query_ids.numel())
+    qp = C.c_void_p(0)
+    if query_ids is not None:
+        query_ids = _dev(query_ids, torch.int32, "query_ids")
+        qp = _ptr(query_ids)
+    best = C.c_float()
+    _check(_lib.vj_autotune_join(index._h, qp, n, float(eps), METRIC[metric], C.byref(params),
+                                 C.byref(best), _stream()))
+    return params, best.value
 
 
 def vj_join_features(index: Index, eps: float, metric: str = "l2",

@@ -26,6 +26,28 @@ MAKERS = {
     "mid": lambda: workloads.config_mid(),
 }
 
+# the batched stream at 1/10 scale: X = 1,000,000 x 96; 200 batches of
+# 100..10,000 queries; eps per batch for the batch's target mean, calibrated
+# on at most 50 of its queries (seed 504 + batch)
+STREAM_SCALE, STREAM_BATCHES, STREAM_SAMPLE = 0.1, 200, 50
+
+
+def make_stream(data):
+    t = time.time()
+    w = workloads.config_stream(scale=STREAM_SCALE, n_batches=STREAM_BATCHES)
+    eps = []
+    for b, (start, count, target) in enumerate(workloads.stream_batches(w)):
+        r = np.random.default_rng(504 + b)
+        m = min(count, STREAM_SAMPLE)
+        idx = start + np.sort(r.choice(count, size=m, replace=False))
+        eps.append(oracle.calibrate_eps(w.Q[idx], w.X, target, w.metric))
+    data["stream"] = {"eps": eps, "scale": STREAM_SCALE, "n_batches": STREAM_BATCHES,
+                      "sample_per_batch": STREAM_SAMPLE, "metric": w.metric,
+                      "Q_sha": checksum(w.Q), "X_sha": checksum(w.X),
+                      "nq": int(w.Q.shape[0]), "nx": int(w.X.shape[0]), "d": w.d}
+    print(f"stream: {len(eps)} batches, eps {min(eps):.4f}..{max(eps):.4f} ({time.time() - t:.1f}s)",
+          flush=True)
+
 
 def checksum(a: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()[:16]
@@ -40,6 +62,11 @@ def sample(w):
 def main(names):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
+        if name == "stream":
+            make_stream(data)
+            with open(OUT, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+            continue
         t = time.time()
         w = MAKERS[name]()
         idx = sample(w)
@@ -55,4 +82,4 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or list(MAKERS))
+    main(sys.argv[1:] or list(MAKERS) + ["stream"])
