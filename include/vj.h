@@ -101,8 +101,15 @@ typedef struct {
                                tables in global memory; a query
                                that outgrows a tier re-runs on the next.  Callers that know
                                their queries are large (high eps) skip the small tiers. */
-    int32_t waves_per_cu;   /* reserved, set 0 */
+    int32_t coop_tables;    /* LDS tables of the workgroup tier (0): 0 large (8192 visited
+                               slots, 1536 pairs, 3 workgroups per CU), 1 small (4096 slots,
+                               1024 pairs, 4 workgroups per CU); same results either way */
     int64_t pair_capacity;  /* initial result capacity hint (0: auto) */
+    int32_t dense_first;    /* self mode (1): launch queries in ascending order of d1, the mean
+                               stored length of their edges to data nodes -- dense
+                               neighbourhoods, whose joins run longest, start first, which
+                               shortens the tail of uneven query costs; 0: the given order.
+                               Results are the same either way. */
 } vj_join_params;
 
 void vj_default_build_params(vj_build_params *p);
@@ -193,7 +200,8 @@ vj_status vj_join_batches(vj_index *idx, const int32_t *query_ids, const int64_t
 
 /*
  * Autotuning: time vj_join on the sample query_ids[0..n) at eps for each
- * candidate launch configuration (first storage tier 0 or 1; fp32 rows, or
+ * candidate launch configuration (first storage tier 0 or 1; large or small
+ * workgroup-tier tables; fp32 rows, or
  * exact u8 rows when the index data allows them -- every candidate gives
  * the same decisions) and write the fastest into *p, keeping its other
  * fields.  best_ms_host (may be NULL): the device time of the pick.

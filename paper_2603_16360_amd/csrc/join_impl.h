@@ -605,7 +605,7 @@ __device__ __forceinline__ int lds_load(const int *p) { return __atomic_load_n(p
 // query, whose distance is needed (d1) even when it was already visited.
 // Occupancy of the cooperative kernels is bound by LDS, so a pass keeps up
 // to 16 16-byte loads per lane in flight.
-template <typename T, int DP, int W>
+template <typename T, int DP, int W, int PGC>
 __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, CoopShared<W> &sh,
                                            CoopWave &cw, const float *qf, int32_t v, bool probe,
                                            bool hyb_active, int heap_cap, int lane) {
@@ -614,7 +614,7 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
     constexpr int LPR = pick_lpr(CPR);
     constexpr int VPL = CPR / LPR;
     constexpr int RPP = 64 / LPR;
-    constexpr int LCAP = kIsBf16<T> ? 8 : 16;  // bf16: registers for the re-check path
+    constexpr int LCAP = kIsBf16<T> ? (PGC < 8 ? PGC : 8) : PGC;  // bf16: registers for the re-check
     constexpr int PG = (LCAP / VPL) < (64 / RPP) ? (LCAP / VPL) : (64 / RPP);
     const bool l2 = a.metric == VJ_L2;
     const int p = lane % LPR, rr = lane / LPR;
@@ -787,7 +787,7 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
 // Runs slot k of the processing list on the tables of m.  Returns true
 // (in every thread) when the query outgrew them: nothing was written but
 // its stats row, and the caller re-runs it on larger tables.
-template <typename T, int DP, int W>
+template <typename T, int DP, int W, int PGC>
 __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem &m,
                                                CoopShared<W> &sh, int heap_cap, int k,
                                                const int32_t *qlist, const int32_t *qpos,
@@ -883,9 +883,9 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
             if (lane == R + 1) v = pcache;
         } else {
             const int32_t sv = lane == 0 ? a.entry : lane == 1 ? pcache : -1;
-            coop_batch<T, DP, W>(a, m, sh, cw, qf, sv, false, false, heap_cap, lane);
+            coop_batch<T, DP, W, PGC>(a, m, sh, cw, qf, sv, false, false, heap_cap, lane);
         }
-        coop_batch<T, DP, W>(a, m, sh, cw, qf, v, a.hyb == VJ_HYB_ADAPT && lane < R, false,
+        coop_batch<T, DP, W, PGC>(a, m, sh, cw, qf, v, a.hyb == VJ_HYB_ADAPT && lane < R, false,
                              heap_cap, lane);
         bool hyb = false;
         if (a.hyb == VJ_HYB_FORCE) {
@@ -921,7 +921,7 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
     }
     for (int t = wib * 64; t < pcnt && t < a.nx + 64; t += 64 * W) {
         const int32_t u = t + lane < pcnt ? a.out_x[pseg + t + lane] : -1;
-        coop_batch<T, DP, W>(a, m, sh, cw, qf, u, false, false, heap_cap, lane);
+        coop_batch<T, DP, W, PGC>(a, m, sh, cw, qf, u, false, false, heap_cap, lane);
     }
     __syncthreads();
     const bool hyb = sh.hyb != 0;
@@ -982,7 +982,7 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
             }
             if (nmine > 0) {
                 nexp += nmine;
-                coop_batch<T, DP, W>(a, m, sh, cw, qf, v, false, hyb_active, heap_cap, lane);
+                coop_batch<T, DP, W, PGC>(a, m, sh, cw, qf, v, false, hyb_active, heap_cap, lane);
             }
             head += take;
             continue;
@@ -1017,7 +1017,7 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
                 if (lane == 0) { atomicOr(a.err, 32); atomicOr(&sh.abort, 1); }
             } else {
                 const int32_t v = lane < R ? a.adj[(size_t)bid * R + lane] : -1;
-                coop_batch<T, DP, W>(a, m, sh, cw, qf, v, false, hyb_active, heap_cap, lane);
+                coop_batch<T, DP, W, PGC>(a, m, sh, cw, qf, v, false, hyb_active, heap_cap, lane);
             }
         }
     }
@@ -1103,8 +1103,8 @@ __device__ __forceinline__ void use_global(WaveMem &m, const GlobalTables &g, si
 // and LIST in-range entries in LDS.  A query that outgrows them takes a free
 // region of global tables (if any is left) and runs again in this launch;
 // otherwise, or if it outgrows those too, its slot goes to the overflow list.
-template <typename T, int DP, bool HYB, int HL, int LIST, int W>
-__global__ void __launch_bounds__(64 * W)
+template <typename T, int DP, bool HYB, int HL, int LIST, int W, int PGC, int MINW>
+__global__ void __launch_bounds__(64 * W, MINW)
 k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos, int k0,
             int k1, GlobalTables g, int32_t *ovf, int32_t *ovf_count) {
     constexpr int HC = HYB ? kBeamMax + 64 * W : 1;
@@ -1133,21 +1133,21 @@ k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t
     m.hi = sh_hi;
     m.aux = sh_aux[kIsBf16<T> ? threadIdx.x >> 6 : 0];
     m.auxf = sh_auxf[kIsBf16<T> ? threadIdx.x >> 6 : 0];
-    if (!run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, 1)) return;
+    if (!run_query_coop<T, DP, W, PGC>(a, m, sh, HC, k, qlist, qpos, 1)) return;
     if (threadIdx.x == 0) sh_region = g.cap > 0 ? atomicAdd(g.next, 1) : 0;
     __syncthreads();
     const int r = sh_region;
     bool again = true;
     if (r < g.cap) {
         use_global(m, g, (size_t)r);
-        again = run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, 1 | 8);
+        again = run_query_coop<T, DP, W, PGC>(a, m, sh, HC, k, qlist, qpos, 1 | 8);
     }
     if (again && threadIdx.x == 0) ovf[atomicAdd(ovf_count, 1)] = k;
 }
 
 // cooperative tier on global tables: one query per workgroup of W waves,
 // its tables in region (block index) of g; a re-run launch of the host
-template <typename T, int DP, bool HYB, int W>
+template <typename T, int DP, bool HYB, int W, int PGC>
 __global__ void __launch_bounds__(64 * W)
 k_join_coop_global(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos,
                    int k0, int k1, GlobalTables g, int32_t *ovf, int32_t *ovf_count) {
@@ -1168,7 +1168,7 @@ k_join_coop_global(const JoinArgs *__restrict__ pa, const int32_t *qlist, const 
     m.hi = sh_hi;
     m.aux = sh_aux[kIsBf16<T> ? threadIdx.x >> 6 : 0];
     m.auxf = sh_auxf[kIsBf16<T> ? threadIdx.x >> 6 : 0];
-    if (run_query_coop<T, DP, W>(a, m, sh, HC, k, qlist, qpos, 1 | 8 | 16) && threadIdx.x == 0)
+    if (run_query_coop<T, DP, W, PGC>(a, m, sh, HC, k, qlist, qpos, 1 | 8 | 16) && threadIdx.x == 0)
         ovf[atomicAdd(ovf_count, 1)] = k;
 }
 
@@ -1192,12 +1192,20 @@ void launch_tier(const JoinLaunch &L, hipStream_t s) {
         g.il_cap = L.il_cap;
         g.next = L.promo_next;
         g.cap = L.promo_cap;
-        if (L.tier == 1)
-            hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 13, 1536, kWaves>), dim3((unsigned)L.count),
-                               dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, g, L.ovf,
-                               L.ovf_count);
+        // workgroup tier: large LDS tables (8,192 slots, 1,536 pairs; three
+        // workgroups per CU) or small ones (4,096 slots, 1,024 pairs; four
+        // workgroups per CU, registers capped for four waves per SIMD up to
+        // 256-wide rows)
+        if (L.tier == 1 && L.coop_small)
+            hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 12, 1024, kWaves, 12, (DP <= 256 ? 4 : 1)>),
+                               dim3((unsigned)L.count), dim3(64 * kWaves), 0, s, L.args, L.qlist,
+                               L.qpos, k0, k1, g, L.ovf, L.ovf_count);
+        else if (L.tier == 1)
+            hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 13, 1536, kWaves, 16, 1>),
+                               dim3((unsigned)L.count), dim3(64 * kWaves), 0, s, L.args, L.qlist,
+                               L.qpos, k0, k1, g, L.ovf, L.ovf_count);
         else
-            hipLaunchKernelGGL((k_join_coop_global<T, DP, HYB, kWaves>), dim3((unsigned)L.count),
+            hipLaunchKernelGGL((k_join_coop_global<T, DP, HYB, kWaves, 16>), dim3((unsigned)L.count),
                                dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, g, L.ovf,
                                L.ovf_count);
     }

@@ -120,6 +120,28 @@ __global__ void k_depth_keys(const int32_t *depth, int64_t nq, const int32_t *id
     pos[i] = (int32_t)i;
 }
 
+// key of query q: the bits of d1 = mean length of its edges to data nodes
+// (the stored edge lengths; +inf without data neighbours, all ones for an
+// invalid id), so that an ascending sort puts dense neighbourhoods first
+__global__ void k_density_keys(const int32_t *adj, const float *elen, int R, int64_t nx,
+                               int64_t nq, const int32_t *ids, int64_t n, uint32_t *keys,
+                               int32_t *pos) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t q = ids ? ids[i] : (int32_t)i;
+    pos[i] = (int32_t)i;
+    if (q < 0 || q >= nq) { keys[i] = 0xffffffffu; return; }
+    const int64_t u = nx + q;
+    float sum = 0.f;
+    int c = 0;
+    for (int j = 0; j < R; ++j) {
+        const int32_t y = adj[u * R + j];
+        if (y >= 0 && y < nx) { sum += elen[u * R + j]; ++c; }
+    }
+    const float d1 = c ? sum / (float)c : INFINITY;
+    keys[i] = __float_as_uint(d1);  // non-negative floats order as their bits
+}
+
 __global__ void k_gather_ids(const int32_t *ids, const int32_t *pos, int64_t n, int32_t *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -232,6 +254,25 @@ void order_by_depth(const int32_t *depth, int64_t nq, const int32_t *ids, int64_
                                      pos.as<int32_t>(), qpos, (size_t)n, 0, 31, s));
     hipLaunchKernelGGL(k_gather_ids, dim3(grid1(n)), dim3(256), 0, s, ids, qpos, n, qlist);
     VJ_HIP(hipStreamSynchronize(s));  // the temporaries above are freed on return
+}
+
+void order_by_density(const int32_t *adj, const float *elen, int R, int64_t nx, int64_t nq,
+                      const int32_t *ids, int64_t n, int32_t *qlist, int32_t *qpos, DevBuf &keys,
+                      DevBuf &keys2, DevBuf &pos, DevBuf &tmp, hipStream_t s) {
+    if (n == 0) return;
+    keys.reserve(n * sizeof(uint32_t));
+    keys2.reserve(n * sizeof(uint32_t));
+    pos.reserve(n * sizeof(int32_t));
+    hipLaunchKernelGGL(k_density_keys, dim3(grid1(n)), dim3(256), 0, s, adj, elen, R, nx, nq, ids, n,
+                       keys.as<uint32_t>(), pos.as<int32_t>());
+    size_t bytes = 0;
+    VJ_HIP(rocprim::radix_sort_pairs(nullptr, bytes, keys.as<uint32_t>(), keys2.as<uint32_t>(),
+                                     pos.as<int32_t>(), qpos, (size_t)n, 0, 32, s));
+    tmp.reserve(bytes);
+    VJ_HIP(rocprim::radix_sort_pairs(tmp.p, bytes, keys.as<uint32_t>(), keys2.as<uint32_t>(),
+                                     pos.as<int32_t>(), qpos, (size_t)n, 0, 32, s));
+    hipLaunchKernelGGL(k_gather_ids, dim3(grid1(n)), dim3(256), 0, s, ids, qpos, n, qlist);
+    VJ_HIP(hipGetLastError());
 }
 
 void export_pairs(const Pairs &r, int32_t *qx, float *dist, bool sorted, hipStream_t s) {

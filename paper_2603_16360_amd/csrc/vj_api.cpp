@@ -210,14 +210,23 @@ struct Order {
     std::vector<int64_t> level_start;  // boundaries of the launches, last = n
 };
 
-static void make_order(Index &ix, const int32_t *ids, int64_t n, int ws, hipStream_t s, Order &o) {
+static void make_order(Index &ix, const int32_t *ids, int64_t n, int ws, bool dense_first,
+                       hipStream_t s, Order &o) {
     o.qlist.reserve(n * sizeof(int32_t));
     o.qpos.reserve(n * sizeof(int32_t));
     o.level_start.clear();
     if (ws == VJ_WS_SELF) {
-        if (ids) VJ_HIP(hipMemcpyAsync(o.qlist.p, ids, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        else iota_i32(o.qlist.as<int32_t>(), n, s);
-        iota_i32(o.qpos.as<int32_t>(), n, s);
+        // queries are independent: any order gives the same result
+        if (dense_first) {
+            JoinWorkspace &jw = ix.jw;
+            order_by_density(ix.adj.as<int32_t>(), ix.elen.as<float>(), ix.R, ix.nx, ix.nq, ids, n,
+                             o.qlist.as<int32_t>(), o.qpos.as<int32_t>(), jw.sort_keys,
+                             jw.sort_keys2, jw.sort_pos, jw.sort_tmp, s);
+        } else {
+            if (ids) VJ_HIP(hipMemcpyAsync(o.qlist.p, ids, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+            else iota_i32(o.qlist.as<int32_t>(), n, s);
+            iota_i32(o.qpos.as<int32_t>(), n, s);
+        }
         o.level_start = {0, n};
         return;
     }
@@ -254,7 +263,7 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
 
     JoinWorkspace &jw = ix.jw;
     Order ord{jw.qlist, jw.qpos, {}};
-    make_order(ix, ids, n, ws, s, ord);
+    make_order(ix, ids, n, ws, p.dense_first != 0, s, ord);
     const int32_t *qlist = ord.qlist.as<int32_t>(), *qpos = ord.qpos.as<int32_t>();
 
     // counters: [0..1] out_count (u64), [2] ovf_count, [3] err, [4] global regions taken,
@@ -336,6 +345,7 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
             L.dp = ix.dp;
             L.prec = prec;
             L.tier = std::min(tier, 2);
+            L.coop_small = p.coop_tables == 1;
             L.hyb = beam > 0;
             L.ovf = ovf.as<int32_t>();
             L.ovf_count = ctr + 2;
@@ -345,25 +355,33 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
             // index; tier 3 tables are as large as the data set
             const int hl2 = std::min(16, ceil_log2(2 * ix.nx));
             const int ilc2 = (int)std::min<int64_t>(ix.nx, 1 << 15);
-            auto global_regions = [&](int64_t regions) {
-                ix.ws_gh.reserve((size_t)regions * ((size_t)1 << hl2) * sizeof(int32_t));
-                ix.ws_gil.reserve((size_t)regions * ilc2 * sizeof(int32_t));
-                ix.ws_gild.reserve((size_t)regions * ilc2 * sizeof(float));
+            auto global_regions = [&](int64_t regions, int hl, int ilc) {
+                ix.ws_gh.reserve((size_t)regions * ((size_t)1 << hl) * sizeof(int32_t));
+                ix.ws_gil.reserve((size_t)regions * ilc * sizeof(int32_t));
+                ix.ws_gild.reserve((size_t)regions * ilc * sizeof(float));
                 L.gh = ix.ws_gh.as<int32_t>();
                 L.gil = ix.ws_gil.as<int32_t>();
                 L.gild = ix.ws_gild.as<float>();
-                L.hash_log2 = hl2;
-                L.il_cap = ilc2;
+                L.hash_log2 = hl;
+                L.il_cap = ilc;
             };
             if (tier == 1) {
-                // regions a query that outgrows LDS may take within the launch
-                L.promo_cap = (int)std::min<int64_t>(1024, std::max<int64_t>(64, cnt / 16));
-                global_regions(L.promo_cap);
+                // regions a query that outgrows LDS may take within the launch;
+                // the small LDS tables overflow more often, so they get more
+                // (and smaller: 2^15 slots, 16,384 pairs) regions
+                if (L.coop_small) {
+                    L.promo_cap = (int)std::min<int64_t>(4096, std::max<int64_t>(64, cnt / 16));
+                    global_regions(L.promo_cap, std::min(15, ceil_log2(2 * ix.nx)),
+                                   (int)std::min<int64_t>(ix.nx, 1 << 14));
+                } else {
+                    L.promo_cap = (int)std::min<int64_t>(1024, std::max<int64_t>(64, cnt / 16));
+                    global_regions(L.promo_cap, hl2, ilc2);
+                }
                 L.promo_next = ctr + 4;
                 VJ_HIP(hipMemsetAsync(ctr + 4, 0, sizeof(int32_t), s));
             } else if (tier == 2) {
                 chunk = 1024;
-                global_regions(std::min(chunk, cnt));
+                global_regions(std::min(chunk, cnt), hl2, ilc2);
             } else if (tier == 3) {
                 L.hash_log2 = ceil_log2(2 * ix.nx);
                 L.il_cap = (int)ix.nx;
@@ -558,7 +576,8 @@ void vj_default_join_params(vj_join_params *p) {
     p->precision = VJ_PREC_FP32;
     p->budget = nullptr;
     p->start_tier = 1;
-    p->waves_per_cu = 0;
+    p->coop_tables = 0;
+    p->dense_first = 1;
     p->pair_capacity = 0;
 }
 
@@ -676,6 +695,7 @@ vj_status vj_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
     VJ_CHECK(p.work_sharing == VJ_WS_SELF || ix.has_mst, VJ_ERR_INVALID_ARG, "work sharing needs the MST");
     VJ_CHECK(p.hybrid != VJ_HYB_BUDGET || p.budget != nullptr, VJ_ERR_INVALID_ARG, "budget mode needs budget[]");
     VJ_CHECK(p.start_tier >= 0 && p.start_tier <= 2, VJ_ERR_INVALID_ARG, "start_tier in [0, 2]");
+    VJ_CHECK(p.coop_tables == 0 || p.coop_tables == 1, VJ_ERR_INVALID_ARG, "coop_tables is 0 or 1");
     VJ_CHECK(p.hybrid != VJ_HYB_LEARNED || ix.pred != nullptr, VJ_ERR_INVALID_ARG,
              "learned routing needs an attached predictor");
     hipStream_t s = (hipStream_t)stream;
@@ -829,14 +849,18 @@ vj_status vj_autotune_join(vj_index *idx, const int32_t *query_ids, int64_t n, f
     // data is exactly u8) u8 rows -- all of them give the same decisions
     std::vector<vj_join_params> cand;
     for (int tier : {0, 1}) {
-        for (int prec : {(int)VJ_PREC_FP32, (int)VJ_PREC_U8}) {
-            if (prec == VJ_PREC_U8 && !ix.integer_u8) continue;
-            if (base.precision != VJ_PREC_FP32 && base.precision != VJ_PREC_U8 &&
-                base.precision != VJ_PREC_AUTO) prec = base.precision;
-            vj_join_params c = base;
-            c.start_tier = tier;
-            c.precision = prec;
-            cand.push_back(c);
+        for (int tables : {0, 1}) {
+            if (tier == 0 && tables == 1) continue;
+            for (int prec : {(int)VJ_PREC_FP32, (int)VJ_PREC_U8}) {
+                if (prec == VJ_PREC_U8 && !ix.integer_u8) continue;
+                if (base.precision != VJ_PREC_FP32 && base.precision != VJ_PREC_U8 &&
+                    base.precision != VJ_PREC_AUTO) prec = base.precision;
+                vj_join_params c = base;
+                c.start_tier = tier;
+                c.coop_tables = tables;
+                c.precision = prec;
+                cand.push_back(c);
+            }
         }
     }
     float best = INFINITY;

@@ -69,6 +69,7 @@ int padded_dim(int d);
 // Buffers of vj_join kept between calls on one index (grow only).
 struct JoinWorkspace {
     DevBuf qlist, qpos, counters, args, ovf, slots, out_q, out_x, out_d;
+    DevBuf sort_keys, sort_keys2, sort_pos, sort_tmp;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     JoinWorkspace() = default;
     JoinWorkspace(const JoinWorkspace &) = delete;
@@ -160,6 +161,7 @@ struct JoinLaunch {
     const int32_t *qpos;      // caller position per processing slot
     int first, count, dp, prec;  // slots [first, first + count) of qlist
     int tier;                    // 0 one wave + LDS, 1 workgroup + LDS, 2 workgroup + global
+    bool coop_small;             // tier 1: the small LDS tables
     bool hyb;
     int32_t *gh;              // global tables: [regions][1 << hash_log2] visited sets
     int hash_log2;

@@ -47,7 +47,8 @@ class vj_join_params(C.Structure):
                 ("hybrid_beam", C.c_int32), ("conv_threshold", C.c_int32),
                 ("ood_ratio", C.c_float), ("precision", C.c_int32),
                 ("budget", C.c_void_p), ("start_tier", C.c_int32),
-                ("waves_per_cu", C.c_int32), ("pair_capacity", C.c_int64)]
+                ("coop_tables", C.c_int32), ("pair_capacity", C.c_int64),
+                ("dense_first", C.c_int32)]
 
 
 _vp, _i64, _i32, _f32 = C.c_void_p, C.c_int64, C.c_int32, C.c_float
@@ -203,8 +204,8 @@ class Index:
 # ---------------------------------------------------------------- functions --
 
 def join_params(work_sharing="self", hybrid="off", hybrid_beam=256, conv_threshold=10,
-                ood_ratio=1.5, precision="fp32", budget=None, start_tier=1, waves_per_cu=0,
-                pair_capacity=0):
+                ood_ratio=1.5, precision="fp32", budget=None, start_tier=1, coop_tables=0,
+                pair_capacity=0, dense_first=1):
     p = vj_join_params()
     _lib.vj_default_join_params(C.byref(p))
     p.work_sharing = WORK_SHARING[work_sharing]
@@ -215,8 +216,9 @@ def join_params(work_sharing="self", hybrid="off", hybrid_beam=256, conv_thresho
     p.precision = PRECISION[precision]
     p.budget = budget.data_ptr() if budget is not None else None
     p.start_tier = start_tier
-    p.waves_per_cu = waves_per_cu
+    p.coop_tables = coop_tables
     p.pair_capacity = pair_capacity
+    p.dense_first = dense_first
     return p
 
 

@@ -167,10 +167,33 @@ def test_tier_overflow_to_global_tables(tiny):
     assert (on_global & ~rerun).sum() == 64 and rerun.sum() > 0
 
 
+def test_tier_overflow_small_tables(tiny):
+    # the small workgroup tables (4,096 slots, 1,024 pairs) overflow earlier
+    eps = tiny.eps * 2.2
+    res = vj.vj_join(tiny.idx, eps, coop_tables=1)
+    st = res.stats().cpu().numpy()
+    ref = oracle.join(tiny.w.Q, tiny.w.X, tiny.g.adj, tiny.g.entry, eps, uncertain="out")
+    refu = oracle.join(tiny.w.Q, tiny.w.X, tiny.g.adj, tiny.g.entry, eps, uncertain="in")
+    assert ref.pairs() <= qx_set(_gpu_pairs(res)[0]) <= refu.pairs()
+    assert ((st[:, 7] & 8) > 0).sum() > 0
+
+
 def test_tier_overflow_chain(tiny):
     # the same from the one-wave tier: every query re-runs, some twice
     st = _overflow_case(tiny, 2.6, 0)
     assert np.all(st[:, 7] & 1) and 0 < ((st[:, 7] & 8) > 0).sum() < len(st)
+
+
+def test_launch_order_keeps_results(tiny):
+    # dense-first launch order (default) and the given order: same pairs and
+    # the same per-query counters, by caller position, incl. a subset
+    ids = torch.from_numpy(np.random.default_rng(8).permutation(1000)[:600].astype(np.int32)).cuda()
+    for q in (None, ids):
+        a = vj.vj_join(tiny.idx, tiny.eps * 1.5, query_ids=q, dense_first=1)
+        b = vj.vj_join(tiny.idx, tiny.eps * 1.5, query_ids=q, dense_first=0)
+        assert qx_set(_gpu_pairs(a)[0]) == qx_set(_gpu_pairs(b)[0])
+        sa, sb = a.stats().cpu().numpy(), b.stats().cpu().numpy()
+        assert np.array_equal(sa[:, :7], sb[:, :7])
 
 
 def test_small_result_capacity_regrows(tiny):
@@ -204,12 +227,13 @@ def test_invalid_arguments(tiny):
     assert e.value.status == 1
 
 
-def _mode_parity(case, start_tier=1, **kw):
+def _mode_parity(case, start_tier=1, coop_tables=0, **kw):
     w = case.w
     par = case.parent if kw.get("work_sharing", "self") != "self" else None
     ref = oracle.join(w.Q, w.X, case.g.adj, case.g.entry, case.eps, metric=w.metric,
                       parent=par, **kw)
-    res = vj.vj_join(case.idx, case.eps, metric=w.metric, start_tier=start_tier, **kw)
+    res = vj.vj_join(case.idx, case.eps, metric=w.metric, start_tier=start_tier,
+                     coop_tables=coop_tables, **kw)
     qx, _ = _gpu_pairs(res)
     got, want = _by_query(qx), _by_query(zip(ref.qi, ref.xj))
     fragile = ref.stats[:, 7].astype(bool)
@@ -242,7 +266,8 @@ def test_modes_match_oracle(tiny, kw):
         assert np.array_equal(st[ok, 4], ref.stats[ok, 4])
 
 
-@pytest.mark.parametrize("start_tier", [0, 2])
+@pytest.mark.parametrize("start_tier,coop_tables", [(0, 0), (2, 0), (1, 1)],
+                         ids=["one-wave", "global", "small-lds"])
 @pytest.mark.parametrize("kw", [
     {},
     {"hybrid": "force"},
@@ -251,12 +276,12 @@ def test_modes_match_oracle(tiny, kw):
     {"work_sharing": "soft", "hybrid": "force"},
     {"work_sharing": "hard"},
 ], ids=lambda k: "-".join(f"{a}={b}" for a, b in k.items()) or "bfs")
-def test_other_tiers_match_oracle(tiny, kw, start_tier):
-    # every query starts on the one-wave tier (0) or on the global-table
-    # tier (2) instead of the default workgroup tier (1); per-query results
-    # and counters as with the default
-    _say(f"vj_join tiny start_tier={start_tier} {kw}")
-    res, ref = _mode_parity(tiny, start_tier=start_tier, **kw)
+def test_other_tiers_match_oracle(tiny, kw, start_tier, coop_tables):
+    # every query starts on the one-wave tier (0), on the global-table tier
+    # (2), or on the workgroup tier with its small LDS tables, instead of the
+    # default; per-query results and counters as with the default
+    _say(f"vj_join tiny start_tier={start_tier} coop_tables={coop_tables} {kw}")
+    res, ref = _mode_parity(tiny, start_tier=start_tier, coop_tables=coop_tables, **kw)
     st = res.stats().cpu().numpy()
     if start_tier == 2:
         assert np.all(st[:, 7] & 8)
