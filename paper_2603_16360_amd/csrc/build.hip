@@ -31,23 +31,30 @@ using brow::kKnnCap;
 using brow::g1b;
 
 // ------------------------------------------------------------------ kNN --
-// A wave owns 16 rows and sweeps all N rows as columns, 128 per step.  Each
-// row keeps a buffer [K best | pending] in global memory; an element enters
-// the buffer when its key (|x|^2 - 2<u,x>, same order as |u-x|^2) is <= the
-// row's current K-th key.  After a step, rows with > K + 128 entries are
-// sorted and cut back to K.
+// A workgroup of 4 waves owns 64 rows (16 per wave) and sweeps all N rows as
+// columns, 128 per step.  Each step's column tile is staged once in LDS (in
+// chunks of 128 dimensions, rows padded by 16 bytes) and read by all four
+// waves; each wave's rows come from global memory (cached).  Each row keeps
+// a buffer [K best | pending] in global memory; an element enters the buffer
+// when its key (|x|^2 - 2<u,x>, same order as |u-x|^2) is <= the row's
+// current K-th key.  After a step, rows with > K + 128 entries are sorted
+// and cut back to K.
+constexpr int kKc = 128;          // dimensions per staged chunk
+constexpr int kLdsRow = kKc + 8;  // bf16 per staged row
+
 template <int NSPLIT>
 __global__ void __launch_bounds__(256)
 k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2, int K,
       float *bkey, int32_t *bid) {
     __shared__ float s_tau[4][16];
     __shared__ int s_cnt[4][16];
+    __shared__ __attribute__((aligned(16))) uint16_t sb_hi[128 * kLdsRow];
+    __shared__ __attribute__((aligned(16))) uint16_t sb_lo[NSPLIT == 3 ? 128 * kLdsRow : 8];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t r0 = (int64_t)blockIdx.x * 64 + w * 16;
     if (lane < 16) { s_tau[w][lane] = INFINITY; s_cnt[w][lane] = 0; }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     __builtin_amdgcn_wave_barrier();
-
     auto merge_row = [&](int r) {
         const int64_t row = r0 + r;
         const int c = min(s_cnt[w][r], kKnnCap);
@@ -84,9 +91,48 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
         __builtin_amdgcn_wave_barrier();
     };
 
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
     for (int64_t c0 = 0; c0 < N; c0 += 128) {
         floatx4 acc[8];
-        mt::tile_16x128<NSPLIT>(Ah, Al, r0, N, Ah, Al, c0, N, Kp, lane, acc);
+#pragma unroll
+        for (int ct = 0; ct < 8; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int kc0 = 0; kc0 < Kp; kc0 += kKc) {
+            const int kw = min(kKc, Kp - kc0);  // a multiple of 32
+            const int cpr = kw / 8;             // 16-byte chunks per staged row
+            __syncthreads();                    // the previous chunk is consumed
+            for (int e = threadIdx.x; e < 128 * cpr; e += 256) {
+                const int rr = e / cpr, ch = e - rr * cpr;
+                const int64_t col = c0 + rr;
+                uint4 vh = make_uint4(0, 0, 0, 0), vl = make_uint4(0, 0, 0, 0);
+                if (col < N) {
+                    vh = *reinterpret_cast<const uint4 *>(Ah + col * Kp + kc0 + ch * 8);
+                    if (NSPLIT == 3) vl = *reinterpret_cast<const uint4 *>(Al + col * Kp + kc0 + ch * 8);
+                }
+                *reinterpret_cast<uint4 *>(sb_hi + rr * kLdsRow + ch * 8) = vh;
+                if (NSPLIT == 3) *reinterpret_cast<uint4 *>(sb_lo + rr * kLdsRow + ch * 8) = vl;
+            }
+            __syncthreads();
+            for (int k0 = 0; k0 < kw; k0 += 32) {
+                const mt::bf16x8 a = mt::load8(Ah, r0 + r16, N, Kp, kc0 + k0 + kq);
+                mt::bf16x8 b[8];
+#pragma unroll
+                for (int ct = 0; ct < 8; ++ct)
+                    b[ct] = *reinterpret_cast<const mt::bf16x8 *>(sb_hi + (ct * 16 + r16) * kLdsRow + k0 + kq);
+#pragma unroll
+                for (int ct = 0; ct < 8; ++ct)
+                    acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[ct], acc[ct], 0, 0, 0);
+                if (NSPLIT == 3) {
+                    const mt::bf16x8 al = mt::load8(Al, r0 + r16, N, Kp, kc0 + k0 + kq);
+#pragma unroll
+                    for (int ct = 0; ct < 8; ++ct) {
+                        const mt::bf16x8 bl = *reinterpret_cast<const mt::bf16x8 *>(
+                            sb_lo + (ct * 16 + r16) * kLdsRow + k0 + kq);
+                        acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[ct], 0, 0, 0);
+                        acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b[ct], acc[ct], 0, 0, 0);
+                    }
+                }
+            }
+        }
 #pragma unroll
         for (int ct = 0; ct < 8; ++ct)
 #pragma unroll

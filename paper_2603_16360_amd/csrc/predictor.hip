@@ -17,7 +17,7 @@
 namespace vj {
 namespace {
 
-inline unsigned g1(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+inline unsigned g1p(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // ------------------------------------------------------------- features --
 // One wave per query.  Distances in the join metric (L2: |q - y|; IP:
@@ -150,7 +150,7 @@ template <bool TA, bool TB>
 void gemm(int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, int ldc,
           const float *bias, bool relu, const float *mask, int ldm, hipStream_t s) {
     if (M <= 0 || N <= 0) return;
-    hipLaunchKernelGGL((k_gemm<TA, TB>), dim3(g1(N, 64), g1(M, 64)), dim3(256), 0, s, M, N, K, A,
+    hipLaunchKernelGGL((k_gemm<TA, TB>), dim3(g1p(N, 64), g1p(M, 64)), dim3(256), 0, s, M, N, K, A,
                        lda, B, ldb, C, ldc, bias, relu ? 1 : 0, mask, ldm);
 }
 
@@ -272,7 +272,7 @@ void forward_acts(const Predictor &p, const float *X, int64_t n, Acts &t, hipStr
     t.a1.reserve((size_t)n * p.h1 * sizeof(float));
     t.a2.reserve((size_t)n * p.h2 * sizeof(float));
     t.z3.reserve((size_t)n * p.k * sizeof(float));
-    hipLaunchKernelGGL(k_normalize, dim3(g1(n * p.din, 256)), dim3(256), 0, s, X, n, p.din,
+    hipLaunchKernelGGL(k_normalize, dim3(g1p(n * p.din, 256)), dim3(256), 0, s, X, n, p.din,
                        p.mu.as<float>(), p.inv_sigma.as<float>(), t.xn.as<float>());
     gemm<false, true>((int)n, p.h1, p.din, t.xn.as<float>(), p.din, p.W1.as<float>(), p.din,
                       t.a1.as<float>(), p.h1, p.b1.as<float>(), true, nullptr, 0, s);
@@ -292,7 +292,7 @@ double backward(const Predictor &p, const float *X, const float *Y, const float 
     DevBuf &aux = t.aux;
     VJ_HIP(hipMemsetAsync(aux.p, 0, 16, s));
     if (mask) {
-        hipLaunchKernelGGL(k_mask_count, dim3(g1(tot, 256)), dim3(256), 0, s, mask, tot,
+        hipLaunchKernelGGL(k_mask_count, dim3(g1p(tot, 256)), dim3(256), 0, s, mask, tot,
                            aux.as<unsigned long long>() + 1);
         unsigned long long c = 0;
         VJ_HIP(hipMemcpyAsync(&c, aux.as<unsigned long long>() + 1, 8, hipMemcpyDeviceToHost, s));
@@ -303,7 +303,7 @@ double backward(const Predictor &p, const float *X, const float *Y, const float 
     t.g2.reserve((size_t)n * p.h2 * sizeof(float));
     t.g1.reserve((size_t)n * p.h1 * sizeof(float));
     DevBuf &g3 = t.g3, &g2 = t.g2, &g1b = t.g1;
-    hipLaunchKernelGGL(k_bce, dim3(g1(tot, 256)), dim3(256), 0, s, t.z3.as<float>(), Y, mask, tot,
+    hipLaunchKernelGGL(k_bce, dim3(g1p(tot, 256)), dim3(256), 0, s, t.z3.as<float>(), Y, mask, tot,
                        (float)(1.0 / cnt), g3.as<float>(), aux.as<double>());
     float *gW1 = g, *gb1 = gW1 + (size_t)p.h1 * p.din, *gW2 = gb1 + p.h1,
           *gb2 = gW2 + (size_t)p.h2 * p.h1, *gW3 = gb2 + p.h2, *gb3 = gW3 + (size_t)p.k * p.h2;
@@ -337,7 +337,7 @@ void compute_features(const Index &ix, const int32_t *qlist, int64_t n, float ep
                       float *out, hipStream_t s) {
     (void)ld;
     if (n == 0) return;
-    hipLaunchKernelGGL(k_features, dim3(g1(n, 4)), dim3(256), 0, s, ix.vec.as<float>(), ix.dp, ix.d,
+    hipLaunchKernelGGL(k_features, dim3(g1p(n, 4)), dim3(256), 0, s, ix.vec.as<float>(), ix.dp, ix.d,
                        ix.nx, ix.adj.as<int32_t>(), ix.elen.as<float>(), ix.R, ix.entry,
                        (int)ix.metric, eps, qlist, n, out);
     VJ_HIP(hipGetLastError());
@@ -434,9 +434,9 @@ void predictor_train(Predictor &p, const float *X, const float *Y, int64_t n, in
         for (int64_t r0 = 0; r0 < n; r0 += batch) {
             const int nb = (int)std::min<int64_t>(batch, n - r0);
             VJ_HIP(hipMemcpyAsync(idx.p, perm.data() + r0, nb * sizeof(int32_t), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_gather_rows, dim3(g1((int64_t)nb * p.din, 256)), dim3(256), 0, s, X,
+            hipLaunchKernelGGL(k_gather_rows, dim3(g1p((int64_t)nb * p.din, 256)), dim3(256), 0, s, X,
                                p.din, idx.as<int32_t>(), (int64_t)nb, xb.as<float>());
-            hipLaunchKernelGGL(k_gather_rows, dim3(g1((int64_t)nb * p.k, 256)), dim3(256), 0, s, Y,
+            hipLaunchKernelGGL(k_gather_rows, dim3(g1p((int64_t)nb * p.k, 256)), dim3(256), 0, s, Y,
                                p.k, idx.as<int32_t>(), (int64_t)nb, yb.as<float>());
             const double loss = backward(p, xb.as<float>(), yb.as<float>(), nullptr, nb, t,
                                          g.as<float>(), s);
@@ -448,7 +448,7 @@ void predictor_train(Predictor &p, const float *X, const float *Y, int64_t n, in
             size_t off = 0;
             for (int i = 0; i < 6; ++i) {
                 const int64_t len = (int64_t)(par[i]->bytes / sizeof(float));
-                hipLaunchKernelGGL(k_adam, dim3(g1(len, 256)), dim3(256), 0, s, par[i]->as<float>(),
+                hipLaunchKernelGGL(k_adam, dim3(g1p(len, 256)), dim3(256), 0, s, par[i]->as<float>(),
                                    g.as<float>() + off, p.m.as<float>() + off, p.v.as<float>() + off,
                                    len, lr, b1, b2, c1, c2);
                 off += (size_t)len;
@@ -463,7 +463,7 @@ void predictor_train(Predictor &p, const float *X, const float *Y, int64_t n, in
 void select_budgets(const float *logits, int64_t n, int k, const int32_t *budgets_dev,
                     float target, int32_t *budget, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_select, dim3(g1(n, 256)), dim3(256), 0, s, logits, n, k, budgets_dev,
+    hipLaunchKernelGGL(k_select, dim3(g1p(n, 256)), dim3(256), 0, s, logits, n, k, budgets_dev,
                        target, budget);
     VJ_HIP(hipGetLastError());
 }
@@ -471,13 +471,13 @@ void select_budgets(const float *logits, int64_t n, int k, const int32_t *budget
 void gather_rows(const float *src, int ld, const int32_t *rows, int64_t n, float *dst,
                  hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_gather_rows, dim3(g1(n * ld, 256)), dim3(256), 0, s, src, ld, rows, n, dst);
+    hipLaunchKernelGGL(k_gather_rows, dim3(g1p(n * ld, 256)), dim3(256), 0, s, src, ld, rows, n, dst);
     VJ_HIP(hipGetLastError());
 }
 
 void remap_ids(int32_t *v, int64_t n, const int32_t *list, hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_remap, dim3(g1(n, 256)), dim3(256), 0, s, v, n, list);
+    hipLaunchKernelGGL(k_remap, dim3(g1p(n, 256)), dim3(256), 0, s, v, n, list);
     VJ_HIP(hipGetLastError());
 }
 
