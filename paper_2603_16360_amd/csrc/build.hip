@@ -217,20 +217,47 @@ __global__ void k_first_unseen(const int *seen, int64_t N, int *first) {
 }
 
 // nearest reached node to w: overall and among nodes with a free slot;
-// results packed as (float bits << 32 | id) so atomicMin gives (d2, id) order
-__global__ void k_nearest_reached(const float *vec, int64_t N, int dp, int32_t w, const int *seen,
-                                  const int32_t *adj, int R, unsigned long long *best_any,
-                                  unsigned long long *best_free) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= N || !seen[p]) return;
+// results packed as (float bits << 32 | id) so atomicMin gives (d2, id) order.
+// 8 lanes per node (16-byte loads), 8 nodes per wave, one atomic per wave.
+__device__ __forceinline__ unsigned long long min_u64(unsigned long long a, unsigned long long b) {
+    return a < b ? a : b;
+}
+
+__global__ void __launch_bounds__(256)
+k_nearest_reached(const float *vec, int64_t N, int dp, int32_t w, const int *seen,
+                  const int32_t *adj, int R, unsigned long long *best_any,
+                  unsigned long long *best_free) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 3, p8 = lane & 7;
+    const int64_t p = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 8 + g;
+    const bool ok = p < N && seen[p];
     float acc = 0.f;
-    for (int c = 0; c < dp; ++c) {
-        const float t = vec[p * dp + c] - vec[(int64_t)w * dp + c];
-        acc = fmaf(t, t, acc);
+    if (ok) {
+        const float4 *a = reinterpret_cast<const float4 *>(vec + p * dp);
+        const float4 *b = reinterpret_cast<const float4 *>(vec + (int64_t)w * dp);
+        for (int c = p8; c < dp / 4; c += 8) {
+            const float4 x = a[c], y = b[c];
+            float t = x.x - y.x; acc = fmaf(t, t, acc);
+            t = x.y - y.y; acc = fmaf(t, t, acc);
+            t = x.z - y.z; acc = fmaf(t, t, acc);
+            t = x.w - y.w; acc = fmaf(t, t, acc);
+        }
     }
-    const unsigned long long key = ((unsigned long long)__float_as_uint(acc) << 32) | (uint32_t)p;
-    atomicMin(best_any, key);
-    if (adj[p * R + R - 1] < 0) atomicMin(best_free, key);
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    const unsigned long long key =
+        ok ? ((unsigned long long)__float_as_uint(acc) << 32) | (uint32_t)p : ~0ull;
+    const bool fr = ok && adj[p * R + R - 1] < 0;
+    unsigned long long ka = key, kf = fr ? key : ~0ull;
+#pragma unroll
+    for (int off = 8; off < 64; off <<= 1) {
+        ka = min_u64(ka, __shfl_xor(ka, off));
+        kf = min_u64(kf, __shfl_xor(kf, off));
+    }
+    if (lane == 0) {
+        if (ka != ~0ull) atomicMin(best_any, ka);
+        if (kf != ~0ull) atomicMin(best_free, kf);
+    }
 }
 
 // put w into row p (free slot, else the last = longest slot), then re-sort
@@ -413,7 +440,7 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
             unsigned long long init[2] = {~0ull, ~0ull}, got[2];
             VJ_HIP(hipMemcpyAsync(misc.as<char>() + 8, init, 16, hipMemcpyHostToDevice, s));
             unsigned long long *bests = reinterpret_cast<unsigned long long *>(misc.as<char>() + 8);
-            hipLaunchKernelGGL(k_nearest_reached, dim3(g1b(N, 256)), dim3(256), 0, s, vec, N, dp,
+            hipLaunchKernelGGL(k_nearest_reached, dim3(g1b(N, 32)), dim3(256), 0, s, vec, N, dp,
                                (int32_t)first, seenp, ix.adj.as<int32_t>(), R, bests, bests + 1);
             VJ_HIP(hipMemcpyAsync(got, bests, 16, hipMemcpyDeviceToHost, s));
             VJ_HIP(hipStreamSynchronize(s));
