@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--variants", default="fp32,u8")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration)")
+    ap.add_argument("--ood", action="store_true",
+                    help="instead of the headline: the OOD inner-product workload at 1/10 scale; "
+                         "MI-BFS, MI+Adapt, forced hybrid and learned routing compared")
     ap.add_argument("--stream", action="store_true",
                     help="instead of the headline: the batched stream workload at 1/10 scale "
                          "(200 batches, p50/p99 batch latency)")
@@ -90,6 +93,8 @@ def main():
 
     if args.stream:
         return stream_main(args, torch, workloads, vj)
+    if args.ood:
+        return ood_main(args, torch, workloads, vj)
 
     t0 = time.time()
     w = workloads.config_mid()
@@ -235,6 +240,94 @@ def main():
         "ground_truth_s": gt_s,
         "ground_truth_pairs": n_gt,
     }
+    print(json.dumps(line), flush=True)
+
+
+def ood_main(args, torch, workloads, vj):
+    """OOD queries (30 % from shifted means), inner product: the paper's MI
+    (BFS), MI+Adapt (d1/d2 rule), hybrid for every query, and the learned
+    router trained on separate training queries indexed in their own merged
+    graph (records: per-query recall of budget-mode joins against the exact
+    join)."""
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "eps.json")))["ood"]
+    scale = golden["scale"]
+    t0 = time.time()
+    w = workloads.config_ood(scale=scale)
+    wt = workloads.config_ood(scale=scale, train=True)
+    for key, arr in (("Q_sha", w.Q), ("X_sha", w.X)):
+        sha = hashlib.sha256(np.ascontiguousarray(arr).tobytes()).hexdigest()[:16]
+        if sha != golden[key]:
+            raise SystemExit(f"generated data differs from the calibrated data ({key})")
+    eps = golden["eps"]
+    nq, nt = w.Q.shape[0], wt.Q.shape[0]
+    log(f"ood: X {w.X.shape}, {nq} test and {nt} training queries, eps={eps} ({time.time() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(w.X).to(dev)
+    Qt = torch.from_numpy(w.Q).to(dev)
+    Qr = torch.from_numpy(wt.Q).to(dev)
+    idx = vj.vj_build_merged_index(Qt, X, metric="ip", R=w.R)
+    idx_tr = vj.vj_build_merged_index(Qr, X, metric="ip", R=wt.R)
+    torch.cuda.synchronize()
+    budgets = (0, 16, 64, 256)
+    # training records
+    t = time.time()
+    F = vj.vj_join_features(idx_tr, eps, metric="ip")
+    gt_tr, _ = vj.vj_bruteforce_join(Qr, X, eps, metric="ip", precision="bf16").export()
+    gtc = torch.bincount(gt_tr[:, 0].long(), minlength=nt).float()
+    Y = []
+    for b in budgets:
+        r = vj.vj_join(idx_tr, eps, metric="ip", hybrid="budget",
+                       budget=torch.full((nt,), b, dtype=torch.int32, device=dev))
+        cnt = r.stats()[:, 0].float()
+        Y.append(torch.where(gtc > 0, cnt / gtc.clamp(min=1), torch.ones_like(cnt)))
+    Y = torch.stack(Y, 1).contiguous()
+    pred = vj.Predictor(w.d + 8, 256, 256, len(budgets), seed=1)
+    pred.fit_normalization(F)
+    torch.cuda.synchronize()
+    ts = time.time()
+    losses = pred.train(F, Y, epochs=40, batch=512, lr=1e-3, seed=2)
+    torch.cuda.synchronize()
+    train_s = time.time() - ts
+    log(f"records + training: {time.time() - t:.1f}s (training {train_s:.1f}s, "
+        f"loss {losses[0]:.4f} -> {losses[-1]:.4f})")
+    target = 0.95
+    vj.vj_index_attach_predictor(idx, pred, recall_target=target, budgets=budgets)
+    gt, _ = vj.vj_bruteforce_join(Qt, X, eps, metric="ip", precision="bf16").export()
+    n_gt = int(gt.shape[0])
+    is_ood = torch.from_numpy(w.meta["is_ood"]).to(dev)
+    gt_ood = int(is_ood[gt[:, 0].long()].sum().item())
+    modes = {"MI (BFS)": {}, "MI+Adapt": {"hybrid": "adapt"}, "hybrid for all": {"hybrid": "force"},
+             "learned": {"hybrid": "learned"}}
+    out = {}
+    for name, kw in modes.items():
+        for _ in range(max(1, args.warmup)):
+            vj.vj_join(idx, eps, metric="ip", **kw)
+        torch.cuda.synchronize()
+        walls = []
+        for _ in range(args.steps):
+            t = time.perf_counter()
+            res = vj.vj_join(idx, eps, metric="ip", **kw)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t)
+        qx, _ = res.export()
+        st = res.stats().cpu().numpy()
+        found_ood = int(is_ood[qx[:, 0].long()].sum().item())
+        out[name] = {"qps": nq / float(np.mean(walls)), "ms": 1000 * float(np.mean(walls)),
+                     "recall": int(qx.shape[0]) / max(1, n_gt),
+                     # null when the exact join has no pair of an OOD query
+                     "recall_ood_queries": found_ood / gt_ood if gt_ood else None,
+                     "hybrid_queries": int(st[:, 5].sum()), "routed_exact": int(((st[:, 7] & 2) > 0).sum())}
+        log(f"{name}: {out[name]}")
+    line = {"metric": "OOD join queries/sec and recall by mode (X=200k x 768, IP)",
+            "value": out["learned"]["qps"], "unit": "queries/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "OOD at 1/10 scale: X=200,000 unit vectors d=768 (512-mean vMF "
+                                   "mixture); 20,000 test queries, 30 % from means rotated 40 deg; "
+                                   "inner product, eps for 20 mean matches; predictor trained on "
+                                   "12,500 separate queries", "recall_target": target},
+            "modes": out, "train_s": train_s, "ground_truth_pairs": n_gt,
+            "ground_truth_pairs_of_ood_queries": gt_ood}
     print(json.dumps(line), flush=True)
 
 

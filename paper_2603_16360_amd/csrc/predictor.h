@@ -9,12 +9,19 @@ namespace vj {
 
 constexpr int kFeatures = 8;  // features after the query vector
 
+// activations and backward scratch of the MLP (kept between calls)
+struct Acts {
+    DevBuf xn, a1, a2, z3;   // forward activations
+    DevBuf g3, g2, g1, aux;  // backward scratch
+};
+
 struct Predictor {
     int din = 0, h1 = 0, h2 = 0, k = 0;
     DevBuf W1, b1, W2, b2, W3, b3;  // float, row-major W[out][in]
     DevBuf mu, inv_sigma;           // float [din] input normalisation (x - mu) * inv_sigma
     DevBuf m, v;                    // Adam moments, all parameters back to back
     int64_t steps = 0;
+    mutable Acts scratch;             // calls on one predictor must not overlap
     size_t n_params() const {
         return (size_t)h1 * din + h1 + (size_t)h2 * h1 + h2 + (size_t)k * h2 + k;
     }

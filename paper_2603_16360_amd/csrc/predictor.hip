@@ -103,17 +103,23 @@ k_gemm(int M, int N, int K, const float *A, int lda, const float *B, int ldb, fl
     for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int e = t + 256 * r;  // 1024 elements of each tile
-            const int kk = e / BM, mm = e % BM;
-            const int gm = m0 + mm, gk = k0 + kk;
-            float va = 0.f;
-            if (gm < M && gk < K) va = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
-            As[kk][mm] = va;
-            const int nn = e % BN;
-            const int gn = n0 + nn;
-            float vb = 0.f;
-            if (gn < N && gk < K) vb = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
-            Bs[kk][nn] = vb;
+            // 1024 elements of each tile; consecutive threads walk the operand's
+            // contiguous dimension
+            const int e = t + 256 * r;
+            {
+                const int kk = TA ? e / BM : e % BK, mm = TA ? e % BM : e / BK;
+                const int gm = m0 + mm, gk = k0 + kk;
+                float va = 0.f;
+                if (gm < M && gk < K) va = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
+                As[kk][mm] = va;
+            }
+            {
+                const int kk = TB ? e % BK : e / BN, nn = TB ? e / BK : e % BN;
+                const int gn = n0 + nn, gk = k0 + kk;
+                float vb = 0.f;
+                if (gn < N && gk < K) vb = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
+                Bs[kk][nn] = vb;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -262,11 +268,6 @@ __global__ void k_remap(int32_t *v, int64_t n, const int32_t *list) {
     if (i < n) v[i] = list[v[i]];
 }
 
-struct Acts {
-    DevBuf xn, a1, a2, z3;  // forward activations
-    DevBuf g3, g2, g1, aux; // backward scratch
-};
-
 void forward_acts(const Predictor &p, const float *X, int64_t n, Acts &t, hipStream_t s) {
     t.xn.reserve((size_t)n * p.din * sizeof(float));
     t.a1.reserve((size_t)n * p.h1 * sizeof(float));
@@ -380,7 +381,7 @@ void predictor_init(Predictor &p, int din, int h1, int h2, int k, uint64_t seed,
 void predictor_forward(const Predictor &p, const float *X, int64_t n, float *logits,
                        hipStream_t s) {
     if (n == 0) return;
-    Acts t;
+    Acts &t = p.scratch;
     forward_acts(p, X, n, t, s);
     VJ_HIP(hipMemcpyAsync(logits, t.z3.p, (size_t)n * p.k * sizeof(float), hipMemcpyDeviceToDevice, s));
     VJ_HIP(hipGetLastError());
@@ -391,7 +392,7 @@ double predictor_loss_grad(const Predictor &p, const float *X, const float *Y, c
                            int64_t n, float *gW1, float *gb1, float *gW2, float *gb2, float *gW3,
                            float *gb3, hipStream_t s) {
     DevBuf g(p.n_params() * sizeof(float));
-    Acts t;
+    Acts &t = p.scratch;
     const double loss = n ? backward(p, X, Y, mask, n, t, g.as<float>(), s) : 0.0;
     float *dst[6] = {gW1, gb1, gW2, gb2, gW3, gb3};
     const size_t len[6] = {(size_t)p.h1 * p.din, (size_t)p.h1, (size_t)p.h2 * p.h1, (size_t)p.h2,
@@ -423,7 +424,7 @@ void predictor_train(Predictor &p, const float *X, const float *Y, int64_t n, in
     std::iota(perm.begin(), perm.end(), 0);
     DevBuf idx((size_t)batch * sizeof(int32_t)), xb((size_t)batch * p.din * sizeof(float)),
         yb((size_t)batch * p.k * sizeof(float)), g(p.n_params() * sizeof(float));
-    Acts t;
+    Acts &t = p.scratch;
     // parameters are separate buffers; Adam runs per buffer over its slice
     DevBuf *par[6] = {&p.W1, &p.b1, &p.W2, &p.b2, &p.W3, &p.b3};
     const float b1 = 0.9f, b2 = 0.999f;
