@@ -280,7 +280,12 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
     int64_t cap = p.pair_capacity > 0 ? p.pair_capacity : std::max<int64_t>(1 << 16, n * 64);
     if (!jw.ev0) VJ_HIP(hipEventCreate(&jw.ev0));
     if (!jw.ev1) VJ_HIP(hipEventCreate(&jw.ev1));
+    if (!jw.pinned) VJ_HIP(hipHostMalloc(&jw.pinned, 4096, hipHostMallocDefault));
     hipEvent_t ev0 = jw.ev0, ev1 = jw.ev1;
+    // pinned host staging: [0, 64) the counters read back, [256, ...) the arguments
+    int32_t *hctr = static_cast<int32_t *>(jw.pinned);
+    JoinArgs *args_h = reinterpret_cast<JoinArgs *>(static_cast<char *>(jw.pinned) + 256);
+    static_assert(sizeof(JoinArgs) <= 4096 - 256, "JoinArgs exceeds the pinned staging area");
     for (int attempt = 0; attempt < 4; ++attempt) {
         r.kernel_ms = 0.f;
         r.spill_ms = 0.f;
@@ -332,9 +337,9 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
         a.out_count = reinterpret_cast<unsigned long long *>(ctr);
         a.stats = r.stats.as<int32_t>();
         a.err = ctr + 3;
-        VJ_HIP(hipMemcpyAsync(argsbuf.p, &a, sizeof(a), hipMemcpyHostToDevice, s));
-
-        int32_t hctr[4] = {0, 0, 0, 0};
+        *args_h = a;
+        VJ_HIP(hipMemcpyAsync(argsbuf.p, args_h, sizeof(a), hipMemcpyHostToDevice, s));
+        std::memset(hctr, 0, 64);
         // One launch (or a sequence of chunks, global tiers) of `cnt` slots
         // of the lists lq/lp on tier `tier`; returns the device time.
         auto run_tier = [&](int tier, const int32_t *lq, const int32_t *lp, int64_t cnt) -> float {
@@ -393,7 +398,10 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
                 L.gil = gil.as<int32_t>();
                 L.gild = gild.as<float>();
             }
+            // one launch: the caller's synchronisation completes the events; a
+            // sequence of chunks synchronises per chunk (they share the scratch)
             float total_ms = 0.f;
+            const bool single = chunk >= cnt;
             for (int64_t c0 = 0; c0 < cnt; c0 += chunk) {
                 L.first = (int)c0;
                 L.count = (int)std::min<int64_t>(chunk, cnt - c0);
@@ -401,15 +409,16 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
                 VJ_CHECK(launch_join(L, s), VJ_ERR_UNSUPPORTED, "no join kernel for this row width");
                 VJ_HIP(hipGetLastError());
                 VJ_HIP(hipEventRecord(ev1, s));
-                VJ_HIP(hipStreamSynchronize(s));  // the next chunk reuses the scratch
-                float ms = 0.f;
-                VJ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-                total_ms += ms;
+                if (!single) {
+                    VJ_HIP(hipStreamSynchronize(s));
+                    float ms = 0.f;
+                    VJ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+                    total_ms += ms;
+                }
                 r.tier_launches[tier] += 1;
             }
-            r.tier_ms[tier] += total_ms;
             r.tier_queries[tier] += cnt;
-            return total_ms;
+            return single ? -1.f : total_ms;
         };
         for (size_t lv = 0; lv + 1 < ord.level_start.size(); ++lv) {
             // one MST level (all queries, self mode): the first tier, then the
@@ -420,11 +429,13 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
             for (int tier = start_tier; pending > 0; ++tier) {
                 VJ_CHECK(tier <= 3, VJ_ERR_INTERNAL, "join tiers exhausted");
                 VJ_HIP(hipMemsetAsync(ctr + 2, 0, sizeof(int32_t), s));
-                const float ms = run_tier(tier, lq, lp, pending);
+                float ms = run_tier(tier, lq, lp, pending);
+                VJ_HIP(hipMemcpyAsync(hctr, ctr, 64, hipMemcpyDeviceToHost, s));
+                VJ_HIP(hipStreamSynchronize(s));
+                if (ms < 0.f) VJ_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+                r.tier_ms[tier] += ms;
                 if (tier == start_tier) r.kernel_ms += ms;
                 else r.spill_ms += ms;
-                VJ_HIP(hipMemcpyAsync(hctr, ctr, sizeof(hctr), hipMemcpyDeviceToHost, s));
-                VJ_HIP(hipStreamSynchronize(s));
                 VJ_CHECK(!(hctr[3] & 8), VJ_ERR_INVALID_ARG, "query id out of range");
                 pending = hctr[2];
                 if (pending == 0) break;
@@ -449,12 +460,15 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
         const int64_t total = (int64_t)(((uint64_t)(uint32_t)hctr[1] << 32) | (uint32_t)hctr[0]);
         if (total <= cap) {
             unsigned long long nre = 0;
-            VJ_HIP(hipMemcpyAsync(&nre, ctr + 6, sizeof(nre), hipMemcpyDeviceToHost, s));
-            // the result owns exact-size copies; the workspace keeps its buffers
+            std::memcpy(&nre, hctr + 6, sizeof(nre));  // read back with the last counters
+            // the result owns exact-size copies (one allocation for the three
+            // arrays); the workspace keeps its buffers
             const size_t m = (size_t)std::max<int64_t>(total, 1);
-            r.q.alloc(m * sizeof(int32_t));
-            r.x.alloc(m * sizeof(int32_t));
-            r.dist.alloc(m * sizeof(float));
+            DevBuf block(m * (2 * sizeof(int32_t) + sizeof(float)));
+            r.x = DevBuf::view(block.as<char>() + m * sizeof(int32_t), m * sizeof(int32_t));
+            r.dist = DevBuf::view(block.as<char>() + 2 * m * sizeof(int32_t), m * sizeof(float));
+            r.q = std::move(block);
+            r.q.bytes = m * sizeof(int32_t);
             if (total > 0) {
                 VJ_HIP(hipMemcpyAsync(r.q.p, out_q.p, total * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
                 VJ_HIP(hipMemcpyAsync(r.x.p, out_x.p, total * sizeof(int32_t), hipMemcpyDeviceToDevice, s));

@@ -36,16 +36,32 @@ struct Error {
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool own = true;  // false: a view into another buffer (not freed here)
     DevBuf() = default;
     explicit DevBuf(size_t n) { alloc(n); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), own(o.own) {
+        o.p = nullptr;
+        o.bytes = 0;
+        o.own = true;
+    }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        if (this != &o) {
+            release();
+            p = o.p; bytes = o.bytes; own = o.own;
+            o.p = nullptr; o.bytes = 0; o.own = true;
+        }
         return *this;
     }
     ~DevBuf() { release(); }
+    static DevBuf view(void *ptr, size_t n) {
+        DevBuf v;
+        v.p = ptr;
+        v.bytes = n;
+        v.own = false;
+        return v;
+    }
     void alloc(size_t n) {
         release();
         if (n == 0) n = 16;
@@ -53,11 +69,12 @@ struct DevBuf {
         bytes = n;
     }
     // grow (contents not kept)
-    void reserve(size_t n) { if (n > bytes) alloc(n); }
+    void reserve(size_t n) { if (n > bytes || !own) alloc(n); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && own) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        own = true;
     }
     template <typename T> T *as() const { return static_cast<T *>(p); }
 };
@@ -71,12 +88,14 @@ struct JoinWorkspace {
     DevBuf qlist, qpos, counters, args, ovf, slots, out_q, out_x, out_d;
     DevBuf sort_keys, sort_keys2, sort_pos, sort_tmp;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    void *pinned = nullptr;  // 4 KiB of pinned host memory: counters read back, arguments sent
     JoinWorkspace() = default;
     JoinWorkspace(const JoinWorkspace &) = delete;
     JoinWorkspace &operator=(const JoinWorkspace &) = delete;
     ~JoinWorkspace() {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        if (pinned) (void)hipHostFree(pinned);
     }
 };
 
