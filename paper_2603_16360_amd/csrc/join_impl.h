@@ -1106,7 +1106,7 @@ __device__ __forceinline__ void use_global(WaveMem &m, const GlobalTables &g, si
 template <typename T, int DP, bool HYB, int HL, int LIST, int W, int PGC, int MINW>
 __global__ void __launch_bounds__(64 * W, MINW)
 k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos, int k0,
-            int k1, GlobalTables g, int32_t *ovf, int32_t *ovf_count) {
+            int k1, const int32_t *cnt_dev, GlobalTables g, int32_t *ovf, int32_t *ovf_count) {
     constexpr int HC = HYB ? kBeamMax + 64 * W : 1;
     __shared__ int32_t sh_hash[1 << HL];
     __shared__ int32_t sh_il[LIST];
@@ -1119,7 +1119,7 @@ k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t
     __shared__ int32_t sh_aux[kIsBf16<T> ? W : 1][64];
     __shared__ float sh_auxf[kIsBf16<T> ? W : 1][64];
     const int k = k0 + (int)blockIdx.x;
-    if (k >= k1) return;
+    if (k >= k1 || (cnt_dev != nullptr && k >= k0 + *cnt_dev)) return;
     const JoinArgs &a = *pa;
     WaveMem m;
     m.hash = sh_hash;
@@ -1145,12 +1145,15 @@ k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t
     if (again && threadIdx.x == 0) ovf[atomicAdd(ovf_count, 1)] = k;
 }
 
-// cooperative tier on global tables: one query per workgroup of W waves,
-// its tables in region (block index) of g; a re-run launch of the host
+// cooperative tier on global tables: one query at a time per workgroup of W
+// waves, its tables in region (block index) of g; a workgroup takes the slots
+// k0 + blockIdx.x, + gridDim.x, ... below k1 (and below k0 + *cnt_dev when
+// the count is on the device)
 template <typename T, int DP, bool HYB, int W, int PGC>
 __global__ void __launch_bounds__(64 * W)
 k_join_coop_global(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos,
-                   int k0, int k1, GlobalTables g, int32_t *ovf, int32_t *ovf_count) {
+                   int k0, int k1, const int32_t *cnt_dev, GlobalTables g, int32_t *ovf,
+                   int32_t *ovf_count) {
     constexpr int HC = HYB ? kBeamMax + 64 * W : 1;
     __shared__ int32_t sh_stage[W][64];
     __shared__ float sh_hk[HC];
@@ -1158,8 +1161,7 @@ k_join_coop_global(const JoinArgs *__restrict__ pa, const int32_t *qlist, const 
     __shared__ CoopShared<W> sh;
     __shared__ int32_t sh_aux[kIsBf16<T> ? W : 1][64];
     __shared__ float sh_auxf[kIsBf16<T> ? W : 1][64];
-    const int k = k0 + (int)blockIdx.x;
-    if (k >= k1) return;
+    const int kend = cnt_dev != nullptr ? min(k1, k0 + *cnt_dev) : k1;
     const JoinArgs &a = *pa;
     WaveMem m;
     use_global(m, g, blockIdx.x);
@@ -1168,8 +1170,12 @@ k_join_coop_global(const JoinArgs *__restrict__ pa, const int32_t *qlist, const 
     m.hi = sh_hi;
     m.aux = sh_aux[kIsBf16<T> ? threadIdx.x >> 6 : 0];
     m.auxf = sh_auxf[kIsBf16<T> ? threadIdx.x >> 6 : 0];
-    if (run_query_coop<T, DP, W, PGC>(a, m, sh, HC, k, qlist, qpos, 1 | 8 | 16) && threadIdx.x == 0)
-        ovf[atomicAdd(ovf_count, 1)] = k;
+    for (int k = k0 + (int)blockIdx.x; k < kend; k += (int)gridDim.x) {
+        if (run_query_coop<T, DP, W, PGC>(a, m, sh, HC, k, qlist, qpos, 1 | 8 | 16) &&
+            threadIdx.x == 0)
+            ovf[atomicAdd(ovf_count, 1)] = k;
+        __syncthreads();  // the next query clears the region's tables
+    }
 }
 
 template <typename T, int DP, bool HYB>
@@ -1196,18 +1202,21 @@ void launch_tier(const JoinLaunch &L, hipStream_t s) {
         // workgroups per CU) or small ones (4,096 slots, 1,024 pairs; four
         // workgroups per CU, registers capped for four waves per SIMD up to
         // 256-wide rows)
+        // grid: one workgroup per slot, or L.grid workgroups looping over
+        // the slots (global tables: one region per workgroup)
+        const unsigned blocks = (unsigned)(L.grid > 0 ? L.grid : L.count);
         if (L.tier == 1 && L.coop_small)
             hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 12, 1024, kWaves, 12, (DP <= 256 ? 4 : 1)>),
                                dim3((unsigned)L.count), dim3(64 * kWaves), 0, s, L.args, L.qlist,
-                               L.qpos, k0, k1, g, L.ovf, L.ovf_count);
+                               L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count);
         else if (L.tier == 1)
             hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 13, 1536, kWaves, 16, 1>),
                                dim3((unsigned)L.count), dim3(64 * kWaves), 0, s, L.args, L.qlist,
-                               L.qpos, k0, k1, g, L.ovf, L.ovf_count);
+                               L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count);
         else
-            hipLaunchKernelGGL((k_join_coop_global<T, DP, HYB, kWaves, 16>), dim3((unsigned)L.count),
-                               dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1, g, L.ovf,
-                               L.ovf_count);
+            hipLaunchKernelGGL((k_join_coop_global<T, DP, HYB, kWaves, 16>), dim3(blocks),
+                               dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1,
+                               L.count_dev, g, L.ovf, L.ovf_count);
     }
 }
 

@@ -156,6 +156,121 @@ __global__ void k_gather_slots(const int32_t *qlist, const int32_t *qpos, const 
     p2[i] = qpos[slots[i]];
 }
 
+// slots listed on the device: q2[i] = qlist[slots[i]], p2[i] = qpos[slots[i]]
+// for i < *cnt (at most nmax)
+__global__ void k_gather_slots_dev(const int32_t *qlist, const int32_t *qpos, const int32_t *slots,
+                                   const int32_t *cnt, int64_t nmax, int32_t *q2, int32_t *p2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nmax || i >= *cnt) return;
+    q2[i] = qlist[slots[i]];
+    p2[i] = qpos[slots[i]];
+}
+
+// replayed batch step: batch b = ctr[kBatchCursor] takes its eps and its
+// rows of the stats block, clears the per-batch counters and records where
+// its pairs begin
+__global__ void k_batch_begin(const BatchDesc *desc, JoinArgs *args, int32_t *stats_all,
+                              int32_t *ctr, uint64_t *rec) {
+    if (threadIdx.x != 0) return;
+    const int b = ctr[kBatchCursor];
+    const BatchDesc d = desc[b];
+    args->eps = d.eps;
+    args->eps2 = d.eps2;
+    args->stats = stats_all + d.stats_off * 8;
+    ctr[kBatchCount] = d.count;
+    ctr[2] = 0;  // first overflow list
+    ctr[4] = 0;  // global regions taken by promotion
+    ctr[kBatchOvf2] = 0;
+    ctr[kBatchOvf3] = 0;
+    rec[kBatchRec * b + 0] = *reinterpret_cast<const unsigned long long *>(ctr);
+    rec[kBatchRec * b + 4] = *reinterpret_cast<const unsigned long long *>(ctr + 6);
+}
+
+// the processing list of the current batch: its query ids in caller order
+__global__ void k_batch_list(const BatchDesc *desc, const int32_t *ctr, const int32_t *ids,
+                             int64_t nmax, int32_t *qlist) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const BatchDesc d = desc[ctr[kBatchCursor]];
+    if (i >= nmax || i >= d.count) return;
+    qlist[i] = ids ? ids[d.start + i] : (int32_t)(d.start + i);
+}
+
+// densest first within a replayed batch, without a sort: slot i goes to the
+// bucket of its d1 (the top 12 bits below the sign of the float: exponent
+// and 4 mantissa bits, so buckets are ordered by d1 and 6 % wide), the
+// buckets are counted, scanned and scattered
+__device__ __forceinline__ int density_bucket(const int32_t *adj, const float *elen, int R,
+                                              int64_t nx, int64_t nq, int32_t q) {
+    if (q < 0 || q >= nq) return kOrderBuckets - 1;
+    const int64_t u = nx + q;
+    float sum = 0.f;
+    int c = 0;
+    for (int j = 0; j < R; ++j) {
+        const int32_t y = adj[u * R + j];
+        if (y >= 0 && y < nx) { sum += elen[u * R + j]; ++c; }
+    }
+    const float d1 = c ? sum / (float)c : INFINITY;
+    return min((int)(__float_as_uint(d1) >> 19), kOrderBuckets - 1);
+}
+
+__global__ void k_batch_bucket(const int32_t *adj, const float *elen, int R, int64_t nx,
+                               int64_t nq, const int32_t *qlist, const int32_t *ctr, int64_t nmax,
+                               int32_t *bucket, uint32_t *hist) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nmax || i >= ctr[kBatchCount]) return;
+    const int b = density_bucket(adj, elen, R, nx, nq, qlist[i]);
+    bucket[i] = b;
+    atomicAdd(&hist[b], 1u);
+}
+
+// one workgroup of 1024 threads, 4 buckets each: off = exclusive scan of
+// hist; hist is cleared for the next batch
+__global__ void __launch_bounds__(1024) k_batch_scan(uint32_t *hist, uint32_t *off) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    uint32_t c[4], sum = 0;
+    for (int j = 0; j < 4; ++j) {
+        c[j] = hist[4 * t + j];
+        sum += c[j];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
+        const uint32_t v = t >= d ? part[t - d] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (int j = 0; j < 4; ++j) {
+        off[4 * t + j] = run;
+        run += c[j];
+        hist[4 * t + j] = 0u;
+    }
+}
+
+__global__ void k_batch_scatter(const int32_t *qlist, const int32_t *ctr, int64_t nmax,
+                                const int32_t *bucket, uint32_t *off, int32_t *q2, int32_t *p2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nmax || i >= ctr[kBatchCount]) return;
+    const uint32_t p = atomicAdd(&off[bucket[i]], 1u);
+    q2[p] = qlist[i];
+    p2[p] = (int32_t)i;
+}
+
+// end of the batch step: where its pairs end, how many queries each re-run
+// took; the cursor moves to the next batch
+__global__ void k_batch_end(int32_t *ctr, uint64_t *rec) {
+    if (threadIdx.x != 0) return;
+    const int b = ctr[kBatchCursor];
+    rec[kBatchRec * b + 1] = *reinterpret_cast<const unsigned long long *>(ctr);
+    rec[kBatchRec * b + 2] = (uint64_t)ctr[2];
+    rec[kBatchRec * b + 3] = (uint64_t)ctr[kBatchOvf2];
+    rec[kBatchRec * b + 5] = *reinterpret_cast<const unsigned long long *>(ctr + 6);
+    if (ctr[kBatchOvf3] != 0) atomicOr(ctr + 3, 64);
+    ctr[kBatchCursor] = b + 1;
+}
+
 __global__ void k_pack_keys(const int32_t *q, const int32_t *x, int64_t n, uint64_t *key) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) key[i] = ((uint64_t)(uint32_t)q[i] << 32) | (uint32_t)x[i];
@@ -237,6 +352,39 @@ void gather_slots(const int32_t *qlist, const int32_t *qpos, const int32_t *slot
                   int32_t *q2, int32_t *p2, hipStream_t s) {
     if (n == 0) return;
     hipLaunchKernelGGL(k_gather_slots, dim3(grid1(n)), dim3(256), 0, s, qlist, qpos, slots, n, q2, p2);
+}
+
+void gather_slots_dev(const int32_t *qlist, const int32_t *qpos, const int32_t *slots,
+                      const int32_t *cnt, int64_t nmax, int32_t *q2, int32_t *p2, hipStream_t s) {
+    if (nmax == 0) return;
+    hipLaunchKernelGGL(k_gather_slots_dev, dim3(grid1(nmax)), dim3(256), 0, s, qlist, qpos, slots,
+                       cnt, nmax, q2, p2);
+}
+
+void batch_begin(const BatchDesc *desc, JoinArgs *args, int32_t *stats_all, int32_t *ctr,
+                 uint64_t *rec, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, desc, args, stats_all, ctr, rec);
+}
+
+void batch_list(const BatchDesc *desc, const int32_t *ctr, const int32_t *ids, int64_t nmax,
+                int32_t *qlist, hipStream_t s) {
+    if (nmax == 0) return;
+    hipLaunchKernelGGL(k_batch_list, dim3(grid1(nmax)), dim3(256), 0, s, desc, ctr, ids, nmax, qlist);
+}
+
+void batch_order(const int32_t *adj, const float *elen, int R, int64_t nx, int64_t nq,
+                 const int32_t *qlist, const int32_t *ctr, int64_t nmax, int32_t *bucket,
+                 uint32_t *hist, uint32_t *off, int32_t *q2, int32_t *p2, hipStream_t s) {
+    if (nmax == 0) return;
+    hipLaunchKernelGGL(k_batch_bucket, dim3(grid1(nmax)), dim3(256), 0, s, adj, elen, R, nx, nq,
+                       qlist, ctr, nmax, bucket, hist);
+    hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(1024), 0, s, hist, off);
+    hipLaunchKernelGGL(k_batch_scatter, dim3(grid1(nmax)), dim3(256), 0, s, qlist, ctr, nmax, bucket,
+                       off, q2, p2);
+}
+
+void batch_end(int32_t *ctr, uint64_t *rec, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(64), 0, s, ctr, rec);
 }
 
 // processing order parents-first: stable sort of caller positions by MST depth

@@ -246,16 +246,57 @@ static void make_order(Index &ix, const int32_t *ids, int64_t n, int ws, bool de
     o.level_start.push_back(n);
 }
 
-static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const vj_join_params &p,
-                     const int32_t *budget, hipStream_t s, Pairs &r) {
-    const int ws = p.work_sharing, hyb = p.hybrid;
-    int prec = p.precision;
+// The join's arguments other than its outputs; ctr: the join counters
+static JoinArgs make_args(const Index &ix, int prec, const vj_join_params &p, int beam, float eps,
+                          const int32_t *budget, int32_t *ctr) {
+    JoinArgs a{};
+    a.rows = prec == VJ_PREC_U8 ? ix.vec_u8.p : prec == VJ_PREC_BF16 ? ix.vec_bf16.p : ix.vec.p;
+    // RNE to bf16 has relative error <= 2^-8 of |x|, i.e. <= 2^-8 / (1 - 2^-8) of |bf16(x)|
+    a.bf_u = prec == VJ_PREC_BF16 && !ix.bf16_exact ? 0.00392157f : 0.f;
+    a.nrecheck = reinterpret_cast<unsigned long long *>(ctr + 6);
+    a.rows32 = ix.vec.as<float>();
+    a.adj = ix.adj.as<int32_t>();
+    a.elen = ix.elen.as<float>();
+    a.nx = ix.nx;
+    a.nq = ix.nq;
+    a.R = ix.R;
+    a.dp = ix.dp;
+    a.entry = ix.entry;
+    a.metric = ix.metric;
+    a.eps = eps;
+    a.eps2 = (float)((double)eps * (double)eps);
+    a.ws = p.work_sharing;
+    a.hyb = p.hybrid;
+    a.beam = beam;
+    a.conv = p.conv_threshold;
+    a.ood_ratio = p.ood_ratio;
+    a.gen = ix.gen;
+    a.parent = ix.has_mst ? ix.parent.as<int32_t>() : nullptr;
+    a.inb = ix.inb.as<int32_t>();
+    a.cache = ix.cache.as<int32_t>();
+    a.seg = ix.seg.as<int64_t>();
+    a.segn = ix.segn.as<int32_t>();
+    a.budget = budget;
+    a.out_count = reinterpret_cast<unsigned long long *>(ctr);
+    a.err = ctr + 3;
+    return a;
+}
+
+// Row type of a join: AUTO takes exact u8 rows when the data allows them
+static int join_precision(Index &ix, int prec, hipStream_t s) {
     if (prec == VJ_PREC_AUTO) prec = ix.integer_u8 ? VJ_PREC_U8 : VJ_PREC_FP32;
     VJ_CHECK(prec != VJ_PREC_U8 || ix.integer_u8, VJ_ERR_INVALID_ARG,
              "u8 precision needs integer data in [0, 255]");
     VJ_CHECK(prec == VJ_PREC_FP32 || prec == VJ_PREC_U8 || prec == VJ_PREC_BF16,
              VJ_ERR_UNSUPPORTED, "precision not supported by the traversal");
     if (prec == VJ_PREC_BF16) ensure_bf16(ix, s);
+    return prec;
+}
+
+static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const vj_join_params &p,
+                     const int32_t *budget, hipStream_t s, Pairs &r) {
+    const int ws = p.work_sharing, hyb = p.hybrid;
+    const int prec = join_precision(ix, p.precision, s);
     // bf16 rows run on the workgroup tiers (they carry the margin re-check)
     const int start_tier = prec == VJ_PREC_BF16 ? std::max(1, (int)p.start_tier) : (int)p.start_tier;
     const int beam = (hyb != VJ_HYB_OFF) ? p.hybrid_beam : 0;
@@ -302,34 +343,7 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
         VJ_HIP(hipMemsetAsync(counters.p, 0, 64, s));
         if (ws != VJ_WS_SELF) stamp_batch(ix.inb.as<int32_t>(), ix.nq, ids, n, ix.gen, ctr + 3, s);
 
-        JoinArgs a{};
-        a.rows = prec == VJ_PREC_U8 ? ix.vec_u8.p : prec == VJ_PREC_BF16 ? ix.vec_bf16.p : ix.vec.p;
-        // RNE to bf16 has relative error <= 2^-8 of |x|, i.e. <= 2^-8 / (1 - 2^-8) of |bf16(x)|
-        a.bf_u = prec == VJ_PREC_BF16 && !ix.bf16_exact ? 0.00392157f : 0.f;
-        a.nrecheck = reinterpret_cast<unsigned long long *>(ctr + 6);
-        a.rows32 = ix.vec.as<float>();
-        a.adj = ix.adj.as<int32_t>();
-        a.elen = ix.elen.as<float>();
-        a.nx = ix.nx;
-        a.nq = ix.nq;
-        a.R = ix.R;
-        a.dp = ix.dp;
-        a.entry = ix.entry;
-        a.metric = ix.metric;
-        a.eps = eps;
-        a.eps2 = (float)((double)eps * (double)eps);
-        a.ws = ws;
-        a.hyb = hyb;
-        a.beam = beam;
-        a.conv = p.conv_threshold;
-        a.ood_ratio = p.ood_ratio;
-        a.gen = ix.gen;
-        a.parent = ix.has_mst ? ix.parent.as<int32_t>() : nullptr;
-        a.inb = ix.inb.as<int32_t>();
-        a.cache = ix.cache.as<int32_t>();
-        a.seg = ix.seg.as<int64_t>();
-        a.segn = ix.segn.as<int32_t>();
-        a.budget = budget;
+        JoinArgs a = make_args(ix, prec, p, beam, eps, budget, ctr);
         a.out_q = out_q.as<int32_t>();
         a.out_x = out_x.as<int32_t>();
         a.out_d = out_d.as<float>();
@@ -544,6 +558,281 @@ static void learned_join(Index &ix, const int32_t *ids, int64_t n, float eps, vj
     r.x = std::move(x2);
     r.dist = std::move(d2);
     r.count = tot;
+}
+
+// arguments shared by the two batch runners
+static void check_batches(const vj_index *idx, const int32_t *query_ids, const int64_t *st,
+                          const int64_t *ct, const float *eps, int32_t nb, vj_pairs **out) {
+    VJ_CHECK(idx != nullptr && out != nullptr && st != nullptr && ct != nullptr && eps != nullptr &&
+                 nb >= 0,
+             VJ_ERR_INVALID_ARG, "null pointer or negative batch count");
+    for (int32_t b = 0; b < nb; ++b) {
+        VJ_CHECK(st[b] >= 0 && ct[b] >= 0, VJ_ERR_INVALID_ARG, "batch ranges must be >= 0");
+        VJ_CHECK(query_ids != nullptr ? true : st[b] + ct[b] <= idx->impl.nq, VJ_ERR_INVALID_ARG,
+                 "batch range beyond the queries");
+        VJ_CHECK(std::isfinite(eps[b]), VJ_ERR_INVALID_ARG, "eps must be finite");
+    }
+}
+
+// ----------------------------------------------------- graph batch runner --
+// The steps of one batch (self mode) are captured once as a HIP graph and
+// replayed per batch with no host synchronisation in between: begin (eps,
+// stats rows, counters) -> the batch's processing list (densest
+// neighbourhoods first by d1 buckets, or the caller's order) -> the
+// workgroup tier with in-launch promotion -> the queries it could not hold,
+// on global tables (a fixed grid looping over a count on the device) -> the
+// queries those could not hold, on tables as large as the data set -> end
+// (pair range, cursor).  Batches run in stream order, so the pairs of each
+// batch are contiguous in the shared output.
+namespace {
+
+struct GraphGuard {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    std::vector<hipEvent_t> ev;
+    ~GraphGuard() {
+        if (e) (void)hipGraphExecDestroy(e);
+        if (g) (void)hipGraphDestroy(g);
+        for (auto x : ev) (void)hipEventDestroy(x);
+    }
+};
+
+}  // namespace
+
+static void run_batches_graph(Index &ix, const int32_t *ids, const int64_t *st_h,
+                              const int64_t *ct_h, const float *eps_h, int32_t nb,
+                              const vj_join_params &p, hipStream_t s,
+                              std::vector<std::unique_ptr<vj_pairs>> &res, float *batch_ms) {
+    VJ_CHECK(p.work_sharing == VJ_WS_SELF, VJ_ERR_UNSUPPORTED,
+             "the graph batch runner joins in self mode only");
+    VJ_CHECK(p.hybrid == VJ_HYB_OFF || p.hybrid == VJ_HYB_FORCE || p.hybrid == VJ_HYB_ADAPT,
+             VJ_ERR_UNSUPPORTED, "the graph batch runner takes hybrid off, force or adapt");
+    const int prec = join_precision(ix, p.precision, s);
+    const int beam = (p.hybrid != VJ_HYB_OFF) ? p.hybrid_beam : 0;
+    VJ_CHECK(beam <= 256, VJ_ERR_UNSUPPORTED, "hybrid_beam must be <= 256");
+
+    // descriptors; a batch with nothing to find (L2, eps <= 0) runs nothing
+    std::vector<BatchDesc> desc((size_t)nb);
+    int64_t nmax = 0, total_q = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        BatchDesc &d = desc[(size_t)b];
+        d.start = st_h[b];
+        d.stats_off = total_q;
+        d.count = (ix.metric == VJ_L2 && eps_h[b] <= 0.0f) ? 0 : (int32_t)ct_h[b];
+        d.eps = eps_h[b];
+        d.eps2 = (float)((double)eps_h[b] * (double)eps_h[b]);
+        d.pad = 0;
+        total_q += ct_h[b];
+        nmax = std::max<int64_t>(nmax, d.count);
+    }
+    auto stats = std::make_shared<DevBuf>((size_t)std::max<int64_t>(total_q, 1) * 8 * sizeof(int32_t));
+    VJ_HIP(hipMemsetAsync(stats->p, 0, stats->bytes, s));
+    auto make_results = [&](const std::shared_ptr<DevBuf> &block, int64_t total,
+                            const std::vector<uint64_t> &rec, GraphGuard *gg) {
+        const size_t m = (size_t)std::max<int64_t>(total, 1);
+        for (int32_t b = 0; b < nb; ++b) {
+            const BatchDesc &d = desc[(size_t)b];
+            auto h = std::make_unique<vj_pairs>();
+            Pairs &r = h->impl;
+            r.n_queries = ct_h[b];
+            r.stats = DevBuf::view(stats->as<int32_t>() + d.stats_off * 8,
+                                   (size_t)ct_h[b] * 8 * sizeof(int32_t));
+            r.keep.push_back(stats);
+            if (block) {
+                const uint64_t *rb = rec.data() + (size_t)b * kBatchRec;
+                const int64_t begin = (int64_t)rb[0], cnt = (int64_t)(rb[1] - rb[0]);
+                r.count = cnt;
+                r.q = DevBuf::view(block->as<int32_t>() + begin, cnt * sizeof(int32_t));
+                r.x = DevBuf::view(block->as<int32_t>() + m + begin, cnt * sizeof(int32_t));
+                r.dist = DevBuf::view(block->as<float>() + 2 * m + begin, cnt * sizeof(float));
+                r.keep.push_back(block);
+                r.n_candidates = (int64_t)(rb[5] - rb[4]);
+                r.tier_queries[1] = d.count;
+                r.tier_queries[2] = (int64_t)rb[2];
+                r.tier_queries[3] = (int64_t)rb[3];
+                r.tier_launches[1] = d.count > 0;
+                r.tier_launches[2] = rb[2] > 0;
+                r.tier_launches[3] = rb[3] > 0;
+                r.n_spilled = (int64_t)rb[2];
+                float ms = 0.f;
+                VJ_HIP(hipEventElapsedTime(&ms, gg->ev[(size_t)b], gg->ev[(size_t)b + 1]));
+                r.kernel_ms = ms;
+                r.tier_ms[1] = ms;
+                if (batch_ms) batch_ms[b] = ms;
+            } else if (batch_ms) {
+                batch_ms[b] = 0.f;
+            }
+            res[(size_t)b] = std::move(h);
+        }
+    };
+    if (nmax == 0) {
+        VJ_HIP(hipStreamSynchronize(s));
+        make_results(nullptr, 0, {}, nullptr);
+        return;
+    }
+
+    JoinWorkspace &jw = ix.jw;
+    jw.counters.reserve(64);
+    jw.args.reserve(sizeof(JoinArgs));
+    if (!jw.pinned) VJ_HIP(hipHostMalloc(&jw.pinned, 4096, hipHostMallocDefault));
+    if (!jw.capture) VJ_HIP(hipStreamCreateWithFlags(&jw.capture, hipStreamNonBlocking));
+    int32_t *ctr = jw.counters.as<int32_t>();
+    int32_t *hctr = static_cast<int32_t *>(jw.pinned);
+    JoinArgs *args_h = reinterpret_cast<JoinArgs *>(static_cast<char *>(jw.pinned) + 256);
+    DevBuf descb(desc.size() * sizeof(BatchDesc));
+    DevBuf recb((size_t)nb * kBatchRec * sizeof(uint64_t));
+    // eleven lists of nmax slots: processing list and positions of the three
+    // launches, the overflow list of each, the batch's ids in caller order
+    // and their density buckets; then the bucket counts and offsets
+    const bool dense = p.dense_first != 0;
+    DevBuf lists((size_t)nmax * 11 * sizeof(int32_t) + 2 * kOrderBuckets * sizeof(uint32_t));
+    int32_t *lq1 = lists.as<int32_t>(), *lp1 = lq1 + nmax, *lq2 = lp1 + nmax, *lp2 = lq2 + nmax;
+    int32_t *lq3 = lp2 + nmax, *lp3 = lq3 + nmax, *ovf1 = lp3 + nmax, *ovf2 = ovf1 + nmax;
+    int32_t *ovf3 = ovf2 + nmax, *lq0 = ovf3 + nmax, *bucket = lq0 + nmax;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(bucket + nmax), *boff = hist + kOrderBuckets;
+    if (dense) VJ_HIP(hipMemsetAsync(hist, 0, kOrderBuckets * sizeof(uint32_t), s));
+    else iota_i32(lp1, nmax, s);
+    VJ_HIP(hipMemcpyAsync(descb.p, desc.data(), descb.bytes, hipMemcpyHostToDevice, s));
+
+    // global tables: the promotion regions of the first launch and the
+    // regions of the re-run share one buffer (the launches do not overlap)
+    const bool small = p.coop_tables == 1;
+    const int hl2 = std::min(16, ceil_log2(2 * ix.nx));
+    const int ilc2 = (int)std::min<int64_t>(ix.nx, 1 << 15);
+    const int hl1 = small ? std::min(15, ceil_log2(2 * ix.nx)) : hl2;
+    const int ilc1 = small ? (int)std::min<int64_t>(ix.nx, 1 << 14) : ilc2;
+    const int promo_cap = (int)std::min<int64_t>(small ? 4096 : 1024, std::max<int64_t>(64, nmax / 16));
+    const int g2 = (int)std::min<int64_t>(1024, nmax);
+    const size_t gh_n = std::max(((size_t)promo_cap) << hl1, ((size_t)g2) << hl2);
+    const size_t il_n = std::max((size_t)promo_cap * ilc1, (size_t)g2 * ilc2);
+    ix.ws_gh.reserve(gh_n * sizeof(int32_t));
+    ix.ws_gil.reserve(il_n * sizeof(int32_t));
+    ix.ws_gild.reserve(il_n * sizeof(float));
+    const int g3 = (int)std::min<int64_t>(16, nmax);
+    const int hl3 = ceil_log2(2 * ix.nx);
+    DevBuf gh3(((size_t)g3 << hl3) * sizeof(int32_t));
+    DevBuf gil3((size_t)g3 * ix.nx * sizeof(int32_t)), gild3((size_t)g3 * ix.nx * sizeof(float));
+
+    auto launch = [&](int tier, const int32_t *lq, const int32_t *lp, const int32_t *cnt,
+                      int32_t *ovf, int32_t *ovf_cnt, hipStream_t cs) {
+        JoinLaunch L{};
+        L.args = jw.args.as<JoinArgs>();
+        L.qlist = lq;
+        L.qpos = lp;
+        L.first = 0;
+        L.count = (int)nmax;
+        L.count_dev = cnt;
+        L.dp = ix.dp;
+        L.prec = prec;
+        L.tier = tier;
+        L.coop_small = tier == 1 && small;
+        L.hyb = beam > 0;
+        L.ovf = ovf;
+        L.ovf_count = ovf_cnt;
+        L.gh = ix.ws_gh.as<int32_t>();
+        L.gil = ix.ws_gil.as<int32_t>();
+        L.gild = ix.ws_gild.as<float>();
+        if (tier == 1) {
+            L.hash_log2 = hl1;
+            L.il_cap = ilc1;
+            L.promo_next = ctr + 4;
+            L.promo_cap = promo_cap;
+        } else if (tier == 2) {
+            L.hash_log2 = hl2;
+            L.il_cap = ilc2;
+            L.grid = g2;
+        } else {
+            L.tier = 2;
+            L.gh = gh3.as<int32_t>();
+            L.gil = gil3.as<int32_t>();
+            L.gild = gild3.as<float>();
+            L.hash_log2 = hl3;
+            L.il_cap = (int)ix.nx;
+            L.grid = g3;
+        }
+        VJ_CHECK(launch_join(L, cs), VJ_ERR_UNSUPPORTED, "no join kernel for this row width");
+    };
+
+    GraphGuard gg;
+    hipStream_t cs = jw.capture;
+    VJ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+        const BatchDesc *dd = descb.as<BatchDesc>();
+        uint64_t *rec = recb.as<uint64_t>();
+        batch_begin(dd, jw.args.as<JoinArgs>(), stats->as<int32_t>(), ctr, rec, cs);
+        if (dense) {
+            batch_list(dd, ctr, ids, nmax, lq0, cs);
+            batch_order(ix.adj.as<int32_t>(), ix.elen.as<float>(), ix.R, ix.nx, ix.nq, lq0, ctr, nmax,
+                        bucket, hist, boff, lq1, lp1, cs);
+        } else {
+            batch_list(dd, ctr, ids, nmax, lq1, cs);
+        }
+        launch(1, lq1, lp1, ctr + kBatchCount, ovf1, ctr + 2, cs);
+        gather_slots_dev(lq1, lp1, ovf1, ctr + 2, nmax, lq2, lp2, cs);
+        launch(2, lq2, lp2, ctr + 2, ovf2, ctr + kBatchOvf2, cs);
+        gather_slots_dev(lq2, lp2, ovf2, ctr + kBatchOvf2, nmax, lq3, lp3, cs);
+        launch(3, lq3, lp3, ctr + kBatchOvf2, ovf3, ctr + kBatchOvf3, cs);
+        batch_end(ctr, rec, cs);
+        VJ_HIP(hipGetLastError());
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cs, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    VJ_HIP(hipStreamEndCapture(cs, &gg.g));
+    VJ_HIP(hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0));
+    gg.ev.assign((size_t)nb + 1, nullptr);
+    for (auto &e : gg.ev) VJ_HIP(hipEventCreate(&e));
+
+    int64_t cap = p.pair_capacity > 0 ? p.pair_capacity : std::max<int64_t>(1 << 16, total_q * 64);
+    std::vector<uint64_t> rec((size_t)nb * kBatchRec);
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        jw.out_q.reserve((size_t)cap * sizeof(int32_t));
+        jw.out_x.reserve((size_t)cap * sizeof(int32_t));
+        jw.out_d.reserve((size_t)cap * sizeof(float));
+        JoinArgs a = make_args(ix, prec, p, beam, 0.f, nullptr, ctr);
+        a.out_q = jw.out_q.as<int32_t>();
+        a.out_x = jw.out_x.as<int32_t>();
+        a.out_d = jw.out_d.as<float>();
+        a.cap = cap;
+        a.stats = stats->as<int32_t>();
+        *args_h = a;
+        VJ_HIP(hipMemcpyAsync(jw.args.p, args_h, sizeof(a), hipMemcpyHostToDevice, s));
+        VJ_HIP(hipMemsetAsync(ctr, 0, 64, s));  // the cursor starts at batch 0
+        VJ_HIP(hipEventRecord(gg.ev[0], s));
+        for (int32_t b = 0; b < nb; ++b) {
+            VJ_HIP(hipGraphLaunch(gg.e, s));
+            VJ_HIP(hipEventRecord(gg.ev[(size_t)b + 1], s));
+        }
+        std::memset(hctr, 0, 64);
+        VJ_HIP(hipMemcpyAsync(hctr, ctr, 64, hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipMemcpyAsync(rec.data(), recb.p, recb.bytes, hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipStreamSynchronize(s));
+        VJ_CHECK(!(hctr[3] & 8), VJ_ERR_INVALID_ARG, "query id out of range");
+        VJ_CHECK(!(hctr[3] & 16), VJ_ERR_INTERNAL, "visited-set probe exceeded the table size");
+        VJ_CHECK(!(hctr[3] & 32), VJ_ERR_INTERNAL, "a worklist entry is not a data node id");
+        VJ_CHECK(!(hctr[3] & 64), VJ_ERR_INTERNAL, "join tiers exhausted");
+        VJ_CHECK(hctr[kBatchCursor] == nb, VJ_ERR_INTERNAL, "batch replays incomplete");
+        const int64_t total = (int64_t)(((uint64_t)(uint32_t)hctr[1] << 32) | (uint32_t)hctr[0]);
+        if (total <= cap) {
+            // one block for the pairs of every batch: q, x and dist arrays
+            const size_t m = (size_t)std::max<int64_t>(total, 1);
+            auto block = std::make_shared<DevBuf>(m * (2 * sizeof(int32_t) + sizeof(float)));
+            if (total > 0) {
+                VJ_HIP(hipMemcpyAsync(block->p, jw.out_q.p, total * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+                VJ_HIP(hipMemcpyAsync(block->as<int32_t>() + m, jw.out_x.p, total * sizeof(int32_t),
+                                      hipMemcpyDeviceToDevice, s));
+                VJ_HIP(hipMemcpyAsync(block->as<float>() + 2 * m, jw.out_d.p, total * sizeof(float),
+                                      hipMemcpyDeviceToDevice, s));
+            }
+            VJ_HIP(hipStreamSynchronize(s));
+            make_results(block, total, rec, &gg);
+            return;
+        }
+        cap = total + total / 16 + 1024;
+    }
+    VJ_CHECK(false, VJ_ERR_INTERNAL, "result capacity did not converge");
 }
 
 }  // namespace vj
@@ -808,17 +1097,7 @@ vj_status vj_join_batches(vj_index *idx, const int32_t *query_ids, const int64_t
                           int32_t n_batches, vj_metric metric, const vj_join_params *pp,
                           void *stream, vj_pairs **out, float *batch_ms_host) {
     API_BEGIN
-    VJ_CHECK(idx != nullptr && out != nullptr && batch_start_host != nullptr &&
-                 batch_count_host != nullptr && eps_host != nullptr && n_batches >= 0,
-             VJ_ERR_INVALID_ARG, "null pointer or negative batch count");
-    Index &ix = idx->impl;
-    for (int32_t b = 0; b < n_batches; ++b) {
-        const int64_t st = batch_start_host[b], ct = batch_count_host[b];
-        VJ_CHECK(st >= 0 && ct >= 0, VJ_ERR_INVALID_ARG, "batch ranges must be >= 0");
-        VJ_CHECK(query_ids != nullptr ? true : st + ct <= ix.nq, VJ_ERR_INVALID_ARG,
-                 "batch range beyond the queries");
-        VJ_CHECK(std::isfinite(eps_host[b]), VJ_ERR_INVALID_ARG, "eps must be finite");
-    }
+    check_batches(idx, query_ids, batch_start_host, batch_count_host, eps_host, n_batches, out);
     std::vector<vj_pairs *> res((size_t)n_batches, nullptr);
     struct Guard {
         std::vector<vj_pairs *> &v;
@@ -849,6 +1128,29 @@ vj_status vj_join_batches(vj_index *idx, const int32_t *query_ids, const int64_t
     }
     for (int32_t b = 0; b < n_batches; ++b) out[b] = res[(size_t)b];
     guard.done = true;
+    API_END
+}
+
+vj_status vj_join_batches_graph(vj_index *idx, const int32_t *query_ids,
+                                const int64_t *batch_start_host, const int64_t *batch_count_host,
+                                const float *eps_host, int32_t n_batches, vj_metric metric,
+                                const vj_join_params *pp, void *stream, vj_pairs **out,
+                                float *batch_ms_host) {
+    API_BEGIN
+    check_batches(idx, query_ids, batch_start_host, batch_count_host, eps_host, n_batches, out);
+    Index &ix = idx->impl;
+    VJ_CHECK(metric == ix.metric, VJ_ERR_METRIC_MISMATCH, "join metric differs from the index metric");
+    vj_join_params p;
+    vj_default_join_params(&p);
+    if (pp) p = *pp;
+    VJ_CHECK(p.hybrid_beam >= 0, VJ_ERR_INVALID_ARG, "hybrid_beam must be >= 0");
+    VJ_CHECK(p.coop_tables == 0 || p.coop_tables == 1, VJ_ERR_INVALID_ARG, "coop_tables is 0 or 1");
+    for (int32_t b = 0; b < n_batches; ++b)
+        VJ_CHECK(batch_count_host[b] < ((int64_t)1 << 31), VJ_ERR_UNSUPPORTED, "batch count must be < 2^31");
+    std::vector<std::unique_ptr<vj_pairs>> res((size_t)n_batches);
+    run_batches_graph(ix, query_ids, batch_start_host, batch_count_host, eps_host, n_batches, p,
+                      (hipStream_t)stream, res, batch_ms_host);
+    for (int32_t b = 0; b < n_batches; ++b) out[b] = res[(size_t)b].release();
     API_END
 }
 

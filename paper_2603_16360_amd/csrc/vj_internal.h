@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <string>
+#include <vector>
 
 #include "../../include/vj.h"
 
@@ -88,6 +90,7 @@ struct JoinWorkspace {
     DevBuf qlist, qpos, counters, args, ovf, slots, out_q, out_x, out_d;
     DevBuf sort_keys, sort_keys2, sort_pos, sort_tmp;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t capture = nullptr;  // private stream the batch graph is captured on
     void *pinned = nullptr;  // 4 KiB of pinned host memory: counters read back, arguments sent
     JoinWorkspace() = default;
     JoinWorkspace(const JoinWorkspace &) = delete;
@@ -95,6 +98,7 @@ struct JoinWorkspace {
     ~JoinWorkspace() {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        if (capture) (void)hipStreamDestroy(capture);
         if (pinned) (void)hipHostFree(pinned);
     }
 };
@@ -142,6 +146,9 @@ struct Pairs {
     int64_t tier_queries[4] = {0, 0, 0, 0};
     DevBuf q, x, dist;       // int32, int32, float [count]
     DevBuf stats;            // int32 [n_queries][8]
+    // blocks that q / x / dist / stats are views into, shared by the results
+    // of one batch run
+    std::vector<std::shared_ptr<DevBuf>> keep;
 };
 
 // --------------------------------------------------------------- kernels --
@@ -190,6 +197,8 @@ struct JoinLaunch {
     int32_t *promo_next;      // tier 1: counter of the global regions taken in the launch
     int promo_cap;            // tier 1: regions of gh / gil / gild it may take (0: none)
     int32_t *ovf, *ovf_count; // slots (indices into qlist) that must be re-run
+    const int32_t *count_dev; // tiers 1-2: the slot count on the device, at most `count` (null: count)
+    int grid;                 // tier 2: workgroups looping over the slots (0: one per slot)
 };
 
 bool launch_join(const JoinLaunch &L, hipStream_t s);
