@@ -144,6 +144,7 @@ def main():
         walls, tier_ms, tier_ln = [], np.zeros(4), np.zeros(4)
         res = None
         for _ in range(args.steps):
+            res = None  # the previous result is released outside the timed region
             torch.cuda.synchronize()
             ts = time.perf_counter()
             res = vj.vj_join(idx, eps, precision=variant)
@@ -304,7 +305,10 @@ def ood_main(args, torch, workloads, vj):
             vj.vj_join(idx, eps, metric="ip", **kw)
         torch.cuda.synchronize()
         walls = []
+        res = None
         for _ in range(args.steps):
+            res = None
+            torch.cuda.synchronize()
             t = time.perf_counter()
             res = vj.vj_join(idx, eps, metric="ip", **kw)
             torch.cuda.synchronize()
@@ -359,18 +363,26 @@ def stream_main(args, torch, workloads, vj):
         starts[0], starts[0] + counts[0], dtype=torch.int32, device=dev))
     log(f"autotuned on batch 0: start_tier={params.start_tier} precision={params.precision} "
         f"({tuned_ms:.3f} ms)")
-    for _ in range(max(1, args.warmup)):
-        vj.vj_join_batches(idx, starts[:4], counts[:4], eps[:4], params=params)
-    torch.cuda.synchronize()
-    walls, lat = [], []
-    res = None
-    for _ in range(args.steps):
+    def run(runner):
+        """Timed runs of one batch runner: (results, wall seconds per run,
+        per-batch ms of every run).  Earlier results are released before the
+        timer starts."""
+        for _ in range(max(1, args.warmup)):
+            vj.vj_join_batches(idx, starts, counts, eps, params=params, runner=runner)
         torch.cuda.synchronize()
-        ts = time.perf_counter()
-        res, ms = vj.vj_join_batches(idx, starts, counts, eps, params=params)
-        torch.cuda.synchronize()
-        walls.append(time.perf_counter() - ts)
-        lat.extend(ms)
+        walls, lat = [], []
+        res = None
+        for _ in range(args.steps):
+            res = None
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            res, ms = vj.vj_join_batches(idx, starts, counts, eps, params=params, runner=runner)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - ts)
+            lat.extend(ms)
+        return res, walls, np.array(lat)
+
+    res, walls, lat = run("host")
     nq = int(sum(counts))
     pairs = sum(r.count() for r in res)
     # recall on every 20th batch against the exact join
@@ -380,24 +392,20 @@ def stream_main(args, torch, workloads, vj):
         gt = vj.vj_bruteforce_join(qb, X, eps[b])
         exact += gt.count()
         found += res[b].count()
-    # the same batches replayed from one captured HIP graph (no host
-    # synchronisation between batches)
-    for _ in range(max(1, args.warmup)):
-        vj.vj_join_batches(idx, starts[:4], counts[:4], eps[:4], params=params, graph=True)
-    torch.cuda.synchronize()
-    gwalls, glat = [], []
-    gres = None
-    for _ in range(args.steps):
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        gres, gms = vj.vj_join_batches(idx, starts, counts, eps, params=params, graph=True)
-        torch.cuda.synchronize()
-        gwalls.append(time.perf_counter() - ts)
-        glat.extend(gms)
-    same = all(a.count() == b.count() for a, b in zip(res, gres))
-    glat = np.array(glat)
-    log(f"graph replay: {nq / float(np.mean(gwalls)):.0f} queries/s, pair counts equal: {same}")
-    lat = np.array(lat)
+    # the same batches driven from the device (no host synchronisation
+    # between batches): direct launches and HIP graph replay
+    dev_runs = {}
+    for runner in ("device", "graph"):
+        dres, dwalls, dlat = run(runner)
+        same = all(a.count() == b.count() for a, b in zip(res, dres))
+        dev_runs[runner] = {
+            "value": nq / float(np.mean(dwalls)), "unit": "queries/s",
+            "ms_per_step": 1000.0 * float(np.mean(dwalls)),
+            "batch_device_ms_p50": float(np.percentile(dlat, 50)),
+            "batch_device_ms_p99": float(np.percentile(dlat, 99)),
+            "pair_counts_equal_host_runner": bool(same)}
+        log(f"{runner} runner: {dev_runs[runner]['value']:.0f} queries/s, pair counts equal: {same}")
+        del dres
     line = {
         "metric": "stream join queries/sec and batch latency (200 batches, X=1M x 96)",
         "value": nq / float(np.mean(walls)), "unit": "queries/s", "n_gpus": 1,
@@ -411,12 +419,8 @@ def stream_main(args, torch, workloads, vj):
         "batch_ms_max": float(lat.max()), "pairs": int(pairs),
         "recall_sampled_batches": found / max(1, exact), "build_s": build_s,
         "tuned": {"start_tier": params.start_tier, "precision": params.precision},
-        "graph_replay": {
-            "value": nq / float(np.mean(gwalls)), "unit": "queries/s",
-            "ms_per_step": 1000.0 * float(np.mean(gwalls)),
-            "batch_device_ms_p50": float(np.percentile(glat, 50)),
-            "batch_device_ms_p99": float(np.percentile(glat, 99)),
-            "pair_counts_equal_sequential": bool(same)},
+        "device_runner": dev_runs["device"],
+        "graph_replay": dev_runs["graph"],
     }
     print(json.dumps(line), flush=True)
 

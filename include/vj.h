@@ -198,27 +198,37 @@ vj_status vj_join_batches(vj_index *idx, const int32_t *query_ids, const int64_t
                           int32_t n_batches, vj_metric metric, const vj_join_params *p,
                           void *stream, vj_pairs **out, float *batch_ms_host);
 
+/* How vj_join_batches_device submits its batch steps. */
+typedef enum {
+    VJ_SUBMIT_DIRECT = 0, /* each step's kernels launched on the slot streams */
+    VJ_SUBMIT_GRAPH = 1   /* steps captured as HIP graphs (16 steps each) and replayed */
+} vj_submit;
+
 /*
- * Batches replayed from one HIP graph: the same arguments and results as
- * vj_join_batches, but the steps of one batch are captured once and the
- * graph is replayed for every batch with no host synchronisation between
- * batches.  The batch descriptors (range, eps) sit in device memory; a query
- * that outgrows the workgroup tier's tables is re-run inside the same replay
- * on global tables, then on tables as large as the data set.
+ * Batches driven from the device: the same arguments and results as
+ * vj_join_batches, but with no host synchronisation between batches.  The
+ * batch descriptors (range, eps) sit in device memory and each batch step
+ * reads its own; a query that outgrows the workgroup tier's tables is
+ * re-run within the step on global tables, then on tables as large as the
+ * data set, from counts kept on the device.  Two slots with their own
+ * state and stream take the even and the odd batches, so one batch's tail
+ * overlaps the next batch's start.  submit chooses direct launches or HIP
+ * graph replay (the graphs are kept in the index for the next call of the
+ * same shape).
  * Differences from vj_join_batches: self mode only (work_sharing =
  * VJ_WS_SELF) and hybrid OFF, FORCE or ADAPT; dense_first orders each batch
  * by buckets of d1 (4,096 buckets, about 6 % wide) instead of a sort;
- * start_tier is not used (the workgroup tier runs first); batch_ms_host[b] is the
- * device time of batch b's replay (HIP events between replays), not the wall
- * time.  The results of one call share one device allocation, freed with the
- * last of them.  Pair sets are those of vj_join on the same queries.
- * Calls on one index must not overlap.
+ * start_tier is not used (the workgroup tier runs first); batch_ms_host[b] is
+ * the device time of batch b (device wall clock at its first and last
+ * kernel), not the wall time.  The results of one call share one device
+ * allocation, freed with the last of them.  Pair sets are those of vj_join
+ * on the same queries.  Calls on one index must not overlap.
  */
-vj_status vj_join_batches_graph(vj_index *idx, const int32_t *query_ids,
-                                const int64_t *batch_start_host, const int64_t *batch_count_host,
-                                const float *eps_host, int32_t n_batches, vj_metric metric,
-                                const vj_join_params *p, void *stream, vj_pairs **out,
-                                float *batch_ms_host);
+vj_status vj_join_batches_device(vj_index *idx, const int32_t *query_ids,
+                                 const int64_t *batch_start_host, const int64_t *batch_count_host,
+                                 const float *eps_host, int32_t n_batches, vj_metric metric,
+                                 const vj_join_params *p, vj_submit submit, void *stream,
+                                 vj_pairs **out, float *batch_ms_host);
 
 /*
  * Autotuning: time vj_join on the sample query_ids[0..n) at eps for each

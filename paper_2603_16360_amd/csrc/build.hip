@@ -227,34 +227,52 @@ __global__ void __launch_bounds__(256)
 k_nearest_reached(const float *vec, int64_t N, int dp, int32_t w, const int *seen,
                   const int32_t *adj, int R, unsigned long long *best_any,
                   unsigned long long *best_free) {
+    // 8 lanes per node, 32 nodes per workgroup step, grid-stride over the
+    // nodes; one atomic per workgroup (the minimum of unique (d2, id) keys
+    // does not depend on the order)
+    __shared__ unsigned long long s_a[4], s_f[4];
     const int lane = threadIdx.x & 63;
     const int g = lane >> 3, p8 = lane & 7;
-    const int64_t p = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 8 + g;
-    const bool ok = p < N && seen[p];
-    float acc = 0.f;
-    if (ok) {
-        const float4 *a = reinterpret_cast<const float4 *>(vec + p * dp);
-        const float4 *b = reinterpret_cast<const float4 *>(vec + (int64_t)w * dp);
-        for (int c = p8; c < dp / 4; c += 8) {
-            const float4 x = a[c], y = b[c];
-            float t = x.x - y.x; acc = fmaf(t, t, acc);
-            t = x.y - y.y; acc = fmaf(t, t, acc);
-            t = x.z - y.z; acc = fmaf(t, t, acc);
-            t = x.w - y.w; acc = fmaf(t, t, acc);
+    const float4 *b = reinterpret_cast<const float4 *>(vec + (int64_t)w * dp);
+    unsigned long long ka = ~0ull, kf = ~0ull;
+    const int64_t stride = (int64_t)gridDim.x * 32;
+    for (int64_t base = (int64_t)blockIdx.x * 32; base < N; base += stride) {
+        const int64_t p = base + (threadIdx.x >> 6) * 8 + g;
+        const bool ok = p < N && seen[p];
+        float acc = 0.f;
+        if (ok) {
+            const float4 *a = reinterpret_cast<const float4 *>(vec + p * dp);
+            for (int c = p8; c < dp / 4; c += 8) {
+                const float4 x = a[c], y = b[c];
+                float t = x.x - y.x; acc = fmaf(t, t, acc);
+                t = x.y - y.y; acc = fmaf(t, t, acc);
+                t = x.z - y.z; acc = fmaf(t, t, acc);
+                t = x.w - y.w; acc = fmaf(t, t, acc);
+            }
+        }
+#pragma unroll
+        for (int off = 4; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (ok) {
+            const unsigned long long key = ((unsigned long long)__float_as_uint(acc) << 32) | (uint32_t)p;
+            ka = min_u64(ka, key);
+            if (adj[p * R + R - 1] < 0) kf = min_u64(kf, key);
         }
     }
 #pragma unroll
-    for (int off = 4; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    const unsigned long long key =
-        ok ? ((unsigned long long)__float_as_uint(acc) << 32) | (uint32_t)p : ~0ull;
-    const bool fr = ok && adj[p * R + R - 1] < 0;
-    unsigned long long ka = key, kf = fr ? key : ~0ull;
-#pragma unroll
-    for (int off = 8; off < 64; off <<= 1) {
+    for (int off = 1; off < 64; off <<= 1) {
         ka = min_u64(ka, __shfl_xor(ka, off));
         kf = min_u64(kf, __shfl_xor(kf, off));
     }
     if (lane == 0) {
+        s_a[threadIdx.x >> 6] = ka;
+        s_f[threadIdx.x >> 6] = kf;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 4; ++i) {
+            ka = min_u64(ka, s_a[i]);
+            kf = min_u64(kf, s_f[i]);
+        }
         if (ka != ~0ull) atomicMin(best_any, ka);
         if (kf != ~0ull) atomicMin(best_free, kf);
     }
@@ -440,7 +458,7 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
             unsigned long long init[2] = {~0ull, ~0ull}, got[2];
             VJ_HIP(hipMemcpyAsync(misc.as<char>() + 8, init, 16, hipMemcpyHostToDevice, s));
             unsigned long long *bests = reinterpret_cast<unsigned long long *>(misc.as<char>() + 8);
-            hipLaunchKernelGGL(k_nearest_reached, dim3(g1b(N, 32)), dim3(256), 0, s, vec, N, dp,
+            hipLaunchKernelGGL(k_nearest_reached, dim3(std::min<unsigned>(g1b(N, 32), 2048)), dim3(256), 0, s, vec, N, dp,
                                (int32_t)first, seenp, ix.adj.as<int32_t>(), R, bests, bests + 1);
             VJ_HIP(hipMemcpyAsync(got, bests, 16, hipMemcpyDeviceToHost, s));
             VJ_HIP(hipStreamSynchronize(s));

@@ -16,12 +16,13 @@ void gather_slots(const int32_t *qlist, const int32_t *qpos, const int32_t *slot
 void gather_slots_dev(const int32_t *qlist, const int32_t *qpos, const int32_t *slots,
                       const int32_t *cnt, int64_t nmax, int32_t *q2, int32_t *p2, hipStream_t s);
 
-// Batch steps replayed from one captured graph: the batch descriptors sit in
+// Batch steps replayed from captured graphs: the batch descriptors sit in
 // device memory and a cursor in the join counters selects the batch.
 struct BatchDesc {
-    int64_t start;      // first entry of the batch in the id list
-    int64_t stats_off;  // first row of the batch in the stats block
-    int32_t count;      // queries (0: the batch runs nothing)
+    const int32_t *ids;  // id list of the batch (null: the ids start, start + 1, ...)
+    int32_t *stats;      // the batch's rows of per-query counters
+    int64_t start;       // first entry of the batch in the id list
+    int32_t count;       // queries (0: the batch runs nothing)
     float eps, eps2;
     int32_t pad;
 };
@@ -29,20 +30,20 @@ struct BatchDesc {
 constexpr int kBatchCount = 5;    // slots of the current batch (first launch)
 constexpr int kBatchOvf2 = 8;     // queries left for the full-size tables
 constexpr int kBatchOvf3 = 9;     // queries no table held (must stay 0)
-constexpr int kBatchCursor = 10;  // batch the next replay runs
+constexpr int kBatchCursor = 10;  // batch the next step runs
 // per batch record: pairs before and after it, queries re-run on global
-// tables and on full-size tables, bf16 re-checks before and after it
-constexpr int kBatchRec = 6;
-void batch_begin(const BatchDesc *desc, JoinArgs *args, int32_t *stats_all, int32_t *ctr,
-                 uint64_t *rec, hipStream_t s);
-void batch_list(const BatchDesc *desc, const int32_t *ctr, const int32_t *ids, int64_t nmax,
-                int32_t *qlist, hipStream_t s);
-// densest neighbourhoods first (bucketed by d1, 4,096 buckets): q2 / p2 get
-// the ids of qlist and their positions; hist must be zero on entry and is
-// zero again on return
+// tables and on full-size tables, bf16 re-checks before and after it, device
+// wall clock at its start and end
+constexpr int kBatchRec = 8;
 constexpr int kOrderBuckets = 4096;
-void batch_order(const int32_t *adj, const float *elen, int R, int64_t nx, int64_t nq,
-                 const int32_t *qlist, const int32_t *ctr, int64_t nmax, int32_t *bucket,
+// the step's first kernel: set-up, the batch's query list, and (bucket
+// non-null) the d1 bucket of each query counted in hist
+void batch_start(const BatchDesc *desc, JoinArgs *args, int32_t *ctr, uint64_t *rec, int64_t nmax,
+                 const int32_t *adj, const float *elen, int R, int64_t nx, int64_t nq,
+                 int32_t *qlist, int32_t *bucket, uint32_t *hist, hipStream_t s);
+// densest neighbourhoods first (4,096 d1 buckets): q2 / p2 get the ids of
+// qlist and their positions; hist is zero again on return
+void batch_order(const int32_t *qlist, const int32_t *ctr, int64_t nmax, const int32_t *bucket,
                  uint32_t *hist, uint32_t *off, int32_t *q2, int32_t *p2, hipStream_t s);
 void batch_end(int32_t *ctr, uint64_t *rec, hipStream_t s);
 

@@ -166,35 +166,6 @@ __global__ void k_gather_slots_dev(const int32_t *qlist, const int32_t *qpos, co
     p2[i] = qpos[slots[i]];
 }
 
-// replayed batch step: batch b = ctr[kBatchCursor] takes its eps and its
-// rows of the stats block, clears the per-batch counters and records where
-// its pairs begin
-__global__ void k_batch_begin(const BatchDesc *desc, JoinArgs *args, int32_t *stats_all,
-                              int32_t *ctr, uint64_t *rec) {
-    if (threadIdx.x != 0) return;
-    const int b = ctr[kBatchCursor];
-    const BatchDesc d = desc[b];
-    args->eps = d.eps;
-    args->eps2 = d.eps2;
-    args->stats = stats_all + d.stats_off * 8;
-    ctr[kBatchCount] = d.count;
-    ctr[2] = 0;  // first overflow list
-    ctr[4] = 0;  // global regions taken by promotion
-    ctr[kBatchOvf2] = 0;
-    ctr[kBatchOvf3] = 0;
-    rec[kBatchRec * b + 0] = *reinterpret_cast<const unsigned long long *>(ctr);
-    rec[kBatchRec * b + 4] = *reinterpret_cast<const unsigned long long *>(ctr + 6);
-}
-
-// the processing list of the current batch: its query ids in caller order
-__global__ void k_batch_list(const BatchDesc *desc, const int32_t *ctr, const int32_t *ids,
-                             int64_t nmax, int32_t *qlist) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const BatchDesc d = desc[ctr[kBatchCursor]];
-    if (i >= nmax || i >= d.count) return;
-    qlist[i] = ids ? ids[d.start + i] : (int32_t)(d.start + i);
-}
-
 // densest first within a replayed batch, without a sort: slot i goes to the
 // bucket of its d1 (the top 12 bits below the sign of the float: exponent
 // and 4 mantissa bits, so buckets are ordered by d1 and 6 % wide), the
@@ -213,14 +184,39 @@ __device__ __forceinline__ int density_bucket(const int32_t *adj, const float *e
     return min((int)(__float_as_uint(d1) >> 19), kOrderBuckets - 1);
 }
 
-__global__ void k_batch_bucket(const int32_t *adj, const float *elen, int R, int64_t nx,
-                               int64_t nq, const int32_t *qlist, const int32_t *ctr, int64_t nmax,
-                               int32_t *bucket, uint32_t *hist) {
+// first kernel of a replayed batch step.  Workgroup 0 sets up batch b =
+// ctr[kBatchCursor]: its eps and stats rows in the join arguments, the
+// per-batch counters cleared, where its pairs begin and the clock.  Every
+// thread i < count writes the batch's query id i to qlist and, when ordering
+// densest first, its d1 bucket (counted in hist).
+__global__ void k_batch_start(const BatchDesc *desc, JoinArgs *args, int32_t *ctr, uint64_t *rec,
+                              int64_t nmax, const int32_t *adj, const float *elen, int R,
+                              int64_t nx, int64_t nq, int32_t *qlist, int32_t *bucket,
+                              uint32_t *hist) {
+    const int b = ctr[kBatchCursor];
+    const BatchDesc d = desc[b];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        args->eps = d.eps;
+        args->eps2 = d.eps2;
+        args->stats = d.stats;
+        ctr[kBatchCount] = d.count;
+        ctr[2] = 0;  // first overflow list
+        ctr[4] = 0;  // global regions taken by promotion
+        ctr[kBatchOvf2] = 0;
+        ctr[kBatchOvf3] = 0;
+        rec[kBatchRec * b + 0] = *reinterpret_cast<const unsigned long long *>(ctr);
+        rec[kBatchRec * b + 4] = *reinterpret_cast<const unsigned long long *>(ctr + 6);
+        rec[kBatchRec * b + 6] = (uint64_t)wall_clock64();
+    }
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nmax || i >= ctr[kBatchCount]) return;
-    const int b = density_bucket(adj, elen, R, nx, nq, qlist[i]);
-    bucket[i] = b;
-    atomicAdd(&hist[b], 1u);
+    if (i >= nmax || i >= d.count) return;
+    const int32_t q = d.ids ? d.ids[d.start + i] : (int32_t)(d.start + i);
+    qlist[i] = q;
+    if (bucket) {
+        const int k = density_bucket(adj, elen, R, nx, nq, q);
+        bucket[i] = k;
+        atomicAdd(&hist[k], 1u);
+    }
 }
 
 // one workgroup of 1024 threads, 4 buckets each: off = exclusive scan of
@@ -267,6 +263,7 @@ __global__ void k_batch_end(int32_t *ctr, uint64_t *rec) {
     rec[kBatchRec * b + 2] = (uint64_t)ctr[2];
     rec[kBatchRec * b + 3] = (uint64_t)ctr[kBatchOvf2];
     rec[kBatchRec * b + 5] = *reinterpret_cast<const unsigned long long *>(ctr + 6);
+    rec[kBatchRec * b + 7] = (uint64_t)wall_clock64();
     if (ctr[kBatchOvf3] != 0) atomicOr(ctr + 3, 64);
     ctr[kBatchCursor] = b + 1;
 }
@@ -361,23 +358,16 @@ void gather_slots_dev(const int32_t *qlist, const int32_t *qpos, const int32_t *
                        cnt, nmax, q2, p2);
 }
 
-void batch_begin(const BatchDesc *desc, JoinArgs *args, int32_t *stats_all, int32_t *ctr,
-                 uint64_t *rec, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, desc, args, stats_all, ctr, rec);
+void batch_start(const BatchDesc *desc, JoinArgs *args, int32_t *ctr, uint64_t *rec, int64_t nmax,
+                 const int32_t *adj, const float *elen, int R, int64_t nx, int64_t nq,
+                 int32_t *qlist, int32_t *bucket, uint32_t *hist, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_start, dim3(std::max(1u, grid1(nmax))), dim3(256), 0, s, desc, args,
+                       ctr, rec, nmax, adj, elen, R, nx, nq, qlist, bucket, hist);
 }
 
-void batch_list(const BatchDesc *desc, const int32_t *ctr, const int32_t *ids, int64_t nmax,
-                int32_t *qlist, hipStream_t s) {
-    if (nmax == 0) return;
-    hipLaunchKernelGGL(k_batch_list, dim3(grid1(nmax)), dim3(256), 0, s, desc, ctr, ids, nmax, qlist);
-}
-
-void batch_order(const int32_t *adj, const float *elen, int R, int64_t nx, int64_t nq,
-                 const int32_t *qlist, const int32_t *ctr, int64_t nmax, int32_t *bucket,
+void batch_order(const int32_t *qlist, const int32_t *ctr, int64_t nmax, const int32_t *bucket,
                  uint32_t *hist, uint32_t *off, int32_t *q2, int32_t *p2, hipStream_t s) {
     if (nmax == 0) return;
-    hipLaunchKernelGGL(k_batch_bucket, dim3(grid1(nmax)), dim3(256), 0, s, adj, elen, R, nx, nq,
-                       qlist, ctr, nmax, bucket, hist);
     hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(1024), 0, s, hist, off);
     hipLaunchKernelGGL(k_batch_scatter, dim3(grid1(nmax)), dim3(256), 0, s, qlist, ctr, nmax, bucket,
                        off, q2, p2);

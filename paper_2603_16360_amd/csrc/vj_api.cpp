@@ -318,7 +318,9 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
     r.stats.alloc((size_t)std::max<int64_t>(n, 1) * 8 * sizeof(int32_t));
     int32_t *ctr = counters.as<int32_t>();
 
-    int64_t cap = p.pair_capacity > 0 ? p.pair_capacity : std::max<int64_t>(1 << 16, n * 64);
+    int64_t cap = p.pair_capacity > 0
+                      ? p.pair_capacity
+                      : std::max<int64_t>({1 << 16, n * 64, (int64_t)(out_q.bytes / sizeof(int32_t))});
     if (!jw.ev0) VJ_HIP(hipEventCreate(&jw.ev0));
     if (!jw.ev1) VJ_HIP(hipEventCreate(&jw.ev1));
     if (!jw.pinned) VJ_HIP(hipHostMalloc(&jw.pinned, 4096, hipHostMallocDefault));
@@ -574,35 +576,32 @@ static void check_batches(const vj_index *idx, const int32_t *query_ids, const i
     }
 }
 
-// ----------------------------------------------------- graph batch runner --
-// The steps of one batch (self mode) are captured once as a HIP graph and
-// replayed per batch with no host synchronisation in between: begin (eps,
-// stats rows, counters) -> the batch's processing list (densest
-// neighbourhoods first by d1 buckets, or the caller's order) -> the
-// workgroup tier with in-launch promotion -> the queries it could not hold,
-// on global tables (a fixed grid looping over a count on the device) -> the
-// queries those could not hold, on tables as large as the data set -> end
-// (pair range, cursor).  Batches run in stream order, so the pairs of each
-// batch are contiguous in the shared output.
+// ---------------------------------------------------- device batch runner --
+// The steps of a batch (self mode) run with no host synchronisation between
+// batches, their parameters read from descriptors in device memory: start (eps, stats rows,
+// counters, the batch's query list and d1 buckets) -> densest
+// neighbourhoods first (bucket scan and scatter; or the caller's order) ->
+// the workgroup tier with in-launch promotion -> the queries it could not
+// hold, on global tables (a fixed grid looping over a count on the device)
+// -> the queries those could not hold, on tables as large as the data set
+// -> end (pair range, clock, cursor).  The steps are launched directly, or
+// captured as a HIP graph of up to kSteps steps that is replayed (and kept
+// for the next call of the same launch shape).  Two replay slots,
+// each with its own state, graph and stream, take the even and the odd
+// batches, so that one batch's tail overlaps the next batch's start; within
+// a slot batches run in order, so the pairs of each batch are contiguous in
+// its slot's output.
 namespace {
 
-struct GraphGuard {
-    hipGraph_t g = nullptr;
-    hipGraphExec_t e = nullptr;
-    std::vector<hipEvent_t> ev;
-    ~GraphGuard() {
-        if (e) (void)hipGraphExecDestroy(e);
-        if (g) (void)hipGraphDestroy(g);
-        for (auto x : ev) (void)hipEventDestroy(x);
-    }
-};
+constexpr int kSlots = 2;
+constexpr int kSteps = 16;
 
 }  // namespace
 
-static void run_batches_graph(Index &ix, const int32_t *ids, const int64_t *st_h,
-                              const int64_t *ct_h, const float *eps_h, int32_t nb,
-                              const vj_join_params &p, hipStream_t s,
-                              std::vector<std::unique_ptr<vj_pairs>> &res, float *batch_ms) {
+static void run_batches_device(Index &ix, const int32_t *ids, const int64_t *st_h,
+                               const int64_t *ct_h, const float *eps_h, int32_t nb,
+                               const vj_join_params &p, bool graph, hipStream_t s,
+                               std::vector<std::unique_ptr<vj_pairs>> &res, float *batch_ms) {
     VJ_CHECK(p.work_sharing == VJ_WS_SELF, VJ_ERR_UNSUPPORTED,
              "the graph batch runner joins in self mode only");
     VJ_CHECK(p.hybrid == VJ_HYB_OFF || p.hybrid == VJ_HYB_FORCE || p.hybrid == VJ_HYB_ADAPT,
@@ -611,36 +610,58 @@ static void run_batches_graph(Index &ix, const int32_t *ids, const int64_t *st_h
     const int beam = (p.hybrid != VJ_HYB_OFF) ? p.hybrid_beam : 0;
     VJ_CHECK(beam <= 256, VJ_ERR_UNSUPPORTED, "hybrid_beam must be <= 256");
 
-    // descriptors; a batch with nothing to find (L2, eps <= 0) runs nothing
-    std::vector<BatchDesc> desc((size_t)nb);
     int64_t nmax = 0, total_q = 0;
+    std::vector<int64_t> stats_off((size_t)nb);
     for (int32_t b = 0; b < nb; ++b) {
-        BatchDesc &d = desc[(size_t)b];
-        d.start = st_h[b];
-        d.stats_off = total_q;
-        d.count = (ix.metric == VJ_L2 && eps_h[b] <= 0.0f) ? 0 : (int32_t)ct_h[b];
-        d.eps = eps_h[b];
-        d.eps2 = (float)((double)eps_h[b] * (double)eps_h[b]);
-        d.pad = 0;
+        stats_off[(size_t)b] = total_q;
         total_q += ct_h[b];
-        nmax = std::max<int64_t>(nmax, d.count);
+        if (!(ix.metric == VJ_L2 && eps_h[b] <= 0.0f)) nmax = std::max<int64_t>(nmax, ct_h[b]);
     }
     auto stats = std::make_shared<DevBuf>((size_t)std::max<int64_t>(total_q, 1) * 8 * sizeof(int32_t));
     VJ_HIP(hipMemsetAsync(stats->p, 0, stats->bytes, s));
-    auto make_results = [&](const std::shared_ptr<DevBuf> &block, int64_t total,
-                            const std::vector<uint64_t> &rec, GraphGuard *gg) {
+    // descriptors of each slot (batch b goes to slot b % 2, entry b / 2),
+    // padded to whole graphs with batches that run nothing; a batch with
+    // nothing to find (L2, eps <= 0) runs nothing either
+    const int nsl = nb > 1 ? kSlots : 1;
+    std::vector<BatchDesc> desc[kSlots];
+    for (int32_t b = 0; b < nb; ++b) {
+        BatchDesc d{};
+        d.ids = ids;
+        d.stats = stats->as<int32_t>() + stats_off[(size_t)b] * 8;
+        d.start = st_h[b];
+        d.count = (ix.metric == VJ_L2 && eps_h[b] <= 0.0f) ? 0 : (int32_t)ct_h[b];
+        d.eps = eps_h[b];
+        d.eps2 = (float)((double)eps_h[b] * (double)eps_h[b]);
+        desc[b % kSlots].push_back(d);
+    }
+    const int64_t per_slot = (nb + nsl - 1) / nsl;
+    // steps per submission: a graph of up to kSteps, or one step launched directly
+    const int steps = graph ? (int)std::min<int64_t>(kSteps, std::max<int64_t>(per_slot, 1)) : 1;
+    int launches[kSlots] = {0, 0};
+    for (int k = 0; k < nsl; ++k) {
+        launches[k] = (int)((desc[k].size() + steps - 1) / steps);
+        BatchDesc pad{};
+        pad.stats = stats->as<int32_t>();
+        desc[k].resize((size_t)launches[k] * steps, pad);
+    }
+    JoinWorkspace &jw = ix.jw;
+    int hz = 0;  // device wall clock, kHz
+    VJ_HIP(hipDeviceGetAttribute(&hz, hipDeviceAttributeWallClockRate, ix.device));
+    // results: slot k's pairs sit at base[k] in the block of all pairs
+    auto make_results = [&](const std::shared_ptr<DevBuf> &block, int64_t total, const int64_t *base,
+                            const std::vector<uint64_t> *rec) {
         const size_t m = (size_t)std::max<int64_t>(total, 1);
         for (int32_t b = 0; b < nb; ++b) {
-            const BatchDesc &d = desc[(size_t)b];
+            const int k = b % kSlots;
+            const BatchDesc &d = desc[k][(size_t)(b / kSlots)];
             auto h = std::make_unique<vj_pairs>();
             Pairs &r = h->impl;
             r.n_queries = ct_h[b];
-            r.stats = DevBuf::view(stats->as<int32_t>() + d.stats_off * 8,
-                                   (size_t)ct_h[b] * 8 * sizeof(int32_t));
+            r.stats = DevBuf::view(d.stats, (size_t)ct_h[b] * 8 * sizeof(int32_t));
             r.keep.push_back(stats);
             if (block) {
-                const uint64_t *rb = rec.data() + (size_t)b * kBatchRec;
-                const int64_t begin = (int64_t)rb[0], cnt = (int64_t)(rb[1] - rb[0]);
+                const uint64_t *rb = rec[k].data() + (size_t)(b / kSlots) * kBatchRec;
+                const int64_t begin = base[k] + (int64_t)rb[0], cnt = (int64_t)(rb[1] - rb[0]);
                 r.count = cnt;
                 r.q = DevBuf::view(block->as<int32_t>() + begin, cnt * sizeof(int32_t));
                 r.x = DevBuf::view(block->as<int32_t>() + m + begin, cnt * sizeof(int32_t));
@@ -654,8 +675,7 @@ static void run_batches_graph(Index &ix, const int32_t *ids, const int64_t *st_h
                 r.tier_launches[2] = rb[2] > 0;
                 r.tier_launches[3] = rb[3] > 0;
                 r.n_spilled = (int64_t)rb[2];
-                float ms = 0.f;
-                VJ_HIP(hipEventElapsedTime(&ms, gg->ev[(size_t)b], gg->ev[(size_t)b + 1]));
+                const float ms = hz > 0 ? (float)((double)(rb[7] - rb[6]) / (double)hz) : 0.f;
                 r.kernel_ms = ms;
                 r.tier_ms[1] = ms;
                 if (batch_ms) batch_ms[b] = ms;
@@ -667,35 +687,18 @@ static void run_batches_graph(Index &ix, const int32_t *ids, const int64_t *st_h
     };
     if (nmax == 0) {
         VJ_HIP(hipStreamSynchronize(s));
-        make_results(nullptr, 0, {}, nullptr);
+        make_results(nullptr, 0, nullptr, nullptr);
         return;
     }
 
-    JoinWorkspace &jw = ix.jw;
-    jw.counters.reserve(64);
-    jw.args.reserve(sizeof(JoinArgs));
     if (!jw.pinned) VJ_HIP(hipHostMalloc(&jw.pinned, 4096, hipHostMallocDefault));
     if (!jw.capture) VJ_HIP(hipStreamCreateWithFlags(&jw.capture, hipStreamNonBlocking));
-    int32_t *ctr = jw.counters.as<int32_t>();
+    for (auto &e : jw.bev)
+        if (!e) VJ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // pinned staging: counters of slot k at [64 k, 64 k + 64), arguments at 256 + 1024 k
+    static_assert(sizeof(JoinArgs) <= 1024, "JoinArgs exceeds its pinned staging slot");
     int32_t *hctr = static_cast<int32_t *>(jw.pinned);
-    JoinArgs *args_h = reinterpret_cast<JoinArgs *>(static_cast<char *>(jw.pinned) + 256);
-    DevBuf descb(desc.size() * sizeof(BatchDesc));
-    DevBuf recb((size_t)nb * kBatchRec * sizeof(uint64_t));
-    // eleven lists of nmax slots: processing list and positions of the three
-    // launches, the overflow list of each, the batch's ids in caller order
-    // and their density buckets; then the bucket counts and offsets
     const bool dense = p.dense_first != 0;
-    DevBuf lists((size_t)nmax * 11 * sizeof(int32_t) + 2 * kOrderBuckets * sizeof(uint32_t));
-    int32_t *lq1 = lists.as<int32_t>(), *lp1 = lq1 + nmax, *lq2 = lp1 + nmax, *lp2 = lq2 + nmax;
-    int32_t *lq3 = lp2 + nmax, *lp3 = lq3 + nmax, *ovf1 = lp3 + nmax, *ovf2 = ovf1 + nmax;
-    int32_t *ovf3 = ovf2 + nmax, *lq0 = ovf3 + nmax, *bucket = lq0 + nmax;
-    uint32_t *hist = reinterpret_cast<uint32_t *>(bucket + nmax), *boff = hist + kOrderBuckets;
-    if (dense) VJ_HIP(hipMemsetAsync(hist, 0, kOrderBuckets * sizeof(uint32_t), s));
-    else iota_i32(lp1, nmax, s);
-    VJ_HIP(hipMemcpyAsync(descb.p, desc.data(), descb.bytes, hipMemcpyHostToDevice, s));
-
-    // global tables: the promotion regions of the first launch and the
-    // regions of the re-run share one buffer (the launches do not overlap)
     const bool small = p.coop_tables == 1;
     const int hl2 = std::min(16, ceil_log2(2 * ix.nx));
     const int ilc2 = (int)std::min<int64_t>(ix.nx, 1 << 15);
@@ -703,134 +706,243 @@ static void run_batches_graph(Index &ix, const int32_t *ids, const int64_t *st_h
     const int ilc1 = small ? (int)std::min<int64_t>(ix.nx, 1 << 14) : ilc2;
     const int promo_cap = (int)std::min<int64_t>(small ? 4096 : 1024, std::max<int64_t>(64, nmax / 16));
     const int g2 = (int)std::min<int64_t>(1024, nmax);
-    const size_t gh_n = std::max(((size_t)promo_cap) << hl1, ((size_t)g2) << hl2);
-    const size_t il_n = std::max((size_t)promo_cap * ilc1, (size_t)g2 * ilc2);
-    ix.ws_gh.reserve(gh_n * sizeof(int32_t));
-    ix.ws_gil.reserve(il_n * sizeof(int32_t));
-    ix.ws_gild.reserve(il_n * sizeof(float));
     const int g3 = (int)std::min<int64_t>(16, nmax);
     const int hl3 = ceil_log2(2 * ix.nx);
-    DevBuf gh3(((size_t)g3 << hl3) * sizeof(int32_t));
-    DevBuf gil3((size_t)g3 * ix.nx * sizeof(int32_t)), gild3((size_t)g3 * ix.nx * sizeof(float));
+    // global tables: the promotion regions of the first launch and the
+    // regions of the re-run share one buffer (the launches do not overlap)
+    const size_t gh_n = std::max(((size_t)promo_cap) << hl1, ((size_t)g2) << hl2);
+    const size_t il_n = std::max((size_t)promo_cap * ilc1, (size_t)g2 * ilc2);
 
-    auto launch = [&](int tier, const int32_t *lq, const int32_t *lp, const int32_t *cnt,
-                      int32_t *ovf, int32_t *ovf_cnt, hipStream_t cs) {
-        JoinLaunch L{};
-        L.args = jw.args.as<JoinArgs>();
-        L.qlist = lq;
-        L.qpos = lp;
-        L.first = 0;
-        L.count = (int)nmax;
-        L.count_dev = cnt;
-        L.dp = ix.dp;
-        L.prec = prec;
-        L.tier = tier;
-        L.coop_small = tier == 1 && small;
-        L.hyb = beam > 0;
-        L.ovf = ovf;
-        L.ovf_count = ovf_cnt;
-        L.gh = ix.ws_gh.as<int32_t>();
-        L.gil = ix.ws_gil.as<int32_t>();
-        L.gild = ix.ws_gild.as<float>();
+    // eleven lists of nmax slots per replay slot: processing list and
+    // positions of the three launches, the overflow list of each, the
+    // batch's ids in caller order and their density buckets; then the
+    // bucket counts and offsets
+    struct Lists {
+        int32_t *lq1, *lp1, *lq2, *lp2, *lq3, *lp3, *ovf1, *ovf2, *ovf3, *lq0, *bucket;
+        uint32_t *hist, *boff;
+    } L[kSlots];
+    for (int k = 0; k < nsl; ++k) {
+        BatchSlot &S = jw.bslot[k];
+        S.args.reserve(sizeof(JoinArgs));
+        S.counters.reserve(64);
+        S.desc.reserve(desc[k].size() * sizeof(BatchDesc));
+        S.rec.reserve(desc[k].size() * kBatchRec * sizeof(uint64_t));
+        S.lists.reserve((size_t)nmax * 11 * sizeof(int32_t) + 2 * kOrderBuckets * sizeof(uint32_t));
+        S.gh.reserve(gh_n * sizeof(int32_t));
+        S.gil.reserve(il_n * sizeof(int32_t));
+        S.gild.reserve(il_n * sizeof(float));
+        S.gh3.reserve(((size_t)g3 << hl3) * sizeof(int32_t));
+        S.gil3.reserve((size_t)g3 * ix.nx * sizeof(int32_t));
+        S.gild3.reserve((size_t)g3 * ix.nx * sizeof(float));
+        if (!S.stream) VJ_HIP(hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking));
+        Lists &l = L[k];
+        l.lq1 = S.lists.as<int32_t>();
+        l.lp1 = l.lq1 + nmax;
+        l.lq2 = l.lp1 + nmax;
+        l.lp2 = l.lq2 + nmax;
+        l.lq3 = l.lp2 + nmax;
+        l.lp3 = l.lq3 + nmax;
+        l.ovf1 = l.lp3 + nmax;
+        l.ovf2 = l.ovf1 + nmax;
+        l.ovf3 = l.ovf2 + nmax;
+        l.lq0 = l.ovf3 + nmax;
+        l.bucket = l.lq0 + nmax;
+        l.hist = reinterpret_cast<uint32_t *>(l.bucket + nmax);
+        l.boff = l.hist + kOrderBuckets;
+    }
+
+    auto launch = [&](BatchSlot &S, int tier, const int32_t *lq, const int32_t *lp,
+                      const int32_t *cnt, int32_t *ovf, int32_t *ovf_cnt, hipStream_t cs) {
+        JoinLaunch J{};
+        J.args = S.args.as<JoinArgs>();
+        J.qlist = lq;
+        J.qpos = lp;
+        J.first = 0;
+        J.count = (int)nmax;
+        J.count_dev = cnt;
+        J.dp = ix.dp;
+        J.prec = prec;
+        J.tier = tier;
+        J.coop_small = tier == 1 && small;
+        J.hyb = beam > 0;
+        J.ovf = ovf;
+        J.ovf_count = ovf_cnt;
+        J.gh = S.gh.as<int32_t>();
+        J.gil = S.gil.as<int32_t>();
+        J.gild = S.gild.as<float>();
         if (tier == 1) {
-            L.hash_log2 = hl1;
-            L.il_cap = ilc1;
-            L.promo_next = ctr + 4;
-            L.promo_cap = promo_cap;
+            J.hash_log2 = hl1;
+            J.il_cap = ilc1;
+            J.promo_next = S.counters.as<int32_t>() + 4;
+            J.promo_cap = promo_cap;
         } else if (tier == 2) {
-            L.hash_log2 = hl2;
-            L.il_cap = ilc2;
-            L.grid = g2;
+            J.hash_log2 = hl2;
+            J.il_cap = ilc2;
+            J.grid = g2;
         } else {
-            L.tier = 2;
-            L.gh = gh3.as<int32_t>();
-            L.gil = gil3.as<int32_t>();
-            L.gild = gild3.as<float>();
-            L.hash_log2 = hl3;
-            L.il_cap = (int)ix.nx;
-            L.grid = g3;
+            J.tier = 2;
+            J.gh = S.gh3.as<int32_t>();
+            J.gil = S.gil3.as<int32_t>();
+            J.gild = S.gild3.as<float>();
+            J.hash_log2 = hl3;
+            J.il_cap = (int)ix.nx;
+            J.grid = g3;
         }
-        VJ_CHECK(launch_join(L, cs), VJ_ERR_UNSUPPORTED, "no join kernel for this row width");
+        VJ_CHECK(launch_join(J, cs), VJ_ERR_UNSUPPORTED, "no join kernel for this row width");
     };
 
-    GraphGuard gg;
-    hipStream_t cs = jw.capture;
-    VJ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    try {
-        const BatchDesc *dd = descb.as<BatchDesc>();
-        uint64_t *rec = recb.as<uint64_t>();
-        batch_begin(dd, jw.args.as<JoinArgs>(), stats->as<int32_t>(), ctr, rec, cs);
+    // one batch step of slot k on stream cs
+    auto enqueue_step = [&](int k, hipStream_t cs) {
+        BatchSlot &S = jw.bslot[k];
+        const Lists &l = L[k];
+        int32_t *ctr = S.counters.as<int32_t>();
+        const BatchDesc *dd = S.desc.as<BatchDesc>();
+        uint64_t *rec = S.rec.as<uint64_t>();
         if (dense) {
-            batch_list(dd, ctr, ids, nmax, lq0, cs);
-            batch_order(ix.adj.as<int32_t>(), ix.elen.as<float>(), ix.R, ix.nx, ix.nq, lq0, ctr, nmax,
-                        bucket, hist, boff, lq1, lp1, cs);
+            batch_start(dd, S.args.as<JoinArgs>(), ctr, rec, nmax, ix.adj.as<int32_t>(),
+                        ix.elen.as<float>(), ix.R, ix.nx, ix.nq, l.lq0, l.bucket, l.hist, cs);
+            batch_order(l.lq0, ctr, nmax, l.bucket, l.hist, l.boff, l.lq1, l.lp1, cs);
         } else {
-            batch_list(dd, ctr, ids, nmax, lq1, cs);
+            batch_start(dd, S.args.as<JoinArgs>(), ctr, rec, nmax, ix.adj.as<int32_t>(),
+                        ix.elen.as<float>(), ix.R, ix.nx, ix.nq, l.lq1, nullptr, nullptr, cs);
         }
-        launch(1, lq1, lp1, ctr + kBatchCount, ovf1, ctr + 2, cs);
-        gather_slots_dev(lq1, lp1, ovf1, ctr + 2, nmax, lq2, lp2, cs);
-        launch(2, lq2, lp2, ctr + 2, ovf2, ctr + kBatchOvf2, cs);
-        gather_slots_dev(lq2, lp2, ovf2, ctr + kBatchOvf2, nmax, lq3, lp3, cs);
-        launch(3, lq3, lp3, ctr + kBatchOvf2, ovf3, ctr + kBatchOvf3, cs);
+        launch(S, 1, l.lq1, l.lp1, ctr + kBatchCount, l.ovf1, ctr + 2, cs);
+        gather_slots_dev(l.lq1, l.lp1, l.ovf1, ctr + 2, nmax, l.lq2, l.lp2, cs);
+        launch(S, 2, l.lq2, l.lp2, ctr + 2, l.ovf2, ctr + kBatchOvf2, cs);
+        gather_slots_dev(l.lq2, l.lp2, l.ovf2, ctr + kBatchOvf2, nmax, l.lq3, l.lp3, cs);
+        launch(S, 3, l.lq3, l.lp3, ctr + kBatchOvf2, l.ovf3, ctr + kBatchOvf3, cs);
         batch_end(ctr, rec, cs);
-        VJ_HIP(hipGetLastError());
-    } catch (...) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(cs, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
-    }
-    VJ_HIP(hipStreamEndCapture(cs, &gg.g));
-    VJ_HIP(hipGraphInstantiate(&gg.e, gg.g, nullptr, nullptr, 0));
-    gg.ev.assign((size_t)nb + 1, nullptr);
-    for (auto &e : gg.ev) VJ_HIP(hipEventCreate(&e));
+    };
 
-    int64_t cap = p.pair_capacity > 0 ? p.pair_capacity : std::max<int64_t>(1 << 16, total_q * 64);
-    std::vector<uint64_t> rec((size_t)nb * kBatchRec);
+    // the graph of each slot: kept while the launch shape and the buffers
+    // it names are the same
+    hipStream_t cs = jw.capture;
+    for (int k = 0; k < nsl && graph; ++k) {
+        BatchSlot &S = jw.bslot[k];
+        const Lists &l = L[k];
+        const std::vector<uint64_t> key = {
+            (uint64_t)steps, (uint64_t)nmax, (uint64_t)dense, (uint64_t)small, (uint64_t)prec,
+            (uint64_t)beam, (uint64_t)ix.dp, (uint64_t)(uintptr_t)ix.adj.p,
+            (uint64_t)(uintptr_t)ix.elen.p, (uint64_t)(uintptr_t)S.args.p,
+            (uint64_t)(uintptr_t)S.counters.p, (uint64_t)(uintptr_t)S.desc.p,
+            (uint64_t)(uintptr_t)S.rec.p, (uint64_t)(uintptr_t)S.lists.p, (uint64_t)(uintptr_t)S.gh.p,
+            (uint64_t)(uintptr_t)S.gil.p, (uint64_t)(uintptr_t)S.gild.p, (uint64_t)(uintptr_t)S.gh3.p,
+            (uint64_t)(uintptr_t)S.gil3.p, (uint64_t)(uintptr_t)S.gild3.p};
+        if (S.exec && S.key == key) continue;
+        if (S.exec) {
+            (void)hipGraphExecDestroy(S.exec);
+            S.exec = nullptr;
+            S.key.clear();
+        }
+        hipGraph_t g = nullptr;
+        VJ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+            for (int step = 0; step < steps; ++step) enqueue_step(k, cs);
+            VJ_HIP(hipGetLastError());
+        } catch (...) {
+            (void)hipStreamEndCapture(cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        VJ_HIP(hipStreamEndCapture(cs, &g));
+        const hipError_t e = hipGraphInstantiate(&S.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            S.exec = nullptr;
+            VJ_HIP(e);
+        }
+        S.key = key;
+    }
+
+    int64_t cap[kSlots];
+    // capacity: the caller's, else an estimate, at least what the slot's
+    // output buffer already holds (a call that outgrew it grew it)
+    for (int k = 0; k < kSlots; ++k)
+        cap[k] = p.pair_capacity > 0
+                     ? p.pair_capacity
+                     : std::max<int64_t>({1 << 16, total_q * 64 / nsl,
+                                          (int64_t)(jw.bslot[k].out_q.bytes / sizeof(int32_t))});
+    std::vector<uint64_t> rec[kSlots];
+    for (int k = 0; k < nsl; ++k) rec[k].assign(desc[k].size() * kBatchRec, 0);
     for (int attempt = 0; attempt < 4; ++attempt) {
-        jw.out_q.reserve((size_t)cap * sizeof(int32_t));
-        jw.out_x.reserve((size_t)cap * sizeof(int32_t));
-        jw.out_d.reserve((size_t)cap * sizeof(float));
-        JoinArgs a = make_args(ix, prec, p, beam, 0.f, nullptr, ctr);
-        a.out_q = jw.out_q.as<int32_t>();
-        a.out_x = jw.out_x.as<int32_t>();
-        a.out_d = jw.out_d.as<float>();
-        a.cap = cap;
-        a.stats = stats->as<int32_t>();
-        *args_h = a;
-        VJ_HIP(hipMemcpyAsync(jw.args.p, args_h, sizeof(a), hipMemcpyHostToDevice, s));
-        VJ_HIP(hipMemsetAsync(ctr, 0, 64, s));  // the cursor starts at batch 0
-        VJ_HIP(hipEventRecord(gg.ev[0], s));
-        for (int32_t b = 0; b < nb; ++b) {
-            VJ_HIP(hipGraphLaunch(gg.e, s));
-            VJ_HIP(hipEventRecord(gg.ev[(size_t)b + 1], s));
+        for (int k = 0; k < nsl; ++k) {
+            BatchSlot &S = jw.bslot[k];
+            int32_t *ctr = S.counters.as<int32_t>();
+            S.out_q.reserve((size_t)cap[k] * sizeof(int32_t));
+            S.out_x.reserve((size_t)cap[k] * sizeof(int32_t));
+            S.out_d.reserve((size_t)cap[k] * sizeof(float));
+            JoinArgs *args_h = reinterpret_cast<JoinArgs *>(static_cast<char *>(jw.pinned) + 256 + 1024 * k);
+            JoinArgs a = make_args(ix, prec, p, beam, 0.f, nullptr, ctr);
+            a.out_q = S.out_q.as<int32_t>();
+            a.out_x = S.out_x.as<int32_t>();
+            a.out_d = S.out_d.as<float>();
+            a.cap = cap[k];
+            a.stats = stats->as<int32_t>();
+            *args_h = a;
+            VJ_HIP(hipMemcpyAsync(S.args.p, args_h, sizeof(a), hipMemcpyHostToDevice, s));
+            VJ_HIP(hipMemcpyAsync(S.desc.p, desc[k].data(), desc[k].size() * sizeof(BatchDesc),
+                                  hipMemcpyHostToDevice, s));
+            VJ_HIP(hipMemsetAsync(ctr, 0, 64, s));  // the cursor starts at the slot's first batch
+            if (dense) VJ_HIP(hipMemsetAsync(L[k].hist, 0, kOrderBuckets * sizeof(uint32_t), s));
+            else iota_i32(L[k].lp1, nmax, s);
         }
-        std::memset(hctr, 0, 64);
-        VJ_HIP(hipMemcpyAsync(hctr, ctr, 64, hipMemcpyDeviceToHost, s));
-        VJ_HIP(hipMemcpyAsync(rec.data(), recb.p, recb.bytes, hipMemcpyDeviceToHost, s));
-        VJ_HIP(hipStreamSynchronize(s));
-        VJ_CHECK(!(hctr[3] & 8), VJ_ERR_INVALID_ARG, "query id out of range");
-        VJ_CHECK(!(hctr[3] & 16), VJ_ERR_INTERNAL, "visited-set probe exceeded the table size");
-        VJ_CHECK(!(hctr[3] & 32), VJ_ERR_INTERNAL, "a worklist entry is not a data node id");
-        VJ_CHECK(!(hctr[3] & 64), VJ_ERR_INTERNAL, "join tiers exhausted");
-        VJ_CHECK(hctr[kBatchCursor] == nb, VJ_ERR_INTERNAL, "batch replays incomplete");
-        const int64_t total = (int64_t)(((uint64_t)(uint32_t)hctr[1] << 32) | (uint32_t)hctr[0]);
-        if (total <= cap) {
-            // one block for the pairs of every batch: q, x and dist arrays
-            const size_t m = (size_t)std::max<int64_t>(total, 1);
-            auto block = std::make_shared<DevBuf>(m * (2 * sizeof(int32_t) + sizeof(float)));
-            if (total > 0) {
-                VJ_HIP(hipMemcpyAsync(block->p, jw.out_q.p, total * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-                VJ_HIP(hipMemcpyAsync(block->as<int32_t>() + m, jw.out_x.p, total * sizeof(int32_t),
-                                      hipMemcpyDeviceToDevice, s));
-                VJ_HIP(hipMemcpyAsync(block->as<float>() + 2 * m, jw.out_d.p, total * sizeof(float),
-                                      hipMemcpyDeviceToDevice, s));
+        VJ_HIP(hipEventRecord(jw.bev[0], s));
+        for (int k = 0; k < nsl; ++k) VJ_HIP(hipStreamWaitEvent(jw.bslot[k].stream, jw.bev[0], 0));
+        // alternate the slots' submissions so that both start early
+        for (int i = 0; i < std::max(launches[0], launches[1]); ++i)
+            for (int k = 0; k < nsl; ++k) {
+                if (i >= launches[k]) continue;
+                if (graph) VJ_HIP(hipGraphLaunch(jw.bslot[k].exec, jw.bslot[k].stream));
+                else enqueue_step(k, jw.bslot[k].stream);
             }
-            VJ_HIP(hipStreamSynchronize(s));
-            make_results(block, total, rec, &gg);
-            return;
+        VJ_HIP(hipGetLastError());
+        for (int k = 0; k < nsl; ++k) {
+            VJ_HIP(hipEventRecord(jw.bev[1 + k], jw.bslot[k].stream));
+            VJ_HIP(hipStreamWaitEvent(s, jw.bev[1 + k], 0));
         }
-        cap = total + total / 16 + 1024;
+        std::memset(hctr, 0, 64 * kSlots);
+        for (int k = 0; k < nsl; ++k) {
+            VJ_HIP(hipMemcpyAsync(hctr + 16 * k, jw.bslot[k].counters.p, 64, hipMemcpyDeviceToHost, s));
+            VJ_HIP(hipMemcpyAsync(rec[k].data(), jw.bslot[k].rec.p, rec[k].size() * sizeof(uint64_t),
+                                  hipMemcpyDeviceToHost, s));
+        }
+        VJ_HIP(hipStreamSynchronize(s));
+        int64_t tot[kSlots] = {0, 0};
+        bool fits = true;
+        for (int k = 0; k < nsl; ++k) {
+            const int32_t *hc = hctr + 16 * k;
+            VJ_CHECK(!(hc[3] & 8), VJ_ERR_INVALID_ARG, "query id out of range");
+            VJ_CHECK(!(hc[3] & 16), VJ_ERR_INTERNAL, "visited-set probe exceeded the table size");
+            VJ_CHECK(!(hc[3] & 32), VJ_ERR_INTERNAL, "a worklist entry is not a data node id");
+            VJ_CHECK(!(hc[3] & 64), VJ_ERR_INTERNAL, "join tiers exhausted");
+            VJ_CHECK(hc[kBatchCursor] == (int32_t)desc[k].size(), VJ_ERR_INTERNAL,
+                     "batch replays incomplete");
+            tot[k] = (int64_t)(((uint64_t)(uint32_t)hc[1] << 32) | (uint32_t)hc[0]);
+            if (tot[k] > cap[k]) {
+                fits = false;
+                cap[k] = tot[k] + tot[k] / 16 + 1024;
+            }
+        }
+        if (!fits) continue;
+        // one block for the pairs of every batch: q, x and dist arrays, the
+        // pairs of slot 0 then those of slot 1
+        const int64_t total = tot[0] + tot[1];
+        const int64_t base[kSlots] = {0, tot[0]};
+        const size_t m = (size_t)std::max<int64_t>(total, 1);
+        auto block = std::make_shared<DevBuf>(m * (2 * sizeof(int32_t) + sizeof(float)));
+        for (int k = 0; k < nsl; ++k) {
+            if (tot[k] == 0) continue;
+            const BatchSlot &S = jw.bslot[k];
+            VJ_HIP(hipMemcpyAsync(block->as<int32_t>() + base[k], S.out_q.p, tot[k] * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, s));
+            VJ_HIP(hipMemcpyAsync(block->as<int32_t>() + m + base[k], S.out_x.p,
+                                  tot[k] * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+            VJ_HIP(hipMemcpyAsync(block->as<float>() + 2 * m + base[k], S.out_d.p,
+                                  tot[k] * sizeof(float), hipMemcpyDeviceToDevice, s));
+        }
+        VJ_HIP(hipStreamSynchronize(s));
+        make_results(block, total, base, rec);
+        return;
     }
     VJ_CHECK(false, VJ_ERR_INTERNAL, "result capacity did not converge");
 }
@@ -1131,11 +1243,11 @@ vj_status vj_join_batches(vj_index *idx, const int32_t *query_ids, const int64_t
     API_END
 }
 
-vj_status vj_join_batches_graph(vj_index *idx, const int32_t *query_ids,
-                                const int64_t *batch_start_host, const int64_t *batch_count_host,
-                                const float *eps_host, int32_t n_batches, vj_metric metric,
-                                const vj_join_params *pp, void *stream, vj_pairs **out,
-                                float *batch_ms_host) {
+vj_status vj_join_batches_device(vj_index *idx, const int32_t *query_ids,
+                                 const int64_t *batch_start_host, const int64_t *batch_count_host,
+                                 const float *eps_host, int32_t n_batches, vj_metric metric,
+                                 const vj_join_params *pp, vj_submit submit, void *stream,
+                                 vj_pairs **out, float *batch_ms_host) {
     API_BEGIN
     check_batches(idx, query_ids, batch_start_host, batch_count_host, eps_host, n_batches, out);
     Index &ix = idx->impl;
@@ -1148,8 +1260,10 @@ vj_status vj_join_batches_graph(vj_index *idx, const int32_t *query_ids,
     for (int32_t b = 0; b < n_batches; ++b)
         VJ_CHECK(batch_count_host[b] < ((int64_t)1 << 31), VJ_ERR_UNSUPPORTED, "batch count must be < 2^31");
     std::vector<std::unique_ptr<vj_pairs>> res((size_t)n_batches);
-    run_batches_graph(ix, query_ids, batch_start_host, batch_count_host, eps_host, n_batches, p,
-                      (hipStream_t)stream, res, batch_ms_host);
+    VJ_CHECK(submit == VJ_SUBMIT_DIRECT || submit == VJ_SUBMIT_GRAPH, VJ_ERR_INVALID_ARG,
+             "submit is VJ_SUBMIT_DIRECT or VJ_SUBMIT_GRAPH");
+    run_batches_device(ix, query_ids, batch_start_host, batch_count_host, eps_host, n_batches, p,
+                       submit == VJ_SUBMIT_GRAPH, (hipStream_t)stream, res, batch_ms_host);
     for (int32_t b = 0; b < n_batches; ++b) out[b] = res[(size_t)b].release();
     API_END
 }

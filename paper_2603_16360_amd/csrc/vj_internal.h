@@ -85,12 +85,30 @@ struct DevBuf {
 int padded_dim(int d);
 
 // ----------------------------------------------------------------- index --
+// State of one replay slot of the graph batch runner (grow only): its
+// arguments, counters, descriptors, lists, global tables and output.
+struct BatchSlot {
+    DevBuf args, counters, desc, rec, lists, gh, gil, gild, gh3, gil3, gild3, out_q, out_x, out_d;
+    hipStream_t stream = nullptr;  // default priority, non-blocking
+    hipGraphExec_t exec = nullptr; // steps captured for the launch shape in `key`
+    std::vector<uint64_t> key;
+    BatchSlot() = default;
+    BatchSlot(const BatchSlot &) = delete;
+    BatchSlot &operator=(const BatchSlot &) = delete;
+    ~BatchSlot() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
 // Buffers of vj_join kept between calls on one index (grow only).
 struct JoinWorkspace {
     DevBuf qlist, qpos, counters, args, ovf, slots, out_q, out_x, out_d;
     DevBuf sort_keys, sort_keys2, sort_pos, sort_tmp;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipStream_t capture = nullptr;  // private stream the batch graph is captured on
+    hipStream_t capture = nullptr;  // private stream the batch graphs are captured on
+    BatchSlot bslot[2];             // the graph batch runner's two replay slots
+    hipEvent_t bev[1 + 2] = {};     // its events: the fork, one join per slot
     void *pinned = nullptr;  // 4 KiB of pinned host memory: counters read back, arguments sent
     JoinWorkspace() = default;
     JoinWorkspace(const JoinWorkspace &) = delete;
@@ -99,6 +117,7 @@ struct JoinWorkspace {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         if (capture) (void)hipStreamDestroy(capture);
+        for (auto e : bev) if (e) (void)hipEventDestroy(e);
         if (pinned) (void)hipHostFree(pinned);
     }
 };

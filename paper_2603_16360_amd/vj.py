@@ -77,8 +77,8 @@ _SIGS = {
     "vj_join_features": (C.c_int, [_vp, _vp, _i64, _f32, C.c_int, _vp, _vp]),
     "vj_join_batches": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _i32, C.c_int, C.POINTER(vj_join_params),
                                   _vp, _vp, _vp]),
-    "vj_join_batches_graph": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _i32, C.c_int,
-                                        C.POINTER(vj_join_params), _vp, _vp, _vp]),
+    "vj_join_batches_device": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _i32, C.c_int,
+                                         C.POINTER(vj_join_params), C.c_int, _vp, _vp, _vp]),
     "vj_autotune_join": (C.c_int, [_vp, _vp, _i64, _f32, C.c_int, C.POINTER(vj_join_params),
                                    _vp, _vp]),
     "vj_predictor_create": (C.c_int, [_i32, _i32, _i32, _i32, C.c_uint64, _vp, _PP]),
@@ -280,15 +280,17 @@ def vj_bruteforce_join(Q: torch.Tensor, X: torch.Tensor, eps: float, metric: str
 
 def vj_join_batches(index: Index, starts, counts, eps_list, metric: str = "l2",
                     query_ids: torch.Tensor | None = None, params: vj_join_params | None = None,
-                    graph: bool = False, **kw):
+                    runner: str = "host", **kw):
     """Run the batches back to back; returns (list of Pairs, ms per batch).
 
-    graph=False: one vj_join per batch, wall ms per batch.  graph=True:
-    vj_join_batches_graph (one captured HIP graph replayed per batch, self
-    mode), device ms per batch."""
+    runner="host": vj_join_batches, one vj_join per batch, wall ms per batch.
+    runner="device" / "graph": vj_join_batches_device (self mode, no host
+    synchronisation between batches) with direct launches / HIP graph
+    replay, device ms per batch."""
     if params is None:
         params = join_params(**kw)
-    fn = _lib.vj_join_batches_graph if graph else _lib.vj_join_batches
+    if runner not in ("host", "device", "graph"):
+        raise ValueError(f"runner must be host, device or graph, not {runner!r}")
     nb = len(starts)
     st = (C.c_int64 * nb)(*[int(v) for v in starts])
     ct = (C.c_int64 * nb)(*[int(v) for v in counts])
@@ -299,7 +301,13 @@ def vj_join_batches(index: Index, starts, counts, eps_list, metric: str = "l2",
     if query_ids is not None:
         query_ids = _dev(query_ids, torch.int32, "query_ids")
         qp = _ptr(query_ids)
-    _check(fn(index._h, qp, st, ct, ep, nb, METRIC[metric], C.byref(params), _stream(), out, ms))
+    if runner == "host":
+        _check(_lib.vj_join_batches(index._h, qp, st, ct, ep, nb, METRIC[metric], C.byref(params),
+                                    _stream(), out, ms))
+    else:
+        _check(_lib.vj_join_batches_device(index._h, qp, st, ct, ep, nb, METRIC[metric],
+                                           C.byref(params), int(runner == "graph"), _stream(), out,
+                                           ms))
     return [Pairs(out[b], int(counts[b])) for b in range(nb)], list(ms)
 
 
