@@ -102,8 +102,8 @@ typedef struct {
                                that outgrows a tier re-runs on the next.  Callers that know
                                their queries are large (high eps) skip the small tiers. */
     int32_t coop_tables;    /* LDS tables of the workgroup tier (0): 0 large (8192 visited
-                               slots, 1536 pairs, 3 workgroups per CU), 1 small (4096 slots,
-                               1024 pairs, 4 workgroups per CU); same results either way */
+                               slots, 768 pairs), 1 small (4096 slots, 1024 pairs); both
+                               run 4 workgroups per CU; same results either way */
     int64_t pair_capacity;  /* initial result capacity hint (0: auto) */
     int32_t dense_first;    /* self mode (1): launch queries in ascending order of d1, the mean
                                stored length of their edges to data nodes -- dense
@@ -161,7 +161,7 @@ void vj_index_free(vj_index *idx);
  * one wavefront with its visited set, worklist and pairs in LDS (1024-slot
  * visited set, 512 pairs, four waves per workgroup); a query that outgrows
  * them is re-run by a whole workgroup of four waves on 8192 LDS slots and
- * 1536 pairs (the default first tier), then on tables in global memory
+ * 768 pairs (the default first tier), then on tables in global memory
  * (2^16 slots and 32768 pairs: within the same launch while the index's
  * regions last, else in a re-run launch; then as large as the data set).
  * Calls on one

@@ -88,8 +88,9 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-__device__ __forceinline__ uint32_t slot_of(int32_t v, int log2n) {
-    return ((uint32_t)v * 0x9E3779B1u) >> (32 - log2n);
+// multiplicative hash scaled to [0, n) (for n = 2^k: its top k bits)
+__device__ __forceinline__ uint32_t slot_of(int32_t v, uint32_t n) {
+    return (uint32_t)(((uint64_t)((uint32_t)v * 0x9E3779B1u) * n) >> 32);
 }
 
 // wave-wide (key, id, index) reduction keeping the min or the max by (key, id)
@@ -118,7 +119,7 @@ struct QState {
 // Everything one wave needs to touch: LDS or spill regions, plus the query.
 struct WaveMem {
     int32_t *hash;   // visited set (LDS or global)
-    int hash_log2, hash_limit;
+    int hash_n, hash_limit;  // slots (any size), nodes it may hold
     int32_t *il;     // in-range worklist ids
     float *ild;      // their distance keys
     int il_cap;
@@ -134,8 +135,8 @@ struct WaveMem {
 __device__ __forceinline__ bool visit(const JoinArgs &a, const WaveMem &m, bool &abort, int32_t v,
                                       bool active) {
     bool isnew = false;
-    const int n = 1 << m.hash_log2;
-    uint32_t h = slot_of(v, m.hash_log2);
+    const int n = m.hash_n;
+    uint32_t h = slot_of(v, (uint32_t)n);
     int probes = 0;
     for (int it = 0; it <= n; ++it) {
         if (__ballot(active) == 0) break;
@@ -147,7 +148,7 @@ __device__ __forceinline__ bool visit(const JoinArgs &a, const WaveMem &m, bool 
                 const int old = atomicCAS(&m.hash[h], -1, v);
                 if (old == -1) { isnew = true; active = false; }
                 else if (old == v) active = false;
-                else h = (h + 1) & (uint32_t)(n - 1);
+                else h = h + 1 == (uint32_t)n ? 0u : h + 1;
             }
         }
     }
@@ -368,7 +369,7 @@ __device__ __forceinline__ void run_query(const JoinArgs &a, const WaveMem &m, i
             }
         }
     }
-    for (int i = lane; i < (1 << m.hash_log2); i += 64) m.hash[i] = -1;
+    for (int i = lane; i < m.hash_n; i += 64) m.hash[i] = -1;
     wave_sync();
 
     QState s{};
@@ -554,7 +555,7 @@ k_join_lds(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t 
     const JoinArgs &a = *pa;
     WaveMem m;
     m.hash = sh_hash[wib];
-    m.hash_log2 = HL;
+    m.hash_n = 1 << HL;
     m.hash_limit = (1 << HL) * 3 / 4 - 64;
     m.il = sh_il[wib];
     m.ild = sh_ild[wib];
@@ -831,7 +832,7 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
             }
         }
     }
-    for (int i = threadIdx.x; i < (1 << m.hash_log2); i += 64 * W) m.hash[i] = -1;
+    for (int i = threadIdx.x; i < m.hash_n; i += 64 * W) m.hash[i] = -1;
     if (threadIdx.x == 0) {
         sh.tail = 0; sh.hc = 0; sh.nvis = 0; sh.abort = 0;
         sh.hyb = 0; sh.ood = 0;
@@ -932,7 +933,7 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
     int head = 0, unprod = 0, before = 0, hpops = 0, nexp = 0;
     bool pending = false;
     const int budget = a.hyb == VJ_HYB_BUDGET ? a.budget[pos] : 0;
-    const int bound = m.il_cap + (1 << m.hash_log2) + 4;
+    const int bound = m.il_cap + m.hash_n + 4;
     // candidates of this wave's nodes in round `head`, from [h, h + n) of
     // the list (lane b * R + j: neighbour j of node h + b)
     auto candidates = [&](int h, int n) -> int32_t {
@@ -1092,7 +1093,7 @@ struct GlobalTables {
 
 __device__ __forceinline__ void use_global(WaveMem &m, const GlobalTables &g, size_t r) {
     m.hash = g.gh + (r << g.hash_log2);
-    m.hash_log2 = g.hash_log2;
+    m.hash_n = 1 << g.hash_log2;
     m.hash_limit = (1 << g.hash_log2) / 2;
     m.il = g.gil + r * (size_t)g.il_cap;
     m.ild = g.gild + r * (size_t)g.il_cap;
@@ -1103,12 +1104,12 @@ __device__ __forceinline__ void use_global(WaveMem &m, const GlobalTables &g, si
 // and LIST in-range entries in LDS.  A query that outgrows them takes a free
 // region of global tables (if any is left) and runs again in this launch;
 // otherwise, or if it outgrows those too, its slot goes to the overflow list.
-template <typename T, int DP, bool HYB, int HL, int LIST, int W, int PGC, int MINW>
+template <typename T, int DP, bool HYB, int HS, int LIST, int W, int PGC, int MINW>
 __global__ void __launch_bounds__(64 * W, MINW)
 k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos, int k0,
             int k1, const int32_t *cnt_dev, GlobalTables g, int32_t *ovf, int32_t *ovf_count) {
     constexpr int HC = HYB ? kBeamMax + 64 * W : 1;
-    __shared__ int32_t sh_hash[1 << HL];
+    __shared__ int32_t sh_hash[HS];
     __shared__ int32_t sh_il[LIST];
     __shared__ float sh_ild[LIST];
     __shared__ int32_t sh_stage[W][64];
@@ -1123,8 +1124,8 @@ k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t
     const JoinArgs &a = *pa;
     WaveMem m;
     m.hash = sh_hash;
-    m.hash_log2 = HL;
-    m.hash_limit = (1 << HL) * 3 / 4 - 64 * W;
+    m.hash_n = HS;
+    m.hash_limit = HS * 3 / 4 - 64 * W;
     m.il = sh_il;
     m.ild = sh_ild;
     m.il_cap = LIST;
@@ -1198,19 +1199,20 @@ void launch_tier(const JoinLaunch &L, hipStream_t s) {
         g.il_cap = L.il_cap;
         g.next = L.promo_next;
         g.cap = L.promo_cap;
-        // workgroup tier: large LDS tables (8,192 slots, 1,536 pairs; three
-        // workgroups per CU) or small ones (4,096 slots, 1,024 pairs; four
-        // workgroups per CU, registers capped for four waves per SIMD up to
-        // 256-wide rows)
+        // workgroup tier: large LDS tables (8,192 visited slots, 768 in-range
+        // pairs: 40 KB, four workgroups per CU) or small ones (4,096 slots,
+        // 1,024 pairs); both cap registers at 128 for four waves per SIMD
+        // up to 256-wide rows.  The visited set fills first: a query visits
+        // about 15 nodes per in-range node
         // grid: one workgroup per slot, or L.grid workgroups looping over
         // the slots (global tables: one region per workgroup)
         const unsigned blocks = (unsigned)(L.grid > 0 ? L.grid : L.count);
         if (L.tier == 1 && L.coop_small)
-            hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 12, 1024, kWaves, 12, (DP <= 256 ? 4 : 1)>),
+            hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 4096, 1024, kWaves, 12, (DP <= 256 ? 4 : 1)>),
                                dim3((unsigned)L.count), dim3(64 * kWaves), 0, s, L.args, L.qlist,
                                L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count);
         else if (L.tier == 1)
-            hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 13, 1536, kWaves, 16, 1>),
+            hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 8192, 768, kWaves, 12, (DP <= 256 ? 4 : 1)>),
                                dim3((unsigned)L.count), dim3(64 * kWaves), 0, s, L.args, L.qlist,
                                L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count);
         else

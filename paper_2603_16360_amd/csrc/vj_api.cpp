@@ -395,7 +395,8 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
                     global_regions(L.promo_cap, std::min(15, ceil_log2(2 * ix.nx)),
                                    (int)std::min<int64_t>(ix.nx, 1 << 14));
                 } else {
-                    L.promo_cap = (int)std::min<int64_t>(1024, std::max<int64_t>(64, cnt / 16));
+                    // about 1.5 % of the queries outgrow the large LDS tables
+                    L.promo_cap = (int)std::min<int64_t>(4096, std::max<int64_t>(64, cnt / 32));
                     global_regions(L.promo_cap, hl2, ilc2);
                 }
                 L.promo_next = ctr + 4;
@@ -704,7 +705,7 @@ static void run_batches_device(Index &ix, const int32_t *ids, const int64_t *st_
     const int ilc2 = (int)std::min<int64_t>(ix.nx, 1 << 15);
     const int hl1 = small ? std::min(15, ceil_log2(2 * ix.nx)) : hl2;
     const int ilc1 = small ? (int)std::min<int64_t>(ix.nx, 1 << 14) : ilc2;
-    const int promo_cap = (int)std::min<int64_t>(small ? 4096 : 1024, std::max<int64_t>(64, nmax / 16));
+    const int promo_cap = (int)std::min<int64_t>(4096, std::max<int64_t>(64, small ? nmax / 16 : nmax / 32));
     const int g2 = (int)std::min<int64_t>(1024, nmax);
     const int g3 = (int)std::min<int64_t>(16, nmax);
     const int hl3 = ceil_log2(2 * ix.nx);
