@@ -580,6 +580,7 @@ k_join_lds(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t 
 
 template <int W> struct CoopShared {
     int tail, hc, nvis, abort;  // live counters (LDS atomics)
+    int head, busy;             // BFS without rounds: next unclaimed entry, waves holding work
     int s_tail, s_hc, s_abort;  // snapshot written by wave 0 between barriers
     int hyb, ood;               // CheckHybrid decision of wave 0
     int ndist[W], nexp[W];
@@ -833,9 +834,13 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
         }
     }
     for (int i = threadIdx.x; i < m.hash_n; i += 64 * W) m.hash[i] = -1;
+    // list entries start unwritten (-1): without rounds a wave may claim an
+    // entry whose slot is reserved but not yet written
+    for (int i = threadIdx.x; i < m.il_cap; i += 64 * W) m.il[i] = -1;
     if (threadIdx.x == 0) {
         sh.tail = 0; sh.hc = 0; sh.nvis = 0; sh.abort = 0;
         sh.hyb = 0; sh.ood = 0;
+        sh.head = 0; sh.busy = W;
     }
     __syncthreads();
 
@@ -928,7 +933,8 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
     const bool hyb = sh.hyb != 0;
     const bool hyb_active = hyb && a.beam > 0;
 
-    // ---- ExpansionPhase in rounds
+    // ---- ExpansionPhase: BFS without rounds; hybrid in rounds (its queue
+    // pops need the same snapshot in every wave)
     const int NB = 64 / R;
     int head = 0, unprod = 0, before = 0, hpops = 0, nexp = 0;
     bool pending = false;
@@ -946,9 +952,98 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
         }
         return v;
     };
+    if (!hyb_active) {
+        // BFS without rounds: the closure does not depend on the order of
+        // expansion, so each wave claims the next NB listed nodes (LDS
+        // compare-and-swap on head) and expands them as soon as they are
+        // listed.  busy counts the waves that hold work (and may append):
+        // a wave leaves when it reads busy == 0 and then nothing unclaimed.
+        // Every wait is bounded (error flag 128 and abort past the bound).
+        bool busy = true;
+        int idle = 0;
+        // claim the next NB listed nodes (lane 0; n = 0 when none is listed)
+        auto claim = [&](int &h, int &n) {
+            h = 0;
+            n = 0;
+            if (lane == 0) {
+                int hh = lds_load(&sh.head);
+                for (;;) {
+                    const int tt = min(lds_load(&sh.tail), m.il_cap);
+                    if (hh >= tt) break;
+                    const int take = min(NB, tt - hh);
+                    const int old = atomicCAS(&sh.head, hh, hh + take);
+                    if (old == hh) { h = hh; n = take; break; }
+                    hh = old;
+                }
+            }
+            h = uni(h);
+            n = uni(n);
+        };
+        // candidates of claimed nodes [h, h + n): lane b * R + j loads
+        // neighbour j of node h + b once its entry is written
+        auto load = [&](int h, int n, bool &stuck) -> int32_t {
+            const int b = lane / R, j = lane - b * R;
+            int32_t v = -1;
+            if (b < n) {
+                int32_t u = lds_load(&m.il[h + b]);
+                for (int spin = 0; u < 0; ++spin) {
+                    if (lds_load(&sh.abort)) break;
+                    if (spin >= (1 << 20)) { stuck = true; break; }
+                    __builtin_amdgcn_s_sleep(1);
+                    u = lds_load(&m.il[h + b]);
+                }
+                if (u >= 0 && u < a.nx) v = a.adj[(size_t)u * R + j];
+                else if (u >= 0) atomicOr(a.err, 32);
+            }
+            return v;
+        };
+        for (;;) {
+            if (uni(lds_load(&sh.abort))) break;
+            int h, n;
+            claim(h, n);
+            if (n > 0) {
+                idle = 0;
+                bool stuck = false;
+                const int32_t v = load(h, n, stuck);
+                if (__ballot(stuck)) {
+                    if (lane == 0) { atomicOr(a.err, 128); atomicOr(&sh.abort, 1); }
+                    break;
+                }
+                nexp += n;
+                coop_batch<T, DP, W, PGC>(a, m, sh, cw, qf, v, false, false, heap_cap, lane);
+                continue;
+            }
+            // nothing to claim: idle until work is listed or every wave is idle
+            if (busy) {
+                if (lane == 0) atomicSub(&sh.busy, 1);
+                busy = false;
+            }
+            int bz = 0, hh = 0, tt = 0;
+            if (lane == 0) {
+                bz = lds_load(&sh.busy);
+                hh = lds_load(&sh.head);
+                tt = min(lds_load(&sh.tail), m.il_cap);
+            }
+            bz = uni(bz);
+            hh = uni(hh);
+            tt = uni(tt);
+            if (hh < tt) {
+                if (lane == 0) atomicAdd(&sh.busy, 1);
+                busy = true;
+                continue;
+            }
+            if (bz == 0) break;
+            if (++idle > (1 << 20)) {
+                if (lane == 0) { atomicOr(a.err, 128); atomicOr(&sh.abort, 1); }
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (busy && lane == 0) atomicSub(&sh.busy, 1);
+    }
     int32_t pre_v = -1;  // candidates loaded one round ahead
     int pre_head = -1;   // the round (list head) they belong to
-    for (int round = 0; round < bound; ++round) {
+    for (int round = 0; round < bound && hyb_active; ++round) {
         __syncthreads();
         if (wib == 0) {
             if (hyb_active) {

@@ -473,6 +473,7 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
             }
             VJ_CHECK(!(hctr[3] & 16), VJ_ERR_INTERNAL, "visited-set probe exceeded the table size");
             VJ_CHECK(!(hctr[3] & 32), VJ_ERR_INTERNAL, "a worklist entry is not a data node id");
+            VJ_CHECK(!(hctr[3] & 128), VJ_ERR_INTERNAL, "a join wave waited past its bound");
         }
         const int64_t total = (int64_t)(((uint64_t)(uint32_t)hctr[1] << 32) | (uint32_t)hctr[0]);
         if (total <= cap) {
@@ -916,6 +917,7 @@ static void run_batches_device(Index &ix, const int32_t *ids, const int64_t *st_
             VJ_CHECK(!(hc[3] & 16), VJ_ERR_INTERNAL, "visited-set probe exceeded the table size");
             VJ_CHECK(!(hc[3] & 32), VJ_ERR_INTERNAL, "a worklist entry is not a data node id");
             VJ_CHECK(!(hc[3] & 64), VJ_ERR_INTERNAL, "join tiers exhausted");
+            VJ_CHECK(!(hc[3] & 128), VJ_ERR_INTERNAL, "a join wave waited past its bound");
             VJ_CHECK(hc[kBatchCursor] == (int32_t)desc[k].size(), VJ_ERR_INTERNAL,
                      "batch replays incomplete");
             tot[k] = (int64_t)(((uint64_t)(uint32_t)hc[1] << 32) | (uint32_t)hc[0]);

@@ -196,7 +196,7 @@ struct JoinArgs {
     int64_t cap;
     unsigned long long *out_count;
     int32_t *stats;           // [n][8] by caller position
-    int32_t *err;             // bit flags
+    int32_t *err;             // bit flags: 8 query id out of range, 16 probe past the table, 32 list entry not a data id, 64 tiers exhausted (batch steps), 128 a wave waited past its bound
 };
 
 // One launch over a contiguous piece of the processing list.
