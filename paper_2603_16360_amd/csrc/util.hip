@@ -120,28 +120,6 @@ __global__ void k_depth_keys(const int32_t *depth, int64_t nq, const int32_t *id
     pos[i] = (int32_t)i;
 }
 
-// key of query q: the bits of d1 = mean length of its edges to data nodes
-// (the stored edge lengths; +inf without data neighbours, all ones for an
-// invalid id), so that an ascending sort puts dense neighbourhoods first
-__global__ void k_density_keys(const int32_t *adj, const float *elen, int R, int64_t nx,
-                               int64_t nq, const int32_t *ids, int64_t n, uint32_t *keys,
-                               int32_t *pos) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t q = ids ? ids[i] : (int32_t)i;
-    pos[i] = (int32_t)i;
-    if (q < 0 || q >= nq) { keys[i] = 0xffffffffu; return; }
-    const int64_t u = nx + q;
-    float sum = 0.f;
-    int c = 0;
-    for (int j = 0; j < R; ++j) {
-        const int32_t y = adj[u * R + j];
-        if (y >= 0 && y < nx) { sum += elen[u * R + j]; ++c; }
-    }
-    const float d1 = c ? sum / (float)c : INFINITY;
-    keys[i] = __float_as_uint(d1);  // non-negative floats order as their bits
-}
-
 __global__ void k_gather_ids(const int32_t *ids, const int32_t *pos, int64_t n, int32_t *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -189,10 +167,11 @@ __device__ __forceinline__ int density_bucket(const int32_t *adj, const float *e
 // per-batch counters cleared, where its pairs begin and the clock.  Every
 // thread i < count writes the batch's query id i to qlist and, when ordering
 // densest first, its d1 bucket (counted in hist).
-__global__ void k_batch_start(const BatchDesc *desc, JoinArgs *args, int32_t *ctr, uint64_t *rec,
-                              int64_t nmax, const int32_t *adj, const float *elen, int R,
-                              int64_t nx, int64_t nq, int32_t *qlist, int32_t *bucket,
-                              uint32_t *hist) {
+__global__ void __launch_bounds__(256)
+k_batch_start(const BatchDesc *desc, JoinArgs *args, int32_t *ctr, uint64_t *rec, int64_t nmax,
+              const int32_t *adj, const float *elen, int R, int64_t nx, int64_t nq,
+              int32_t *qlist, int32_t *bucket, uint32_t *hist) {
+    __shared__ uint32_t lh[kOrderBuckets];
     const int b = ctr[kBatchCursor];
     const BatchDesc d = desc[b];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -209,14 +188,24 @@ __global__ void k_batch_start(const BatchDesc *desc, JoinArgs *args, int32_t *ct
         rec[kBatchRec * b + 6] = (uint64_t)wall_clock64();
     }
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nmax || i >= d.count) return;
-    const int32_t q = d.ids ? d.ids[d.start + i] : (int32_t)(d.start + i);
-    qlist[i] = q;
-    if (bucket) {
+    const bool ok = i < nmax && i < d.count;
+    int32_t q = 0;
+    if (ok) {
+        q = d.ids ? d.ids[d.start + i] : (int32_t)(d.start + i);
+        qlist[i] = q;
+    }
+    if (bucket == nullptr) return;  // the same for every thread
+    // bucket counts: per workgroup in LDS, then one global atomic per bucket
+    for (int k = threadIdx.x; k < kOrderBuckets; k += blockDim.x) lh[k] = 0u;
+    __syncthreads();
+    if (ok) {
         const int k = density_bucket(adj, elen, R, nx, nq, q);
         bucket[i] = k;
-        atomicAdd(&hist[k], 1u);
+        atomicAdd(&lh[k], 1u);
     }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kOrderBuckets; k += blockDim.x)
+        if (lh[k]) atomicAdd(&hist[k], lh[k]);
 }
 
 // one workgroup of 1024 threads, 4 buckets each: off = exclusive scan of
@@ -245,13 +234,69 @@ __global__ void __launch_bounds__(1024) k_batch_scan(uint32_t *hist, uint32_t *o
     }
 }
 
-__global__ void k_batch_scatter(const int32_t *qlist, const int32_t *ctr, int64_t nmax,
-                                const int32_t *bucket, uint32_t *off, int32_t *q2, int32_t *p2) {
+// slot i goes to off[bucket] + its rank: each workgroup reserves one range
+// per bucket (one global atomic per bucket), ranks come from LDS counters
+__device__ __forceinline__ void scatter_ranked(bool ok, int k, uint32_t *off, uint32_t *lh,
+                                               uint32_t *lb, uint32_t &p) {
+    for (int j = threadIdx.x; j < kOrderBuckets; j += blockDim.x) lh[j] = 0u;
+    __syncthreads();
+    uint32_t r = 0;
+    if (ok) r = atomicAdd(&lh[k], 1u);
+    __syncthreads();
+    for (int j = threadIdx.x; j < kOrderBuckets; j += blockDim.x)
+        if (lh[j]) lb[j] = atomicAdd(&off[j], lh[j]);
+    __syncthreads();
+    if (ok) p = lb[k] + r;
+}
+
+__global__ void __launch_bounds__(256)
+k_batch_scatter(const int32_t *qlist, const int32_t *ctr, int64_t nmax, const int32_t *bucket,
+                uint32_t *off, int32_t *q2, int32_t *p2) {
+    __shared__ uint32_t lh[kOrderBuckets], lb[kOrderBuckets];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nmax || i >= ctr[kBatchCount]) return;
-    const uint32_t p = atomicAdd(&off[bucket[i]], 1u);
-    q2[p] = qlist[i];
-    p2[p] = (int32_t)i;
+    const bool ok = i < nmax && i < ctr[kBatchCount];
+    const int k = ok ? bucket[i] : 0;
+    uint32_t p = 0;
+    scatter_ranked(ok, k, off, lh, lb, p);
+    if (ok) {
+        q2[p] = qlist[i];
+        p2[p] = (int32_t)i;
+    }
+}
+
+// densest first for one join: the d1 bucket of each slot, counted per
+// workgroup in LDS (one global atomic per bucket and workgroup)
+__global__ void __launch_bounds__(256)
+k_density_buckets(const int32_t *adj, const float *elen, int R, int64_t nx, int64_t nq,
+                  const int32_t *ids, int64_t n, int32_t *bucket, uint32_t *hist) {
+    __shared__ uint32_t lh[kOrderBuckets];
+    for (int k = threadIdx.x; k < kOrderBuckets; k += blockDim.x) lh[k] = 0u;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int k = density_bucket(adj, elen, R, nx, nq, ids ? ids[i] : (int32_t)i);
+        bucket[i] = k;
+        atomicAdd(&lh[k], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kOrderBuckets; k += blockDim.x)
+        if (lh[k]) atomicAdd(&hist[k], lh[k]);
+}
+
+// ... and each slot placed after the slots of lower buckets
+__global__ void __launch_bounds__(256)
+k_bucket_scatter(const int32_t *ids, int64_t n, const int32_t *bucket, uint32_t *off,
+                 int32_t *qlist, int32_t *qpos) {
+    __shared__ uint32_t lh[kOrderBuckets], lb[kOrderBuckets];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = i < n;
+    const int k = ok ? bucket[i] : 0;
+    uint32_t p = 0;
+    scatter_ranked(ok, k, off, lh, lb, p);
+    if (ok) {
+        qlist[p] = ids ? ids[i] : (int32_t)i;
+        qpos[p] = (int32_t)i;
+    }
 }
 
 // end of the batch step: where its pairs end, how many queries each re-run
@@ -397,19 +442,21 @@ void order_by_depth(const int32_t *depth, int64_t nq, const int32_t *ids, int64_
 void order_by_density(const int32_t *adj, const float *elen, int R, int64_t nx, int64_t nq,
                       const int32_t *ids, int64_t n, int32_t *qlist, int32_t *qpos, DevBuf &keys,
                       DevBuf &keys2, DevBuf &pos, DevBuf &tmp, hipStream_t s) {
+    (void)keys2;
+    (void)pos;
     if (n == 0) return;
-    keys.reserve(n * sizeof(uint32_t));
-    keys2.reserve(n * sizeof(uint32_t));
-    pos.reserve(n * sizeof(int32_t));
-    hipLaunchKernelGGL(k_density_keys, dim3(grid1(n)), dim3(256), 0, s, adj, elen, R, nx, nq, ids, n,
-                       keys.as<uint32_t>(), pos.as<int32_t>());
-    size_t bytes = 0;
-    VJ_HIP(rocprim::radix_sort_pairs(nullptr, bytes, keys.as<uint32_t>(), keys2.as<uint32_t>(),
-                                     pos.as<int32_t>(), qpos, (size_t)n, 0, 32, s));
-    tmp.reserve(bytes);
-    VJ_HIP(rocprim::radix_sort_pairs(tmp.p, bytes, keys.as<uint32_t>(), keys2.as<uint32_t>(),
-                                     pos.as<int32_t>(), qpos, (size_t)n, 0, 32, s));
-    hipLaunchKernelGGL(k_gather_ids, dim3(grid1(n)), dim3(256), 0, s, ids, qpos, n, qlist);
+    // d1 buckets (4,096, about 6 % wide) counted, scanned and scattered: the
+    // order only has to start dense neighbourhoods first, and three small
+    // kernels cost less than a radix sort
+    keys.reserve(n * sizeof(int32_t));
+    tmp.reserve(2 * kOrderBuckets * sizeof(uint32_t));
+    uint32_t *hist = tmp.as<uint32_t>(), *off = hist + kOrderBuckets;
+    VJ_HIP(hipMemsetAsync(hist, 0, kOrderBuckets * sizeof(uint32_t), s));
+    hipLaunchKernelGGL(k_density_buckets, dim3(grid1(n)), dim3(256), 0, s, adj, elen, R, nx, nq, ids,
+                       n, keys.as<int32_t>(), hist);
+    hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(1024), 0, s, hist, off);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(grid1(n)), dim3(256), 0, s, ids, n, keys.as<int32_t>(),
+                       off, qlist, qpos);
     VJ_HIP(hipGetLastError());
 }
 
