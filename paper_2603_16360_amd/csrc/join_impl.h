@@ -789,7 +789,9 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
 // Runs slot k of the processing list on the tables of m.  Returns true
 // (in every thread) when the query outgrew them: nothing was written but
 // its stats row, and the caller re-runs it on larger tables.
-template <typename T, int DP, int W, int PGC>
+// HYB: the kernel may run hybrid queries (an out-range queue); without it
+// the hybrid code is compiled out
+template <typename T, int DP, int W, int PGC, bool HYB>
 __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem &m,
                                                CoopShared<W> &sh, int heap_cap, int k,
                                                const int32_t *qlist, const int32_t *qpos,
@@ -931,7 +933,7 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
     }
     __syncthreads();
     const bool hyb = sh.hyb != 0;
-    const bool hyb_active = hyb && a.beam > 0;
+    const bool hyb_active = HYB && hyb && a.beam > 0;
 
     // ---- ExpansionPhase: BFS without rounds; hybrid in rounds (its queue
     // pops need the same snapshot in every wave)
@@ -1229,14 +1231,14 @@ k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t
     m.hi = sh_hi;
     m.aux = sh_aux[kIsBf16<T> ? threadIdx.x >> 6 : 0];
     m.auxf = sh_auxf[kIsBf16<T> ? threadIdx.x >> 6 : 0];
-    if (!run_query_coop<T, DP, W, PGC>(a, m, sh, HC, k, qlist, qpos, 1)) return;
+    if (!run_query_coop<T, DP, W, PGC, HYB>(a, m, sh, HC, k, qlist, qpos, 1)) return;
     if (threadIdx.x == 0) sh_region = g.cap > 0 ? atomicAdd(g.next, 1) : 0;
     __syncthreads();
     const int r = sh_region;
     bool again = true;
     if (r < g.cap) {
         use_global(m, g, (size_t)r);
-        again = run_query_coop<T, DP, W, PGC>(a, m, sh, HC, k, qlist, qpos, 1 | 8);
+        again = run_query_coop<T, DP, W, PGC, HYB>(a, m, sh, HC, k, qlist, qpos, 1 | 8);
     }
     if (again && threadIdx.x == 0) ovf[atomicAdd(ovf_count, 1)] = k;
 }
@@ -1267,7 +1269,7 @@ k_join_coop_global(const JoinArgs *__restrict__ pa, const int32_t *qlist, const 
     m.aux = sh_aux[kIsBf16<T> ? threadIdx.x >> 6 : 0];
     m.auxf = sh_auxf[kIsBf16<T> ? threadIdx.x >> 6 : 0];
     for (int k = k0 + (int)blockIdx.x; k < kend; k += (int)gridDim.x) {
-        if (run_query_coop<T, DP, W, PGC>(a, m, sh, HC, k, qlist, qpos, 1 | 8 | 16) &&
+        if (run_query_coop<T, DP, W, PGC, HYB>(a, m, sh, HC, k, qlist, qpos, 1 | 8 | 16) &&
             threadIdx.x == 0)
             ovf[atomicAdd(ovf_count, 1)] = k;
         __syncthreads();  // the next query clears the region's tables
