@@ -1308,10 +1308,20 @@ void launch_tier(const JoinLaunch &L, hipStream_t s) {
             hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 4096, 1024, kWaves, 12, (DP <= 256 ? 4 : 1)>),
                                dim3((unsigned)L.count), dim3(64 * kWaves), 0, s, L.args, L.qlist,
                                L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count);
-        else if (L.tier == 1)
-            hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 8192, 768, kWaves, 12, (DP <= 256 ? 4 : 1)>),
-                               dim3((unsigned)L.count), dim3(64 * kWaves), 0, s, L.args, L.qlist,
-                               L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count);
+        else if (L.tier == 1) {
+            if constexpr (kIsBf16<T> && DP <= 256)
+                // bf16 rows: the re-check buffers take 2 KB of LDS and the
+                // margin registers, so 7,680 visited slots and 4 loads per
+                // lane in flight keep four workgroups per CU (a row takes at
+                // most 4 loads per lane up to 256 wide)
+                hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 7680, 768, kWaves, 4, 4>),
+                                   dim3((unsigned)L.count), dim3(64 * kWaves), 0, s, L.args,
+                                   L.qlist, L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count);
+            else
+                hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 8192, 768, kWaves, 12, (DP <= 256 ? 4 : 1)>),
+                                   dim3((unsigned)L.count), dim3(64 * kWaves), 0, s, L.args,
+                                   L.qlist, L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count);
+        }
         else
             hipLaunchKernelGGL((k_join_coop_global<T, DP, HYB, kWaves, 16>), dim3(blocks),
                                dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1,
