@@ -1244,14 +1244,16 @@ k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t
 }
 
 // cooperative tier on global tables: one query at a time per workgroup of W
-// waves, its tables in region (block index) of g; a workgroup takes the slots
-// k0 + blockIdx.x, + gridDim.x, ... below k1 (and below k0 + *cnt_dev when
-// the count is on the device)
+// waves, its tables in region (block index) of g; a workgroup takes the
+// entries k0 + blockIdx.x, + gridDim.x, ... below k1 (and below k0 +
+// *cnt_dev when the count is on the device).  Entry k is slot k of qlist, or
+// slot slots[k] when a slot list is given; overflowing slots are appended
+// to ovf as slots of qlist.
 template <typename T, int DP, bool HYB, int W, int PGC>
 __global__ void __launch_bounds__(64 * W)
 k_join_coop_global(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos,
-                   int k0, int k1, const int32_t *cnt_dev, GlobalTables g, int32_t *ovf,
-                   int32_t *ovf_count) {
+                   const int32_t *slots, int k0, int k1, const int32_t *cnt_dev, GlobalTables g,
+                   int32_t *ovf, int32_t *ovf_count) {
     constexpr int HC = HYB ? kBeamMax + 64 * W : 1;
     __shared__ int32_t sh_stage[W][64];
     __shared__ float sh_hk[HC];
@@ -1269,9 +1271,10 @@ k_join_coop_global(const JoinArgs *__restrict__ pa, const int32_t *qlist, const 
     m.aux = sh_aux[kIsBf16<T> ? threadIdx.x >> 6 : 0];
     m.auxf = sh_auxf[kIsBf16<T> ? threadIdx.x >> 6 : 0];
     for (int k = k0 + (int)blockIdx.x; k < kend; k += (int)gridDim.x) {
-        if (run_query_coop<T, DP, W, PGC, HYB>(a, m, sh, HC, k, qlist, qpos, 1 | 8 | 16) &&
+        const int slot = slots != nullptr ? slots[k] : k;
+        if (run_query_coop<T, DP, W, PGC, HYB>(a, m, sh, HC, slot, qlist, qpos, 1 | 8 | 16) &&
             threadIdx.x == 0)
-            ovf[atomicAdd(ovf_count, 1)] = k;
+            ovf[atomicAdd(ovf_count, 1)] = slot;
         __syncthreads();  // the next query clears the region's tables
     }
 }
@@ -1324,7 +1327,7 @@ void launch_tier(const JoinLaunch &L, hipStream_t s) {
         }
         else
             hipLaunchKernelGGL((k_join_coop_global<T, DP, HYB, kWaves, 16>), dim3(blocks),
-                               dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, k0, k1,
+                               dim3(64 * kWaves), 0, s, L.args, L.qlist, L.qpos, L.slots, k0, k1,
                                L.count_dev, g, L.ovf, L.ovf_count);
     }
 }

@@ -13,8 +13,6 @@ void stamp_batch(int32_t *inb, int64_t nq, const int32_t *ids, int64_t n, int32_
                  int32_t *err, hipStream_t s);
 void gather_slots(const int32_t *qlist, const int32_t *qpos, const int32_t *slots, int64_t n,
                   int32_t *q2, int32_t *p2, hipStream_t s);
-void gather_slots_dev(const int32_t *qlist, const int32_t *qpos, const int32_t *slots,
-                      const int32_t *cnt, int64_t nmax, int32_t *q2, int32_t *p2, hipStream_t s);
 
 // Batch steps replayed from captured graphs: the batch descriptors sit in
 // device memory and a cursor in the join counters selects the batch.

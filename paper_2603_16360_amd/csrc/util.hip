@@ -134,20 +134,10 @@ __global__ void k_gather_slots(const int32_t *qlist, const int32_t *qpos, const 
     p2[i] = qpos[slots[i]];
 }
 
-// slots listed on the device: q2[i] = qlist[slots[i]], p2[i] = qpos[slots[i]]
-// for i < *cnt (at most nmax)
-__global__ void k_gather_slots_dev(const int32_t *qlist, const int32_t *qpos, const int32_t *slots,
-                                   const int32_t *cnt, int64_t nmax, int32_t *q2, int32_t *p2) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nmax || i >= *cnt) return;
-    q2[i] = qlist[slots[i]];
-    p2[i] = qpos[slots[i]];
-}
-
-// densest first within a replayed batch, without a sort: slot i goes to the
-// bucket of its d1 (the top 12 bits below the sign of the float: exponent
-// and 4 mantissa bits, so buckets are ordered by d1 and 6 % wide), the
-// buckets are counted, scanned and scattered
+// densest first without a sort: slot i goes to the bucket of its d1 (the
+// top 12 bits below the sign of the float: exponent and 4 mantissa bits, so
+// buckets are ordered by d1 and 6 % wide), the buckets are counted, scanned
+// and scattered
 __device__ __forceinline__ int density_bucket(const int32_t *adj, const float *elen, int R,
                                               int64_t nx, int64_t nq, int32_t q) {
     if (q < 0 || q >= nq) return kOrderBuckets - 1;
@@ -394,13 +384,6 @@ void gather_slots(const int32_t *qlist, const int32_t *qpos, const int32_t *slot
                   int32_t *q2, int32_t *p2, hipStream_t s) {
     if (n == 0) return;
     hipLaunchKernelGGL(k_gather_slots, dim3(grid1(n)), dim3(256), 0, s, qlist, qpos, slots, n, q2, p2);
-}
-
-void gather_slots_dev(const int32_t *qlist, const int32_t *qpos, const int32_t *slots,
-                      const int32_t *cnt, int64_t nmax, int32_t *q2, int32_t *p2, hipStream_t s) {
-    if (nmax == 0) return;
-    hipLaunchKernelGGL(k_gather_slots_dev, dim3(grid1(nmax)), dim3(256), 0, s, qlist, qpos, slots,
-                       cnt, nmax, q2, p2);
 }
 
 void batch_start(const BatchDesc *desc, JoinArgs *args, int32_t *ctr, uint64_t *rec, int64_t nmax,

@@ -584,8 +584,9 @@ static void check_batches(const vj_index *idx, const int32_t *query_ids, const i
 // counters, the batch's query list and d1 buckets) -> densest
 // neighbourhoods first (bucket scan and scatter; or the caller's order) ->
 // the workgroup tier with in-launch promotion -> the queries it could not
-// hold, on global tables (a fixed grid looping over a count on the device)
-// -> the queries those could not hold, on tables as large as the data set
+// hold, read through its overflow list, on global tables (a fixed grid
+// looping over a count on the device) -> the queries those could not hold,
+// on tables as large as the data set
 // -> end (pair range, clock, cursor).  The steps are launched directly, or
 // captured as a HIP graph of up to kSteps steps that is replayed (and kept
 // for the next call of the same launch shape).  Two replay slots,
@@ -605,9 +606,9 @@ static void run_batches_device(Index &ix, const int32_t *ids, const int64_t *st_
                                const vj_join_params &p, bool graph, hipStream_t s,
                                std::vector<std::unique_ptr<vj_pairs>> &res, float *batch_ms) {
     VJ_CHECK(p.work_sharing == VJ_WS_SELF, VJ_ERR_UNSUPPORTED,
-             "the graph batch runner joins in self mode only");
+             "the device batch runner joins in self mode only");
     VJ_CHECK(p.hybrid == VJ_HYB_OFF || p.hybrid == VJ_HYB_FORCE || p.hybrid == VJ_HYB_ADAPT,
-             VJ_ERR_UNSUPPORTED, "the graph batch runner takes hybrid off, force or adapt");
+             VJ_ERR_UNSUPPORTED, "the device batch runner takes hybrid off, force or adapt");
     const int prec = join_precision(ix, p.precision, s);
     const int beam = (p.hybrid != VJ_HYB_OFF) ? p.hybrid_beam : 0;
     VJ_CHECK(beam <= 256, VJ_ERR_UNSUPPORTED, "hybrid_beam must be <= 256");
@@ -715,12 +716,11 @@ static void run_batches_device(Index &ix, const int32_t *ids, const int64_t *st_
     const size_t gh_n = std::max(((size_t)promo_cap) << hl1, ((size_t)g2) << hl2);
     const size_t il_n = std::max((size_t)promo_cap * ilc1, (size_t)g2 * ilc2);
 
-    // eleven lists of nmax slots per replay slot: processing list and
-    // positions of the three launches, the overflow list of each, the
-    // batch's ids in caller order and their density buckets; then the
-    // bucket counts and offsets
+    // seven lists of nmax slots per replay slot: the processing list and
+    // positions, the overflow list of each launch, the batch's ids in caller
+    // order and their density buckets; then the bucket counts and offsets
     struct Lists {
-        int32_t *lq1, *lp1, *lq2, *lp2, *lq3, *lp3, *ovf1, *ovf2, *ovf3, *lq0, *bucket;
+        int32_t *lq1, *lp1, *ovf1, *ovf2, *ovf3, *lq0, *bucket;
         uint32_t *hist, *boff;
     } L[kSlots];
     for (int k = 0; k < nsl; ++k) {
@@ -729,7 +729,7 @@ static void run_batches_device(Index &ix, const int32_t *ids, const int64_t *st_
         S.counters.reserve(64);
         S.desc.reserve(desc[k].size() * sizeof(BatchDesc));
         S.rec.reserve(desc[k].size() * kBatchRec * sizeof(uint64_t));
-        S.lists.reserve((size_t)nmax * 11 * sizeof(int32_t) + 2 * kOrderBuckets * sizeof(uint32_t));
+        S.lists.reserve((size_t)nmax * 7 * sizeof(int32_t) + 2 * kOrderBuckets * sizeof(uint32_t));
         S.gh.reserve(gh_n * sizeof(int32_t));
         S.gil.reserve(il_n * sizeof(int32_t));
         S.gild.reserve(il_n * sizeof(float));
@@ -740,11 +740,7 @@ static void run_batches_device(Index &ix, const int32_t *ids, const int64_t *st_
         Lists &l = L[k];
         l.lq1 = S.lists.as<int32_t>();
         l.lp1 = l.lq1 + nmax;
-        l.lq2 = l.lp1 + nmax;
-        l.lp2 = l.lq2 + nmax;
-        l.lq3 = l.lp2 + nmax;
-        l.lp3 = l.lq3 + nmax;
-        l.ovf1 = l.lp3 + nmax;
+        l.ovf1 = l.lp1 + nmax;
         l.ovf2 = l.ovf1 + nmax;
         l.ovf3 = l.ovf2 + nmax;
         l.lq0 = l.ovf3 + nmax;
@@ -754,11 +750,13 @@ static void run_batches_device(Index &ix, const int32_t *ids, const int64_t *st_
     }
 
     auto launch = [&](BatchSlot &S, int tier, const int32_t *lq, const int32_t *lp,
-                      const int32_t *cnt, int32_t *ovf, int32_t *ovf_cnt, hipStream_t cs) {
+                      const int32_t *sl, const int32_t *cnt, int32_t *ovf, int32_t *ovf_cnt,
+                      hipStream_t cs) {
         JoinLaunch J{};
         J.args = S.args.as<JoinArgs>();
         J.qlist = lq;
         J.qpos = lp;
+        J.slots = sl;
         J.first = 0;
         J.count = (int)nmax;
         J.count_dev = cnt;
@@ -808,11 +806,11 @@ static void run_batches_device(Index &ix, const int32_t *ids, const int64_t *st_
             batch_start(dd, S.args.as<JoinArgs>(), ctr, rec, nmax, ix.adj.as<int32_t>(),
                         ix.elen.as<float>(), ix.R, ix.nx, ix.nq, l.lq1, nullptr, nullptr, cs);
         }
-        launch(S, 1, l.lq1, l.lp1, ctr + kBatchCount, l.ovf1, ctr + 2, cs);
-        gather_slots_dev(l.lq1, l.lp1, l.ovf1, ctr + 2, nmax, l.lq2, l.lp2, cs);
-        launch(S, 2, l.lq2, l.lp2, ctr + 2, l.ovf2, ctr + kBatchOvf2, cs);
-        gather_slots_dev(l.lq2, l.lp2, l.ovf2, ctr + kBatchOvf2, nmax, l.lq3, l.lp3, cs);
-        launch(S, 3, l.lq3, l.lp3, ctr + kBatchOvf2, l.ovf3, ctr + kBatchOvf3, cs);
+        // the re-runs read their queries through the overflow lists (slots
+        // of the first list) and append slots of the first list
+        launch(S, 1, l.lq1, l.lp1, nullptr, ctr + kBatchCount, l.ovf1, ctr + 2, cs);
+        launch(S, 2, l.lq1, l.lp1, l.ovf1, ctr + 2, l.ovf2, ctr + kBatchOvf2, cs);
+        launch(S, 3, l.lq1, l.lp1, l.ovf2, ctr + kBatchOvf2, l.ovf3, ctr + kBatchOvf3, cs);
         batch_end(ctr, rec, cs);
     };
 

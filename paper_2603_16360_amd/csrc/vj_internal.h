@@ -217,6 +217,7 @@ struct JoinLaunch {
     int promo_cap;            // tier 1: regions of gh / gil / gild it may take (0: none)
     int32_t *ovf, *ovf_count; // slots (indices into qlist) that must be re-run
     const int32_t *count_dev; // tiers 1-2: the slot count on the device, at most `count` (null: count)
+    const int32_t *slots;     // tier 2: entry k is slot slots[k] of qlist (null: slot k)
     int grid;                 // tier 2: workgroups looping over the slots (0: one per slot)
 };
 
