@@ -100,13 +100,17 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
             const int kw = min(kKc, Kp - kc0);  // a multiple of 32
             const int cpr = kw / 8;             // 16-byte chunks per staged row
             __syncthreads();                    // the previous chunk is consumed
+            // one 64-bit base per tile, 32-bit offsets inside it (128 rows)
+            const uint16_t *th = Ah + c0 * Kp + kc0;
+            const uint16_t *tl = NSPLIT == 3 ? Al + c0 * Kp + kc0 : nullptr;
+            const int nrow = (int)std::min<int64_t>(128, N - c0);
             for (int e = threadIdx.x; e < 128 * cpr; e += 256) {
                 const int rr = e / cpr, ch = e - rr * cpr;
-                const int64_t col = c0 + rr;
                 uint4 vh = make_uint4(0, 0, 0, 0), vl = make_uint4(0, 0, 0, 0);
-                if (col < N) {
-                    vh = *reinterpret_cast<const uint4 *>(Ah + col * Kp + kc0 + ch * 8);
-                    if (NSPLIT == 3) vl = *reinterpret_cast<const uint4 *>(Al + col * Kp + kc0 + ch * 8);
+                if (rr < nrow) {
+                    const int off = rr * Kp + ch * 8;
+                    vh = *reinterpret_cast<const uint4 *>(th + off);
+                    if (NSPLIT == 3) vl = *reinterpret_cast<const uint4 *>(tl + off);
                 }
                 *reinterpret_cast<uint4 *>(sb_hi + rr * kLdsRow + ch * 8) = vh;
                 if (NSPLIT == 3) *reinterpret_cast<uint4 *>(sb_lo + rr * kLdsRow + ch * 8) = vl;
@@ -133,28 +137,42 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
                 }
             }
         }
+        // the filter in 32-bit indices (N < 2^31) with each row's threshold
+        // read once per tile: the same keys and decisions as the row-wise loop
+        {
+            const int n32 = (int)N, row0 = (int)r0 + (lane >> 4) * 4;
+            float tau[4];
 #pragma unroll
-        for (int ct = 0; ct < 8; ++ct)
+            for (int i = 0; i < 4; ++i) tau[i] = s_tau[w][(lane >> 4) * 4 + i];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = (lane >> 4) * 4 + i;
-                const int64_t row = r0 + r;
-                const int64_t col = c0 + ct * 16 + (lane & 15);
-                if (row < N && col < N && col != row) {
-                    const float key = n2[col] - 2.f * acc[ct][i];
-                    if (key <= s_tau[w][r]) {
-                        const int at = atomicAdd(&s_cnt[w][r], 1);
+            for (int ct = 0; ct < 8; ++ct) {
+                const int col = (int)c0 + ct * 16 + (lane & 15);
+                const float nc = col < n32 ? n2[col] : 0.f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = row0 + i;
+                    const float key = nc - 2.f * acc[ct][i];
+                    if (key <= tau[i] && row < n32 && col < n32 && col != row) {
+                        const int at = atomicAdd(&s_cnt[w][(lane >> 4) * 4 + i], 1);
                         if (at < kKnnCap) {
-                            bkey[row * kKnnCap + at] = key;
-                            bid[row * kKnnCap + at] = (int32_t)col;
+                            bkey[(int64_t)row * kKnnCap + at] = key;
+                            bid[(int64_t)row * kKnnCap + at] = col;
                         }
                     }
                 }
             }
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        for (int r = 0; r < 16; ++r)
-            if (s_cnt[w][r] > K + 128) merge_row(r);
+        // rows whose buffers passed K + 128 entries: one read per lane, then
+        // the rows of the ballot (each merge touches its own row only)
+        const int cl = lane < 16 ? s_cnt[w][lane] : 0;
+        uint64_t full = __ballot(lane < 16 && cl > K + 128);
+        while (full) {
+            const int r = __ffsll((unsigned long long)full) - 1;
+            full &= full - 1;
+            merge_row(r);
+        }
     }
     for (int r = 0; r < 16; ++r) merge_row(r);
 }
@@ -350,6 +368,7 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
     const int64_t N = ix.N;
     const int R = ix.R, dp = ix.dp;
     VJ_CHECK(N >= 2, VJ_ERR_INVALID_ARG, "need at least two vectors");
+    VJ_CHECK(N < ((int64_t)1 << 31), VJ_ERR_UNSUPPORTED, "node ids are int32: N < 2^31");
     kc = (int)std::min<int64_t>(kc, N - 1);
     const int K = std::min(128, kc + 16);  // top-K of the tile sweep, re-ranked to kc
     const float *vec = ix.vec.as<float>();
