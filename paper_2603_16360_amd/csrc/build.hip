@@ -100,12 +100,15 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
             const int kw = min(kKc, Kp - kc0);  // a multiple of 32
             const int cpr = kw / 8;             // 16-byte chunks per staged row
             __syncthreads();                    // the previous chunk is consumed
-            // one 64-bit base per tile, 32-bit offsets inside it (128 rows)
+            // one 64-bit base per tile, 32-bit offsets inside it (128 rows);
+            // e / cpr as a multiply: with inv = ceil(2^16 / cpr) the quotient
+            // is exact for e < 2^16 / 16 and cpr <= 16
             const uint16_t *th = Ah + c0 * Kp + kc0;
             const uint16_t *tl = NSPLIT == 3 ? Al + c0 * Kp + kc0 : nullptr;
             const int nrow = (int)std::min<int64_t>(128, N - c0);
+            const uint32_t inv = (65536u + (uint32_t)cpr - 1u) / (uint32_t)cpr;
             for (int e = threadIdx.x; e < 128 * cpr; e += 256) {
-                const int rr = e / cpr, ch = e - rr * cpr;
+                const int rr = (int)(((uint32_t)e * inv) >> 16), ch = e - rr * cpr;
                 uint4 vh = make_uint4(0, 0, 0, 0), vl = make_uint4(0, 0, 0, 0);
                 if (rr < nrow) {
                     const int off = rr * Kp + ch * 8;
