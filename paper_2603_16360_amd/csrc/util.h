@@ -47,11 +47,11 @@ void batch_end(int32_t *ctr, uint64_t *rec, hipStream_t s);
 
 // self mode: slots ordered by d1 of the query (mean edge length to its data
 // neighbours) ascending, in 4,096 buckets about 6 % wide -- densest
-// neighbourhoods, the longest queries, first; the buffers are caller-owned
-// scratch (keys2 and pos are not used)
+// neighbourhoods, the longest queries, first; keys and tmp are caller-owned
+// scratch
 void order_by_density(const int32_t *adj, const float *elen, int R, int64_t nx, int64_t nq,
                       const int32_t *ids, int64_t n, int32_t *qlist, int32_t *qpos, DevBuf &keys,
-                      DevBuf &keys2, DevBuf &pos, DevBuf &tmp, hipStream_t s);
+                      DevBuf &tmp, hipStream_t s);
 void order_by_depth(const int32_t *depth, int64_t nq, const int32_t *ids, int64_t n,
                     int32_t *qlist, int32_t *qpos, DevBuf &tmp, hipStream_t s);
 

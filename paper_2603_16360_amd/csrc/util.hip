@@ -424,9 +424,7 @@ void order_by_depth(const int32_t *depth, int64_t nq, const int32_t *ids, int64_
 
 void order_by_density(const int32_t *adj, const float *elen, int R, int64_t nx, int64_t nq,
                       const int32_t *ids, int64_t n, int32_t *qlist, int32_t *qpos, DevBuf &keys,
-                      DevBuf &keys2, DevBuf &pos, DevBuf &tmp, hipStream_t s) {
-    (void)keys2;
-    (void)pos;
+                      DevBuf &tmp, hipStream_t s) {
     if (n == 0) return;
     // d1 buckets (4,096, about 6 % wide) counted, scanned and scattered: the
     // order only has to start dense neighbourhoods first, and three small

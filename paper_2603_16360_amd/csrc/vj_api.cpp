@@ -220,8 +220,8 @@ static void make_order(Index &ix, const int32_t *ids, int64_t n, int ws, bool de
         if (dense_first) {
             JoinWorkspace &jw = ix.jw;
             order_by_density(ix.adj.as<int32_t>(), ix.elen.as<float>(), ix.R, ix.nx, ix.nq, ids, n,
-                             o.qlist.as<int32_t>(), o.qpos.as<int32_t>(), jw.sort_keys,
-                             jw.sort_keys2, jw.sort_pos, jw.sort_tmp, s);
+                             o.qlist.as<int32_t>(), o.qpos.as<int32_t>(), jw.sort_keys, jw.sort_tmp,
+                             s);
         } else {
             if (ids) VJ_HIP(hipMemcpyAsync(o.qlist.p, ids, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
             else iota_i32(o.qlist.as<int32_t>(), n, s);

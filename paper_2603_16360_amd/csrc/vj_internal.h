@@ -85,7 +85,7 @@ struct DevBuf {
 int padded_dim(int d);
 
 // ----------------------------------------------------------------- index --
-// State of one replay slot of the graph batch runner (grow only): its
+// State of one replay slot of the device batch runner (grow only): its
 // arguments, counters, descriptors, lists, global tables and output.
 struct BatchSlot {
     DevBuf args, counters, desc, rec, lists, gh, gil, gild, gh3, gil3, gild3, out_q, out_x, out_d;
@@ -104,10 +104,10 @@ struct BatchSlot {
 // Buffers of vj_join kept between calls on one index (grow only).
 struct JoinWorkspace {
     DevBuf qlist, qpos, counters, args, ovf, slots, out_q, out_x, out_d;
-    DevBuf sort_keys, sort_keys2, sort_pos, sort_tmp;
+    DevBuf sort_keys, sort_tmp;     // densest-first order: d1 buckets, bucket counts
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipStream_t capture = nullptr;  // private stream the batch graphs are captured on
-    BatchSlot bslot[2];             // the graph batch runner's two replay slots
+    BatchSlot bslot[2];             // the device batch runner's two replay slots
     hipEvent_t bev[1 + 2] = {};     // its events: the fork, one join per slot
     void *pinned = nullptr;  // 4 KiB of pinned host memory: counters read back, arguments sent
     JoinWorkspace() = default;
