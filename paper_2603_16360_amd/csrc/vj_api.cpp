@@ -527,12 +527,15 @@ static void learned_join(Index &ix, const int32_t *ids, int64_t n, float eps, vj
     predictor_forward(P, feat.as<float>(), n, logits.as<float>(), s);
     select_budgets(logits.as<float>(), n, P.k, ix.pred_budgets.as<int32_t>(), ix.pred_target,
                    bud.as<int32_t>(), s);
-    p.hybrid = VJ_HYB_BUDGET;
-    run_join(ix, ids, n, eps, p, bud.as<int32_t>(), s, r);
-    // queries routed to the exact join
     std::vector<int32_t> bud_h((size_t)n), routed;
     VJ_HIP(hipMemcpyAsync(bud_h.data(), bud.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     VJ_HIP(hipStreamSynchronize(s));
+    p.hybrid = VJ_HYB_BUDGET;
+    // no query got out-range pops: the kernels without the out-range queue
+    // run it (budget 0 is BFS; routed queries are skipped either way)
+    if (*std::max_element(bud_h.begin(), bud_h.end()) <= 0) p.hybrid_beam = 0;
+    run_join(ix, ids, n, eps, p, bud.as<int32_t>(), s, r);
+    // queries routed to the exact join
     for (int64_t i = 0; i < n; ++i)
         if (bud_h[(size_t)i] < 0) routed.push_back(ids_h[(size_t)i]);
     if (routed.empty()) return;
