@@ -86,21 +86,46 @@ k_range_tiles(const uint16_t *Qh, const uint16_t *Ql, int64_t nq, const uint16_t
     floatx4 acc[4][2];
     mt::tile_64x32<NSPLIT>(Qh, Ql, q0, nq, Xh, Xl, x0, nx, Kp, lane, acc);
     uint32_t hits = 0;  // bit (rt*8 + ct*4 + i)
+    // the tile's row and column terms, read once per lane (16 rows, 2
+    // columns), indices in 32 bits (nq, nx < 2^31); the same comparisons
+    const int nq32 = (int)nq, nx32 = (int)nx, qb = (int)q0, xb = (int)x0;
+    float rq2[4][4], rthr[4][4], cx2[2];
+    bool rok[4][4], cok[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+        const int x = xb + mt::tile_brow(ct, lane);
+        cok[ct] = x < nx32;
+        cx2[ct] = cok[ct] ? nx2[x] : 0.f;
+    }
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+        for (int i = 0; i < 4; ++i) {
+            const int q = qb + mt::tile_arow(rt, i, lane);
+            rok[rt][i] = q < nq32;
+            rq2[rt][i] = rok[rt][i] ? nq2[q] : 0.f;
+            rthr[rt][i] = rok[rt][i] ? thr[q] : 0.f;
+        }
+    if (metric == VJ_L2) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int64_t q = q0 + mt::tile_arow(rt, i, lane);
-                const int64_t x = x0 + mt::tile_brow(ct, lane);
-                if (q < nq && x < nx) {
-                    const float dot = acc[rt][ct][i];
-                    const bool c = metric == VJ_L2 ? (nq2[q] + nx2[x] - 2.f * dot < thr[q])
-                                                   : (dot > thr[q]);
-                    if (c) hits |= 1u << (rt * 8 + ct * 4 + i);
-                }
-            }
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (rok[rt][i] && cok[ct] &&
+                        rq2[rt][i] + cx2[ct] - 2.f * acc[rt][ct][i] < rthr[rt][i])
+                        hits |= 1u << (rt * 8 + ct * 4 + i);
+    } else {
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (rok[rt][i] && cok[ct] && acc[rt][ct][i] > rthr[rt][i])
+                        hits |= 1u << (rt * 8 + ct * 4 + i);
+    }
     if (__ballot(hits != 0) == 0) return;
     int excl;
     const int total = mt::wave_scan(__popc(hits), lane, excl);
