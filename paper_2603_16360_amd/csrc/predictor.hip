@@ -22,10 +22,24 @@ inline unsigned g1p(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 // ------------------------------------------------------------- features --
 // One wave per query.  Distances in the join metric (L2: |q - y|; IP:
 // 1 - <q, y>); d1 and d2 in L2 units (|q - y| from the vectors, stored edge
-// lengths for d2).  Row layout: q[0..d), f0..f7.
+// lengths for d2).  Row layout: q[0..d), f0..f7.  The neighbours of q are
+// evaluated 8 at a time (8 lanes per row) and the R x R second-hop entries
+// are spread over the lanes, so the loads of a query are independent.
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+    return v;
+}
+
+__device__ __forceinline__ float group8_sum(float v) {
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) v += __shfl_xor(v, off);
     return v;
 }
 
@@ -34,43 +48,72 @@ k_features(const float *vec, int dp, int d, int64_t nx, const int32_t *adj, cons
            int R, int32_t entry, int metric, float eps, const int32_t *qlist, int64_t n,
            float *out) {
     const int lane = threadIdx.x & 63;
+    const int g = lane >> 3, p = lane & 7;
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
     const int64_t q = nx + qlist[i];
     const float *qv = vec + q * dp;
     float *o = out + i * (int64_t)(d + kFeatures);
     for (int c = lane; c < d; c += 64) o[c] = qv[c];
-    auto l2sq = [&](const float *a, const float *b) {
+    const bool l2 = metric == VJ_L2;
+    // f1: the entry, one whole-wave dot
+    float f1;
+    {
+        const float *ev = vec + (int64_t)entry * dp;
         float acc = 0.f;
-        for (int c = lane; c < dp; c += 64) { const float t = a[c] - b[c]; acc = fmaf(t, t, acc); }
-        return wave_sum(acc);
-    };
-    auto ip = [&](const float *a, const float *b) {
-        float acc = 0.f;
-        for (int c = lane; c < dp; c += 64) acc = fmaf(a[c], b[c], acc);
-        return wave_sum(acc);
-    };
-    auto dist = [&](const float *b) {
-        return metric == VJ_L2 ? sqrtf(l2sq(qv, b)) : 1.0f - ip(qv, b);
-    };
-    const float f1 = dist(vec + (int64_t)entry * dp);
-    float mn = 0.f, s1 = 0.f, s2 = 0.f;
-    int na = 0, nin = 0, c2 = 0;
-    for (int j = 0; j < R; ++j) {
-        const int32_t y = adj[q * R + j];
-        if (y < 0 || y >= nx) continue;
-        const float *yv = vec + (int64_t)y * dp;
-        const float dy = dist(yv);
-        if (na == 0 || dy < mn) mn = dy;
-        if (dy < eps) ++nin;
-        s1 += metric == VJ_L2 ? dy : sqrtf(l2sq(qv, yv));
-        ++na;
-        const int32_t z = lane < R ? adj[(int64_t)y * R + lane] : -1;
-        const bool ok = z >= 0 && z < nx && z != q;
-        const float e = ok ? elen[(int64_t)y * R + lane] : 0.f;
-        s2 += wave_sum(e);
-        c2 += __popcll(__ballot(ok));
+        for (int c = lane; c < dp; c += 64) {
+            if (l2) { const float t = qv[c] - ev[c]; acc = fmaf(t, t, acc); }
+            else acc = fmaf(qv[c], ev[c], acc);
+        }
+        acc = wave_sum(acc);
+        f1 = l2 ? sqrtf(acc) : 1.0f - acc;
     }
+    // A = N(q) among the data nodes: group g takes neighbours g, g + 8, ...
+    float mn = INFINITY, s1 = 0.f;
+    int na = 0, nin = 0;
+    for (int j0 = 0; j0 < R; j0 += 8) {
+        const int j = j0 + g;
+        const int32_t y = j < R ? adj[q * R + j] : -1;
+        const bool ok = y >= 0 && y < nx;
+        float sq = 0.f, dt = 0.f;
+        if (ok) {
+            const float *yv = vec + (int64_t)y * dp;
+            for (int c = p; c < dp; c += 8) {
+                const float a = qv[c], b = yv[c];
+                const float t = a - b;
+                sq = fmaf(t, t, sq);
+                dt = fmaf(a, b, dt);
+            }
+        }
+        sq = group8_sum(sq);
+        dt = group8_sum(dt);
+        if (ok && p == 0) {
+            const float dy = l2 ? sqrtf(sq) : 1.0f - dt;
+            mn = fminf(mn, dy);
+            if (dy < eps) ++nin;
+            s1 += sqrtf(sq);
+            ++na;
+        }
+    }
+    // d2: stored edge lengths of N(y) for y in A, z a data node other than q
+    float s2 = 0.f;
+    int c2 = 0;
+    for (int e = lane; e < R * R; e += 64) {
+        const int yj = e / R, zj = e - yj * R;
+        const int32_t y = adj[q * R + yj];
+        if (y < 0 || y >= nx) continue;
+        const int32_t z = adj[(int64_t)y * R + zj];
+        if (z >= 0 && z < nx && z != q) {
+            s2 += elen[(int64_t)y * R + zj];
+            ++c2;
+        }
+    }
+    mn = wave_min(mn);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    na = (int)wave_sum((float)na);
+    nin = (int)wave_sum((float)nin);
+    c2 = (int)wave_sum((float)c2);
     if (lane == 0) {
         const float d1 = na ? s1 / (float)na : 0.f;
         const float d2 = c2 ? s2 / (float)c2 : 0.f;
