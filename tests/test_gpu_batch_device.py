@@ -148,20 +148,21 @@ def test_many_batches_and_kept_graphs(tiny):
 
 
 @pytest.mark.parametrize("runner", RUNNERS)
-def test_batches_adapt_matches_oracle(tiny, runner):
+@pytest.mark.parametrize("hybrid", ["adapt", "force"])
+def test_batches_hybrid_matches_oracle(tiny, runner, hybrid):
     w = tiny.w
     n = w.Q.shape[0]
     res, _ = vj.vj_join_batches(tiny.idx, [0, 123, 600], [123, 477, n - 600], [tiny.eps] * 3,
-                                runner=runner, hybrid="adapt")
+                                runner=runner, hybrid=hybrid)
     got = {}
     for r in res:
         for q, xs in _by_query(r.export(sorted=True)[0].cpu().numpy().tolist()).items():
             got[q] = xs
-    ref = oracle.join(w.Q, w.X, tiny.g.adj, tiny.g.entry, tiny.eps, hybrid="adapt")
+    ref = oracle.join(w.Q, w.X, tiny.g.adj, tiny.g.entry, tiny.eps, hybrid=hybrid)
     want = _by_query(zip(ref.qi.tolist(), ref.xj.tolist()))
     fragile = ref.stats[:, 7].astype(bool)
     mism = [q for q in range(n) if not fragile[q] and got.get(q, set()) != want.get(q, set())]
-    _say(f"{runner} adapt: fragile {fragile.mean():.4f}, mismatches {len(mism)}")
+    _say(f"{runner} {hybrid}: fragile {fragile.mean():.4f}, mismatches {len(mism)}")
     assert not mism, f"{len(mism)} non-fragile queries differ, e.g. {mism[:5]}"
 
 
