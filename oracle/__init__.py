@@ -94,6 +94,8 @@ def _declare(L):
     L.or_mlp_bce_backward.restype = _dbl
     L.or_mlp_bce_backward.argtypes = ([_int] * 5 + [_f64p] * 7 + [_f64p, C.c_void_p]
                                       + [_f64p] * 6)
+    L.or_adam_step.restype = None
+    L.or_adam_step.argtypes = [_i64, _f64p, _f64p, _f64p, _f64p, _i64, _dbl, _dbl, _dbl, _dbl]
 
 
 def _f32(a):
@@ -338,3 +340,15 @@ def mlp_bce_backward(params, Xin, Y, mask=None):
                                      W1, b1, W2, b2, W3, b3, Y,
                                      m.ctypes.data if m is not None else None, *grads)
     return loss, grads
+
+
+def adam_step(p, g, m, v, t: int, lr: float, b1: float = 0.9, b2: float = 0.999,
+              eps: float = 1e-8):
+    """One fp64 Adam step (Kingma and Ba 2015, Algorithm 1) at step number t
+    >= 1, in place on the float64 arrays p, m, v (g is read)."""
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    g = np.ascontiguousarray(g, np.float64)
+    assert p.shape == g.shape == m.shape == v.shape
+    lib().or_adam_step(p.size, p.reshape(-1), g.reshape(-1), m.reshape(-1), v.reshape(-1),
+                       int(t), lr, b1, b2, eps)

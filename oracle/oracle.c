@@ -14,7 +14,7 @@
  *   - Algorithms 1-8:                  or_join
  *   - difficulty MLP (not in the paper; fp64 reference):
  *                                      or_features, or_mlp_forward,
- *                                      or_mlp_bce_backward
+ *                                      or_mlp_bce_backward, or_adam_step
  *
  * Readings of points the paper leaves open are marked "reading:".
  */
@@ -989,4 +989,27 @@ double or_mlp_bce_backward(int n, int din, int h1, int h2, int k, const double *
         }
     free(a1); free(a2); free(z); free(g3); free(g2); free(g1);
     return loss;
+}
+
+/* ------------------------------------------------------------------------
+ * O5: one step of Adam (Kingma and Ba, "Adam: a method for stochastic
+ * optimization", ICLR 2015, Algorithm 1) on n parameters, step number t >= 1:
+ *   m <- b1 m + (1 - b1) g
+ *   v <- b2 v + (1 - b2) g^2
+ *   p <- p - lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+ * (bias-corrected moments; eps added outside the square root).  The
+ * optimizer that trains the difficulty MLP; not in the paper.
+ * ---------------------------------------------------------------------- */
+void or_adam_step(int64_t n, double *p, const double *g, double *m, double *v, int64_t t,
+                  double lr, double b1, double b2, double eps)
+{
+    double c1 = 1.0 - pow(b1, (double)t);
+    double c2 = 1.0 - pow(b2, (double)t);
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        double mhat = m[i] / c1;
+        double vhat = v[i] / c2;
+        p[i] -= lr * mhat / (sqrt(vhat) + eps);
+    }
 }

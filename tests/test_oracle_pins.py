@@ -531,3 +531,46 @@ def test_mlp_training_reduces_loss():
     assert loss < 0.2 * l0
     acc = ((oracle.mlp_forward(p, Xin) > 0) == (Y > 0.5)).mean()
     assert acc > 0.95
+
+
+def test_adam_step_hand_examples():
+    """or_adam_step against hand-derived values (Kingma and Ba 2015, Algorithm
+    1): two steps of a scalar, and the constant-gradient closed form, which a
+    wrong bias correction or an eps inside the square root would break."""
+    ex = json.load(open(os.path.join(GOLDEN, "adam_worked_example.json")))
+    e = ex["two_steps"]
+    h = e["hyper"]
+    p, m, v = (np.array([x], np.float64) for x in (e["p0"], 0.0, 0.0))
+    for t, (g, want) in enumerate(zip(e["grads"], e["after"]), start=1):
+        oracle.adam_step(p, np.array([g]), m, v, t, h["lr"], h["beta1"], h["beta2"], h["eps"])
+        assert m[0] == pytest.approx(want["m"], rel=1e-14)
+        assert v[0] == pytest.approx(want["v"], rel=1e-13)
+        assert p[0] == pytest.approx(want["p"], rel=1e-14)
+    c = ex["constant_gradient"]
+    h = c["hyper"]
+    p = np.array(c["p0"], np.float64)
+    m, v = np.zeros_like(p), np.zeros_like(p)
+    for t in range(1, c["steps"] + 1):
+        oracle.adam_step(p, np.array(c["g"]), m, v, t, h["lr"], h["beta1"], h["beta2"], h["eps"])
+    np.testing.assert_allclose(p, c["p_after"], rtol=1e-12, atol=1e-15)
+
+
+def test_nlj_counts_per_query_against_scipy():
+    """Per-query counts of the exact join on integer data, at an eps equal to
+    an actual pair distance: the pairs at exactly eps must not be counted
+    (strict predicate of Definition 1), and each query's count is its own."""
+    r = np.random.default_rng(77)
+    Q = r.integers(0, 6, size=(45, 5)).astype(np.float32)
+    X = r.integers(0, 6, size=(260, 5)).astype(np.float32)
+    D = cdist(Q.astype(np.float64), X.astype(np.float64))
+    # squared distances are small integers: sqrt of one is the same double on
+    # both sides, and many pairs tie with it
+    eps = float(np.sqrt(np.median(np.rint(D * D))))
+    ties = int((np.rint(D * D) == np.rint(eps * eps)).sum())
+    assert ties > 100
+    want = (D < eps).sum(axis=1)
+    got = oracle.nlj_counts(Q, X, eps)
+    assert np.array_equal(got, want)
+    assert len(set(want.tolist())) > 10  # the split differs from query to query
+    assert np.array_equal(oracle.nlj_counts(Q, X, eps, "l2"),
+                          np.bincount(oracle.nlj(Q, X, eps)[0], minlength=Q.shape[0]))
