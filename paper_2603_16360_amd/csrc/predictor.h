@@ -41,9 +41,15 @@ void predictor_forward(const Predictor &p, const float *X, int64_t n, float *log
 double predictor_loss_grad(const Predictor &p, const float *X, const float *Y, const float *mask,
                            int64_t n, float *gW1, float *gb1, float *gW2, float *gb2, float *gW3,
                            float *gb3, hipStream_t s);
+// one Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected) with the
+// gradient g of every parameter, back to back in the order W1 b1 W2 b2 W3 b3
+void predictor_adam(Predictor &p, const float *g, float lr, hipStream_t s);
 // Adam over shuffled minibatches; loss_per_epoch (host, may be null)
 void predictor_train(Predictor &p, const float *X, const float *Y, int64_t n, int epochs,
                      int batch, float lr, uint64_t seed, float *loss_per_epoch, hipStream_t s);
+// predictor files: parameters, normalisation, Adam moments and step count
+void predictor_save(const Predictor &p, const char *path);
+void predictor_load(Predictor &p, const char *path, hipStream_t s);
 // mu / inv_sigma from the columns of X (constant columns get inv_sigma 1)
 void predictor_fit_normalization(Predictor &p, const float *X, int64_t n, hipStream_t s);
 // budget[i] = budgets[j] for the smallest j whose predicted recall

@@ -247,13 +247,15 @@ __global__ void k_colsum(const float *G, int64_t n, int k, float *out) {
     if (threadIdx.x == 0) out[col] = part[0] + part[1] + part[2] + part[3];
 }
 
+// omb1 = 1 - b1 and omb2 = 1 - b2 come from the host in double: 1 - 0.999f in
+// fp32 is off by 1.3e-5 relative (0.999 is not a float)
 __global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
-                       float b2, float c1, float c2) {
+                       float omb1, float b2, float omb2, float c1, float c2) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     const float gg = g[e];
-    const float mm = b1 * m[e] + (1.f - b1) * gg;
-    const float vv = b2 * v[e] + (1.f - b2) * gg * gg;
+    const float mm = b1 * m[e] + omb1 * gg;
+    const float vv = b2 * v[e] + omb2 * gg * gg;
     m[e] = mm;
     v[e] = vv;
     p[e] -= lr * (mm * c1) / (sqrtf(vv * c2) + 1e-8f);
@@ -458,6 +460,25 @@ void predictor_fit_normalization(Predictor &p, const float *X, int64_t n, hipStr
     VJ_HIP(hipStreamSynchronize(s));
 }
 
+void predictor_adam(Predictor &p, const float *g, float lr, hipStream_t s) {
+    // parameters are separate buffers; Adam runs per buffer over its slice of
+    // g, m and v (all parameters back to back in the order W1 b1 W2 b2 W3 b3)
+    DevBuf *par[6] = {&p.W1, &p.b1, &p.W2, &p.b2, &p.W3, &p.b3};
+    const double b1 = 0.9, b2 = 0.999;
+    p.steps += 1;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)p.steps)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)p.steps)));
+    size_t off = 0;
+    for (int i = 0; i < 6; ++i) {
+        const int64_t len = (int64_t)(par[i]->bytes / sizeof(float));
+        hipLaunchKernelGGL(k_adam, dim3(g1p(len, 256)), dim3(256), 0, s, par[i]->as<float>(),
+                           g + off, p.m.as<float>() + off, p.v.as<float>() + off, len, lr,
+                           (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), c1, c2);
+        off += (size_t)len;
+    }
+    VJ_HIP(hipGetLastError());
+}
+
 void predictor_train(Predictor &p, const float *X, const float *Y, int64_t n, int epochs,
                      int batch, float lr, uint64_t seed, float *loss_per_epoch, hipStream_t s) {
     if (n == 0 || epochs <= 0) return;
@@ -468,9 +489,6 @@ void predictor_train(Predictor &p, const float *X, const float *Y, int64_t n, in
     DevBuf idx((size_t)batch * sizeof(int32_t)), xb((size_t)batch * p.din * sizeof(float)),
         yb((size_t)batch * p.k * sizeof(float)), g(p.n_params() * sizeof(float));
     Acts &t = p.scratch;
-    // parameters are separate buffers; Adam runs per buffer over its slice
-    DevBuf *par[6] = {&p.W1, &p.b1, &p.W2, &p.b2, &p.W3, &p.b3};
-    const float b1 = 0.9f, b2 = 0.999f;
     for (int e = 0; e < epochs; ++e) {
         std::shuffle(perm.begin(), perm.end(), rng);
         double sum = 0.0;
@@ -486,18 +504,7 @@ void predictor_train(Predictor &p, const float *X, const float *Y, int64_t n, in
                                          g.as<float>(), s);
             sum += loss * nb;
             seen += nb;
-            p.steps += 1;
-            const float c1 = 1.f / (1.f - std::pow(b1, (float)p.steps));
-            const float c2 = 1.f / (1.f - std::pow(b2, (float)p.steps));
-            size_t off = 0;
-            for (int i = 0; i < 6; ++i) {
-                const int64_t len = (int64_t)(par[i]->bytes / sizeof(float));
-                hipLaunchKernelGGL(k_adam, dim3(g1p(len, 256)), dim3(256), 0, s, par[i]->as<float>(),
-                                   g.as<float>() + off, p.m.as<float>() + off, p.v.as<float>() + off,
-                                   len, lr, b1, b2, c1, c2);
-                off += (size_t)len;
-            }
-            VJ_HIP(hipGetLastError());
+            predictor_adam(p, g.as<float>(), lr, s);
         }
         if (loss_per_epoch) loss_per_epoch[e] = (float)(sum / (double)seen);
     }

@@ -3,6 +3,11 @@
 * post-probe features (vj_join_features) against the oracle's fp64 features;
 * MLP forward and the BCE gradients (vj_predictor_loss_grad) against the
   oracle's fp64 MLP: relative max-norm error <= 1e-4 on a fixed minibatch;
+* the same at the product shape (768 + 8) -> 256 -> 256 -> 4 on a 1,024-row
+  minibatch, which runs the multi-tile paths of the device GEMMs;
+* the device Adam step against the oracle's fp64 Adam from the same
+  parameters and the same gradients: parameters, moments and step count
+  after steps 1, 2 and 10;
 * training on the device reduces the loss;
 * VJ_HYB_LEARNED: with the same weights on both sides, the oracle's fp64
   features -> fp64 MLP -> budget choice -> oracle budget-mode join (routed
@@ -103,6 +108,75 @@ def test_mlp_forward_and_gradients_match_oracle():
         err = np.abs(got - ref_g).max() / max(np.abs(ref_g).max(), 1e-12)
         print(f"[mlp] grad {name} rel max-norm error {err:.2e}", flush=True)
         assert err <= 1e-4, name
+
+
+def test_mlp_gradients_match_oracle_at_product_shape():
+    rng = np.random.default_rng(17)
+    n, din, h1, h2, k = 1024, 768 + 8, 256, 256, 4
+    params = _rand_params(rng, din, h1, h2, k)
+    X = rng.standard_normal((n, din)).astype(np.float32)
+    mu = (rng.standard_normal(din) * 0.1).astype(np.float32)
+    inv_sigma = (0.8 + 0.4 * rng.random(din)).astype(np.float32)
+    Y = rng.random((n, k)).astype(np.float32)
+    p = vj.Predictor(din, h1, h2, k, seed=1)
+    p.set_params(**_to_dev(params, mu, inv_sigma))
+    Xn = (X.astype(np.float64) - mu) * inv_sigma.astype(np.float64)
+    logits = p.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    ref = oracle.mlp_forward(params, Xn)
+    fwd_err = np.abs(logits - ref).max() / max(1.0, np.abs(ref).max())
+    print(f"[mlp] product shape forward rel error {fwd_err:.2e}", flush=True)
+    assert fwd_err <= 1e-4
+    loss, g = p.loss_grad(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda())
+    rloss, rg = oracle.mlp_bce_backward(params, Xn, Y)
+    assert loss == pytest.approx(rloss, rel=1e-5)
+    for name, ref_g in zip(("W1", "b1", "W2", "b2", "W3", "b3"), rg):
+        got = g[name].cpu().numpy().astype(np.float64)
+        err = np.abs(got - ref_g).max() / max(np.abs(ref_g).max(), 1e-12)
+        print(f"[mlp] product shape grad {name} rel max-norm error {err:.2e}", flush=True)
+        assert err <= 1e-4, name
+
+
+def test_adam_matches_oracle():
+    rng = np.random.default_rng(29)
+    din, h1, h2, k = 768 + 8, 256, 256, 4
+    params = _rand_params(rng, din, h1, h2, k)
+    p = vj.Predictor(din, h1, h2, k, seed=3)
+    p.set_params(**_to_dev(params, np.zeros(din, np.float32), np.ones(din, np.float32)))
+    flat0 = np.concatenate([x.ravel() for x in params]).astype(np.float64)
+    n = flat0.size
+    assert n == p.n_params
+    P, M, V = flat0.copy(), np.zeros(n), np.zeros(n)
+    lr = 3e-3
+    path = np.zeros(n)  # sum over steps of |step|: successive steps may cancel
+    for t in range(1, 11):
+        # gradients of mixed scales, with exact zeros and values near eps
+        g = rng.standard_normal(n) * np.exp(rng.uniform(-12, 2, n))
+        g[rng.random(n) < 0.05] = 0.0
+        g[rng.random(n) < 0.01] = 1e-8
+        g = g.astype(np.float32)
+        p.adam_step(torch.from_numpy(g).cuda(), lr)
+        before = P.copy()
+        oracle.adam_step(P, g.astype(np.float64), M, V, t, lr)
+        path += np.abs(P - before)
+        if t in (1, 2, 10):
+            got = torch.cat([v.reshape(-1) for k2, v in p.get_params().items()
+                             if k2 in vj.Predictor.PARAMS]).cpu().numpy().astype(np.float64)
+            m, v, steps = p.adam_state()
+            m, v = m.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64)
+            assert steps == t
+            # the displacement from the start is what Adam computed: each step
+            # within 1e-5 of its size, plus the fp32 rounding of the parameter
+            # itself (an ulp per step)
+            disp_err = np.abs((got - flat0) - (P - flat0))
+            tol = 1e-5 * path + 2 * t * np.abs(P) * 2.0 ** -24 + 1e-12
+            worst = float((disp_err / tol).max())
+            m_err = np.abs(m - M).max() / np.abs(M).max()
+            v_err = np.abs(v - V).max() / np.abs(V).max()
+            print(f"[adam] t={t}: displacement err / tol {worst:.3f}, m rel {m_err:.2e}, "
+                  f"v rel {v_err:.2e}", flush=True)
+            assert worst <= 1.0
+            np.testing.assert_allclose(m, M, rtol=1e-5, atol=1e-5 * np.abs(M).max())
+            np.testing.assert_allclose(v, V, rtol=1e-5, atol=1e-5 * np.abs(V).max())
 
 
 def test_training_reduces_loss():
