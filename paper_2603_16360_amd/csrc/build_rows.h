@@ -88,11 +88,12 @@ k_rerank(const float *vec, int64_t N, const int32_t *bid, int K, int Kc, int32_t
 }
 
 // RNG prune of one wave's candidate list (sorted by (d2, id), m entries, in
-// LDS).  keep v unless a kept w has d2(w, v) < d2(u, v); at most R kept.
+// LDS), continuing from the nk0 ids already in kept[]: keep v unless a kept w
+// has d2(w, v) < d2(u, v); at most R kept.  Returns the new kept count.
 template <int DP>
 __device__ __forceinline__ int rng_prune(const float *vec, const int32_t *cid, const float *cd2,
-                                         int m, int R, int32_t *kept, int lane) {
-    int nk = 0;
+                                         int m, int R, int32_t *kept, int lane, int nk0 = 0) {
+    int nk = nk0;
     for (int i = 0; i < m && nk < R; ++i) {
         const int32_t v = cid[i];
         const float dv = cd2[i];
@@ -143,8 +144,11 @@ k_prune_fwd(const float *vec, int64_t N, const int32_t *kid, const float *kd2, i
 
 
 // final rows: fwd(v) + rev(v), sorted by (d2, id), deduplicated; kept whole
-// if <= R, else RNG-pruned to R.  Reverse lists longer than the buffer keep
-// their smallest (d2, id) entries (streamed through a sorted 1024 buffer).
+// if <= R, else RNG-pruned to R over the whole sorted list.  The candidates
+// are streamed through a sorted buffer of 1024 (16 per lane); when more than
+// 1024 pass a pass's filter, only the first 768 of the buffer are exact ranks,
+// so the prune takes those and the next pass streams the candidates after
+// the last of them again, until R are kept or the list is exhausted.
 template <int DP>
 __global__ void __launch_bounds__(256)
 k_prune_rev(const float *vec, int64_t N, int R, const int32_t *fwd, const float *fwd_d2,
@@ -156,59 +160,79 @@ k_prune_rev(const float *vec, int64_t N, int R, const int32_t *fwd, const float 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t v = (int64_t)blockIdx.x * 4 + w;
     if (v >= N) return;
-    float key[16];
-    int id[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) { key[j] = INFINITY; id[j] = 0x7fffffff; }
     const int nf = fdeg[v];
     const int64_t r0 = roff[v], nr = roff[v + 1] - r0;
     const int64_t total = nf + nr;
-    // stream all candidates through the sorted buffer, 256 new ones at a time
-    for (int64_t base = 0; base < total; base += 256) {
+    // exclusive lower bound (in (d2, id) order) of the candidates a pass takes
+    float lo_k = -INFINITY;
+    int lo_i = -1;
+    int nk = 0;
+    for (int pass = 0;; ++pass) {
+        float key[16];
+        int id[16];
 #pragma unroll
-        for (int j = 12; j < 16; ++j) {
-            const int64_t e = base + (j - 12) * 64 + lane;
-            float k = INFINITY;
-            int i = 0x7fffffff;
-            if (e < total) {
-                if (e < nf) { i = fwd[v * R + e]; k = fwd_d2[v * R + e]; }
-                else { i = rid[r0 + (e - nf)]; k = rd2[r0 + (e - nf)]; }
+        for (int j = 0; j < 16; ++j) { key[j] = INFINITY; id[j] = 0x7fffffff; }
+        // stream the candidates after the bound, 256 new ones at a time into
+        // ranks 768..1023 of the sorted buffer; ranks 0..767 always hold the
+        // 768 smallest streamed so far.  `lost`: a candidate at ranks
+        // 768..1023 was overwritten, so only ranks 0..767 are exact.
+        bool lost = false;
+        for (int64_t base = 0; base < total; base += 256) {
+            lost |= __ballot(id[12] != 0x7fffffff || id[13] != 0x7fffffff ||
+                             id[14] != 0x7fffffff || id[15] != 0x7fffffff) != 0;
+#pragma unroll
+            for (int j = 12; j < 16; ++j) {
+                const int64_t e = base + (j - 12) * 64 + lane;
+                float k = INFINITY;
+                int i = 0x7fffffff;
+                if (e < total) {
+                    if (e < nf) { i = fwd[v * R + e]; k = fwd_d2[v * R + e]; }
+                    else { i = rid[r0 + (e - nf)]; k = rd2[r0 + (e - nf)]; }
+                    if (!mt::kless(lo_k, lo_i, k, i)) { k = INFINITY; i = 0x7fffffff; }
+                }
+                key[j] = k;
+                id[j] = i;
             }
-            key[j] = k;
-            id[j] = i;
+            mt::wave_sort<16>(key, id, lane);
         }
-        mt::wave_sort<16>(key, id, lane);
-    }
-    // dedup (equal ids are adjacent: same id, same squared distance); when
-    // more than 1024 candidates were streamed only the first 768 of the
-    // sorted buffer are exact ranks, so only those are used
-    const int limit = total > kCandMax ? 768 : kCandMax;
-    int m = 0;
+        // nothing lost: the buffer holds every remaining candidate, in order
+        const bool last = !lost;
+        const int limit = last ? kCandMax : 768;
+        // dedup (equal ids are adjacent: same id, same squared distance)
+        int m = 0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int up = __shfl_up(id[j], 1);
-        const int last = j > 0 ? __shfl(id[j > 0 ? j - 1 : 0], 63) : -2;
-        const int prev = lane == 0 ? last : up;
-        const bool keep = (j * 64 + lane) < limit && key[j] < INFINITY && id[j] != 0x7fffffff &&
-                          id[j] != prev;
-        const uint64_t mk = __ballot(keep);
-        if (keep) {
-            const int at = m + __popcll(mk & ((1ull << lane) - 1ull));
-            s_cid[w][at] = id[j];
-            s_cd[w][at] = key[j];
+        for (int j = 0; j < 16; ++j) {
+            const int up = __shfl_up(id[j], 1);
+            const int prv = j > 0 ? __shfl(id[j > 0 ? j - 1 : 0], 63) : -2;
+            const int prev = lane == 0 ? prv : up;
+            const bool keep = (j * 64 + lane) < limit && key[j] < INFINITY && id[j] != 0x7fffffff &&
+                              id[j] != prev;
+            const uint64_t mk = __ballot(keep);
+            if (keep) {
+                const int at = m + __popcll(mk & ((1ull << lane) - 1ull));
+                s_cid[w][at] = id[j];
+                s_cd[w][at] = key[j];
+            }
+            m += __popcll(mk);
         }
-        m += __popcll(mk);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    int nk;
-    if (m <= R) {
-        for (int e = lane; e < m; e += 64) s_kept[w][e] = s_cid[w][e];
-        nk = m;
+        // the last exact rank of this pass bounds the next one (entry 767:
+        // register 11 of lane 63)
+        lo_k = __shfl(key[11], 63);
+        lo_i = __shfl(id[11], 63);
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
         __builtin_amdgcn_wave_barrier();
-    } else {
-        nk = rng_prune<DP>(vec, s_cid[w], s_cd[w], m, R, s_kept[w], lane);
+        if (pass == 0 && last && m <= R) {
+            // the whole list fits: keep every candidate
+            for (int e = lane; e < m; e += 64) s_kept[w][e] = s_cid[w][e];
+            nk = m;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            break;
+        }
+        nk = rng_prune<DP>(vec, s_cid[w], s_cd[w], m, R, s_kept[w], lane, nk);
+        if (last || nk >= R) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
     }
     for (int e = lane; e < R; e += 64) adj[v * R + e] = e < nk ? s_kept[w][e] : -1;
 }

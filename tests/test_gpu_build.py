@@ -67,6 +67,21 @@ def test_build_integer_data_identical():
     _invariants(w, adj, elen, info["entry"], 32)
 
 
+def test_build_hub_identical():
+    # one node with 1,024 reverse-edge candidates whose 768 nearest prune to
+    # fewer than R edges: the build must prune the whole list, as the oracle
+    # does (its rows are pinned by a hand derivation on the CPU)
+    w = workloads.hub_chain()
+    idx, adj, elen, parent = _build(w, 32)
+    g = oracle.build_merged(w.Q, w.X, 32)
+    assert idx.info()["entry"] == g.entry
+    print(f"[build] hub row {adj[0].tolist()}", flush=True)
+    assert adj[0].tolist() == g.adj[0].tolist()
+    same = (adj == g.adj).all(axis=1)
+    assert same.all(), np.nonzero(~same)[0][:10]
+    _invariants(w, adj, elen, g.entry, 32)
+
+
 def test_build_float_data():
     w = workloads.config_tiny()  # 10,000 + 1,000 nodes, d=32
     idx, adj, elen, parent = _build(w, 16)

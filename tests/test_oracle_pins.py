@@ -574,3 +574,27 @@ def test_nlj_counts_per_query_against_scipy():
     assert len(set(want.tolist())) > 10  # the split differs from query to query
     assert np.array_equal(oracle.nlj_counts(Q, X, eps, "l2"),
                           np.bincount(oracle.nlj(Q, X, eps)[0], minlength=Q.shape[0]))
+
+
+def test_build_hub_worked_example():
+    """or_build_merged on the hub workload, against rows derived by hand from
+    the RNG rule of Appendix C (keep v unless a kept w has dist(w, v) <
+    dist(u, v); ties by id).  Chain vector a_t (node 1 + t) is at squared
+    distance 2k from a_(t+-k) (k < 60) and 60 from the hub (node 0): its kNN
+    list puts a_(t-1), a_(t+1) first, both kept, every other chain vector is
+    blocked by one of them, and the hub (at 60, not strictly farther from
+    a_(t-1) than from a_t) is kept.  So the hub has 1,024 reverse-edge
+    candidates, all at squared distance 60, scanned by id: a_s is blocked by
+    a kept a_t iff the cyclic offset |s - t| < 30, so the kept ones are a_0,
+    a_30, ..., up to R = 32 of them.  A prune limited to the 768 nearest
+    candidates would stop at a_750 with 26 edges."""
+    w = workloads.hub_chain()
+    g = oracle.build_merged(w.Q, w.X, 32)
+    assert g.adj[0].tolist() == [1 + 30 * j for j in range(32)]
+    for t in (5, 500, 1000):
+        assert g.adj[1 + t, :3].tolist() == [t, t + 2, 0] and (g.adj[1 + t, 3:] == -1).all()
+    # the same prune over the first 768 candidates only keeps 26
+    V = np.concatenate([w.X, w.Q])
+    cand = np.arange(1, 769, dtype=np.int32)
+    kept = oracle.rng_prune(V, 0, cand, np.full(768, np.sqrt(60.0)), 32)
+    assert kept.tolist() == [1 + 30 * j for j in range(26)]

@@ -36,6 +36,7 @@ __all__ = [
     "config_ood",
     "config_stream",
     "vmf_kappa_for_mean_cosine",
+    "hub_chain",
 ]
 
 
@@ -316,3 +317,24 @@ def config_stream(scale: float = 1.0, n_batches: int = 200) -> Workload:
 def stream_batches(w: Workload):
     """(start, count, target_mean) of each batch of a stream workload."""
     return list(w.meta["batches"])
+
+
+def hub_chain(d: int = 1024, window: int = 60, n_queries: int = 8) -> Workload:
+    """A graph-build edge case: one hub with more reverse-edge candidates
+    than a node usually has (0/1 integer data, exact in every precision).
+
+    X[0] is the origin (the hub); X[1 + t], t = 0..d-1, is the 0/1 vector
+    with ones at the ``window`` cyclically consecutive coordinates starting
+    at t.  Every chain vector lies at the same distance sqrt(window) from
+    the hub, and two chain vectors at cyclic offset k differ in 2 min(k,
+    window) coordinates.  Q holds ``n_queries`` far-away points (value 200 in
+    one coordinate).  No randomness.
+    """
+    X = np.zeros((1 + d, d), np.float32)
+    for t in range(d):
+        X[1 + t, (t + np.arange(window)) % d] = 1.0
+    Q = np.zeros((n_queries, d), np.float32)
+    for i in range(n_queries):
+        Q[i, (i * 97) % d] = 200.0
+    return Workload("hub_chain", Q, X, "l2", 32, 1.0, 0, n_queries,
+                    {"window": window, "integer": True})
