@@ -43,7 +43,8 @@ typedef enum {
     VJ_ERR_OOM = 3,             /* device allocation failed */
     VJ_ERR_HIP = 4,             /* a HIP runtime call failed */
     VJ_ERR_INTERNAL = 5,        /* a kernel reported an inconsistency */
-    VJ_ERR_UNSUPPORTED = 6      /* shape outside the supported range (see each call) */
+    VJ_ERR_UNSUPPORTED = 6,     /* shape outside the supported range (see each call) */
+    VJ_ERR_IO = 7               /* a file could not be written or read, or is not a valid file */
 } vj_status;
 
 typedef enum { VJ_L2 = 0, VJ_IP = 1 } vj_metric;
@@ -123,7 +124,7 @@ void vj_default_join_params(vj_join_params *p);
  * edge lengths -> query MST (Section 3.2).  The graph is always built on L2
  * geometry; `metric` is the metric joins must use (for VJ_IP the rows
  * should be unit-norm, where L2 and IP orders coincide).
- * Limits: 1 <= d <= 1024, nq + nx < 2^31, 1 <= R <= 64.
+ * Limits: 1 <= d <= 1024, nq + nx < 2^30, 1 <= R <= 64 (VJ_ERR_UNSUPPORTED).
  */
 vj_status vj_build_merged_index(const float *Q, int64_t nq, const float *X, int64_t nx,
                                 int32_t d, vj_metric metric, const vj_build_params *p,
@@ -153,19 +154,35 @@ vj_status vj_index_info(const vj_index *idx, int64_t *nq, int64_t *nx, int32_t *
 void vj_index_free(vj_index *idx);
 
 /*
+ * Index files.  The paper builds the merged index once, offline, and reuses
+ * it for every later join and threshold (Section 4.3); a file keeps it
+ * across processes.  vj_index_save writes the vectors (padded fp32 rows),
+ * the graph, its edge lengths, the entry node and the query MST to `path`
+ * (host string; the file is overwritten) and synchronises the device.
+ * vj_index_load reads such a file into a new index on the current device
+ * (exact low-precision copies and the join state are rebuilt there); joins
+ * on it give the same results as on the saved index.  A missing,
+ * truncated or corrupt file (checked by a hash of its bytes) returns
+ * VJ_ERR_IO.  An attached predictor is not part of the index file.
+ */
+vj_status vj_index_save(const vj_index *idx, const char *path);
+vj_status vj_index_load(const char *path, void *stream, vj_index **out);
+
+/*
  * The merged-index join (Algorithm 1 with cfg.merged = true) of the queries
  * query_ids[0..n) (indices into Q; NULL = all nq queries in order) at
  * threshold eps.  In SOFT/HARD mode queries are processed parents-first
  * along the MST; a query whose MST parent is not in this call gets no
- * cached seed.  eps <= 0 (L2) returns an empty result.  Each query runs on
- * one wavefront with its visited set, worklist and pairs in LDS (1024-slot
- * visited set, 512 pairs, four waves per workgroup); a query that outgrows
- * them is re-run by a whole workgroup of four waves on 8192 LDS slots and
- * 768 pairs (the default first tier), then on tables in global memory
- * (2^16 slots and 32768 pairs: within the same launch while the index's
- * regions last, else in a re-run launch; then as large as the data set).
- * Calls on one
- * index must not overlap (they share the index's per-query cache).
+ * cached seed.  eps <= 0 (L2) returns an empty result.  By default
+ * (start_tier = 1) each query runs on one workgroup of four waves with its
+ * visited set, in-range list and out-range queue in LDS (8192 visited slots
+ * and 768 pairs, or 4096 and 1024 with coop_tables = 1); start_tier = 0
+ * starts every query on one wavefront (1024 slots, 512 pairs, four queries
+ * per workgroup).  A query that outgrows its tier re-runs on the next: one
+ * workgroup on tables in global memory (2^16 slots and 32768 pairs: within
+ * the same launch while the index's regions last, else in a re-run
+ * launch), then on tables as large as the data set.  Calls on one index
+ * must not overlap (they share the index's per-query cache).
  * Limits: hybrid_beam <= 256.
  */
 vj_status vj_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
@@ -331,6 +348,26 @@ vj_status vj_predictor_loss_grad(const vj_predictor *p, const float *X, const fl
 vj_status vj_predictor_train(vj_predictor *p, const float *X, const float *Y, int64_t n,
                              int32_t epochs, int32_t batch, float lr, uint64_t seed,
                              float *loss_per_epoch_host, void *stream);
+/* One Adam step (Kingma and Ba 2015, Algorithm 1: beta 0.9 / 0.999, eps
+ * 1e-8 outside the square root, bias-corrected moments; the step counter is
+ * the predictor's, shared with vj_predictor_train) with the caller's
+ * gradient: grad, device, n_params floats = every parameter back to back in
+ * the order W1 b1 W2 b2 W3 b3 (the shapes above), with n_params = h1*din +
+ * h1 + h2*h1 + h2 + k*h2 + k. */
+vj_status vj_predictor_adam_step(vj_predictor *p, const float *grad, float lr, void *stream);
+/* The optimizer state: first and second moments (device, n_params floats
+ * each, layout of vj_predictor_adam_step's grad; either may be NULL) and the
+ * number of steps taken (host, may be NULL). */
+vj_status vj_predictor_get_adam_state(const vj_predictor *p, float *m, float *v, int64_t *steps,
+                                      void *stream);
+/* Layer widths of a predictor (host; any pointer may be NULL). */
+vj_status vj_predictor_info(const vj_predictor *p, int32_t *din, int32_t *h1, int32_t *h2,
+                            int32_t *k);
+/* Predictor files (host path string): parameters, input normalisation, the
+ * optimizer's moments and step count, so training can resume.  Errors as
+ * for vj_index_save / vj_index_load. */
+vj_status vj_predictor_save(const vj_predictor *p, const char *path);
+vj_status vj_predictor_load(const char *path, void *stream, vj_predictor **out);
 /* Attach a predictor to an index for VJ_HYB_LEARNED joins (NULL detaches):
  * head j predicts the recall under budgets_host[j] out-range pops (k values,
  * ascending, >= 0).  The predictor must outlive its use by the index. */

@@ -1,8 +1,10 @@
 // Merged-index join kernel: the online path of Algorithm 1 with cfg.merged =
 // true (Sections 4.1-4.4).  Included by one translation unit per row type.
 //
-// Shape: one wavefront (64 lanes) per query; a launch covers a contiguous
-// range of a processing list, four waves per workgroup.  Per query:
+// Shape: by default one workgroup (four waves) per query (the workgroup
+// tier); the small tier runs one wavefront (64 lanes) per query, four per
+// workgroup.  A launch covers a contiguous range of a processing list.  Per
+// query:
 //   seeds    {s} (+ the parent's cached node, soft mode; its in-range
 //            nodes, hard mode)                                  Algorithm 3
 //   probe    the neighbours of the query node q                 Algorithms 4-5
@@ -13,9 +15,9 @@
 //   cache    closest visited data node (soft)                   Algorithm 8
 // All per-query state lives in LDS: the visited hash, the in-range worklist
 // (which is also the query's pair buffer) and the out-range queue.  A query
-// that outgrows them is re-run on a larger tier: a whole workgroup with 8x
-// the LDS visited slots, then (in the same launch while free regions last) a
-// whole workgroup with tables in global memory.
+// that outgrows them is re-run on a larger tier: from the one-wave tier a
+// whole workgroup with 8x the LDS visited slots, then (in the same launch
+// while free regions last) a whole workgroup with tables in global memory.
 //
 // Rows are gathered LPR lanes per row, 16 bytes per lane per load (a row
 // group's load covers whole 128-byte lines), and reduced with xor shuffles

@@ -42,11 +42,8 @@ static int ceil_log2(int64_t v) {
 
 // ----------------------------------------------------------------- index --
 
-// copy + pad the vectors, exact low-precision copies, join state
-static void init_vectors(Index &ix, const float *Q, const float *X, hipStream_t s) {
-    ix.vec.alloc((size_t)ix.N * ix.dp * sizeof(float));
-    launch_pad_rows(X, ix.nx, ix.d, ix.vec.as<float>(), ix.dp, s);
-    launch_pad_rows(Q, ix.nq, ix.d, ix.vec.as<float>() + (size_t)ix.nx * ix.dp, ix.dp, s);
+// exact low-precision copies of the padded rows in ix.vec, join state
+static void finish_vectors(Index &ix, hipStream_t s) {
     DevBuf flag(sizeof(int32_t));
     VJ_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
     ix.vec_u8.alloc((size_t)ix.N * ix.dp);
@@ -66,6 +63,14 @@ static void init_vectors(Index &ix, const float *Q, const float *X, hipStream_t 
     VJ_HIP(hipMemsetAsync(ix.inb.p, 0, ix.inb.bytes, s));
     VJ_HIP(hipMemsetAsync(ix.seg.p, 0, ix.seg.bytes, s));
     VJ_HIP(hipMemsetAsync(ix.segn.p, 0, ix.segn.bytes, s));
+}
+
+// copy + pad the vectors, exact low-precision copies, join state
+static void init_vectors(Index &ix, const float *Q, const float *X, hipStream_t s) {
+    ix.vec.alloc((size_t)ix.N * ix.dp * sizeof(float));
+    launch_pad_rows(X, ix.nx, ix.d, ix.vec.as<float>(), ix.dp, s);
+    launch_pad_rows(Q, ix.nq, ix.d, ix.vec.as<float>() + (size_t)ix.nx * ix.dp, ix.dp, s);
+    finish_vectors(ix, s);
 }
 
 void ensure_bf16(Index &ix, hipStream_t s) {
@@ -197,6 +202,12 @@ static void check_shape(const float *Q, int64_t nq, const float *X, int64_t nx, 
     VJ_CHECK(d >= 1, VJ_ERR_INVALID_ARG, "d must be >= 1");
     VJ_CHECK(d <= 1024, VJ_ERR_UNSUPPORTED, "d must be <= 1024");
     VJ_CHECK(nq + nx < ((int64_t)1 << 31) - 1, VJ_ERR_UNSUPPORTED, "nq + nx must be < 2^31 - 1");
+}
+
+// An index's node ids must stay below 2^30: the workgroup tier of the join
+// carries a flag in bit 30 of the node ids it stages.
+static void check_index_size(int64_t nq, int64_t nx) {
+    VJ_CHECK(nq + nx < ((int64_t)1 << 30), VJ_ERR_UNSUPPORTED, "an index needs nq + nx < 2^30");
 }
 
 // ------------------------------------------------------------------ join --
@@ -1008,6 +1019,7 @@ vj_status vj_index_from_graph(const float *Q, int64_t nq, const float *X, int64_
     API_BEGIN
     VJ_CHECK(out != nullptr && adj != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
     check_shape(Q, nq, X, nx, d);
+    check_index_size(nq, nx);
     VJ_CHECK(metric == VJ_L2 || metric == VJ_IP, VJ_ERR_INVALID_ARG, "unknown metric");
     VJ_CHECK(R >= 1 && R <= 64, VJ_ERR_UNSUPPORTED, "R must be in [1, 64]");
     VJ_CHECK(entry >= 0 && entry < nq + nx, VJ_ERR_INVALID_ARG, "entry out of range");
@@ -1040,6 +1052,7 @@ vj_status vj_build_merged_index(const float *Q, int64_t nq, const float *X, int6
     API_BEGIN
     VJ_CHECK(out != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
     check_shape(Q, nq, X, nx, d);
+    check_index_size(nq, nx);
     VJ_CHECK(metric == VJ_L2 || metric == VJ_IP, VJ_ERR_INVALID_ARG, "unknown metric");
     vj_build_params p;
     vj_default_build_params(&p);
@@ -1093,6 +1106,25 @@ vj_status vj_index_info(const vj_index *idx, int64_t *nq, int64_t *nx, int32_t *
 }
 
 void vj_index_free(vj_index *idx) { delete idx; }
+
+vj_status vj_index_save(const vj_index *idx, const char *path) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr && path != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    VJ_HIP(hipDeviceSynchronize());
+    index_save(idx->impl, path);
+    API_END
+}
+
+vj_status vj_index_load(const char *path, void *stream, vj_index **out) {
+    API_BEGIN
+    VJ_CHECK(path != nullptr && out != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    auto h = std::make_unique<vj_index>();
+    index_load(h->impl, path, finish_vectors, s);
+    VJ_HIP(hipStreamSynchronize(s));
+    *out = h.release();
+    API_END
+}
 
 vj_status vj_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps, vj_metric metric,
                   const vj_join_params *pp, void *stream, vj_pairs **out) {
@@ -1433,6 +1465,61 @@ vj_status vj_predictor_train(vj_predictor *pr, const float *X, const float *Y, i
              "epochs >= 0, batch >= 1, lr > 0");
     predictor_train(pr->impl, X, Y, n, epochs, batch, lr, seed, loss_per_epoch_host,
                     (hipStream_t)stream);
+    API_END
+}
+
+vj_status vj_predictor_info(const vj_predictor *pr, int32_t *din, int32_t *h1, int32_t *h2,
+                            int32_t *k) {
+    API_BEGIN
+    VJ_CHECK(pr != nullptr, VJ_ERR_INVALID_ARG, "null predictor");
+    const Predictor &p = pr->impl;
+    if (din) *din = p.din;
+    if (h1) *h1 = p.h1;
+    if (h2) *h2 = p.h2;
+    if (k) *k = p.k;
+    API_END
+}
+
+vj_status vj_predictor_save(const vj_predictor *pr, const char *path) {
+    API_BEGIN
+    VJ_CHECK(pr != nullptr && path != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    VJ_HIP(hipDeviceSynchronize());
+    predictor_save(pr->impl, path);
+    API_END
+}
+
+vj_status vj_predictor_load(const char *path, void *stream, vj_predictor **out) {
+    API_BEGIN
+    VJ_CHECK(path != nullptr && out != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    auto h = std::make_unique<vj_predictor>();
+    predictor_load(h->impl, path, s);
+    VJ_HIP(hipStreamSynchronize(s));
+    *out = h.release();
+    API_END
+}
+
+vj_status vj_predictor_adam_step(vj_predictor *pr, const float *grad, float lr, void *stream) {
+    API_BEGIN
+    VJ_CHECK(pr != nullptr && grad != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    VJ_CHECK(std::isfinite(lr) && lr > 0.f, VJ_ERR_INVALID_ARG, "lr > 0");
+    hipStream_t s = (hipStream_t)stream;
+    predictor_adam(pr->impl, grad, lr, s);
+    VJ_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
+vj_status vj_predictor_get_adam_state(const vj_predictor *pr, float *m, float *v,
+                                      int64_t *steps, void *stream) {
+    API_BEGIN
+    VJ_CHECK(pr != nullptr, VJ_ERR_INVALID_ARG, "null predictor");
+    const Predictor &p = pr->impl;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = p.n_params() * sizeof(float);
+    if (m) VJ_HIP(hipMemcpyAsync(m, p.m.p, bytes, hipMemcpyDeviceToDevice, s));
+    if (v) VJ_HIP(hipMemcpyAsync(v, p.v.p, bytes, hipMemcpyDeviceToDevice, s));
+    if (steps) *steps = p.steps;
+    VJ_HIP(hipStreamSynchronize(s));
     API_END
 }
 

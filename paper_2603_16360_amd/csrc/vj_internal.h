@@ -240,4 +240,9 @@ void launch_quantize(const float *vec, int64_t rows, int dp, uint8_t *u8, uint16
 // pairs export
 void export_pairs(const Pairs &r, int32_t *qx, float *dist, bool sorted, hipStream_t s);
 
+// index files: the padded rows, graph, edge lengths and MST; at load
+// `finish` rebuilds the exact low-precision copies and the join state
+void index_save(const Index &ix, const char *path);
+void index_load(Index &ix, const char *path, void (*finish)(Index &, hipStream_t), hipStream_t s);
+
 }  // namespace vj

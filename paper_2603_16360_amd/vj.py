@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -22,7 +23,7 @@ _lib = C.CDLL(LIB_PATH)
 
 VJ_OK = 0
 STATUS = {0: "VJ_OK", 1: "VJ_ERR_INVALID_ARG", 2: "VJ_ERR_METRIC_MISMATCH", 3: "VJ_ERR_OOM",
-          4: "VJ_ERR_HIP", 5: "VJ_ERR_INTERNAL", 6: "VJ_ERR_UNSUPPORTED"}
+          4: "VJ_ERR_HIP", 5: "VJ_ERR_INTERNAL", 6: "VJ_ERR_UNSUPPORTED", 7: "VJ_ERR_IO"}
 METRIC = {"l2": 0, "ip": 1}
 WORK_SHARING = {"self": 0, "soft": 1, "hard": 2}
 HYBRID = {"off": 0, "force": 1, "adapt": 2, "budget": 3, "learned": 4}
@@ -64,6 +65,11 @@ _SIGS = {
     "vj_index_export_graph": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vj_index_info": (C.c_int, [_vp] + [_vp] * 6),
     "vj_index_free": (None, [_vp]),
+    "vj_index_save": (C.c_int, [_vp, C.c_char_p]),
+    "vj_index_load": (C.c_int, [C.c_char_p, _vp, _PP]),
+    "vj_predictor_save": (C.c_int, [_vp, C.c_char_p]),
+    "vj_predictor_load": (C.c_int, [C.c_char_p, _vp, _PP]),
+    "vj_predictor_info": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vj_join": (C.c_int, [_vp, _vp, _i64, _f32, C.c_int, C.POINTER(vj_join_params), _vp, _PP]),
     "vj_bruteforce_join": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _f32, C.c_int, C.c_int,
                                      _vp, _PP]),
@@ -90,6 +96,8 @@ _SIGS = {
     "vj_predictor_loss_grad": (C.c_int, [_vp, _vp, _vp, _vp, _i64, C.POINTER(C.c_double)]
                                + [_vp] * 6 + [_vp]),
     "vj_predictor_train": (C.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _f32, C.c_uint64, _vp, _vp]),
+    "vj_predictor_adam_step": (C.c_int, [_vp, _vp, _f32, _vp]),
+    "vj_predictor_get_adam_state": (C.c_int, [_vp, _vp, _vp, C.POINTER(_i64), _vp]),
     "vj_index_attach_predictor": (C.c_int, [_vp, _vp, _f32, _vp]),
     "vj_last_error": (C.c_char_p, []),
 }
@@ -201,6 +209,17 @@ class Index:
         parent = torch.empty(i["nq"], dtype=torch.int32, device="cuda")
         _check(_lib.vj_index_export_graph(self._h, _ptr(adj), _ptr(elen), _ptr(parent), _stream()))
         return adj, elen, parent
+
+    def save(self, path: str):
+        """Write the index to a file (vj_index_save)."""
+        _check(_lib.vj_index_save(self._h, os.fsencode(path)))
+
+
+def vj_index_load(path: str) -> Index:
+    """Read an index file written by Index.save (vj_index_load)."""
+    h = C.c_void_p()
+    _check(_lib.vj_index_load(os.fsencode(path), _stream(), C.byref(h)))
+    return Index(h.value)
 
 
 # ---------------------------------------------------------------- functions --
@@ -402,6 +421,51 @@ class Predictor:
         _check(_lib.vj_predictor_train(self._h, _ptr(X), _ptr(Y), X.shape[0], epochs, batch,
                                        float(lr), seed, losses, _stream()))
         return list(losses)[:epochs]
+
+    PARAMS = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+    def save(self, path: str):
+        """Write parameters, normalisation and optimizer state (vj_predictor_save)."""
+        _check(_lib.vj_predictor_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path: str) -> "Predictor":
+        """Read a predictor file (vj_predictor_load)."""
+        h = C.c_void_p()
+        _check(_lib.vj_predictor_load(os.fsencode(path), _stream(), C.byref(h)))
+        p = cls.__new__(cls)
+        p._h = h
+        p._read_shapes()
+        return p
+
+    def _read_shapes(self):
+        din, h1, h2, k = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(_lib.vj_predictor_info(self._h, C.byref(din), C.byref(h1), C.byref(h2), C.byref(k)))
+        din, h1, h2, k = din.value, h1.value, h2.value, k.value
+        self.shapes = {"W1": (h1, din), "b1": (h1,), "W2": (h2, h1), "b2": (h2,),
+                       "W3": (k, h2), "b3": (k,), "mu": (din,), "inv_sigma": (din,)}
+        self.din, self.k = din, k
+
+    @property
+    def n_params(self) -> int:
+        return sum(int(np.prod(self.shapes[k])) for k in self.PARAMS)
+
+    def adam_step(self, grad: torch.Tensor, lr: float = 1e-3):
+        """One Adam step with the caller's gradient: every parameter back to
+        back (order W1 b1 W2 b2 W3 b3), n_params floats."""
+        g = _dev(grad, torch.float32, "grad").reshape(-1)
+        if g.numel() != self.n_params:
+            raise ValueError(f"grad must hold {self.n_params} floats")
+        _check(_lib.vj_predictor_adam_step(self._h, _ptr(g), float(lr), _stream()))
+
+    def adam_state(self):
+        """(m, v, steps): the optimizer's moments (flat, layout of adam_step)
+        and its step count."""
+        m = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        v = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        t = C.c_int64()
+        _check(_lib.vj_predictor_get_adam_state(self._h, _ptr(m), _ptr(v), C.byref(t), _stream()))
+        return m, v, t.value
 
 
 def vj_index_attach_predictor(index: Index, pred: Predictor | None, recall_target: float = 0.95,

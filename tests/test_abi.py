@@ -46,3 +46,25 @@ def test_last_error_is_empty_string_initially():
     lib = ctypes.CDLL(LIB)
     lib.vj_last_error.restype = ctypes.c_char_p
     assert lib.vj_last_error() == b""
+
+
+def test_index_size_limit_is_checked_before_any_device_work():
+    # node ids of an index must stay below 2^30; the check runs before any
+    # HIP call, so it needs no GPU (the pointers are never read)
+    import pytest
+    if not os.path.exists(LIB):
+        pytest.skip("libvj.so not built")
+    lib = ctypes.CDLL(LIB)
+    lib.vj_last_error.restype = ctypes.c_char_p
+    f = lib.vj_build_merged_index
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                  ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(16)
+    st = f(fake, 1 << 29, fake, 1 << 29, 16, 0, None, None, ctypes.byref(out))
+    assert st == 6 and b"2^30" in lib.vj_last_error()
+    assert out.value is None
+    # d out of range and a null vector pointer are argument errors too
+    assert f(fake, 4, fake, 4, 0, 0, None, None, ctypes.byref(out)) == 1
+    assert f(fake, 4, None, 4, 8, 0, None, None, ctypes.byref(out)) == 1
