@@ -202,6 +202,27 @@ vj_status vj_bruteforce_join(const float *Q, int64_t nq, const float *X, int64_t
                              void *stream, vj_pairs **out);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture of the surrounding work, tight serving loops, harnesses that
+ * forbid hipMalloc): vj_bruteforce_join with no allocation of any kind.
+ * Its temporaries (bf16 tile rows and norms of Q and X, thresholds,
+ * candidate pairs, counters) live in one fixed device region of 64 MiB per
+ * device, held by the library until the process ends; the pairs go to the
+ * caller's qx [cap][2] int32 (query index, data index) and dist [cap]
+ * float32 (may be NULL), in no particular order.  *count_host receives the
+ * number of pairs; if it exceeds cap only cap of them were written (which
+ * ones is unspecified) and the call must be repeated with a larger buffer.
+ * Inputs whose temporaries do not fit (about (nq + nx) * (4 Kp + 4) bytes
+ * for VJ_PREC_FP32, Kp = d rounded up to 32, plus 8 bytes per candidate
+ * pair) return VJ_ERR_UNSUPPORTED.  The call synchronises `stream`.
+ * Calls that overlap on one device race on the region: serialise them.
+ */
+vj_status vj_bruteforce_join_noalloc(const float *Q, int64_t nq, const float *X, int64_t nx,
+                                     int32_t d, float eps, vj_metric metric, vj_precision prec,
+                                     int32_t *qx, float *dist, int64_t cap, int64_t *count_host,
+                                     void *stream);
+
+/*
  * Batches (a stream of joins on one index): batch b joins the queries
  * query_ids[start[b] .. start[b] + count[b]) (indices into Q; query_ids NULL:
  * the ids start[b] .. start[b] + count[b] - 1 themselves) at eps_host[b],

@@ -16,8 +16,28 @@ struct TileRows {
     bool small_int = false;  // every value an integer with |v| <= 256
 };
 
+// Device memory for one call's temporaries: fresh allocations (base null),
+// or 256-byte aligned slices of a fixed region that is never grown, so a
+// call on a region allocates nothing.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    DevBuf take(size_t bytes) {
+        if (!base) return DevBuf(bytes);
+        const size_t at = (used + 255) & ~(size_t)255;
+        VJ_CHECK(at <= cap && bytes <= cap - at, VJ_ERR_UNSUPPORTED,
+                 "the call's temporaries exceed the fixed scratch region");
+        used = at + bytes;
+        return DevBuf::view(base + at, bytes);
+    }
+    size_t left() const {
+        const size_t at = (used + 255) & ~(size_t)255;
+        return at < cap ? cap - at : 0;
+    }
+};
+
 void prepare_rows(const float *src, int64_t rows, int d, int Kp, bool split, TileRows &t,
-                  hipStream_t s);
+                  hipStream_t s, Arena *arena = nullptr);
 
 // Bounds of the tile value's error: |dot~ - dot| <= e_dot |a||b| and the
 // remaining fp32 operations add at most e_fin (|a| + |b|)^2 (0 and 0 when the
@@ -29,5 +49,15 @@ void tile_error_bounds(const TileRows &a, const TileRows &b, int nsplit, double 
 // every pair whose tile value lies inside the rounding-error bound of eps.
 void bruteforce_join(const float *Q, int64_t nq, const float *X, int64_t nx, int d, float eps,
                      vj_metric metric, vj_precision prec, hipStream_t s, Pairs &out);
+
+// The same join with every temporary in the library's fixed device scratch
+// region (kNoAllocScratchBytes per device; no allocation of any kind) and
+// the pairs written to the caller's qx [cap][2] (query, data) and dist
+// [cap] (may be null), in no particular order.  Returns the number of pairs
+// (if it exceeds cap, cap of them were written).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+int64_t bruteforce_join_noalloc(const float *Q, int64_t nq, const float *X, int64_t nx, int d,
+                                float eps, vj_metric metric, vj_precision prec, int32_t *qx,
+                                float *dist, int64_t cap, hipStream_t s);
 
 }  // namespace vj

@@ -6,6 +6,8 @@
 // result equals the exact decision dist < eps computed in fp64.
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "mfma_tile.h"
@@ -147,7 +149,8 @@ k_range_tiles(const uint16_t *Qh, const uint16_t *Ql, int64_t nq, const uint16_t
 // fp64 decision for every candidate: 8 lanes per candidate
 __global__ void k_recheck(const float *Q, const float *X, int d, int metric, double eps,
                           const int32_t *cq, const int32_t *cx, int64_t n, int32_t *oq,
-                          int32_t *ox, float *od, unsigned long long *count) {
+                          int32_t *ox, int ostride, float *od, int64_t ocap,
+                          unsigned long long *count) {
     const int lane = threadIdx.x & 63;
     const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
     const int p = lane & 7;
@@ -172,10 +175,16 @@ __global__ void k_recheck(const float *Q, const float *X, int d, int metric, dou
     base = __shfl(base, 0);
     if (keep) {
         const unsigned long long at = base + __popcll(m & ((1ull << lane) - 1ull));
-        oq[at] = q;
-        ox[at] = x;
-        od[at] = (float)dist;
+        if (at < (unsigned long long)ocap) {
+            oq[at * ostride] = q;
+            ox[at * ostride] = x;
+            if (od) od[at] = (float)dist;
+        }
     }
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
 inline unsigned g1(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -183,15 +192,17 @@ inline unsigned g1(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 }  // namespace
 
 void prepare_rows(const float *src, int64_t rows, int d, int Kp, bool split, TileRows &t,
-                  hipStream_t s) {
+                  hipStream_t s, Arena *arena) {
+    Arena fresh;
+    Arena &A = arena ? *arena : fresh;
     t.rows = rows;
     t.Kp = Kp;
-    t.hi.alloc((size_t)std::max<int64_t>(rows, 1) * Kp * sizeof(uint16_t));
-    if (split) t.lo.alloc((size_t)std::max<int64_t>(rows, 1) * Kp * sizeof(uint16_t));
+    t.hi = A.take((size_t)std::max<int64_t>(rows, 1) * Kp * sizeof(uint16_t));
+    if (split) t.lo = A.take((size_t)std::max<int64_t>(rows, 1) * Kp * sizeof(uint16_t));
     else t.lo.release();
-    t.norm2.alloc((size_t)std::max<int64_t>(rows, 1) * sizeof(float));
-    DevBuf stats(16);
-    VJ_HIP(hipMemsetAsync(stats.p, 0, 16, s));
+    t.norm2 = A.take((size_t)std::max<int64_t>(rows, 1) * sizeof(float));
+    DevBuf stats = A.take(16);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, stats.as<unsigned long long>(), 2);
     unsigned *u = stats.as<unsigned>();
     if (rows > 0)
         hipLaunchKernelGGL(k_prep, dim3(g1(rows, 4)), dim3(256), 0, s, src, rows, d, Kp,
@@ -227,31 +238,53 @@ void tile_error_bounds(const TileRows &a, const TileRows &b, int nsplit, double 
     e_fin = 5.0 * u32;                                       // norms and the final adds
 }
 
-void bruteforce_join(const float *Q, int64_t nq, const float *X, int64_t nx, int d, float eps,
-                     vj_metric metric, vj_precision prec, hipStream_t s, Pairs &out) {
-    out.n_queries = 0;
-    out.count = 0;
-    if (nq == 0 || (metric == VJ_L2 && eps <= 0.0f)) return;
+namespace {
+
+// Where the kept pairs go: q / x with a stride (1: two arrays, 2: one
+// interleaved array), dist (may be null), room for cap pairs.
+struct PairSink {
+    int32_t *q = nullptr, *x = nullptr;
+    int stride = 1;
+    float *dist = nullptr;
+    int64_t cap = 0;
+};
+
+// The brute-force join's steps with its temporaries from `A`.  With a fixed
+// region the candidate list gets what is left of it (one attempt); with
+// fresh allocations it grows until the candidates fit.  `sink(ncand)` gives
+// the output once the candidate count is known.  Returns the pair count
+// (not capped) and the candidate count in *ncand_out.
+template <typename SinkFn>
+int64_t bruteforce_core(const float *Q, int64_t nq, const float *X, int64_t nx, int d, float eps,
+                        vj_metric metric, vj_precision prec, hipStream_t s, Arena &A,
+                        SinkFn sink, int64_t *ncand_out) {
+    *ncand_out = 0;
+    if (nq == 0 || (metric == VJ_L2 && eps <= 0.0f)) { sink(0); return 0; }
     const int Kp = ((d + 31) / 32) * 32;
     const int nsplit = prec == VJ_PREC_FP32 ? 3 : 1;
+    const dim3 grid(g1(nx, 128), g1(nq, 64));
+    VJ_CHECK(grid.y <= 65535u, VJ_ERR_UNSUPPORTED, "too many query rows for one call");
     TileRows tq, tx;
-    prepare_rows(Q, nq, d, Kp, nsplit == 3, tq, s);
-    prepare_rows(X, nx, d, Kp, nsplit == 3, tx, s);
+    prepare_rows(Q, nq, d, Kp, nsplit == 3, tq, s, &A);
+    prepare_rows(X, nx, d, Kp, nsplit == 3, tx, s, &A);
     double e_dot, e_fin;
     tile_error_bounds(tq, tx, nsplit, e_dot, e_fin);
-    DevBuf thr((size_t)nq * sizeof(float));
+    DevBuf thr = A.take((size_t)nq * sizeof(float));
     hipLaunchKernelGGL(k_thresholds, dim3(g1(nq, 256)), dim3(256), 0, s, tq.norm2.as<float>(), nq,
                        (double)eps, (int)metric, e_dot, e_fin, tx.maxnorm, thr.as<float>());
-    DevBuf ctr(16);
-    int64_t cap = std::max<int64_t>(1 << 20, nq * 64);
+    DevBuf ctr = A.take(16);
+    const bool fixed = A.base != nullptr;
+    // fixed region: two candidate arrays in what is left (less alignment)
+    const int64_t room = (int64_t)A.left();
+    int64_t cap = fixed ? (room > 2048 ? (room / 2 - 512) / (int64_t)sizeof(int32_t) : 0)
+                        : std::max<int64_t>(1 << 20, nq * 64);
+    VJ_CHECK(cap >= 1024, VJ_ERR_UNSUPPORTED, "no room for candidates in the fixed scratch region");
     DevBuf cq, cx;
     unsigned long long ncand = 0;
     for (int attempt = 0; attempt < 3; ++attempt) {
-        cq.reserve((size_t)cap * sizeof(int32_t));
-        cx.reserve((size_t)cap * sizeof(int32_t));
-        VJ_HIP(hipMemsetAsync(ctr.p, 0, 16, s));
-        const dim3 grid(g1(nx, 128), g1(nq, 64));
-        VJ_CHECK(grid.y <= 65535u, VJ_ERR_UNSUPPORTED, "too many query rows for one call");
+        cq = A.take((size_t)cap * sizeof(int32_t));
+        cx = A.take((size_t)cap * sizeof(int32_t));
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr.as<unsigned long long>(), 2);
         if (nsplit == 3)
             hipLaunchKernelGGL(k_range_tiles<3>, grid, dim3(256), 0, s, tq.hi.as<uint16_t>(),
                                tq.lo.as<uint16_t>(), nq, tx.hi.as<uint16_t>(), tx.lo.as<uint16_t>(),
@@ -268,24 +301,80 @@ void bruteforce_join(const float *Q, int64_t nq, const float *X, int64_t nx, int
         VJ_HIP(hipMemcpyAsync(&ncand, ctr.p, 8, hipMemcpyDeviceToHost, s));
         VJ_HIP(hipStreamSynchronize(s));
         if ((int64_t)ncand <= cap) break;
+        VJ_CHECK(!fixed, VJ_ERR_UNSUPPORTED,
+                 "the candidate pairs exceed the fixed scratch region (" + std::to_string(ncand) +
+                     " candidates, room for " + std::to_string(cap) + ")");
         cap = (int64_t)ncand + (int64_t)ncand / 8 + 1024;
         VJ_CHECK(attempt < 2, VJ_ERR_INTERNAL, "candidate capacity did not converge");
     }
-    out.q.alloc((size_t)std::max<unsigned long long>(ncand, 1) * sizeof(int32_t));
-    out.x.alloc((size_t)std::max<unsigned long long>(ncand, 1) * sizeof(int32_t));
-    out.dist.alloc((size_t)std::max<unsigned long long>(ncand, 1) * sizeof(float));
-    VJ_HIP(hipMemsetAsync(ctr.as<char>() + 8, 0, 8, s));
+    *ncand_out = (int64_t)ncand;
+    const PairSink o = sink((int64_t)ncand);
     if (ncand > 0)
         hipLaunchKernelGGL(k_recheck, dim3(g1((int64_t)ncand * 8, 256)), dim3(256), 0, s, Q, X, d,
                            (int)metric, (double)eps, cq.as<int32_t>(), cx.as<int32_t>(),
-                           (int64_t)ncand, out.q.as<int32_t>(), out.x.as<int32_t>(),
-                           out.dist.as<float>(), ctr.as<unsigned long long>() + 1);
+                           (int64_t)ncand, o.q, o.x, o.stride, o.dist, o.cap,
+                           ctr.as<unsigned long long>() + 1);
     VJ_HIP(hipGetLastError());
     unsigned long long kept = 0;
     VJ_HIP(hipMemcpyAsync(&kept, ctr.as<char>() + 8, 8, hipMemcpyDeviceToHost, s));
     VJ_HIP(hipStreamSynchronize(s));
-    out.count = (int64_t)kept;
-    out.n_candidates = (int64_t)ncand;
+    return (int64_t)kept;
+}
+
+}  // namespace
+
+// The fixed scratch region of the allocation-free entry point: one copy per
+// device, reached through its address on that device (looked up once per
+// device with the device current; host code never uses the symbol itself
+// as an address).  Calls that overlap on one device race on it.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+char *noalloc_scratch() {
+    static std::mutex mu;
+    static void *addr[64] = {};
+    int dev = 0;
+    VJ_HIP(hipGetDevice(&dev));
+    VJ_CHECK(dev >= 0 && dev < 64, VJ_ERR_UNSUPPORTED, "device index >= 64");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        VJ_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        VJ_CHECK(p != nullptr, VJ_ERR_HIP, "no device address for the scratch region");
+        addr[dev] = p;
+    }
+    return static_cast<char *>(addr[dev]);
+}
+
+}  // namespace
+
+void bruteforce_join(const float *Q, int64_t nq, const float *X, int64_t nx, int d, float eps,
+                     vj_metric metric, vj_precision prec, hipStream_t s, Pairs &out) {
+    out.n_queries = 0;
+    out.count = 0;
+    Arena A;  // fresh allocations
+    auto sink = [&](int64_t ncand) {
+        const size_t n = (size_t)std::max<int64_t>(ncand, 1);
+        out.q.alloc(n * sizeof(int32_t));
+        out.x.alloc(n * sizeof(int32_t));
+        out.dist.alloc(n * sizeof(float));
+        return PairSink{out.q.as<int32_t>(), out.x.as<int32_t>(), 1, out.dist.as<float>(), ncand};
+    };
+    int64_t ncand = 0;
+    out.count = bruteforce_core(Q, nq, X, nx, d, eps, metric, prec, s, A, sink, &ncand);
+    out.n_candidates = ncand;
+}
+
+int64_t bruteforce_join_noalloc(const float *Q, int64_t nq, const float *X, int64_t nx, int d,
+                                float eps, vj_metric metric, vj_precision prec, int32_t *qx,
+                                float *dist, int64_t cap, hipStream_t s) {
+    Arena A;
+    A.base = noalloc_scratch();
+    A.cap = kNoAllocScratchBytes;
+    auto sink = [&](int64_t) { return PairSink{qx, qx + 1, 2, dist, cap}; };
+    int64_t ncand = 0;
+    return bruteforce_core(Q, nq, X, nx, d, eps, metric, prec, s, A, sink, &ncand);
 }
 
 }  // namespace vj

@@ -1185,6 +1185,23 @@ vj_status vj_bruteforce_join(const float *Q, int64_t nq, const float *X, int64_t
     API_END
 }
 
+vj_status vj_bruteforce_join_noalloc(const float *Q, int64_t nq, const float *X, int64_t nx,
+                                     int32_t d, float eps, vj_metric metric, vj_precision prec,
+                                     int32_t *qx, float *dist, int64_t cap, int64_t *count_host,
+                                     void *stream) {
+    API_BEGIN
+    VJ_CHECK(count_host != nullptr && cap >= 0 && (cap == 0 || qx != nullptr), VJ_ERR_INVALID_ARG,
+             "need count_host, cap >= 0 and qx when cap > 0");
+    check_shape(Q, nq, X, nx, d);
+    VJ_CHECK(std::isfinite(eps), VJ_ERR_INVALID_ARG, "eps must be finite");
+    VJ_CHECK(metric == VJ_L2 || metric == VJ_IP, VJ_ERR_INVALID_ARG, "unknown metric");
+    VJ_CHECK(prec == VJ_PREC_FP32 || prec == VJ_PREC_BF16, VJ_ERR_UNSUPPORTED,
+             "brute force supports FP32 (split bf16) and BF16 tiles");
+    *count_host = bruteforce_join_noalloc(Q, nq, X, nx, d, eps, metric, prec, qx, dist, cap,
+                                          (hipStream_t)stream);
+    API_END
+}
+
 int64_t vj_pairs_count(const vj_pairs *r) { return r ? r->impl.count : -1; }
 
 vj_status vj_pairs_export(const vj_pairs *r, int32_t *qx, float *dist, int sorted, void *stream) {

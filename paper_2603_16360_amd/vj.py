@@ -73,6 +73,8 @@ _SIGS = {
     "vj_join": (C.c_int, [_vp, _vp, _i64, _f32, C.c_int, C.POINTER(vj_join_params), _vp, _PP]),
     "vj_bruteforce_join": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _f32, C.c_int, C.c_int,
                                      _vp, _PP]),
+    "vj_bruteforce_join_noalloc": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _f32, C.c_int, C.c_int,
+                                             _vp, _vp, _i64, C.POINTER(_i64), _vp]),
     "vj_pairs_count": (_i64, [_vp]),
     "vj_pairs_export": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
     "vj_pairs_stats": (C.c_int, [_vp, _vp, _vp]),
@@ -295,6 +297,29 @@ def vj_bruteforce_join(Q: torch.Tensor, X: torch.Tensor, eps: float, metric: str
                                    float(eps), METRIC[metric], PRECISION[precision],
                                    _stream(), C.byref(h)))
     return Pairs(h.value, 0)
+
+
+def vj_bruteforce_join_noalloc(Q: torch.Tensor, X: torch.Tensor, eps: float, qx: torch.Tensor,
+                               dist: torch.Tensor | None = None, metric: str = "l2",
+                               precision: str = "fp32") -> int:
+    """vj_bruteforce_join into the caller's qx [cap, 2] int32 and dist [cap]
+    float32 (may be None) with no device allocation by the library; returns
+    the pair count (if above cap, only cap pairs were written)."""
+    Q = _dev(Q, torch.float32, "Q")
+    X = _dev(X, torch.float32, "X")
+    if not (qx.is_cuda and qx.dtype == torch.int32 and qx.dim() == 2 and qx.shape[1] == 2
+            and qx.is_contiguous()):
+        raise TypeError("qx must be a contiguous CUDA int32 tensor of shape [cap, 2]")
+    cap = qx.shape[0]
+    if dist is not None and not (dist.is_cuda and dist.dtype == torch.float32
+                                 and dist.is_contiguous() and dist.numel() >= cap):
+        raise TypeError("dist must be a contiguous CUDA float32 tensor of at least cap values")
+    cnt = C.c_int64()
+    _check(_lib.vj_bruteforce_join_noalloc(_ptr(Q), Q.shape[0], _ptr(X), X.shape[0], X.shape[1],
+                                           float(eps), METRIC[metric], PRECISION[precision],
+                                           _ptr(qx), _ptr(dist) if dist is not None else None,
+                                           cap, C.byref(cnt), _stream()))
+    return cnt.value
 
 
 def vj_join_batches(index: Index, starts, counts, eps_list, metric: str = "l2",
