@@ -20,7 +20,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 METRICS = {"l2": 0, "ip": 1}
-WS = {"self": 0, "soft": 1, "hard": 2}
+WS = {"self": 0, "none": 0, "soft": 1, "hard": 2}
 HYB = {"off": 0, "force": 1, "adapt": 2, "budget": 3}
 STAT_FIELDS = ("pairs", "n_dist", "n_expanded", "h_pops", "ood", "hybrid",
                "visited_data", "fragile")
@@ -54,7 +54,7 @@ class _Cfg(C.Structure):
                 ("hybrid_beam", C.c_int32), ("conv_threshold", C.c_int32),
                 ("ood_ratio", C.c_double), ("uncertain_policy", C.c_int32),
                 ("uncertain_rel", C.c_double), ("shuffle_seed", C.c_uint64),
-                ("fragile_rel", C.c_double)]
+                ("fragile_rel", C.c_double), ("merged", C.c_int32), ("greedy_beam", C.c_int32)]
 
 
 def _declare(L):
@@ -222,6 +222,19 @@ def build_merged(Q, X, R: int, Kc: int | None = None) -> Graph:
     return Graph(adj, elen, int(ent.value), int(rep))
 
 
+def build_separate(Q, X, R: int, Kc: int | None = None):
+    """Separate indexes (cfg.merged = false): the data graph G_X and the
+    query graph G_Q, each built by the same recipe as the merged graph over
+    its own set alone.  Returns (adj [nx + nq][R] with rows 0..nx-1 = G_X
+    in data ids and rows nx.. = G_Q in node ids nx + j, entry of G_X, the
+    two Graphs)."""
+    gx = build_merged(np.zeros((0, X.shape[1]), np.float32), X, R, Kc)
+    gq = build_merged(np.zeros((0, Q.shape[1]), np.float32), Q, R, Kc)
+    nx = X.shape[0]
+    adjq = np.where(gq.adj >= 0, gq.adj + nx, -1).astype(np.int32)
+    return np.ascontiguousarray(np.concatenate([gx.adj, adjq])), gx.entry, gx, gq
+
+
 def mst_parents(Q, X, adj, entry: int):
     """MST parents of the query nodes (node id, or -1 for the root s), BFS
     order of query indices, and the total tree weight."""
@@ -253,18 +266,26 @@ def join(Q, X, adj, entry: int, eps: float, metric: str = "l2", query_ids=None,
          work_sharing: str = "self", hybrid: str = "off", hybrid_beam: int = 256,
          conv_threshold: int = 10, ood_ratio: float = 1.5, parent=None,
          budget=None, uncertain: str = "plain", uncertain_rel: float = 1e-5,
-         shuffle_seed: int = 0, fragile_rel: float | None = None) -> JoinResult:
+         shuffle_seed: int = 0, fragile_rel: float | None = None, merged: bool = True,
+         greedy_beam: int = 256) -> JoinResult:
+    """The join of Algorithm 1 on a merged graph (merged=True: adj is [N][R]
+    over X then Q) or on separate indexes (merged=False: adj rows 0..nx-1
+    are the data graph G_X with entry `entry`, rows nx.. the query graph
+    G_Q in node ids, used only by the MST; work_sharing "none" is INLJ)."""
     V = np.ascontiguousarray(np.concatenate([_f32(X), _f32(Q)], axis=0))
     nq, nx, d = Q.shape[0], X.shape[0], Q.shape[1]
     adj = np.ascontiguousarray(adj, np.int32)
     R = adj.shape[1]
     qids = np.arange(nq, dtype=np.int32) if query_ids is None else np.ascontiguousarray(query_ids, np.int32)
     n = qids.shape[0]
+    if not merged and work_sharing == "self":
+        raise ValueError("self mode needs the merged index (use 'none' for INLJ)")
     cfg = _Cfg(WS[work_sharing], HYB[hybrid], hybrid_beam, conv_threshold, ood_ratio,
                {"plain": 0, "out": 1, "in": 2}[uncertain], uncertain_rel, shuffle_seed,
-               4.0 * d * 2.0 ** -24 if fragile_rel is None else fragile_rel)
+               4.0 * d * 2.0 ** -24 if fragile_rel is None else fragile_rel, int(merged),
+               greedy_beam)
     par = None
-    if work_sharing != "self":
+    if work_sharing not in ("self", "none"):
         if parent is None:
             raise ValueError("work sharing needs MST parents")
         par = np.ascontiguousarray(parent, np.int32)

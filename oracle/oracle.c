@@ -507,8 +507,10 @@ double or_mst_parents(const float *V, int64_t nx, int64_t nq, int d,
 }
 
 /* ------------------------------------------------------------------------
- * O3: merged-index join, Algorithm 1 with Algorithms 3-8 for cfg.merged =
- * true.  Readings (documented with the design):
+ * O3: the join of Algorithm 1 with Algorithms 3-8, for cfg.merged = true (one
+ * graph over X and Q) and for cfg.merged = false (separate indexes: adj rows
+ * 0..nx-1 are the data graph G_X with entry s, rows nx.. the query graph,
+ * read only by the MST).  Readings (documented with the design):
  *   - seeds are {s, q} plus the parent's cache in soft/hard mode (q is always
  *     a seed on the merged index, so the probe of N(q) always runs);
  *   - the greedy phase on the merged index pops q (distance 0, first) and
@@ -526,6 +528,20 @@ double or_mst_parents(const float *V, int64_t nx, int64_t nq, int d,
  *     d2 = mean dist(y, z), z in N(y) cap X, z != q; N(q) cap X empty =>
  *     OOD; no (y, z) pair => not OOD.  Distances in L2 units; for the inner
  *     product metric d1 uses sqrt(2 (1 - <q, y>)).
+ * Separate indexes (cfg.merged = 0):
+ *   - seeds are {s} plus the parent's cache (q is not a node of G_X);
+ *   - the greedy phase is best-first search over a queue initialised with
+ *     the seeds, keyed by (dist, id): before each pop, stop if the front is
+ *     in range (rule 1) or if the front distance has not fallen below the
+ *     smallest front distance seen for conv_threshold consecutive checks
+ *     (rule 2; <= 0: no rule 2); pop the front, visit its unvisited
+ *     neighbours (into the queue, and into I when in range), then trim the
+ *     queue to its greedy_beam smallest entries (trimmed nodes stay
+ *     visited);
+ *   - CheckHybrid is force_hybrid (adapt needs the merged index);
+ *   - the expansion starts from I with the visited set of the greedy
+ *     phase, as in the merged case.
+ *   Stats column 4 (OOD in the merged case) counts the greedy pops.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int32_t work_sharing;     /* 0 self, 1 soft, 2 hard */
@@ -537,6 +553,8 @@ typedef struct {
     double uncertain_rel;     /* band half-width relative to eps */
     uint64_t shuffle_seed;    /* 0: FIFO worklist; else random pops */
     double fragile_rel;       /* relative gap under which an order is fragile */
+    int32_t merged;           /* cfg.merged: 1 merged index, 0 separate indexes */
+    int32_t greedy_beam;      /* cfg.greedy_beam_size (separate indexes) */
 } or_cfg;
 
 enum { ST_PAIRS, ST_NDIST, ST_NEXP, ST_HPOPS, ST_OOD, ST_HYB, ST_VDATA, ST_FRAGILE, ST_N };
@@ -565,6 +583,9 @@ int64_t or_join(const float *V, int64_t nx, int64_t nq, int d, int metric,
     int32_t *W = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
     int hcap = cfg->hybrid_beam > 0 ? cfg->hybrid_beam : 0;
     hent *H = (hent *)malloc(sizeof(hent) * (size_t)(hcap + 2));
+    /* greedy queue of the separate-index mode: <= beam + R entries after a
+     * pop, or every seed before the first */
+    hent *G = (hent *)malloc(sizeof(hent) * (size_t)(N + cfg->greedy_beam + R + 4));
     /* cache: soft -> one node id per query; hard -> a list per query */
     int32_t *soft = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nq + 1));
     int64_t *hoff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nq + 1));
@@ -641,12 +662,15 @@ int64_t or_join(const float *V, int64_t nx, int64_t nq, int d, int metric,
                 } \
             } } while (0)
 
-        /* SeedPhase (Algorithm 3): S = {s} + cache of the parent + {q} */
+        /* SeedPhase (Algorithm 3): S = {s} + cache of the parent (+ {q} on
+         * the merged index) */
         int32_t seeds[4];
         int ns = 0;
         seeds[ns++] = s;
-        stamp[q] = i; /* q is visited, at distance 0, and never in X */
-        dq[q] = 0.0;
+        if (cfg->merged) {
+            stamp[q] = i; /* q is visited, at distance 0, and never in X */
+            dq[q] = 0.0;
+        }
         if (cfg->work_sharing == 1) {
             int32_t p = parent[qi];
             if (p >= 0 && inbatch[p - nx] && soft[p - nx] >= 0) seeds[ns++] = soft[p - nx];
@@ -669,21 +693,79 @@ int64_t or_join(const float *V, int64_t nx, int64_t nq, int d, int metric,
             }
         }
 
-        /* GreedySearchPhase (Algorithms 4, 5): pop q and probe N(q), then
-         * stop by rule 3. */
+        /* GreedySearchPhase (Algorithms 4, 5).  Merged: pop q and probe
+         * N(q), then stop by rule 3.  Separate: best-first from the seeds,
+         * stop rules 1 and 2. */
         const int32_t *nqrow = adj + (int64_t)q * R;
-        for (int j = 0; j < R; ++j) {
-            int32_t v = nqrow[j];
-            if (v < 0 || stamp[v] == i) continue;
-            VISIT(v);
-            if (v < nx && IN_RANGE(dq[v])) I[ni++] = v;
+        int32_t gpops = 0;
+        if (cfg->merged) {
+            for (int j = 0; j < R; ++j) {
+                int32_t v = nqrow[j];
+                if (v < 0 || stamp[v] == i) continue;
+                VISIT(v);
+                if (v < nx && IN_RANGE(dq[v])) I[ni++] = v;
+            }
+        } else {
+            /* the queue starts as every visited seed (all data nodes) */
+            int64_t ng = 0;
+            for (int k = 0; k < ns; ++k)
+                if (seeds[k] >= 0 && stamp[seeds[k]] == i) {
+                    int dup = 0;
+                    for (int64_t t = 0; t < ng; ++t) if (G[t].id == seeds[k]) dup = 1;
+                    if (!dup) { G[ng].d = dq[seeds[k]]; G[ng].id = seeds[k]; ++ng; }
+                }
+            if (cfg->work_sharing == 2) {
+                int32_t p = parent[qi];
+                if (p >= 0 && inbatch[p - nx])
+                    for (int64_t t = 0; t < hlen[p - nx]; ++t) {
+                        int32_t u = hpool[hoff[p - nx] + t];
+                        int dup = 0;
+                        for (int64_t k = 0; k < ng; ++k) if (G[k].id == u) dup = 1;
+                        if (!dup) { G[ng].d = dq[u]; G[ng].id = u; ++ng; }
+                    }
+            }
+            double best = INFINITY;
+            int32_t stall = 0;
+            for (;;) {
+                if (ng == 0) break;
+                int64_t mn = 0;
+                for (int64_t k = 1; k < ng; ++k)
+                    if (lt_pair(G[k].d, G[k].id, G[mn].d, G[mn].id)) mn = k;
+                for (int64_t k = 0; k < ng; ++k)
+                    if (k != mn && fabs(G[k].d - G[mn].d) <= frel * fabs(G[mn].d)) fragile = 1;
+                if (fabs(G[mn].d - eps) <= band || fabs(G[mn].d - eps) <= frel * fabs(eps)) fragile = 1;
+                if (G[mn].id < nx && IN_RANGE(G[mn].d)) break;               /* rule 1 */
+                if (isfinite(best) && fabs(G[mn].d - best) <= frel * fabs(best)) fragile = 1;
+                if (G[mn].d < best) { best = G[mn].d; stall = 0; }
+                else ++stall;
+                if (cfg->conv_threshold > 0 && stall >= cfg->conv_threshold) break; /* rule 2 */
+                int32_t u = G[mn].id;
+                G[mn] = G[--ng];
+                ++gpops;
+                const int32_t *row = adj + (int64_t)u * R;
+                for (int j = 0; j < R; ++j) {
+                    int32_t v = row[j];
+                    if (v < 0 || v >= nx || stamp[v] == i) continue;
+                    VISIT(v);
+                    G[ng].d = dq[v]; G[ng].id = v; ++ng;
+                    if (IN_RANGE(dq[v])) I[ni++] = v;
+                }
+                while (ng > cfg->greedy_beam) {
+                    int64_t mx = 0;
+                    for (int64_t k = 1; k < ng; ++k)
+                        if (lt_pair(G[mx].d, G[mx].id, G[k].d, G[k].id)) mx = k;
+                    for (int64_t k = 0; k < ng; ++k)
+                        if (k != mx && fabs(G[k].d - G[mx].d) <= frel * fabs(G[mx].d)) fragile = 1;
+                    G[mx] = G[--ng];
+                }
+            }
         }
 
-        /* CheckHybrid (Algorithm 6) */
+        /* CheckHybrid (Algorithm 6): adapt only on the merged index */
         int hyb = 0;
         if (cfg->hybrid == 1) hyb = 1;
         else if (cfg->hybrid == 3) hyb = budget[i] > 0;
-        else if (cfg->hybrid == 2) {
+        else if (cfg->hybrid == 2 && cfg->merged) {
             double s1 = 0.0, s2 = 0.0;
             int64_t c1 = 0, c2 = 0;
             for (int j = 0; j < R; ++j) {
@@ -742,6 +824,7 @@ int64_t or_join(const float *V, int64_t nx, int64_t nq, int d, int metric,
             EXPAND(b);
         }
         st[ST_HPOPS] = (int32_t)hpops;
+        if (!cfg->merged) st[ST_OOD] = gpops;
 
         /* UpdateCache (Algorithm 8) */
         if (cfg->work_sharing == 1) {
@@ -780,7 +863,7 @@ int64_t or_join(const float *V, int64_t nx, int64_t nq, int d, int metric,
 #undef VISIT
 #undef EXPAND
     }
-    free(stamp); free(dq); free(I); free(W); free(H); free(soft); free(hoff);
+    free(stamp); free(dq); free(I); free(W); free(H); free(G); free(soft); free(hoff);
     free(hlen); free(hpool); free(inbatch); free(ordr);
     return npairs;
 }

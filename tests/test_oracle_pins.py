@@ -598,3 +598,77 @@ def test_build_hub_worked_example():
     cand = np.arange(1, 769, dtype=np.int32)
     kept = oracle.rng_prune(V, 0, cand, np.full(768, np.sqrt(60.0)), 32)
     assert kept.tolist() == [1 + 30 * j for j in range(26)]
+
+
+# ------------------------------------------- O3, separate indexes ---------
+
+def _line_sep(Qv, eps, entry, **kw):
+    """Data 0..9 on a line (node i at coordinate i), the data graph a chain
+    (i - 1, i + 1), queries at Qv; separate-index join of Algorithm 1."""
+    X = np.arange(10, dtype=np.float32)[:, None]
+    Q = np.asarray(Qv, np.float32)[:, None]
+    nx, nq = 10, Q.shape[0]
+    adj = np.full((nx + nq, 2), -1, np.int32)
+    for i in range(nx):
+        adj[i] = [i - 1 if i > 0 else -1, i + 1 if i < 9 else -1]
+    adj[:nx] = np.sort(np.where(adj[:nx] < 0, 99, adj[:nx]), 1)
+    adj[adj == 99] = -1
+    return oracle.join(Q, X, adj, entry, eps, merged=False, work_sharing="none", **kw)
+
+
+def test_separate_greedy_rule1_worked_example():
+    """Query at 7.2, entry 0.  eps = 0.5: best-first walks 0, 1, ..., 6 (7
+    pops) until the front is 7 (distance 0.2 < eps, rule 1); the expansion
+    from 7 finds 6 (1.2) and 8 (0.8) out of range: I = {7}.  eps = 1.3: the
+    pop of 5 visits 6 (1.2, in range) which is then the front: 6 pops; the
+    expansion adds 7 (0.2) and 8 (0.8), 9 (1.8) is out: I = {6, 7, 8}."""
+    r = _line_sep([7.2], 0.5, 0)
+    assert sorted(r.xj.tolist()) == [7] and r.stats[0, 4] == 7
+    r = _line_sep([7.2], 1.3, 0)
+    assert sorted(r.xj.tolist()) == [6, 7, 8] and r.stats[0, 4] == 6
+
+
+def _star(conv, beam):
+    """Entry 0 at the origin, 10 leaves at coordinates 2, 3, ..., 11 (ids
+    1..10), edges 0 <-> leaf; the query at -1 (distance 1 to the entry, 3..12
+    to the leaves), eps = 0.5: nothing in range."""
+    X = np.array([[0.0]] + [[2.0 + k] for k in range(10)], np.float32)
+    Q = np.array([[-1.0]], np.float32)
+    adj = np.full((12, 10), -1, np.int32)
+    adj[0, :10] = np.arange(1, 11)
+    adj[1:11, 0] = 0
+    return oracle.join(Q, X, adj, 0, 0.5, merged=False, work_sharing="none",
+                       conv_threshold=conv, greedy_beam=beam)
+
+
+def test_separate_greedy_rule2_and_trim_worked_example():
+    """Rule 2 with conv_threshold 3: check 1 (front = entry, distance 1)
+    sets the best and pops; checks 2 and 3 see leaves at 3 and 4 (no
+    decrease: stall 1, 2) and pop them; check 4 sees the leaf at 5, stall 3
+    -> stop: 3 pops, every node visited by the first pop.  Without rule 2
+    all 11 nodes are popped.  With greedy_beam 2 the first pop's queue is
+    trimmed to the two nearest leaves: 3 pops, all 11 nodes still visited."""
+    r = _star(3, 256)
+    assert r.qi.size == 0 and r.stats[0, 4] == 3 and r.stats[0, 6] == 11
+    r = _star(0, 256)
+    assert r.stats[0, 4] == 11 and r.stats[0, 6] == 11
+    r = _star(0, 2)
+    assert r.stats[0, 4] == 3 and r.stats[0, 6] == 11
+
+
+def test_separate_complete_graph_gives_exact_join():
+    # a complete data graph: the first pop visits every data node, so INLJ
+    # (and HWS / SWS) return the exact join for every query
+    Q, X = _rand(12, 4, 31), _rand(40, 4, 32)
+    nx = X.shape[0]
+    adj = np.full((nx + 12, nx - 1), -1, np.int32)
+    for i in range(nx):
+        adj[i] = [j for j in range(nx) if j != i]
+    for i in range(12):  # query graph: a chain
+        adj[nx + i, 0] = nx + (i + 1) % 12
+    eps = 1.6
+    want = _pairs(*oracle.nlj(Q, X, eps)[:2])
+    par, _, _ = oracle.mst_parents(Q, X, adj, 0)
+    for ws in ("none", "soft", "hard"):
+        r = oracle.join(Q, X, adj, 0, eps, merged=False, work_sharing=ws, parent=par)
+        assert r.pairs() == want, ws
