@@ -110,7 +110,9 @@ typedef struct {
                                stored length of their edges to data nodes -- dense
                                neighbourhoods, whose joins run longest, start first, which
                                shortens the tail of uneven query costs; 0: the given order.
-                               Results are the same either way. */
+                               Results are the same either way.  Merged indexes only. */
+    int32_t greedy_beam;    /* separate indexes: bound on the best-first greedy queue
+                               (cfg.greedy_beam_size, default 256, at most 256) */
 } vj_join_params;
 
 void vj_default_build_params(vj_build_params *p);
@@ -141,6 +143,33 @@ vj_status vj_index_from_graph(const float *Q, int64_t nq, const float *X, int64_
                               int32_t d, vj_metric metric, const int32_t *adj, int32_t R,
                               int32_t entry, const int32_t *parent, void *stream,
                               vj_index **out);
+
+/*
+ * Separate indexes (cfg.merged = false, Section 2.2 and Algorithms 1-8):
+ * the data graph G_X over X alone and the query graph G_Q over Q alone,
+ * each built by the merged build's recipe over its own set.  Joins on such
+ * an index seed each query with the entry of G_X (plus the parent's cache
+ * under SOFT / HARD work sharing; VJ_WS_SELF means no sharing, the INLJ of
+ * Section 2.2), run the best-first greedy phase of Algorithms 4-5 (queue
+ * bound greedy_beam, stop rules 1 and 2 with conv_threshold), then the same
+ * expansion as the merged index.  The query MST (SOFT / HARD order) uses the
+ * edges of G_Q plus an (entry, q) edge per query, rooted at the entry.
+ * VJ_HYB_ADAPT behaves as VJ_HYB_OFF there (Algorithm 6: the OOD test needs
+ * the merged index); VJ_HYB_LEARNED, vj_join_features and the device batch
+ * runner are refused.  Stats column 4 holds the greedy pops.  The graph is
+ * exported as for a merged index: rows 0..nx-1 = G_X (data ids), rows
+ * nx.. = G_Q (query node ids nx + j).
+ */
+vj_status vj_build_separate_index(const float *Q, int64_t nq, const float *X, int64_t nx,
+                                  int32_t d, vj_metric metric, const vj_build_params *p,
+                                  void *stream, vj_index **out);
+/* Separate indexes around graphs built elsewhere: adj [nq + nx][R] in the
+ * layout above (a data row may hold only data ids, a query row only query
+ * node ids; VJ_ERR_INVALID_ARG otherwise); entry: a data node. */
+vj_status vj_index_from_separate_graphs(const float *Q, int64_t nq, const float *X, int64_t nx,
+                                        int32_t d, vj_metric metric, const int32_t *adj,
+                                        int32_t R, int32_t entry, const int32_t *parent,
+                                        void *stream, vj_index **out);
 
 /* Copy the graph out: adj [N][R] int32, elen [N][R] float32 (either may be
  * NULL), parent [nq] int32 (may be NULL; -1 = entry).  Device pointers. */

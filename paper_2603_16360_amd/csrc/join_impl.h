@@ -609,10 +609,13 @@ __device__ __forceinline__ int lds_load(const int *p) { return __atomic_load_n(p
 // query, whose distance is needed (d1) even when it was already visited.
 // Occupancy of the cooperative kernels is bound by LDS, so a pass keeps up
 // to 16 16-byte loads per lane in flight.
+// push_all: every newly visited node also goes to the queue (hk / hi): the
+// greedy phase of separate indexes keeps in-range and out-range nodes there.
 template <typename T, int DP, int W, int PGC>
 __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, CoopShared<W> &sh,
                                            CoopWave &cw, const float *qf, int32_t v, bool probe,
-                                           bool hyb_active, int heap_cap, int lane) {
+                                           bool hyb_active, int heap_cap, int lane,
+                                           bool push_all = false) {
     constexpr int CE = Elem<T>::CE;
     constexpr int CPR = DP / CE;
     constexpr int LPR = pick_lpr(CPR);
@@ -766,8 +769,8 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
                     m.ild[o] = key;
                 }
             }
-            if (hyb_active) {
-                const bool hp = lead && nw && !inr;
+            if (hyb_active || push_all) {
+                const bool hp = lead && nw && (push_all || !inr);
                 const uint64_t mh = __ballot(hp);
                 const int nh = __popcll(mh);
                 if (nh) {
@@ -885,7 +888,76 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
     // visited set and the in-range set after this phase are the same as
     // with seeds first, then the probe.  CheckHybrid follows on wave 0; the
     // first round's barriers publish it.
-    if (wib == 0) {
+    const bool separate = a.merged == 0;
+    if (separate) {
+        // ---- separate indexes: seeds {s} + the soft cache + the parent's
+        // in-range list (hard, chunks of 64) on wave 0, every visited node
+        // into the queue, which keeps its gbeam + 1 smallest entries (the
+        // first pop's trim would drop the rest); then best-first greedy
+        // with stop rules 1 and 2 (Algorithms 4-5), the queue trimmed to
+        // gbeam after each pop.  The expansion starts from I alone, with the
+        // greedy phase's visited set.
+        if (wib == 0) {
+            const int32_t sv = lane == 0 ? a.entry : lane == 1 ? pcache : -1;
+            coop_batch<T, DP, W, PGC>(a, m, sh, cw, qf, sv, false, false, heap_cap, lane, true);
+            for (int t = 0; t < pcnt && t < a.nx + 64; t += 64) {
+                const int32_t u = t + lane < pcnt ? a.out_x[pseg + t + lane] : -1;
+                coop_batch<T, DP, W, PGC>(a, m, sh, cw, qf, u, false, false, heap_cap, lane, true);
+                int hc = uni(lds_load(&sh.hc));
+                if (hc > a.gbeam + 1) {
+                    heap_trim(m, hc, a.gbeam + 1, lane);
+                    if (lane == 0) sh.hc = hc;
+                    wave_sync();
+                }
+            }
+            const bool l2g = a.metric == VJ_L2;
+            float best = INFINITY;
+            int stall = 0, gpops = 0;
+            for (int it = 0; it < m.hash_n + 4; ++it) {
+                if (uni(lds_load(&sh.abort))) break;
+                const int hc = uni(lds_load(&sh.hc));
+                if (hc == 0) break;
+                float bk = INFINITY;
+                int bid = 0x7fffffff, bx = 0;
+                for (int i = lane; i < hc; i += 64) {
+                    const float kk = m.hk[i];
+                    const int id = m.hi[i];
+                    if (kk < bk || (kk == bk && id < bid)) { bk = kk; bid = id; bx = i; }
+                }
+                wave_best(bk, bid, bx, false);
+                bid = uni(bid);
+                bx = uni(bx);
+                if (l2g ? bk < a.eps2 : bk < a.eps) break;          // rule 1
+                if (bk < best) { best = bk; stall = 0; }
+                else ++stall;
+                if (a.conv > 0 && stall >= a.conv) break;           // rule 2
+                if (lane == 0) {
+                    m.hk[bx] = m.hk[hc - 1];
+                    m.hi[bx] = m.hi[hc - 1];
+                    sh.hc = hc - 1;
+                }
+                wave_sync();
+                gpops += 1;
+                if (bid < 0 || bid >= a.nx) {
+                    if (lane == 0) { atomicOr(a.err, 32); atomicOr(&sh.abort, 1); }
+                    break;
+                }
+                const int32_t v = lane < R ? a.adj[(size_t)bid * R + lane] : -1;
+                coop_batch<T, DP, W, PGC>(a, m, sh, cw, qf, v, false, false, heap_cap, lane, true);
+                int hc2 = uni(lds_load(&sh.hc));
+                if (hc2 > a.gbeam) {
+                    heap_trim(m, hc2, a.gbeam, lane);
+                    if (lane == 0) sh.hc = hc2;
+                    wave_sync();
+                }
+            }
+            if (lane == 0) {
+                sh.hc = 0;
+                sh.ood = gpops;  // stats column 4 of separate indexes: greedy pops
+                sh.hyb = a.hyb == VJ_HYB_FORCE || (a.hyb == VJ_HYB_BUDGET && a.budget[pos] > 0);
+            }
+        }
+    } else if (wib == 0) {
         const int32_t nbq = lane < R ? a.adj[(size_t)q * R + lane] : -1;
         int32_t v = nbq;
         if (R <= 62) {
@@ -929,7 +1001,7 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
         }
         if (lane == 0) sh.hyb = hyb ? 1 : 0;
     }
-    for (int t = wib * 64; t < pcnt && t < a.nx + 64; t += 64 * W) {
+    for (int t = wib * 64; !separate && t < pcnt && t < a.nx + 64; t += 64 * W) {
         const int32_t u = t + lane < pcnt ? a.out_x[pseg + t + lane] : -1;
         coop_batch<T, DP, W, PGC>(a, m, sh, cw, qf, u, false, false, heap_cap, lane);
     }

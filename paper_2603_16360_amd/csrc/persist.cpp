@@ -25,7 +25,7 @@ constexpr size_t kChunk = (size_t)32 << 20;
 
 struct IndexHeader {
     int64_t nq, nx, repairs;
-    int32_t d, dp, R, entry, metric, has_mst;
+    int32_t d, dp, R, entry, metric, has_mst, separate, pad;
 };
 
 struct PredHeader {
@@ -105,7 +105,7 @@ void index_save(const Index &ix, const char *path) {
     Writer w(path);
     w.host(kIndexMagic, 8);
     IndexHeader h{ix.nq, ix.nx, ix.repairs, ix.d, ix.dp, ix.R, ix.entry, (int32_t)ix.metric,
-                  ix.has_mst ? 1 : 0};
+                  ix.has_mst ? 1 : 0, ix.separate ? 1 : 0, 0};
     w.host(&h, sizeof(h));
     w.device(ix.vec.p, (size_t)ix.N * ix.dp * sizeof(float));
     w.device(ix.adj.p, (size_t)ix.N * ix.R * sizeof(int32_t));
@@ -126,10 +126,12 @@ void index_load(Index &ix, const char *path, void (*finish)(Index &, hipStream_t
     r.host(&h, sizeof(h));
     VJ_CHECK(h.nq >= 0 && h.nx >= 1 && h.nq + h.nx < ((int64_t)1 << 30) && h.d >= 1 &&
                  h.d <= 1024 && h.dp == padded_dim(h.d) && h.R >= 1 && h.R <= 64 &&
-                 h.entry >= 0 && h.entry < h.nq + h.nx && (h.metric == VJ_L2 || h.metric == VJ_IP),
+                 h.entry >= 0 && h.entry < h.nq + h.nx && (h.metric == VJ_L2 || h.metric == VJ_IP) &&
+                 (h.separate == 0 || h.separate == 1),
              VJ_ERR_IO, "index file header is out of range");
     ix.nq = h.nq; ix.nx = h.nx; ix.N = h.nq + h.nx; ix.d = h.d; ix.dp = h.dp; ix.R = h.R;
     ix.entry = h.entry; ix.metric = (vj_metric)h.metric; ix.repairs = h.repairs;
+    ix.separate = h.separate != 0;
     VJ_HIP(hipGetDevice(&ix.device));
     ix.vec.alloc((size_t)ix.N * ix.dp * sizeof(float));
     ix.adj.alloc((size_t)ix.N * ix.R * sizeof(int32_t));

@@ -97,6 +97,11 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+__global__ void k_offset_ids(int32_t *p, int64_t n, int32_t off) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && p[i] >= 0) p[i] += off;
+}
+
 __global__ void k_iota(int32_t *p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = (int32_t)i;
@@ -367,6 +372,12 @@ void launch_dist_to_node(const float *vec, int dp, int64_t first, int64_t n, int
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     if (n == 0) return;
     hipLaunchKernelGGL(k_fill_i32, dim3(grid1(n)), dim3(256), 0, s, p, n, v);
+}
+
+void offset_ids(int32_t *p, int64_t n, int32_t off, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_offset_ids, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, off);
+    VJ_HIP(hipGetLastError());
 }
 
 void iota_i32(int32_t *p, int64_t n, hipStream_t s) {

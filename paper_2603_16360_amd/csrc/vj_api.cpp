@@ -278,6 +278,8 @@ static JoinArgs make_args(const Index &ix, int prec, const vj_join_params &p, in
     a.eps2 = (float)((double)eps * (double)eps);
     a.ws = p.work_sharing;
     a.hyb = p.hybrid;
+    a.merged = ix.separate ? 0 : 1;
+    a.gbeam = p.greedy_beam;
     a.beam = beam;
     a.conv = p.conv_threshold;
     a.ood_ratio = p.ood_ratio;
@@ -309,13 +311,18 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
     const int ws = p.work_sharing, hyb = p.hybrid;
     const int prec = join_precision(ix, p.precision, s);
     // bf16 rows run on the workgroup tiers (they carry the margin re-check)
-    const int start_tier = prec == VJ_PREC_BF16 ? std::max(1, (int)p.start_tier) : (int)p.start_tier;
+    // bf16 rows and separate indexes run on the workgroup tiers (they carry
+    // the margin re-check, resp. the greedy phase)
+    const int start_tier = prec == VJ_PREC_BF16 || ix.separate ? std::max(1, (int)p.start_tier)
+                                                               : (int)p.start_tier;
     const int beam = (hyb != VJ_HYB_OFF) ? p.hybrid_beam : 0;
     VJ_CHECK(beam <= 256, VJ_ERR_UNSUPPORTED, "hybrid_beam must be <= 256");
 
     JoinWorkspace &jw = ix.jw;
     Order ord{jw.qlist, jw.qpos, {}};
-    make_order(ix, ids, n, ws, p.dense_first != 0, s, ord);
+    // densest first reads the stored lengths of a query's edges to data
+    // nodes: the merged graph's (a separate query graph has none)
+    make_order(ix, ids, n, ws, p.dense_first != 0 && !ix.separate, s, ord);
     const int32_t *qlist = ord.qlist.as<int32_t>(), *qpos = ord.qpos.as<int32_t>();
 
     // counters: [0..1] out_count (u64), [2] ovf_count, [3] err, [4] global regions taken,
@@ -378,7 +385,9 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
             L.prec = prec;
             L.tier = std::min(tier, 2);
             L.coop_small = p.coop_tables == 1;
-            L.hyb = beam > 0;
+            // the greedy phase of separate indexes keeps its queue in the
+            // out-range queue's arrays
+            L.hyb = beam > 0 || ix.separate;
             L.ovf = ovf.as<int32_t>();
             L.ovf_count = ctr + 2;
             int64_t chunk = cnt;
@@ -1009,38 +1018,138 @@ void vj_default_join_params(vj_join_params *p) {
     p->coop_tables = 0;
     p->dense_first = 1;
     p->pair_capacity = 0;
+    p->greedy_beam = 256;
 }
 
 const char *vj_last_error(void) { return vj::last_error(); }
+
+}  // extern "C"
+
+namespace vj {
+// An index around a graph built elsewhere.  separate: adj rows 0..nx-1 are a
+// data graph over data ids only, rows nx.. a query graph over query node ids
+// only, and the entry is a data node.
+static void index_from_graph(const float *Q, int64_t nq, const float *X, int64_t nx, int32_t d,
+                             vj_metric metric, const int32_t *adj, int32_t R, int32_t entry,
+                             const int32_t *parent, bool separate, hipStream_t s, Index &ix) {
+    VJ_CHECK(adj != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    check_shape(Q, nq, X, nx, d);
+    check_index_size(nq, nx);
+    VJ_CHECK(metric == VJ_L2 || metric == VJ_IP, VJ_ERR_INVALID_ARG, "unknown metric");
+    VJ_CHECK(R >= 1 && R <= 64, VJ_ERR_UNSUPPORTED, "R must be in [1, 64]");
+    VJ_CHECK(entry >= 0 && entry < (separate ? nx : nq + nx), VJ_ERR_INVALID_ARG,
+             separate ? "the entry of separate indexes is a data node" : "entry out of range");
+    ix.nq = nq; ix.nx = nx; ix.N = nq + nx; ix.d = d; ix.dp = padded_dim(d); ix.R = R;
+    ix.entry = entry; ix.metric = metric; ix.separate = separate;
+    VJ_HIP(hipGetDevice(&ix.device));
+    init_vectors(ix, Q, X, s);
+    ix.adj.alloc((size_t)ix.N * R * sizeof(int32_t));
+    VJ_HIP(hipMemcpyAsync(ix.adj.p, adj, ix.adj.bytes, hipMemcpyDeviceToDevice, s));
+    // every id must be -1 or a node id (separate: of the row's own set)
+    std::vector<int32_t> ah((size_t)ix.N * R);
+    VJ_HIP(hipMemcpyAsync(ah.data(), adj, ah.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    for (size_t e = 0; e < ah.size(); ++e) {
+        const int32_t v = ah[e];
+        VJ_CHECK(v >= -1 && v < ix.N, VJ_ERR_INVALID_ARG, "adjacency id out of range");
+        if (separate && v >= 0) {
+            const bool data_row = (int64_t)(e / R) < nx;
+            VJ_CHECK(data_row == (v < nx), VJ_ERR_INVALID_ARG,
+                     "separate indexes: a data row may only hold data ids and a query row "
+                     "only query node ids");
+        }
+    }
+    ix.elen.alloc((size_t)ix.N * R * sizeof(float));
+    launch_edge_lengths(ix.vec.as<float>(), ix.dp, ix.adj.as<int32_t>(), ix.N, R, ix.elen.as<float>(), s);
+    if (parent) set_parents(ix, parent, s);
+    else compute_mst(ix, s);
+    VJ_HIP(hipStreamSynchronize(s));
+}
+
+// The graph of rows [first, first + n) of ix's vectors, built by the merged
+// build's recipe over that set alone, into rows [first, first + n) of
+// ix.adj with node ids offset by `first`.
+static void build_part(Index &ix, int64_t first, int64_t n, int kc, hipStream_t s, int32_t *entry,
+                       int64_t *repairs) {
+    if (n < 2) {
+        fill_i32(ix.adj.as<int32_t>() + (size_t)first * ix.R, n * ix.R, -1, s);
+        *entry = (int32_t)first;
+        return;
+    }
+    Index part;
+    part.nq = 0; part.nx = n; part.N = n; part.d = ix.d; part.dp = ix.dp; part.R = ix.R;
+    part.metric = ix.metric;
+    part.vec = DevBuf::view(ix.vec.as<float>() + (size_t)first * ix.dp, (size_t)n * ix.dp * sizeof(float));
+    build_graph(part, (int)std::min<int64_t>(kc, n - 1), s);
+    int32_t *dst = ix.adj.as<int32_t>() + (size_t)first * ix.R;
+    VJ_HIP(hipMemcpyAsync(dst, part.adj.p, (size_t)n * ix.R * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (first) offset_ids(dst, n * ix.R, (int32_t)first, s);
+    VJ_HIP(hipStreamSynchronize(s));
+    *entry = (int32_t)(part.entry + first);
+    *repairs += part.repairs;
+}
+}  // namespace vj
+
+extern "C" {
 
 vj_status vj_index_from_graph(const float *Q, int64_t nq, const float *X, int64_t nx, int32_t d,
                               vj_metric metric, const int32_t *adj, int32_t R, int32_t entry,
                               const int32_t *parent, void *stream, vj_index **out) {
     API_BEGIN
-    VJ_CHECK(out != nullptr && adj != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    VJ_CHECK(out != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    auto h = std::make_unique<vj_index>();
+    index_from_graph(Q, nq, X, nx, d, metric, adj, R, entry, parent, false, (hipStream_t)stream,
+                     h->impl);
+    *out = h.release();
+    API_END
+}
+
+vj_status vj_index_from_separate_graphs(const float *Q, int64_t nq, const float *X, int64_t nx,
+                                        int32_t d, vj_metric metric, const int32_t *adj, int32_t R,
+                                        int32_t entry, const int32_t *parent, void *stream,
+                                        vj_index **out) {
+    API_BEGIN
+    VJ_CHECK(out != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    auto h = std::make_unique<vj_index>();
+    index_from_graph(Q, nq, X, nx, d, metric, adj, R, entry, parent, true, (hipStream_t)stream,
+                     h->impl);
+    *out = h.release();
+    API_END
+}
+
+vj_status vj_build_separate_index(const float *Q, int64_t nq, const float *X, int64_t nx,
+                                  int32_t d, vj_metric metric, const vj_build_params *bp,
+                                  void *stream, vj_index **out) {
+    API_BEGIN
+    VJ_CHECK(out != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
     check_shape(Q, nq, X, nx, d);
     check_index_size(nq, nx);
+    VJ_CHECK(nx >= 2, VJ_ERR_INVALID_ARG, "the data graph needs nx >= 2");
     VJ_CHECK(metric == VJ_L2 || metric == VJ_IP, VJ_ERR_INVALID_ARG, "unknown metric");
-    VJ_CHECK(R >= 1 && R <= 64, VJ_ERR_UNSUPPORTED, "R must be in [1, 64]");
-    VJ_CHECK(entry >= 0 && entry < nq + nx, VJ_ERR_INVALID_ARG, "entry out of range");
+    vj_build_params p;
+    vj_default_build_params(&p);
+    if (bp) p = *bp;
+    VJ_CHECK(p.R >= 1 && p.R <= 64, VJ_ERR_UNSUPPORTED, "R must be in [1, 64]");
+    const int kc = p.K_cand > 0 ? p.K_cand : std::min(2 * p.R, 112);
+    VJ_CHECK(kc >= 1 && kc <= 112, VJ_ERR_UNSUPPORTED, "K_cand must be in [1, 112]");
     hipStream_t s = (hipStream_t)stream;
     auto h = std::make_unique<vj_index>();
     Index &ix = h->impl;
-    ix.nq = nq; ix.nx = nx; ix.N = nq + nx; ix.d = d; ix.dp = padded_dim(d); ix.R = R;
-    ix.entry = entry; ix.metric = metric;
+    ix.nq = nq; ix.nx = nx; ix.N = nq + nx; ix.d = d; ix.dp = padded_dim(d); ix.R = p.R;
+    ix.metric = metric;
+    ix.separate = true;
     VJ_HIP(hipGetDevice(&ix.device));
     init_vectors(ix, Q, X, s);
-    ix.adj.alloc((size_t)ix.N * R * sizeof(int32_t));
-    VJ_HIP(hipMemcpyAsync(ix.adj.p, adj, ix.adj.bytes, hipMemcpyDeviceToDevice, s));
-    // every id must be -1 or a node id
-    std::vector<int32_t> ah((size_t)ix.N * R);
-    VJ_HIP(hipMemcpyAsync(ah.data(), adj, ah.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    VJ_HIP(hipStreamSynchronize(s));
-    for (int32_t v : ah) VJ_CHECK(v >= -1 && v < ix.N, VJ_ERR_INVALID_ARG, "adjacency id out of range");
-    ix.elen.alloc((size_t)ix.N * R * sizeof(float));
-    launch_edge_lengths(ix.vec.as<float>(), ix.dp, ix.adj.as<int32_t>(), ix.N, R, ix.elen.as<float>(), s);
-    if (parent) set_parents(ix, parent, s);
-    else compute_mst(ix, s);
+    ix.adj.alloc((size_t)ix.N * ix.R * sizeof(int32_t));
+    int32_t ex = 0, eq = 0;
+    build_part(ix, 0, nx, kc, s, &ex, &ix.repairs);
+    build_part(ix, nx, nq, kc, s, &eq, &ix.repairs);
+    ix.entry = ex;
+    ix.elen.alloc((size_t)ix.N * ix.R * sizeof(float));
+    launch_edge_lengths(ix.vec.as<float>(), ix.dp, ix.adj.as<int32_t>(), ix.N, ix.R,
+                        ix.elen.as<float>(), s);
+    if (p.copies & 1) ensure_bf16(ix, s);
+    if (p.build_mst) compute_mst(ix, s);
     VJ_HIP(hipStreamSynchronize(s));
     *out = h.release();
     API_END
@@ -1149,6 +1258,10 @@ vj_status vj_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
     VJ_CHECK(p.coop_tables == 0 || p.coop_tables == 1, VJ_ERR_INVALID_ARG, "coop_tables is 0 or 1");
     VJ_CHECK(p.hybrid != VJ_HYB_LEARNED || ix.pred != nullptr, VJ_ERR_INVALID_ARG,
              "learned routing needs an attached predictor");
+    VJ_CHECK(!ix.separate || p.hybrid != VJ_HYB_LEARNED, VJ_ERR_INVALID_ARG,
+             "learned routing needs the merged index (its features come from the probe of q)");
+    VJ_CHECK(p.greedy_beam >= 1 && p.greedy_beam <= 256, VJ_ERR_INVALID_ARG,
+             "greedy_beam in [1, 256]");
     hipStream_t s = (hipStream_t)stream;
     auto h = std::make_unique<vj_pairs>();
     Pairs &r = h->impl;
@@ -1310,6 +1423,8 @@ vj_status vj_join_batches_device(vj_index *idx, const int32_t *query_ids,
     if (pp) p = *pp;
     VJ_CHECK(p.hybrid_beam >= 0, VJ_ERR_INVALID_ARG, "hybrid_beam must be >= 0");
     VJ_CHECK(p.coop_tables == 0 || p.coop_tables == 1, VJ_ERR_INVALID_ARG, "coop_tables is 0 or 1");
+    VJ_CHECK(!ix.separate, VJ_ERR_INVALID_ARG,
+             "the device batch runner needs a merged index (use vj_join_batches)");
     for (int32_t b = 0; b < n_batches; ++b)
         VJ_CHECK(batch_count_host[b] < ((int64_t)1 << 31), VJ_ERR_UNSUPPORTED, "batch count must be < 2^31");
     std::vector<std::unique_ptr<vj_pairs>> res((size_t)n_batches);
@@ -1379,6 +1494,7 @@ vj_status vj_join_features(vj_index *idx, const int32_t *query_ids, int64_t n, f
              "query_ids may be NULL only with n == nq");
     VJ_CHECK(std::isfinite(eps), VJ_ERR_INVALID_ARG, "eps must be finite");
     VJ_CHECK(metric == ix.metric, VJ_ERR_METRIC_MISMATCH, "metric differs from the index metric");
+    VJ_CHECK(!ix.separate, VJ_ERR_INVALID_ARG, "features need the merged index (the probe of q)");
     hipStream_t s = (hipStream_t)stream;
     if (n == 0) {
         vj::set_error("");

@@ -137,6 +137,10 @@ struct Index {
     DevBuf parent;   // int32 [nq] MST parent node id (-1: entry)
     DevBuf depth;    // int32 [nq] depth in the MST (root children: 0)
     bool has_mst = false;
+    // separate indexes (cfg.merged = false): adj rows 0..nx-1 are the data
+    // graph G_X (entry: its entry), rows nx.. the query graph G_Q (node ids),
+    // read only by the MST
+    bool separate = false;
     int64_t repairs = 0;  // connectivity-repair edges added by the build
     // join state shared by calls on this index (calls on one index must not overlap)
     DevBuf cache;    // int32 [nq] soft work sharing: closest visited data node
@@ -183,6 +187,8 @@ struct JoinArgs {
     float bf_u;               // bf16 rows: bound on |x - bf16(x)| / |bf16(x)| (0: exact copy)
     unsigned long long *nrecheck;  // bf16 rows: candidates re-decided from fp32 rows
     int32_t ws, hyb, beam, conv;
+    int32_t merged;           // 1 merged index; 0 separate indexes (adj rows < nx: data graph)
+    int32_t gbeam;            // separate indexes: greedy queue bound (cfg.greedy_beam_size)
     float ood_ratio;
     int32_t gen;              // stamp of this call in inb[]
     const int32_t *parent;    // [nq] MST parent node id (-1: entry)

@@ -25,7 +25,7 @@ VJ_OK = 0
 STATUS = {0: "VJ_OK", 1: "VJ_ERR_INVALID_ARG", 2: "VJ_ERR_METRIC_MISMATCH", 3: "VJ_ERR_OOM",
           4: "VJ_ERR_HIP", 5: "VJ_ERR_INTERNAL", 6: "VJ_ERR_UNSUPPORTED", 7: "VJ_ERR_IO"}
 METRIC = {"l2": 0, "ip": 1}
-WORK_SHARING = {"self": 0, "soft": 1, "hard": 2}
+WORK_SHARING = {"self": 0, "none": 0, "soft": 1, "hard": 2}  # "none": no sharing (INLJ)
 HYBRID = {"off": 0, "force": 1, "adapt": 2, "budget": 3, "learned": 4}
 PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2, "u8": 3, "auto": 4}
 STAT_FIELDS = ("pairs", "n_dist", "n_expanded", "h_pops", "ood", "hybrid",
@@ -49,7 +49,7 @@ class vj_join_params(C.Structure):
                 ("ood_ratio", C.c_float), ("precision", C.c_int32),
                 ("budget", C.c_void_p), ("start_tier", C.c_int32),
                 ("coop_tables", C.c_int32), ("pair_capacity", C.c_int64),
-                ("dense_first", C.c_int32)]
+                ("dense_first", C.c_int32), ("greedy_beam", C.c_int32)]
 
 
 _vp, _i64, _i32, _f32 = C.c_void_p, C.c_int64, C.c_int32, C.c_float
@@ -62,6 +62,10 @@ _SIGS = {
                                         C.POINTER(vj_build_params), _vp, _PP]),
     "vj_index_from_graph": (C.c_int, [_vp, _i64, _vp, _i64, _i32, C.c_int, _vp, _i32, _i32,
                                       _vp, _vp, _PP]),
+    "vj_build_separate_index": (C.c_int, [_vp, _i64, _vp, _i64, _i32, C.c_int,
+                                          C.POINTER(vj_build_params), _vp, _PP]),
+    "vj_index_from_separate_graphs": (C.c_int, [_vp, _i64, _vp, _i64, _i32, C.c_int, _vp, _i32,
+                                                _i32, _vp, _vp, _PP]),
     "vj_index_export_graph": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vj_index_info": (C.c_int, [_vp] + [_vp] * 6),
     "vj_index_free": (None, [_vp]),
@@ -228,7 +232,7 @@ def vj_index_load(path: str) -> Index:
 
 def join_params(work_sharing="self", hybrid="off", hybrid_beam=256, conv_threshold=10,
                 ood_ratio=1.5, precision="fp32", budget=None, start_tier=1, coop_tables=0,
-                pair_capacity=0, dense_first=1):
+                pair_capacity=0, dense_first=1, greedy_beam=256):
     p = vj_join_params()
     _lib.vj_default_join_params(C.byref(p))
     p.work_sharing = WORK_SHARING[work_sharing]
@@ -242,6 +246,7 @@ def join_params(work_sharing="self", hybrid="off", hybrid_beam=256, conv_thresho
     p.coop_tables = coop_tables
     p.pair_capacity = pair_capacity
     p.dense_first = dense_first
+    p.greedy_beam = greedy_beam
     return p
 
 
@@ -255,6 +260,36 @@ def vj_build_merged_index(Q: torch.Tensor, X: torch.Tensor, metric: str = "l2", 
     h = C.c_void_p()
     _check(_lib.vj_build_merged_index(_ptr(Q), Q.shape[0], _ptr(X), X.shape[0], X.shape[1],
                                       METRIC[metric], C.byref(bp), _stream(), C.byref(h)))
+    return Index(h.value)
+
+
+def vj_build_separate_index(Q: torch.Tensor, X: torch.Tensor, metric: str = "l2", R: int = 32,
+                            K_cand: int = 0, build_mst: bool = True, copies: int = 0) -> Index:
+    """Separate indexes G_X and G_Q (cfg.merged = false)."""
+    Q = _dev(Q, torch.float32, "Q")
+    X = _dev(X, torch.float32, "X")
+    bp = vj_build_params()
+    _lib.vj_default_build_params(C.byref(bp))
+    bp.R, bp.K_cand, bp.build_mst, bp.copies = R, K_cand, int(build_mst), copies
+    h = C.c_void_p()
+    _check(_lib.vj_build_separate_index(_ptr(Q), Q.shape[0], _ptr(X), X.shape[0], X.shape[1],
+                                        METRIC[metric], C.byref(bp), _stream(), C.byref(h)))
+    return Index(h.value)
+
+
+def vj_index_from_separate_graphs(Q: torch.Tensor, X: torch.Tensor, adj: torch.Tensor,
+                                  entry: int, metric: str = "l2",
+                                  parent: torch.Tensor | None = None) -> Index:
+    Q = _dev(Q, torch.float32, "Q")
+    X = _dev(X, torch.float32, "X")
+    adj = _dev(adj, torch.int32, "adj")
+    if parent is not None:
+        parent = _dev(parent, torch.int32, "parent")
+    h = C.c_void_p()
+    _check(_lib.vj_index_from_separate_graphs(_ptr(Q), Q.shape[0], _ptr(X), X.shape[0], X.shape[1],
+                                              METRIC[metric], _ptr(adj), adj.shape[1], entry,
+                                              _ptr(parent) if parent is not None else C.c_void_p(0),
+                                              _stream(), C.byref(h)))
     return Index(h.value)
 
 
