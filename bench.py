@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--ood", action="store_true",
                     help="instead of the headline: the OOD inner-product workload at 1/10 scale; "
                          "MI-BFS, MI+Adapt, forced hybrid and learned routing compared")
+    ap.add_argument("--modes", action="store_true",
+                    help="instead of the headline: MI, MI+SWS, MI+HWS on the merged index against "
+                         "INLJ, SWS, HWS on separate indexes, on the headline workload")
     ap.add_argument("--stream", action="store_true",
                     help="instead of the headline: the batched stream workload at 1/10 scale "
                          "(200 batches, p50/p99 batch latency)")
@@ -93,6 +96,8 @@ def main():
 
     if args.stream:
         return stream_main(args, torch, workloads, vj)
+    if args.modes:
+        return modes_main(args, torch, workloads, vj)
     if args.ood:
         return ood_main(args, torch, workloads, vj)
 
@@ -241,6 +246,71 @@ def main():
         "ground_truth_s": gt_s,
         "ground_truth_pairs": n_gt,
     }
+    print(json.dumps(line), flush=True)
+
+
+def modes_main(args, torch, workloads, vj):
+    """The paper's execution modes on the headline workload (Sections 2.2 and
+    4.1-4.3): INLJ, HWS and SWS on separate indexes (G_X over X, G_Q over Q;
+    best-first greedy from the entry of G_X) against MI, MI+SWS and MI+HWS on
+    the merged index, at the same eps.  Soft / hard modes run one launch per
+    MST depth level (parents before children), so their launch count is the
+    MST depth."""
+    w = workloads.config_mid()
+    eps = float(json.load(open(os.path.join(ROOT, "tests", "golden", "eps.json")))["mid"]["eps"])
+    nq, nx = w.Q.shape[0], w.X.shape[0]
+    dev = torch.device("cuda:0")
+    Q = torch.from_numpy(w.Q).to(dev)
+    X = torch.from_numpy(w.X).to(dev)
+    t = time.time()
+    merged = vj.vj_build_merged_index(Q, X, R=w.R)
+    torch.cuda.synchronize()
+    bm = time.time() - t
+    t = time.time()
+    sep = vj.vj_build_separate_index(Q, X, R=w.R)
+    torch.cuda.synchronize()
+    bs = time.time() - t
+    log(f"merged index {bm:.2f}s, separate indexes {bs:.2f}s")
+    gt_qx, _ = vj.vj_bruteforce_join(Q, X, eps, precision="bf16").export(sorted=True)
+    gt_keys = gt_qx[:, 0].to(torch.int64) * nx + gt_qx[:, 1].to(torch.int64)
+    n_gt = int(gt_keys.numel())
+    modes = {
+        "MI": (merged, {}), "MI+SWS": (merged, {"work_sharing": "soft"}),
+        "MI+HWS": (merged, {"work_sharing": "hard"}),
+        "INLJ": (sep, {"work_sharing": "none"}), "SWS": (sep, {"work_sharing": "soft"}),
+        "HWS": (sep, {"work_sharing": "hard"}),
+    }
+    out = {}
+    for name, (idx, kw) in modes.items():
+        for _ in range(args.warmup):
+            vj.vj_join(idx, eps, **kw)
+        torch.cuda.synchronize()
+        walls = []
+        res = None
+        for _ in range(args.steps):
+            res = None
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            res = vj.vj_join(idx, eps, **kw)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - ts)
+        qx, _ = res.export(sorted=True)
+        keys = qx[:, 0].to(torch.int64) * nx + qx[:, 1].to(torch.int64)
+        st = res.stats().cpu().numpy()
+        tiers = res.tiers()
+        out[name] = {"qps": nq / float(np.mean(walls)), "ms": 1000 * float(np.mean(walls)),
+                     "recall": keys.numel() / max(1, n_gt),
+                     "precision_is_one": bool(torch.isin(keys, gt_keys).all().item()),
+                     "launches": int(sum(tt["launches"] for tt in tiers)),
+                     "mean_dist_evals": float(st[:, 1].mean()),
+                     "mean_greedy_pops": float(st[:, 4].mean()) if idx is sep else 0.0}
+        log(f"{name}: {out[name]}")
+    line = {"metric": "join queries/sec by execution mode (1Mx128, 100k queries, same eps)",
+            "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "data": "synthetic",
+            "config": {"workload": "X=1,000,000 Q=100,000 d=128 integer-valued 256-cluster "
+                                   "mixture, L2, eps for mean 50 matches, R=32", "eps": eps},
+            "build_s": {"merged": bm, "separate": bs}, "ground_truth_pairs": n_gt, "modes": out}
     print(json.dumps(line), flush=True)
 
 
