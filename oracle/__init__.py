@@ -20,7 +20,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 METRICS = {"l2": 0, "ip": 1}
-WS = {"self": 0, "none": 0, "soft": 1, "hard": 2}
+WS = {"self": 0, "none": 0, "soft": 1, "hard": 2, "nnmap": 3}
 HYB = {"off": 0, "force": 1, "adapt": 2, "budget": 3}
 STAT_FIELDS = ("pairs", "n_dist", "n_expanded", "h_pops", "ood", "hybrid",
                "visited_data", "fragile")
@@ -82,7 +82,11 @@ def _declare(L):
     L.or_join.restype = _i64
     L.or_join.argtypes = [_f32p, _i64, _i64, _int, _int, _i32p, _int, C.c_int32,
                           C.c_void_p, _i32p, _i64, _dbl, C.POINTER(_Cfg), C.c_void_p,
+                          C.c_void_p, C.c_void_p, C.c_void_p,
                           _i64, _i32p, _i32p, _f64p, _i32p]
+    L.or_nnmap.restype = None
+    L.or_nnmap.argtypes = [_f32p, _i64, _i64, _int, _int, _i32p, _int, _dbl, _i32p, _f64p,
+                           np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")]
     L.or_join_self_counts.restype = None
     L.or_join_self_counts.argtypes = [_f32p, _i64, _i64, _int, _int, _i32p, _int,
                                       C.c_int32, _i32p, _i64, _dbl, _i64p]
@@ -267,7 +271,7 @@ def join(Q, X, adj, entry: int, eps: float, metric: str = "l2", query_ids=None,
          conv_threshold: int = 10, ood_ratio: float = 1.5, parent=None,
          budget=None, uncertain: str = "plain", uncertain_rel: float = 1e-5,
          shuffle_seed: int = 0, fragile_rel: float | None = None, merged: bool = True,
-         greedy_beam: int = 256) -> JoinResult:
+         greedy_beam: int = 256, nnmap=None) -> JoinResult:
     """The join of Algorithm 1 on a merged graph (merged=True: adj is [N][R]
     over X then Q) or on separate indexes (merged=False: adj rows 0..nx-1
     are the data graph G_X with entry `entry`, rows nx.. the query graph
@@ -285,7 +289,14 @@ def join(Q, X, adj, entry: int, eps: float, metric: str = "l2", query_ids=None,
                4.0 * d * 2.0 ** -24 if fragile_rel is None else fragile_rel, int(merged),
                greedy_beam)
     par = None
-    if work_sharing not in ("self", "none"):
+    nnw = nnd = nno = None
+    if work_sharing == "nnmap":
+        if merged or nnmap is None:
+            raise ValueError("NN-Map joins run on separate indexes with the map from nnmap()")
+        nnw = np.ascontiguousarray(nnmap.w, np.int32)
+        nnd = np.ascontiguousarray(nnmap.dist, np.float64)
+        nno = np.ascontiguousarray(nnmap.ood, np.uint8)
+    elif work_sharing not in ("self", "none"):
         if parent is None:
             raise ValueError("work sharing needs MST parents")
         par = np.ascontiguousarray(parent, np.int32)
@@ -297,12 +308,36 @@ def join(Q, X, adj, entry: int, eps: float, metric: str = "l2", query_ids=None,
     L = lib()
     args = (V, nx, nq, d, METRICS[metric], adj, R, entry,
             par.ctypes.data if par is not None else None, qids, n, eps, C.byref(cfg),
-            bud.ctypes.data if bud is not None else None)
+            bud.ctypes.data if bud is not None else None,
+            nnw.ctypes.data if nnw is not None else None,
+            nnd.ctypes.data if nnd is not None else None,
+            nno.ctypes.data if nno is not None else None)
     e32, e64 = np.empty(0, np.int32), np.empty(0, np.float64)
     cnt = L.or_join(*args, 0, e32, e32, e64, stats)
     oq, ox, od = np.empty(cnt, np.int32), np.empty(cnt, np.int32), np.empty(cnt, np.float64)
     L.or_join(*args, cnt, oq, ox, od, stats)
     return JoinResult(oq, ox, od, stats)
+
+
+@dataclass
+class NNMap:
+    w: np.ndarray     # [nq] int32 nearest data node of each query
+    dist: np.ndarray  # [nq] float64 its distance (join metric)
+    ood: np.ndarray   # [nq] uint8 OOD bit
+
+
+def nnmap(Q, X, adj, metric: str = "l2", ratio: float = 1.5) -> NNMap:
+    """NN-Map of Section 6: exact nearest data node of every query (fp64,
+    ties to the smaller id), its distance and the OOD bit from the witness
+    and its data-graph edges (adj rows 0..nx-1; see or_nnmap)."""
+    V = np.ascontiguousarray(np.concatenate([_f32(X), _f32(Q)], axis=0))
+    nq, nx, d = Q.shape[0], X.shape[0], Q.shape[1]
+    adj = np.ascontiguousarray(adj, np.int32)
+    w = np.empty(nq, np.int32)
+    dist = np.empty(nq, np.float64)
+    ood = np.empty(nq, np.uint8)
+    lib().or_nnmap(V, nx, nq, d, METRICS[metric], adj, adj.shape[1], ratio, w, dist, ood)
+    return NNMap(w, dist, ood)
 
 
 def join_self_counts(Q, X, adj, entry: int, eps: float, metric: str = "l2",

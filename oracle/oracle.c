@@ -542,6 +542,11 @@ double or_mst_parents(const float *V, int64_t nx, int64_t nq, int d,
  *   - the expansion starts from I with the visited set of the greedy
  *     phase, as in the merged case.
  *   Stats column 4 (OOD in the merged case) counts the greedy pops.
+ * NN-Map (Section 6; work_sharing = 3, separate indexes, arrays nn_w, nn_d,
+ * nn_ood from or_nnmap): if nn_d[q] >= eps the result is empty without a
+ * distance evaluation (the witness certificate); otherwise the seed is the
+ * witness nn_w[q] alone, the greedy phase is skipped, and adapt mode takes
+ * the stored OOD bit as CheckHybrid's prediction.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int32_t work_sharing;     /* 0 self, 1 soft, 2 hard */
@@ -573,7 +578,8 @@ static uint64_t lcg_next(uint64_t *s)
 int64_t or_join(const float *V, int64_t nx, int64_t nq, int d, int metric,
                 const int32_t *adj, int R, int32_t s, const int32_t *parent,
                 const int32_t *qidx, int64_t n, double eps, const or_cfg *cfg,
-                const int32_t *budget, int64_t cap, int32_t *oq, int32_t *ox,
+                const int32_t *budget, const int32_t *nn_w, const double *nn_d,
+                const uint8_t *nn_ood, int64_t cap, int32_t *oq, int32_t *ox,
                 double *od, int32_t *stats)
 {
     int64_t N = nx + nq;
@@ -601,7 +607,7 @@ int64_t or_join(const float *V, int64_t nx, int64_t nq, int d, int metric,
     /* processing order: given order for self mode; parents first otherwise
      * (any parent-before-child order gives the same result) */
     for (int64_t i = 0; i < n; ++i) ordr[i] = i;
-    if (cfg->work_sharing != 0) {
+    if (cfg->work_sharing == 1 || cfg->work_sharing == 2) {
         int32_t *depth = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
         for (int64_t i = 0; i < n; ++i) {
             int32_t dd = 0, p = parent[qidx[i]];
@@ -666,7 +672,12 @@ int64_t or_join(const float *V, int64_t nx, int64_t nq, int d, int metric,
          * the merged index) */
         int32_t seeds[4];
         int ns = 0;
-        seeds[ns++] = s;
+        const int nnmap = cfg->work_sharing == 3;
+        if (nnmap) {
+            if (nn_d[qi] < eps) seeds[ns++] = nn_w[qi];
+        } else {
+            seeds[ns++] = s;
+        }
         if (cfg->merged) {
             stamp[q] = i; /* q is visited, at distance 0, and never in X */
             dq[q] = 0.0;
@@ -705,7 +716,7 @@ int64_t or_join(const float *V, int64_t nx, int64_t nq, int d, int metric,
                 VISIT(v);
                 if (v < nx && IN_RANGE(dq[v])) I[ni++] = v;
             }
-        } else {
+        } else if (!nnmap) {
             /* the queue starts as every visited seed (all data nodes) */
             int64_t ng = 0;
             for (int k = 0; k < ns; ++k)
@@ -765,7 +776,10 @@ int64_t or_join(const float *V, int64_t nx, int64_t nq, int d, int metric,
         int hyb = 0;
         if (cfg->hybrid == 1) hyb = 1;
         else if (cfg->hybrid == 3) hyb = budget[i] > 0;
-        else if (cfg->hybrid == 2 && cfg->merged) {
+        else if (cfg->hybrid == 2 && nnmap) {
+            hyb = nn_ood[qi] != 0;
+            st[ST_OOD] = hyb;
+        } else if (cfg->hybrid == 2 && cfg->merged) {
             double s1 = 0.0, s2 = 0.0;
             int64_t c1 = 0, c2 = 0;
             for (int j = 0; j < R; ++j) {
@@ -824,7 +838,7 @@ int64_t or_join(const float *V, int64_t nx, int64_t nq, int d, int metric,
             EXPAND(b);
         }
         st[ST_HPOPS] = (int32_t)hpops;
-        if (!cfg->merged) st[ST_OOD] = gpops;
+        if (!cfg->merged && !nnmap) st[ST_OOD] = gpops;
 
         /* UpdateCache (Algorithm 8) */
         if (cfg->work_sharing == 1) {
@@ -1094,5 +1108,42 @@ void or_adam_step(int64_t n, double *p, const double *g, double *m, double *v, i
         double mhat = m[i] / c1;
         double vhat = v[i] / c2;
         p[i] -= lr * mhat / (sqrt(vhat) + eps);
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * NN-Map build (Section 6, planned in the paper): for every query q its
+ * nearest data node w[q] by the join metric (exact, fp64, ties to the
+ * smaller id), dist[q] = dist(q, w[q]), and an OOD bit.  Reading of the OOD
+ * bit (the paper says only that it is the score the merged index would
+ * derive): the d1/d2 rule of Section 4.4 with A = {w[q]}, i.e. d1 = the L2
+ * distance |q - w[q]| and d2 = the mean L2 length of w[q]'s edges to data
+ * nodes in the data graph (adj rows 0..nx-1); OOD iff d1/d2 > ratio (no edge:
+ * not OOD).
+ * ---------------------------------------------------------------------- */
+void or_nnmap(const float *V, int64_t nx, int64_t nq, int d, int metric, const int32_t *adj,
+              int R, double ratio, int32_t *w, double *dist, uint8_t *ood)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < nq; ++i) {
+        const float *qv = V + (nx + i) * (int64_t)d;
+        int32_t bi = -1;
+        double bd = INFINITY;
+        for (int64_t j = 0; j < nx; ++j) {
+            double t = dist64(qv, V + j * (int64_t)d, d, metric);
+            if (t < bd) { bd = t; bi = (int32_t)j; }   /* strict: ties keep the smaller id */
+        }
+        w[i] = bi;
+        dist[i] = bd;
+        double s2 = 0.0;
+        int64_t c2 = 0;
+        for (int k = 0; k < R; ++k) {
+            int32_t z = adj[(int64_t)bi * R + k];
+            if (z < 0 || z >= nx) continue;
+            s2 += l2_64(V + (int64_t)bi * d, V + (int64_t)z * d, d);
+            ++c2;
+        }
+        double d1 = l2_64(qv, V + (int64_t)bi * d, d);
+        ood[i] = c2 > 0 && d1 / (s2 / (double)c2) > ratio;
     }
 }

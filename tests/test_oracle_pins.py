@@ -672,3 +672,74 @@ def test_separate_complete_graph_gives_exact_join():
     for ws in ("none", "soft", "hard"):
         r = oracle.join(Q, X, adj, 0, eps, merged=False, work_sharing=ws, parent=par)
         assert r.pairs() == want, ws
+
+
+# ---------------------------------------------------------- NN-Map --------
+
+def test_nnmap_witness_matches_brute_force_and_property():
+    """Witnesses against a brute-force argmin on integer data (exact, the
+    first of equal minima = the smaller id), and the witness property of
+    Section 6 for many thresholds: dist[q] >= eps gives no match for q,
+    otherwise the witness itself is a match."""
+    r = np.random.default_rng(41)
+    Q = r.integers(0, 5, size=(60, 6)).astype(np.float32)
+    X = r.integers(0, 5, size=(300, 6)).astype(np.float32)
+    adj, entry, _, _ = oracle.build_separate(Q, X, 8)
+    m = oracle.nnmap(Q, X, adj)
+    D = cdist(Q.astype(np.float64), X.astype(np.float64))
+    assert np.array_equal(m.w, np.argmin(D, axis=1))
+    assert np.array_equal(m.dist, D.min(axis=1))
+    for eps in np.unique(np.round(D.ravel(), 6))[:40]:
+        counts = (D < eps).sum(axis=1)
+        assert np.all(counts[m.dist >= eps] == 0)
+        has = m.dist < eps
+        assert np.all(D[np.nonzero(has)[0], m.w[has]] < eps)
+
+
+def test_nnmap_ood_bit_worked_example():
+    """Data: a tight line 0, 1, 2, 3 (chain edges, length 1) on the x axis.
+    Query A at (1, 0.5): witness 1 (distance 0.5), d2 = mean edge length of
+    node 1 = 1 -> ratio 0.5, not OOD.  Query B at (2, 3): witness 2 (distance
+    3), ratio 3 > 1.5 -> OOD."""
+    X = np.array([[0, 0], [1, 0], [2, 0], [3, 0]], np.float32)
+    Q = np.array([[1, 0.5], [2, 3]], np.float32)
+    adj = np.full((6, 2), -1, np.int32)
+    adj[0, 0] = 1
+    adj[1] = [0, 2]
+    adj[2] = [1, 3]
+    adj[3, 0] = 2
+    m = oracle.nnmap(Q, X, adj)
+    assert m.w.tolist() == [1, 2]
+    np.testing.assert_allclose(m.dist, [0.5, 3.0])
+    assert m.ood.tolist() == [0, 1]
+
+
+def test_nnmap_join_worked_example():
+    """Line 0..9 with chain edges, query at 7.2.  eps = 1.3: the witness 7
+    (0.2) is in range, BFS adds 6 (1.2) and 8 (0.8), not 5 (2.2) or 9 (1.8):
+    {6, 7, 8}.  eps = 0.1 <= dist = 0.2: certified empty, nothing visited."""
+    X = np.arange(10, dtype=np.float32)[:, None]
+    Q = np.array([[7.2]], np.float32)
+    adj = np.full((11, 2), -1, np.int32)
+    for i in range(10):
+        row = [j for j in (i - 1, i + 1) if 0 <= j < 10]
+        adj[i, :len(row)] = row
+    m = oracle.nnmap(Q, X, adj)
+    assert m.w.tolist() == [7]
+    r = oracle.join(Q, X, adj, 0, 1.3, merged=False, work_sharing="nnmap", nnmap=m)
+    assert sorted(r.xj.tolist()) == [6, 7, 8]
+    r = oracle.join(Q, X, adj, 0, 0.1, merged=False, work_sharing="nnmap", nnmap=m)
+    assert r.qi.size == 0 and r.stats[0, 1] == 0 and r.stats[0, 6] == 0
+
+
+def test_nnmap_complete_graph_gives_exact_join():
+    Q, X = _rand(15, 4, 51), _rand(50, 4, 52)
+    nx = X.shape[0]
+    adj = np.full((nx + 15, nx - 1), -1, np.int32)
+    for i in range(nx):
+        adj[i] = [j for j in range(nx) if j != i]
+    m = oracle.nnmap(Q, X, adj)
+    for eps in (0.8, 1.5, 2.5):
+        want = _pairs(*oracle.nlj(Q, X, eps)[:2])
+        r = oracle.join(Q, X, adj, 0, eps, merged=False, work_sharing="nnmap", nnmap=m)
+        assert r.pairs() == want
