@@ -53,7 +53,11 @@ typedef enum { VJ_L2 = 0, VJ_IP = 1 } vj_metric;
 typedef enum {
     VJ_WS_SELF = 0, /* seeds {s, q}: the merged-index default (MI) */
     VJ_WS_SOFT = 1, /* + the parent query's closest visited data node (SWS) */
-    VJ_WS_HARD = 2  /* + every in-range node the parent found (HWS) */
+    VJ_WS_HARD = 2, /* + every in-range node the parent found (HWS) */
+    VJ_WS_NNMAP = 3 /* separate indexes with an NN-Map (Section 6, vj_build_nnmap): a query
+                       whose nearest data node lies at dist >= eps is certified empty,
+                       otherwise that node is the only seed and the greedy phase is
+                       skipped; VJ_HYB_ADAPT takes the map's OOD bit */
 } vj_work_sharing;
 
 /* Expansion mode (cfg.force_hybrid / cfg.adapt_hybrid, Algorithms 6-7). */
@@ -170,6 +174,21 @@ vj_status vj_index_from_separate_graphs(const float *Q, int64_t nq, const float 
                                         int32_t d, vj_metric metric, const int32_t *adj,
                                         int32_t R, int32_t entry, const int32_t *parent,
                                         void *stream, vj_index **out);
+
+/*
+ * NN-Map (Section 6): for every query of a separate index its nearest data
+ * node w (exact by the index metric: MFMA tile minima, then every candidate
+ * within twice the tiles' proven error bound re-decided in fp64; ties to the
+ * smaller id), that distance (fp64) and an OOD bit.  Reading of the OOD bit:
+ * the d1/d2 rule of Section 4.4 with the witness as the only neighbour, d1 =
+ * |q - w| and d2 = the mean L2 length of w's edges to data nodes in the data
+ * graph; OOD iff d1 / d2 > ood_ratio (1.5).  Joins with VJ_WS_NNMAP use it.
+ */
+vj_status vj_build_nnmap(vj_index *idx, float ood_ratio, void *stream);
+/* Copy the map out: w [nq] int32, dist [nq] float64, ood [nq] uint8 (device;
+ * any may be NULL). */
+vj_status vj_index_export_nnmap(const vj_index *idx, int32_t *w, double *dist, uint8_t *ood,
+                                void *stream);
 
 /* Copy the graph out: adj [N][R] int32, elen [N][R] float32 (either may be
  * NULL), parent [nq] int32 (may be NULL; -1 = entry).  Device pointers. */

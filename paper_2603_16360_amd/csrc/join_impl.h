@@ -351,7 +351,7 @@ __device__ __forceinline__ void run_query(const JoinArgs &a, const WaveMem &m, i
     const int32_t q = (int32_t)(a.nx + qi);
     if (a.hyb == VJ_HYB_BUDGET && a.budget[pos] < 0) {  // routed to brute force
         if (lane < 8) st[lane] = lane == 7 ? 2 : 0;
-        if (lane == 0 && a.ws != VJ_WS_SELF) a.cache[qi] = -1;
+        if (lane == 0 && a.ws == VJ_WS_SOFT) a.cache[qi] = -1;
         return;
     }
 
@@ -382,7 +382,7 @@ __device__ __forceinline__ void run_query(const JoinArgs &a, const WaveMem &m, i
     int pcache = -1;
     int64_t pseg = 0;
     int pcnt = 0;
-    if (a.ws != VJ_WS_SELF) {
+    if (a.ws == VJ_WS_SOFT || a.ws == VJ_WS_HARD) {
         const int32_t par = a.parent[qi];
         if (par >= a.nx && par < a.nx + a.nq && a.inb[par - a.nx] == (int32_t)a.gen) {
             const int pq = par - (int32_t)a.nx;
@@ -821,7 +821,7 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
     const int32_t q = (int32_t)(a.nx + qi);
     if (a.hyb == VJ_HYB_BUDGET && a.budget[pos] < 0) {
         if (threadIdx.x < 8) st[threadIdx.x] = threadIdx.x == 7 ? 2 : 0;
-        if (threadIdx.x == 0 && a.ws != VJ_WS_SELF) a.cache[qi] = -1;
+        if (threadIdx.x == 0 && a.ws == VJ_WS_SOFT) a.cache[qi] = -1;
         return false;
     }
 
@@ -869,7 +869,7 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
     int pcache = -1;
     int64_t pseg = 0;
     int pcnt = 0;
-    if (a.ws != VJ_WS_SELF) {
+    if (a.ws == VJ_WS_SOFT || a.ws == VJ_WS_HARD) {
         const int32_t par = a.parent[qi];
         if (par >= a.nx && par < a.nx + a.nq && a.inb[par - a.nx] == (int32_t)a.gen) {
             const int pq = par - (int32_t)a.nx;
@@ -897,7 +897,20 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
         // with stop rules 1 and 2 (Algorithms 4-5), the queue trimmed to
         // gbeam after each pop.  The expansion starts from I alone, with the
         // greedy phase's visited set.
-        if (wib == 0) {
+        if (wib == 0 && a.ws == VJ_WS_NNMAP) {
+            // NN-Map (Section 6): certified empty when the witness is not
+            // in range, else the witness is the only seed and the greedy
+            // phase disappears; the stored OOD bit replaces d1/d2
+            const bool in = a.nn_d[qi] < (double)a.eps;
+            const int32_t sv = lane == 0 && in ? a.nn_w[qi] : -1;
+            coop_batch<T, DP, W, PGC>(a, m, sh, cw, qf, sv, false, false, heap_cap, lane);
+            if (lane == 0) {
+                const bool ood = a.nn_ood[qi] != 0;
+                sh.ood = a.hyb == VJ_HYB_ADAPT && ood ? 1 : 0;
+                sh.hyb = a.hyb == VJ_HYB_FORCE || (a.hyb == VJ_HYB_ADAPT && ood) ||
+                         (a.hyb == VJ_HYB_BUDGET && a.budget[pos] > 0);
+            }
+        } else if (wib == 0) {
             const int32_t sv = lane == 0 ? a.entry : lane == 1 ? pcache : -1;
             coop_batch<T, DP, W, PGC>(a, m, sh, cw, qf, sv, false, false, heap_cap, lane, true);
             for (int t = 0; t < pcnt && t < a.nx + 64; t += 64) {

@@ -50,6 +50,13 @@ void tile_error_bounds(const TileRows &a, const TileRows &b, int nsplit, double 
 void bruteforce_join(const float *Q, int64_t nq, const float *X, int64_t nx, int d, float eps,
                      vj_metric metric, vj_precision prec, hipStream_t s, Pairs &out);
 
+// Exact nearest row of X for every row of Q by the metric (L2 distance, or
+// 1 - <q, x>), ties to the smaller index: tile minima on MFMA, then every
+// pair within twice the tiles' proven error bound of its row's minimum
+// re-decided in fp64.  w [nq] int32, dist [nq] float64 (device).
+void exact_top1(const float *Q, int64_t nq, const float *X, int64_t nx, int d, vj_metric metric,
+                int32_t *w, double *dist, hipStream_t s);
+
 // The same join with every temporary in the library's fixed device scratch
 // region (kNoAllocScratchBytes per device; no allocation of any kind) and
 // the pairs written to the caller's qx [cap][2] (query, data) and dist

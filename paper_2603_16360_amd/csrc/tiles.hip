@@ -187,6 +187,175 @@ __global__ void k_zero_u64(unsigned long long *p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
+// ------------------------------------------------------ exact top-1 -----
+// Order-preserving maps of floats / doubles to unsigned integers (for
+// atomicMin on keys that may be negative).
+__device__ __forceinline__ unsigned ord32(float f) {
+    const unsigned u = __float_as_uint(f);
+    return (u >> 31) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float unord32(unsigned u) {
+    return __uint_as_float((u >> 31) ? (u & 0x7fffffffu) : ~u);
+}
+__device__ __forceinline__ unsigned long long ord64(double f) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(f);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double unord64(unsigned long long u) {
+    return __longlong_as_double((long long)((u >> 63) ? (u & 0x7fffffffffffffffull) : ~u));
+}
+
+// tile value of the key: L2 the squared distance (clamped at 0), IP 1 - <q, x>
+__device__ __forceinline__ float tile_key(float q2, float x2, float dot, int metric) {
+    return metric == VJ_L2 ? fmaxf(q2 + x2 - 2.f * dot, 0.f) : 1.f - dot;
+}
+
+// pass 1: the smallest tile key of every query row
+template <int NSPLIT>
+__global__ void __launch_bounds__(256)
+k_top1_min(const uint16_t *Qh, const uint16_t *Ql, int64_t nq, const uint16_t *Xh,
+           const uint16_t *Xl, int64_t nx, int Kp, const float *nq2, const float *nx2, int metric,
+           unsigned *minkey) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q0 = (int64_t)blockIdx.y * 64;
+    const int64_t x0 = (int64_t)blockIdx.x * 128 + w * 32;
+    floatx4 acc[4][2];
+    mt::tile_64x32<NSPLIT>(Qh, Ql, q0, nq, Xh, Xl, x0, nx, Kp, lane, acc);
+    float cx2[2];
+    bool cok[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+        const int64_t x = x0 + mt::tile_brow(ct, lane);
+        cok[ct] = x < nx;
+        cx2[ct] = cok[ct] ? nx2[x] : 0.f;
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t q = q0 + mt::tile_arow(rt, i, lane);
+            const float rq2 = q < nq ? nq2[q] : 0.f;
+            unsigned k = 0xffffffffu;
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+                if (cok[ct]) k = min(k, ord32(tile_key(rq2, cx2[ct], acc[rt][ct][i], metric)));
+            // the 16 lanes of one row group hold its 32 columns
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) k = min(k, (unsigned)__shfl_xor((int)k, off));
+            if ((lane & 15) == 0 && q < nq && k != 0xffffffffu) atomicMin(&minkey[q], k);
+        }
+}
+
+// per row: the largest tile key a nearest row can have, min + 2 * bound
+__global__ void k_top1_thr(const unsigned *minkey, const float *nq2, int64_t nq, int metric,
+                           double e_dot, double e_fin, float maxnorm_x, float *thr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const double qn = sqrt((double)nq2[i]), xn = (double)maxnorm_x;
+    // IP: plus the rounding of the key's fp32 subtraction 1 - dot~
+    const double m = metric == VJ_L2
+                         ? 2.0 * e_dot * qn * xn + e_fin * (qn + xn) * (qn + xn)
+                         : e_dot * qn * xn + e_fin + 1.2e-7 * (1.0 + qn * xn * (1.0 + e_dot));
+    thr[i] = __double2float_ru((double)unord32(minkey[i]) + 2.0 * m);
+}
+
+// pass 2: every (q, x) whose tile key is within the bound of the row's min
+template <int NSPLIT>
+__global__ void __launch_bounds__(256)
+k_top1_cand(const uint16_t *Qh, const uint16_t *Ql, int64_t nq, const uint16_t *Xh,
+            const uint16_t *Xl, int64_t nx, int Kp, const float *nq2, const float *nx2,
+            const float *thr, int metric, int32_t *cq, int32_t *cx, int64_t cap,
+            unsigned long long *count) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q0 = (int64_t)blockIdx.y * 64;
+    const int64_t x0 = (int64_t)blockIdx.x * 128 + w * 32;
+    floatx4 acc[4][2];
+    mt::tile_64x32<NSPLIT>(Qh, Ql, q0, nq, Xh, Xl, x0, nx, Kp, lane, acc);
+    uint32_t hits = 0;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t q = q0 + mt::tile_arow(rt, i, lane);
+            if (q >= nq) continue;
+            const float rq2 = nq2[q], t = thr[q];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+                const int64_t x = x0 + mt::tile_brow(ct, lane);
+                if (x < nx && tile_key(rq2, nx2[x], acc[rt][ct][i], metric) <= t)
+                    hits |= 1u << (rt * 8 + ct * 4 + i);
+            }
+        }
+    if (__ballot(hits != 0) == 0) return;
+    int excl;
+    const int total = mt::wave_scan(__popc(hits), lane, excl);
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(count, (unsigned long long)total);
+    base = __shfl(base, 0);
+    int o = 0;
+    for (int b = 0; b < 32; ++b) {
+        if (!(hits & (1u << b))) continue;
+        const int rt = b >> 3, ct = (b >> 2) & 1, i = b & 3;
+        const unsigned long long at = base + excl + o++;
+        if (at < (unsigned long long)cap) {
+            cq[at] = (int32_t)(q0 + mt::tile_arow(rt, i, lane));
+            cx[at] = (int32_t)(x0 + mt::tile_brow(ct, lane));
+        }
+    }
+}
+
+// fp64 key of every candidate (8 lanes each) and the row's exact minimum
+__global__ void k_top1_recheck(const float *Q, const float *X, int d, int metric, const int32_t *cq,
+                               const int32_t *cx, int64_t n, double *key,
+                               unsigned long long *min64) {
+    const int lane = threadIdx.x & 63;
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const int p = lane & 7;
+    const bool ok = c < n;
+    const int32_t q = ok ? cq[c] : 0, x = ok ? cx[c] : 0;
+    double acc = 0.0;
+    if (ok)
+        for (int k = p; k < d; k += 8) {
+            const double a = Q[(int64_t)q * d + k], b = X[(int64_t)x * d + k];
+            if (metric == VJ_L2) { const double t = a - b; acc += t * t; }
+            else acc += a * b;
+        }
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (ok && p == 0) {
+        const double kk = metric == VJ_L2 ? acc : 1.0 - acc;
+        key[c] = kk;
+        atomicMin(&min64[q], ord64(kk));
+    }
+}
+
+// the smallest index among the candidates at the exact minimum
+__global__ void k_top1_tie(const int32_t *cq, const int32_t *cx, int64_t n, const double *key,
+                           const unsigned long long *min64, int32_t *wid) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int32_t q = cq[c];
+    if (ord64(key[c]) == min64[q]) atomicMin(&wid[q], cx[c]);
+}
+
+__global__ void k_top1_out(const unsigned long long *min64, const int32_t *wid, int64_t nq,
+                           int metric, int32_t *w, double *dist) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const double kk = unord64(min64[i]);
+    w[i] = wid[i];
+    dist[i] = metric == VJ_L2 ? sqrt(kk) : kk;
+}
+
+__global__ void k_fill_u32(unsigned *p, int64_t n, unsigned v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 inline unsigned g1(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -364,6 +533,84 @@ void bruteforce_join(const float *Q, int64_t nq, const float *X, int64_t nx, int
     int64_t ncand = 0;
     out.count = bruteforce_core(Q, nq, X, nx, d, eps, metric, prec, s, A, sink, &ncand);
     out.n_candidates = ncand;
+}
+
+void exact_top1(const float *Q, int64_t nq, const float *X, int64_t nx, int d, vj_metric metric,
+                int32_t *w, double *dist, hipStream_t s) {
+    if (nq == 0) return;
+    const int Kp = ((d + 31) / 32) * 32;
+    TileRows tq, tx;
+    prepare_rows(Q, nq, d, Kp, true, tq, s);
+    prepare_rows(X, nx, d, Kp, true, tx, s);
+    double e_dot, e_fin;
+    tile_error_bounds(tq, tx, 3, e_dot, e_fin);
+    const int nsplit = e_dot == 0.0 && e_fin == 0.0 ? 1 : 3;
+    if (nsplit == 1) tile_error_bounds(tq, tx, 1, e_dot, e_fin);
+    const dim3 grid(g1(nx, 128), g1(nq, 64));
+    VJ_CHECK(grid.y <= 65535u, VJ_ERR_UNSUPPORTED, "too many query rows for one call");
+    DevBuf minkey((size_t)nq * sizeof(unsigned)), thr((size_t)nq * sizeof(float));
+    hipLaunchKernelGGL(k_fill_u32, dim3(g1(nq, 256)), dim3(256), 0, s, minkey.as<unsigned>(), nq,
+                       0xffffffffu);
+    const uint16_t *ql = nsplit == 3 ? tq.lo.as<uint16_t>() : nullptr;
+    const uint16_t *xl = nsplit == 3 ? tx.lo.as<uint16_t>() : nullptr;
+    if (nsplit == 3)
+        hipLaunchKernelGGL(k_top1_min<3>, grid, dim3(256), 0, s, tq.hi.as<uint16_t>(), ql, nq,
+                           tx.hi.as<uint16_t>(), xl, nx, Kp, tq.norm2.as<float>(),
+                           tx.norm2.as<float>(), (int)metric, minkey.as<unsigned>());
+    else
+        hipLaunchKernelGGL(k_top1_min<1>, grid, dim3(256), 0, s, tq.hi.as<uint16_t>(), ql, nq,
+                           tx.hi.as<uint16_t>(), xl, nx, Kp, tq.norm2.as<float>(),
+                           tx.norm2.as<float>(), (int)metric, minkey.as<unsigned>());
+    hipLaunchKernelGGL(k_top1_thr, dim3(g1(nq, 256)), dim3(256), 0, s, minkey.as<unsigned>(),
+                       tq.norm2.as<float>(), nq, (int)metric, e_dot, e_fin, tx.maxnorm,
+                       thr.as<float>());
+    VJ_HIP(hipGetLastError());
+    DevBuf ctr(16);
+    int64_t cap = std::max<int64_t>(1 << 20, nq * 8);
+    DevBuf cq, cx;
+    unsigned long long ncand = 0;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        cq.alloc((size_t)cap * sizeof(int32_t));
+        cx.alloc((size_t)cap * sizeof(int32_t));
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr.as<unsigned long long>(), 2);
+        if (nsplit == 3)
+            hipLaunchKernelGGL(k_top1_cand<3>, grid, dim3(256), 0, s, tq.hi.as<uint16_t>(), ql, nq,
+                               tx.hi.as<uint16_t>(), xl, nx, Kp, tq.norm2.as<float>(),
+                               tx.norm2.as<float>(), thr.as<float>(), (int)metric,
+                               cq.as<int32_t>(), cx.as<int32_t>(), cap,
+                               ctr.as<unsigned long long>());
+        else
+            hipLaunchKernelGGL(k_top1_cand<1>, grid, dim3(256), 0, s, tq.hi.as<uint16_t>(), ql, nq,
+                               tx.hi.as<uint16_t>(), xl, nx, Kp, tq.norm2.as<float>(),
+                               tx.norm2.as<float>(), thr.as<float>(), (int)metric,
+                               cq.as<int32_t>(), cx.as<int32_t>(), cap,
+                               ctr.as<unsigned long long>());
+        VJ_HIP(hipGetLastError());
+        VJ_HIP(hipMemcpyAsync(&ncand, ctr.p, 8, hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipStreamSynchronize(s));
+        if ((int64_t)ncand <= cap) break;
+        cap = (int64_t)ncand + (int64_t)ncand / 8 + 1024;
+        VJ_CHECK(attempt < 2, VJ_ERR_INTERNAL, "candidate capacity did not converge");
+    }
+    // every row has at least its tile minimum as a candidate
+    DevBuf key((size_t)std::max<unsigned long long>(ncand, 1) * sizeof(double));
+    DevBuf min64((size_t)nq * sizeof(unsigned long long)), wid((size_t)nq * sizeof(int32_t));
+    hipLaunchKernelGGL(k_fill_u64, dim3(g1(nq, 256)), dim3(256), 0, s,
+                       min64.as<unsigned long long>(), nq, ~0ull);
+    hipLaunchKernelGGL(k_fill_u32, dim3(g1(nq, 256)), dim3(256), 0, s, wid.as<unsigned>(), nq,
+                       0x7fffffffu);
+    if (ncand > 0) {
+        hipLaunchKernelGGL(k_top1_recheck, dim3(g1((int64_t)ncand * 8, 256)), dim3(256), 0, s, Q, X,
+                           d, (int)metric, cq.as<int32_t>(), cx.as<int32_t>(), (int64_t)ncand,
+                           key.as<double>(), min64.as<unsigned long long>());
+        hipLaunchKernelGGL(k_top1_tie, dim3(g1((int64_t)ncand, 256)), dim3(256), 0, s,
+                           cq.as<int32_t>(), cx.as<int32_t>(), (int64_t)ncand, key.as<double>(),
+                           min64.as<unsigned long long>(), wid.as<int32_t>());
+    }
+    hipLaunchKernelGGL(k_top1_out, dim3(g1(nq, 256)), dim3(256), 0, s,
+                       min64.as<unsigned long long>(), wid.as<int32_t>(), nq, (int)metric, w, dist);
+    VJ_HIP(hipGetLastError());
+    VJ_HIP(hipStreamSynchronize(s));
 }
 
 int64_t bruteforce_join_noalloc(const float *Q, int64_t nq, const float *X, int64_t nx, int d,

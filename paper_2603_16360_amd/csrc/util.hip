@@ -97,6 +97,41 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+// NN-Map OOD bit, one wave per query (fp64 sums of the fp32 rows): d1 =
+// |q - w|, d2 = mean |w - z| over w's data neighbours z; OOD iff d1 / d2 >
+// ratio (no such z: not OOD)
+__global__ void k_nn_ood(const float *vec, int dp, int64_t nx, int64_t nq, const int32_t *adj,
+                         int R, const int32_t *w, double ratio, uint8_t *ood) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (i >= nq) return;
+    const int32_t y = w[i];
+    auto l2 = [&](int64_t a, int64_t b) {
+        double acc = 0.0;
+        for (int k = lane; k < dp; k += 64) {
+            const double t = (double)vec[a * dp + k] - (double)vec[b * dp + k];
+            acc += t * t;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        return sqrt(acc);
+    };
+    if (y < 0 || y >= nx) {
+        if (lane == 0) ood[i] = 0;
+        return;
+    }
+    const double d1 = l2(nx + i, y);
+    double s2 = 0.0;
+    int c2 = 0;
+    for (int k = 0; k < R; ++k) {
+        const int32_t z = adj[(int64_t)y * R + k];
+        if (z < 0 || z >= nx) continue;
+        s2 += l2(y, z);
+        ++c2;
+    }
+    if (lane == 0) ood[i] = c2 > 0 && d1 / (s2 / (double)c2) > ratio;
+}
+
 __global__ void k_offset_ids(int32_t *p, int64_t n, int32_t off) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n && p[i] >= 0) p[i] += off;
@@ -372,6 +407,14 @@ void launch_dist_to_node(const float *vec, int dp, int64_t first, int64_t n, int
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     if (n == 0) return;
     hipLaunchKernelGGL(k_fill_i32, dim3(grid1(n)), dim3(256), 0, s, p, n, v);
+}
+
+void nn_ood(const float *vec, int dp, int64_t nx, int64_t nq, const int32_t *adj, int R,
+            const int32_t *w, double ratio, uint8_t *ood, hipStream_t s) {
+    if (nq <= 0) return;
+    hipLaunchKernelGGL(k_nn_ood, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, vec, dp, nx, nq,
+                       adj, R, w, ratio, ood);
+    VJ_HIP(hipGetLastError());
 }
 
 void offset_ids(int32_t *p, int64_t n, int32_t off, hipStream_t s) {

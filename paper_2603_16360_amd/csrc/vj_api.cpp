@@ -226,7 +226,7 @@ static void make_order(Index &ix, const int32_t *ids, int64_t n, int ws, bool de
     o.qlist.reserve(n * sizeof(int32_t));
     o.qpos.reserve(n * sizeof(int32_t));
     o.level_start.clear();
-    if (ws == VJ_WS_SELF) {
+    if (ws == VJ_WS_SELF || ws == VJ_WS_NNMAP) {
         // queries are independent: any order gives the same result
         if (dense_first) {
             JoinWorkspace &jw = ix.jw;
@@ -280,6 +280,9 @@ static JoinArgs make_args(const Index &ix, int prec, const vj_join_params &p, in
     a.hyb = p.hybrid;
     a.merged = ix.separate ? 0 : 1;
     a.gbeam = p.greedy_beam;
+    a.nn_w = ix.has_nnmap ? ix.nn_w.as<int32_t>() : nullptr;
+    a.nn_d = ix.has_nnmap ? ix.nn_d.as<double>() : nullptr;
+    a.nn_ood = ix.has_nnmap ? ix.nn_ood.as<uint8_t>() : nullptr;
     a.beam = beam;
     a.conv = p.conv_threshold;
     a.ood_ratio = p.ood_ratio;
@@ -361,7 +364,8 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
         out_d.reserve((size_t)cap * sizeof(float));
         ix.gen += 1;
         VJ_HIP(hipMemsetAsync(counters.p, 0, 64, s));
-        if (ws != VJ_WS_SELF) stamp_batch(ix.inb.as<int32_t>(), ix.nq, ids, n, ix.gen, ctr + 3, s);
+        if (ws == VJ_WS_SOFT || ws == VJ_WS_HARD)
+            stamp_batch(ix.inb.as<int32_t>(), ix.nq, ids, n, ix.gen, ctr + 3, s);
 
         JoinArgs a = make_args(ix, prec, p, beam, eps, budget, ctr);
         a.out_q = out_q.as<int32_t>();
@@ -1184,6 +1188,41 @@ vj_status vj_build_merged_index(const float *Q, int64_t nq, const float *X, int6
     API_END
 }
 
+vj_status vj_build_nnmap(vj_index *idx, float ood_ratio, void *stream) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr, VJ_ERR_INVALID_ARG, "null index");
+    Index &ix = idx->impl;
+    VJ_CHECK(ix.separate, VJ_ERR_INVALID_ARG, "an NN-Map is built on separate indexes");
+    VJ_CHECK(std::isfinite(ood_ratio) && ood_ratio > 0.f, VJ_ERR_INVALID_ARG, "ood_ratio > 0");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nq = (size_t)std::max<int64_t>(ix.nq, 1);
+    ix.nn_w.alloc(nq * sizeof(int32_t));
+    ix.nn_d.alloc(nq * sizeof(double));
+    ix.nn_ood.alloc(nq);
+    const float *vec = ix.vec.as<float>();
+    exact_top1(vec + (size_t)ix.nx * ix.dp, ix.nq, vec, ix.nx, ix.dp, ix.metric,
+               ix.nn_w.as<int32_t>(), ix.nn_d.as<double>(), s);
+    nn_ood(vec, ix.dp, ix.nx, ix.nq, ix.adj.as<int32_t>(), ix.R, ix.nn_w.as<int32_t>(),
+           (double)ood_ratio, ix.nn_ood.as<uint8_t>(), s);
+    VJ_HIP(hipStreamSynchronize(s));
+    ix.has_nnmap = true;
+    API_END
+}
+
+vj_status vj_index_export_nnmap(const vj_index *idx, int32_t *w, double *dist, uint8_t *ood,
+                                void *stream) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr, VJ_ERR_INVALID_ARG, "null index");
+    const Index &ix = idx->impl;
+    VJ_CHECK(ix.has_nnmap, VJ_ERR_INVALID_ARG, "the index has no NN-Map");
+    hipStream_t s = (hipStream_t)stream;
+    if (w) VJ_HIP(hipMemcpyAsync(w, ix.nn_w.p, (size_t)ix.nq * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (dist) VJ_HIP(hipMemcpyAsync(dist, ix.nn_d.p, (size_t)ix.nq * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (ood) VJ_HIP(hipMemcpyAsync(ood, ix.nn_ood.p, (size_t)ix.nq, hipMemcpyDeviceToDevice, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
 vj_status vj_index_export_graph(const vj_index *idx, int32_t *adj, float *elen, int32_t *parent,
                                 void *stream) {
     API_BEGIN
@@ -1249,10 +1288,13 @@ vj_status vj_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
     vj_join_params p;
     vj_default_join_params(&p);
     if (pp) p = *pp;
-    VJ_CHECK(p.work_sharing >= VJ_WS_SELF && p.work_sharing <= VJ_WS_HARD, VJ_ERR_INVALID_ARG, "work_sharing");
+    VJ_CHECK(p.work_sharing >= VJ_WS_SELF && p.work_sharing <= VJ_WS_NNMAP, VJ_ERR_INVALID_ARG, "work_sharing");
+    VJ_CHECK(p.work_sharing != VJ_WS_NNMAP || (ix.separate && ix.has_nnmap), VJ_ERR_INVALID_ARG,
+             "NN-Map joins need a separate index with an NN-Map (vj_build_nnmap)");
     VJ_CHECK(p.hybrid >= VJ_HYB_OFF && p.hybrid <= VJ_HYB_LEARNED, VJ_ERR_INVALID_ARG, "hybrid");
     VJ_CHECK(p.hybrid_beam >= 0 && p.hybrid_beam <= 4096, VJ_ERR_INVALID_ARG, "hybrid_beam in [0, 4096]");
-    VJ_CHECK(p.work_sharing == VJ_WS_SELF || ix.has_mst, VJ_ERR_INVALID_ARG, "work sharing needs the MST");
+    VJ_CHECK((p.work_sharing != VJ_WS_SOFT && p.work_sharing != VJ_WS_HARD) || ix.has_mst,
+             VJ_ERR_INVALID_ARG, "work sharing needs the MST");
     VJ_CHECK(p.hybrid != VJ_HYB_BUDGET || p.budget != nullptr, VJ_ERR_INVALID_ARG, "budget mode needs budget[]");
     VJ_CHECK(p.start_tier >= 0 && p.start_tier <= 2, VJ_ERR_INVALID_ARG, "start_tier in [0, 2]");
     VJ_CHECK(p.coop_tables == 0 || p.coop_tables == 1, VJ_ERR_INVALID_ARG, "coop_tables is 0 or 1");

@@ -141,6 +141,9 @@ struct Index {
     // graph G_X (entry: its entry), rows nx.. the query graph G_Q (node ids),
     // read only by the MST
     bool separate = false;
+    // NN-Map of the queries (Section 6): witness, its distance, OOD bit
+    DevBuf nn_w, nn_d, nn_ood;
+    bool has_nnmap = false;
     int64_t repairs = 0;  // connectivity-repair edges added by the build
     // join state shared by calls on this index (calls on one index must not overlap)
     DevBuf cache;    // int32 [nq] soft work sharing: closest visited data node
@@ -188,6 +191,9 @@ struct JoinArgs {
     unsigned long long *nrecheck;  // bf16 rows: candidates re-decided from fp32 rows
     int32_t ws, hyb, beam, conv;
     int32_t merged;           // 1 merged index; 0 separate indexes (adj rows < nx: data graph)
+    const int32_t *nn_w;      // NN-Map: [nq] witness (nearest data node) of each query
+    const double *nn_d;       // [nq] its distance (join metric, fp64)
+    const uint8_t *nn_ood;    // [nq] OOD bit
     int32_t gbeam;            // separate indexes: greedy queue bound (cfg.greedy_beam_size)
     float ood_ratio;
     int32_t gen;              // stamp of this call in inb[]

@@ -25,7 +25,8 @@ VJ_OK = 0
 STATUS = {0: "VJ_OK", 1: "VJ_ERR_INVALID_ARG", 2: "VJ_ERR_METRIC_MISMATCH", 3: "VJ_ERR_OOM",
           4: "VJ_ERR_HIP", 5: "VJ_ERR_INTERNAL", 6: "VJ_ERR_UNSUPPORTED", 7: "VJ_ERR_IO"}
 METRIC = {"l2": 0, "ip": 1}
-WORK_SHARING = {"self": 0, "none": 0, "soft": 1, "hard": 2}  # "none": no sharing (INLJ)
+WORK_SHARING = {"self": 0, "none": 0, "soft": 1, "hard": 2,  # "none": no sharing (INLJ)
+                "nnmap": 3}
 HYBRID = {"off": 0, "force": 1, "adapt": 2, "budget": 3, "learned": 4}
 PRECISION = {"fp32": 0, "bf16": 1, "fp8": 2, "u8": 3, "auto": 4}
 STAT_FIELDS = ("pairs", "n_dist", "n_expanded", "h_pops", "ood", "hybrid",
@@ -66,6 +67,8 @@ _SIGS = {
                                           C.POINTER(vj_build_params), _vp, _PP]),
     "vj_index_from_separate_graphs": (C.c_int, [_vp, _i64, _vp, _i64, _i32, C.c_int, _vp, _i32,
                                                 _i32, _vp, _vp, _PP]),
+    "vj_build_nnmap": (C.c_int, [_vp, _f32, _vp]),
+    "vj_index_export_nnmap": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vj_index_export_graph": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vj_index_info": (C.c_int, [_vp] + [_vp] * 6),
     "vj_index_free": (None, [_vp]),
@@ -215,6 +218,19 @@ class Index:
         parent = torch.empty(i["nq"], dtype=torch.int32, device="cuda")
         _check(_lib.vj_index_export_graph(self._h, _ptr(adj), _ptr(elen), _ptr(parent), _stream()))
         return adj, elen, parent
+
+    def build_nnmap(self, ood_ratio: float = 1.5):
+        """NN-Map of the queries (vj_build_nnmap; separate indexes)."""
+        _check(_lib.vj_build_nnmap(self._h, float(ood_ratio), _stream()))
+
+    def export_nnmap(self):
+        """(w int32 [nq], dist float64 [nq], ood uint8 [nq]) on the GPU."""
+        nq = self.info()["nq"]
+        w = torch.empty(nq, dtype=torch.int32, device="cuda")
+        dist = torch.empty(nq, dtype=torch.float64, device="cuda")
+        ood = torch.empty(nq, dtype=torch.uint8, device="cuda")
+        _check(_lib.vj_index_export_nnmap(self._h, _ptr(w), _ptr(dist), _ptr(ood), _stream()))
+        return w, dist, ood
 
     def save(self, path: str):
         """Write the index to a file (vj_index_save)."""
