@@ -176,6 +176,22 @@ vj_status vj_index_from_separate_graphs(const float *Q, int64_t nq, const float 
                                         void *stream, vj_index **out);
 
 /*
+ * Query-data role switch of a merged index (Appendix E: the join is
+ * symmetric, and for large thresholds iterating over the larger set while
+ * traversing the smaller set's part of the graph avoids most random
+ * accesses).  The new index has the same graph and vectors with the roles
+ * exchanged: its queries are the old data rows (query index j = old data
+ * index j) and its data are the old queries (data index i = old query index
+ * i); node ids are relabelled (data first), the entry follows its node.  A
+ * join on it returns pairs (old data index, old query index): the
+ * role-switched join, to be read transposed.  build_mst != 0 computes the
+ * MST of the new query set (needed only for SOFT / HARD).  Merged indexes
+ * only (VJ_ERR_INVALID_ARG otherwise).
+ */
+vj_status vj_index_swap_roles(const vj_index *idx, int32_t build_mst, void *stream,
+                              vj_index **out);
+
+/*
  * NN-Map (Section 6): for every query of a separate index its nearest data
  * node w (exact by the index metric: MFMA tile minima, then every candidate
  * within twice the tiles' proven error bound re-decided in fp64; ties to the

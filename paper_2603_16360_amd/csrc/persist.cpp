@@ -9,6 +9,7 @@
 //   streamed through a host buffer in chunks.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -25,7 +26,7 @@ constexpr size_t kChunk = (size_t)32 << 20;
 
 struct IndexHeader {
     int64_t nq, nx, repairs;
-    int32_t d, dp, R, entry, metric, has_mst, separate, pad;
+    int32_t d, dp, R, entry, metric, has_mst, separate, has_nnmap;
 };
 
 struct PredHeader {
@@ -105,7 +106,7 @@ void index_save(const Index &ix, const char *path) {
     Writer w(path);
     w.host(kIndexMagic, 8);
     IndexHeader h{ix.nq, ix.nx, ix.repairs, ix.d, ix.dp, ix.R, ix.entry, (int32_t)ix.metric,
-                  ix.has_mst ? 1 : 0, ix.separate ? 1 : 0, 0};
+                  ix.has_mst ? 1 : 0, ix.separate ? 1 : 0, ix.has_nnmap ? 1 : 0};
     w.host(&h, sizeof(h));
     w.device(ix.vec.p, (size_t)ix.N * ix.dp * sizeof(float));
     w.device(ix.adj.p, (size_t)ix.N * ix.R * sizeof(int32_t));
@@ -113,6 +114,11 @@ void index_save(const Index &ix, const char *path) {
     if (ix.has_mst && ix.nq > 0) {
         w.device(ix.parent.p, (size_t)ix.nq * sizeof(int32_t));
         w.device(ix.depth.p, (size_t)ix.nq * sizeof(int32_t));
+    }
+    if (ix.has_nnmap && ix.nq > 0) {
+        w.device(ix.nn_w.p, (size_t)ix.nq * sizeof(int32_t));
+        w.device(ix.nn_d.p, (size_t)ix.nq * sizeof(double));
+        w.device(ix.nn_ood.p, (size_t)ix.nq);
     }
     w.close();
 }
@@ -127,7 +133,7 @@ void index_load(Index &ix, const char *path, void (*finish)(Index &, hipStream_t
     VJ_CHECK(h.nq >= 0 && h.nx >= 1 && h.nq + h.nx < ((int64_t)1 << 30) && h.d >= 1 &&
                  h.d <= 1024 && h.dp == padded_dim(h.d) && h.R >= 1 && h.R <= 64 &&
                  h.entry >= 0 && h.entry < h.nq + h.nx && (h.metric == VJ_L2 || h.metric == VJ_IP) &&
-                 (h.separate == 0 || h.separate == 1),
+                 (h.separate == 0 || h.separate == 1) && (h.has_nnmap == 0 || h.has_nnmap == 1),
              VJ_ERR_IO, "index file header is out of range");
     ix.nq = h.nq; ix.nx = h.nx; ix.N = h.nq + h.nx; ix.d = h.d; ix.dp = h.dp; ix.R = h.R;
     ix.entry = h.entry; ix.metric = (vj_metric)h.metric; ix.repairs = h.repairs;
@@ -148,6 +154,18 @@ void index_load(Index &ix, const char *path, void (*finish)(Index &, hipStream_t
             r.device(ix.parent.p, (size_t)ix.nq * sizeof(int32_t));
             r.device(ix.depth.p, (size_t)ix.nq * sizeof(int32_t));
         }
+    }
+    if (h.has_nnmap) {
+        const size_t nq = (size_t)std::max<int64_t>(ix.nq, 1);
+        ix.nn_w.alloc(nq * sizeof(int32_t));
+        ix.nn_d.alloc(nq * sizeof(double));
+        ix.nn_ood.alloc(nq);
+        if (ix.nq > 0) {
+            r.device(ix.nn_w.p, (size_t)ix.nq * sizeof(int32_t));
+            r.device(ix.nn_d.p, (size_t)ix.nq * sizeof(double));
+            r.device(ix.nn_ood.p, (size_t)ix.nq);
+        }
+        ix.has_nnmap = true;
     }
     r.check_end();
     finish(ix, s);

@@ -12,6 +12,8 @@ void iota_i32(int32_t *p, int64_t n, hipStream_t s);
 // NN-Map OOD bits of the queries from their witnesses w (see k_nn_ood)
 void nn_ood(const float *vec, int dp, int64_t nx, int64_t nq, const int32_t *adj, int R,
             const int32_t *w, double ratio, uint8_t *ood, hipStream_t s);
+// role switch of a merged index's node ids (data v -> nq + v, query v -> v - nx)
+void swap_ids(int32_t *p, int64_t n, int32_t nx, int32_t nq, hipStream_t s);
 // p[i] += off for every id >= 0 (-1 padding stays)
 void offset_ids(int32_t *p, int64_t n, int32_t off, hipStream_t s);
 void stamp_batch(int32_t *inb, int64_t nq, const int32_t *ids, int64_t n, int32_t gen,

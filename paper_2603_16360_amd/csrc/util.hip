@@ -132,6 +132,15 @@ __global__ void k_nn_ood(const float *vec, int dp, int64_t nx, int64_t nq, const
     if (lane == 0) ood[i] = c2 > 0 && d1 / (s2 / (double)c2) > ratio;
 }
 
+// role switch of a merged index: data id v < nx becomes nq + v, query node
+// id v >= nx becomes v - nx (-1 padding stays)
+__global__ void k_swap_ids(int32_t *p, int64_t n, int32_t nx, int32_t nq) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = p[i];
+    if (v >= 0) p[i] = v < nx ? v + nq : v - nx;
+}
+
 __global__ void k_offset_ids(int32_t *p, int64_t n, int32_t off) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n && p[i] >= 0) p[i] += off;
@@ -414,6 +423,12 @@ void nn_ood(const float *vec, int dp, int64_t nx, int64_t nq, const int32_t *adj
     if (nq <= 0) return;
     hipLaunchKernelGGL(k_nn_ood, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, vec, dp, nx, nq,
                        adj, R, w, ratio, ood);
+    VJ_HIP(hipGetLastError());
+}
+
+void swap_ids(int32_t *p, int64_t n, int32_t nx, int32_t nq, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_swap_ids, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, nx, nq);
     VJ_HIP(hipGetLastError());
 }
 

@@ -1188,6 +1188,41 @@ vj_status vj_build_merged_index(const float *Q, int64_t nq, const float *X, int6
     API_END
 }
 
+vj_status vj_index_swap_roles(const vj_index *idx, int32_t build_mst, void *stream,
+                              vj_index **out) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr && out != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    const Index &a = idx->impl;
+    VJ_CHECK(!a.separate, VJ_ERR_INVALID_ARG, "the role switch is defined on a merged index");
+    VJ_CHECK(a.nq >= 1, VJ_ERR_INVALID_ARG, "the role switch needs at least one query");
+    hipStream_t s = (hipStream_t)stream;
+    auto h = std::make_unique<vj_index>();
+    Index &b = h->impl;
+    b.nq = a.nx; b.nx = a.nq; b.N = a.N; b.d = a.d; b.dp = a.dp; b.R = a.R;
+    b.metric = a.metric;
+    b.entry = a.entry < a.nx ? a.entry + (int32_t)a.nq : a.entry - (int32_t)a.nx;
+    b.repairs = a.repairs;
+    VJ_HIP(hipGetDevice(&b.device));
+    // the old query rows come first, then the old data rows
+    const size_t rq = (size_t)a.nq, rx = (size_t)a.nx;
+    b.vec.alloc((size_t)b.N * b.dp * sizeof(float));
+    const size_t vrow = (size_t)a.dp * sizeof(float), arow = (size_t)a.R * sizeof(int32_t);
+    VJ_HIP(hipMemcpyAsync(b.vec.p, a.vec.as<char>() + rx * vrow, rq * vrow, hipMemcpyDeviceToDevice, s));
+    VJ_HIP(hipMemcpyAsync(b.vec.as<char>() + rq * vrow, a.vec.p, rx * vrow, hipMemcpyDeviceToDevice, s));
+    b.adj.alloc((size_t)b.N * arow);
+    VJ_HIP(hipMemcpyAsync(b.adj.p, a.adj.as<char>() + rx * arow, rq * arow, hipMemcpyDeviceToDevice, s));
+    VJ_HIP(hipMemcpyAsync(b.adj.as<char>() + rq * arow, a.adj.p, rx * arow, hipMemcpyDeviceToDevice, s));
+    swap_ids(b.adj.as<int32_t>(), b.N * b.R, (int32_t)a.nx, (int32_t)a.nq, s);
+    b.elen.alloc((size_t)b.N * b.R * sizeof(float));
+    VJ_HIP(hipMemcpyAsync(b.elen.p, a.elen.as<char>() + rx * arow, rq * arow, hipMemcpyDeviceToDevice, s));
+    VJ_HIP(hipMemcpyAsync(b.elen.as<char>() + rq * arow, a.elen.p, rx * arow, hipMemcpyDeviceToDevice, s));
+    finish_vectors(b, s);
+    if (build_mst) compute_mst(b, s);
+    VJ_HIP(hipStreamSynchronize(s));
+    *out = h.release();
+    API_END
+}
+
 vj_status vj_build_nnmap(vj_index *idx, float ood_ratio, void *stream) {
     API_BEGIN
     VJ_CHECK(idx != nullptr, VJ_ERR_INVALID_ARG, "null index");

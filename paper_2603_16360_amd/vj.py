@@ -67,6 +67,7 @@ _SIGS = {
                                           C.POINTER(vj_build_params), _vp, _PP]),
     "vj_index_from_separate_graphs": (C.c_int, [_vp, _i64, _vp, _i64, _i32, C.c_int, _vp, _i32,
                                                 _i32, _vp, _vp, _PP]),
+    "vj_index_swap_roles": (C.c_int, [_vp, _i32, _vp, _PP]),
     "vj_build_nnmap": (C.c_int, [_vp, _f32, _vp]),
     "vj_index_export_nnmap": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vj_index_export_graph": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -209,15 +210,24 @@ class Index:
         return {"nq": nq.value, "nx": nx.value, "d": d.value, "R": R.value,
                 "entry": e.value, "metric": m.value}
 
-    def export_graph(self):
-        """(adj int32 [N, R], elen float32 [N, R], parent int32 [nq]) on the GPU."""
+    def export_graph(self, with_parent: bool = True):
+        """(adj int32 [N, R], elen float32 [N, R], parent int32 [nq] or None
+        without an MST) on the GPU."""
         i = self.info()
         N = i["nq"] + i["nx"]
         adj = torch.empty((N, i["R"]), dtype=torch.int32, device="cuda")
         elen = torch.empty((N, i["R"]), dtype=torch.float32, device="cuda")
         parent = torch.empty(i["nq"], dtype=torch.int32, device="cuda")
-        _check(_lib.vj_index_export_graph(self._h, _ptr(adj), _ptr(elen), _ptr(parent), _stream()))
-        return adj, elen, parent
+        _check(_lib.vj_index_export_graph(self._h, _ptr(adj), _ptr(elen),
+                                          _ptr(parent) if with_parent else None, _stream()))
+        return adj, elen, parent if with_parent else None
+
+    def swap_roles(self, build_mst: bool = False) -> "Index":
+        """The role-switched merged index (vj_index_swap_roles): joins on it
+        return (old data index, old query index) pairs."""
+        h = C.c_void_p()
+        _check(_lib.vj_index_swap_roles(self._h, int(build_mst), _stream(), C.byref(h)))
+        return Index(h.value)
 
     def build_nnmap(self, ood_ratio: float = 1.5):
         """NN-Map of the queries (vj_build_nnmap; separate indexes)."""

@@ -48,6 +48,23 @@ def test_index_round_trip(tmp_path):
     assert lo <= got <= hi
 
 
+def test_separate_index_with_nnmap_round_trip(tmp_path):
+    w = workloads.config_tiny(scale=0.2)
+    eps = oracle.calibrate_eps(w.Q, w.X, w.target_matches)
+    a = vj.vj_build_separate_index(torch.from_numpy(w.Q).cuda(), torch.from_numpy(w.X).cuda(), R=16)
+    a.build_nnmap()
+    path = str(tmp_path / "sep.vjx")
+    a.save(path)
+    b = vj.vj_index_load(path)
+    for x, y in zip(a.export_nnmap(), b.export_nnmap()):
+        assert torch.equal(x, y)
+    for kw in ({"work_sharing": "none"}, {"work_sharing": "soft"}, {"work_sharing": "nnmap"},
+               {"work_sharing": "nnmap", "hybrid": "adapt"}):
+        ra, rb = _sorted_result(vj.vj_join(a, eps, **kw)), _sorted_result(vj.vj_join(b, eps, **kw))
+        for x, y in zip(ra, rb):
+            assert np.array_equal(x, y), kw
+
+
 def test_index_file_damage_is_refused(tmp_path):
     w = workloads.config_tiny(scale=0.05)
     a = vj.vj_build_merged_index(torch.from_numpy(w.Q).cuda(), torch.from_numpy(w.X).cuda(), R=16)
