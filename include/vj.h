@@ -77,7 +77,11 @@ typedef enum {
                          proven error margin of eps is re-decided from the fp32 rows in the
                          fp32 kernels' arithmetic, so in/out decisions equal VJ_PREC_FP32's
                          (join: workgroup tiers only) */
-    VJ_PREC_FP8 = 2,  /* e4m3 copy (per-row scale), fp32 re-check near eps */
+    VJ_PREC_FP8 = 2,  /* OCP e4m3 rows with a power-of-two scale per row and a stored
+                         bound on |x - x~| (fp64, rounded up); fp32 query and accumulation; a
+                         candidate within that margin of eps (triangle inequality) is
+                         re-decided from the fp32 rows in the fp32 kernels' arithmetic, so
+                         in/out decisions equal VJ_PREC_FP32's (join: workgroup tiers only) */
     VJ_PREC_U8 = 3,   /* exact u8 copy (integer data in [0, 255] only) */
     VJ_PREC_AUTO = 4  /* u8 if the index data is exactly u8, else fp32 */
 } vj_precision;
@@ -90,7 +94,8 @@ typedef struct {
     int32_t R;           /* max out-degree, 1..64 */
     int32_t K_cand;      /* exact-kNN candidates per node before pruning, <= 112 (0: min(2R, 112)) */
     int32_t build_mst;   /* 1: compute the query MST (needed for SOFT/HARD) */
-    int32_t copies;      /* bit mask of low-precision copies: 1 bf16, 2 fp8, 4 u8 */
+    int32_t copies;      /* low-precision copies made at build (else on first use): 1 bf16,
+                            2 fp8; exact u8 rows are made whenever the data allows them */
 } vj_build_params;
 
 typedef struct {

@@ -29,7 +29,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 # join_inst.hip is compiled once per (row type, padded width)
 JOIN_WIDTHS = (32, 64, 96, 128, 192, 256, 384, 512, 768, 1024)
-JOIN_TYPES = (("f32", "float"), ("u8", "uint8_t"), ("bf16", "uint16_t"))
+JOIN_TYPES = (("f32", "float"), ("u8", "uint8_t"), ("bf16", "uint16_t"), ("f8", "vj::f8e4m3"))
 
 
 def sources() -> list[tuple[str, list[str], str]]:

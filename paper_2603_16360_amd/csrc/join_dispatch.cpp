@@ -8,7 +8,8 @@ namespace vj {
 #define VJ_DECL(dp)                                               \
     bool launch_join_f32_##dp(const JoinLaunch &, hipStream_t);   \
     bool launch_join_u8_##dp(const JoinLaunch &, hipStream_t);    \
-    bool launch_join_bf16_##dp(const JoinLaunch &, hipStream_t);
+    bool launch_join_bf16_##dp(const JoinLaunch &, hipStream_t);  \
+    bool launch_join_f8_##dp(const JoinLaunch &, hipStream_t);
 VJ_WIDTHS(VJ_DECL)
 #undef VJ_DECL
 
@@ -33,6 +34,15 @@ bool launch_join_u8(const JoinLaunch &L, hipStream_t s) {
 bool launch_join_bf16(const JoinLaunch &L, hipStream_t s) {
     switch (L.dp) {
 #define VJ_CASE(dp) case dp: return launch_join_bf16_##dp(L, s);
+        VJ_WIDTHS(VJ_CASE)
+#undef VJ_CASE
+    default: return false;
+    }
+}
+
+bool launch_join_f8(const JoinLaunch &L, hipStream_t s) {
+    switch (L.dp) {
+#define VJ_CASE(dp) case dp: return launch_join_f8_##dp(L, s);
         VJ_WIDTHS(VJ_CASE)
 #undef VJ_CASE
     default: return false;

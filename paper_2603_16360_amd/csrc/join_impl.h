@@ -43,9 +43,12 @@ template <typename T> struct Elem;
 template <> struct Elem<float> { static constexpr int CE = 4; };
 template <> struct Elem<uint8_t> { static constexpr int CE = 16; };
 template <> struct Elem<uint16_t> { static constexpr int CE = 8; };  // bf16 bits
+template <> struct Elem<f8e4m3> { static constexpr int CE = 16; };   // e4m3 codes
 
-// bf16 rows carry a rounding error that the kernels bound and re-check
-template <typename T> constexpr bool kIsBf16 = std::is_same<T, uint16_t>::value;
+// bf16 and fp8 rows carry a rounding error that the kernels bound and
+// re-check (kLowp); fp8 rows are scaled per row
+template <typename T> constexpr bool kIsF8 = std::is_same<T, f8e4m3>::value;
+template <typename T> constexpr bool kIsBf16 = std::is_same<T, uint16_t>::value || kIsF8<T>;
 
 // lanes per row: a power of two with at most 8 16-byte chunks per lane
 constexpr int pick_lpr(int cpr) {
@@ -70,6 +73,15 @@ __device__ __forceinline__ void to_float(const uint4 &r, float *f, uint8_t) {
         f[4 * i + 1] = (float)((w[i] >> 8) & 0xffu);
         f[4 * i + 2] = (float)((w[i] >> 16) & 0xffu);
         f[4 * i + 3] = (float)(w[i] >> 24);
+    }
+}
+
+__device__ __forceinline__ void to_float(const uint4 &r, float *f, f8e4m3) {
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) f[4 * i + b] = f8_value((w[i] >> (8 * b)) & 0xffu);
     }
 }
 
@@ -179,12 +191,16 @@ __device__ __forceinline__ float row_partial(const uint4 *buf, const float *qf, 
 // as row_partial, plus the squared norm of the row (xn2)
 template <int LPR, int VPL, int CE, typename T>
 __device__ __forceinline__ float row_partial_n(const uint4 *buf, const float *qf, bool l2,
-                                               float &xn2) {
+                                               float &xn2, float scale = 1.f) {
     float acc = 0.f, nn = 0.f;
 #pragma unroll
     for (int w = 0; w < VPL; ++w) {
         float f[CE];
         to_float(buf[w], f, T());
+        if constexpr (kIsF8<T>) {
+#pragma unroll
+            for (int e = 0; e < CE; ++e) f[e] *= scale;  // exact: a power of two
+        }
 #pragma unroll
         for (int e = 0; e < CE; ++e) {
             if (l2) { const float t = f[e] - qf[w * CE + e]; acc = fmaf(t, t, acc); }
@@ -651,6 +667,7 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
     for (int base = 0; base < cnt; base += RPP * PG) {
         uint4 buf[PG][VPL];
         int sid[PG];
+        float2 sev[PG];  // fp8 rows: (scale, error bound) of each row
 #pragma unroll
         for (int g = 0; g < PG; ++g) {
             const int c = base + g * RPP + rr;
@@ -661,6 +678,7 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
 #pragma unroll
             for (int w = 0; w < VPL; ++w)
                 buf[g][w] = c < cnt ? row[p + w * LPR] : make_uint4(0, 0, 0, 0);
+            if constexpr (kIsF8<T>) sev[g] = c < cnt ? a.f8meta[id] : make_float2(1.f, 0.f);
         }
         float keyv[PG];
         bool inrv[PG], uncv[PG];
@@ -672,27 +690,35 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
             float acc;
             uncv[g] = false;
             if constexpr (kIsBf16<T>) {
-                // |q - x~| differs from |q - x| by at most |x - x~| <= bf_u |x~|
-                // (triangle inequality; q is exact); GB bounds the relative
-                // error of the fp32 sums here and in the fp32 kernels
+                // |q - x~| differs from |q - x| by at most |x - x~|: for bf16
+                // rows <= bf_u |x~|, for fp8 rows the bound stored with the
+                // row (triangle inequality; q is exact); GB bounds the
+                // relative error of the fp32 sums here and in the fp32 kernels
                 constexpr float GB = (float)(2 * (VPL * CE + 5 + 16)) * 5.9604645e-8f;
                 float xn2;
-                acc = row_partial_n<LPR, VPL, CE, T>(buf[g], qf, l2, xn2);
+                float2 se = make_float2(1.f, 0.f);
+                if constexpr (kIsF8<T>) se = sev[g];
+                acc = row_partial_n<LPR, VPL, CE, T>(buf[g], qf, l2, xn2, se.x);
                 const float xn = sqrtf(xn2) * (1.f + GB);
+                const float exr = kIsF8<T> ? se.y * (1.f + GB) : a.bf_u * xn;
                 bool sure;
                 if (l2) {
                     const float dt = sqrtf(acc);
-                    const float ex = a.bf_u * xn;
+                    const float ex = exr;
                     const float hi = (dt * (1.f + GB) + ex) * (1.f + GB);
                     const float lo = fmaxf(0.f, dt * (1.f - GB) - ex) * (1.f - GB);
                     sure = hi * hi * (1.f + GB) < a.eps2 || lo * lo * (1.f - GB) >= a.eps2;
                 } else {
-                    const float mrg = cw.qn * xn * (a.bf_u + 2.f * GB * (1.f + a.bf_u)) +
-                                      GB * (1.f + fabsf(acc));
+                    const float mrg = kIsF8<T>
+                                          ? cw.qn * (exr + 2.f * GB * xn) + GB * (1.f + fabsf(acc))
+                                          : cw.qn * xn * (a.bf_u + 2.f * GB * (1.f + a.bf_u)) +
+                                                GB * (1.f + fabsf(acc));
                     const float key = 1.0f - acc;
                     sure = key + mrg < a.eps || key - mrg >= a.eps;
                 }
-                uncv[g] = lead && !sure;
+                // the greedy queue of separate indexes orders and stops by
+                // the keys: those are always the fp32 kernels' values
+                uncv[g] = lead && (!sure || push_all);
                 unc_any |= __ballot(uncv[g]);
             } else {
                 acc = row_partial<LPR, VPL, CE, T>(buf[g], qf, l2);

@@ -97,6 +97,59 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+// OCP fp8 e4m3: 1 sign, 4 exponent (bias 7), 3 mantissa bits; largest
+// finite 448, subnormal step 2^-9, code 0x7f (and 0xff) NaN, never produced.
+__device__ __forceinline__ uint32_t f8_encode(float v) {
+    const uint32_t sign = v < 0.f ? 0x80u : 0u;
+    const float a = fabsf(v);
+    uint32_t code;
+    if (!(a < 448.f)) {
+        code = 0x7eu;  // saturate (also NaN input: never produced by finite rows)
+    } else if (a < 0.015625f) {  // below 2^-6: subnormal, step 2^-9
+        code = (uint32_t)rintf(a * 512.f);  // 0..8; 8 is the smallest normal
+    } else {
+        int e;
+        const float f = frexpf(a, &e);  // a = f 2^e, f in [0.5, 1)
+        int E = e - 1;
+        uint32_t m = (uint32_t)rintf((2.f * f - 1.f) * 8.f);
+        if (m == 8u) { m = 0u; E += 1; }
+        const int field = E + 7;
+        code = (field > 15 || (field == 15 && m == 7u)) ? 0x7eu : ((uint32_t)field << 3) | m;
+    }
+    return sign | code;
+}
+
+// one wave per row: scale, codes and the fp64 bound of the rounding error
+__global__ void k_quantize_f8(const float *vec, int64_t rows, int dp, uint8_t *codes, float2 *meta) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (r >= rows) return;
+    const float *x = vec + r * dp;
+    float amax = 0.f;
+    for (int k = lane; k < dp; k += 64) amax = fmaxf(amax, fabsf(x[k]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+    // smallest power of two s with amax / s <= 448
+    float sc = 1.f;
+    if (amax > 0.f) {
+        int e;
+        frexpf(amax / 448.f, &e);  // amax / 448 < 2^e
+        sc = ldexpf(1.f, e);
+        if (amax / ldexpf(1.f, e - 1) <= 448.f) sc = ldexpf(1.f, e - 1);
+    }
+    const float inv = 1.f / sc;  // exact: a power of two
+    double err = 0.0;
+    for (int k = lane; k < dp; k += 64) {
+        const uint32_t c = f8_encode(x[k] * inv);
+        codes[r * dp + k] = (uint8_t)c;
+        const double t = (double)x[k] - (double)sc * (double)f8_value(c);
+        err += t * t;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) err += __shfl_xor(err, off);
+    if (lane == 0) meta[r] = make_float2(sc, __double2float_ru(sqrt(err) * (1.0 + 1e-12)));
+}
+
 // NN-Map OOD bit, one wave per query (fp64 sums of the fp32 rows): d1 =
 // |q - w|, d2 = mean |w - z| over w's data neighbours z; OOD iff d1 / d2 >
 // ratio (no such z: not OOD)
@@ -429,6 +482,14 @@ void nn_ood(const float *vec, int dp, int64_t nx, int64_t nq, const int32_t *adj
 void swap_ids(int32_t *p, int64_t n, int32_t nx, int32_t nq, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_swap_ids, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, nx, nq);
+    VJ_HIP(hipGetLastError());
+}
+
+void launch_quantize_f8(const float *vec, int64_t rows, int dp, uint8_t *codes, float2 *meta,
+                        hipStream_t s) {
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(k_quantize_f8, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, vec, rows,
+                       dp, codes, meta);
     VJ_HIP(hipGetLastError());
 }
 

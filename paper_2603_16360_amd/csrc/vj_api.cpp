@@ -86,6 +86,15 @@ void ensure_bf16(Index &ix, hipStream_t s) {
     ix.bf16_exact = (h & 2) == 0;
 }
 
+void ensure_f8(Index &ix, hipStream_t s) {
+    if (ix.vec_f8.p) return;
+    ix.vec_f8.alloc((size_t)ix.N * ix.dp);
+    ix.f8meta.alloc((size_t)ix.N * sizeof(float2));
+    launch_quantize_f8(ix.vec.as<float>(), ix.N, ix.dp, ix.vec_f8.as<uint8_t>(),
+                       ix.f8meta.as<float2>(), s);
+    VJ_HIP(hipStreamSynchronize(s));
+}
+
 // MST over the query nodes plus (s, q) edges, rooted at s (Section 3.2);
 // Kruskal with ties on (w, min id, max id); weights are fp32 L2 lengths.
 void compute_mst(Index &ix, hipStream_t s) {
@@ -261,7 +270,11 @@ static void make_order(Index &ix, const int32_t *ids, int64_t n, int ws, bool de
 static JoinArgs make_args(const Index &ix, int prec, const vj_join_params &p, int beam, float eps,
                           const int32_t *budget, int32_t *ctr) {
     JoinArgs a{};
-    a.rows = prec == VJ_PREC_U8 ? ix.vec_u8.p : prec == VJ_PREC_BF16 ? ix.vec_bf16.p : ix.vec.p;
+    a.rows = prec == VJ_PREC_U8     ? ix.vec_u8.p
+             : prec == VJ_PREC_BF16 ? ix.vec_bf16.p
+             : prec == VJ_PREC_FP8  ? ix.vec_f8.p
+                                    : ix.vec.p;
+    a.f8meta = prec == VJ_PREC_FP8 ? ix.f8meta.as<float2>() : nullptr;
     // RNE to bf16 has relative error <= 2^-8 of |x|, i.e. <= 2^-8 / (1 - 2^-8) of |bf16(x)|
     a.bf_u = prec == VJ_PREC_BF16 && !ix.bf16_exact ? 0.00392157f : 0.f;
     a.nrecheck = reinterpret_cast<unsigned long long *>(ctr + 6);
@@ -303,9 +316,11 @@ static int join_precision(Index &ix, int prec, hipStream_t s) {
     if (prec == VJ_PREC_AUTO) prec = ix.integer_u8 ? VJ_PREC_U8 : VJ_PREC_FP32;
     VJ_CHECK(prec != VJ_PREC_U8 || ix.integer_u8, VJ_ERR_INVALID_ARG,
              "u8 precision needs integer data in [0, 255]");
-    VJ_CHECK(prec == VJ_PREC_FP32 || prec == VJ_PREC_U8 || prec == VJ_PREC_BF16,
+    VJ_CHECK(prec == VJ_PREC_FP32 || prec == VJ_PREC_U8 || prec == VJ_PREC_BF16 ||
+                 prec == VJ_PREC_FP8,
              VJ_ERR_UNSUPPORTED, "precision not supported by the traversal");
     if (prec == VJ_PREC_BF16) ensure_bf16(ix, s);
+    if (prec == VJ_PREC_FP8) ensure_f8(ix, s);
     return prec;
 }
 
@@ -316,8 +331,9 @@ static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const 
     // bf16 rows run on the workgroup tiers (they carry the margin re-check)
     // bf16 rows and separate indexes run on the workgroup tiers (they carry
     // the margin re-check, resp. the greedy phase)
-    const int start_tier = prec == VJ_PREC_BF16 || ix.separate ? std::max(1, (int)p.start_tier)
-                                                               : (int)p.start_tier;
+    const int start_tier = prec == VJ_PREC_BF16 || prec == VJ_PREC_FP8 || ix.separate
+                               ? std::max(1, (int)p.start_tier)
+                               : (int)p.start_tier;
     const int beam = (hyb != VJ_HYB_OFF) ? p.hybrid_beam : 0;
     VJ_CHECK(beam <= 256, VJ_ERR_UNSUPPORTED, "hybrid_beam must be <= 256");
 
@@ -1153,6 +1169,7 @@ vj_status vj_build_separate_index(const float *Q, int64_t nq, const float *X, in
     launch_edge_lengths(ix.vec.as<float>(), ix.dp, ix.adj.as<int32_t>(), ix.N, ix.R,
                         ix.elen.as<float>(), s);
     if (p.copies & 1) ensure_bf16(ix, s);
+    if (p.copies & 2) ensure_f8(ix, s);
     if (p.build_mst) compute_mst(ix, s);
     VJ_HIP(hipStreamSynchronize(s));
     *out = h.release();
@@ -1182,6 +1199,7 @@ vj_status vj_build_merged_index(const float *Q, int64_t nq, const float *X, int6
     init_vectors(ix, Q, X, s);
     build_graph(ix, (int)std::min<int64_t>(kc, ix.N - 1), s);
     if (p.copies & 1) ensure_bf16(ix, s);
+    if (p.copies & 2) ensure_f8(ix, s);
     if (p.build_mst) compute_mst(ix, s);
     VJ_HIP(hipStreamSynchronize(s));
     *out = h.release();
@@ -1767,6 +1785,7 @@ bool launch_join(const JoinLaunch &L, hipStream_t s) {
     switch (L.prec) {
     case VJ_PREC_FP32: return launch_join_f32(L, s);
     case VJ_PREC_U8: return launch_join_u8(L, s);
+    case VJ_PREC_FP8: return launch_join_f8(L, s);
     case VJ_PREC_BF16: return launch_join_bf16(L, s);
     default: return false;
     }

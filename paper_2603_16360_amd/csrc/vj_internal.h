@@ -81,6 +81,19 @@ struct DevBuf {
     template <typename T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Element tag of fp8 (OCP e4m3) rows: one byte per value, scaled per row.
+struct f8e4m3 {
+    uint8_t bits;
+};
+
+// value of an OCP e4m3 code (normal: exponent field + 120 into the fp32
+// exponent; subnormal: m 2^-9)
+__device__ __forceinline__ float f8_value(uint32_t b) {
+    const uint32_t em = b & 0x7fu;
+    const float f = em >= 8u ? __uint_as_float((em << 20) + 0x3C000000u) : (float)em * 0.001953125f;
+    return (b & 0x80u) ? -f : f;
+}
+
 // Padded row widths the kernels are compiled for (elements).
 int padded_dim(int d);
 
@@ -132,6 +145,8 @@ struct Index {
     DevBuf vec;      // float [N][dp], zero padded
     DevBuf vec_u8;   // uint8 [N][dp] (integer_u8 only)
     DevBuf vec_bf16; // bf16 [N][dp] (optional)
+    DevBuf vec_f8;   // fp8 e4m3 codes [N][dp] (optional): x~ = scale * decode(code)
+    DevBuf f8meta;   // float2 [N]: (power-of-two row scale, bound on |x - x~| rounded up)
     DevBuf adj;      // int32 [N][R], -1 padded
     DevBuf elen;     // float [N][R] L2 edge lengths, +inf padded
     DevBuf parent;   // int32 [nq] MST parent node id (-1: entry)
@@ -188,6 +203,7 @@ struct JoinArgs {
     int32_t R, dp, entry, metric;
     float eps, eps2;          // L2 compares the squared distance with eps2
     float bf_u;               // bf16 rows: bound on |x - bf16(x)| / |bf16(x)| (0: exact copy)
+    const float2 *f8meta;     // fp8 rows: per row (scale, bound on |x - x~|)
     unsigned long long *nrecheck;  // bf16 rows: candidates re-decided from fp32 rows
     int32_t ws, hyb, beam, conv;
     int32_t merged;           // 1 merged index; 0 separate indexes (adj rows < nx: data graph)
@@ -237,6 +253,7 @@ bool launch_join(const JoinLaunch &L, hipStream_t s);
 bool launch_join_f32(const JoinLaunch &L, hipStream_t s);
 bool launch_join_u8(const JoinLaunch &L, hipStream_t s);
 bool launch_join_bf16(const JoinLaunch &L, hipStream_t s);
+bool launch_join_f8(const JoinLaunch &L, hipStream_t s);
 int num_cus();
 
 // edge lengths of every adjacency entry (L2)
@@ -248,6 +265,11 @@ void launch_pad_rows(const float *src, int64_t rows, int d, float *dst, int dp,
 // u8 / bf16 copies; flag[0] |= 1 if some value is not an integer in [0,255]
 void launch_quantize(const float *vec, int64_t rows, int dp, uint8_t *u8, uint16_t *bf16,
                      int32_t *flag, hipStream_t s);
+// fp8 e4m3 copy: per row a power-of-two scale s >= max|x| / 448, codes of
+// x / s rounded to nearest even (saturating), meta = (s, |x - s decode|
+// computed in fp64 and rounded up)
+void launch_quantize_f8(const float *vec, int64_t rows, int dp, uint8_t *codes, float2 *meta,
+                        hipStream_t s);
 
 // pairs export
 void export_pairs(const Pairs &r, int32_t *qx, float *dist, bool sorted, hipStream_t s);
