@@ -122,6 +122,13 @@ typedef struct {
                                Results are the same either way.  Merged indexes only. */
     int32_t greedy_beam;    /* separate indexes: bound on the best-first greedy queue
                                (cfg.greedy_beam_size, default 256, at most 256) */
+    int32_t persistent;     /* 0 (default, and the only value accepted at present: others
+                               return VJ_ERR_UNSUPPORTED): one workgroup per query, one launch
+                               per MST level in SOFT / HARD mode.  1 would run the workgroup
+                               tier as ONE launch of resident workgroups claiming queries in
+                               processing order, children waiting on the device for their MST
+                               parent; it is switched off while a GPU fault seen with it is
+                               investigated. */
 } vj_join_params;
 
 void vj_default_build_params(vj_build_params *p);

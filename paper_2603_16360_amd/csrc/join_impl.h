@@ -601,6 +601,7 @@ template <int W> struct CoopShared {
     int head, busy;             // BFS without rounds: next unclaimed entry, waves holding work
     int s_tail, s_hc, s_abort;  // snapshot written by wave 0 between barriers
     int hyb, ood;               // CheckHybrid decision of wave 0
+    int wait;                   // persistent launch: 1 parent published, 2 deferred
     int ndist[W], nexp[W];
     float bk[W];
     int bi[W];
@@ -822,7 +823,7 @@ __device__ __forceinline__ void coop_batch(const JoinArgs &a, const WaveMem &m, 
 // its stats row, and the caller re-runs it on larger tables.
 // HYB: the kernel may run hybrid queries (an out-range queue); without it
 // the hybrid code is compiled out
-template <typename T, int DP, int W, int PGC, bool HYB>
+template <typename T, int DP, int W, int PGC, bool HYB, bool PERSIST = false>
 __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem &m,
                                                CoopShared<W> &sh, int heap_cap, int k,
                                                const int32_t *qlist, const int32_t *qpos,
@@ -847,7 +848,15 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
     const int32_t q = (int32_t)(a.nx + qi);
     if (a.hyb == VJ_HYB_BUDGET && a.budget[pos] < 0) {
         if (threadIdx.x < 8) st[threadIdx.x] = threadIdx.x == 7 ? 2 : 0;
-        if (threadIdx.x == 0 && a.ws == VJ_WS_SOFT) a.cache[qi] = -1;
+        if (threadIdx.x == 0) {
+            if (a.ws == VJ_WS_SOFT) a.cache[qi] = -1;
+            if (a.ws == VJ_WS_HARD) a.segn[qi] = 0;
+            if (PERSIST && a.done != nullptr && (a.ws == VJ_WS_SOFT || a.ws == VJ_WS_HARD)) {
+                __threadfence();
+                __hip_atomic_store(&a.done[qi], (int32_t)a.gen, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         return false;
     }
 
@@ -874,6 +883,7 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
         sh.tail = 0; sh.hc = 0; sh.nvis = 0; sh.abort = 0;
         sh.hyb = 0; sh.ood = 0;
         sh.head = 0; sh.busy = W;
+        sh.wait = 0;
     }
     __syncthreads();
 
@@ -899,6 +909,31 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
         const int32_t par = a.parent[qi];
         if (par >= a.nx && par < a.nx + a.nq && a.inb[par - a.nx] == (int32_t)a.gen) {
             const int pq = par - (int32_t)a.nx;
+            if (PERSIST && a.done != nullptr) {
+                // persistent launch: the parent's slot comes earlier in the
+                // list, so a resident workgroup holds it; wait (bounded) for
+                // its stamp.  A deferred parent defers this query as well.
+                // (relaxed polls: an acquire per poll would invalidate the
+                // XCD's L2 each time; one fence follows the stamp)
+                if (threadIdx.x == 0) {
+                    int st = 0, spin = 0;
+                    for (;;) {
+                        const int d = __hip_atomic_load(&a.done[pq], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+                        if (d == (int32_t)a.gen) { st = 1; break; }
+                        if (d == ((int32_t)a.gen | kDeferred)) { st = 2; break; }
+                        if (++spin > (1 << 22)) { st = 2; atomicOr(a.err, 256); break; }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                    sh.wait = st;
+                }
+                __syncthreads();
+                if (sh.wait == 2) {
+                    if (threadIdx.x < 8) st[threadIdx.x] = threadIdx.x == 7 ? 4 : 0;
+                    return true;  // deferred: straight to the overflow list
+                }
+                __threadfence();
+            }
             if (a.ws == VJ_WS_SOFT) {
                 pcache = uni(a.cache[pq]);
             } else {
@@ -914,7 +949,10 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
     // visited set and the in-range set after this phase are the same as
     // with seeds first, then the probe.  CheckHybrid follows on wave 0; the
     // first round's barriers publish it.
-    const bool separate = a.merged == 0;
+    // separate indexes launch the kernels with an out-range queue (HYB): the
+    // greedy phase keeps its queue there; the BFS-only kernels compile it out
+    const bool separate = HYB && a.merged == 0;
+    if constexpr (HYB) {
     if (separate) {
         // ---- separate indexes: seeds {s} + the soft cache + the parent's
         // in-range list (hard, chunks of 64) on wave 0, every visited node
@@ -996,7 +1034,9 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
                 sh.hyb = a.hyb == VJ_HYB_FORCE || (a.hyb == VJ_HYB_BUDGET && a.budget[pos] > 0);
             }
         }
-    } else if (wib == 0) {
+    }
+    }
+    if (!separate && wib == 0) {
         const int32_t nbq = lane < R ? a.adj[(size_t)q * R + lane] : -1;
         int32_t v = nbq;
         if (R <= 62) {
@@ -1287,6 +1327,15 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
         st[6] = lds_load(&sh.nvis);
         st[7] = flags;
     }
+    if (PERSIST && a.done != nullptr && (a.ws == VJ_WS_SOFT || a.ws == VJ_WS_HARD)) {
+        // publish: every thread's pair writes, then the cache / segment, then
+        // the stamp (release at device scope)
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&a.done[qi], (int32_t)a.gen, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
     return false;
 }
 
@@ -1314,10 +1363,14 @@ __device__ __forceinline__ void use_global(WaveMem &m, const GlobalTables &g, si
 // and LIST in-range entries in LDS.  A query that outgrows them takes a free
 // region of global tables (if any is left) and runs again in this launch;
 // otherwise, or if it outgrows those too, its slot goes to the overflow list.
-template <typename T, int DP, bool HYB, int HS, int LIST, int W, int PGC, int MINW>
+// claim: persistent launch -- each workgroup claims slots in list order from
+// the counter until they run out (null: one workgroup per slot).
+template <typename T, int DP, bool HYB, int HS, int LIST, int W, int PGC, int MINW,
+          bool PERSIST = false>
 __global__ void __launch_bounds__(64 * W, MINW)
 k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t *qpos, int k0,
-            int k1, const int32_t *cnt_dev, GlobalTables g, int32_t *ovf, int32_t *ovf_count) {
+            int k1, const int32_t *cnt_dev, GlobalTables g, int32_t *ovf, int32_t *ovf_count,
+            int32_t *claim) {
     constexpr int HC = HYB ? kBeamMax + 64 * W : 1;
     __shared__ int32_t sh_hash[HS];
     __shared__ int32_t sh_il[LIST];
@@ -1329,8 +1382,8 @@ k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t
     __shared__ int sh_region;
     __shared__ int32_t sh_aux[kIsBf16<T> ? W : 1][64];
     __shared__ float sh_auxf[kIsBf16<T> ? W : 1][64];
-    const int k = k0 + (int)blockIdx.x;
-    if (k >= k1 || (cnt_dev != nullptr && k >= k0 + *cnt_dev)) return;
+    __shared__ int sh_k;
+    const int kend = cnt_dev != nullptr ? min(k1, k0 + *cnt_dev) : k1;
     const JoinArgs &a = *pa;
     WaveMem m;
     m.hash = sh_hash;
@@ -1344,16 +1397,50 @@ k_join_coop(const JoinArgs *__restrict__ pa, const int32_t *qlist, const int32_t
     m.hi = sh_hi;
     m.aux = sh_aux[kIsBf16<T> ? threadIdx.x >> 6 : 0];
     m.auxf = sh_auxf[kIsBf16<T> ? threadIdx.x >> 6 : 0];
-    if (!run_query_coop<T, DP, W, PGC, HYB>(a, m, sh, HC, k, qlist, qpos, 1)) return;
-    if (threadIdx.x == 0) sh_region = g.cap > 0 ? atomicAdd(g.next, 1) : 0;
-    __syncthreads();
-    const int r = sh_region;
-    bool again = true;
-    if (r < g.cap) {
-        use_global(m, g, (size_t)r);
-        again = run_query_coop<T, DP, W, PGC, HYB>(a, m, sh, HC, k, qlist, qpos, 1 | 8);
+    if constexpr (!PERSIST) {
+        // one workgroup per slot
+        const int k = k0 + (int)blockIdx.x;
+        if (k >= kend) return;
+        if (!run_query_coop<T, DP, W, PGC, HYB>(a, m, sh, HC, k, qlist, qpos, 1)) return;
+        if (threadIdx.x == 0) sh_region = g.cap > 0 ? atomicAdd(g.next, 1) : 0;
+        __syncthreads();
+        const int r = sh_region;
+        bool again = true;
+        if (r < g.cap) {
+            use_global(m, g, (size_t)r);
+            again = run_query_coop<T, DP, W, PGC, HYB>(a, m, sh, HC, k, qlist, qpos, 1 | 8);
+        }
+        if (again && threadIdx.x == 0) ovf[atomicAdd(ovf_count, 1)] = k;
+    } else {
+        // persistent: claim slots in list order until they run out
+        const WaveMem lds = m;
+        for (;;) {
+            if (threadIdx.x == 0) sh_k = k0 + atomicAdd(claim, 1);
+            __syncthreads();
+            const int k = sh_k;
+            __syncthreads();  // every thread read sh_k before the next claim
+            if (k >= kend) break;
+            m = lds;
+            if (!run_query_coop<T, DP, W, PGC, HYB, true>(a, m, sh, HC, k, qlist, qpos, 1)) continue;
+            // a deferred query (its parent was deferred) takes no region
+            const bool deferred = a.done != nullptr && sh.wait == 2;
+            if (threadIdx.x == 0) sh_region = g.cap > 0 && !deferred ? atomicAdd(g.next, 1) : g.cap;
+            __syncthreads();
+            const int r = sh_region;
+            bool again = true;
+            if (r < g.cap) {
+                use_global(m, g, (size_t)r);
+                again = run_query_coop<T, DP, W, PGC, HYB, true>(a, m, sh, HC, k, qlist, qpos, 1 | 8);
+            }
+            if (again && threadIdx.x == 0) {
+                ovf[atomicAdd(ovf_count, 1)] = k;
+                if (a.done != nullptr && (a.ws == VJ_WS_SOFT || a.ws == VJ_WS_HARD))
+                    __hip_atomic_store(&a.done[uni(qlist[k])], (int32_t)a.gen | kDeferred,
+                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();  // the next query clears the tables
+        }
     }
-    if (again && threadIdx.x == 0) ovf[atomicAdd(ovf_count, 1)] = k;
 }
 
 // cooperative tier on global tables: one query at a time per workgroup of W
@@ -1420,23 +1507,40 @@ void launch_tier(const JoinLaunch &L, hipStream_t s) {
         // grid: one workgroup per slot, or L.grid workgroups looping over
         // the slots (global tables: one region per workgroup)
         const unsigned blocks = (unsigned)(L.grid > 0 ? L.grid : L.count);
+        // tier 1: one workgroup per slot, or a persistent grid claiming slots
+        const unsigned t1grid = (unsigned)(L.claim != nullptr && L.grid > 0 ? L.grid : L.count);
         if (L.tier == 1 && L.coop_small)
+            // one workgroup per slot (the small tables have no persistent form)
             hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 4096, 1024, kWaves, 12, (DP <= 256 ? 4 : 1)>),
                                dim3((unsigned)L.count), dim3(64 * kWaves), 0, s, L.args, L.qlist,
-                               L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count);
-        else if (L.tier == 1) {
+                               L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count, nullptr);
+        else if (L.tier == 1 && L.claim != nullptr) {
+            // persistent: resident workgroups claim the slots in order
+            if constexpr (kIsBf16<T> && DP <= 256)
+                hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 7680, 768, kWaves, 4, 4, true>),
+                                   dim3(t1grid), dim3(64 * kWaves), 0, s, L.args,
+                                   L.qlist, L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count,
+                                   L.claim);
+            else
+                hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 8192, 768, kWaves, 12, (DP <= 256 ? 4 : 1), true>),
+                                   dim3(t1grid), dim3(64 * kWaves), 0, s, L.args,
+                                   L.qlist, L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count,
+                                   L.claim);
+        } else if (L.tier == 1) {
             if constexpr (kIsBf16<T> && DP <= 256)
                 // bf16 rows: the re-check buffers take 2 KB of LDS and the
                 // margin registers, so 7,680 visited slots and 4 loads per
                 // lane in flight keep four workgroups per CU (a row takes at
                 // most 4 loads per lane up to 256 wide)
                 hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 7680, 768, kWaves, 4, 4>),
-                                   dim3((unsigned)L.count), dim3(64 * kWaves), 0, s, L.args,
-                                   L.qlist, L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count);
+                                   dim3(t1grid), dim3(64 * kWaves), 0, s, L.args,
+                                   L.qlist, L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count,
+                                   L.claim);
             else
                 hipLaunchKernelGGL((k_join_coop<T, DP, HYB, 8192, 768, kWaves, 12, (DP <= 256 ? 4 : 1)>),
-                                   dim3((unsigned)L.count), dim3(64 * kWaves), 0, s, L.args,
-                                   L.qlist, L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count);
+                                   dim3(t1grid), dim3(64 * kWaves), 0, s, L.args,
+                                   L.qlist, L.qpos, k0, k1, L.count_dev, g, L.ovf, L.ovf_count,
+                                   L.claim);
         }
         else
             hipLaunchKernelGGL((k_join_coop_global<T, DP, HYB, kWaves, 16>), dim3(blocks),

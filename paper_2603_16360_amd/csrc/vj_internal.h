@@ -165,6 +165,7 @@ struct Index {
     DevBuf inb;      // int32 [nq] generation stamp: query is part of the current call
     DevBuf seg;      // int64 [nq] offset of the query's pairs in the call's output
     DevBuf segn;     // int32 [nq] number of pairs of the query
+    DevBuf done;     // int32 [nq] persistent soft / hard joins: publication stamp (gen)
     DevBuf ws_gh, ws_gil, ws_gild;  // global tables of the join (kept between calls)
     JoinWorkspace jw;
     // attached difficulty predictor (VJ_HYB_LEARNED); not owned
@@ -224,7 +225,12 @@ struct JoinArgs {
     int64_t cap;
     unsigned long long *out_count;
     int32_t *stats;           // [n][8] by caller position
-    int32_t *err;             // bit flags: 8 query id out of range, 16 probe past the table, 32 list entry not a data id, 64 tiers exhausted (batch steps), 128 a wave waited past its bound
+    int32_t *err;             // bit flags: 8 query id out of range, 16 probe past the table, 32 list entry not a data id, 64 tiers exhausted (batch steps), 128 a wave waited past its bound, 256 a parent wait passed its bound
+    // persistent launches of soft / hard work sharing: done[qi] == gen once
+    // query qi's cache (soft) or pairs (hard) are published, gen | kDeferred
+    // when it was deferred to a later launch; null: parents ran in an
+    // earlier launch (no waiting)
+    int32_t *done;
 };
 
 // One launch over a contiguous piece of the processing list.
@@ -247,7 +253,11 @@ struct JoinLaunch {
     const int32_t *count_dev; // tiers 1-2: the slot count on the device, at most `count` (null: count)
     const int32_t *slots;     // tier 2: entry k is slot slots[k] of qlist (null: slot k)
     int grid;                 // tier 2: workgroups looping over the slots (0: one per slot)
+    int32_t *claim;           // tier 1: persistent launch of L.grid workgroups that claim the
+                              // slots in order from this counter (null: one workgroup per slot)
 };
+
+constexpr int32_t kDeferred = 1 << 30;  // done[] flag of a query deferred to a later launch
 
 bool launch_join(const JoinLaunch &L, hipStream_t s);
 bool launch_join_f32(const JoinLaunch &L, hipStream_t s);

@@ -50,7 +50,8 @@ class vj_join_params(C.Structure):
                 ("ood_ratio", C.c_float), ("precision", C.c_int32),
                 ("budget", C.c_void_p), ("start_tier", C.c_int32),
                 ("coop_tables", C.c_int32), ("pair_capacity", C.c_int64),
-                ("dense_first", C.c_int32), ("greedy_beam", C.c_int32)]
+                ("dense_first", C.c_int32), ("greedy_beam", C.c_int32),
+                ("persistent", C.c_int32)]
 
 
 _vp, _i64, _i32, _f32 = C.c_void_p, C.c_int64, C.c_int32, C.c_float
@@ -258,7 +259,7 @@ def vj_index_load(path: str) -> Index:
 
 def join_params(work_sharing="self", hybrid="off", hybrid_beam=256, conv_threshold=10,
                 ood_ratio=1.5, precision="fp32", budget=None, start_tier=1, coop_tables=0,
-                pair_capacity=0, dense_first=1, greedy_beam=256):
+                pair_capacity=0, dense_first=1, greedy_beam=256, persistent=0):
     p = vj_join_params()
     _lib.vj_default_join_params(C.byref(p))
     p.work_sharing = WORK_SHARING[work_sharing]
@@ -273,6 +274,7 @@ def join_params(work_sharing="self", hybrid="off", hybrid_beam=256, conv_thresho
     p.pair_capacity = pair_capacity
     p.dense_first = dense_first
     p.greedy_beam = greedy_beam
+    p.persistent = persistent
     return p
 
 
