@@ -84,6 +84,8 @@ def _declare(L):
                           C.c_void_p, _i32p, _i64, _dbl, C.POINTER(_Cfg), C.c_void_p,
                           C.c_void_p, C.c_void_p, C.c_void_p,
                           _i64, _i32p, _i32p, _f64p, _i32p]
+    L.or_insert_batch.restype = _i64
+    L.or_insert_batch.argtypes = [_f32p, _i64, _i64, _int, _int, _int, _i32p, _f64p, C.c_int32]
     L.or_nnmap.restype = None
     L.or_nnmap.argtypes = [_f32p, _i64, _i64, _int, _int, _i32p, _int, _dbl, _i32p, _f64p,
                            np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")]
@@ -237,6 +239,22 @@ def build_separate(Q, X, R: int, Kc: int | None = None):
     nx = X.shape[0]
     adjq = np.where(gq.adj >= 0, gq.adj + nx, -1).astype(np.int32)
     return np.ascontiguousarray(np.concatenate([gx.adj, adjq])), gx.entry, gx, gq
+
+
+def insert_batch(Q_old, X, adj, entry: int, Q_new, R: int | None = None, Kc: int | None = None):
+    """Incremental insertion of the query batch Q_new into the merged graph
+    adj over [X; Q_old] (see or_insert_batch).  Returns the Graph over
+    [X; Q_old; Q_new] (entry unchanged)."""
+    V = np.ascontiguousarray(np.concatenate([_f32(X), _f32(Q_old), _f32(Q_new)], axis=0))
+    R = R or adj.shape[1]
+    Kc = Kc or 2 * R
+    n_old = X.shape[0] + Q_old.shape[0]
+    n = V.shape[0]
+    out = np.full((n, R), -1, np.int32)
+    out[:n_old] = adj
+    elen = np.empty((n, R), np.float64)
+    rep = lib().or_insert_batch(V, n_old, n - n_old, V.shape[1], R, Kc, out, elen, entry)
+    return Graph(out, elen, int(entry), int(rep))
 
 
 def mst_parents(Q, X, adj, entry: int):

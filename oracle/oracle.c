@@ -1147,3 +1147,128 @@ void or_nnmap(const float *V, int64_t nx, int64_t nq, int d, int metric, const i
         ood[i] = c2 > 0 && d1 / (s2 / (double)c2) > ratio;
     }
 }
+
+/* ------------------------------------------------------------------------
+ * Incremental insertion of a batch of query nodes into a merged graph
+ * (Section 4.3, index maintenance: a node update needs only its set label;
+ * existing update mechanisms apply).  Reading: the new nodes get the
+ * build's recipe -- exact kNN (K = Kc) among ALL nodes, old and new, RNG
+ * prune to R -- and their kept edges are offered as reverse edges; a node v
+ * that receives offers gets cand(v) = its current row (old nodes) or its
+ * pruned list (new nodes) plus the offers, kept whole if |cand| <= R, else
+ * RNG-pruned; rows without offers stay as they are.  Then the build's
+ * connectivity repair from the (unchanged) entry, and the edge lengths.
+ * V holds all n_old + n_new rows; adj [n_old + n_new][R] holds the old rows
+ * on entry (the new rows are written).  Returns the repair edges added.
+ * ---------------------------------------------------------------------- */
+int64_t or_insert_batch(const float *V, int64_t n_old, int64_t n_new, int d, int R, int Kc,
+                        int32_t *adj, double *elen, int32_t s)
+{
+    int64_t n = n_old + n_new;
+    int32_t *knn = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_new * Kc + 1));
+    double *kd = (double *)malloc(sizeof(double) * (size_t)(n_new * Kc + 1));
+    int32_t *fwd = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_new * R + 1));
+    int *fdeg = (int *)calloc((size_t)n_new + 1, sizeof(int));
+    /* exact kNN of each new node among all nodes (self excluded) */
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n_new; ++i) {
+        int64_t u = n_old + i;
+        int32_t *ri = knn + i * Kc;
+        double *rd = kd + i * Kc;
+        int cnt = 0;
+        for (int64_t v = 0; v < n; ++v) {
+            if (v == u) continue;
+            double t = l2_64(V + u * d, V + v * d, d);
+            if (cnt == Kc && !lt_pair(t, (int32_t)v, rd[Kc - 1], ri[Kc - 1])) continue;
+            int p = cnt < Kc ? cnt++ : Kc - 1;
+            while (p > 0 && lt_pair(t, (int32_t)v, rd[p - 1], ri[p - 1])) {
+                rd[p] = rd[p - 1]; ri[p] = ri[p - 1]; --p;
+            }
+            rd[p] = t; ri[p] = (int32_t)v;
+        }
+        for (int p = cnt; p < Kc; ++p) { ri[p] = -1; rd[p] = INFINITY; }
+        fdeg[i] = or_rng_prune(V, d, u, ri, rd, Kc, R, fwd + i * R);
+    }
+    /* offers: v gets u for every kept (u, v) of a new node u */
+    int64_t *ocnt = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < n_new; ++i)
+        for (int j = 0; j < fdeg[i]; ++j) ocnt[fwd[i * R + j] + 1]++;
+    for (int64_t v = 0; v < n; ++v) ocnt[v + 1] += ocnt[v];
+    int32_t *off = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ocnt[n] + 1));
+    int64_t *opos = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t v = 0; v < n; ++v) opos[v] = ocnt[v];
+    for (int64_t i = 0; i < n_new; ++i)
+        for (int j = 0; j < fdeg[i]; ++j) off[opos[fwd[i * R + j]]++] = (int32_t)(n_old + i);
+    /* new rows start as their pruned lists */
+    for (int64_t i = 0; i < n_new; ++i) {
+        int32_t *row = adj + (n_old + i) * R;
+        for (int j = 0; j < R; ++j) row[j] = j < fdeg[i] ? fwd[i * R + j] : -1;
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t no = ocnt[v + 1] - ocnt[v];
+        if (no == 0) continue;
+        int32_t *row = adj + v * R;
+        int deg = row_degree(row, R);
+        or_cand *c = (or_cand *)malloc(sizeof(or_cand) * (size_t)(deg + no + 1));
+        int m = 0;
+        for (int j = 0; j < deg; ++j) c[m++].id = row[j];
+        for (int64_t t = ocnt[v]; t < ocnt[v + 1]; ++t) {
+            int32_t u = off[t];
+            int dup = 0;
+            for (int j = 0; j < m; ++j) if (c[j].id == u) { dup = 1; break; }
+            if (!dup) c[m++].id = u;
+        }
+        for (int j = 0; j < m; ++j) c[j].d = l2_64(V + v * d, V + (int64_t)c[j].id * d, d);
+        qsort(c, (size_t)m, sizeof(or_cand), cmp_cand);
+        for (int j = 0; j < R; ++j) row[j] = -1;
+        if (m <= R) {
+            for (int j = 0; j < m; ++j) row[j] = c[j].id;
+        } else {
+            int32_t *ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)m);
+            double *cdd = (double *)malloc(sizeof(double) * (size_t)m);
+            for (int j = 0; j < m; ++j) { ci[j] = c[j].id; cdd[j] = c[j].d; }
+            or_rng_prune(V, d, v, ci, cdd, m, R, row);
+            free(ci); free(cdd);
+        }
+        free(c);
+    }
+    /* connectivity repair from s, as in the build */
+    uint8_t *reach = (uint8_t *)malloc((size_t)n);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t added = 0;
+    for (;;) {
+        bfs_reach(adj, n, R, s, reach, queue);
+        int64_t w = -1;
+        for (int64_t u = 0; u < n; ++u) if (!reach[u]) { w = u; break; }
+        if (w < 0) break;
+        int64_t pf = -1, pa = -1;
+        double df = INFINITY, da = INFINITY;
+        for (int64_t p = 0; p < n; ++p) {
+            if (!reach[p]) continue;
+            double t = l2_64(V + p * d, V + w * d, d);
+            if (lt_pair(t, (int32_t)p, da, (int32_t)pa)) { da = t; pa = p; }
+            if (row_degree(adj + p * R, R) < R && lt_pair(t, (int32_t)p, df, (int32_t)pf)) {
+                df = t; pf = p;
+            }
+        }
+        if (pf >= 0) {
+            int32_t *row = adj + pf * R;
+            row[row_degree(row, R)] = (int32_t)w;
+            sort_row(V, d, pf, row, R);
+        } else {
+            int32_t *row = adj + pa * R;
+            row[R - 1] = (int32_t)w;
+            sort_row(V, d, pa, row, R);
+        }
+        ++added;
+    }
+    for (int64_t u = 0; u < n; ++u)
+        for (int j = 0; j < R; ++j) {
+            int32_t v = adj[u * R + j];
+            elen[u * R + j] = v >= 0 ? l2_64(V + u * d, V + (int64_t)v * d, d) : INFINITY;
+        }
+    free(knn); free(kd); free(fwd); free(fdeg); free(ocnt); free(off); free(opos);
+    free(reach); free(queue);
+    return added;
+}
