@@ -188,6 +188,26 @@ vj_status vj_index_from_separate_graphs(const float *Q, int64_t nq, const float 
                                         void *stream, vj_index **out);
 
 /*
+ * Incremental insertion of a query batch into a merged index (Section 4.3:
+ * updating a merged graph needs only the set label of each node, and the
+ * graph's own update rules apply).  Q: device fp32 [n][d] row-major (d of
+ * the index), copied; the new queries get query indexes nq_old .. nq_old+n-1
+ * (node ids nx + nq_old + i); existing ids do not change.  The update:
+ * exact K_cand nearest neighbours of each new node among all nodes (ties by
+ * smaller id), RNG prune to R; each kept edge (u, v) is offered to v as a
+ * reverse edge; every node that receives offers takes its current row (a
+ * new node: its pruned list) plus the offers, whole if they fit in R, else
+ * RNG-pruned; rows without offers do not change; then the build's
+ * connectivity repair from the (unchanged) entry.  K_cand <= 0: min(2R,
+ * 112), the build's default.  The index's MST, if it has one, and its
+ * low-precision copies are recomputed.  n == 0 is a no-op.  Separate
+ * indexes: VJ_ERR_UNSUPPORTED.  Must not overlap a join on the same index.
+ * On an error after the argument checks the index keeps its old graph.
+ */
+vj_status vj_index_insert_queries(vj_index *idx, const float *Q, int64_t n, int32_t K_cand,
+                                  void *stream);
+
+/*
  * Query-data role switch of a merged index (Appendix E: the join is
  * symmetric, and for large thresholds iterating over the larger set while
  * traversing the smaller set's part of the graph avoids most random

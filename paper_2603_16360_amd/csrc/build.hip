@@ -38,20 +38,22 @@ using brow::g1b;
 // a buffer [K best | pending] in global memory; an element enters the buffer
 // when its key (|x|^2 - 2<u,x>, same order as |u-x|^2) is <= the row's
 // current K-th key.  After a step, rows with > K + 128 entries are sorted
-// and cut back to K.
+// and cut back to K.  The rows are [rb, rb + M) of the N (buffers indexed
+// from rb), the columns all N.
 constexpr int kKc = 128;          // dimensions per staged chunk
 constexpr int kLdsRow = kKc + 8;  // bf16 per staged row
 
 template <int NSPLIT>
 __global__ void __launch_bounds__(256)
 k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2, int K,
-      float *bkey, int32_t *bid) {
+      float *bkey, int32_t *bid, int64_t rb, int64_t M) {
     __shared__ float s_tau[4][16];
     __shared__ int s_cnt[4][16];
     __shared__ __attribute__((aligned(16))) uint16_t sb_hi[128 * kLdsRow];
     __shared__ __attribute__((aligned(16))) uint16_t sb_lo[NSPLIT == 3 ? 128 * kLdsRow : 8];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t r0 = (int64_t)blockIdx.x * 64 + w * 16;
+    const int64_t r0 = rb + (int64_t)blockIdx.x * 64 + w * 16;
+    const int64_t rend = rb + M;
     if (lane < 16) { s_tau[w][lane] = INFINITY; s_cnt[w][lane] = 0; }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -63,18 +65,18 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int e = j * 64 + lane;
-            const bool ok = e < c && row < N;
-            key[j] = ok ? bkey[row * kKnnCap + e] : INFINITY;
-            id[j] = ok ? bid[row * kKnnCap + e] : 0x7fffffff;
+            const bool ok = e < c && row < rend;
+            key[j] = ok ? bkey[(row - rb) * kKnnCap + e] : INFINITY;
+            id[j] = ok ? bid[(row - rb) * kKnnCap + e] : 0x7fffffff;
         }
         mt::wave_sort<8>(key, id, lane);
         const int keep = min(c, K);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int e = j * 64 + lane;
-            if (e < K && row < N) {
-                bkey[row * kKnnCap + e] = e < keep ? key[j] : INFINITY;
-                bid[row * kKnnCap + e] = e < keep ? id[j] : -1;
+            if (e < K && row < rend) {
+                bkey[(row - rb) * kKnnCap + e] = e < keep ? key[j] : INFINITY;
+                bid[(row - rb) * kKnnCap + e] = e < keep ? id[j] : -1;
             }
         }
         // K-th key (element K-1) is register (K-1)/64 of lane (K-1)%64
@@ -143,7 +145,8 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
         // the filter in 32-bit indices (N < 2^31) with each row's threshold
         // read once per tile: the same keys and decisions as the row-wise loop
         {
-            const int n32 = (int)N, row0 = (int)r0 + (lane >> 4) * 4;
+            const int n32 = (int)N, re32 = (int)rend, rb32 = (int)rb;
+            const int row0 = (int)r0 + (lane >> 4) * 4;
             float tau[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) tau[i] = s_tau[w][(lane >> 4) * 4 + i];
@@ -155,11 +158,11 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
                 for (int i = 0; i < 4; ++i) {
                     const int row = row0 + i;
                     const float key = nc - 2.f * acc[ct][i];
-                    if (key <= tau[i] && row < n32 && col < n32 && col != row) {
+                    if (key <= tau[i] && row < re32 && col < n32 && col != row) {
                         const int at = atomicAdd(&s_cnt[w][(lane >> 4) * 4 + i], 1);
                         if (at < kKnnCap) {
-                            bkey[(int64_t)row * kKnnCap + at] = key;
-                            bid[(int64_t)row * kKnnCap + at] = col;
+                            bkey[(int64_t)(row - rb32) * kKnnCap + at] = key;
+                            bid[(int64_t)(row - rb32) * kKnnCap + at] = col;
                         }
                     }
                 }
@@ -180,13 +183,15 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
     for (int r = 0; r < 16; ++r) merge_row(r);
 }
 
-__global__ void k_scatter_rev(int64_t N, int R, const int32_t *fwd, const float *fwd_d2,
-                              const int64_t *roff, int32_t *rpos, int32_t *rid, float *rd2) {
+// reverse offers of the forward lists of rows [rb, rb + M) (fwd indexed from rb)
+__global__ void k_scatter_rev(int64_t M, int R, const int32_t *fwd, const float *fwd_d2,
+                              const int64_t *roff, int32_t *rpos, int32_t *rid, float *rd2,
+                              int64_t rb) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= N * R) return;
+    if (e >= M * R) return;
     const int32_t v = fwd[e];
     if (v < 0) return;
-    const int64_t u = e / R;
+    const int64_t u = rb + e / R;
     const int at = atomicAdd(&rpos[v], 1);
     rid[roff[v] + at] = (int32_t)u;
     rd2[roff[v] + at] = fwd_d2[e];
@@ -334,10 +339,14 @@ __global__ void k_attach(const float *vec, int dp, int32_t *adj, int R, int32_t 
 #define VJ_BUILD_WIDTHS(X) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 #define VJ_DECL(dp)                                                                         \
     void build_rows_##dp(const float *, int64_t, int, int, int, const int32_t *, int32_t *,  \
-                         float *, int32_t *, float *, int32_t *, int32_t *, hipStream_t);    \
+                         float *, int32_t *, float *, int32_t *, int32_t *, int64_t,         \
+                         int64_t, hipStream_t);                                              \
     void build_rev_##dp(const float *, int64_t, int, const int32_t *, const float *,         \
                         const int32_t *, const int64_t *, const int32_t *, const float *,    \
-                        int32_t *, hipStream_t);
+                        int32_t *, const int32_t *, hipStream_t);                            \
+    void build_gather_##dp(const float *, int, const int32_t *, const int32_t *,             \
+                           const int32_t *, int64_t, const int32_t *, int64_t, int32_t *,    \
+                           float *, int32_t *, hipStream_t);
 VJ_BUILD_WIDTHS(VJ_DECL)
 #undef VJ_DECL
 
@@ -345,23 +354,119 @@ namespace {
 
 void launch_rows(int dp, const float *vec, int64_t N, int R, int K, int Kc, const int32_t *bid,
                  int32_t *kid, float *kd2, int32_t *fwd, float *fwd_d2, int32_t *fdeg,
-                 int32_t *indeg, hipStream_t s) {
+                 int32_t *indeg, int64_t rb, int64_t M, hipStream_t s) {
     switch (dp) {
-#define VJ_CASE(w) case w: build_rows_##w(vec, N, R, K, Kc, bid, kid, kd2, fwd, fwd_d2, fdeg, indeg, s); return;
+#define VJ_CASE(w) case w: build_rows_##w(vec, N, R, K, Kc, bid, kid, kd2, fwd, fwd_d2, fdeg, indeg, rb, M, s); return;
         VJ_BUILD_WIDTHS(VJ_CASE)
 #undef VJ_CASE
     default: VJ_CHECK(false, VJ_ERR_UNSUPPORTED, "row width");
     }
 }
 
-void launch_rev(int dp, const float *vec, int64_t N, int R, const int32_t *fwd,
+void launch_rev(int dp, const float *vec, int64_t M, int R, const int32_t *fwd,
                 const float *fwd_d2, const int32_t *fdeg, const int64_t *roff,
-                const int32_t *rid, const float *rd2, int32_t *adj, hipStream_t s) {
+                const int32_t *rid, const float *rd2, int32_t *adj, const int32_t *rows,
+                hipStream_t s) {
     switch (dp) {
-#define VJ_CASE(w) case w: build_rev_##w(vec, N, R, fwd, fwd_d2, fdeg, roff, rid, rd2, adj, s); return;
+#define VJ_CASE(w) case w: build_rev_##w(vec, M, R, fwd, fwd_d2, fdeg, roff, rid, rd2, adj, rows, s); return;
         VJ_BUILD_WIDTHS(VJ_CASE)
 #undef VJ_CASE
     default: VJ_CHECK(false, VJ_ERR_UNSUPPORTED, "row width");
+    }
+}
+
+void launch_gather(int dp, const float *vec, int R, const int32_t *adj, const int32_t *fwd_new,
+                   const int32_t *fdeg_new, int64_t n_old, const int32_t *rows, int64_t M,
+                   int32_t *fwd, float *fwd_d2, int32_t *fdeg, hipStream_t s) {
+    switch (dp) {
+#define VJ_CASE(w) case w: build_gather_##w(vec, R, adj, fwd_new, fdeg_new, n_old, rows, M, fwd, fwd_d2, fdeg, s); return;
+        VJ_BUILD_WIDTHS(VJ_CASE)
+#undef VJ_CASE
+    default: VJ_CHECK(false, VJ_ERR_UNSUPPORTED, "row width");
+    }
+}
+
+// exact top-K candidate lists (ids in bid [M][kKnnCap], K of them) of rows
+// [rb, rb + M) of ix.vec among all ix.N rows, on MFMA tiles
+void knn_candidates(const Index &ix, int64_t rb, int64_t M, int K, DevBuf &bidb, hipStream_t s) {
+    const int64_t N = ix.N;
+    const int dp = ix.dp;
+    const float *vec = ix.vec.as<float>();
+    TileRows t;
+    const int Kp = ((dp + 31) / 32) * 32;
+    prepare_rows(vec, N, dp, Kp, true, t, s);
+    double e_dot, e_fin;
+    tile_error_bounds(t, t, 1, e_dot, e_fin);
+    const int nsplit = (e_dot == 0.0) ? 1 : 3;
+    DevBuf bkey((size_t)M * kKnnCap * sizeof(float));
+    bidb.alloc((size_t)M * kKnnCap * sizeof(int32_t));
+    if (nsplit == 3)
+        hipLaunchKernelGGL(k_knn<3>, dim3(g1b(M, 64)), dim3(256), 0, s, t.hi.as<uint16_t>(),
+                           t.lo.as<uint16_t>(), N, Kp, t.norm2.as<float>(), K, bkey.as<float>(),
+                           bidb.as<int32_t>(), rb, M);
+    else
+        hipLaunchKernelGGL(k_knn<1>, dim3(g1b(M, 64)), dim3(256), 0, s, t.hi.as<uint16_t>(),
+                           nullptr, N, Kp, t.norm2.as<float>(), K, bkey.as<float>(),
+                           bidb.as<int32_t>(), rb, M);
+    VJ_HIP(hipGetLastError());
+    VJ_HIP(hipStreamSynchronize(s));
+}
+
+// connectivity repair from the entry: the smallest unreachable node gets an
+// edge from its nearest reached node with a free slot (else that node's
+// longest edge is replaced), until every node is reached.  The rows changed
+// are appended to `touched` (if given).
+void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched) {
+    const int64_t N = ix.N;
+    const int R = ix.R, dp = ix.dp;
+    const float *vec = ix.vec.as<float>();
+    DevBuf seen((size_t)N * sizeof(int)), fa((size_t)N * sizeof(int32_t)),
+        fb((size_t)N * sizeof(int32_t)), misc(32);
+    int *seenp = seen.as<int>();
+    int32_t *misc_i = misc.as<int32_t>();
+    auto bfs_from = [&](int32_t start, bool reset) {
+        if (reset) VJ_HIP(hipMemsetAsync(seen.p, 0, seen.bytes, s));
+        int one = 1;
+        VJ_HIP(hipMemcpyAsync(seenp + start, &one, sizeof(int), hipMemcpyHostToDevice, s));
+        VJ_HIP(hipMemcpyAsync(fa.p, &start, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        int nf = 1;
+        int32_t *cur = fa.as<int32_t>(), *nxt = fb.as<int32_t>();
+        for (int64_t level = 0; nf > 0 && level <= N; ++level) {
+            VJ_HIP(hipMemsetAsync(misc_i, 0, sizeof(int), s));
+            hipLaunchKernelGGL(k_bfs_step, dim3(g1b((int64_t)nf * R, 256)), dim3(256), 0, s,
+                               ix.adj.as<int32_t>(), R, cur, nf, seenp, nxt, misc_i);
+            VJ_HIP(hipMemcpyAsync(&nf, misc_i, sizeof(int), hipMemcpyDeviceToHost, s));
+            VJ_HIP(hipStreamSynchronize(s));
+            std::swap(cur, nxt);
+        }
+    };
+    bfs_from(ix.entry, true);
+    const int64_t max_iter = std::min<int64_t>(N, 200000);
+    for (int64_t iter = 0;; ++iter) {
+        VJ_CHECK(iter <= max_iter, VJ_ERR_INTERNAL, "connectivity repair did not converge");
+        int first = 0x7fffffff;
+        VJ_HIP(hipMemcpyAsync(misc_i, &first, sizeof(int), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_first_unseen, dim3(g1b(N, 256)), dim3(256), 0, s, seenp, N, misc_i);
+        VJ_HIP(hipMemcpyAsync(&first, misc_i, sizeof(int), hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipStreamSynchronize(s));
+        if (first == 0x7fffffff) break;
+        unsigned long long init[2] = {~0ull, ~0ull}, got[2];
+        VJ_HIP(hipMemcpyAsync(misc.as<char>() + 8, init, 16, hipMemcpyHostToDevice, s));
+        unsigned long long *bests = reinterpret_cast<unsigned long long *>(misc.as<char>() + 8);
+        hipLaunchKernelGGL(k_nearest_reached, dim3(std::min<unsigned>(g1b(N, 32), 2048)), dim3(256), 0, s, vec, N, dp,
+                           (int32_t)first, seenp, ix.adj.as<int32_t>(), R, bests, bests + 1);
+        VJ_HIP(hipMemcpyAsync(got, bests, 16, hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipStreamSynchronize(s));
+        const bool has_free = got[1] != ~0ull;
+        const int32_t p = (int32_t)(uint32_t)(has_free ? got[1] : got[0]);
+        VJ_CHECK(p >= 0 && p < N, VJ_ERR_INTERNAL, "repair source");
+        hipLaunchKernelGGL(k_attach, dim3(1), dim3(64), 0, s, vec, dp, ix.adj.as<int32_t>(), R, p,
+                           (int32_t)first);
+        ix.repairs += 1;
+        if (touched) touched->push_back(p);
+        // a new edge only adds reachability; an overwritten edge may remove some
+        if (has_free) bfs_from((int32_t)first, false);
+        else bfs_from(ix.entry, true);
     }
 }
 
@@ -377,25 +482,8 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
     const float *vec = ix.vec.as<float>();
 
     // 1. kNN on MFMA tiles over all nodes, then exact re-rank
-    TileRows t;
-    const int Kp = ((dp + 31) / 32) * 32;
-    prepare_rows(vec, N, dp, Kp, true, t, s);
-    double e_dot, e_fin;
-    tile_error_bounds(t, t, 1, e_dot, e_fin);
-    const int nsplit = (e_dot == 0.0) ? 1 : 3;
-    DevBuf bkey((size_t)N * kKnnCap * sizeof(float)), bidb((size_t)N * kKnnCap * sizeof(int32_t));
-    if (nsplit == 3)
-        hipLaunchKernelGGL(k_knn<3>, dim3(g1b(N, 64)), dim3(256), 0, s, t.hi.as<uint16_t>(),
-                           t.lo.as<uint16_t>(), N, Kp, t.norm2.as<float>(), K, bkey.as<float>(),
-                           bidb.as<int32_t>());
-    else
-        hipLaunchKernelGGL(k_knn<1>, dim3(g1b(N, 64)), dim3(256), 0, s, t.hi.as<uint16_t>(),
-                           nullptr, N, Kp, t.norm2.as<float>(), K, bkey.as<float>(),
-                           bidb.as<int32_t>());
-    VJ_HIP(hipGetLastError());
-    t.hi.release();
-    t.lo.release();
-    bkey.release();
+    DevBuf bidb;
+    knn_candidates(ix, 0, N, K, bidb, s);
 
     // 2. re-rank + forward prune
     DevBuf kid((size_t)N * kc * sizeof(int32_t)), kd2((size_t)N * kc * sizeof(float));
@@ -403,7 +491,7 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
     DevBuf fdeg((size_t)N * sizeof(int32_t)), indeg((size_t)N * sizeof(int32_t));
     VJ_HIP(hipMemsetAsync(indeg.p, 0, indeg.bytes, s));
     launch_rows(dp, vec, N, R, K, kc, bidb.as<int32_t>(), kid.as<int32_t>(), kd2.as<float>(),
-                fwd.as<int32_t>(), fwd_d2.as<float>(), fdeg.as<int32_t>(), indeg.as<int32_t>(), s);
+                fwd.as<int32_t>(), fwd_d2.as<float>(), fdeg.as<int32_t>(), indeg.as<int32_t>(), 0, N, s);
     VJ_HIP(hipGetLastError());
     bidb.release();
 
@@ -420,10 +508,11 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
     VJ_HIP(hipMemsetAsync(rpos.p, 0, rpos.bytes, s));
     hipLaunchKernelGGL(k_scatter_rev, dim3(g1b(N * R, 256)), dim3(256), 0, s, N, R,
                        fwd.as<int32_t>(), fwd_d2.as<float>(), roff.as<int64_t>(),
-                       rpos.as<int32_t>(), rid.as<int32_t>(), rd2.as<float>());
+                       rpos.as<int32_t>(), rid.as<int32_t>(), rd2.as<float>(), (int64_t)0);
     ix.adj.alloc((size_t)N * R * sizeof(int32_t));
     launch_rev(dp, vec, N, R, fwd.as<int32_t>(), fwd_d2.as<float>(), fdeg.as<int32_t>(),
-               roff.as<int64_t>(), rid.as<int32_t>(), rd2.as<float>(), ix.adj.as<int32_t>(), s);
+               roff.as<int64_t>(), rid.as<int32_t>(), rd2.as<float>(), ix.adj.as<int32_t>(),
+               nullptr, s);
     VJ_HIP(hipGetLastError());
 
     // 4. entry = node nearest to the fp64 centroid (ties: smaller id)
@@ -446,59 +535,84 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
     }
 
     // 5. connectivity repair from the entry
-    {
-        DevBuf seen((size_t)N * sizeof(int)), fa((size_t)N * sizeof(int32_t)),
-            fb((size_t)N * sizeof(int32_t)), misc(32);
-        int *seenp = seen.as<int>();
-        int32_t *misc_i = misc.as<int32_t>();
-        auto bfs_from = [&](int32_t start, bool reset) {
-            if (reset) VJ_HIP(hipMemsetAsync(seen.p, 0, seen.bytes, s));
-            int one = 1;
-            VJ_HIP(hipMemcpyAsync(seenp + start, &one, sizeof(int), hipMemcpyHostToDevice, s));
-            VJ_HIP(hipMemcpyAsync(fa.p, &start, sizeof(int32_t), hipMemcpyHostToDevice, s));
-            int nf = 1;
-            int32_t *cur = fa.as<int32_t>(), *nxt = fb.as<int32_t>();
-            for (int64_t level = 0; nf > 0 && level <= N; ++level) {
-                VJ_HIP(hipMemsetAsync(misc_i, 0, sizeof(int), s));
-                hipLaunchKernelGGL(k_bfs_step, dim3(g1b((int64_t)nf * R, 256)), dim3(256), 0, s,
-                                   ix.adj.as<int32_t>(), R, cur, nf, seenp, nxt, misc_i);
-                VJ_HIP(hipMemcpyAsync(&nf, misc_i, sizeof(int), hipMemcpyDeviceToHost, s));
-                VJ_HIP(hipStreamSynchronize(s));
-                std::swap(cur, nxt);
-            }
-        };
-        bfs_from(ix.entry, true);
-        const int64_t max_iter = std::min<int64_t>(N, 200000);
-        for (int64_t iter = 0;; ++iter) {
-            VJ_CHECK(iter <= max_iter, VJ_ERR_INTERNAL, "connectivity repair did not converge");
-            int first = 0x7fffffff;
-            VJ_HIP(hipMemcpyAsync(misc_i, &first, sizeof(int), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_first_unseen, dim3(g1b(N, 256)), dim3(256), 0, s, seenp, N, misc_i);
-            VJ_HIP(hipMemcpyAsync(&first, misc_i, sizeof(int), hipMemcpyDeviceToHost, s));
-            VJ_HIP(hipStreamSynchronize(s));
-            if (first == 0x7fffffff) break;
-            unsigned long long init[2] = {~0ull, ~0ull}, got[2];
-            VJ_HIP(hipMemcpyAsync(misc.as<char>() + 8, init, 16, hipMemcpyHostToDevice, s));
-            unsigned long long *bests = reinterpret_cast<unsigned long long *>(misc.as<char>() + 8);
-            hipLaunchKernelGGL(k_nearest_reached, dim3(std::min<unsigned>(g1b(N, 32), 2048)), dim3(256), 0, s, vec, N, dp,
-                               (int32_t)first, seenp, ix.adj.as<int32_t>(), R, bests, bests + 1);
-            VJ_HIP(hipMemcpyAsync(got, bests, 16, hipMemcpyDeviceToHost, s));
-            VJ_HIP(hipStreamSynchronize(s));
-            const bool has_free = got[1] != ~0ull;
-            const int32_t p = (int32_t)(uint32_t)(has_free ? got[1] : got[0]);
-            VJ_CHECK(p >= 0 && p < N, VJ_ERR_INTERNAL, "repair source");
-            hipLaunchKernelGGL(k_attach, dim3(1), dim3(64), 0, s, vec, dp, ix.adj.as<int32_t>(), R, p,
-                               (int32_t)first);
-            ix.repairs += 1;
-            // a new edge only adds reachability; an overwritten edge may remove some
-            if (has_free) bfs_from((int32_t)first, false);
-            else bfs_from(ix.entry, true);
-        }
-    }
+    repair_connectivity(ix, s, nullptr);
 
     // 6. edge lengths
     ix.elen.alloc((size_t)N * R * sizeof(float));
     launch_edge_lengths(vec, dp, ix.adj.as<int32_t>(), N, R, ix.elen.as<float>(), s);
+    VJ_HIP(hipGetLastError());
+    VJ_HIP(hipStreamSynchronize(s));
+}
+
+void insert_graph(Index &ix, int64_t n_old, int kc, hipStream_t s) {
+    const int64_t N = ix.N, M = N - n_old;
+    const int R = ix.R, dp = ix.dp;
+    VJ_CHECK(M >= 0 && n_old >= 1, VJ_ERR_INTERNAL, "insertion rows");
+    if (M == 0) return;
+    kc = (int)std::min<int64_t>(kc, N - 1);
+    const int K = std::min(128, kc + 16);
+    const float *vec = ix.vec.as<float>();
+    int32_t *adj = ix.adj.as<int32_t>();
+
+    // 1. candidates of the new rows among all rows, re-rank, forward prune
+    DevBuf bidb;
+    knn_candidates(ix, n_old, M, K, bidb, s);
+    DevBuf kid((size_t)M * kc * sizeof(int32_t)), kd2((size_t)M * kc * sizeof(float));
+    DevBuf fwd((size_t)M * R * sizeof(int32_t)), fwd_d2((size_t)M * R * sizeof(float));
+    DevBuf fdeg((size_t)M * sizeof(int32_t)), indeg((size_t)N * sizeof(int32_t));
+    VJ_HIP(hipMemsetAsync(indeg.p, 0, indeg.bytes, s));
+    launch_rows(dp, vec, N, R, K, kc, bidb.as<int32_t>(), kid.as<int32_t>(), kd2.as<float>(),
+                fwd.as<int32_t>(), fwd_d2.as<float>(), fdeg.as<int32_t>(), indeg.as<int32_t>(),
+                n_old, M, s);
+    VJ_HIP(hipGetLastError());
+    std::vector<int32_t> indeg_h((size_t)N);
+    VJ_HIP(hipMemcpyAsync(indeg_h.data(), indeg.p, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    bidb.release();
+    kid.release();
+    kd2.release();
+
+    // 2. offers (CSR by target) and the rows that change: every old row that
+    //    receives an offer, and every new row
+    std::vector<int64_t> roff_h((size_t)N + 1, 0);
+    for (int64_t v = 0; v < N; ++v) roff_h[v + 1] = roff_h[v] + indeg_h[v];
+    std::vector<int32_t> rows_h;
+    for (int64_t v = 0; v < n_old; ++v)
+        if (indeg_h[v] > 0) rows_h.push_back((int32_t)v);
+    for (int64_t v = n_old; v < N; ++v) rows_h.push_back((int32_t)v);
+    const int64_t L = (int64_t)rows_h.size();
+    DevBuf roff((size_t)(N + 1) * sizeof(int64_t)), rpos((size_t)N * sizeof(int32_t));
+    DevBuf rid((size_t)std::max<int64_t>(roff_h[N], 1) * sizeof(int32_t));
+    DevBuf rd2((size_t)std::max<int64_t>(roff_h[N], 1) * sizeof(float));
+    DevBuf rows((size_t)L * sizeof(int32_t));
+    VJ_HIP(hipMemcpyAsync(roff.p, roff_h.data(), (N + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    VJ_HIP(hipMemcpyAsync(rows.p, rows_h.data(), L * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    VJ_HIP(hipMemsetAsync(rpos.p, 0, rpos.bytes, s));
+    hipLaunchKernelGGL(k_scatter_rev, dim3(g1b(M * R, 256)), dim3(256), 0, s, M, R,
+                       fwd.as<int32_t>(), fwd_d2.as<float>(), roff.as<int64_t>(),
+                       rpos.as<int32_t>(), rid.as<int32_t>(), rd2.as<float>(), n_old);
+
+    // 3. candidates of each changing row (current row or forward list, plus
+    //    its offers), kept whole if they fit, else RNG-pruned
+    DevBuf gf((size_t)L * R * sizeof(int32_t)), gd((size_t)L * R * sizeof(float)),
+        gdeg((size_t)L * sizeof(int32_t));
+    launch_gather(dp, vec, R, adj, fwd.as<int32_t>(), fdeg.as<int32_t>(), n_old,
+                  rows.as<int32_t>(), L, gf.as<int32_t>(), gd.as<float>(), gdeg.as<int32_t>(), s);
+    launch_rev(dp, vec, L, R, gf.as<int32_t>(), gd.as<float>(), gdeg.as<int32_t>(),
+               roff.as<int64_t>(), rid.as<int32_t>(), rd2.as<float>(), adj, rows.as<int32_t>(), s);
+    VJ_HIP(hipGetLastError());
+    VJ_HIP(hipStreamSynchronize(s));
+
+    // 4. connectivity repair from the (unchanged) entry, then the lengths of
+    //    every row that changed
+    repair_connectivity(ix, s, &rows_h);
+    if ((int64_t)rows_h.size() > L) {
+        rows.alloc(rows_h.size() * sizeof(int32_t));
+        VJ_HIP(hipMemcpyAsync(rows.p, rows_h.data(), rows_h.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+    }
+    launch_edge_lengths_rows(vec, dp, adj, N, R, rows.as<int32_t>(), (int64_t)rows_h.size(),
+                             ix.elen.as<float>(), s);
     VJ_HIP(hipGetLastError());
     VJ_HIP(hipStreamSynchronize(s));
 }

@@ -43,22 +43,24 @@ __device__ __forceinline__ float dist8(const float *vec, int32_t u, int32_t v, i
     return acc;
 }
 
-// Exact re-rank of the K buffered neighbours of every row: direct fp32 squared
-// distances, sorted by (distance, id); the first Kc are written out.
+// Exact re-rank of the K buffered neighbours of rows [rb, rb + M) (buffers
+// indexed from rb): direct fp32 squared distances, sorted by (distance, id);
+// the first Kc are written out.
 template <int DP>
 __global__ void __launch_bounds__(256)
 k_rerank(const float *vec, int64_t N, const int32_t *bid, int K, int Kc, int32_t *out_id,
-         float *out_d2) {
+         float *out_d2, int64_t rb, int64_t M) {
     const int lane = threadIdx.x & 63;
-    const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (u >= N) return;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= M) return;
+    const int64_t u = rb + i;
     float key[2];
     int id[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) { key[j] = INFINITY; id[j] = 0x7fffffff; }
     for (int base = 0; base < K; base += 8) {
         const int e = base + (lane >> 3);
-        const int32_t v = e < K ? bid[u * kKnnCap + e] : -1;
+        const int32_t v = e < K ? bid[i * kKnnCap + e] : -1;
         const bool ok = e < K && v >= 0 && v < N && v != u;
         const float d2 = dist8<DP>(vec, (int32_t)u, ok ? v : (int32_t)u, lane);
         // element e goes to register e / 64 of lane e % 64
@@ -81,8 +83,8 @@ k_rerank(const float *vec, int64_t N, const int32_t *bid, int K, int Kc, int32_t
         const int e = j * 64 + lane;
         if (e < Kc) {
             const bool ok = key[j] < INFINITY;
-            out_id[u * Kc + e] = ok ? id[j] : -1;
-            out_d2[u * Kc + e] = key[j];
+            out_id[i * Kc + e] = ok ? id[j] : -1;
+            out_d2[i * Kc + e] = key[j];
         }
     }
 }
@@ -115,31 +117,33 @@ __device__ __forceinline__ int rng_prune(const float *vec, const int32_t *cid, c
     return nk;
 }
 
-// forward prune of every node's re-ranked kNN list
+// forward prune of the re-ranked kNN lists of rows [rb, rb + M) (every
+// buffer indexed from rb; indeg by node id)
 template <int DP>
 __global__ void __launch_bounds__(256)
-k_prune_fwd(const float *vec, int64_t N, const int32_t *kid, const float *kd2, int Kc, int R,
-            int32_t *fwd, float *fwd_d2, int32_t *fdeg, int32_t *indeg) {
+k_prune_fwd(const float *vec, int64_t M, const int32_t *kid, const float *kd2, int Kc, int R,
+            int32_t *fwd, float *fwd_d2, int32_t *fdeg, int32_t *indeg, int64_t rb) {
     __shared__ int32_t s_kept[4][64];
     __shared__ int32_t s_cid[4][256];
     __shared__ float s_cd[4][256];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t u = (int64_t)blockIdx.x * 4 + w;
-    if (u >= N) return;
-    for (int e = lane; e < Kc; e += 64) { s_cid[w][e] = kid[u * Kc + e]; s_cd[w][e] = kd2[u * Kc + e]; }
+    const int64_t i = (int64_t)blockIdx.x * 4 + w;
+    if (i >= M) return;
+    const int64_t u = rb + i;
+    for (int e = lane; e < Kc; e += 64) { s_cid[w][e] = kid[i * Kc + e]; s_cd[w][e] = kd2[i * Kc + e]; }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     __builtin_amdgcn_wave_barrier();
     const int nk = rng_prune<DP>(vec, s_cid[w], s_cd[w], Kc, R, s_kept[w], lane);
     for (int e = lane; e < R; e += 64) {
         const int32_t v = e < nk ? s_kept[w][e] : -1;
-        fwd[u * R + e] = v;
+        fwd[i * R + e] = v;
         float dv = INFINITY;
         for (int t = 0; t < Kc; ++t)
             if (s_cid[w][t] == v) { dv = s_cd[w][t]; break; }
-        fwd_d2[u * R + e] = e < nk ? dv : INFINITY;
+        fwd_d2[i * R + e] = e < nk ? dv : INFINITY;
         if (e < nk) atomicAdd(&indeg[v], 1);
     }
-    if (lane == 0) fdeg[u] = nk;
+    if (lane == 0) fdeg[i] = nk;
 }
 
 
@@ -149,18 +153,21 @@ k_prune_fwd(const float *vec, int64_t N, const int32_t *kid, const float *kd2, i
 // 1024 pass a pass's filter, only the first 768 of the buffer are exact ranks,
 // so the prune takes those and the next pass streams the candidates after
 // the last of them again, until R are kept or the list is exhausted.
+// The rows are rows[0..M) (all rows 0..M-1 when rows is null); fwd, fwd_d2
+// and fdeg are indexed by the position in that list, roff and adj by node.
 template <int DP>
 __global__ void __launch_bounds__(256)
-k_prune_rev(const float *vec, int64_t N, int R, const int32_t *fwd, const float *fwd_d2,
+k_prune_rev(const float *vec, int64_t M, int R, const int32_t *fwd, const float *fwd_d2,
             const int32_t *fdeg, const int64_t *roff, const int32_t *rid, const float *rd2,
-            int32_t *adj) {
+            int32_t *adj, const int32_t *rows) {
     __shared__ int32_t s_kept[4][64];
     __shared__ int32_t s_cid[4][kCandMax];
     __shared__ float s_cd[4][kCandMax];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t v = (int64_t)blockIdx.x * 4 + w;
-    if (v >= N) return;
-    const int nf = fdeg[v];
+    const int64_t li = (int64_t)blockIdx.x * 4 + w;
+    if (li >= M) return;
+    const int64_t v = rows ? (int64_t)rows[li] : li;
+    const int nf = fdeg[li];
     const int64_t r0 = roff[v], nr = roff[v + 1] - r0;
     const int64_t total = nf + nr;
     // exclusive lower bound (in (d2, id) order) of the candidates a pass takes
@@ -186,7 +193,7 @@ k_prune_rev(const float *vec, int64_t N, int R, const int32_t *fwd, const float 
                 float k = INFINITY;
                 int i = 0x7fffffff;
                 if (e < total) {
-                    if (e < nf) { i = fwd[v * R + e]; k = fwd_d2[v * R + e]; }
+                    if (e < nf) { i = fwd[li * R + e]; k = fwd_d2[li * R + e]; }
                     else { i = rid[r0 + (e - nf)]; k = rd2[r0 + (e - nf)]; }
                     if (!mt::kless(lo_k, lo_i, k, i)) { k = INFINITY; i = 0x7fffffff; }
                 }
@@ -237,21 +244,61 @@ k_prune_rev(const float *vec, int64_t N, int R, const int32_t *fwd, const float 
     for (int e = lane; e < R; e += 64) adj[v * R + e] = e < nk ? s_kept[w][e] : -1;
 }
 
+// the current rows of the listed nodes below n_old (from adj), the forward
+// lists of the others (from fwd_new, indexed from n_old), with fp32 squared
+// lengths, as the forward part of an insertion's final prune
 template <int DP>
-void launch_rows(const float *vec, int64_t N, int R, int K, int Kc, const int32_t *bid,
-                 int32_t *kid, float *kd2, int32_t *fwd, float *fwd_d2, int32_t *fdeg,
-                 int32_t *indeg, hipStream_t s) {
-    hipLaunchKernelGGL(k_rerank<DP>, dim3(g1b(N, 4)), dim3(256), 0, s, vec, N, bid, K, Kc, kid, kd2);
-    hipLaunchKernelGGL(k_prune_fwd<DP>, dim3(g1b(N, 4)), dim3(256), 0, s, vec, N, kid, kd2, Kc, R,
-                       fwd, fwd_d2, fdeg, indeg);
+__global__ void __launch_bounds__(256)
+k_gather_rows(const float *vec, int R, const int32_t *adj, const int32_t *fwd_new,
+              const int32_t *fdeg_new, int64_t n_old, const int32_t *rows, int64_t M,
+              int32_t *fwd, float *fwd_d2, int32_t *fdeg) {
+    const int lane = threadIdx.x & 63;
+    const int64_t li = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (li >= M) return;
+    const int64_t v = rows[li];
+    const int32_t *src = v < n_old ? adj + v * R : fwd_new + (v - n_old) * R;
+    int deg = 0;
+    if (v < n_old) {
+        for (int j = 0; j < R; ++j) deg += src[j] >= 0;
+    } else {
+        deg = fdeg_new[v - n_old];
+    }
+    for (int b = 0; b < R; b += 8) {
+        const int e = b + (lane >> 3);
+        const int32_t x = e < deg ? src[e] : -1;
+        const float d2 = dist8<DP>(vec, (int32_t)v, x >= 0 ? x : (int32_t)v, lane);
+        if ((lane & 7) == 0 && e < R) {
+            fwd[li * R + e] = x;
+            fwd_d2[li * R + e] = x >= 0 ? d2 : INFINITY;
+        }
+    }
+    if (lane == 0) fdeg[li] = deg;
 }
 
 template <int DP>
-void launch_rev(const float *vec, int64_t N, int R, const int32_t *fwd, const float *fwd_d2,
+void launch_rows(const float *vec, int64_t N, int R, int K, int Kc, const int32_t *bid,
+                 int32_t *kid, float *kd2, int32_t *fwd, float *fwd_d2, int32_t *fdeg,
+                 int32_t *indeg, int64_t rb, int64_t M, hipStream_t s) {
+    hipLaunchKernelGGL(k_rerank<DP>, dim3(g1b(M, 4)), dim3(256), 0, s, vec, N, bid, K, Kc, kid,
+                       kd2, rb, M);
+    hipLaunchKernelGGL(k_prune_fwd<DP>, dim3(g1b(M, 4)), dim3(256), 0, s, vec, M, kid, kd2, Kc, R,
+                       fwd, fwd_d2, fdeg, indeg, rb);
+}
+
+template <int DP>
+void launch_rev(const float *vec, int64_t M, int R, const int32_t *fwd, const float *fwd_d2,
                 const int32_t *fdeg, const int64_t *roff, const int32_t *rid, const float *rd2,
-                int32_t *adj, hipStream_t s) {
-    hipLaunchKernelGGL(k_prune_rev<DP>, dim3(g1b(N, 4)), dim3(256), 0, s, vec, N, R, fwd, fwd_d2,
-                       fdeg, roff, rid, rd2, adj);
+                int32_t *adj, const int32_t *rows, hipStream_t s) {
+    hipLaunchKernelGGL(k_prune_rev<DP>, dim3(g1b(M, 4)), dim3(256), 0, s, vec, M, R, fwd, fwd_d2,
+                       fdeg, roff, rid, rd2, adj, rows);
+}
+
+template <int DP>
+void launch_gather(const float *vec, int R, const int32_t *adj, const int32_t *fwd_new,
+                   const int32_t *fdeg_new, int64_t n_old, const int32_t *rows, int64_t M,
+                   int32_t *fwd, float *fwd_d2, int32_t *fdeg, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_rows<DP>, dim3(g1b(M, 4)), dim3(256), 0, s, vec, R, adj, fwd_new,
+                       fdeg_new, n_old, rows, M, fwd, fwd_d2, fdeg);
 }
 
 }  // namespace brow

@@ -51,10 +51,11 @@ __global__ void k_quantize(const float *vec, int64_t n, uint8_t *u8, uint16_t *b
         atomicOr(flag, bits);
 }
 
-// one 64-thread block per node; thread j handles edge j (R <= 64)
+// one 64-thread block per node (node rows[block] when rows is given); thread
+// j handles edge j (R <= 64)
 __global__ void k_edge_lengths(const float *vec, int dp, const int32_t *adj, int64_t N, int R,
-                               float *elen) {
-    const int64_t u = blockIdx.x;
+                               float *elen, const int32_t *rows) {
+    const int64_t u = rows ? (int64_t)rows[blockIdx.x] : (int64_t)blockIdx.x;
     const int j = threadIdx.x;
     if (u >= N || j >= R) return;
     const int32_t v = adj[u * R + j];
@@ -457,7 +458,15 @@ void launch_quantize(const float *vec, int64_t rows, int dp, uint8_t *u8, uint16
 void launch_edge_lengths(const float *vec, int dp, const int32_t *adj, int64_t N, int R,
                          float *elen, hipStream_t s) {
     if (N == 0) return;
-    hipLaunchKernelGGL(k_edge_lengths, dim3((unsigned)N), dim3(64), 0, s, vec, dp, adj, N, R, elen);
+    hipLaunchKernelGGL(k_edge_lengths, dim3((unsigned)N), dim3(64), 0, s, vec, dp, adj, N, R, elen,
+                       nullptr);
+}
+
+void launch_edge_lengths_rows(const float *vec, int dp, const int32_t *adj, int64_t N, int R,
+                              const int32_t *rows, int64_t M, float *elen, hipStream_t s) {
+    if (M == 0) return;
+    hipLaunchKernelGGL(k_edge_lengths, dim3((unsigned)M), dim3(64), 0, s, vec, dp, adj, N, R, elen,
+                       rows);
 }
 
 void launch_dist_to_node(const float *vec, int dp, int64_t first, int64_t n, int32_t node,

@@ -1291,6 +1291,56 @@ vj_status vj_index_swap_roles(const vj_index *idx, int32_t build_mst, void *stre
     API_END
 }
 
+vj_status vj_index_insert_queries(vj_index *idx, const float *Q, int64_t n, int32_t K_cand,
+                                  void *stream) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr, VJ_ERR_INVALID_ARG, "null index");
+    Index &ix = idx->impl;
+    VJ_CHECK(!ix.separate, VJ_ERR_UNSUPPORTED, "insertion is defined on merged indexes");
+    VJ_CHECK(n >= 0, VJ_ERR_INVALID_ARG, "n must be >= 0");
+    if (n == 0) return VJ_OK;
+    VJ_CHECK(Q != nullptr, VJ_ERR_INVALID_ARG, "null vector pointer");
+    check_index_size(ix.nq + n, ix.nx);
+    const int kc = K_cand > 0 ? K_cand : std::min(2 * ix.R, 112);
+    VJ_CHECK(kc >= 1 && kc <= 112, VJ_ERR_UNSUPPORTED, "K_cand must be in [1, 112]");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n_old = ix.N, N = n_old + n;
+    const size_t R = (size_t)ix.R, dp = (size_t)ix.dp;
+    // the grown graph is built beside the old one and swapped in at the end
+    Index b;
+    b.nq = ix.nq + n; b.nx = ix.nx; b.N = N; b.d = ix.d; b.dp = ix.dp; b.R = ix.R;
+    b.entry = ix.entry; b.metric = ix.metric; b.device = ix.device;
+    b.vec.alloc((size_t)N * dp * sizeof(float));
+    VJ_HIP(hipMemcpyAsync(b.vec.p, ix.vec.p, (size_t)n_old * dp * sizeof(float),
+                          hipMemcpyDeviceToDevice, s));
+    launch_pad_rows(Q, n, ix.d, b.vec.as<float>() + (size_t)n_old * dp, ix.dp, s);
+    b.adj.alloc((size_t)N * R * sizeof(int32_t));
+    VJ_HIP(hipMemcpyAsync(b.adj.p, ix.adj.p, (size_t)n_old * R * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, s));
+    fill_i32(b.adj.as<int32_t>() + (size_t)n_old * R, n * (int64_t)R, -1, s);
+    b.elen.alloc((size_t)N * R * sizeof(float));
+    VJ_HIP(hipMemcpyAsync(b.elen.p, ix.elen.p, (size_t)n_old * R * sizeof(float),
+                          hipMemcpyDeviceToDevice, s));
+    insert_graph(b, n_old, kc, s);
+    // swap in, then the derived state
+    ix.vec = std::move(b.vec);
+    ix.adj = std::move(b.adj);
+    ix.elen = std::move(b.elen);
+    ix.nq = b.nq;
+    ix.N = N;
+    ix.repairs += b.repairs;
+    const bool had_bf16 = ix.vec_bf16.p != nullptr, had_f8 = ix.vec_f8.p != nullptr;
+    ix.vec_bf16.release();
+    ix.vec_f8.release();
+    ix.f8meta.release();
+    finish_vectors(ix, s);
+    if (had_bf16) ensure_bf16(ix, s);
+    if (had_f8) ensure_f8(ix, s);
+    if (ix.has_mst) compute_mst(ix, s);
+    VJ_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
 vj_status vj_build_nnmap(vj_index *idx, float ood_ratio, void *stream) {
     API_BEGIN
     VJ_CHECK(idx != nullptr, VJ_ERR_INVALID_ARG, "null index");

@@ -269,6 +269,9 @@ int num_cus();
 // edge lengths of every adjacency entry (L2)
 void launch_edge_lengths(const float *vec, int dp, const int32_t *adj, int64_t N, int R,
                          float *elen, hipStream_t s);
+// the same for the rows rows[0..M) only
+void launch_edge_lengths_rows(const float *vec, int dp, const int32_t *adj, int64_t N, int R,
+                              const int32_t *rows, int64_t M, float *elen, hipStream_t s);
 // copy rows into a zero-padded layout
 void launch_pad_rows(const float *src, int64_t rows, int d, float *dst, int dp,
                      hipStream_t s);

@@ -69,6 +69,7 @@ _SIGS = {
     "vj_index_from_separate_graphs": (C.c_int, [_vp, _i64, _vp, _i64, _i32, C.c_int, _vp, _i32,
                                                 _i32, _vp, _vp, _PP]),
     "vj_index_swap_roles": (C.c_int, [_vp, _i32, _vp, _PP]),
+    "vj_index_insert_queries": (C.c_int, [_vp, _vp, _i64, _i32, _vp]),
     "vj_build_nnmap": (C.c_int, [_vp, _f32, _vp]),
     "vj_index_export_nnmap": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vj_index_export_graph": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -229,6 +230,12 @@ class Index:
         h = C.c_void_p()
         _check(_lib.vj_index_swap_roles(self._h, int(build_mst), _stream(), C.byref(h)))
         return Index(h.value)
+
+    def insert_queries(self, Q: torch.Tensor, K_cand: int = 0):
+        """Append the query batch Q [n, d] (vj_index_insert_queries); the new
+        queries get the next query indexes."""
+        Q = _dev(Q, torch.float32, "Q")
+        _check(_lib.vj_index_insert_queries(self._h, _ptr(Q), Q.shape[0], int(K_cand), _stream()))
 
     def build_nnmap(self, ood_ratio: float = 1.5):
         """NN-Map of the queries (vj_build_nnmap; separate indexes)."""
