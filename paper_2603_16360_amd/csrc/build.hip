@@ -13,6 +13,7 @@
 //      gets an edge from its nearest reachable node with a free slot (else
 //      it replaces that node's longest edge), until all are reachable.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -181,6 +182,401 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
         }
     }
     for (int r = 0; r < 16; ++r) merge_row(r);
+}
+
+// kNN sweep with the rows' fragments held in registers (Kp <= 256).
+// A workgroup of 4 waves owns 4 * RT * 16 rows (RT row tiles of 16 per wave)
+// and sweeps the columns [cb, ce) of its split (blockIdx.y) 32 at a time.
+// Column tiles stream through a ring of NB LDS stages filled by direct
+// global-to-LDS loads (global_load_lds_dwordx4), NB - 1 tiles ahead of the
+// tile being multiplied, so the loads' latency hides behind NB - 2 tiles of
+// MFMA work; one barrier per tile.  A staged row is CPR + 1 chunks of 16
+// bytes (one pad chunk), which spreads a fragment read's 16 rows over
+// distinct banks.  Every wave issues the same number of load instructions
+// per tile (slots past the tile load a real chunk into the pad area), so a
+// fixed vmcnt marks the tile as landed.
+// Per element the epilogue is one fma (key = |x|^2 - 2<u,x>, the order of
+// |u-x|^2 for a fixed row u) and one compare against the row's threshold;
+// a wave takes the append path only for a 16 x 16 tile where some element
+// passes.  Thresholds are the K-th key of the last merge (FLT_MAX until a
+// row holds K entries), so every element of the final top-K passes when it
+// is seen.  Columns outside [cb, ce) get |x|^2 = +inf and never pass; rows
+// outside [rb, rb + M) get threshold -inf.
+template <int NSPLIT, int KP>
+struct KnnReg {
+    static constexpr int KS = KP / 32;                 // MFMA k-steps of 32
+    static constexpr int TERMS = NSPLIT == 3 ? 2 : 1;  // hi (+ lo) parts
+    static constexpr int RT = TERMS * 16 * KS <= 64 ? 4 : 2;
+    static constexpr int CT = 2;
+    static constexpr int BN = 16 * CT;                 // columns per tile
+    static constexpr int ROWS = 4 * RT * 16;           // rows per workgroup
+    static constexpr int CPR = KP / 8;                 // 16-byte chunks per row
+    static constexpr int SPR = CPR + 1;                // staged slots per row
+    static constexpr int IPW = (BN * SPR + 255) / 256; // load instructions per wave and part
+    static constexpr int PART = 4 * IPW * 1024;        // bytes of one part of a stage
+    static constexpr int STAGE = TERMS * PART + 4 * 256;  // + each wave's copy of |x|^2
+    static constexpr int NB0 = (76 * 1024) / STAGE;
+    static constexpr int NB = NB0 > 8 ? 8 : NB0;       // stages in the ring
+    static constexpr int LPT = TERMS * IPW + 1;        // load instructions per wave and tile
+    static constexpr bool OK = KP % 32 == 0 && KP <= 256 && NB >= 3 && (NB - 2) * LPT <= 60;
+};
+
+// one direct global-to-LDS load per lane: 16 bytes (or 4) from the
+// wave-uniform base plus the lane's byte offset, to LDS byte address
+// lds + 16 * lane (4 * lane); lds must be wave-uniform.  M0 is saved and
+// restored inside the block.
+__device__ __forceinline__ void lds_dma16(const void *base, uint32_t off, uint32_t lds) {
+    uint32_t saved;
+    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\t"
+                 "global_load_lds_dwordx4 %2, %3\n\ts_nop 0\n\ts_mov_b32 m0, %0"
+                 : "=&s"(saved) : "s"(lds), "v"(off), "s"(base) : "memory");
+}
+__device__ __forceinline__ void lds_dma4(const void *base, uint32_t off, uint32_t lds) {
+    uint32_t saved;
+    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\t"
+                 "global_load_lds_dword %2, %3\n\ts_nop 0\n\ts_mov_b32 m0, %0"
+                 : "=&s"(saved) : "s"(lds), "v"(off), "s"(base) : "memory");
+}
+__device__ __forceinline__ uint32_t lds_byte_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+// wait until at most N of this wave's vector memory operations are in
+// flight and its LDS operations are done, then the workgroup barrier
+template <int N>
+__device__ __forceinline__ void wait_barrier() {
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+// order-preserving map of a float key to uint32 (-0 and +0 both map as +0)
+__device__ __forceinline__ uint32_t key_bits(float k) {
+    const uint32_t b = __float_as_uint(k + 0.0f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// count of elements in the wave (E per lane) for which pred holds
+template <int E, typename P>
+__device__ __forceinline__ int wave_count(P pred) {
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < E; ++j) c += __popcll(__ballot(pred(j)));
+    return c;
+}
+
+// keep the K smallest (key, id) entries of row buffer [off, off + cnt) in
+// its first K slots (unordered; the re-rank orders them) and return the
+// K-th smallest key (FLT_MAX while fewer than K are held).  A bitwise
+// search on order-preserving key bits finds the K-th key T; entries equal
+// to T are kept by smallest id (a second bitwise search on the ids).  One
+// wave; E * 64 >= kKnnCap.
+__device__ __noinline__ float knn_merge_row(float *bkey, int32_t *bid, int64_t off, int cnt,
+                                            int K, int lane) {
+    constexpr int E = (kKnnCap + 63) / 64;
+    const int c = min(cnt, kKnnCap);
+    float key[E];
+    int id[E];
+    uint32_t u[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int e = j * 64 + lane;
+        const bool ok = e < c;
+        key[j] = ok ? bkey[off + e] : INFINITY;
+        id[j] = ok ? bid[off + e] : 0x7fffffff;
+        u[j] = ok ? key_bits(key[j]) : 0xffffffffu;
+    }
+    if (c <= K) {  // everything is kept
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+            const int e = j * 64 + lane;
+            if (e >= c && e < K) {
+                bkey[off + e] = INFINITY;
+                bid[off + e] = -1;
+            }
+        }
+        return FLT_MAX;
+    }
+    // T = the smallest t with #(u <= t) >= K
+    uint32_t T = 0;
+    for (int bit = 31; bit >= 0; --bit) {
+        const uint32_t cand = T | ((1u << bit) - 1u);
+        if (wave_count<E>([&](int j) { return u[j] <= cand; }) < K) T |= 1u << bit;
+    }
+    const int nless = wave_count<E>([&](int j) { return u[j] < T; });
+    const int need = K - nless;  // entries equal to T that are kept, >= 1
+    // I = the smallest i with #(u == T && id <= i) >= need (ids >= 0)
+    int32_t I = 0x7fffffff;
+    if (wave_count<E>([&](int j) { return u[j] == T; }) > need) {
+        uint32_t t = 0;
+        for (int bit = 30; bit >= 0; --bit) {
+            const uint32_t cand = t | ((1u << bit) - 1u);
+            if (wave_count<E>([&](int j) { return u[j] == T && (uint32_t)id[j] <= cand; }) < need)
+                t |= 1u << bit;
+        }
+        I = (int32_t)t;
+    }
+    // compact the kept entries into slots [0, K)
+    int base = 0;
+    float kth = 0.f;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const bool keep = u[j] < T || (u[j] == T && id[j] <= I);
+        const uint64_t m = __ballot(keep);
+        const int rank = base + __popcll(m & ((1ull << lane) - 1ull));
+        if (keep) {
+            bkey[off + rank] = key[j];
+            bid[off + rank] = id[j];
+        }
+        if (u[j] == T) kth = key[j];
+        base += __popcll(m);
+    }
+    // every lane returns T's key (some lane holds an entry equal to T)
+    bool h = false;
+#pragma unroll
+    for (int j = 0; j < E; ++j) h |= u[j] == T;
+    const uint64_t hasT = __ballot(h);
+    return __shfl(kth, __ffsll((unsigned long long)hasT) - 1);
+}
+
+template <int NSPLIT, int KP>
+__global__ void __launch_bounds__(256, 2)
+k_knn_reg(const uint16_t *Ah, const uint16_t *Al, int32_t N, const float *n2, int K,
+          float *bkey, int32_t *bid, int32_t rb, int32_t M, int32_t cols_per_split) {
+    using S = KnnReg<NSPLIT, KP>;
+    constexpr int RT = S::RT, CT = S::CT, KS = S::KS, BN = S::BN, CPR = S::CPR, SPR = S::SPR;
+    constexpr int IPW = S::IPW, TERMS = S::TERMS, PART = S::PART, STAGE = S::STAGE, NB = S::NB;
+    constexpr int LPT = S::LPT;
+    __shared__ __attribute__((aligned(1024))) char ring[NB * STAGE];
+    __shared__ float s_tau[4][RT * 16];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r16 = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4, grp = lane >> 4;
+    const int32_t wrow0 = rb + (int32_t)blockIdx.x * S::ROWS + w * RT * 16;  // wave's first row
+    const int32_t rend = rb + M;
+    const int32_t cb = (int32_t)blockIdx.y * cols_per_split;
+    const int32_t ce = min(N, cb + cols_per_split);
+    const int64_t boff = (int64_t)blockIdx.y * M;  // this split's buffer rows
+    // a row is cut back to K once it holds more than merge_at entries: the
+    // threshold then tightens early, which keeps the appends few
+    const int merge_at = min(K + 96, kKnnCap - BN);
+    // entries held by the wave's row r: lane r of cnt
+    int cnt = 0;
+    if (lane < RT * 16) s_tau[w][lane] = wrow0 + lane < rend ? FLT_MAX : -INFINITY;
+
+    // the wave's rows: fragment (rt, ks) holds row rt*16 + (lane & 15),
+    // dimensions ks*32 + (lane >> 4)*8 .. +7
+    mt::bf16x8 a[RT][KS], al[NSPLIT == 3 ? RT : 1][NSPLIT == 3 ? KS : 1];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            a[rt][ks] = mt::load8(Ah, wrow0 + rt * 16 + r16, rend, KP, ks * 32 + kq);
+            if (NSPLIT == 3) al[rt][ks] = mt::load8(Al, wrow0 + rt * 16 + r16, rend, KP, ks * 32 + kq);
+        }
+
+    // loads of the tile at column c0 into stage st: slot s of a part is
+    // row s / SPR, chunk s % SPR; pad chunks and slots past the tile load
+    // the tile's first chunk; rows past N load row N - 1 (masked by |x|^2).
+    // A lane's slots are the same in every tile, so their byte offsets
+    // from the tile's first row are fixed; only the last tile clamps.
+    const uint32_t ring0 = lds_byte_addr(ring);
+    uint32_t soff[IPW];
+    int srow[IPW];
+#pragma unroll
+    for (int j = 0; j < IPW; ++j) {
+        const int sl = (w * IPW + j) * 64 + lane;
+        const int rr = sl / SPR, ch = sl - rr * SPR;
+        const bool real = rr < BN && ch < CPR;
+        srow[j] = real ? rr : 0;
+        soff[j] = real ? (uint32_t)((rr * KP + ch * 8) * 2) : 0u;
+    }
+    auto issue = [&](int32_t c0, int st) {
+        const uint32_t sbase = ring0 + (uint32_t)(st * STAGE);
+        const char *th = reinterpret_cast<const char *>(Ah + (int64_t)c0 * KP);
+        const char *tl = NSPLIT == 3 ? reinterpret_cast<const char *>(Al + (int64_t)c0 * KP) : nullptr;
+        const bool whole = c0 + BN <= N;
+#pragma unroll
+        for (int j = 0; j < IPW; ++j) {
+            uint32_t off = soff[j];
+            if (!whole && c0 + srow[j] > N - 1)  // past the last row: row N - 1
+                off = (uint32_t)(((N - 1 - c0) * KP) * 2) + (off - (uint32_t)(srow[j] * KP * 2));
+            const uint32_t dst = sbase + (uint32_t)((w * IPW + j) * 1024);
+            lds_dma16(th, off, dst);
+            if (NSPLIT == 3) lds_dma16(tl, off, dst + PART);
+        }
+        const int nr = min(lane < BN ? lane : 0, N - 1 - c0);
+        lds_dma4(n2 + c0, (uint32_t)(nr * 4), sbase + TERMS * PART + w * 256);
+    };
+
+    float tau[RT][4];
+    auto load_tau = [&]() {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) tau[rt][i] = s_tau[w][rt * 16 + rq + i];
+    };
+    auto merge = [&](int r) {
+        const int c = __builtin_amdgcn_readlane(cnt, r);
+        const float kth = knn_merge_row(bkey, bid, (boff + (wrow0 - rb) + r) * kKnnCap, c, K, lane);
+        cnt = lane == r ? min(c, K) : cnt;
+        if (lane == 0) s_tau[w][r] = kth;
+    };
+
+    const int ntile = ce > cb ? (ce - cb + BN - 1) / BN : 0;
+    // prologue: tiles 0 .. NB-2 in flight (every wave issues LPT loads per
+    // tile slot, a slot past the last tile re-loads tile 0's stage 0 data
+    // into the last stage, which no tile reads before it is re-issued)
+#pragma unroll
+    for (int p = 0; p < NB - 1; ++p) issue(cb + (p < ntile ? p : 0) * BN, p < ntile ? p : NB - 1);
+    for (int it = 0; it < ntile; ++it) {
+        const int st = it % NB;
+        // tile it has landed when at most (NB - 2) tiles' loads are in
+        // flight: loads complete in issue order, and the appends' stores
+        // issued since only add to the count, so they can only make this
+        // wait longer
+        wait_barrier<(NB - 2) * LPT>();
+        if (it == 0) load_tau();
+        {
+            const int nx = it + NB - 1;  // into the stage read at it - 1
+            issue(cb + (nx < ntile ? nx : 0) * BN, nx < ntile ? nx % NB : (it + NB - 1) % NB);
+        }
+        const char *sp = ring + st * STAGE;
+        floatx4 acc[RT][CT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            mt::bf16x8 b[CT], bl[NSPLIT == 3 ? CT : 1];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const int off = ((ct * 16 + r16) * SPR + ks * 4 + (lane >> 4)) * 16;
+                b[ct] = *reinterpret_cast<const mt::bf16x8 *>(sp + off);
+                if (NSPLIT == 3) bl[ct] = *reinterpret_cast<const mt::bf16x8 *>(sp + PART + off);
+            }
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt][ks], b[ct], acc[rt][ct], 0, 0, 0);
+                    if (NSPLIT == 3) {
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt][ks], bl[ct], acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rt][ks], b[ct], acc[rt][ct], 0, 0, 0);
+                    }
+                }
+        }
+        // epilogue: the keys (in place of the products) and one pass test
+        // for the whole step; only a step with a passing element looks at
+        // its 16 x 16 tiles and appends (rare once the rows hold K)
+        const int32_t c0 = cb + it * BN;
+        const float *snc = reinterpret_cast<const float *>(sp + TERMS * PART + w * 256);
+        bool any = false;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            const int32_t col = c0 + ct * 16 + r16;
+            const float nc = col < ce ? snc[ct * 16 + r16] : INFINITY;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    acc[rt][ct][i] = fmaf(-2.f, acc[rt][ct][i], nc);
+                    any |= acc[rt][ct][i] <= tau[rt][i];
+                }
+        }
+        bool appended = false;
+        if (__ballot(any)) {
+            appended = true;
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const int32_t col = c0 + ct * 16 + r16;
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    bool hit = false;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) hit |= acc[rt][ct][i] <= tau[rt][i];
+                    if (!__ballot(hit)) continue;
+                    // per row (rt*16 + 4g + i of lane group g) the passing
+                    // lanes' slots: the row's count (lane r of cnt) plus the
+                    // lane's rank among its group's passing lanes
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const bool ok = acc[rt][ct][i] <= tau[rt][i] && col != wrow0 + rt * 16 + rq + i;
+                        const uint64_t m = __ballot(ok);
+                        if (!m) continue;
+                        int at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            const int r = rt * 16 + 4 * g + i;
+                            const int below = __popcll(m & ((1ull << (16 * g)) - 1ull));
+                            const int here = __popcll((m >> (16 * g)) & 0xffffull);
+                            const int base = __builtin_amdgcn_readlane(cnt, r);
+                            cnt = lane == r ? base + here : cnt;
+                            at += grp == g ? base - below : 0;
+                        }
+                        if (ok && at < kKnnCap) {
+                            const int64_t o = (boff + (wrow0 - rb) + rt * 16 + rq + i) * kKnnCap + at;
+                            bkey[o] = acc[rt][ct][i];
+                            bid[o] = col;
+                        }
+                    }
+                }
+            }
+        }
+        if (appended) {
+            // rows that could not take another full tile: cut to K
+            uint64_t full = __ballot(lane < RT * 16 && cnt > merge_at);
+            if (full) {
+                // the appends' stores complete before the merges read them
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                while (full) {
+                    const int r = __ffsll((unsigned long long)full) - 1;
+                    full &= full - 1;
+                    merge(r);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                load_tau();
+            }
+        }
+    }
+    // every load in flight lands before the workgroup ends
+    wait_barrier<0>();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    for (int r = 0; r < RT * 16; ++r)
+        if (wrow0 + r < rend) merge(r);
+}
+
+// top-K of each row over the splits' sorted lists (split s of row i at
+// (s * M + i) * kKnnCap), written to split 0; one wave per row, S * K <= 512
+__global__ void __launch_bounds__(256)
+k_knn_merge_splits(float *bkey, int32_t *bid, int64_t M, int S, int K) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= M) return;
+    float key[8];
+    int id[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int e = j * 64 + lane;
+        const int sp = e / K, k = e - sp * K;
+        const bool ok = sp < S;
+        const int64_t o = ((int64_t)sp * M + i) * kKnnCap + k;
+        key[j] = ok ? bkey[o] : INFINITY;
+        id[j] = ok ? bid[o] : 0x7fffffff;
+        if (ok && id[j] < 0) { key[j] = INFINITY; id[j] = 0x7fffffff; }
+    }
+    mt::wave_sort<8>(key, id, lane);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int e = j * 64 + lane;
+        if (e < K) {
+            const bool ok = key[j] < INFINITY;
+            bkey[i * kKnnCap + e] = key[j];
+            bid[i * kKnnCap + e] = ok ? id[j] : -1;
+        }
+    }
 }
 
 // reverse offers of the forward lists of rows [rb, rb + M) (fwd indexed from rb)
@@ -386,6 +782,50 @@ void launch_gather(int dp, const float *vec, int R, const int32_t *adj, const in
     }
 }
 
+// the register-row kNN sweep for one (NSPLIT, Kp); false if that shape has
+// no instantiation.  Column splits keep >= 1,024 workgroups when M is small
+// (an insertion batch); their lists are merged into split 0.
+template <int NSPLIT, int KP>
+bool launch_knn_reg_t(const TileRows &t, int64_t N, int K, int64_t rb, int64_t M, DevBuf &bkey,
+                      DevBuf &bidb, hipStream_t s) {
+    using S = KnnReg<NSPLIT, KP>;
+    if constexpr (!S::OK) {
+        return false;
+    } else {
+        const int64_t nb = (M + S::ROWS - 1) / S::ROWS;
+        int splits = 1;
+        while (splits * 2 * K <= 512 && nb * splits < 1024 && N / (splits * 2) >= 8 * S::BN)
+            splits *= 2;
+        const int64_t cps = ((N + splits - 1) / splits + S::BN - 1) / S::BN * S::BN;
+        bkey.alloc((size_t)splits * M * kKnnCap * sizeof(float));
+        bidb.alloc((size_t)splits * M * kKnnCap * sizeof(int32_t));
+        hipLaunchKernelGGL((k_knn_reg<NSPLIT, KP>), dim3((unsigned)nb, (unsigned)splits), dim3(256),
+                           0, s, t.hi.as<uint16_t>(),
+                           NSPLIT == 3 ? t.lo.as<uint16_t>() : nullptr, (int32_t)N,
+                           t.norm2.as<float>(), K, bkey.as<float>(), bidb.as<int32_t>(),
+                           (int32_t)rb, (int32_t)M, (int32_t)cps);
+        if (splits > 1)
+            hipLaunchKernelGGL(k_knn_merge_splits, dim3(g1b(M, 4)), dim3(256), 0, s,
+                               bkey.as<float>(), bidb.as<int32_t>(), M, splits, K);
+        return true;
+    }
+}
+
+bool launch_knn_reg(int nsplit, int Kp, const TileRows &t, int64_t N, int K, int64_t rb,
+                    int64_t M, DevBuf &bkey, DevBuf &bidb, hipStream_t s) {
+    if (K > 128 || M <= 0) return false;
+#define VJ_KNN_CASE(kp)                                                                        \
+    case kp:                                                                                   \
+        return nsplit == 3 ? launch_knn_reg_t<3, kp>(t, N, K, rb, M, bkey, bidb, s)             \
+                           : launch_knn_reg_t<1, kp>(t, N, K, rb, M, bkey, bidb, s);
+    switch (Kp) {
+        VJ_KNN_CASE(32) VJ_KNN_CASE(64) VJ_KNN_CASE(96) VJ_KNN_CASE(128) VJ_KNN_CASE(192)
+        VJ_KNN_CASE(256)
+    default: return false;
+    }
+#undef VJ_KNN_CASE
+}
+
 // exact top-K candidate lists (ids in bid [M][kKnnCap], K of them) of rows
 // [rb, rb + M) of ix.vec among all ix.N rows, on MFMA tiles
 void knn_candidates(const Index &ix, int64_t rb, int64_t M, int K, DevBuf &bidb, hipStream_t s) {
@@ -398,7 +838,13 @@ void knn_candidates(const Index &ix, int64_t rb, int64_t M, int K, DevBuf &bidb,
     double e_dot, e_fin;
     tile_error_bounds(t, t, 1, e_dot, e_fin);
     const int nsplit = (e_dot == 0.0) ? 1 : 3;
-    DevBuf bkey((size_t)M * kKnnCap * sizeof(float));
+    DevBuf bkey;
+    if (launch_knn_reg(nsplit, Kp, t, N, K, rb, M, bkey, bidb, s)) {
+        VJ_HIP(hipGetLastError());
+        VJ_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    bkey.alloc((size_t)M * kKnnCap * sizeof(float));
     bidb.alloc((size_t)M * kKnnCap * sizeof(int32_t));
     if (nsplit == 3)
         hipLaunchKernelGGL(k_knn<3>, dim3(g1b(M, 64)), dim3(256), 0, s, t.hi.as<uint16_t>(),

@@ -113,6 +113,31 @@ def test_build_float_data():
     assert tot == pytest.approx(want, rel=1e-5)
 
 
+# row widths of the kNN sweep's register-row kernel: (d, integer, vmax);
+# integer cases keep 2 Kp vmax^2 < 2^24 so the one-term tiles are exact
+WIDTHS = [(40, True, 218), (96, True, 218), (160, True, 150), (200, True, 100),
+          (64, False, 0), (96, False, 0), (128, False, 0)]
+
+
+@pytest.mark.parametrize("d,integer,vmax", WIDTHS,
+                         ids=[f"d{d}-{'int' if i else 'float'}" for d, i, _ in WIDTHS])
+def test_build_widths(d, integer, vmax):
+    # ragged node counts (not multiples of any tile) and small enough for
+    # the column-split path of the kNN sweep
+    w = workloads.width_case(d, 5_003, 697, integer, 900 + d, vmax=vmax or 218)
+    idx, adj, elen, parent = _build(w, 16)
+    g = oracle.build_merged(w.Q, w.X, 16)
+    assert idx.info()["entry"] == g.entry
+    same = (adj == g.adj).all(axis=1)
+    print(f"[build] width {d} {'integer' if integer else 'float'} rows identical "
+          f"{same.mean():.5f}", flush=True)
+    if integer:
+        assert same.all(), np.nonzero(~same)[0][:10]
+    else:
+        assert same.mean() >= 0.995
+    _invariants(w, adj, elen, g.entry, 16)
+
+
 def test_build_then_join_recall():
     # end to end: GPU graph + GPU join vs the GPU brute-force ground truth
     w = workloads.config_tiny()

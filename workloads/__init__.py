@@ -319,6 +319,24 @@ def stream_batches(w: Workload):
     return list(w.meta["batches"])
 
 
+def width_case(d: int, n_x: int, n_q: int, integer: bool, seed: int,
+               vmax: int = 218) -> Workload:
+    """Small build-parity inputs of width d: the mid workload's integer
+    recipe at width d (16 clusters, values clipped to [0, vmax]) or a
+    16-component Gaussian mixture with means ~ N(0, 4 I) and sigma = 1.
+    X uses ``seed``, Q ``seed + 1``; R = 16, L2."""
+    if integer:
+        weights, scales, means = mid_params(d, 16)
+        X = integer_mixture(n_x, means, scales, weights, seed, vmax=vmax)
+        Q = integer_mixture(n_q, means, scales, weights, seed + 1, vmax=vmax)
+    else:
+        means = 2.0 * _rng(seed + 2).standard_normal((16, d))
+        X = gaussian_mixture(n_x, means, 1.0, seed)
+        Q = gaussian_mixture(n_q, means, 1.0, seed + 1)
+    return Workload(f"width{d}", Q, X, "l2", 16, 10.0, seed + 3, n_q,
+                    {"integer": integer, "value_max": vmax})
+
+
 def hub_chain(d: int = 1024, window: int = 60, n_queries: int = 8) -> Workload:
     """A graph-build edge case: one hub with more reverse-edge candidates
     than a node usually has (0/1 integer data, exact in every precision).
