@@ -36,6 +36,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    """The host CPU's model name (as lscpu reports it)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def kernel_source_sha():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -73,14 +84,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--variants", default="fp32,u8")
+    ap.add_argument("--gather-calib", action="store_true",
+                    help="run the counter-calibration gather first (2,000,000 random 512-byte rows)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a plain 1 GiB device copy first (HBM counter calibration)")
     ap.add_argument("--ood", action="store_true",
-                    help="instead of the headline: the OOD inner-product workload at 1/10 scale; "
-                         "MI-BFS, MI+Adapt, forced hybrid and learned routing compared")
+                    help="instead of the headline: the OOD inner-product workload (2M x 768, 200k "
+                         "queries); plain fp32 modes against learned routing at equal recall")
+    ap.add_argument("--ood-scale", type=float, default=1.0,
+                    help="1.0 (the stated size) or 0.1 (X = 200k, 20k queries)")
     ap.add_argument("--modes", action="store_true",
                     help="instead of the headline: MI, MI+SWS, MI+HWS on the merged index against "
                          "INLJ, SWS, HWS on separate indexes, on the headline workload")
+    ap.add_argument("--highdim", action="store_true",
+                    help="instead of the headline: the 1M x 960 workload, fp32 rows against bf16 "
+                         "rows with fp32 re-check, error against fp64")
     ap.add_argument("--stream", action="store_true",
                     help="instead of the headline: the batched stream workload at 1/10 scale "
                          "(200 batches, p50/p99 batch latency)")
@@ -100,6 +118,8 @@ def main():
         return modes_main(args, torch, workloads, vj)
     if args.ood:
         return ood_main(args, torch, workloads, vj)
+    if args.highdim:
+        return highdim_main(args, torch, workloads, vj)
 
     t0 = time.time()
     w = workloads.config_mid()
@@ -121,6 +141,19 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log("copy calibration: 1 GiB device-to-device copy done")
+    if args.gather_calib:
+        # 2,000,000 distinct random rows of 4,000,000 x 128 fp32 (2 GB, far
+        # beyond the caches), read with the join's row-read layout: the rows
+        # move exactly 1,024,000,000 bytes; ids and output 16,000,000 more
+        g = torch.Generator(device=dev)
+        g.manual_seed(5)
+        rows = torch.rand((4_000_000, 128), device=dev, generator=g)
+        ids = torch.randperm(4_000_000, device=dev, generator=g)[:2_000_000].to(torch.int32)
+        torch.cuda.synchronize()
+        vj.vj_calib_gather(rows, ids)
+        torch.cuda.synchronize()
+        del rows, ids
+        log("gather calibration: 2,000,000 rows of 512 bytes read")
     Q = torch.from_numpy(w.Q).to(dev)
     X = torch.from_numpy(w.X).to(dev)
     torch.cuda.synchronize()
@@ -209,11 +242,23 @@ def main():
             cpu_s += time.time() - t
             npairs = int(counts.sum())
             reps += 1
+        # the ground truth on the CPU: the fp64 nested-loop join on a fixed
+        # 2,000-query sample, extrapolated linearly to all queries
+        gt_sample = np.sort(np.random.default_rng(203).choice(nq, size=2000, replace=False))
+        t = time.time()
+        gt_counts = oracle.nlj_counts(w.Q[gt_sample], w.X, eps)
+        nlj_s = time.time() - t
         cpu = {"value": reps * nq / cpu_s, "unit": "queries/s", "cores": cores,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"all {nq} queries x {reps} repetitions ({cpu_s:.1f}s): self-seeded BFS "
                          f"merged-index join in fp64 with OpenMP over queries, same graph and eps; "
-                         f"{npairs} pairs per repetition"}
+                         f"{npairs} pairs per repetition",
+               "nlj_ground_truth": {
+                   "sample_queries": int(gt_sample.size), "sample_s": nlj_s,
+                   "sample_pairs": int(gt_counts.sum()),
+                   "extrapolated_s_all_queries": nlj_s * nq / gt_sample.size,
+                   "note": "fp64 nested-loop join (OpenMP) on a fixed 2,000-query sample (seed "
+                           "203), extrapolated linearly to all queries"}}
         log(f"cpu baseline: {cpu}")
 
     dom = head["tiers"][head["dominant_tier"]]
@@ -321,20 +366,26 @@ def modes_main(args, torch, workloads, vj):
 
 
 def ood_main(args, torch, workloads, vj):
-    """OOD queries (30 % from shifted means), inner product: the paper's MI
-    (BFS), MI+Adapt (d1/d2 rule), hybrid for every query, and the learned
-    router trained on separate training queries indexed in their own merged
-    graph (records: per-query recall of budget-mode joins against the exact
-    join)."""
-    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "eps.json")))["ood"]
+    """OOD queries (30 % from shifted means), inner product, at the stated
+    size by default (--ood-scale 0.1 for the 1/10 workload).  The plain fp32
+    join's family is the paper's MI (BFS), MI+Adapt (d1/d2 rule) and the
+    hybrid search for every query at three queue bounds; the learned family
+    is the router trained on separate training queries indexed in their own
+    merged graph (records: per-query recall of budget-mode joins against the
+    exact join) at three recall targets, in fp32 and with low-precision rows.
+    For each learned point the fastest plain point with at least its recall
+    gives the speed ratio at equal recall.  OOD queries' recall is reported
+    on its own."""
+    key = "ood_full" if args.ood_scale >= 1.0 else "ood"
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "eps.json")))[key]
     scale = golden["scale"]
     t0 = time.time()
     w = workloads.config_ood(scale=scale)
     wt = workloads.config_ood(scale=scale, train=True)
-    for key, arr in (("Q_sha", w.Q), ("X_sha", w.X)):
+    for k, arr in (("Q_sha", w.Q), ("X_sha", w.X)):
         sha = hashlib.sha256(np.ascontiguousarray(arr).tobytes()).hexdigest()[:16]
-        if sha != golden[key]:
-            raise SystemExit(f"generated data differs from the calibrated data ({key})")
+        if sha != golden[k]:
+            raise SystemExit(f"generated data differs from the calibrated data ({k})")
     eps = golden["eps"]
     nq, nt = w.Q.shape[0], wt.Q.shape[0]
     log(f"ood: X {w.X.shape}, {nq} test and {nt} training queries, eps={eps} ({time.time() - t0:.1f}s)")
@@ -342,41 +393,52 @@ def ood_main(args, torch, workloads, vj):
     X = torch.from_numpy(w.X).to(dev)
     Qt = torch.from_numpy(w.Q).to(dev)
     Qr = torch.from_numpy(wt.Q).to(dev)
+    del w.X
+    t = time.time()
     idx = vj.vj_build_merged_index(Qt, X, metric="ip", R=w.R)
+    torch.cuda.synchronize()
+    build_s = time.time() - t
+    log(f"test index built in {build_s:.1f}s")
+    t = time.time()
     idx_tr = vj.vj_build_merged_index(Qr, X, metric="ip", R=wt.R)
     torch.cuda.synchronize()
+    log(f"training index built in {time.time() - t:.1f}s")
     budgets = (0, 16, 64, 256)
     # training records
     t = time.time()
     F = vj.vj_join_features(idx_tr, eps, metric="ip")
     gt_tr, _ = vj.vj_bruteforce_join(Qr, X, eps, metric="ip", precision="bf16").export()
     gtc = torch.bincount(gt_tr[:, 0].long(), minlength=nt).float()
+    del gt_tr
     Y = []
     for b in budgets:
         r = vj.vj_join(idx_tr, eps, metric="ip", hybrid="budget",
                        budget=torch.full((nt,), b, dtype=torch.int32, device=dev))
         cnt = r.stats()[:, 0].float()
         Y.append(torch.where(gtc > 0, cnt / gtc.clamp(min=1), torch.ones_like(cnt)))
+        del r
     Y = torch.stack(Y, 1).contiguous()
+    del idx_tr
+    records_s = time.time() - t
     pred = vj.Predictor(w.d + 8, 256, 256, len(budgets), seed=1)
     pred.fit_normalization(F)
     torch.cuda.synchronize()
     ts = time.time()
-    losses = pred.train(F, Y, epochs=40, batch=512, lr=1e-3, seed=2)
+    epochs = max(4, int(round(40 * min(1.0, 12_500 / nt))))
+    losses = pred.train(F, Y, epochs=epochs, batch=512, lr=1e-3, seed=2)
     torch.cuda.synchronize()
     train_s = time.time() - ts
-    log(f"records + training: {time.time() - t:.1f}s (training {train_s:.1f}s, "
-        f"loss {losses[0]:.4f} -> {losses[-1]:.4f})")
-    target = 0.95
-    vj.vj_index_attach_predictor(idx, pred, recall_target=target, budgets=budgets)
+    log(f"records {records_s:.1f}s ({nt} queries x {len(budgets)} budgets), training {train_s:.1f}s "
+        f"({epochs} epochs, loss {losses[0]:.4f} -> {losses[-1]:.4f})")
     gt, _ = vj.vj_bruteforce_join(Qt, X, eps, metric="ip", precision="bf16").export()
     n_gt = int(gt.shape[0])
     is_ood = torch.from_numpy(w.meta["is_ood"]).to(dev)
     gt_ood = int(is_ood[gt[:, 0].long()].sum().item())
-    modes = {"MI (BFS)": {}, "MI+Adapt": {"hybrid": "adapt"}, "hybrid for all": {"hybrid": "force"},
-             "learned": {"hybrid": "learned"}}
-    out = {}
-    for name, kw in modes.items():
+    del gt
+
+    def measure(name, kw, target=None):
+        if target is not None:
+            vj.vj_index_attach_predictor(idx, pred, recall_target=target, budgets=budgets)
         for _ in range(max(1, args.warmup)):
             vj.vj_join(idx, eps, metric="ip", **kw)
         torch.cuda.synchronize()
@@ -385,29 +447,144 @@ def ood_main(args, torch, workloads, vj):
         for _ in range(args.steps):
             res = None
             torch.cuda.synchronize()
-            t = time.perf_counter()
+            ts = time.perf_counter()
             res = vj.vj_join(idx, eps, metric="ip", **kw)
             torch.cuda.synchronize()
-            walls.append(time.perf_counter() - t)
+            walls.append(time.perf_counter() - ts)
         qx, _ = res.export()
         st = res.stats().cpu().numpy()
         found_ood = int(is_ood[qx[:, 0].long()].sum().item())
-        out[name] = {"qps": nq / float(np.mean(walls)), "ms": 1000 * float(np.mean(walls)),
-                     "recall": int(qx.shape[0]) / max(1, n_gt),
-                     # null when the exact join has no pair of an OOD query
-                     "recall_ood_queries": found_ood / gt_ood if gt_ood else None,
-                     "hybrid_queries": int(st[:, 5].sum()), "routed_exact": int(((st[:, 7] & 2) > 0).sum())}
-        log(f"{name}: {out[name]}")
-    line = {"metric": "OOD join queries/sec and recall by mode (X=200k x 768, IP)",
-            "value": out["learned"]["qps"], "unit": "queries/s", "n_gpus": 1,
+        r = {"qps": nq / float(np.mean(walls)), "ms": 1000 * float(np.mean(walls)),
+             "recall": int(qx.shape[0]) / max(1, n_gt),
+             "recall_ood_queries": found_ood / gt_ood if gt_ood else None,
+             "recall_in_distribution_queries": (int(qx.shape[0]) - found_ood) / max(1, n_gt - gt_ood),
+             "hybrid_queries": int(st[:, 5].sum()), "routed_exact": int(((st[:, 7] & 2) > 0).sum()),
+             "precision": kw.get("precision", "fp32")}
+        if target is not None:
+            r["recall_target"] = target
+        log(f"{name}: {r}")
+        return r
+
+    plain = {"MI (BFS)": measure("MI (BFS)", {}),
+             "MI+Adapt": measure("MI+Adapt", {"hybrid": "adapt"})}
+    for beam in (16, 64, 256):
+        name = f"hybrid for all, B={beam}"
+        plain[name] = measure(name, {"hybrid": "force", "hybrid_beam": beam})
+    learned = {}
+    for target in (0.9, 0.95, 0.98):
+        name = f"learned, target {target}"
+        learned[name] = measure(name, {"hybrid": "learned"}, target)
+    # the learned router with low-precision rows (bf16 and fp8 with their
+    # proven margins and fp32 re-checks) at the middle target
+    for prec in ("bf16", "fp8"):
+        name = f"learned, target 0.95, {prec} rows"
+        learned[name] = measure(name, {"hybrid": "learned", "precision": prec}, 0.95)
+    # equal recall: the fastest plain point whose recall reaches the learned one's
+    compare = {}
+    for name, r in learned.items():
+        ok = [(p["qps"], pn) for pn, p in plain.items() if p["recall"] >= r["recall"]]
+        if ok:
+            q, pn = max(ok)
+            compare[name] = {"plain": pn, "plain_qps": q, "speedup": r["qps"] / q}
+        else:
+            compare[name] = {"plain": None, "plain_qps": None, "speedup": None,
+                             "note": "no plain fp32 point reaches this recall"}
+    best = max(learned.items(), key=lambda kv: (compare[kv[0]]["speedup"] or 0.0))
+    line = {"metric": "OOD join queries/sec at equal recall: learned mixed-precision form vs plain fp32 join",
+            "value": best[1]["qps"], "unit": "queries/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "OOD at 1/10 scale: X=200,000 unit vectors d=768 (512-mean vMF "
-                                   "mixture); 20,000 test queries, 30 % from means rotated 40 deg; "
-                                   "inner product, eps for 20 mean matches; predictor trained on "
-                                   "12,500 separate queries", "recall_target": target},
-            "modes": out, "train_s": train_s, "ground_truth_pairs": n_gt,
-            "ground_truth_pairs_of_ood_queries": gt_ood}
+            "scaling": "weak", "vs_baseline": None, "dtype": best[1]["precision"], "data": "synthetic",
+            "config": {"workload": f"OOD{'' if scale >= 1.0 else ' at 1/10 scale'}: X={X.shape[0]:,} "
+                                   f"unit vectors d=768 (512-mean vMF mixture); {nq:,} test queries, "
+                                   "30 % from means rotated 40 deg (concentrated at mean cosine 0.92); "
+                                   f"inner product, eps for 20 mean matches; predictor trained on "
+                                   f"{nt:,} separate queries", "eps": eps},
+            "best_learned": best[0], "equal_recall": compare, "plain": plain, "learned": learned,
+            "build_s": build_s, "records_s": records_s, "train_s": train_s, "train_epochs": epochs,
+            "ground_truth_pairs": n_gt, "ground_truth_pairs_of_ood_queries": gt_ood}
+    print(json.dumps(line), flush=True)
+
+
+def highdim_main(args, torch, workloads, vj):
+    """High-dimensional data with the precision form: X = 1,000,000 and
+    Q = 10,000 vectors of d = 960 in [0, 1] (100-cluster Beta mixture), L2,
+    eps for a mean of 10 matches.  The join with fp32 rows against the join
+    with bf16 rows (a proven per-row margin, fp32 re-check of every candidate
+    inside it), both BFS on the same merged index; recall against the exact
+    MFMA brute-force join; the error of every reported distance against
+    fp64, max |d - d64| / eps."""
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "eps.json")))["highdim"]
+    t0 = time.time()
+    w = workloads.config_highdim()
+    for k, arr in (("Q_sha", w.Q), ("X_sha", w.X)):
+        sha = hashlib.sha256(np.ascontiguousarray(arr).tobytes()).hexdigest()[:16]
+        if sha != golden[k]:
+            raise SystemExit(f"generated data differs from the calibrated data ({k})")
+    eps = golden["eps"]
+    nq = w.Q.shape[0]
+    log(f"highdim: X {w.X.shape}, {nq} queries, eps={eps} ({time.time() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    Q = torch.from_numpy(w.Q).to(dev)
+    X = torch.from_numpy(w.X).to(dev)
+    del w.X
+    t = time.time()
+    idx = vj.vj_build_merged_index(Q, X, metric="l2", R=w.R, copies=1)
+    torch.cuda.synchronize()
+    build_s = time.time() - t
+    log(f"merged index built in {build_s:.1f}s")
+    t = time.time()
+    gtr = vj.vj_bruteforce_join(Q, X, eps, precision="bf16")
+    torch.cuda.synchronize()
+    gt_s = time.time() - t
+    gt_qx, gt_d = gtr.export(sorted=True)
+    gt_keys = gt_qx[:, 0].to(torch.int64) * X.shape[0] + gt_qx[:, 1].to(torch.int64)
+    n_gt = int(gt_keys.numel())
+
+    def err(qx, d):
+        """max |d - d64| / eps over the pairs, d64 from the fp32 inputs in fp64"""
+        m = 0.0
+        for a in range(0, qx.shape[0], 1 << 16):
+            q = Q[qx[a:a + (1 << 16), 0].long()].double()
+            x = X[qx[a:a + (1 << 16), 1].long()].double()
+            d64 = (q - x).pow(2).sum(1).sqrt()
+            m = max(m, float((d[a:a + (1 << 16)].double() - d64).abs().max().item()) if d64.numel() else 0.0)
+        return m / eps
+
+    out = {}
+    sets = {}
+    for prec in ("fp32", "bf16"):
+        for _ in range(max(1, args.warmup)):
+            vj.vj_join(idx, eps, precision=prec)
+        torch.cuda.synchronize()
+        walls = []
+        res = None
+        for _ in range(args.steps):
+            res = None
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            res = vj.vj_join(idx, eps, precision=prec)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - ts)
+        qx, d = res.export(sorted=True)
+        keys = qx[:, 0].to(torch.int64) * X.shape[0] + qx[:, 1].to(torch.int64)
+        sets[prec] = keys
+        out[prec] = {"qps": nq / float(np.mean(walls)), "ms": 1000 * float(np.mean(walls)),
+                     "recall": keys.numel() / max(1, n_gt),
+                     "precision_is_one": bool(torch.isin(keys, gt_keys).all().item()),
+                     "pairs": int(keys.numel()), "rechecked": res.rechecked(),
+                     "max_abs_err_over_eps": err(qx, d)}
+        log(f"{prec}: {out[prec]}")
+    same = bool(sets["fp32"].numel() == sets["bf16"].numel() and torch.equal(sets["fp32"], sets["bf16"]))
+    line = {"metric": "high-dim join queries/sec (1Mx960, bf16 rows with fp32 re-check vs fp32 rows)",
+            "value": out["bf16"]["qps"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": "X=1,000,000 Q=10,000 d=960 in [0,1], 100-cluster Beta mixture, L2, "
+                                   "eps for mean 10 matches, merged graph R=32, self-seeded BFS",
+                       "eps": eps},
+            "variants": out, "bf16_pairs_equal_fp32_pairs": same, "build_s": build_s,
+            "ground_truth_s": gt_s, "ground_truth_pairs": n_gt,
+            "ground_truth_max_abs_err_over_eps": err(gt_qx, gt_d)}
     print(json.dumps(line), flush=True)
 
 

@@ -494,6 +494,21 @@ vj_status vj_index_attach_predictor(vj_index *idx, const vj_predictor *p, float 
 /* Text of the last error on the calling thread ("" if none). */
 const char *vj_last_error(void);
 
+/*
+ * Hardware-counter calibration (not part of the method): out[i] = the sum
+ * of row ids[i] of rows, for i < n.  rows: [nrows][dp] fp32 on the device,
+ * dp a positive multiple of 32; ids: [n] int32 (an id outside [0, nrows)
+ * gives 0); out: [n] fp32.  A row is read exactly as the join reads one
+ * (8 lanes, 16 bytes per lane per load, whole 128-byte lines per load), so
+ * with n distinct ids over a set far larger than the caches the kernel
+ * moves n * dp * 4 bytes of rows plus 8 n bytes of ids and output; the
+ * memory counters' reading for it calibrates theirs for the join's gathers.
+ * Errors: VJ_ERR_INVALID_ARG (n or nrows < 0, dp not a positive multiple of
+ * 32, a null pointer with n > 0).
+ */
+vj_status vj_calib_gather(const float *rows, int64_t nrows, int32_t dp, const int32_t *ids,
+                          int64_t n, float *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,9 @@ namespace vj {
 void launch_dist_to_node(const float *vec, int dp, int64_t first, int64_t n, int32_t node,
                          float *out, hipStream_t s);
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+// counter calibration gather (the join's row-read layout); see vj_calib_gather
+void calib_gather(const float *rows, int64_t nrows, int dp, const int32_t *ids, int64_t n,
+                  float *out, hipStream_t s);
 void iota_i32(int32_t *p, int64_t n, hipStream_t s);
 // NN-Map OOD bits of the queries from their witnesses w (see k_nn_ood)
 void nn_ood(const float *vec, int dp, int64_t nx, int64_t nq, const int32_t *adj, int R,

@@ -475,6 +475,39 @@ void launch_dist_to_node(const float *vec, int dp, int64_t first, int64_t n, int
     hipLaunchKernelGGL(k_dist_to_node, dim3(grid1(n)), dim3(256), 0, s, vec, dp, first, n, node, out);
 }
 
+// Counter calibration: out[i] = sum of row ids[i] of rows [nrows][dp]
+// (fp32, dp a multiple of 32), read as the join reads a row: 8 lanes per
+// row, 16 bytes per lane per load, each load of the 8-lane group covering
+// whole 128-byte lines; 8 rows per wave.
+__global__ void __launch_bounds__(256)
+k_calib_gather(const float *rows, int64_t nrows, int dp, const int32_t *ids, int64_t n,
+               float *out) {
+    const int lane = threadIdx.x & 63, g = lane >> 3, p = lane & 7;
+    const int64_t i = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 8 + g;
+    const bool ok = i < n;
+    const int32_t r = ok ? ids[i] : 0;
+    const bool rok = ok && r >= 0 && r < nrows;
+    const float4 *row = reinterpret_cast<const float4 *>(rows + (int64_t)(rok ? r : 0) * dp);
+    float acc = 0.f;
+    if (rok)
+        for (int c = p; c < dp / 4; c += 8) {
+            const float4 v = row[c];
+            acc += (v.x + v.y) + (v.z + v.w);
+        }
+    acc += __shfl_xor(acc, 4);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 1);
+    if (ok && p == 0) out[i] = acc;
+}
+
+void calib_gather(const float *rows, int64_t nrows, int dp, const int32_t *ids, int64_t n,
+                  float *out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_calib_gather, dim3((unsigned)((n + 31) / 32)), dim3(256), 0, s, rows,
+                       nrows, dp, ids, n, out);
+    VJ_HIP(hipGetLastError());
+}
+
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     if (n == 0) return;
     hipLaunchKernelGGL(k_fill_i32, dim3(grid1(n)), dim3(256), 0, s, p, n, v);

@@ -1093,6 +1093,16 @@ void vj_default_join_params(vj_join_params *p) {
 
 const char *vj_last_error(void) { return vj::last_error(); }
 
+vj_status vj_calib_gather(const float *rows, int64_t nrows, int32_t dp, const int32_t *ids,
+                          int64_t n, float *out, void *stream) {
+    API_BEGIN
+    VJ_CHECK(n >= 0 && nrows >= 0, VJ_ERR_INVALID_ARG, "n and nrows must be >= 0");
+    VJ_CHECK(dp > 0 && dp % 32 == 0, VJ_ERR_INVALID_ARG, "dp must be a positive multiple of 32");
+    VJ_CHECK(n == 0 || (rows && ids && out), VJ_ERR_INVALID_ARG, "null pointer");
+    calib_gather(rows, nrows, dp, ids, n, out, (hipStream_t)stream);
+    API_END
+}
+
 }  // extern "C"
 
 namespace vj {

@@ -112,6 +112,7 @@ _SIGS = {
     "vj_predictor_get_adam_state": (C.c_int, [_vp, _vp, _vp, C.POINTER(_i64), _vp]),
     "vj_index_attach_predictor": (C.c_int, [_vp, _vp, _f32, _vp]),
     "vj_last_error": (C.c_char_p, []),
+    "vj_calib_gather": (C.c_int, [_vp, _i64, _i32, _vp, _i64, _vp, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -573,3 +574,14 @@ def vj_index_attach_predictor(index: Index, pred: Predictor | None, recall_targe
 
 def vj_last_error() -> str:
     return _lib.vj_last_error().decode()
+
+
+def vj_calib_gather(rows: torch.Tensor, ids: torch.Tensor) -> torch.Tensor:
+    """Counter calibration: the sum of each listed row, read with the join's
+    row-read layout (see include/vj.h)."""
+    rows = _dev(rows, torch.float32, "rows")
+    ids = _dev(ids, torch.int32, "ids")
+    out = torch.empty(ids.numel(), dtype=torch.float32, device=rows.device)
+    _check(_lib.vj_calib_gather(_ptr(rows), rows.shape[0], rows.shape[1], _ptr(ids), ids.numel(),
+                                _ptr(out), _stream()))
+    return out

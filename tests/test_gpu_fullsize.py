@@ -4,7 +4,7 @@ merged index, default join parameters, fp32 and u8 rows).
 
 The oracle cannot build the graph or join every query at this size, so the
 check uses sampled outputs and properties that hold at any size:
-* for 64 sampled queries, fp64 distances to all of X (numpy) give the exact
+* for 2,000 sampled queries, fp64 distances to all of X (numpy) give the exact
   in-range sets: every GPU pair is in them (precision 1) and the GPU's
   reported distances are exact (integer data: fp32 squared distances are
   exact);
@@ -72,30 +72,37 @@ def _closure(w, adj, entry, eps, qi, d64):
     return seen
 
 
-@pytest.mark.parametrize("precision", ["fp32", "u8"])
-def test_fullsize_sampled_queries(mid, precision):
+def test_fullsize_sampled_queries(mid):
     w, eps, Q, X, idx, adj = mid
-    res = vj.vj_join(idx, eps, precision=precision)
-    qx, dist = res.export(sorted=True)
-    qx, dist = qx.cpu().numpy(), dist.cpu().numpy()
     entry = idx.info()["entry"]
     rng = np.random.default_rng(17)
-    sample = np.sort(rng.choice(w.Q.shape[0], size=64, replace=False))
-    D = _exact_dists(w, sample)
-    starts = np.searchsorted(qx[:, 0], sample, side="left")
-    ends = np.searchsorted(qx[:, 0], sample, side="right")
-    n_exact = n_got = 0
-    for j, (qi, a, b) in enumerate(zip(sample.tolist(), starts.tolist(), ends.tolist())):
-        d64 = D[:, j]
-        got = set(qx[a:b, 1].tolist())
-        exact = set(np.nonzero(d64 < eps)[0].tolist())
-        assert got <= exact, qi                                   # precision 1
-        assert got == _closure(w, adj, entry, eps, qi, d64), qi   # BFS closure
-        np.testing.assert_allclose(dist[a:b], d64[qx[a:b, 1]], rtol=1e-6)
-        n_exact += len(exact)
-        n_got += len(got)
-    print(f"[fullsize] {precision}: sampled recall {n_got / max(1, n_exact):.4f} "
-          f"({n_got} of {n_exact} pairs, 64 queries)", flush=True)
+    sample = np.sort(rng.choice(w.Q.shape[0], size=2000, replace=False))
+    results = {}
+    for precision in ("fp32", "u8"):
+        qx, dist = vj.vj_join(idx, eps, precision=precision).export(sorted=True)
+        qx, dist = qx.cpu().numpy(), dist.cpu().numpy()
+        results[precision] = (qx, dist, np.searchsorted(qx[:, 0], sample, side="left"),
+                              np.searchsorted(qx[:, 0], sample, side="right"))
+    n_exact = 0
+    n_got = {p: 0 for p in results}
+    for c0 in range(0, sample.size, 250):  # 250 queries' distances at a time (2 GB)
+        chunk = sample[c0:c0 + 250]
+        D = _exact_dists(w, chunk)
+        for j, qi in enumerate(chunk.tolist()):
+            d64 = D[:, j]
+            exact = set(np.nonzero(d64 < eps)[0].tolist())
+            closure = _closure(w, adj, entry, eps, qi, d64)
+            n_exact += len(exact)
+            for precision, (qx, dist, starts, ends) in results.items():
+                a, b = int(starts[c0 + j]), int(ends[c0 + j])
+                got = set(qx[a:b, 1].tolist())
+                assert got <= exact, (precision, qi)              # precision 1
+                assert got == closure, (precision, qi)            # BFS closure
+                np.testing.assert_allclose(dist[a:b], d64[qx[a:b, 1]], rtol=1e-6)
+                n_got[precision] += len(got)
+    for precision in results:
+        print(f"[fullsize] {precision}: sampled recall {n_got[precision] / max(1, n_exact):.4f} "
+              f"({n_got[precision]} of {n_exact} pairs, {sample.size} queries)", flush=True)
 
 
 def test_fullsize_bruteforce_sampled(mid):
