@@ -82,8 +82,15 @@ def _declare(L):
     L.or_join.restype = _i64
     L.or_join.argtypes = [_f32p, _i64, _i64, _int, _int, _i32p, _int, C.c_int32,
                           C.c_void_p, _i32p, _i64, _dbl, C.POINTER(_Cfg), C.c_void_p,
-                          C.c_void_p, C.c_void_p, C.c_void_p,
+                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                           _i64, _i32p, _i32p, _f64p, _i32p]
+    L.or_splitmix64.restype = C.c_uint64
+    L.or_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+    L.or_levels.restype = None
+    L.or_levels.argtypes = [_i64, C.c_uint64, _int, np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS")]
+    L.or_descend.restype = None
+    L.or_descend.argtypes = [_f32p, _i64, _i64, _int, _int, _int, _i64p, _i32p, _i32p, _int,
+                             _i32p, _i32p, _i64, _i32p, _i32p]
     L.or_insert_batch.restype = _i64
     L.or_insert_batch.argtypes = [_f32p, _i64, _i64, _int, _int, _int, _i32p, _f64p, C.c_int32]
     L.or_nnmap.restype = None
@@ -289,11 +296,13 @@ def join(Q, X, adj, entry: int, eps: float, metric: str = "l2", query_ids=None,
          conv_threshold: int = 10, ood_ratio: float = 1.5, parent=None,
          budget=None, uncertain: str = "plain", uncertain_rel: float = 1e-5,
          shuffle_seed: int = 0, fragile_rel: float | None = None, merged: bool = True,
-         greedy_beam: int = 256, nnmap=None) -> JoinResult:
+         greedy_beam: int = 256, nnmap=None, qseed=None) -> JoinResult:
     """The join of Algorithm 1 on a merged graph (merged=True: adj is [N][R]
     over X then Q) or on separate indexes (merged=False: adj rows 0..nx-1
     are the data graph G_X with entry `entry`, rows nx.. the query graph
-    G_Q in node ids, used only by the MST; work_sharing "none" is INLJ)."""
+    G_Q in node ids, used only by the MST; work_sharing "none" is INLJ).
+    qseed: optional [nq] per-query seed replacing the entry (the node an
+    upper-layer descent reached, see descend())."""
     V = np.ascontiguousarray(np.concatenate([_f32(X), _f32(Q)], axis=0))
     nq, nx, d = Q.shape[0], X.shape[0], Q.shape[1]
     adj = np.ascontiguousarray(adj, np.int32)
@@ -322,6 +331,10 @@ def join(Q, X, adj, entry: int, eps: float, metric: str = "l2", query_ids=None,
     if hybrid == "budget":
         bud = np.ascontiguousarray(budget, np.int32)
         assert bud.shape[0] == n
+    qs = None
+    if qseed is not None:
+        qs = np.ascontiguousarray(qseed, np.int32)
+        assert qs.shape[0] == nq and np.all((qs >= 0) & (qs < nx))
     stats = np.zeros((n, len(STAT_FIELDS)), np.int32)
     L = lib()
     args = (V, nx, nq, d, METRICS[metric], adj, R, entry,
@@ -329,7 +342,8 @@ def join(Q, X, adj, entry: int, eps: float, metric: str = "l2", query_ids=None,
             bud.ctypes.data if bud is not None else None,
             nnw.ctypes.data if nnw is not None else None,
             nnd.ctypes.data if nnd is not None else None,
-            nno.ctypes.data if nno is not None else None)
+            nno.ctypes.data if nno is not None else None,
+            qs.ctypes.data if qs is not None else None)
     e32, e64 = np.empty(0, np.int32), np.empty(0, np.float64)
     cnt = L.or_join(*args, 0, e32, e32, e64, stats)
     oq, ox, od = np.empty(cnt, np.int32), np.empty(cnt, np.int32), np.empty(cnt, np.float64)
@@ -426,3 +440,71 @@ def adam_step(p, g, m, v, t: int, lr: float, b1: float = 0.9, b2: float = 0.999,
     assert p.shape == g.shape == m.shape == v.shape
     lib().or_adam_step(p.size, p.reshape(-1), g.reshape(-1), m.reshape(-1), v.reshape(-1),
                        int(t), lr, b1, b2, eps)
+
+
+# ---------------------------------------------------------------------------
+# HNSW-style upper layers (Section 5, varying index type)
+# ---------------------------------------------------------------------------
+
+def splitmix64(seed: int, k: int) -> int:
+    """Output k (k >= 1) of SplitMix64 seeded with `seed`."""
+    return int(lib().or_splitmix64(seed, k))
+
+
+def levels(n: int, seed: int, max_levels: int = 8) -> np.ndarray:
+    """Level of each of n data nodes: trailing zero 4-bit digits of its
+    SplitMix64 output, capped at max_levels (P(level >= l) = 16^-l)."""
+    out = np.empty(n, np.int8)
+    lib().or_levels(n, seed, max_levels, out)
+    return out
+
+
+@dataclass
+class Layers:
+    lvl: np.ndarray    # [nx] int8 level of each data node
+    ids: list          # per layer (layer 1 first): sorted data ids
+    adj: list          # per layer: [n_l][R] int32 data ids, -1 padded
+    entry: list        # per layer: entry data id
+
+
+def build_layers(X, R: int, seed: int = 1, max_levels: int = 8, Kc: int | None = None) -> Layers:
+    """Upper layers over the data nodes: layer l holds the nodes of level
+    >= l and its graph is the merged-graph recipe over them alone; layers
+    stop before the first one with fewer than two nodes."""
+    X = _f32(X)
+    lvl = levels(X.shape[0], seed, max_levels)
+    ids, adjs, entries = [], [], []
+    for l in range(1, max_levels + 1):
+        sel = np.nonzero(lvl >= l)[0].astype(np.int32)
+        if sel.size < 2:
+            break
+        g = build_merged(np.zeros((0, X.shape[1]), np.float32), X[sel], R, Kc)
+        adjs.append(np.where(g.adj >= 0, sel[np.maximum(g.adj, 0)], -1).astype(np.int32))
+        ids.append(sel)
+        entries.append(int(sel[g.entry]))
+    return Layers(lvl, ids, adjs, entries)
+
+
+def descend(Q, X, layers: Layers, metric: str = "l2", query_ids=None):
+    """Greedy descent of each query through the upper layers; returns
+    (seed [n] data ids, moves [n]).  No layers: the seeds are -1."""
+    nq, nx, d = Q.shape[0], X.shape[0], Q.shape[1]
+    qids = np.arange(nq, dtype=np.int32) if query_ids is None else np.ascontiguousarray(query_ids, np.int32)
+    n = qids.shape[0]
+    nl = len(layers.ids)
+    if nl == 0:
+        return np.full(n, -1, np.int32), np.zeros(n, np.int32)
+    R = layers.adj[0].shape[1]
+    off = np.zeros(nl, np.int64)
+    for j in range(1, nl):
+        off[j] = off[j - 1] + layers.ids[j - 1].size
+    pos = np.full((nl, nx), -1, np.int32)
+    for j, sel in enumerate(layers.ids):
+        pos[j, sel] = np.arange(sel.size, dtype=np.int32)
+    adj = np.ascontiguousarray(np.concatenate(layers.adj), np.int32)
+    V = np.ascontiguousarray(np.concatenate([_f32(X), _f32(Q)], axis=0))
+    seed = np.empty(n, np.int32)
+    moves = np.empty(n, np.int32)
+    lib().or_descend(V, nx, nq, d, METRICS[metric], nl, off, np.ascontiguousarray(pos), adj, R,
+                     np.asarray(layers.entry, np.int32), qids, n, seed, moves)
+    return seed, moves

@@ -12,6 +12,8 @@
  *   - Section 4.3 + Appendix C (RNG):  or_knn, or_rng_prune, or_build_merged
  *   - Section 3.2 (work sharing, MST): or_mst_parents
  *   - Algorithms 1-8:                  or_join
+ *   - Section 5, varying index type (HNSW-style upper layers):
+ *                                      or_splitmix64, or_levels, or_descend
  *   - difficulty MLP (not in the paper; fp64 reference):
  *                                      or_features, or_mlp_forward,
  *                                      or_mlp_bce_backward, or_adam_step
@@ -579,7 +581,7 @@ int64_t or_join(const float *V, int64_t nx, int64_t nq, int d, int metric,
                 const int32_t *adj, int R, int32_t s, const int32_t *parent,
                 const int32_t *qidx, int64_t n, double eps, const or_cfg *cfg,
                 const int32_t *budget, const int32_t *nn_w, const double *nn_d,
-                const uint8_t *nn_ood, int64_t cap, int32_t *oq, int32_t *ox,
+                const uint8_t *nn_ood, const int32_t *qseed, int64_t cap, int32_t *oq, int32_t *ox,
                 double *od, int32_t *stats)
 {
     int64_t N = nx + nq;
@@ -676,7 +678,8 @@ int64_t or_join(const float *V, int64_t nx, int64_t nq, int d, int metric,
         if (nnmap) {
             if (nn_d[qi] < eps) seeds[ns++] = nn_w[qi];
         } else {
-            seeds[ns++] = s;
+            /* per-query seed (the node an upper-layer descent reached), else s */
+            seeds[ns++] = qseed ? qseed[qi] : s;
         }
         if (cfg->merged) {
             stamp[q] = i; /* q is visited, at distance 0, and never in X */
@@ -1271,4 +1274,83 @@ int64_t or_insert_batch(const float *V, int64_t n_old, int64_t n_new, int d, int
     free(knn); free(kd); free(fwd); free(fdeg); free(ocnt); free(off); free(opos);
     free(reach); free(queue);
     return added;
+}
+
+/* ---------------------------------------------------------------------------
+ * HNSW-style upper layers over the data graph (the paper's index-type
+ * experiment, Section 5: the method treats the graph index as a black box,
+ * and HNSW reaches its base layer through a greedy descent over sparser
+ * upper layers).
+ *
+ * Levels: data node v gets L(v) = the number of trailing zero 4-bit digits
+ * of output v + 1 of SplitMix64 (Steele, Lea and Flood 2014) seeded with
+ * `seed`, capped at max_levels.  So P(L >= l) = 16^-l and the layers are
+ * nested.  Layer l (l >= 1) holds the nodes with L >= l; its graph is the
+ * merged-graph recipe over those nodes alone (built by the Python wrapper
+ * with or_build_merged, ids mapped to data ids).
+ *
+ * Descent (reading: HNSW's upper-layer search with a queue of one): from
+ * the top layer's entry, repeatedly move to the neighbour in that layer that
+ * is smallest by (dist(q, .), id) while it is smaller than the current node
+ * by (dist, id); then continue in the next layer down from the node reached.
+ * The node reached in layer 1 seeds the query's greedy phase on the data
+ * graph (or_join's qseed) in place of the data graph's entry.
+ * ---------------------------------------------------------------------------
+ */
+
+/* output k (k >= 1) of SplitMix64 seeded with `seed` */
+uint64_t or_splitmix64(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + k * 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+void or_levels(int64_t n, uint64_t seed, int max_levels, int8_t *lvl)
+{
+    for (int64_t v = 0; v < n; ++v) {
+        uint64_t z = or_splitmix64(seed, (uint64_t)v + 1);
+        int l = 0;
+        while (l < max_levels && (z & 15u) == 0) { ++l; z >>= 4; }
+        lvl[v] = (int8_t)l;
+    }
+}
+
+/* V = [X; Q].  Layer j (0 = layer 1) has rows layer_off[j] .. of adj
+ * ([rows][R], data ids, -1 padded); pos[j * nx + v] is node v's row within
+ * layer j (-1 if absent); entries[j] is layer j's entry.  For each listed
+ * query qidx[i] (query index) writes the seed and the number of moves. */
+void or_descend(const float *V, int64_t nx, int64_t nq, int d, int metric, int nl,
+                const int64_t *layer_off, const int32_t *pos, const int32_t *adj, int R,
+                const int32_t *entries, const int32_t *qidx, int64_t n, int32_t *seed,
+                int32_t *moves)
+{
+    (void)nq;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        const float *qv = V + (nx + (int64_t)qidx[i]) * d;
+        int32_t c = entries[nl - 1];
+        double dc = dist64(qv, V + (int64_t)c * d, d, metric);
+        int32_t mv = 0;
+        for (int j = nl - 1; j >= 0; --j) {
+            for (;;) {
+                const int32_t *row = adj + (layer_off[j] + pos[(int64_t)j * nx + c]) * R;
+                int32_t b = c;
+                double db = dc;
+                for (int k = 0; k < R; ++k) {
+                    int32_t v = row[k];
+                    if (v < 0) continue;
+                    double dv = dist64(qv, V + (int64_t)v * d, d, metric);
+                    if (dv < db || (dv == db && v < b)) { b = v; db = dv; }
+                }
+                if (b == c) break;
+                c = b;
+                dc = db;
+                ++mv;
+            }
+        }
+        seed[i] = c;
+        moves[i] = mv;
+    }
 }
