@@ -319,7 +319,15 @@ def modes_main(args, torch, workloads, vj):
     sep.build_nnmap()
     torch.cuda.synchronize()
     bn = time.time() - t
-    log(f"merged index {bm:.2f}s, separate indexes {bs:.2f}s, NN-Map {bn:.2f}s")
+    # HNSW-style upper layers over the data graph: each separate-index query
+    # may start its greedy phase where a descent through them ends
+    t = time.time()
+    vj.vj_index_build_layers(sep, R=w.R, seed=1)
+    torch.cuda.synchronize()
+    bl = time.time() - t
+    layers = [int(ids.numel()) for ids, _, _ in vj.vj_index_layers(sep)]
+    log(f"merged index {bm:.2f}s, separate indexes {bs:.2f}s, NN-Map {bn:.2f}s, "
+        f"upper layers {layers} {bl:.2f}s")
     gt_qx, _ = vj.vj_bruteforce_join(Q, X, eps, precision="bf16").export(sorted=True)
     gt_keys = gt_qx[:, 0].to(torch.int64) * nx + gt_qx[:, 1].to(torch.int64)
     n_gt = int(gt_keys.numel())
@@ -329,6 +337,9 @@ def modes_main(args, torch, workloads, vj):
         "INLJ": (sep, {"work_sharing": "none"}), "SWS": (sep, {"work_sharing": "soft"}),
         "HWS": (sep, {"work_sharing": "hard"}),
         "NN-Map": (sep, {"work_sharing": "nnmap"}),
+        "INLJ, layer seeds": (sep, {"work_sharing": "none", "layer_seeds": 1}),
+        "SWS, layer seeds": (sep, {"work_sharing": "soft", "layer_seeds": 1}),
+        "HWS, layer seeds": (sep, {"work_sharing": "hard", "layer_seeds": 1}),
     }
     out = {}
     for name, (idx, kw) in modes.items():
@@ -360,7 +371,8 @@ def modes_main(args, torch, workloads, vj):
             "data": "synthetic",
             "config": {"workload": "X=1,000,000 Q=100,000 d=128 integer-valued 256-cluster "
                                    "mixture, L2, eps for mean 50 matches, R=32", "eps": eps},
-            "build_s": {"merged": bm, "separate": bs, "nnmap": bn}, "ground_truth_pairs": n_gt,
+            "build_s": {"merged": bm, "separate": bs, "nnmap": bn, "upper_layers": bl},
+            "upper_layer_sizes": layers, "ground_truth_pairs": n_gt,
             "modes": out}
     print(json.dumps(line), flush=True)
 

@@ -129,6 +129,10 @@ typedef struct {
                                processing order, children waiting on the device for their MST
                                parent; it is switched off while a GPU fault seen with it is
                                investigated. */
+    int32_t layer_seeds;    /* separate indexes with upper layers (vj_index_build_layers): 1
+                               seeds each query's greedy phase with the node its greedy
+                               descent through the layers reaches, in place of the data
+                               graph's entry; 0 (default): the entry */
 } vj_join_params;
 
 void vj_default_build_params(vj_build_params *p);
@@ -490,6 +494,42 @@ vj_status vj_predictor_load(const char *path, void *stream, vj_predictor **out);
  * ascending, >= 0).  The predictor must outlive its use by the index. */
 vj_status vj_index_attach_predictor(vj_index *idx, const vj_predictor *p, float recall_target,
                                     const int32_t *budgets_host);
+
+/*
+ * HNSW-style upper layers over the data nodes of an index (the paper
+ * evaluates the method on HNSW as well as NSG, Section 5; the index is a
+ * black box to the join).  Data node v gets level L(v) = the number of
+ * trailing zero 4-bit digits of output v + 1 of SplitMix64 seeded with
+ * `seed`, capped at max_levels (1..16), so P(L >= l) = 16^-l and the layers
+ * are nested.  Layer l (l >= 1) holds the nodes with L >= l and its graph is
+ * this library's build recipe (exact kNN, RNG prune to R, reverse edges,
+ * connectivity repair, entry nearest to the centroid) over those nodes
+ * alone; layers stop before the first with fewer than two nodes.  Replaces
+ * any layers the index had.  A separate-index join with
+ * vj_join_params.layer_seeds = 1 seeds each query's greedy phase with the
+ * node a greedy descent reaches: from the top layer's entry, repeatedly
+ * move to the neighbour in that layer smallest by (dist(q, .), id) while it
+ * is smaller than the current node, then continue one layer down; the node
+ * reached in layer 1 is the seed.  Layers are not stored by vj_index_save.
+ * R in [1, 64].  Errors: VJ_ERR_INVALID_ARG (null index, R or max_levels
+ * out of range).
+ */
+vj_status vj_index_build_layers(vj_index *idx, int32_t R, uint64_t seed, int32_t max_levels,
+                                void *stream);
+/* Number of layers and their out-degree R (host int32, R may be NULL) and,
+ * for each layer (layer 1 first), its node count and entry (host arrays of
+ * at least *n_layers entries, or NULL). */
+vj_status vj_index_layers_info(const vj_index *idx, int32_t *n_layers, int32_t *R,
+                               int64_t *counts, int32_t *entries);
+/* Layer `layer` (1-based): its data ids, ascending ([count] int32, device)
+ * and its adjacency ([count][R] int32 data ids, -1 padded, device). */
+vj_status vj_index_export_layer(const vj_index *idx, int32_t layer, int32_t *ids, int32_t *adj,
+                                void *stream);
+/* The descent's seed of each listed query (query_ids: device [n] query
+ * indexes, NULL = all; seeds: device [n] data ids; moves: device [n] or
+ * NULL, the number of moves).  Errors: VJ_ERR_INVALID_ARG (no layers). */
+vj_status vj_index_descend(vj_index *idx, const int32_t *query_ids, int64_t n, int32_t *seeds,
+                           int32_t *moves, void *stream);
 
 /* Text of the last error on the calling thread ("" if none). */
 const char *vj_last_error(void);

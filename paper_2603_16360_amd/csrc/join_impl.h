@@ -975,7 +975,10 @@ __device__ __forceinline__ bool run_query_coop(const JoinArgs &a, const WaveMem 
                          (a.hyb == VJ_HYB_BUDGET && a.budget[pos] > 0);
             }
         } else if (wib == 0) {
-            const int32_t sv = lane == 0 ? a.entry : lane == 1 ? pcache : -1;
+            // the data graph's entry, or the query's own seed (the node its
+            // descent through upper layers reached)
+            const int32_t s0 = a.qseed ? a.qseed[qi] : a.entry;
+            const int32_t sv = lane == 0 ? s0 : lane == 1 ? pcache : -1;
             coop_batch<T, DP, W, PGC>(a, m, sh, cw, qf, sv, false, false, heap_cap, lane, true);
             for (int t = 0; t < pcnt && t < a.nx + 64; t += 64) {
                 const int32_t u = t + lane < pcnt ? a.out_x[pseg + t + lane] : -1;

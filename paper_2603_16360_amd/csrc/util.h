@@ -8,6 +8,16 @@ namespace vj {
 void launch_dist_to_node(const float *vec, int dp, int64_t first, int64_t n, int32_t node,
                          float *out, hipStream_t s);
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+// upper layers: row gather, local -> data ids, positions, greedy descent
+// (see k_descend)
+void gather_rows_f32(const float *src, int dp, const int32_t *ids, int64_t n, float *dst,
+                     hipStream_t s);
+void map_ids(int32_t *adj, int64_t n, const int32_t *ids, hipStream_t s);
+void scatter_pos(int32_t *pos, const int32_t *ids, int64_t n, hipStream_t s);
+void descend(const float *vec, int dp, int64_t nx, int metric, int nl, const int64_t *loff,
+             const int64_t *lcnt, const int32_t *lpos, const int32_t *ladj, int R, int32_t top,
+             const int32_t *qids, int64_t n, int32_t *seed_i, int32_t *seed_q, int32_t *moves,
+             int32_t *err, hipStream_t s);
 // counter calibration gather (the join's row-read layout); see vj_calib_gather
 void calib_gather(const float *rows, int64_t nrows, int dp, const int32_t *ids, int64_t n,
                   float *out, hipStream_t s);

@@ -475,6 +475,137 @@ void launch_dist_to_node(const float *vec, int dp, int64_t first, int64_t n, int
     hipLaunchKernelGGL(k_dist_to_node, dim3(grid1(n)), dim3(256), 0, s, vec, dp, first, n, node, out);
 }
 
+// ----------------------------------------------------- upper layers --
+// dst[i][:] = src[ids[i]][:] (rows of dp floats)
+__global__ void k_gather_rows_f32(const float *src, int dp, const int32_t *ids, int64_t n,
+                                  float *dst) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * (dp / 4)) return;
+    const int64_t i = e / (dp / 4), c = e - i * (dp / 4);
+    reinterpret_cast<float4 *>(dst + i * dp)[c] =
+        reinterpret_cast<const float4 *>(src + (int64_t)ids[i] * dp)[c];
+}
+
+// adj[e] = ids[adj[e]] for every entry >= 0 (local row -> data id)
+__global__ void k_map_ids(int32_t *adj, int64_t n, const int32_t *ids) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n && adj[e] >= 0) adj[e] = ids[adj[e]];
+}
+
+// pos[ids[i]] = i
+__global__ void k_scatter_pos(int32_t *pos, const int32_t *ids, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) pos[ids[i]] = (int32_t)i;
+}
+
+// Greedy descent through the upper layers, one wave per query: from the top
+// layer's entry, move to the neighbour smallest by (distance, id) while it
+// is smaller than the current node, then one layer down; 8 lanes per
+// neighbour row (16-byte loads), fp32 distances (squared for L2).  The
+// moves of a layer are bounded by its node count (each move strictly
+// decreases (distance, id)).
+__global__ void __launch_bounds__(256)
+k_descend(const float *vec, int dp, int64_t nx, int metric, int nl, const int64_t *loff,
+          const int64_t *lcnt, const int32_t *lpos, const int32_t *ladj, int R, int32_t top,
+          const int32_t *qids, int64_t n, int32_t *seed_i, int32_t *seed_q, int32_t *moves,
+          int32_t *err) {
+    const int lane = threadIdx.x & 63, g = lane >> 3, p = lane & 7;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const int32_t qi = qids ? qids[i] : (int32_t)i;
+    const float4 *q = reinterpret_cast<const float4 *>(vec + (nx + qi) * dp);
+    auto dist = [&](int32_t v) {  // every lane of the 8-lane group gets it
+        const float4 *x = reinterpret_cast<const float4 *>(vec + (int64_t)v * dp);
+        float acc = 0.f;
+        for (int c = p; c < dp / 4; c += 8) {
+            const float4 a = q[c], b = x[c];
+            if (metric == VJ_L2) {
+                float t = a.x - b.x; acc = fmaf(t, t, acc);
+                t = a.y - b.y; acc = fmaf(t, t, acc);
+                t = a.z - b.z; acc = fmaf(t, t, acc);
+                t = a.w - b.w; acc = fmaf(t, t, acc);
+            } else {
+                acc = fmaf(a.x, b.x, acc); acc = fmaf(a.y, b.y, acc);
+                acc = fmaf(a.z, b.z, acc); acc = fmaf(a.w, b.w, acc);
+            }
+        }
+        acc += __shfl_xor(acc, 4);
+        acc += __shfl_xor(acc, 2);
+        acc += __shfl_xor(acc, 1);
+        return metric == VJ_L2 ? acc : 1.f - acc;
+    };
+    int32_t c = top;
+    float dc = dist(c);
+    int32_t mv = 0;
+    for (int j = nl - 1; j >= 0; --j) {
+        for (int64_t it = 0; it < lcnt[j]; ++it) {
+            const int32_t r = lpos[(int64_t)j * nx + c];
+            if (r < 0) {  // the layers are nested: cannot happen
+                if (lane == 0) atomicOr(err, 1);
+                break;
+            }
+            const int32_t *row = ladj + (loff[j] + r) * R;
+            float bd = dc;
+            int32_t bv = c;
+            for (int b0 = 0; b0 < R; b0 += 8) {
+                const int k = b0 + g;
+                const int32_t v = k < R ? row[k] : -1;
+                // every lane of the group evaluates (a padding slot evaluates c)
+                const bool ok = v >= 0 && v < nx;
+                const float dv = dist(ok ? v : c);
+                if (ok && (dv < bd || (dv == bd && v < bv))) { bd = dv; bv = v; }
+            }
+            // the smallest (distance, id) over the eight groups
+#pragma unroll
+            for (int off = 8; off < 64; off <<= 1) {
+                const float od = __shfl_xor(bd, off);
+                const int32_t ov = __shfl_xor(bv, off);
+                if (od < bd || (od == bd && ov < bv)) { bd = od; bv = ov; }
+            }
+            if (bv == c) break;
+            c = bv;
+            dc = bd;
+            ++mv;
+        }
+    }
+    if (lane == 0) {
+        if (seed_i) seed_i[i] = c;
+        if (seed_q) seed_q[qi] = c;
+        if (moves) moves[i] = mv;
+    }
+}
+
+void gather_rows_f32(const float *src, int dp, const int32_t *ids, int64_t n, float *dst,
+                     hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather_rows_f32, dim3(grid1(n * (dp / 4))), dim3(256), 0, s, src, dp, ids,
+                       n, dst);
+    VJ_HIP(hipGetLastError());
+}
+
+void map_ids(int32_t *adj, int64_t n, const int32_t *ids, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_map_ids, dim3(grid1(n)), dim3(256), 0, s, adj, n, ids);
+    VJ_HIP(hipGetLastError());
+}
+
+void scatter_pos(int32_t *pos, const int32_t *ids, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_scatter_pos, dim3(grid1(n)), dim3(256), 0, s, pos, ids, n);
+    VJ_HIP(hipGetLastError());
+}
+
+void descend(const float *vec, int dp, int64_t nx, int metric, int nl, const int64_t *loff,
+             const int64_t *lcnt, const int32_t *lpos, const int32_t *ladj, int R, int32_t top,
+             const int32_t *qids, int64_t n, int32_t *seed_i, int32_t *seed_q, int32_t *moves,
+             int32_t *err, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_descend, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, vec, dp, nx,
+                       metric, nl, loff, lcnt, lpos, ladj, R, top, qids, n, seed_i, seed_q, moves,
+                       err);
+    VJ_HIP(hipGetLastError());
+}
+
 // Counter calibration: out[i] = sum of row ids[i] of rows [nrows][dp]
 // (fp32, dp a multiple of 32), read as the join reads a row: 8 lanes per
 // row, 16 bytes per lane per load, each load of the 8-lane group covering

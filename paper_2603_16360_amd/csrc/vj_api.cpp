@@ -295,6 +295,7 @@ static JoinArgs make_args(const Index &ix, int prec, const vj_join_params &p, in
     a.hyb = p.hybrid;
     a.merged = ix.separate ? 0 : 1;
     a.gbeam = p.greedy_beam;
+    a.qseed = p.layer_seeds && ix.separate && ix.lay_n > 0 ? ix.lay_seed.as<int32_t>() : nullptr;
     a.nn_w = ix.has_nnmap ? ix.nn_w.as<int32_t>() : nullptr;
     a.nn_d = ix.has_nnmap ? ix.nn_d.as<double>() : nullptr;
     a.nn_ood = ix.has_nnmap ? ix.nn_ood.as<uint8_t>() : nullptr;
@@ -326,8 +327,25 @@ static int join_precision(Index &ix, int prec, hipStream_t s) {
     return prec;
 }
 
+// the seeds of the listed queries (ids: query indexes, null = all) from the
+// greedy descent through the index's upper layers, into ix.lay_seed[qi]
+static void layer_seeds(Index &ix, const int32_t *ids, int64_t n, int32_t *seed_i, int32_t *moves,
+                        hipStream_t s) {
+    DevBuf err(sizeof(int32_t));
+    VJ_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), s));
+    descend(ix.vec.as<float>(), ix.dp, ix.nx, ix.metric, ix.lay_n, ix.lay_offd.as<int64_t>(),
+            ix.lay_offd.as<int64_t>() + ix.lay_n, ix.lay_pos.as<int32_t>(), ix.lay_adj.as<int32_t>(),
+            ix.lay_R, ix.lay_entry.back(), ids, n, seed_i, seed_i ? nullptr : ix.lay_seed.as<int32_t>(),
+            moves, err.as<int32_t>(), s);
+    int32_t e = 0;
+    VJ_HIP(hipMemcpyAsync(&e, err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    VJ_CHECK(e == 0, VJ_ERR_INTERNAL, "upper layers are not nested");
+}
+
 static void run_join(Index &ix, const int32_t *ids, int64_t n, float eps, const vj_join_params &p,
                      const int32_t *budget, hipStream_t s, Pairs &r) {
+    if (p.layer_seeds && ix.separate && ix.lay_n > 0) layer_seeds(ix, ids, n, nullptr, nullptr, s);
     const int ws = p.work_sharing, hyb = p.hybrid;
     const int prec = join_precision(ix, p.precision, s);
     // bf16 rows run on the workgroup tiers (they carry the margin re-check)
@@ -1089,6 +1107,7 @@ void vj_default_join_params(vj_join_params *p) {
     p->pair_capacity = 0;
     p->greedy_beam = 256;
     p->persistent = 0;
+    p->layer_seeds = 0;
 }
 
 const char *vj_last_error(void) { return vj::last_error(); }
@@ -1100,6 +1119,138 @@ vj_status vj_calib_gather(const float *rows, int64_t nrows, int32_t dp, const in
     VJ_CHECK(dp > 0 && dp % 32 == 0, VJ_ERR_INVALID_ARG, "dp must be a positive multiple of 32");
     VJ_CHECK(n == 0 || (rows && ids && out), VJ_ERR_INVALID_ARG, "null pointer");
     calib_gather(rows, nrows, dp, ids, n, out, (hipStream_t)stream);
+    API_END
+}
+
+// output k (k >= 1) of SplitMix64 seeded with `seed` (Steele, Lea and Flood 2014)
+static uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + k * 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+vj_status vj_index_build_layers(vj_index *idx, int32_t R, uint64_t seed, int32_t max_levels,
+                                void *stream) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr, VJ_ERR_INVALID_ARG, "null index");
+    VJ_CHECK(R >= 1 && R <= 64, VJ_ERR_INVALID_ARG, "R must be in [1, 64]");
+    VJ_CHECK(max_levels >= 1 && max_levels <= 16, VJ_ERR_INVALID_ARG, "max_levels in [1, 16]");
+    Index &ix = idx->impl;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nx = ix.nx;
+    // levels: trailing zero 4-bit digits of each data node's output
+    std::vector<int> lvl((size_t)nx);
+    for (int64_t v = 0; v < nx; ++v) {
+        uint64_t z = splitmix64_at(seed, (uint64_t)v + 1);
+        int l = 0;
+        while (l < max_levels && (z & 15u) == 0) { ++l; z >>= 4; }
+        lvl[(size_t)v] = l;
+    }
+    std::vector<std::vector<int32_t>> sets;
+    for (int l = 1; l <= max_levels; ++l) {
+        std::vector<int32_t> sel;
+        for (int64_t v = 0; v < nx; ++v)
+            if (lvl[(size_t)v] >= l) sel.push_back((int32_t)v);
+        if (sel.size() < 2) break;
+        sets.push_back(std::move(sel));
+    }
+    const int nl = (int)sets.size();
+    ix.lay_n = 0;
+    ix.lay_R = R;
+    ix.lay_off.assign((size_t)nl, 0);
+    ix.lay_cnt.assign((size_t)nl, 0);
+    ix.lay_entry.assign((size_t)nl, 0);
+    int64_t total = 0;
+    for (int j = 0; j < nl; ++j) {
+        ix.lay_off[(size_t)j] = total;
+        ix.lay_cnt[(size_t)j] = (int64_t)sets[(size_t)j].size();
+        total += ix.lay_cnt[(size_t)j];
+    }
+    if (nl > 0) {
+        ix.lay_adj.alloc((size_t)total * R * sizeof(int32_t));
+        ix.lay_ids.alloc((size_t)total * sizeof(int32_t));
+        ix.lay_pos.alloc((size_t)nl * nx * sizeof(int32_t));
+        fill_i32(ix.lay_pos.as<int32_t>(), nl * nx, -1, s);
+        const int kc = std::min(2 * R, 112);
+        for (int j = 0; j < nl; ++j) {
+            const int64_t n = ix.lay_cnt[(size_t)j];
+            int32_t *ids = ix.lay_ids.as<int32_t>() + ix.lay_off[(size_t)j];
+            VJ_HIP(hipMemcpyAsync(ids, sets[(size_t)j].data(), (size_t)n * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, s));
+            Index part;
+            part.nq = 0; part.nx = n; part.N = n; part.d = ix.d; part.dp = ix.dp; part.R = R;
+            part.metric = ix.metric;
+            part.vec.alloc((size_t)n * ix.dp * sizeof(float));
+            gather_rows_f32(ix.vec.as<float>(), ix.dp, ids, n, part.vec.as<float>(), s);
+            build_graph(part, (int)std::min<int64_t>(kc, n - 1), s);
+            int32_t *dst = ix.lay_adj.as<int32_t>() + ix.lay_off[(size_t)j] * R;
+            VJ_HIP(hipMemcpyAsync(dst, part.adj.p, (size_t)n * R * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, s));
+            map_ids(dst, n * R, ids, s);
+            scatter_pos(ix.lay_pos.as<int32_t>() + (int64_t)j * nx, ids, n, s);
+            ix.lay_entry[(size_t)j] = sets[(size_t)j][(size_t)part.entry];
+            VJ_HIP(hipStreamSynchronize(s));
+        }
+        std::vector<int64_t> oc(ix.lay_off);
+        oc.insert(oc.end(), ix.lay_cnt.begin(), ix.lay_cnt.end());
+        ix.lay_offd.alloc(oc.size() * sizeof(int64_t));
+        VJ_HIP(hipMemcpyAsync(ix.lay_offd.p, oc.data(), oc.size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s));
+        ix.lay_seed.alloc((size_t)std::max<int64_t>(ix.nq, 1) * sizeof(int32_t));
+        fill_i32(ix.lay_seed.as<int32_t>(), std::max<int64_t>(ix.nq, 1), ix.entry, s);
+    }
+    VJ_HIP(hipStreamSynchronize(s));
+    ix.lay_n = nl;
+    API_END
+}
+
+vj_status vj_index_layers_info(const vj_index *idx, int32_t *n_layers, int32_t *R,
+                               int64_t *counts, int32_t *entries) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr && n_layers != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    const Index &ix = idx->impl;
+    *n_layers = ix.lay_n;
+    if (R) *R = ix.lay_R;
+    for (int j = 0; j < ix.lay_n; ++j) {
+        if (counts) counts[j] = ix.lay_cnt[(size_t)j];
+        if (entries) entries[j] = ix.lay_entry[(size_t)j];
+    }
+    API_END
+}
+
+vj_status vj_index_export_layer(const vj_index *idx, int32_t layer, int32_t *ids, int32_t *adj,
+                                void *stream) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr, VJ_ERR_INVALID_ARG, "null index");
+    const Index &ix = idx->impl;
+    VJ_CHECK(layer >= 1 && layer <= ix.lay_n, VJ_ERR_INVALID_ARG, "no such layer");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t off = ix.lay_off[(size_t)layer - 1], n = ix.lay_cnt[(size_t)layer - 1];
+    if (ids)
+        VJ_HIP(hipMemcpyAsync(ids, ix.lay_ids.as<int32_t>() + off, (size_t)n * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, s));
+    if (adj)
+        VJ_HIP(hipMemcpyAsync(adj, ix.lay_adj.as<int32_t>() + off * ix.lay_R,
+                              (size_t)n * ix.lay_R * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
+vj_status vj_index_descend(vj_index *idx, const int32_t *query_ids, int64_t n, int32_t *seeds,
+                           int32_t *moves, void *stream) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr && seeds != nullptr, VJ_ERR_INVALID_ARG, "null pointer");
+    Index &ix = idx->impl;
+    VJ_CHECK(ix.lay_n > 0, VJ_ERR_INVALID_ARG, "the index has no upper layers");
+    VJ_CHECK(n >= 0 && (query_ids != nullptr || n == ix.nq), VJ_ERR_INVALID_ARG,
+             "n must be nq when query_ids is null");
+    if (query_ids != nullptr && n > 0) {
+        std::vector<int32_t> h((size_t)n);
+        VJ_HIP(hipMemcpy(h.data(), query_ids, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int32_t q : h) VJ_CHECK(q >= 0 && q < ix.nq, VJ_ERR_INVALID_ARG, "query id out of range");
+    }
+    layer_seeds(ix, query_ids, n, seeds, moves, (hipStream_t)stream);
     API_END
 }
 
@@ -1467,6 +1618,8 @@ vj_status vj_join(vj_index *idx, const int32_t *query_ids, int64_t n, float eps,
              "learned routing needs the merged index (its features come from the probe of q)");
     VJ_CHECK(p.greedy_beam >= 1 && p.greedy_beam <= 256, VJ_ERR_INVALID_ARG,
              "greedy_beam in [1, 256]");
+    VJ_CHECK(p.layer_seeds == 0 || (ix.separate && ix.lay_n > 0), VJ_ERR_INVALID_ARG,
+             "layer seeds need a separate index with upper layers (vj_index_build_layers)");
     // the persistent launch faulted the GPU once in soft work-sharing mode
     // and its cause is not established: it is switched off until it is
     VJ_CHECK(p.persistent == 0, VJ_ERR_UNSUPPORTED,

@@ -159,6 +159,14 @@ struct Index {
     // NN-Map of the queries (Section 6): witness, its distance, OOD bit
     DevBuf nn_w, nn_d, nn_ood;
     bool has_nnmap = false;
+    // HNSW-style upper layers over the data nodes (layer 1 first): row
+    // offsets, node counts and entries of each layer; adjacency [rows][lay_R]
+    // in data ids; lay_pos [layers][nx] the row of node v in each layer (-1:
+    // absent); lay_seed [nq] the seeds of the last descent
+    int32_t lay_n = 0, lay_R = 0;
+    std::vector<int64_t> lay_off, lay_cnt;
+    std::vector<int32_t> lay_entry;
+    DevBuf lay_adj, lay_pos, lay_ids, lay_offd, lay_seed;
     int64_t repairs = 0;  // connectivity-repair edges added by the build
     // join state shared by calls on this index (calls on one index must not overlap)
     DevBuf cache;    // int32 [nq] soft work sharing: closest visited data node
@@ -212,6 +220,7 @@ struct JoinArgs {
     const double *nn_d;       // [nq] its distance (join metric, fp64)
     const uint8_t *nn_ood;    // [nq] OOD bit
     int32_t gbeam;            // separate indexes: greedy queue bound (cfg.greedy_beam_size)
+    const int32_t *qseed;     // separate indexes: [nq] per-query seed in place of the entry (null: entry)
     float ood_ratio;
     int32_t gen;              // stamp of this call in inb[]
     const int32_t *parent;    // [nq] MST parent node id (-1: entry)

@@ -51,7 +51,7 @@ class vj_join_params(C.Structure):
                 ("budget", C.c_void_p), ("start_tier", C.c_int32),
                 ("coop_tables", C.c_int32), ("pair_capacity", C.c_int64),
                 ("dense_first", C.c_int32), ("greedy_beam", C.c_int32),
-                ("persistent", C.c_int32)]
+                ("persistent", C.c_int32), ("layer_seeds", C.c_int32)]
 
 
 _vp, _i64, _i32, _f32 = C.c_void_p, C.c_int64, C.c_int32, C.c_float
@@ -113,6 +113,10 @@ _SIGS = {
     "vj_index_attach_predictor": (C.c_int, [_vp, _vp, _f32, _vp]),
     "vj_last_error": (C.c_char_p, []),
     "vj_calib_gather": (C.c_int, [_vp, _i64, _i32, _vp, _i64, _vp, _vp]),
+    "vj_index_build_layers": (C.c_int, [_vp, _i32, C.c_uint64, _i32, _vp]),
+    "vj_index_layers_info": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "vj_index_export_layer": (C.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "vj_index_descend": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -267,7 +271,7 @@ def vj_index_load(path: str) -> Index:
 
 def join_params(work_sharing="self", hybrid="off", hybrid_beam=256, conv_threshold=10,
                 ood_ratio=1.5, precision="fp32", budget=None, start_tier=1, coop_tables=0,
-                pair_capacity=0, dense_first=1, greedy_beam=256, persistent=0):
+                pair_capacity=0, dense_first=1, greedy_beam=256, persistent=0, layer_seeds=0):
     p = vj_join_params()
     _lib.vj_default_join_params(C.byref(p))
     p.work_sharing = WORK_SHARING[work_sharing]
@@ -283,6 +287,7 @@ def join_params(work_sharing="self", hybrid="off", hybrid_beam=256, conv_thresho
     p.dense_first = dense_first
     p.greedy_beam = greedy_beam
     p.persistent = persistent
+    p.layer_seeds = layer_seeds
     return p
 
 
@@ -574,6 +579,40 @@ def vj_index_attach_predictor(index: Index, pred: Predictor | None, recall_targe
 
 def vj_last_error() -> str:
     return _lib.vj_last_error().decode()
+
+
+def vj_index_build_layers(index: Index, R: int = 16, seed: int = 1, max_levels: int = 8):
+    """HNSW-style upper layers over the data nodes (see include/vj.h)."""
+    _check(_lib.vj_index_build_layers(index._h, R, seed, max_levels, _stream()))
+
+
+def vj_index_layers(index: Index):
+    """[(data ids, adjacency [n][R], entry)] of each upper layer, layer 1 first."""
+    nl, R = C.c_int32(), C.c_int32()
+    _check(_lib.vj_index_layers_info(index._h, C.byref(nl), C.byref(R), None, None))
+    counts = (C.c_int64 * max(1, nl.value))()
+    entries = (C.c_int32 * max(1, nl.value))()
+    _check(_lib.vj_index_layers_info(index._h, C.byref(nl), C.byref(R), counts, entries))
+    out = []
+    for j in range(nl.value):
+        ids = torch.empty(counts[j], dtype=torch.int32, device="cuda")
+        adj = torch.empty((counts[j], R.value), dtype=torch.int32, device="cuda")
+        _check(_lib.vj_index_export_layer(index._h, j + 1, _ptr(ids), _ptr(adj), _stream()))
+        out.append((ids, adj, entries[j]))
+    return out
+
+
+def vj_index_descend(index: Index, query_ids: torch.Tensor | None = None):
+    """(seed, moves) of each listed query's descent through the upper layers."""
+    n = index.info()["nq"] if query_ids is None else int(query_ids.numel())
+    qp = C.c_void_p(0)
+    if query_ids is not None:
+        query_ids = _dev(query_ids, torch.int32, "query_ids")
+        qp = _ptr(query_ids)
+    seed = torch.empty(n, dtype=torch.int32, device="cuda")
+    moves = torch.empty(n, dtype=torch.int32, device="cuda")
+    _check(_lib.vj_index_descend(index._h, qp, n, _ptr(seed), _ptr(moves), _stream()))
+    return seed, moves
 
 
 def vj_calib_gather(rows: torch.Tensor, ids: torch.Tensor) -> torch.Tensor:
