@@ -26,7 +26,12 @@ MAKERS = {
     "mid": lambda: workloads.config_mid(),
     # the OOD workload at 1/10 scale (X = 200,000 x 768, 20,000 test queries)
     "ood": lambda: workloads.config_ood(scale=0.1),
+    # and at its stated size (X = 2,000,000 x 768, 200,000 test queries)
+    "ood_full": lambda: workloads.config_ood(scale=1.0),
+    # the high-dimensional workload (X = 1,000,000 x 960, 10,000 queries)
+    "highdim": lambda: workloads.config_highdim(),
 }
+SCALES = {"ood": 0.1}
 
 # the batched stream at 1/10 scale: X = 1,000,000 x 96; 200 batches of
 # 100..10,000 queries; eps per batch for the batch's target mean, calibrated
@@ -75,7 +80,7 @@ def main(names):
         eps = oracle.calibrate_eps(w.Q[idx], w.X, w.target_matches, w.metric,
                                    integer=bool(w.meta.get("integer")))
         data[name] = {"eps": eps, "metric": w.metric, "target_mean_matches": w.target_matches,
-                      "scale": 0.1 if name == "ood" else 1.0,
+                      "scale": SCALES.get(name, 1.0),
                       "sample_queries": int(idx.size), "sample_seed": w.eps_sample_seed,
                       "Q_sha": checksum(w.Q), "X_sha": checksum(w.X),
                       "nq": int(w.Q.shape[0]), "nx": int(w.X.shape[0]), "d": w.d}

@@ -263,14 +263,18 @@ def config_highdim(scale: float = 1.0) -> Workload:
                     {"clusters": k})
 
 
-def config_ood(scale: float = 1.0, train: bool = False) -> Workload:
+def config_ood(scale: float = 1.0, train: bool = False, ood_mean_cos: float = 0.92) -> Workload:
     """X=2,000,000 unit vectors, d=768, 512-cluster vMF mixture, inner product.
 
     Means uniform on the sphere (seed 401); κ gives E[cos to mean] = 0.7.
     Q=200,000: 70% from the same mixture, 30% from means rotated 40 degrees
-    away (seed 403).  ``train=True`` gives 125,000 training queries from the
-    same recipe with seed 404 (never the test queries).  ε for a mean of
-    20 matches.  Stands in for the OOD sets (COCO, ImageNet, LAION).
+    away (seed 403), concentrated at E[cos to the shifted mean] =
+    ``ood_mean_cos``.  With 0.92 an OOD query's nearest nodes in Q ∪ X are
+    other OOD queries (its merged-graph neighbourhood holds no data node),
+    yet at the shared ε (pooled mean of 20 matches) it has about as many
+    matches as an in-distribution query.  ``train=True`` gives 125,000
+    training queries from the same recipe with seed 404 (never the test
+    queries).  Stands in for the OOD sets (COCO, ImageNet, LAION).
     """
     d, k = 768, 512
     means = _random_unit(_rng(401), k, d)
@@ -282,12 +286,12 @@ def config_ood(scale: float = 1.0, train: bool = False) -> Workload:
     rng = _rng(qseed + 1000)
     shifted = _rotate_away(rng, means, 40.0)
     q_id = vmf_mixture(nq - n_ood, means, kappa, qseed)
-    q_ood = vmf_mixture(n_ood, shifted, kappa, qseed + 2000)
+    q_ood = vmf_mixture(n_ood, shifted, vmf_kappa_for_mean_cosine(d, ood_mean_cos), qseed + 2000)
     Q = np.concatenate([q_id, q_ood], axis=0)
     is_ood = np.zeros(nq, dtype=bool)
     is_ood[nq - n_ood:] = True
     return Workload("ood", Q, X, "ip", 32, 20.0, 405, min(2_000, nq),
-                    {"clusters": k, "kappa": kappa, "is_ood": is_ood})
+                    {"clusters": k, "kappa": kappa, "is_ood": is_ood, "ood_mean_cos": ood_mean_cos})
 
 
 def config_stream(scale: float = 1.0, n_batches: int = 200) -> Workload:
