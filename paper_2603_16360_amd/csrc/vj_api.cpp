@@ -651,9 +651,14 @@ static void learned_join(Index &ix, const int32_t *ids, int64_t n, float eps, vj
     VJ_HIP(hipMemcpyAsync(rl.p, routed.data(), nr * sizeof(int32_t), hipMemcpyHostToDevice, s));
     gather_rows(ix.vec.as<float>() + (size_t)ix.nx * ix.dp, ix.dp, rl.as<int32_t>(), nr,
                 rows.as<float>(), s);
+    // the exact join on MFMA tiles: with low-precision rows the one-term bf16
+    // tiles (a proven margin, fp64 re-check; a third of the fp32 form's
+    // MFMA work), else the three-term form; both give the exact pair set
+    const vj_precision rp = p.precision == VJ_PREC_BF16 || p.precision == VJ_PREC_FP8
+                                ? VJ_PREC_BF16 : VJ_PREC_FP32;
     Pairs bp;
-    bruteforce_join(rows.as<float>(), nr, ix.vec.as<float>(), ix.nx, ix.dp, eps, ix.metric,
-                    VJ_PREC_FP32, s, bp);
+    bruteforce_join(rows.as<float>(), nr, ix.vec.as<float>(), ix.nx, ix.dp, eps, ix.metric, rp, s,
+                    bp);
     if (bp.count == 0) return;
     remap_ids(bp.q.as<int32_t>(), bp.count, rl.as<int32_t>(), s);
     const int64_t tot = r.count + bp.count;
