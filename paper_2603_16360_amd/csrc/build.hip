@@ -186,7 +186,13 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
 
 // kNN sweep with the rows' fragments held in registers (Kp <= 256).
 // A workgroup of 4 waves owns 4 * RT * 16 rows (RT row tiles of 16 per wave)
-// and sweeps the columns [cb, ce) of its split (blockIdx.y) 32 at a time.
+// of the call's rows, taken in a given processing order (rowperm), and
+// sweeps the column tiles of its split (blockIdx.y) 32 columns at a time.
+// The columns come as a copy in sweep order (node ids bid_of, +inf norms
+// and id -1 past the last node, whole tiles); a row block starts at its own
+// start tile and wraps around.  When rows and columns are ordered by their
+// nearest pivot node, a block first meets the columns nearest to its rows,
+// so its thresholds tighten in the first tiles and few later columns pass.
 // Column tiles stream through a ring of NB LDS stages filled by direct
 // global-to-LDS loads (global_load_lds_dwordx4), NB - 1 tiles ahead of the
 // tile being multiplied, so the loads' latency hides behind NB - 2 tiles of
@@ -194,14 +200,14 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
 // bytes (one pad chunk), which spreads a fragment read's 16 rows over
 // distinct banks.  Every wave issues the same number of load instructions
 // per tile (slots past the tile load a real chunk into the pad area), so a
-// fixed vmcnt marks the tile as landed.
+// fixed vmcnt marks the tile as landed.  The tile's norms and node ids are
+// staged beside it (each wave its own copy).
 // Per element the epilogue is one fma (key = |x|^2 - 2<u,x>, the order of
 // |u-x|^2 for a fixed row u) and one compare against the row's threshold;
 // a wave takes the append path only for a 16 x 16 tile where some element
 // passes.  Thresholds are the K-th key of the last merge (FLT_MAX until a
 // row holds K entries), so every element of the final top-K passes when it
-// is seen.  Columns outside [cb, ce) get |x|^2 = +inf and never pass; rows
-// outside [rb, rb + M) get threshold -inf.
+// is seen, whatever the order.  Rows past the call's M get threshold -inf.
 template <int NSPLIT, int KP>
 struct KnnReg {
     static constexpr int KS = KP / 32;                 // MFMA k-steps of 32
@@ -214,10 +220,11 @@ struct KnnReg {
     static constexpr int SPR = CPR + 1;                // staged slots per row
     static constexpr int IPW = (BN * SPR + 255) / 256; // load instructions per wave and part
     static constexpr int PART = 4 * IPW * 1024;        // bytes of one part of a stage
-    static constexpr int STAGE = TERMS * PART + 4 * 256;  // + each wave's copy of |x|^2
-    static constexpr int NB0 = (76 * 1024) / STAGE;
+    // + each wave's copy of the tile's |x|^2 and node ids
+    static constexpr int STAGE = TERMS * PART + 2 * 4 * 256;
+    static constexpr int NB0 = (78 * 1024) / STAGE;  // two workgroups per CU fit in 160 KB
     static constexpr int NB = NB0 > 8 ? 8 : NB0;       // stages in the ring
-    static constexpr int LPT = TERMS * IPW + 1;        // load instructions per wave and tile
+    static constexpr int LPT = TERMS * IPW + 2;        // load instructions per wave and tile
     static constexpr bool OK = KP % 32 == 0 && KP <= 256 && NB >= 3 && (NB - 2) * LPT <= 60;
 };
 
@@ -338,73 +345,80 @@ __device__ __noinline__ float knn_merge_row(float *bkey, int32_t *bid, int64_t o
 
 template <int NSPLIT, int KP>
 __global__ void __launch_bounds__(256, 2)
-k_knn_reg(const uint16_t *Ah, const uint16_t *Al, int32_t N, const float *n2, int K,
-          float *bkey, int32_t *bid, int32_t rb, int32_t M, int32_t cols_per_split) {
+k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_t M,
+          const uint16_t *Bh, const uint16_t *Bl, const float *bn2, const int32_t *bid_of,
+          int32_t T, const int32_t *start_tile, int32_t tiles_per_split, int K, float *bkey,
+          int32_t *bid, int32_t rb) {
     using S = KnnReg<NSPLIT, KP>;
     constexpr int RT = S::RT, CT = S::CT, KS = S::KS, BN = S::BN, CPR = S::CPR, SPR = S::SPR;
     constexpr int IPW = S::IPW, TERMS = S::TERMS, PART = S::PART, STAGE = S::STAGE, NB = S::NB;
     constexpr int LPT = S::LPT;
     __shared__ __attribute__((aligned(1024))) char ring[NB * STAGE];
     __shared__ float s_tau[4][RT * 16];
+    __shared__ int32_t s_node[4][RT * 16];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r16 = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4, grp = lane >> 4;
-    const int32_t wrow0 = rb + (int32_t)blockIdx.x * S::ROWS + w * RT * 16;  // wave's first row
-    const int32_t rend = rb + M;
-    const int32_t cb = (int32_t)blockIdx.y * cols_per_split;
-    const int32_t ce = min(N, cb + cols_per_split);
+    const int32_t prow0 = (int32_t)blockIdx.x * S::ROWS + w * RT * 16;  // wave's first row (order)
     const int64_t boff = (int64_t)blockIdx.y * M;  // this split's buffer rows
+    // this split's sweep positions [jb, je); position j is tile (t0 + j) % T
+    const int32_t jb = (int32_t)blockIdx.y * tiles_per_split;
+    const int32_t je = min(T, jb + tiles_per_split);
+    const int32_t t0 = start_tile[blockIdx.x];
     // a row is cut back to K once it holds more than merge_at entries: the
     // threshold then tightens early, which keeps the appends few
     const int merge_at = min(K + 96, kKnnCap - BN);
     // entries held by the wave's row r: lane r of cnt
     int cnt = 0;
-    if (lane < RT * 16) s_tau[w][lane] = wrow0 + lane < rend ? FLT_MAX : -INFINITY;
+    if (lane < RT * 16) {
+        const int32_t node = prow0 + lane < M ? rowperm[prow0 + lane] : -1;
+        s_node[w][lane] = node;
+        s_tau[w][lane] = node >= 0 ? FLT_MAX : -INFINITY;
+    }
 
     // the wave's rows: fragment (rt, ks) holds row rt*16 + (lane & 15),
     // dimensions ks*32 + (lane >> 4)*8 .. +7
     mt::bf16x8 a[RT][KS], al[NSPLIT == 3 ? RT : 1][NSPLIT == 3 ? KS : 1];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int rt = 0; rt < RT; ++rt) {
+        const int32_t pr = prow0 + rt * 16 + r16;
+        const int32_t node = pr < M ? rowperm[pr] : -1;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            a[rt][ks] = mt::load8(Ah, wrow0 + rt * 16 + r16, rend, KP, ks * 32 + kq);
-            if (NSPLIT == 3) al[rt][ks] = mt::load8(Al, wrow0 + rt * 16 + r16, rend, KP, ks * 32 + kq);
+            a[rt][ks] = mt::load8(Ah, node < 0 ? 0 : node, node < 0 ? 0 : node + 1, KP, ks * 32 + kq);
+            if (NSPLIT == 3)
+                al[rt][ks] = mt::load8(Al, node < 0 ? 0 : node, node < 0 ? 0 : node + 1, KP, ks * 32 + kq);
         }
+    }
 
     // loads of the tile at column c0 into stage st: slot s of a part is
     // row s / SPR, chunk s % SPR; pad chunks and slots past the tile load
-    // the tile's first chunk; rows past N load row N - 1 (masked by |x|^2).
-    // A lane's slots are the same in every tile, so their byte offsets
-    // from the tile's first row are fixed; only the last tile clamps.
+    // the tile's first chunk.  A lane's slots are the same in every tile, so
+    // their byte offsets from the tile's first row are fixed.
     const uint32_t ring0 = lds_byte_addr(ring);
     uint32_t soff[IPW];
-    int srow[IPW];
 #pragma unroll
     for (int j = 0; j < IPW; ++j) {
         const int sl = (w * IPW + j) * 64 + lane;
         const int rr = sl / SPR, ch = sl - rr * SPR;
         const bool real = rr < BN && ch < CPR;
-        srow[j] = real ? rr : 0;
         soff[j] = real ? (uint32_t)((rr * KP + ch * 8) * 2) : 0u;
     }
+    const uint32_t soff4 = (uint32_t)((lane < BN ? lane : 0) * 4);
     auto issue = [&](int32_t c0, int st) {
         const uint32_t sbase = ring0 + (uint32_t)(st * STAGE);
-        const char *th = reinterpret_cast<const char *>(Ah + (int64_t)c0 * KP);
-        const char *tl = NSPLIT == 3 ? reinterpret_cast<const char *>(Al + (int64_t)c0 * KP) : nullptr;
-        const bool whole = c0 + BN <= N;
+        const char *th = reinterpret_cast<const char *>(Bh + (int64_t)c0 * KP);
+        const char *tl = NSPLIT == 3 ? reinterpret_cast<const char *>(Bl + (int64_t)c0 * KP) : nullptr;
 #pragma unroll
         for (int j = 0; j < IPW; ++j) {
-            uint32_t off = soff[j];
-            if (!whole && c0 + srow[j] > N - 1)  // past the last row: row N - 1
-                off = (uint32_t)(((N - 1 - c0) * KP) * 2) + (off - (uint32_t)(srow[j] * KP * 2));
             const uint32_t dst = sbase + (uint32_t)((w * IPW + j) * 1024);
-            lds_dma16(th, off, dst);
-            if (NSPLIT == 3) lds_dma16(tl, off, dst + PART);
+            lds_dma16(th, soff[j], dst);
+            if (NSPLIT == 3) lds_dma16(tl, soff[j], dst + PART);
         }
-        const int nr = min(lane < BN ? lane : 0, N - 1 - c0);
-        lds_dma4(n2 + c0, (uint32_t)(nr * 4), sbase + TERMS * PART + w * 256);
+        lds_dma4(bn2 + c0, soff4, sbase + TERMS * PART + w * 256);
+        lds_dma4(bid_of + c0, soff4, sbase + TERMS * PART + 1024 + w * 256);
     };
+    auto tile_col = [&](int32_t j) { return (int32_t)((int64_t)((t0 + j) % T) * BN); };
 
     float tau[RT][4];
     auto load_tau = [&]() {
@@ -415,17 +429,19 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, int32_t N, const float *n2, in
     };
     auto merge = [&](int r) {
         const int c = __builtin_amdgcn_readlane(cnt, r);
-        const float kth = knn_merge_row(bkey, bid, (boff + (wrow0 - rb) + r) * kKnnCap, c, K, lane);
+        const int32_t node = s_node[w][r];
+        const float kth = knn_merge_row(bkey, bid, (boff + (node - rb)) * kKnnCap, c, K, lane);
         cnt = lane == r ? min(c, K) : cnt;
         if (lane == 0) s_tau[w][r] = kth;
     };
 
-    const int ntile = ce > cb ? (ce - cb + BN - 1) / BN : 0;
+    const int ntile = je > jb ? je - jb : 0;
     // prologue: tiles 0 .. NB-2 in flight (every wave issues LPT loads per
     // tile slot, a slot past the last tile re-loads tile 0's stage 0 data
     // into the last stage, which no tile reads before it is re-issued)
 #pragma unroll
-    for (int p = 0; p < NB - 1; ++p) issue(cb + (p < ntile ? p : 0) * BN, p < ntile ? p : NB - 1);
+    for (int p = 0; p < NB - 1; ++p)
+        issue(tile_col(jb + (p < ntile ? p : 0)), p < ntile ? p : NB - 1);
     for (int it = 0; it < ntile; ++it) {
         const int st = it % NB;
         // tile it has landed when at most (NB - 2) tiles' loads are in
@@ -436,7 +452,7 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, int32_t N, const float *n2, in
         if (it == 0) load_tau();
         {
             const int nx = it + NB - 1;  // into the stage read at it - 1
-            issue(cb + (nx < ntile ? nx : 0) * BN, nx < ntile ? nx % NB : (it + NB - 1) % NB);
+            issue(tile_col(jb + (nx < ntile ? nx : 0)), nx < ntile ? nx % NB : (it + NB - 1) % NB);
         }
         const char *sp = ring + st * STAGE;
         floatx4 acc[RT][CT];
@@ -467,13 +483,12 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, int32_t N, const float *n2, in
         // epilogue: the keys (in place of the products) and one pass test
         // for the whole step; only a step with a passing element looks at
         // its 16 x 16 tiles and appends (rare once the rows hold K)
-        const int32_t c0 = cb + it * BN;
         const float *snc = reinterpret_cast<const float *>(sp + TERMS * PART + w * 256);
+        const int32_t *sid = reinterpret_cast<const int32_t *>(sp + TERMS * PART + 1024 + w * 256);
         bool any = false;
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
-            const int32_t col = c0 + ct * 16 + r16;
-            const float nc = col < ce ? snc[ct * 16 + r16] : INFINITY;
+            const float nc = snc[ct * 16 + r16];  // +inf past the last node
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -487,7 +502,7 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, int32_t N, const float *n2, in
             appended = true;
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
-                const int32_t col = c0 + ct * 16 + r16;
+                const int32_t col = sid[ct * 16 + r16];  // node id of the lane's column
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) {
                     bool hit = false;
@@ -499,7 +514,8 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, int32_t N, const float *n2, in
                     // lane's rank among its group's passing lanes
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const bool ok = acc[rt][ct][i] <= tau[rt][i] && col != wrow0 + rt * 16 + rq + i;
+                        const int32_t node = s_node[w][rt * 16 + rq + i];
+                        const bool ok = acc[rt][ct][i] <= tau[rt][i] && col >= 0 && col != node;
                         const uint64_t m = __ballot(ok);
                         if (!m) continue;
                         int at = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -514,7 +530,7 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, int32_t N, const float *n2, in
                             at += grp == g ? base - below : 0;
                         }
                         if (ok && at < kKnnCap) {
-                            const int64_t o = (boff + (wrow0 - rb) + rt * 16 + rq + i) * kKnnCap + at;
+                            const int64_t o = (boff + (node - rb)) * kKnnCap + at;
                             bkey[o] = acc[rt][ct][i];
                             bid[o] = col;
                         }
@@ -545,7 +561,7 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, int32_t N, const float *n2, in
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     __builtin_amdgcn_wave_barrier();
     for (int r = 0; r < RT * 16; ++r)
-        if (wrow0 + r < rend) merge(r);
+        if (s_node[w][r] >= 0) merge(r);
 }
 
 // top-K of each row over the splits' sorted lists (split s of row i at
@@ -782,42 +798,170 @@ void launch_gather(int dp, const float *vec, int R, const int32_t *adj, const in
     }
 }
 
+// ---- cluster order of the kNN sweep
+// nearest of P pivot rows (fp32 L2; the smaller pivot index on ties) for
+// every node; 32 pivot rows at a time in LDS (dp <= 256)
+__global__ void __launch_bounds__(256)
+k_assign_pivot(const float *vec, int dp, int64_t N, const float *piv, int P, int32_t *assign) {
+    __shared__ __attribute__((aligned(16))) float sp[32 * 256];
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const float *x = vec + (v < N ? v : 0) * dp;
+    float best = INFINITY;
+    int bi = 0;
+    for (int p0 = 0; p0 < P; p0 += 32) {
+        const int np = min(32, P - p0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < np * dp; e += 256) sp[e] = piv[(int64_t)p0 * dp + e];
+        __syncthreads();
+        float acc[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) acc[k] = 0.f;
+        for (int c = 0; c < dp; c += 4) {
+            const float4 xv = *reinterpret_cast<const float4 *>(x + c);
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                if (k < np) {
+                    const float4 pv = *reinterpret_cast<const float4 *>(sp + k * dp + c);
+                    float t = xv.x - pv.x; acc[k] = fmaf(t, t, acc[k]);
+                    t = xv.y - pv.y; acc[k] = fmaf(t, t, acc[k]);
+                    t = xv.z - pv.z; acc[k] = fmaf(t, t, acc[k]);
+                    t = xv.w - pv.w; acc[k] = fmaf(t, t, acc[k]);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+            if (k < np && acc[k] < best) { best = acc[k]; bi = p0 + k; }
+    }
+    if (v < N) assign[v] = bi;
+}
+
+// sweep-order copy of the tile rows: row j of the copy is node perm[j]
+// (j < N), a zero row with |x|^2 = +inf and id -1 past N (j < Np)
+__global__ void k_sweep_copy(const uint16_t *hi, const uint16_t *lo, const float *n2, int Kp,
+                             const int32_t *perm, int64_t N, int64_t Np, uint16_t *bh,
+                             uint16_t *bl, float *bn2, int32_t *bid_of) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int cpr = Kp / 8;
+    if (e >= Np * cpr) return;
+    const int64_t j = e / cpr, c = e - j * cpr;
+    const int32_t v = j < N ? perm[j] : -1;
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    reinterpret_cast<uint4 *>(bh + j * Kp)[c] = v >= 0 ? reinterpret_cast<const uint4 *>(hi + (int64_t)v * Kp)[c] : z;
+    if (bl) reinterpret_cast<uint4 *>(bl + j * Kp)[c] = v >= 0 ? reinterpret_cast<const uint4 *>(lo + (int64_t)v * Kp)[c] : z;
+    if (c == 0) {
+        bn2[j] = v >= 0 ? n2[v] : INFINITY;
+        bid_of[j] = v;
+    }
+}
+
+// first sweep position of each pivot group (keys: the sorted pivot ids)
+__global__ void k_group_start(const int32_t *keys, int64_t N, int32_t *gstart) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < N && (j == 0 || keys[j] != keys[j - 1])) gstart[keys[j]] = (int32_t)j;
+}
+
+// keys and values of the call's rows [rb, rb + M): their pivot, their id
+__global__ void k_row_keys(const int32_t *assign, int64_t rb, int64_t M, int32_t *keys,
+                           int32_t *vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    keys[i] = assign[rb + i];
+    vals[i] = (int32_t)(rb + i);
+}
+
+// start tile of row block b: the tile holding the start of the pivot group
+// of the block's first row (rkeys: the rows' sorted pivot ids)
+__global__ void k_start_tiles(const int32_t *rkeys, int64_t M, int rows, const int32_t *gstart,
+                              int bn, int64_t nb, int32_t *start_tile) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int32_t g = gstart[rkeys[b * rows]];
+    start_tile[b] = g >= 0 ? g / bn : 0;
+}
+
 // the register-row kNN sweep for one (NSPLIT, Kp); false if that shape has
-// no instantiation.  Column splits keep >= 1,024 workgroups when M is small
-// (an insertion batch); their lists are merged into split 0.
+// no instantiation.  Rows and columns are ordered by their nearest of up to
+// 1,024 pivot nodes (every (N / P)-th node), and each row block starts its
+// sweep at its own group.  Column splits keep >= 1,024 workgroups when M is
+// small (an insertion batch); their lists are merged into split 0.
 template <int NSPLIT, int KP>
-bool launch_knn_reg_t(const TileRows &t, int64_t N, int K, int64_t rb, int64_t M, DevBuf &bkey,
-                      DevBuf &bidb, hipStream_t s) {
+bool launch_knn_reg_t(const TileRows &t, const float *vec, int dp, int64_t N, int K, int64_t rb,
+                      int64_t M, DevBuf &bkey, DevBuf &bidb, hipStream_t s) {
     using S = KnnReg<NSPLIT, KP>;
     if constexpr (!S::OK) {
         return false;
     } else {
+        constexpr int BN = S::BN;
+        if (dp > 256) return false;
+        const int64_t T = (N + BN - 1) / BN, Np = T * BN;
+        // 1. the nearest pivot of every node
+        const int P = (int)std::min<int64_t>(1024, std::max<int64_t>(1, N / 512));
+        std::vector<int32_t> ph((size_t)P);
+        for (int k = 0; k < P; ++k) ph[(size_t)k] = (int32_t)((int64_t)k * (N / P));
+        DevBuf pids((size_t)P * sizeof(int32_t)), piv((size_t)P * dp * sizeof(float)),
+            assign((size_t)N * sizeof(int32_t));
+        VJ_HIP(hipMemcpyAsync(pids.p, ph.data(), (size_t)P * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        gather_rows_f32(vec, dp, pids.as<int32_t>(), P, piv.as<float>(), s);
+        hipLaunchKernelGGL(k_assign_pivot, dim3(g1b(N, 256)), dim3(256), 0, s, vec, dp, N,
+                           piv.as<float>(), P, assign.as<int32_t>());
+        // 2. columns in pivot order, as sweep-order copies padded to whole tiles
+        DevBuf skeys((size_t)N * sizeof(int32_t)), iota((size_t)N * sizeof(int32_t)),
+            perm((size_t)N * sizeof(int32_t)), tmp;
+        iota_i32(iota.as<int32_t>(), N, s);
+        sort_pairs_i32(assign.as<int32_t>(), skeys.as<int32_t>(), iota.as<int32_t>(),
+                       perm.as<int32_t>(), N, 11, tmp, s);
+        DevBuf bh((size_t)Np * KP * sizeof(uint16_t)),
+            bl(NSPLIT == 3 ? (size_t)Np * KP * sizeof(uint16_t) : 16), bn2((size_t)Np * sizeof(float)),
+            bid_of((size_t)Np * sizeof(int32_t)), gstart((size_t)P * sizeof(int32_t));
+        hipLaunchKernelGGL(k_sweep_copy, dim3(g1b(Np * (KP / 8), 256)), dim3(256), 0, s,
+                           t.hi.as<uint16_t>(), NSPLIT == 3 ? t.lo.as<uint16_t>() : nullptr,
+                           t.norm2.as<float>(), KP, perm.as<int32_t>(), N, Np, bh.as<uint16_t>(),
+                           NSPLIT == 3 ? bl.as<uint16_t>() : nullptr, bn2.as<float>(),
+                           bid_of.as<int32_t>());
+        fill_i32(gstart.as<int32_t>(), P, -1, s);
+        hipLaunchKernelGGL(k_group_start, dim3(g1b(N, 256)), dim3(256), 0, s, skeys.as<int32_t>(),
+                           N, gstart.as<int32_t>());
+        // 3. the call's rows in pivot order, and each block's start tile
         const int64_t nb = (M + S::ROWS - 1) / S::ROWS;
+        DevBuf rkeys((size_t)M * sizeof(int32_t)), rkeys2((size_t)M * sizeof(int32_t)),
+            rvals((size_t)M * sizeof(int32_t)), rowperm((size_t)M * sizeof(int32_t)),
+            start_tile((size_t)nb * sizeof(int32_t));
+        hipLaunchKernelGGL(k_row_keys, dim3(g1b(M, 256)), dim3(256), 0, s, assign.as<int32_t>(),
+                           rb, M, rkeys.as<int32_t>(), rvals.as<int32_t>());
+        sort_pairs_i32(rkeys.as<int32_t>(), rkeys2.as<int32_t>(), rvals.as<int32_t>(),
+                       rowperm.as<int32_t>(), M, 11, tmp, s);
+        hipLaunchKernelGGL(k_start_tiles, dim3(g1b(nb, 256)), dim3(256), 0, s,
+                           rkeys2.as<int32_t>(), M, S::ROWS, gstart.as<int32_t>(), BN, nb,
+                           start_tile.as<int32_t>());
+        // 4. the sweep
         int splits = 1;
-        while (splits * 2 * K <= 512 && nb * splits < 1024 && N / (splits * 2) >= 8 * S::BN)
-            splits *= 2;
-        const int64_t cps = ((N + splits - 1) / splits + S::BN - 1) / S::BN * S::BN;
+        while (splits * 2 * K <= 512 && nb * splits < 1024 && T / (splits * 2) >= 8) splits *= 2;
+        const int64_t tps = (T + splits - 1) / splits;
         bkey.alloc((size_t)splits * M * kKnnCap * sizeof(float));
         bidb.alloc((size_t)splits * M * kKnnCap * sizeof(int32_t));
         hipLaunchKernelGGL((k_knn_reg<NSPLIT, KP>), dim3((unsigned)nb, (unsigned)splits), dim3(256),
-                           0, s, t.hi.as<uint16_t>(),
-                           NSPLIT == 3 ? t.lo.as<uint16_t>() : nullptr, (int32_t)N,
-                           t.norm2.as<float>(), K, bkey.as<float>(), bidb.as<int32_t>(),
-                           (int32_t)rb, (int32_t)M, (int32_t)cps);
+                           0, s, t.hi.as<uint16_t>(), NSPLIT == 3 ? t.lo.as<uint16_t>() : nullptr,
+                           rowperm.as<int32_t>(), (int32_t)M, bh.as<uint16_t>(),
+                           NSPLIT == 3 ? bl.as<uint16_t>() : nullptr, bn2.as<float>(),
+                           bid_of.as<int32_t>(), (int32_t)T, start_tile.as<int32_t>(),
+                           (int32_t)tps, K, bkey.as<float>(), bidb.as<int32_t>(), (int32_t)rb);
         if (splits > 1)
             hipLaunchKernelGGL(k_knn_merge_splits, dim3(g1b(M, 4)), dim3(256), 0, s,
                                bkey.as<float>(), bidb.as<int32_t>(), M, splits, K);
+        VJ_HIP(hipGetLastError());
+        VJ_HIP(hipStreamSynchronize(s));  // the temporaries above are freed on return
         return true;
     }
 }
 
-bool launch_knn_reg(int nsplit, int Kp, const TileRows &t, int64_t N, int K, int64_t rb,
-                    int64_t M, DevBuf &bkey, DevBuf &bidb, hipStream_t s) {
+bool launch_knn_reg(int nsplit, int Kp, const TileRows &t, const float *vec, int dp, int64_t N,
+                    int K, int64_t rb, int64_t M, DevBuf &bkey, DevBuf &bidb, hipStream_t s) {
     if (K > 128 || M <= 0) return false;
-#define VJ_KNN_CASE(kp)                                                                        \
-    case kp:                                                                                   \
-        return nsplit == 3 ? launch_knn_reg_t<3, kp>(t, N, K, rb, M, bkey, bidb, s)             \
-                           : launch_knn_reg_t<1, kp>(t, N, K, rb, M, bkey, bidb, s);
+#define VJ_KNN_CASE(kp)                                                                         \
+    case kp:                                                                                    \
+        return nsplit == 3 ? launch_knn_reg_t<3, kp>(t, vec, dp, N, K, rb, M, bkey, bidb, s)     \
+                           : launch_knn_reg_t<1, kp>(t, vec, dp, N, K, rb, M, bkey, bidb, s);
     switch (Kp) {
         VJ_KNN_CASE(32) VJ_KNN_CASE(64) VJ_KNN_CASE(96) VJ_KNN_CASE(128) VJ_KNN_CASE(192)
         VJ_KNN_CASE(256)
@@ -839,7 +983,7 @@ void knn_candidates(const Index &ix, int64_t rb, int64_t M, int K, DevBuf &bidb,
     tile_error_bounds(t, t, 1, e_dot, e_fin);
     const int nsplit = (e_dot == 0.0) ? 1 : 3;
     DevBuf bkey;
-    if (launch_knn_reg(nsplit, Kp, t, N, K, rb, M, bkey, bidb, s)) {
+    if (launch_knn_reg(nsplit, Kp, t, vec, dp, N, K, rb, M, bkey, bidb, s)) {
         VJ_HIP(hipGetLastError());
         VJ_HIP(hipStreamSynchronize(s));
         return;

@@ -72,6 +72,10 @@ void batch_end(int32_t *ctr, uint64_t *rec, hipStream_t s);
 void order_by_density(const int32_t *adj, const float *elen, int R, int64_t nx, int64_t nq,
                       const int32_t *ids, int64_t n, int32_t *qlist, int32_t *qpos, DevBuf &keys,
                       DevBuf &tmp, hipStream_t s);
+// stable radix sort of (key, value) int32 pairs on key bits [0, end_bit);
+// keys must be non-negative; tmp is grown as needed
+void sort_pairs_i32(const int32_t *keys_in, int32_t *keys_out, const int32_t *vals_in,
+                    int32_t *vals_out, int64_t n, int end_bit, DevBuf &tmp, hipStream_t s);
 void order_by_depth(const int32_t *depth, int64_t nq, const int32_t *ids, int64_t n,
                     int32_t *qlist, int32_t *qpos, DevBuf &tmp, hipStream_t s);
 

@@ -709,6 +709,17 @@ void batch_end(int32_t *ctr, uint64_t *rec, hipStream_t s) {
 }
 
 // processing order parents-first: stable sort of caller positions by MST depth
+void sort_pairs_i32(const int32_t *keys_in, int32_t *keys_out, const int32_t *vals_in,
+                    int32_t *vals_out, int64_t n, int end_bit, DevBuf &tmp, hipStream_t s) {
+    if (n == 0) return;
+    size_t bytes = 0;
+    VJ_HIP(rocprim::radix_sort_pairs(nullptr, bytes, keys_in, keys_out, vals_in, vals_out,
+                                     (size_t)n, 0, end_bit, s));
+    tmp.reserve(bytes);
+    VJ_HIP(rocprim::radix_sort_pairs(tmp.p, bytes, keys_in, keys_out, vals_in, vals_out,
+                                     (size_t)n, 0, end_bit, s));
+}
+
 void order_by_depth(const int32_t *depth, int64_t nq, const int32_t *ids, int64_t n,
                     int32_t *qlist, int32_t *qpos, DevBuf &tmp, hipStream_t s) {
     if (n == 0) return;
