@@ -100,8 +100,15 @@ def main():
                     help="instead of the headline: the 1M x 960 workload, fp32 rows against bf16 "
                          "rows with fp32 re-check, error against fp64")
     ap.add_argument("--stream", action="store_true",
-                    help="instead of the headline: the batched stream workload at 1/10 scale "
-                         "(200 batches, p50/p99 batch latency)")
+                    help="instead of the headline: the batched stream workload (200 batches, "
+                         "p50/p99 batch latency)")
+    ap.add_argument("--stream-scale", type=float, default=0.1,
+                    help="0.1 (X = 1M, 487k queries) or 1.0 (the stated size: X = 10M, 4.87M "
+                         "queries)")
+    ap.add_argument("--stream-insert", action="store_true",
+                    help="with --stream: the index starts over X alone and each batch is "
+                         "inserted (vj_index_insert_queries) right before its join; batch "
+                         "latency = insertion + join")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -613,33 +620,67 @@ def highdim_main(args, torch, workloads, vj):
 
 
 def stream_main(args, torch, workloads, vj):
-    """The batched stream: one merged index over X and every batch's queries,
-    then the batches joined one after the other (vj_join_batches), each at
-    its own eps (oracle-calibrated, tests/golden/eps.json)."""
-    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "eps.json")))["stream"]
+    """The batched stream: 200 join batches, each at its own eps
+    (oracle-calibrated, tests/golden/eps.json).
+
+    Offline (default): one merged index over X and every batch's queries,
+    then the batches joined one after the other (vj_join_batches) by the
+    host runner, the device runner and HIP graph replay.
+    --stream-insert: the index starts over X alone; each batch's queries are
+    inserted into it (vj_index_insert_queries) and then joined, so a batch's
+    latency is its insertion plus its join (every step starts from a fresh
+    X-only index, built outside the timed region)."""
+    if args.stream_scale not in (0.1, 1.0):
+        raise SystemExit("--stream-scale is 0.1 or 1.0")
+    key = "stream" if args.stream_scale == 0.1 else "stream_full"
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "eps.json")))[key]
     t0 = time.time()
     w = workloads.config_stream(scale=golden["scale"], n_batches=golden["n_batches"])
-    for key, arr in (("Q_sha", w.Q), ("X_sha", w.X)):
+    for k, arr in (("Q_sha", w.Q), ("X_sha", w.X)):
         sha = hashlib.sha256(np.ascontiguousarray(arr).tobytes()).hexdigest()[:16]
-        if sha != golden[key]:
-            raise SystemExit(f"generated data differs from the calibrated data ({key})")
+        if sha != golden[k]:
+            raise SystemExit(f"generated data differs from the calibrated data ({k})")
     batches = workloads.stream_batches(w)
     starts = [b[0] for b in batches]
     counts = [b[1] for b in batches]
     eps = golden["eps"]
+    nq = int(sum(counts))
+    nx = w.X.shape[0]
+    size = f"X={nx:,} x {w.d}"
     log(f"stream: X {w.X.shape}, {len(batches)} batches, {w.Q.shape[0]} queries ({time.time() - t0:.1f}s)")
     dev = torch.device("cuda:0")
     Q = torch.from_numpy(w.Q).to(dev)
     X = torch.from_numpy(w.X).to(dev)
+    del w.Q, w.X
+    lo, hi = min(counts), max(counts)
+    workload = (f"stream at {'the stated size' if key == 'stream_full' else '1/10 scale'}: {size} "
+                f"1,024-cluster Gaussian mixture; 200 batches of {lo:,}..{hi:,} queries "
+                f"(log-uniform), eps per batch for 5..200 mean matches")
+
+    def recall(res):
+        """Pairs found / exact pairs on every 20th batch (MFMA brute force)."""
+        found = exact = 0
+        for b in range(0, len(batches), 20):
+            qb = Q[starts[b]:starts[b] + counts[b]]
+            gt = vj.vj_bruteforce_join(qb, X, eps[b])
+            exact += gt.count()
+            found += res[b].count()
+            del gt
+        return found / max(1, exact)
+
+    if args.stream_insert:
+        return stream_insert(args, torch, vj, Q, X, starts, counts, eps, nq, workload, recall)
+
     t = time.time()
     idx = vj.vj_build_merged_index(Q, X, metric="l2", R=w.R)
     torch.cuda.synchronize()
     build_s = time.time() - t
-    log(f"merged index over {w.Q.shape[0] + w.X.shape[0]} nodes built in {build_s:.1f}s")
+    log(f"merged index over {nq + nx} nodes built in {build_s:.1f}s")
     params, tuned_ms = vj.vj_autotune_join(idx, eps[0], query_ids=torch.arange(
         starts[0], starts[0] + counts[0], dtype=torch.int32, device=dev))
     log(f"autotuned on batch 0: start_tier={params.start_tier} precision={params.precision} "
         f"({tuned_ms:.3f} ms)")
+
     def run(runner):
         """Timed runs of one batch runner: (results, wall seconds per run,
         per-batch ms of every run).  Earlier results are released before the
@@ -660,15 +701,8 @@ def stream_main(args, torch, workloads, vj):
         return res, walls, np.array(lat)
 
     res, walls, lat = run("host")
-    nq = int(sum(counts))
     pairs = sum(r.count() for r in res)
-    # recall on every 20th batch against the exact join
-    found = exact = 0
-    for b in range(0, len(batches), 20):
-        qb = Q[starts[b]:starts[b] + counts[b]]
-        gt = vj.vj_bruteforce_join(qb, X, eps[b])
-        exact += gt.count()
-        found += res[b].count()
+    rec = recall(res)
     # the same batches driven from the device (no host synchronisation
     # between batches): direct launches and HIP graph replay
     dev_runs = {}
@@ -684,20 +718,91 @@ def stream_main(args, torch, workloads, vj):
         log(f"{runner} runner: {dev_runs[runner]['value']:.0f} queries/s, pair counts equal: {same}")
         del dres
     line = {
-        "metric": "stream join queries/sec and batch latency (200 batches, X=1M x 96)",
+        "metric": f"stream join queries/sec and batch latency (200 batches, {size})",
         "value": nq / float(np.mean(walls)), "unit": "queries/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1000.0 * float(np.mean(walls)), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "stream at 1/10 scale: X=1,000,000 d=96 1,024-cluster Gaussian "
-                               "mixture; 200 batches of 100..10,000 queries (log-uniform), eps "
-                               "per batch for 5..200 mean matches", "queries": nq},
+        "config": {"workload": workload, "queries": nq},
         "batch_ms_p50": float(np.percentile(lat, 50)), "batch_ms_p99": float(np.percentile(lat, 99)),
         "batch_ms_max": float(lat.max()), "pairs": int(pairs),
-        "recall_sampled_batches": found / max(1, exact), "build_s": build_s,
+        "recall_sampled_batches": rec, "build_s": build_s,
         "tuned": {"start_tier": params.start_tier, "precision": params.precision},
         "device_runner": dev_runs["device"],
         "graph_replay": dev_runs["graph"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def stream_insert(args, torch, vj, Q, X, starts, counts, eps, nq, workload, recall):
+    """The stream with insertion: per step a fresh index over X alone (not
+    timed), then for each batch its insertion and its join, timed together;
+    per-batch wall ms of the insertion and of the join are reported apart."""
+    def fresh():
+        idx = vj.vj_build_merged_index(Q[:0], X, metric="l2", R=32, build_mst=False)
+        torch.cuda.synchronize()
+        return idx
+
+    t = time.time()
+    idx = fresh()
+    build_s = time.time() - t
+    log(f"index over X alone built in {build_s:.1f}s")
+    params = vj.join_params()
+
+    def one_pass(idx):
+        res, ins_ms, join_ms = [], [], []
+        for b in range(len(starts)):
+            qb = Q[starts[b]:starts[b] + counts[b]]
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            idx.insert_queries(qb)
+            torch.cuda.synchronize()
+            tj = time.perf_counter()
+            r, _ = vj.vj_join_batches(idx, [starts[b]], [counts[b]], [eps[b]], params=params)
+            torch.cuda.synchronize()
+            te = time.perf_counter()
+            res.append(r[0])
+            ins_ms.append(1000.0 * (tj - ts))
+            join_ms.append(1000.0 * (te - tj))
+        return res, np.array(ins_ms), np.array(join_ms)
+
+    for _ in range(max(1, args.warmup)):
+        one_pass(idx)
+        idx = None
+        idx = fresh()
+    walls, ins, jn = [], [], []
+    res = None
+    for s in range(args.steps):
+        res = None
+        ts = time.perf_counter()
+        res, i_ms, j_ms = one_pass(idx)
+        walls.append(time.perf_counter() - ts)
+        ins.append(i_ms)
+        jn.append(j_ms)
+        log(f"step {s}: {nq / walls[-1]:.0f} queries/s (insert {i_ms.sum():.0f} ms, join "
+            f"{j_ms.sum():.0f} ms)")
+        if s + 1 < args.steps:
+            idx = None
+            idx = fresh()
+    ins, jn = np.concatenate(ins), np.concatenate(jn)
+    lat = ins + jn
+    rec = recall(res)
+    pairs = sum(r.count() for r in res)
+    line = {
+        "metric": "stream with insertion: queries/sec and batch latency (insert + join)",
+        "value": nq / float(np.mean(walls)), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * float(np.mean(walls)), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": workload + "; index over X alone, each batch inserted before "
+                   "its join", "queries": nq},
+        "batch_ms_p50": float(np.percentile(lat, 50)), "batch_ms_p99": float(np.percentile(lat, 99)),
+        "batch_ms_max": float(lat.max()),
+        "insert_ms_p50": float(np.percentile(ins, 50)), "insert_ms_p99": float(np.percentile(ins, 99)),
+        "join_ms_p50": float(np.percentile(jn, 50)), "join_ms_p99": float(np.percentile(jn, 99)),
+        "insert_ms_total": float(ins.sum() / args.steps),
+        "join_ms_total": float(jn.sum() / args.steps),
+        "pairs": int(pairs), "recall_sampled_batches": rec, "x_only_build_s": build_s,
     }
     print(json.dumps(line), flush=True)
 

@@ -20,6 +20,7 @@
 
 #include "build.h"
 #include "build_rows.h"
+#include "lds_ring.h"
 #include "mfma_tile.h"
 #include "tiles.h"
 #include "util.h"
@@ -208,52 +209,6 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
 // passes.  Thresholds are the K-th key of the last merge (FLT_MAX until a
 // row holds K entries), so every element of the final top-K passes when it
 // is seen, whatever the order.  Rows past the call's M get threshold -inf.
-template <int NSPLIT, int KP>
-struct KnnReg {
-    static constexpr int KS = KP / 32;                 // MFMA k-steps of 32
-    static constexpr int TERMS = NSPLIT == 3 ? 2 : 1;  // hi (+ lo) parts
-    static constexpr int RT = TERMS * 16 * KS <= 64 ? 4 : 2;
-    static constexpr int CT = 2;
-    static constexpr int BN = 16 * CT;                 // columns per tile
-    static constexpr int ROWS = 4 * RT * 16;           // rows per workgroup
-    static constexpr int CPR = KP / 8;                 // 16-byte chunks per row
-    static constexpr int SPR = CPR + 1;                // staged slots per row
-    static constexpr int IPW = (BN * SPR + 255) / 256; // load instructions per wave and part
-    static constexpr int PART = 4 * IPW * 1024;        // bytes of one part of a stage
-    // + each wave's copy of the tile's |x|^2 and node ids
-    static constexpr int STAGE = TERMS * PART + 2 * 4 * 256;
-    static constexpr int NB0 = (78 * 1024) / STAGE;  // two workgroups per CU fit in 160 KB
-    static constexpr int NB = NB0 > 8 ? 8 : NB0;       // stages in the ring
-    static constexpr int LPT = TERMS * IPW + 2;        // load instructions per wave and tile
-    static constexpr bool OK = KP % 32 == 0 && KP <= 256 && NB >= 3 && (NB - 2) * LPT <= 60;
-};
-
-// one direct global-to-LDS load per lane: 16 bytes (or 4) from the
-// wave-uniform base plus the lane's byte offset, to LDS byte address
-// lds + 16 * lane (4 * lane); lds must be wave-uniform.  M0 is saved and
-// restored inside the block.
-__device__ __forceinline__ void lds_dma16(const void *base, uint32_t off, uint32_t lds) {
-    uint32_t saved;
-    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\t"
-                 "global_load_lds_dwordx4 %2, %3\n\ts_nop 0\n\ts_mov_b32 m0, %0"
-                 : "=&s"(saved) : "s"(lds), "v"(off), "s"(base) : "memory");
-}
-__device__ __forceinline__ void lds_dma4(const void *base, uint32_t off, uint32_t lds) {
-    uint32_t saved;
-    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\t"
-                 "global_load_lds_dword %2, %3\n\ts_nop 0\n\ts_mov_b32 m0, %0"
-                 : "=&s"(saved) : "s"(lds), "v"(off), "s"(base) : "memory");
-}
-__device__ __forceinline__ uint32_t lds_byte_addr(const void *p) {
-    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
-}
-// wait until at most N of this wave's vector memory operations are in
-// flight and its LDS operations are done, then the workgroup barrier
-template <int N>
-__device__ __forceinline__ void wait_barrier() {
-    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
-}
-
 // order-preserving map of a float key to uint32 (-0 and +0 both map as +0)
 __device__ __forceinline__ uint32_t key_bits(float k) {
     const uint32_t b = __float_as_uint(k + 0.0f);
@@ -349,11 +304,11 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
           const uint16_t *Bh, const uint16_t *Bl, const float *bn2, const int32_t *bid_of,
           int32_t T, const int32_t *start_tile, int32_t tiles_per_split, int K, float *bkey,
           int32_t *bid, int32_t rb) {
-    using S = KnnReg<NSPLIT, KP>;
+    using S = ring::Shape<NSPLIT, KP>;
     constexpr int RT = S::RT, CT = S::CT, KS = S::KS, BN = S::BN, CPR = S::CPR, SPR = S::SPR;
     constexpr int IPW = S::IPW, TERMS = S::TERMS, PART = S::PART, STAGE = S::STAGE, NB = S::NB;
     constexpr int LPT = S::LPT;
-    __shared__ __attribute__((aligned(1024))) char ring[NB * STAGE];
+    __shared__ __attribute__((aligned(1024))) char sring[NB * STAGE];
     __shared__ float s_tau[4][RT * 16];
     __shared__ int32_t s_node[4][RT * 16];
     const int lane = threadIdx.x & 63;
@@ -395,7 +350,7 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
     // row s / SPR, chunk s % SPR; pad chunks and slots past the tile load
     // the tile's first chunk.  A lane's slots are the same in every tile, so
     // their byte offsets from the tile's first row are fixed.
-    const uint32_t ring0 = lds_byte_addr(ring);
+    const uint32_t ring0 = ring::lds_byte_addr(sring);
     uint32_t soff[IPW];
 #pragma unroll
     for (int j = 0; j < IPW; ++j) {
@@ -412,11 +367,11 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
 #pragma unroll
         for (int j = 0; j < IPW; ++j) {
             const uint32_t dst = sbase + (uint32_t)((w * IPW + j) * 1024);
-            lds_dma16(th, soff[j], dst);
-            if (NSPLIT == 3) lds_dma16(tl, soff[j], dst + PART);
+            ring::lds_dma16(th, soff[j], dst);
+            if (NSPLIT == 3) ring::lds_dma16(tl, soff[j], dst + PART);
         }
-        lds_dma4(bn2 + c0, soff4, sbase + TERMS * PART + w * 256);
-        lds_dma4(bid_of + c0, soff4, sbase + TERMS * PART + 1024 + w * 256);
+        ring::lds_dma4(bn2 + c0, soff4, sbase + TERMS * PART + w * 256);
+        ring::lds_dma4(bid_of + c0, soff4, sbase + TERMS * PART + 1024 + w * 256);
     };
     auto tile_col = [&](int32_t j) { return (int32_t)((int64_t)((t0 + j) % T) * BN); };
 
@@ -448,13 +403,13 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
         // flight: loads complete in issue order, and the appends' stores
         // issued since only add to the count, so they can only make this
         // wait longer
-        wait_barrier<(NB - 2) * LPT>();
+        ring::wait_barrier<(NB - 2) * LPT>();
         if (it == 0) load_tau();
         {
             const int nx = it + NB - 1;  // into the stage read at it - 1
             issue(tile_col(jb + (nx < ntile ? nx : 0)), nx < ntile ? nx % NB : (it + NB - 1) % NB);
         }
-        const char *sp = ring + st * STAGE;
+        const char *sp = sring + st * STAGE;
         floatx4 acc[RT][CT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
@@ -557,7 +512,7 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
         }
     }
     // every load in flight lands before the workgroup ends
-    wait_barrier<0>();
+    ring::wait_barrier<0>();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     __builtin_amdgcn_wave_barrier();
     for (int r = 0; r < RT * 16; ++r)
@@ -888,7 +843,7 @@ __global__ void k_start_tiles(const int32_t *rkeys, int64_t M, int rows, const i
 template <int NSPLIT, int KP>
 bool launch_knn_reg_t(const TileRows &t, const float *vec, int dp, int64_t N, int K, int64_t rb,
                       int64_t M, DevBuf &bkey, DevBuf &bidb, hipStream_t s) {
-    using S = KnnReg<NSPLIT, KP>;
+    using S = ring::Shape<NSPLIT, KP>;
     if constexpr (!S::OK) {
         return false;
     } else {

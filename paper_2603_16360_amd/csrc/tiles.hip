@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "lds_ring.h"
 #include "mfma_tile.h"
 #include "tiles.h"
 
@@ -144,6 +145,254 @@ k_range_tiles(const uint16_t *Qh, const uint16_t *Ql, int64_t nq, const uint16_t
             cx[at] = (int32_t)(x0 + mt::tile_brow(ct, lane));
         }
     }
+}
+
+// The same candidate test on register-row tiles (Kp <= 256): a workgroup of
+// 4 waves holds 4 * RT * 16 query rows in registers and sweeps the data rows
+// [cb, ce) of its split (blockIdx.y) 32 at a time through a ring of LDS
+// stages filled by direct global-to-LDS loads (see lds_ring.h).  Per
+// element one compare of the tile value with the query row's threshold, in
+// the same arithmetic as k_range_tiles; a step with a passing element
+// recomputes its hit bits and appends the candidates to the wave's own
+// buffer of kRangeBuf entries in LDS, which goes out to the candidate
+// arrays with one global atomic when the next append would overflow it and
+// at the end.  (Same-address device atomics serialise across the chip: one
+// per appending wave-step took more time than the tiles.)
+constexpr int kRangeBuf = 64;
+
+template <int NSPLIT, int KP>
+__global__ void __launch_bounds__(256, 2)
+k_range_reg(const uint16_t *Qh, const uint16_t *Ql, int32_t nq, const uint16_t *Xh,
+            const uint16_t *Xl, int32_t nx, const float *nq2, const float *nx2, const float *thr,
+            int metric, int32_t cols_per_split, int32_t *cq, int32_t *cx, int64_t cap,
+            unsigned long long *count) {
+    using S = ring::Shape<NSPLIT, KP>;
+    constexpr int RT = S::RT, CT = S::CT, KS = S::KS, BN = S::BN, CPR = S::CPR, SPR = S::SPR;
+    constexpr int IPW = S::IPW, TERMS = S::TERMS, PART = S::PART, STAGE = S::STAGE, NB = S::NB;
+    constexpr int LPT = S::LPT;
+    __shared__ __attribute__((aligned(1024))) char sring[NB * STAGE];
+    __shared__ int2 sbuf[4][kRangeBuf];
+    static_assert(NB * STAGE + sizeof(sbuf) <= 80 * 1024, "two workgroups per CU");
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r16 = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
+    const int32_t prow0 = (int32_t)blockIdx.x * S::ROWS + w * RT * 16;
+    int2 *wbuf = sbuf[w];
+    int nbuf = 0;  // entries in the wave's buffer (wave-uniform)
+    // the buffer to the candidate arrays: one atomic, then lane-strided
+    // copies (entries past cap are counted, not written)
+    auto flush = [&]() {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(count, (unsigned long long)nbuf);
+        base = __shfl(base, 0);
+        for (int e = lane; e < nbuf; e += 64) {
+            const unsigned long long at = base + e;
+            if (at < (unsigned long long)cap) {
+                const int2 v = wbuf[e];
+                cq[at] = v.x;
+                cx[at] = v.y;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        nbuf = 0;
+    };
+    const int32_t cb = (int32_t)blockIdx.y * cols_per_split;
+    const int32_t ce = min(nx, cb + cols_per_split);
+    const bool l2 = metric == VJ_L2;
+    // the query rows' fragments and terms; rows past nq never pass
+    mt::bf16x8 a[RT][KS], al[NSPLIT == 3 ? RT : 1][NSPLIT == 3 ? KS : 1];
+    float rq2[RT][4], rthr[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            a[rt][ks] = mt::load8(Qh, prow0 + rt * 16 + r16, nq, KP, ks * 32 + kq);
+            if (NSPLIT == 3) al[rt][ks] = mt::load8(Ql, prow0 + rt * 16 + r16, nq, KP, ks * 32 + kq);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int32_t q = prow0 + rt * 16 + rq + i;
+            rq2[rt][i] = q < nq ? nq2[q] : 0.f;
+            rthr[rt][i] = q < nq ? thr[q] : (l2 ? -INFINITY : INFINITY);
+        }
+    }
+    // loads of the data tile at row c0 into stage st (rows past nx load row
+    // nx - 1, masked in the test; pad slots load the tile's first chunk)
+    const uint32_t ring0 = ring::lds_byte_addr(sring);
+    uint32_t soff[IPW];
+    int srow[IPW];
+#pragma unroll
+    for (int j = 0; j < IPW; ++j) {
+        const int sl = (w * IPW + j) * 64 + lane;
+        const int rr = sl / SPR, ch = sl - rr * SPR;
+        const bool real = rr < BN && ch < CPR;
+        srow[j] = real ? rr : 0;
+        soff[j] = real ? (uint32_t)((rr * KP + ch * 8) * 2) : 0u;
+    }
+    auto issue = [&](int32_t c0, int st) {
+        const uint32_t sbase = ring0 + (uint32_t)(st * STAGE);
+        const char *th = reinterpret_cast<const char *>(Xh + (int64_t)c0 * KP);
+        const char *tl = NSPLIT == 3 ? reinterpret_cast<const char *>(Xl + (int64_t)c0 * KP) : nullptr;
+        const bool whole = c0 + BN <= nx;
+#pragma unroll
+        for (int j = 0; j < IPW; ++j) {
+            uint32_t off = soff[j];
+            if (!whole && c0 + srow[j] > nx - 1)
+                off = (uint32_t)(((nx - 1 - c0) * KP) * 2) + (off - (uint32_t)(srow[j] * KP * 2));
+            const uint32_t dst = sbase + (uint32_t)((w * IPW + j) * 1024);
+            ring::lds_dma16(th, off, dst);
+            if (NSPLIT == 3) ring::lds_dma16(tl, off, dst + PART);
+        }
+        const int nr = min(lane < BN ? lane : 0, nx - 1 - c0);
+        ring::lds_dma4(nx2 + c0, (uint32_t)(nr * 4), sbase + TERMS * PART + w * 256);
+        // the second slot is unused here; the load keeps LPT loads per tile
+        ring::lds_dma4(nx2 + c0, (uint32_t)(nr * 4), sbase + TERMS * PART + 1024 + w * 256);
+    };
+    const int ntile = ce > cb ? (ce - cb + BN - 1) / BN : 0;
+    // prologue: tiles 0 .. NB-2 in flight; a slot past the last tile (or
+    // any slot of an empty split, whose cb may lie past nx) re-loads a
+    // valid tile into the last stage, which no tile reads before it is
+    // re-issued
+    const int32_t cvalid = ntile > 0 ? cb : 0;
+#pragma unroll
+    for (int p = 0; p < NB - 1; ++p) issue(p < ntile ? cb + p * BN : cvalid, p < ntile ? p : NB - 1);
+    for (int it = 0; it < ntile; ++it) {
+        const int st = it % NB;
+        ring::wait_barrier<(NB - 2) * LPT>();
+        {
+            const int nxt = it + NB - 1;
+            issue(cb + (nxt < ntile ? nxt : 0) * BN, nxt < ntile ? nxt % NB : (it + NB - 1) % NB);
+        }
+        const char *sp = sring + st * STAGE;
+        floatx4 acc[RT][CT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            mt::bf16x8 b[CT], bl[NSPLIT == 3 ? CT : 1];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const int off = ((ct * 16 + r16) * SPR + ks * 4 + (lane >> 4)) * 16;
+                b[ct] = *reinterpret_cast<const mt::bf16x8 *>(sp + off);
+                if (NSPLIT == 3) bl[ct] = *reinterpret_cast<const mt::bf16x8 *>(sp + PART + off);
+            }
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt][ks], b[ct], acc[rt][ct], 0, 0, 0);
+                    if (NSPLIT == 3) {
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt][ks], bl[ct], acc[rt][ct], 0, 0, 0);
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rt][ks], b[ct], acc[rt][ct], 0, 0, 0);
+                    }
+                }
+        }
+        const int32_t c0 = cb + it * BN;
+        const float *snc = reinterpret_cast<const float *>(sp + TERMS * PART + w * 256);
+        float nc[CT];
+        bool cok[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            cok[ct] = c0 + ct * 16 + r16 < ce;
+            nc[ct] = cok[ct] ? snc[ct * 16 + r16] : INFINITY;
+        }
+        auto pass = [&](int rt, int ct, int i) {
+            return l2 ? rq2[rt][i] + nc[ct] - 2.f * acc[rt][ct][i] < rthr[rt][i]
+                      : cok[ct] && acc[rt][ct][i] > rthr[rt][i];
+        };
+        bool any = false;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) any |= pass(rt, ct, i);
+        if (__ballot(any)) {
+            uint32_t hits = 0;  // bit (rt * CT + ct) * 4 + i
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (pass(rt, ct, i)) hits |= 1u << ((rt * CT + ct) * 4 + i);
+            int excl;
+            const int total =
+                __builtin_amdgcn_readfirstlane(mt::wave_scan(__popc(hits), lane, excl));
+            if (nbuf + total > kRangeBuf) flush();
+            if (total <= kRangeBuf) {
+                int o = nbuf + excl;
+                for (int bt = 0; bt < RT * CT * 4; ++bt) {
+                    if (!(hits & (1u << bt))) continue;
+                    const int rt = bt / (CT * 4), ct = (bt / 4) % CT, i = bt & 3;
+                    wbuf[o++] = make_int2(prow0 + rt * 16 + rq + i, c0 + ct * 16 + r16);
+                }
+                __builtin_amdgcn_wave_barrier();
+                nbuf += total;
+            } else {
+                // more than the buffer holds: straight to the arrays
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(count, (unsigned long long)total);
+                base = __shfl(base, 0);
+                int o = 0;
+                for (int bt = 0; bt < RT * CT * 4; ++bt) {
+                    if (!(hits & (1u << bt))) continue;
+                    const int rt = bt / (CT * 4), ct = (bt / 4) % CT, i = bt & 3;
+                    const unsigned long long at = base + excl + o++;
+                    if (at < (unsigned long long)cap) {
+                        cq[at] = prow0 + rt * 16 + rq + i;
+                        cx[at] = c0 + ct * 16 + r16;
+                    }
+                }
+            }
+        }
+    }
+    if (nbuf > 0) flush();
+    ring::wait_barrier<0>();
+}
+
+template <int NSPLIT, int KP>
+bool launch_range_reg_t(const TileRows &tq, const TileRows &tx, int64_t nq, int64_t nx,
+                        const float *thr, int metric, int32_t *cq, int32_t *cx, int64_t cap,
+                        unsigned long long *count, hipStream_t s) {
+    using S = ring::Shape<NSPLIT, KP>;
+    if constexpr (!S::OK) {
+        return false;
+    } else {
+        const int64_t nb = (nq + S::ROWS - 1) / S::ROWS;
+        const int64_t T = (nx + S::BN - 1) / S::BN;
+        int splits = 1;
+        // no merge across splits here: split until the grid fills the chip
+        // several times over, keeping at least 64 tiles per split
+        while (nb * splits < 4096 && T / (splits * 2) >= 64 && splits < 256) splits *= 2;
+        const int64_t cps = (T + splits - 1) / splits * S::BN;
+        hipLaunchKernelGGL((k_range_reg<NSPLIT, KP>), dim3((unsigned)nb, (unsigned)splits),
+                           dim3(256), 0, s, tq.hi.as<uint16_t>(),
+                           NSPLIT == 3 ? tq.lo.as<uint16_t>() : nullptr, (int32_t)nq,
+                           tx.hi.as<uint16_t>(), NSPLIT == 3 ? tx.lo.as<uint16_t>() : nullptr,
+                           (int32_t)nx, tq.norm2.as<float>(), tx.norm2.as<float>(), thr, metric,
+                           (int32_t)cps, cq, cx, cap, count);
+        return true;
+    }
+}
+
+// the register-row tiles for row widths up to 256, else false
+bool launch_range_reg(int nsplit, int Kp, const TileRows &tq, const TileRows &tx, int64_t nq,
+                      int64_t nx, const float *thr, int metric, int32_t *cq, int32_t *cx,
+                      int64_t cap, unsigned long long *count, hipStream_t s) {
+    if (nq <= 0 || nx <= 0 || nq >= (1ll << 31) || nx >= (1ll << 31)) return false;
+#define VJ_RANGE_CASE(kp)                                                                         \
+    case kp:                                                                                      \
+        return nsplit == 3 ? launch_range_reg_t<3, kp>(tq, tx, nq, nx, thr, metric, cq, cx, cap, count, s) \
+                           : launch_range_reg_t<1, kp>(tq, tx, nq, nx, thr, metric, cq, cx, cap, count, s);
+    switch (Kp) {
+        VJ_RANGE_CASE(32) VJ_RANGE_CASE(64) VJ_RANGE_CASE(96) VJ_RANGE_CASE(128)
+        VJ_RANGE_CASE(192) VJ_RANGE_CASE(256)
+    default: return false;
+    }
+#undef VJ_RANGE_CASE
 }
 
 // fp64 decision for every candidate: 8 lanes per candidate
@@ -454,7 +703,10 @@ int64_t bruteforce_core(const float *Q, int64_t nq, const float *X, int64_t nx, 
         cq = A.take((size_t)cap * sizeof(int32_t));
         cx = A.take((size_t)cap * sizeof(int32_t));
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, ctr.as<unsigned long long>(), 2);
-        if (nsplit == 3)
+        if (launch_range_reg(nsplit, Kp, tq, tx, nq, nx, thr.as<float>(), (int)metric,
+                             cq.as<int32_t>(), cx.as<int32_t>(), cap, ctr.as<unsigned long long>(), s))
+            ;
+        else if (nsplit == 3)
             hipLaunchKernelGGL(k_range_tiles<3>, grid, dim3(256), 0, s, tq.hi.as<uint16_t>(),
                                tq.lo.as<uint16_t>(), nq, tx.hi.as<uint16_t>(), tx.lo.as<uint16_t>(),
                                nx, Kp, tq.norm2.as<float>(), tx.norm2.as<float>(), thr.as<float>(),

@@ -33,26 +33,29 @@ MAKERS = {
 }
 SCALES = {"ood": 0.1}
 
-# the batched stream at 1/10 scale: X = 1,000,000 x 96; 200 batches of
-# 100..10,000 queries; eps per batch for the batch's target mean, calibrated
-# on at most 50 of its queries (seed 504 + batch)
+# the batched stream: 200 batches, eps per batch for the batch's target
+# mean, calibrated on a few of its queries (seed 504 + batch).  "stream" is
+# the 1/10 scale (X = 1,000,000 x 96, batches of 100..10,000 queries, 50
+# sampled per batch); "stream_full" the stated size (X = 10,000,000 x 96,
+# batches of 1,000..100,000 queries, 20 sampled per batch)
 STREAM_SCALE, STREAM_BATCHES, STREAM_SAMPLE = 0.1, 200, 50
+STREAM_FULL_SAMPLE = 20
 
 
-def make_stream(data):
+def make_stream(data, scale=STREAM_SCALE, sample=STREAM_SAMPLE, key="stream"):
     t = time.time()
-    w = workloads.config_stream(scale=STREAM_SCALE, n_batches=STREAM_BATCHES)
+    w = workloads.config_stream(scale=scale, n_batches=STREAM_BATCHES)
     eps = []
     for b, (start, count, target) in enumerate(workloads.stream_batches(w)):
         r = np.random.default_rng(504 + b)
-        m = min(count, STREAM_SAMPLE)
+        m = min(count, sample)
         idx = start + np.sort(r.choice(count, size=m, replace=False))
         eps.append(oracle.calibrate_eps(w.Q[idx], w.X, target, w.metric))
-    data["stream"] = {"eps": eps, "scale": STREAM_SCALE, "n_batches": STREAM_BATCHES,
-                      "sample_per_batch": STREAM_SAMPLE, "metric": w.metric,
+    data[key] = {"eps": eps, "scale": scale, "n_batches": STREAM_BATCHES,
+                      "sample_per_batch": sample, "metric": w.metric,
                       "Q_sha": checksum(w.Q), "X_sha": checksum(w.X),
                       "nq": int(w.Q.shape[0]), "nx": int(w.X.shape[0]), "d": w.d}
-    print(f"stream: {len(eps)} batches, eps {min(eps):.4f}..{max(eps):.4f} ({time.time() - t:.1f}s)",
+    print(f"{key}: {len(eps)} batches, eps {min(eps):.4f}..{max(eps):.4f} ({time.time() - t:.1f}s)",
           flush=True)
 
 
@@ -69,8 +72,11 @@ def sample(w):
 def main(names):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
-        if name == "stream":
-            make_stream(data)
+        if name in ("stream", "stream_full"):
+            if name == "stream":
+                make_stream(data)
+            else:
+                make_stream(data, 1.0, STREAM_FULL_SAMPLE, "stream_full")
             with open(OUT, "w") as f:
                 json.dump(data, f, indent=1, sort_keys=True)
             continue
@@ -90,4 +96,4 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or list(MAKERS) + ["stream"])
+    main(sys.argv[1:] or list(MAKERS) + ["stream", "stream_full"])

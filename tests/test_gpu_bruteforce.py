@@ -106,3 +106,21 @@ def test_nonpositive_eps_and_errors():
     with pytest.raises(vj.VJError):
         vj.vj_bruteforce_join(torch.ones((3, 4), device="cuda"), torch.ones((5, 4), device="cuda"),
                               float("inf"))
+
+
+@pytest.mark.parametrize("d", [96, 128, 250])
+@pytest.mark.parametrize("metric", ["l2", "ip"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_register_row_widths_and_splits(d, metric, precision):
+    # 37 query rows (one row block) against 16,411 data rows: 513 tiles of
+    # 32, split 32 ways, so the last split of the sweep is empty
+    r = np.random.default_rng(d)
+    Q = r.standard_normal((37, d)).astype(np.float32)
+    X = r.standard_normal((16_411, d)).astype(np.float32)
+    if metric == "ip":
+        Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+    D = oracle.dist_matrix(Q, X, metric)
+    eps = float(np.quantile(D, 0.002))
+    G, O = _check(Q, X, eps, metric, precision)
+    assert len(O) > 500
