@@ -27,37 +27,47 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// One wave per row: bf16 hi (and lo) copies padded to Kp, squared norm
-// (fp64 sum rounded to fp32), and flags: bit 0 set if a value is not an
-// integer of magnitude <= 256; max |value| and max norm via atomicMax on the
-// (non-negative) float bits.
-__global__ void k_prep(const float *src, int64_t rows, int d, int Kp, uint16_t *hi, uint16_t *lo,
-                       float *norm2, unsigned *maxabs, unsigned *maxnorm, int *flags) {
-    const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (r >= rows) return;
-    double acc = 0.0;
-    float mabs = 0.f;
+// One wave per row, grid-stride: bf16 hi (and lo) copies padded to Kp,
+// squared norm (fp64 sum rounded to fp32), and flags: bit 0 set if a value
+// is not an integer of magnitude <= 256; max |value| and max norm via one
+// atomicMax per workgroup on the (non-negative) float bits (same-address
+// atomics serialise, so not one per row).
+__global__ void __launch_bounds__(256)
+k_prep(const float *src, int64_t rows, int d, int Kp, uint16_t *hi, uint16_t *lo, float *norm2,
+       unsigned *maxabs, unsigned *maxnorm, int *flags) {
+    __shared__ float s_abs[4], s_norm[4];
+    __shared__ int s_nonint[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    float mabs = 0.f, mnorm = 0.f;
     bool nonint = false;
-    for (int k = lane; k < Kp; k += 64) {
-        const float f = k < d ? src[r * d + k] : 0.f;
-        const uint16_t h = bf16_rne(f);
-        hi[r * Kp + k] = h;
-        if (lo) lo[r * Kp + k] = bf16_rne(f - bf16_to_f(h));
-        acc += (double)f * (double)f;
-        mabs = fmaxf(mabs, fabsf(f));
-        nonint |= !(rintf(f) == f && fabsf(f) <= 256.f);
+    for (int64_t r = (int64_t)blockIdx.x * 4 + w; r < rows; r += (int64_t)gridDim.x * 4) {
+        double acc = 0.0;
+        for (int k = lane; k < Kp; k += 64) {
+            const float f = k < d ? src[r * d + k] : 0.f;
+            const uint16_t h = bf16_rne(f);
+            hi[r * Kp + k] = h;
+            if (lo) lo[r * Kp + k] = bf16_rne(f - bf16_to_f(h));
+            acc += (double)f * (double)f;
+            mabs = fmaxf(mabs, fabsf(f));
+            nonint |= !(rintf(f) == f && fabsf(f) <= 256.f);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) norm2[r] = (float)acc;
+        mnorm = fmaxf(mnorm, (float)sqrt(acc));
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        acc += __shfl_xor(acc, off);
-        mabs = fmaxf(mabs, __shfl_xor(mabs, off));
-    }
-    if (__ballot(nonint) && lane == 0) atomicOr(flags, 1);
-    if (lane == 0) {
-        norm2[r] = (float)acc;
-        atomicMax(maxabs, __float_as_uint(mabs));
-        atomicMax(maxnorm, __float_as_uint((float)sqrt(acc)));
+    for (int off = 32; off > 0; off >>= 1) mabs = fmaxf(mabs, __shfl_xor(mabs, off));
+    const bool wn = __ballot(nonint) != 0;
+    if (lane == 0) { s_abs[w] = mabs; s_norm[w] = mnorm; s_nonint[w] = wn; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float a = 0.f, n = 0.f;
+        int f = 0;
+        for (int i = 0; i < 4; ++i) { a = fmaxf(a, s_abs[i]); n = fmaxf(n, s_norm[i]); f |= s_nonint[i]; }
+        if (f) atomicOr(flags, 1);
+        atomicMax(maxabs, __float_as_uint(a));
+        atomicMax(maxnorm, __float_as_uint(n));
     }
 }
 
@@ -160,11 +170,11 @@ k_range_tiles(const uint16_t *Qh, const uint16_t *Ql, int64_t nq, const uint16_t
 // per appending wave-step took more time than the tiles.)
 constexpr int kRangeBuf = 64;
 
-template <int NSPLIT, int KP>
+template <int NSPLIT, int KP, bool L2>
 __global__ void __launch_bounds__(256, 2)
 k_range_reg(const uint16_t *Qh, const uint16_t *Ql, int32_t nq, const uint16_t *Xh,
             const uint16_t *Xl, int32_t nx, const float *nq2, const float *nx2, const float *thr,
-            int metric, int32_t cols_per_split, int32_t *cq, int32_t *cx, int64_t cap,
+            int32_t cols_per_split, int32_t *cq, int32_t *cx, int64_t cap,
             unsigned long long *count) {
     using S = ring::Shape<NSPLIT, KP>;
     constexpr int RT = S::RT, CT = S::CT, KS = S::KS, BN = S::BN, CPR = S::CPR, SPR = S::SPR;
@@ -198,7 +208,6 @@ k_range_reg(const uint16_t *Qh, const uint16_t *Ql, int32_t nq, const uint16_t *
     };
     const int32_t cb = (int32_t)blockIdx.y * cols_per_split;
     const int32_t ce = min(nx, cb + cols_per_split);
-    const bool l2 = metric == VJ_L2;
     // the query rows' fragments and terms; rows past nq never pass
     mt::bf16x8 a[RT][KS], al[NSPLIT == 3 ? RT : 1][NSPLIT == 3 ? KS : 1];
     float rq2[RT][4], rthr[RT][4];
@@ -213,9 +222,13 @@ k_range_reg(const uint16_t *Qh, const uint16_t *Ql, int32_t nq, const uint16_t *
         for (int i = 0; i < 4; ++i) {
             const int32_t q = prow0 + rt * 16 + rq + i;
             rq2[rt][i] = q < nq ? nq2[q] : 0.f;
-            rthr[rt][i] = q < nq ? thr[q] : (l2 ? -INFINITY : INFINITY);
+            rthr[rt][i] = q < nq ? thr[q] : (L2 ? -INFINITY : INFINITY);
         }
     }
+    // the rows' loads land here, once: the compiler does not see the ring's
+    // loads (inline asm), so without this it waits for them all (vmcnt 0)
+    // before every tile's first MFMA
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     // loads of the data tile at row c0 into stage st (rows past nx load row
     // nx - 1, masked in the test; pad slots load the tile's first chunk)
     const uint32_t ring0 = ring::lds_byte_addr(sring);
@@ -291,24 +304,53 @@ k_range_reg(const uint16_t *Qh, const uint16_t *Ql, int32_t nq, const uint16_t *
         }
         const int32_t c0 = cb + it * BN;
         const float *snc = reinterpret_cast<const float *>(sp + TERMS * PART + w * 256);
+        // columns past the split's end (rows past nx load row nx - 1) occur
+        // only in its last tile: +inf norms (L2) / -inf values (IP) there
+        const bool whole = c0 + BN <= ce;
         float nc[CT];
         bool cok[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
             cok[ct] = c0 + ct * 16 + r16 < ce;
-            nc[ct] = cok[ct] ? snc[ct * 16 + r16] : INFINITY;
+            const float v = snc[ct * 16 + r16];
+            nc[ct] = cok[ct] ? v : INFINITY;
+        }
+        if (!L2 && !whole) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        acc[rt][ct][i] = cok[ct] ? acc[rt][ct][i] : -INFINITY;
+        }
+        // the tile values of k_range_tiles' test, in the same arithmetic,
+        // computed once: d~^2 (L2) or <q, x>~ (IP)
+        if (L2) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        acc[rt][ct][i] = rq2[rt][i] + nc[ct] - 2.f * acc[rt][ct][i];
         }
         auto pass = [&](int rt, int ct, int i) {
-            return l2 ? rq2[rt][i] + nc[ct] - 2.f * acc[rt][ct][i] < rthr[rt][i]
-                      : cok[ct] && acc[rt][ct][i] > rthr[rt][i];
+            return L2 ? acc[rt][ct][i] < rthr[rt][i] : acc[rt][ct][i] > rthr[rt][i];
         };
+        // a row passes somewhere iff the extreme of its values does (min /
+        // max are exact): one compare per row and lane
         bool any = false;
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
+            for (int i = 0; i < 4; ++i) {
+                float e = acc[rt][0][i];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) any |= pass(rt, ct, i);
+                for (int ct = 1; ct < CT; ++ct)
+                    e = L2 ? fminf(e, acc[rt][ct][i]) : fmaxf(e, acc[rt][ct][i]);
+                any |= L2 ? e < rthr[rt][i] : e > rthr[rt][i];
+            }
         if (__ballot(any)) {
             uint32_t hits = 0;  // bit (rt * CT + ct) * 4 + i
 #pragma unroll
@@ -368,12 +410,13 @@ bool launch_range_reg_t(const TileRows &tq, const TileRows &tx, int64_t nq, int6
         // several times over, keeping at least 64 tiles per split
         while (nb * splits < 4096 && T / (splits * 2) >= 64 && splits < 256) splits *= 2;
         const int64_t cps = (T + splits - 1) / splits * S::BN;
-        hipLaunchKernelGGL((k_range_reg<NSPLIT, KP>), dim3((unsigned)nb, (unsigned)splits),
-                           dim3(256), 0, s, tq.hi.as<uint16_t>(),
-                           NSPLIT == 3 ? tq.lo.as<uint16_t>() : nullptr, (int32_t)nq,
-                           tx.hi.as<uint16_t>(), NSPLIT == 3 ? tx.lo.as<uint16_t>() : nullptr,
-                           (int32_t)nx, tq.norm2.as<float>(), tx.norm2.as<float>(), thr, metric,
-                           (int32_t)cps, cq, cx, cap, count);
+        auto kern = metric == VJ_L2 ? k_range_reg<NSPLIT, KP, true> : k_range_reg<NSPLIT, KP, false>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)nb, (unsigned)splits), dim3(256), 0, s,
+                           tq.hi.as<uint16_t>(), NSPLIT == 3 ? tq.lo.as<uint16_t>() : nullptr,
+                           (int32_t)nq, tx.hi.as<uint16_t>(),
+                           NSPLIT == 3 ? tx.lo.as<uint16_t>() : nullptr, (int32_t)nx,
+                           tq.norm2.as<float>(), tx.norm2.as<float>(), thr, (int32_t)cps, cq, cx,
+                           cap, count);
         return true;
     }
 }
@@ -623,7 +666,7 @@ void prepare_rows(const float *src, int64_t rows, int d, int Kp, bool split, Til
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, stats.as<unsigned long long>(), 2);
     unsigned *u = stats.as<unsigned>();
     if (rows > 0)
-        hipLaunchKernelGGL(k_prep, dim3(g1(rows, 4)), dim3(256), 0, s, src, rows, d, Kp,
+        hipLaunchKernelGGL(k_prep, dim3(std::min<unsigned>(g1(rows, 4), 4096)), dim3(256), 0, s, src, rows, d, Kp,
                            t.hi.as<uint16_t>(), split ? t.lo.as<uint16_t>() : nullptr,
                            t.norm2.as<float>(), u, u + 1, reinterpret_cast<int *>(u + 2));
     VJ_HIP(hipGetLastError());
