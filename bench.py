@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--stream-scale", type=float, default=0.1,
                     help="0.1 (X = 1M, 487k queries) or 1.0 (the stated size: X = 10M, 4.87M "
                          "queries)")
+    ap.add_argument("--stream-modes", action="store_true",
+                    help="with --stream (offline index): also join every batch in MI+Adapt "
+                         "(hybrid ADAPT) and hybrid-for-all (FORCE) mode; queries/s and recall")
     ap.add_argument("--stream-insert", action="store_true",
                     help="with --stream: the index starts over X alone and each batch is "
                          "inserted (vj_index_insert_queries) right before its join; batch "
@@ -717,6 +720,28 @@ def stream_main(args, torch, workloads, vj):
             "pair_counts_equal_host_runner": bool(same)}
         log(f"{runner} runner: {dev_runs[runner]['value']:.0f} queries/s, pair counts equal: {same}")
         del dres
+    # the paper's hybrid forms on the same batches (host runner, one timed run
+    # each): MI+Adapt routes the queries its d1/d2 rule flags, FORCE all
+    hybrid_runs = {}
+    if args.stream_modes:
+        for mode in ("adapt", "force"):
+            p2 = vj.join_params(hybrid=mode, start_tier=params.start_tier)
+            p2.precision = params.precision
+            vj.vj_join_batches(idx, starts, counts, eps, params=p2)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            hres, hms = vj.vj_join_batches(idx, starts, counts, eps, params=p2)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - ts
+            hybrid_runs[mode] = {
+                "value": nq / wall, "unit": "queries/s", "ms_per_step": 1000.0 * wall,
+                "batch_ms_p50": float(np.percentile(hms, 50)),
+                "batch_ms_p99": float(np.percentile(hms, 99)),
+                "pairs": int(sum(r.count() for r in hres)),
+                "recall_sampled_batches": recall(hres)}
+            log(f"hybrid {mode}: {hybrid_runs[mode]['value']:.0f} queries/s, recall "
+                f"{hybrid_runs[mode]['recall_sampled_batches']:.4f}")
+            del hres
     line = {
         "metric": f"stream join queries/sec and batch latency (200 batches, {size})",
         "value": nq / float(np.mean(walls)), "unit": "queries/s", "n_gpus": 1,
@@ -731,6 +756,8 @@ def stream_main(args, torch, workloads, vj):
         "device_runner": dev_runs["device"],
         "graph_replay": dev_runs["graph"],
     }
+    if hybrid_runs:
+        line["hybrid_modes"] = hybrid_runs
     print(json.dumps(line), flush=True)
 
 
@@ -764,6 +791,8 @@ def stream_insert(args, torch, vj, Q, X, starts, counts, eps, nq, workload, reca
             res.append(r[0])
             ins_ms.append(1000.0 * (tj - ts))
             join_ms.append(1000.0 * (te - tj))
+            if (b + 1) % 20 == 0:
+                log(f"  batch {b + 1}: insert {sum(ins_ms):.0f} ms, join {sum(join_ms):.0f} ms so far")
         return res, np.array(ins_ms), np.array(join_ms)
 
     for _ in range(max(1, args.warmup)):

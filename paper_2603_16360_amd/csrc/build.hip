@@ -14,6 +14,10 @@
 //      it replaces that node's longest edge), until all are reachable.
 #include <algorithm>
 #include <cfloat>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -209,6 +213,27 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
 // passes.  Thresholds are the K-th key of the last merge (FLT_MAX until a
 // row holds K entries), so every element of the final top-K passes when it
 // is seen, whatever the order.  Rows past the call's M get threshold -inf.
+// progress of long builds on stderr when the environment sets VJ_LOG (the
+// stream is synchronised first, so the time is that of the finished step)
+constexpr int64_t kKnnChunk = 16384;  // row blocks per kNN sweep launch
+double build_clock() {
+    using C = std::chrono::steady_clock;
+    static const C::time_point t0 = C::now();
+    return std::chrono::duration<double>(C::now() - t0).count();
+}
+void build_log(hipStream_t s, const char *fmt, ...) {
+    static const bool on = std::getenv("VJ_LOG") != nullptr;
+    if (!on) return;
+    VJ_HIP(hipStreamSynchronize(s));
+    char msg[256];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(msg, sizeof msg, fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[vj %.1fs] %s\n", build_clock(), msg);
+    std::fflush(stderr);
+}
+
 // order-preserving map of a float key to uint32 (-0 and +0 both map as +0)
 __device__ __forceinline__ uint32_t key_bits(float k) {
     const uint32_t b = __float_as_uint(k + 0.0f);
@@ -302,8 +327,9 @@ template <int NSPLIT, int KP>
 __global__ void __launch_bounds__(256, 2)
 k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_t M,
           const uint16_t *Bh, const uint16_t *Bl, const float *bn2, const int32_t *bid_of,
-          int32_t T, const int32_t *start_tile, int32_t tiles_per_split, int K, float *bkey,
-          int32_t *bid, int32_t rb) {
+          int32_t T, const int32_t *start_tile, int32_t j0, int32_t tiles_per_split,
+          int32_t split_base, const float *tau_in, int K, float *bkey,
+          int32_t *bid, int32_t rb, int32_t blk0) {
     using S = ring::Shape<NSPLIT, KP>;
     constexpr int RT = S::RT, CT = S::CT, KS = S::KS, BN = S::BN, CPR = S::CPR, SPR = S::SPR;
     constexpr int IPW = S::IPW, TERMS = S::TERMS, PART = S::PART, STAGE = S::STAGE, NB = S::NB;
@@ -314,12 +340,13 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r16 = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4, grp = lane >> 4;
-    const int32_t prow0 = (int32_t)blockIdx.x * S::ROWS + w * RT * 16;  // wave's first row (order)
-    const int64_t boff = (int64_t)blockIdx.y * M;  // this split's buffer rows
+    const int32_t blk = blk0 + (int32_t)blockIdx.x;  // row block (launches may be chunked)
+    const int32_t prow0 = blk * S::ROWS + w * RT * 16;  // wave's first row (order)
+    const int64_t boff = (int64_t)(split_base + blockIdx.y) * M;  // this split's buffer rows
     // this split's sweep positions [jb, je); position j is tile (t0 + j) % T
-    const int32_t jb = (int32_t)blockIdx.y * tiles_per_split;
+    const int32_t jb = j0 + (int32_t)blockIdx.y * tiles_per_split;
     const int32_t je = min(T, jb + tiles_per_split);
-    const int32_t t0 = start_tile[blockIdx.x];
+    const int32_t t0 = start_tile[blk];
     // a row is cut back to K once it holds more than merge_at entries: the
     // threshold then tightens early, which keeps the appends few
     const int merge_at = min(K + 96, kKnnCap - BN);
@@ -328,7 +355,7 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
     if (lane < RT * 16) {
         const int32_t node = prow0 + lane < M ? rowperm[prow0 + lane] : -1;
         s_node[w][lane] = node;
-        s_tau[w][lane] = node >= 0 ? FLT_MAX : -INFINITY;
+        s_tau[w][lane] = node < 0 ? -INFINITY : tau_in ? tau_in[prow0 + lane] : FLT_MAX;
     }
 
     // the wave's rows: fragment (rt, ks) holds row rt*16 + (lane & 15),
@@ -387,7 +414,7 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
         const int32_t node = s_node[w][r];
         const float kth = knn_merge_row(bkey, bid, (boff + (node - rb)) * kKnnCap, c, K, lane);
         cnt = lane == r ? min(c, K) : cnt;
-        if (lane == 0) s_tau[w][r] = kth;
+        if (lane == 0) s_tau[w][r] = fminf(s_tau[w][r], kth);
     };
 
     const int ntile = je > jb ? je - jb : 0;
@@ -519,35 +546,56 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
         if (s_node[w][r] >= 0) merge(r);
 }
 
-// top-K of each row over the splits' sorted lists (split s of row i at
-// (s * M + i) * kKnnCap), written to split 0; one wave per row, S * K <= 512
+// one round of the split merge: group g of row i merges lists b + j * step
+// (j < G, list index < S; b = g * G * step; list s of row i at
+// (s * M + i) * kKnnCap, its first K entries) into list b's first K
+// entries, by (key, id); one wave per (row, group), G * K <= 512
 __global__ void __launch_bounds__(256)
-k_knn_merge_splits(float *bkey, int32_t *bid, int64_t M, int S, int K) {
+k_knn_merge_splits(float *bkey, int32_t *bid, int64_t M, int S, int K, int G, int step) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int ng = (S + G * step - 1) / (G * step);
+    const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t i = wv / ng;
     if (i >= M) return;
+    const int b = (int)(wv - i * ng) * G * step;
     float key[8];
     int id[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int e = j * 64 + lane;
-        const int sp = e / K, k = e - sp * K;
-        const bool ok = sp < S;
+        const int jl = e / K, k = e - jl * K;
+        const int sp = b + jl * step;
+        const bool ok = jl < G && sp < S;
         const int64_t o = ((int64_t)sp * M + i) * kKnnCap + k;
         key[j] = ok ? bkey[o] : INFINITY;
         id[j] = ok ? bid[o] : 0x7fffffff;
         if (ok && id[j] < 0) { key[j] = INFINITY; id[j] = 0x7fffffff; }
     }
     mt::wave_sort<8>(key, id, lane);
+    const int64_t ob = ((int64_t)b * M + i) * kKnnCap;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int e = j * 64 + lane;
         if (e < K) {
             const bool ok = key[j] < INFINITY;
-            bkey[i * kKnnCap + e] = key[j];
-            bid[i * kKnnCap + e] = ok ? id[j] : -1;
+            bkey[ob + e] = key[j];
+            bid[ob + e] = ok ? id[j] : -1;
         }
     }
+}
+
+// starting thresholds of a later pass: the K-th key of each row's list 0,
+// i.e. the largest of its K kept entries (kept unordered or sorted),
+// FLT_MAX while it holds fewer than K; by processing position
+// (rowperm[pos] is row rb + i of list 0)
+__global__ void k_list_tau(const float *bkey, const int32_t *bid, const int32_t *rowperm,
+                           int64_t M, int64_t rb, int K, float *tau) {
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= M) return;
+    const int64_t o = ((int64_t)rowperm[pos] - rb) * kKnnCap;
+    float t = -FLT_MAX;
+    for (int e = 0; e < K; ++e) t = bid[o + e] >= 0 ? fmaxf(t, bkey[o + e]) : FLT_MAX;
+    tau[pos] = t;
 }
 
 // reverse offers of the forward lists of rows [rb, rb + M) (fwd indexed from rb)
@@ -576,14 +624,23 @@ __global__ void k_centroid(const float *vec, int64_t N, int dp, double *sum) {
 __global__ void k_centroid_dist(const float *vec, int64_t N, int dp, const double *sum,
                                 double *dist, unsigned long long *best) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= N) return;
-    double acc = 0.0;
-    for (int c = 0; c < dp; ++c) {
-        const double t = (double)vec[r * dp + c] - sum[c] / (double)N;
-        acc += t * t;
+    unsigned long long key = ~0ull;  // non-negative doubles order as their bits
+    if (r < N) {
+        double acc = 0.0;
+        for (int c = 0; c < dp; ++c) {
+            const double t = (double)vec[r * dp + c] - sum[c] / (double)N;
+            acc += t * t;
+        }
+        dist[r] = acc;
+        key = (unsigned long long)__double_as_longlong(acc);
     }
-    dist[r] = acc;
-    atomicMin(best, (unsigned long long)__double_as_longlong(acc));
+    // one atomic per wave
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(key, off);
+        key = o < key ? o : key;
+    }
+    if ((threadIdx.x & 63) == 0 && key != ~0ull) atomicMin(best, key);
 }
 
 __global__ void k_argmin_id(const double *dist, int64_t N, const unsigned long long *best,
@@ -594,19 +651,29 @@ __global__ void k_argmin_id(const double *dist, int64_t N, const unsigned long l
 }
 
 // ------------------------------------------------------ connectivity --
+// one BFS level: every edge of the front; a node seen first here goes to the
+// next front (one counter atomic per wave)
 __global__ void k_bfs_step(const int32_t *adj, int R, const int32_t *front, int nf, int *seen,
                            int32_t *next, int *nnext) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)nf * R) return;
-    const int32_t u = front[t / R];
-    const int32_t v = adj[(int64_t)u * R + t % R];
-    if (v < 0) return;
-    if (atomicExch(&seen[v], 1) == 0) next[atomicAdd(nnext, 1)] = v;
+    int32_t v = -1;
+    if (t < (int64_t)nf * R) v = adj[(int64_t)front[t / R] * R + t % R];
+    const bool fresh = v >= 0 && atomicExch(&seen[v], 1) == 0;
+    const unsigned long long m = __ballot(fresh);
+    if (m == 0) return;
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(nnext, __popcll(m));
+    base = __shfl(base, 0);
+    if (fresh) next[base + __popcll(m & ((1ull << lane) - 1))] = v;
 }
 
+// smallest unseen node: within a wave the lowest lane holds the smallest
+// index, so one atomic per wave
 __global__ void k_first_unseen(const int *seen, int64_t N, int *first) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < N && !seen[r]) atomicMin(first, (int)r);
+    const unsigned long long m = __ballot(r < N && !seen[r]);
+    if (m != 0 && (threadIdx.x & 63) == __ffsll(m) - 1) atomicMin(first, (int)r);
 }
 
 // nearest reached node to w: overall and among nodes with a free slot;
@@ -811,9 +878,11 @@ __global__ void k_sweep_copy(const uint16_t *hi, const uint16_t *lo, const float
 }
 
 // first sweep position of each pivot group (keys: the sorted pivot ids)
-__global__ void k_group_start(const int32_t *keys, int64_t N, int32_t *gstart) {
+__global__ void k_group_start(const int32_t *keys, int64_t N, int32_t *gstart, int32_t *gend) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < N && (j == 0 || keys[j] != keys[j - 1])) gstart[keys[j]] = (int32_t)j;
+    if (j >= N) return;
+    if (j == 0 || keys[j] != keys[j - 1]) gstart[keys[j]] = (int32_t)j;
+    if (j == N - 1 || keys[j] != keys[j + 1]) gend[keys[j]] = (int32_t)(j + 1);
 }
 
 // keys and values of the call's rows [rb, rb + M): their pivot, their id
@@ -826,13 +895,19 @@ __global__ void k_row_keys(const int32_t *assign, int64_t rb, int64_t M, int32_t
 }
 
 // start tile of row block b: the tile holding the start of the pivot group
-// of the block's first row (rkeys: the rows' sorted pivot ids)
+// of the block's first row (rkeys: the rows' sorted pivot ids); span: the
+// tiles from there to the end of the group of the block's last row (every
+// row's own group holds at least the row itself)
 __global__ void k_start_tiles(const int32_t *rkeys, int64_t M, int rows, const int32_t *gstart,
-                              int bn, int64_t nb, int32_t *start_tile) {
+                              const int32_t *gend, int bn, int64_t nb, int32_t *start_tile,
+                              int32_t *span) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
     const int32_t g = gstart[rkeys[b * rows]];
-    start_tile[b] = g >= 0 ? g / bn : 0;
+    const int32_t t0 = g >= 0 ? g / bn : 0;
+    const int32_t e = gend[rkeys[min(M, (b + 1) * rows) - 1]];
+    start_tile[b] = t0;
+    span[b] = e > 0 ? (e + bn - 1) / bn - t0 : 0;
 }
 
 // the register-row kNN sweep for one (NSPLIT, Kp); false if that shape has
@@ -841,8 +916,8 @@ __global__ void k_start_tiles(const int32_t *rkeys, int64_t M, int rows, const i
 // sweep at its own group.  Column splits keep >= 1,024 workgroups when M is
 // small (an insertion batch); their lists are merged into split 0.
 template <int NSPLIT, int KP>
-bool launch_knn_reg_t(const TileRows &t, const float *vec, int dp, int64_t N, int K, int64_t rb,
-                      int64_t M, DevBuf &bkey, DevBuf &bidb, hipStream_t s) {
+bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, int64_t N, int K,
+                      int64_t rb, int64_t M, DevBuf &bkey, DevBuf &bidb, hipStream_t s) {
     using S = ring::Shape<NSPLIT, KP>;
     if constexpr (!S::OK) {
         return false;
@@ -850,16 +925,35 @@ bool launch_knn_reg_t(const TileRows &t, const float *vec, int dp, int64_t N, in
         constexpr int BN = S::BN;
         if (dp > 256) return false;
         const int64_t T = (N + BN - 1) / BN, Np = T * BN;
-        // 1. the nearest pivot of every node
-        const int P = (int)std::min<int64_t>(1024, std::max<int64_t>(1, N / 512));
-        std::vector<int32_t> ph((size_t)P);
-        for (int k = 0; k < P; ++k) ph[(size_t)k] = (int32_t)((int64_t)k * (N / P));
-        DevBuf pids((size_t)P * sizeof(int32_t)), piv((size_t)P * dp * sizeof(float)),
-            assign((size_t)N * sizeof(int32_t));
-        VJ_HIP(hipMemcpyAsync(pids.p, ph.data(), (size_t)P * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        gather_rows_f32(vec, dp, pids.as<int32_t>(), P, piv.as<float>(), s);
-        hipLaunchKernelGGL(k_assign_pivot, dim3(g1b(N, 256)), dim3(256), 0, s, vec, dp, N,
-                           piv.as<float>(), P, assign.as<int32_t>());
+        // 1. the nearest pivot of every node: all nodes after a build's
+        //    choice of pivots; an insertion (rows [rb, N) appended to a graph
+        //    whose nodes [0, rb) are labelled) labels only its new nodes
+        if (ix.piv_n == 0 || rb == 0 || ix.piv_cnt != rb) {
+            const int P = (int)std::min<int64_t>(1024, std::max<int64_t>(1, N / 512));
+            std::vector<int32_t> ph((size_t)P);
+            for (int k = 0; k < P; ++k) ph[(size_t)k] = (int32_t)((int64_t)k * (N / P));
+            DevBuf pids((size_t)P * sizeof(int32_t));
+            ix.piv_rows.alloc((size_t)P * dp * sizeof(float));
+            ix.piv_of.alloc((size_t)N * sizeof(int32_t));
+            VJ_HIP(hipMemcpyAsync(pids.p, ph.data(), (size_t)P * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, s));
+            gather_rows_f32(vec, dp, pids.as<int32_t>(), P, ix.piv_rows.as<float>(), s);
+            hipLaunchKernelGGL(k_assign_pivot, dim3(g1b(N, 256)), dim3(256), 0, s, vec, dp, N,
+                               ix.piv_rows.as<float>(), P, ix.piv_of.as<int32_t>());
+            VJ_HIP(hipStreamSynchronize(s));  // pids is freed on return
+            ix.piv_n = P;
+        } else {
+            DevBuf grown((size_t)N * sizeof(int32_t));
+            VJ_HIP(hipMemcpyAsync(grown.p, ix.piv_of.p, (size_t)rb * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL(k_assign_pivot, dim3(g1b(N - rb, 256)), dim3(256), 0, s,
+                               vec + rb * dp, dp, N - rb, ix.piv_rows.as<float>(), ix.piv_n,
+                               grown.as<int32_t>() + rb);
+            ix.piv_of = std::move(grown);
+        }
+        ix.piv_cnt = N;
+        const int P = ix.piv_n;
+        DevBuf assign = DevBuf::view(ix.piv_of.p, (size_t)N * sizeof(int32_t));
         // 2. columns in pivot order, as sweep-order copies padded to whole tiles
         DevBuf skeys((size_t)N * sizeof(int32_t)), iota((size_t)N * sizeof(int32_t)),
             perm((size_t)N * sizeof(int32_t)), tmp;
@@ -868,55 +962,121 @@ bool launch_knn_reg_t(const TileRows &t, const float *vec, int dp, int64_t N, in
                        perm.as<int32_t>(), N, 11, tmp, s);
         DevBuf bh((size_t)Np * KP * sizeof(uint16_t)),
             bl(NSPLIT == 3 ? (size_t)Np * KP * sizeof(uint16_t) : 16), bn2((size_t)Np * sizeof(float)),
-            bid_of((size_t)Np * sizeof(int32_t)), gstart((size_t)P * sizeof(int32_t));
+            bid_of((size_t)Np * sizeof(int32_t)), gstart((size_t)P * sizeof(int32_t)),
+            gend((size_t)P * sizeof(int32_t));
         hipLaunchKernelGGL(k_sweep_copy, dim3(g1b(Np * (KP / 8), 256)), dim3(256), 0, s,
                            t.hi.as<uint16_t>(), NSPLIT == 3 ? t.lo.as<uint16_t>() : nullptr,
                            t.norm2.as<float>(), KP, perm.as<int32_t>(), N, Np, bh.as<uint16_t>(),
                            NSPLIT == 3 ? bl.as<uint16_t>() : nullptr, bn2.as<float>(),
                            bid_of.as<int32_t>());
         fill_i32(gstart.as<int32_t>(), P, -1, s);
+        fill_i32(gend.as<int32_t>(), P, 0, s);
         hipLaunchKernelGGL(k_group_start, dim3(g1b(N, 256)), dim3(256), 0, s, skeys.as<int32_t>(),
-                           N, gstart.as<int32_t>());
+                           N, gstart.as<int32_t>(), gend.as<int32_t>());
         // 3. the call's rows in pivot order, and each block's start tile
         const int64_t nb = (M + S::ROWS - 1) / S::ROWS;
         DevBuf rkeys((size_t)M * sizeof(int32_t)), rkeys2((size_t)M * sizeof(int32_t)),
             rvals((size_t)M * sizeof(int32_t)), rowperm((size_t)M * sizeof(int32_t)),
-            start_tile((size_t)nb * sizeof(int32_t));
+            start_tile((size_t)nb * sizeof(int32_t)), span((size_t)nb * sizeof(int32_t));
         hipLaunchKernelGGL(k_row_keys, dim3(g1b(M, 256)), dim3(256), 0, s, assign.as<int32_t>(),
                            rb, M, rkeys.as<int32_t>(), rvals.as<int32_t>());
         sort_pairs_i32(rkeys.as<int32_t>(), rkeys2.as<int32_t>(), rvals.as<int32_t>(),
                        rowperm.as<int32_t>(), M, 11, tmp, s);
         hipLaunchKernelGGL(k_start_tiles, dim3(g1b(nb, 256)), dim3(256), 0, s,
-                           rkeys2.as<int32_t>(), M, S::ROWS, gstart.as<int32_t>(), BN, nb,
-                           start_tile.as<int32_t>());
-        // 4. the sweep
-        int splits = 1;
-        while (splits * 2 * K <= 512 && nb * splits < 1024 && T / (splits * 2) >= 8) splits *= 2;
-        const int64_t tps = (T + splits - 1) / splits;
-        bkey.alloc((size_t)splits * M * kKnnCap * sizeof(float));
-        bidb.alloc((size_t)splits * M * kKnnCap * sizeof(int32_t));
-        hipLaunchKernelGGL((k_knn_reg<NSPLIT, KP>), dim3((unsigned)nb, (unsigned)splits), dim3(256),
-                           0, s, t.hi.as<uint16_t>(), NSPLIT == 3 ? t.lo.as<uint16_t>() : nullptr,
-                           rowperm.as<int32_t>(), (int32_t)M, bh.as<uint16_t>(),
-                           NSPLIT == 3 ? bl.as<uint16_t>() : nullptr, bn2.as<float>(),
-                           bid_of.as<int32_t>(), (int32_t)T, start_tile.as<int32_t>(),
-                           (int32_t)tps, K, bkey.as<float>(), bidb.as<int32_t>(), (int32_t)rb);
-        if (splits > 1)
-            hipLaunchKernelGGL(k_knn_merge_splits, dim3(g1b(M, 4)), dim3(256), 0, s,
-                               bkey.as<float>(), bidb.as<int32_t>(), M, splits, K);
+                           rkeys2.as<int32_t>(), M, S::ROWS, gstart.as<int32_t>(),
+                           gend.as<int32_t>(), BN, nb, start_tile.as<int32_t>(),
+                           span.as<int32_t>());
+        // 4. the sweep.  With enough row blocks, one pass over all tiles.
+        //    Otherwise (an insertion batch) two passes, each split over
+        //    columns so that the grid fills the chip: the first over the P1
+        //    tiles from each block's start, P1 covering the groups of all of
+        //    the block's rows (at least 64); its lists are merged and the
+        //    K-th key of each row is the starting threshold of every split of
+        //    the second pass over the remaining tiles (a true top-K entry is
+        //    at or below it, so it passes in its split and survives that
+        //    split's merges); then the lists are merged again.
+        // launches of at most kKnnChunk row blocks (progress between them
+        // when logging; no launch runs for minutes on the largest builds)
+        auto sweep = [&](int32_t j0, int32_t ntiles, int splits, int32_t split_base,
+                         const float *tau_in) {
+            const int64_t tps = (ntiles + splits - 1) / splits;
+            for (int64_t b0 = 0; b0 < nb; b0 += kKnnChunk) {
+                const int64_t nbc = std::min<int64_t>(kKnnChunk, nb - b0);
+                hipLaunchKernelGGL((k_knn_reg<NSPLIT, KP>), dim3((unsigned)nbc, (unsigned)splits),
+                                   dim3(256), 0, s, t.hi.as<uint16_t>(),
+                                   NSPLIT == 3 ? t.lo.as<uint16_t>() : nullptr,
+                                   rowperm.as<int32_t>(), (int32_t)M, bh.as<uint16_t>(),
+                                   NSPLIT == 3 ? bl.as<uint16_t>() : nullptr, bn2.as<float>(),
+                                   bid_of.as<int32_t>(), (int32_t)T, start_tile.as<int32_t>(), j0,
+                                   (int32_t)tps, split_base, tau_in, K, bkey.as<float>(),
+                                   bidb.as<int32_t>(), (int32_t)rb, (int32_t)b0);
+                if (nb > kKnnChunk)
+                    build_log(s, "kNN sweep: row blocks %lld of %lld", (long long)(b0 + nbc),
+                              (long long)nb);
+            }
+        };
+        auto nsplits = [&](int64_t ntiles) {
+            int sp = 1;
+            while (nb * sp < 1024 && ntiles / (sp * 2) >= 8 && sp < 256) sp *= 2;
+            return sp;
+        };
+        // lists 0 .. S-1 of every row into list 0 (sorted), in rounds
+        auto merge_lists = [&](int S) {
+            const int G = std::max(2, 512 / K);
+            for (int64_t step = 1; step < S; step *= G) {
+                const int64_t ng = (S + G * step - 1) / (G * step);
+                hipLaunchKernelGGL(k_knn_merge_splits, dim3(g1b(M * ng, 4)), dim3(256), 0, s,
+                                   bkey.as<float>(), bidb.as<int32_t>(), M, S, K, G, (int)step);
+            }
+        };
+        if (nsplits(T) == 1) {
+            bkey.alloc((size_t)M * kKnnCap * sizeof(float));
+            bidb.alloc((size_t)M * kKnnCap * sizeof(int32_t));
+            sweep(0, (int32_t)T, 1, 0, nullptr);
+        } else {
+            std::vector<int32_t> span_h((size_t)nb);
+            VJ_HIP(hipMemcpyAsync(span_h.data(), span.p, (size_t)nb * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, s));
+            VJ_HIP(hipStreamSynchronize(s));
+            int64_t P1 = 64;
+            for (int32_t v : span_h) P1 = std::max<int64_t>(P1, v);
+            P1 = std::min<int64_t>(T, P1);
+            // a split ends at its start + tiles_per_split (or T): P1 a
+            // multiple of the first pass's splits, so the passes do not
+            // overlap (a column seen twice would be kept twice)
+            const int s1 = nsplits(P1);
+            P1 = std::min<int64_t>(T, (P1 + s1 - 1) / s1 * s1);
+            const int s2 = T > P1 ? nsplits(T - P1) : 0;
+            const int nl = std::max(s1, 1 + s2);
+            bkey.alloc((size_t)nl * M * kKnnCap * sizeof(float));
+            bidb.alloc((size_t)nl * M * kKnnCap * sizeof(int32_t));
+            sweep(0, (int32_t)P1, s1, 0, nullptr);
+            merge_lists(s1);
+            if (s2 > 0) {
+                DevBuf tau((size_t)M * sizeof(float));
+                hipLaunchKernelGGL(k_list_tau, dim3(g1b(M, 256)), dim3(256), 0, s,
+                                   bkey.as<float>(), bidb.as<int32_t>(), rowperm.as<int32_t>(), M,
+                                   rb, K, tau.as<float>());
+                sweep((int32_t)P1, (int32_t)(T - P1), s2, 1, tau.as<float>());
+                merge_lists(1 + s2);
+                VJ_HIP(hipGetLastError());
+                VJ_HIP(hipStreamSynchronize(s));  // tau is freed on return
+            }
+        }
         VJ_HIP(hipGetLastError());
         VJ_HIP(hipStreamSynchronize(s));  // the temporaries above are freed on return
         return true;
     }
 }
 
-bool launch_knn_reg(int nsplit, int Kp, const TileRows &t, const float *vec, int dp, int64_t N,
-                    int K, int64_t rb, int64_t M, DevBuf &bkey, DevBuf &bidb, hipStream_t s) {
+bool launch_knn_reg(Index &ix, int nsplit, int Kp, const TileRows &t, const float *vec, int dp,
+                    int64_t N, int K, int64_t rb, int64_t M, DevBuf &bkey, DevBuf &bidb,
+                    hipStream_t s) {
     if (K > 128 || M <= 0) return false;
 #define VJ_KNN_CASE(kp)                                                                         \
     case kp:                                                                                    \
-        return nsplit == 3 ? launch_knn_reg_t<3, kp>(t, vec, dp, N, K, rb, M, bkey, bidb, s)     \
-                           : launch_knn_reg_t<1, kp>(t, vec, dp, N, K, rb, M, bkey, bidb, s);
+        return nsplit == 3 ? launch_knn_reg_t<3, kp>(ix, t, vec, dp, N, K, rb, M, bkey, bidb, s) \
+                           : launch_knn_reg_t<1, kp>(ix, t, vec, dp, N, K, rb, M, bkey, bidb, s);
     switch (Kp) {
         VJ_KNN_CASE(32) VJ_KNN_CASE(64) VJ_KNN_CASE(96) VJ_KNN_CASE(128) VJ_KNN_CASE(192)
         VJ_KNN_CASE(256)
@@ -927,7 +1087,7 @@ bool launch_knn_reg(int nsplit, int Kp, const TileRows &t, const float *vec, int
 
 // exact top-K candidate lists (ids in bid [M][kKnnCap], K of them) of rows
 // [rb, rb + M) of ix.vec among all ix.N rows, on MFMA tiles
-void knn_candidates(const Index &ix, int64_t rb, int64_t M, int K, DevBuf &bidb, hipStream_t s) {
+void knn_candidates(Index &ix, int64_t rb, int64_t M, int K, DevBuf &bidb, hipStream_t s) {
     const int64_t N = ix.N;
     const int dp = ix.dp;
     const float *vec = ix.vec.as<float>();
@@ -938,7 +1098,7 @@ void knn_candidates(const Index &ix, int64_t rb, int64_t M, int K, DevBuf &bidb,
     tile_error_bounds(t, t, 1, e_dot, e_fin);
     const int nsplit = (e_dot == 0.0) ? 1 : 3;
     DevBuf bkey;
-    if (launch_knn_reg(nsplit, Kp, t, vec, dp, N, K, rb, M, bkey, bidb, s)) {
+    if (launch_knn_reg(ix, nsplit, Kp, t, vec, dp, N, K, rb, M, bkey, bidb, s)) {
         VJ_HIP(hipGetLastError());
         VJ_HIP(hipStreamSynchronize(s));
         return;
@@ -1008,6 +1168,7 @@ void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched
         hipLaunchKernelGGL(k_attach, dim3(1), dim3(64), 0, s, vec, dp, ix.adj.as<int32_t>(), R, p,
                            (int32_t)first);
         ix.repairs += 1;
+        if ((iter + 1) % 1024 == 0) build_log(s, "connectivity repair: %lld edges", (long long)(iter + 1));
         if (touched) touched->push_back(p);
         // a new edge only adds reachability; an overwritten edge may remove some
         if (has_free) bfs_from((int32_t)first, false);
@@ -1028,7 +1189,9 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
 
     // 1. kNN on MFMA tiles over all nodes, then exact re-rank
     DevBuf bidb;
+    build_log(s, "build over %lld nodes: start", (long long)N);
     knn_candidates(ix, 0, N, K, bidb, s);
+    build_log(s, "kNN lists done");
 
     // 2. re-rank + forward prune
     DevBuf kid((size_t)N * kc * sizeof(int32_t)), kd2((size_t)N * kc * sizeof(float));
@@ -1060,6 +1223,7 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
                nullptr, s);
     VJ_HIP(hipGetLastError());
 
+    build_log(s, "forward and reverse prunes done");
     // 4. entry = node nearest to the fp64 centroid (ties: smaller id)
     {
         DevBuf sum((size_t)dp * sizeof(double)), dist((size_t)N * sizeof(double)), best(16);
@@ -1081,6 +1245,7 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
 
     // 5. connectivity repair from the entry
     repair_connectivity(ix, s, nullptr);
+    build_log(s, "connectivity repair done (%lld edges)", (long long)ix.repairs);
 
     // 6. edge lengths
     ix.elen.alloc((size_t)N * R * sizeof(float));

@@ -28,27 +28,35 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 
-__global__ void k_quantize(const float *vec, int64_t n, uint8_t *u8, uint16_t *bf, int32_t *flag) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float f = vec[i];
+// u8 and bf16 copies of n values, grid-stride.  flag bit 0: a value is not
+// an integer in [0, 255]; bit 1: a value is not exact in bf16.  One atomic
+// per workgroup (same-address atomics serialise).
+__global__ void __launch_bounds__(256)
+k_quantize(const float *vec, int64_t n, uint8_t *u8, uint16_t *bf, int32_t *flag) {
+    __shared__ int s_bits[4];
     bool bad_u8 = false, bad_bf = false;
-    if (u8) {
-        const float r = rintf(f);
-        const bool ok = r == f && f >= 0.0f && f <= 255.0f;
-        bad_u8 = !ok;
-        u8[i] = ok ? (uint8_t)r : 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float f = vec[i];
+        if (u8) {
+            const float r = rintf(f);
+            const bool ok = r == f && f >= 0.0f && f <= 255.0f;
+            bad_u8 |= !ok;
+            u8[i] = ok ? (uint8_t)r : 0;
+        }
+        if (bf) {
+            const uint16_t h = to_bf16(f);
+            bf[i] = h;
+            bad_bf |= __uint_as_float((uint32_t)h << 16) != f;
+        }
     }
-    if (bf) {
-        const uint16_t h = to_bf16(f);
-        bf[i] = h;
-        bad_bf = __uint_as_float((uint32_t)h << 16) != f;
-    }
-    // flag bit 0: a value is not an integer in [0, 255]; bit 1: a value is
-    // not exact in bf16 (one atomic per wave)
     const int bits = (__ballot(bad_u8) ? 1 : 0) | (__ballot(bad_bf) ? 2 : 0);
-    if (flag && bits && (threadIdx.x & 63) == __builtin_amdgcn_readfirstlane(threadIdx.x & 63))
-        atomicOr(flag, bits);
+    if ((threadIdx.x & 63) == 0) s_bits[threadIdx.x >> 6] = bits;
+    __syncthreads();
+    if (threadIdx.x == 0 && flag) {
+        const int b = s_bits[0] | s_bits[1] | s_bits[2] | s_bits[3];
+        if (b) atomicOr(flag, b);
+    }
 }
 
 // one 64-thread block per node (node rows[block] when rows is given); thread
@@ -452,7 +460,8 @@ void launch_quantize(const float *vec, int64_t rows, int dp, uint8_t *u8, uint16
                      int32_t *flag, hipStream_t s) {
     const int64_t n = rows * (int64_t)dp;
     if (n == 0) return;
-    hipLaunchKernelGGL(k_quantize, dim3(grid1(n)), dim3(256), 0, s, vec, n, u8, bf16, flag);
+    hipLaunchKernelGGL(k_quantize, dim3(std::min<unsigned>(grid1(n), 8192)), dim3(256), 0, s, vec, n, u8,
+                       bf16, flag);
 }
 
 void launch_edge_lengths(const float *vec, int dp, const int32_t *adj, int64_t N, int R,

@@ -1487,11 +1487,23 @@ vj_status vj_index_insert_queries(vj_index *idx, const float *Q, int64_t n, int3
     b.elen.alloc((size_t)N * R * sizeof(float));
     VJ_HIP(hipMemcpyAsync(b.elen.p, ix.elen.p, (size_t)n_old * R * sizeof(float),
                           hipMemcpyDeviceToDevice, s));
+    // the kNN sweep's pivot labels of the old nodes go with the graph (on an
+    // error they are dropped, and the next insertion labels every node)
+    b.piv_rows = std::move(ix.piv_rows);
+    b.piv_of = std::move(ix.piv_of);
+    b.piv_n = ix.piv_n;
+    b.piv_cnt = ix.piv_cnt;
+    ix.piv_n = 0;
+    ix.piv_cnt = 0;
     insert_graph(b, n_old, kc, s);
     // swap in, then the derived state
     ix.vec = std::move(b.vec);
     ix.adj = std::move(b.adj);
     ix.elen = std::move(b.elen);
+    ix.piv_rows = std::move(b.piv_rows);
+    ix.piv_of = std::move(b.piv_of);
+    ix.piv_n = b.piv_n;
+    ix.piv_cnt = b.piv_cnt;
     ix.nq = b.nq;
     ix.N = N;
     ix.repairs += b.repairs;

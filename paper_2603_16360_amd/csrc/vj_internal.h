@@ -168,6 +168,12 @@ struct Index {
     std::vector<int32_t> lay_entry;
     DevBuf lay_adj, lay_pos, lay_ids, lay_offd, lay_seed;
     int64_t repairs = 0;  // connectivity-repair edges added by the build
+    // pivot order of the kNN sweep, kept so that an insertion labels only
+    // its new nodes: pivot rows (fp32 [piv_n][dp]) and the nearest pivot of
+    // nodes [0, piv_cnt)
+    DevBuf piv_rows, piv_of;
+    int32_t piv_n = 0;
+    int64_t piv_cnt = 0;
     // join state shared by calls on this index (calls on one index must not overlap)
     DevBuf cache;    // int32 [nq] soft work sharing: closest visited data node
     DevBuf inb;      // int32 [nq] generation stamp: query is part of the current call
