@@ -467,20 +467,30 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
         // its 16 x 16 tiles and appends (rare once the rows hold K)
         const float *snc = reinterpret_cast<const float *>(sp + TERMS * PART + w * 256);
         const int32_t *sid = reinterpret_cast<const int32_t *>(sp + TERMS * PART + 1024 + w * 256);
-        bool any = false;
+        float nc[CT];
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-            const float nc = snc[ct * 16 + r16];  // +inf past the last node
+        for (int ct = 0; ct < CT; ++ct) nc[ct] = snc[ct * 16 + r16];  // +inf past the last node
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    acc[rt][ct][i] = fmaf(-2.f, acc[rt][ct][i], nc);
-                    any |= acc[rt][ct][i] <= tau[rt][i];
-                }
-        }
+                for (int i = 0; i < 4; ++i) acc[rt][ct][i] = fmaf(-2.f, acc[rt][ct][i], nc[ct]);
+        // a row passes somewhere iff the smallest of its keys does (fminf is
+        // exact): one compare per row and lane, its wave mask (the compare's
+        // own SGPR result) or-ed into one, no per-element masks kept
+        uint64_t pass_mask = 0;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float m = acc[rt][0][i];
+#pragma unroll
+                for (int ct = 1; ct < CT; ++ct) m = fminf(m, acc[rt][ct][i]);
+                pass_mask |= __ballot(m <= tau[rt][i]);
+            }
         bool appended = false;
-        if (__ballot(any)) {
+        if (pass_mask) {
             appended = true;
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {

@@ -104,3 +104,24 @@ def test_insert_edge_cases():
         s.insert_queries(torch.from_numpy(Q[:4]).cuda())
     with pytest.raises(TypeError):
         idx.insert_queries(torch.from_numpy(Q[:4]))   # host tensor
+
+
+@pytest.mark.parametrize("nx,q0,n", [(10_000, 100, 2_900), (600, 10, 400)],
+                         ids=["two-passes", "first-pass-covers-all"])
+def test_large_batch_identical_to_oracle(nx, q0, n):
+    # one batch large enough that the insertion's kNN sweep splits its first
+    # pass (the tiles of the pivot groups of each block's rows) over several
+    # workgroups and merges them before the second pass; with 1,000 nodes or
+    # fewer there is one pivot group and the first pass covers every tile
+    w = workloads.width_case(128, nx, q0 + n, True, 77)
+    X, Q = w.X, w.Q
+    R = 32
+    g = oracle.build_merged(Q[:q0], X, R)
+    print(f"[gpu-step] insert: index over {nx} + {q0}, one batch of {n}", flush=True)
+    idx = vj.vj_index_from_graph(torch.from_numpy(Q[:q0]).cuda(), torch.from_numpy(X).cuda(),
+                                 torch.from_numpy(g.adj).cuda(), g.entry)
+    want = oracle.insert_batch(Q[:q0], X, g.adj, g.entry, Q[q0:])
+    idx.insert_queries(torch.from_numpy(Q[q0:]).cuda())
+    a = idx.export_graph()[0].cpu().numpy()
+    bad = np.nonzero((a != want.adj).any(1))[0]
+    assert bad.size == 0, f"{bad.size} rows differ: {bad[:10].tolist()}"
