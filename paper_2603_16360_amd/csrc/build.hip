@@ -678,13 +678,48 @@ __global__ void k_bfs_step(const int32_t *adj, int R, const int32_t *front, int 
     if (fresh) next[base + __popcll(m & ((1ull << lane) - 1))] = v;
 }
 
-// smallest unseen node: within a wave the lowest lane holds the smallest
-// index, so one atomic per wave
-__global__ void k_first_unseen(const int *seen, int64_t N, int *first) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const unsigned long long m = __ballot(r < N && !seen[r]);
-    if (m != 0 && (threadIdx.x & 63) == __ffsll(m) - 1) atomicMin(first, (int)r);
+// smallest unseen node in [from, N), grid-stride: a thread's first unseen
+// index is its smallest, the workgroup's minimum goes out with one atomic
+__global__ void __launch_bounds__(256)
+k_first_unseen(const int *seen, int64_t from, int64_t N, int *first) {
+    __shared__ int s_min[4];
+    int best = 0x7fffffff;
+    for (int64_t r = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N;
+         r += (int64_t)gridDim.x * blockDim.x)
+        if (!seen[r]) { best = (int)r; break; }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) best = min(best, __shfl_xor(best, off));
+    if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        best = min(min(s_min[0], s_min[1]), min(s_min[2], s_min[3]));
+        if (best != 0x7fffffff) atomicMin(first, best);
+    }
 }
+
+// the repair loop's device-side state (one copy, read back once per step)
+struct RepairCtl {
+    int first;                     // smallest unseen node (INT_MAX: none)
+    int nnext;                     // BFS: size of the next front
+    unsigned long long best_any;   // (d2 bits << 32 | id) of the nearest reached node
+    unsigned long long best_free;  // the same among nodes with a free slot
+};
+
+__global__ void k_repair_reset(RepairCtl *c) {
+    c->first = 0x7fffffff;
+    c->nnext = 0;
+    c->best_any = ~0ull;
+    c->best_free = ~0ull;
+}
+
+// BFS seed: start is seen, the front is {start}
+__global__ void k_bfs_seed(int *seen, int32_t *front, int32_t start, RepairCtl *c) {
+    seen[start] = 1;
+    front[0] = start;
+    c->nnext = 0;
+}
+
+__global__ void k_zero_nnext(RepairCtl *c) { c->nnext = 0; }
 
 // nearest reached node to w: overall and among nodes with a free slot;
 // results packed as (float bits << 32 | id) so atomicMin gives (d2, id) order.
@@ -693,14 +728,36 @@ __device__ __forceinline__ unsigned long long min_u64(unsigned long long a, unsi
     return a < b ? a : b;
 }
 
+// one lane's share of |a - b|^2 over float4 chunks p8, p8 + 8, ... (8 lanes
+// per node; the caller sums the 8 lanes with xor shuffles 4, 2, 1): every
+// repair kernel uses this order, so equal inputs give equal bits
+__device__ __forceinline__ float d2_part(const float4 *a, const float4 *b, int nc4, int p8) {
+    float acc = 0.f;
+    for (int c = p8; c < nc4; c += 8) {
+        const float4 x = a[c], y = b[c];
+        float t = x.x - y.x; acc = fmaf(t, t, acc);
+        t = x.y - y.y; acc = fmaf(t, t, acc);
+        t = x.z - y.z; acc = fmaf(t, t, acc);
+        t = x.w - y.w; acc = fmaf(t, t, acc);
+    }
+    return acc;
+}
+__device__ __forceinline__ float sum8(float acc) {
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    return acc;
+}
+
 __global__ void __launch_bounds__(256)
-k_nearest_reached(const float *vec, int64_t N, int dp, int32_t w, const int *seen,
+k_nearest_reached(const float *vec, int64_t N, int dp, const int *wp, const int *seen,
                   const int32_t *adj, int R, unsigned long long *best_any,
                   unsigned long long *best_free) {
     // 8 lanes per node, 32 nodes per workgroup step, grid-stride over the
     // nodes; one atomic per workgroup (the minimum of unique (d2, id) keys
-    // does not depend on the order)
+    // does not depend on the order).  w (*wp) INT_MAX: nothing to do.
     __shared__ unsigned long long s_a[4], s_f[4];
+    const int32_t w = *wp;
+    if (w == 0x7fffffff) return;
     const int lane = threadIdx.x & 63;
     const int g = lane >> 3, p8 = lane & 7;
     const float4 *b = reinterpret_cast<const float4 *>(vec + (int64_t)w * dp);
@@ -710,18 +767,8 @@ k_nearest_reached(const float *vec, int64_t N, int dp, int32_t w, const int *see
         const int64_t p = base + (threadIdx.x >> 6) * 8 + g;
         const bool ok = p < N && seen[p];
         float acc = 0.f;
-        if (ok) {
-            const float4 *a = reinterpret_cast<const float4 *>(vec + p * dp);
-            for (int c = p8; c < dp / 4; c += 8) {
-                const float4 x = a[c], y = b[c];
-                float t = x.x - y.x; acc = fmaf(t, t, acc);
-                t = x.y - y.y; acc = fmaf(t, t, acc);
-                t = x.z - y.z; acc = fmaf(t, t, acc);
-                t = x.w - y.w; acc = fmaf(t, t, acc);
-            }
-        }
-#pragma unroll
-        for (int off = 4; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (ok) acc = d2_part(reinterpret_cast<const float4 *>(vec + p * dp), b, dp / 4, p8);
+        acc = sum8(acc);
         if (ok) {
             const unsigned long long key = ((unsigned long long)__float_as_uint(acc) << 32) | (uint32_t)p;
             ka = min_u64(ka, key);
@@ -1136,53 +1183,67 @@ void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched
     const int R = ix.R, dp = ix.dp;
     const float *vec = ix.vec.as<float>();
     DevBuf seen((size_t)N * sizeof(int)), fa((size_t)N * sizeof(int32_t)),
-        fb((size_t)N * sizeof(int32_t)), misc(32);
+        fb((size_t)N * sizeof(int32_t)), ctlb(sizeof(RepairCtl));
     int *seenp = seen.as<int>();
-    int32_t *misc_i = misc.as<int32_t>();
+    RepairCtl *ctl = ctlb.as<RepairCtl>();
+    // pinned mirror of the control block: one small read-back per step
+    RepairCtl *h = nullptr;
+    VJ_HIP(hipHostMalloc((void **)&h, sizeof(RepairCtl), hipHostMallocDefault));
+    struct Free {
+        RepairCtl *p;
+        ~Free() { (void)hipHostFree(p); }
+    } free_h{h};
+    auto readback = [&]() {
+        VJ_HIP(hipMemcpyAsync(h, ctl, sizeof(RepairCtl), hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipStreamSynchronize(s));
+    };
     auto bfs_from = [&](int32_t start, bool reset) {
         if (reset) VJ_HIP(hipMemsetAsync(seen.p, 0, seen.bytes, s));
-        int one = 1;
-        VJ_HIP(hipMemcpyAsync(seenp + start, &one, sizeof(int), hipMemcpyHostToDevice, s));
-        VJ_HIP(hipMemcpyAsync(fa.p, &start, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_bfs_seed, dim3(1), dim3(1), 0, s, seenp, fa.as<int32_t>(), start, ctl);
         int nf = 1;
         int32_t *cur = fa.as<int32_t>(), *nxt = fb.as<int32_t>();
         for (int64_t level = 0; nf > 0 && level <= N; ++level) {
-            VJ_HIP(hipMemsetAsync(misc_i, 0, sizeof(int), s));
+            if (level > 0) hipLaunchKernelGGL(k_zero_nnext, dim3(1), dim3(1), 0, s, ctl);
             hipLaunchKernelGGL(k_bfs_step, dim3(g1b((int64_t)nf * R, 256)), dim3(256), 0, s,
-                               ix.adj.as<int32_t>(), R, cur, nf, seenp, nxt, misc_i);
-            VJ_HIP(hipMemcpyAsync(&nf, misc_i, sizeof(int), hipMemcpyDeviceToHost, s));
-            VJ_HIP(hipStreamSynchronize(s));
+                               ix.adj.as<int32_t>(), R, cur, nf, seenp, nxt, &ctl->nnext);
+            readback();
+            nf = h->nnext;
             std::swap(cur, nxt);
         }
     };
     bfs_from(ix.entry, true);
     const int64_t max_iter = std::min<int64_t>(N, 200000);
+    // while edges are only added, reachability only grows and the smallest
+    // unseen node only moves up: each scan starts after the last one
+    int64_t from = 0;
+    const unsigned scan_grid = std::min<unsigned>(g1b(N, 256), 1024);
     for (int64_t iter = 0;; ++iter) {
         VJ_CHECK(iter <= max_iter, VJ_ERR_INTERNAL, "connectivity repair did not converge");
-        int first = 0x7fffffff;
-        VJ_HIP(hipMemcpyAsync(misc_i, &first, sizeof(int), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_first_unseen, dim3(g1b(N, 256)), dim3(256), 0, s, seenp, N, misc_i);
-        VJ_HIP(hipMemcpyAsync(&first, misc_i, sizeof(int), hipMemcpyDeviceToHost, s));
-        VJ_HIP(hipStreamSynchronize(s));
+        hipLaunchKernelGGL(k_repair_reset, dim3(1), dim3(1), 0, s, ctl);
+        hipLaunchKernelGGL(k_first_unseen, dim3(scan_grid), dim3(256), 0, s, seenp, from, N,
+                           &ctl->first);
+        hipLaunchKernelGGL(k_nearest_reached, dim3(std::min<unsigned>(g1b(N, 32), 2048)), dim3(256),
+                           0, s, vec, N, dp, &ctl->first, seenp, ix.adj.as<int32_t>(), R,
+                           &ctl->best_any, &ctl->best_free);
+        readback();
+        const int32_t first = h->first;
         if (first == 0x7fffffff) break;
-        unsigned long long init[2] = {~0ull, ~0ull}, got[2];
-        VJ_HIP(hipMemcpyAsync(misc.as<char>() + 8, init, 16, hipMemcpyHostToDevice, s));
-        unsigned long long *bests = reinterpret_cast<unsigned long long *>(misc.as<char>() + 8);
-        hipLaunchKernelGGL(k_nearest_reached, dim3(std::min<unsigned>(g1b(N, 32), 2048)), dim3(256), 0, s, vec, N, dp,
-                           (int32_t)first, seenp, ix.adj.as<int32_t>(), R, bests, bests + 1);
-        VJ_HIP(hipMemcpyAsync(got, bests, 16, hipMemcpyDeviceToHost, s));
-        VJ_HIP(hipStreamSynchronize(s));
-        const bool has_free = got[1] != ~0ull;
-        const int32_t p = (int32_t)(uint32_t)(has_free ? got[1] : got[0]);
+        const bool has_free = h->best_free != ~0ull;
+        const int32_t p = (int32_t)(uint32_t)(has_free ? h->best_free : h->best_any);
         VJ_CHECK(p >= 0 && p < N, VJ_ERR_INTERNAL, "repair source");
         hipLaunchKernelGGL(k_attach, dim3(1), dim3(64), 0, s, vec, dp, ix.adj.as<int32_t>(), R, p,
-                           (int32_t)first);
+                           first);
         ix.repairs += 1;
         if ((iter + 1) % 1024 == 0) build_log(s, "connectivity repair: %lld edges", (long long)(iter + 1));
         if (touched) touched->push_back(p);
         // a new edge only adds reachability; an overwritten edge may remove some
-        if (has_free) bfs_from((int32_t)first, false);
-        else bfs_from(ix.entry, true);
+        if (has_free) {
+            bfs_from(first, false);
+            from = first + 1;
+        } else {
+            bfs_from(ix.entry, true);
+            from = 0;
+        }
     }
 }
 
