@@ -976,7 +976,7 @@ template <int NSPLIT, int KP>
 bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, int64_t N, int K,
                       int64_t rb, int64_t M, DevBuf &bkey, DevBuf &bidb, hipStream_t s) {
     using S = ring::Shape<NSPLIT, KP>;
-    if constexpr (!S::OK) {
+    if constexpr (!S::OK || !S::WHOLE) {
         return false;
     } else {
         constexpr int BN = S::BN;

@@ -157,7 +157,7 @@ k_range_tiles(const uint16_t *Qh, const uint16_t *Ql, int64_t nq, const uint16_t
     }
 }
 
-// The same candidate test on register-row tiles (Kp <= 256): a workgroup of
+// The same candidate test on register-row tiles (Kp <= 1,024): a workgroup of
 // 4 waves holds 4 * RT * 16 query rows in registers and sweeps the data rows
 // [cb, ce) of its split (blockIdx.y) 32 at a time through a ring of LDS
 // stages filled by direct global-to-LDS loads (see lds_ring.h).  Per
@@ -179,7 +179,7 @@ k_range_reg(const uint16_t *Qh, const uint16_t *Ql, int32_t nq, const uint16_t *
     using S = ring::Shape<NSPLIT, KP>;
     constexpr int RT = S::RT, CT = S::CT, KS = S::KS, BN = S::BN, CPR = S::CPR, SPR = S::SPR;
     constexpr int IPW = S::IPW, TERMS = S::TERMS, PART = S::PART, STAGE = S::STAGE, NB = S::NB;
-    constexpr int LPT = S::LPT;
+    constexpr int LPT = S::LPT, KC = S::KC, NCH = S::NCH, KCS = S::KCS;
     __shared__ __attribute__((aligned(1024))) char sring[NB * STAGE];
     __shared__ int2 sbuf[4][kRangeBuf];
     static_assert(NB * STAGE + sizeof(sbuf) <= 80 * 1024, "two workgroups per CU");
@@ -242,10 +242,16 @@ k_range_reg(const uint16_t *Qh, const uint16_t *Ql, int32_t nq, const uint16_t *
         srow[j] = real ? rr : 0;
         soff[j] = real ? (uint32_t)((rr * KP + ch * 8) * 2) : 0u;
     }
-    auto issue = [&](int32_t c0, int st) {
+    const int ntile = ce > cb ? (ce - cb + BN - 1) / BN : 0;
+    const int nstage = ntile * NCH;  // (tile, chunk) stages of this split, in order
+    // stage sg (tile sg / NCH, dimensions (sg % NCH) * KC ..) into ring slot
+    // st; an empty split (cb may lie past nx) loads from row 0
+    auto issue = [&](int sg, int st) {
+        const int32_t c0 = ntile > 0 ? cb + (sg / NCH) * BN : 0;
+        const int kc0 = (sg % NCH) * KC;
         const uint32_t sbase = ring0 + (uint32_t)(st * STAGE);
-        const char *th = reinterpret_cast<const char *>(Xh + (int64_t)c0 * KP);
-        const char *tl = NSPLIT == 3 ? reinterpret_cast<const char *>(Xl + (int64_t)c0 * KP) : nullptr;
+        const char *th = reinterpret_cast<const char *>(Xh + (int64_t)c0 * KP + kc0);
+        const char *tl = NSPLIT == 3 ? reinterpret_cast<const char *>(Xl + (int64_t)c0 * KP + kc0) : nullptr;
         const bool whole = c0 + BN <= nx;
 #pragma unroll
         for (int j = 0; j < IPW; ++j) {
@@ -258,36 +264,39 @@ k_range_reg(const uint16_t *Qh, const uint16_t *Ql, int32_t nq, const uint16_t *
         }
         const int nr = min(lane < BN ? lane : 0, nx - 1 - c0);
         ring::lds_dma4(nx2 + c0, (uint32_t)(nr * 4), sbase + TERMS * PART + w * 256);
-        // the second slot is unused here; the load keeps LPT loads per tile
+        // the second slot is unused here; the load keeps LPT loads per stage
         ring::lds_dma4(nx2 + c0, (uint32_t)(nr * 4), sbase + TERMS * PART + 1024 + w * 256);
     };
-    const int ntile = ce > cb ? (ce - cb + BN - 1) / BN : 0;
-    // prologue: tiles 0 .. NB-2 in flight; a slot past the last tile (or
-    // any slot of an empty split, whose cb may lie past nx) re-loads a
-    // valid tile into the last stage, which no tile reads before it is
-    // re-issued
-    const int32_t cvalid = ntile > 0 ? cb : 0;
+    // prologue: stages 0 .. NB-2 in flight; a slot past the last stage
+    // re-loads stage 0 into the last ring slot, which no stage reads before
+    // it is re-issued
 #pragma unroll
-    for (int p = 0; p < NB - 1; ++p) issue(p < ntile ? cb + p * BN : cvalid, p < ntile ? p : NB - 1);
+    for (int p = 0; p < NB - 1; ++p) issue(p < nstage ? p : 0, p < nstage ? p : NB - 1);
+    floatx4 acc[RT][CT];
     for (int it = 0; it < ntile; ++it) {
-        const int st = it % NB;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        const int sidx = it * NCH + ch;
+        const int st = sidx % NB;
         ring::wait_barrier<(NB - 2) * LPT>();
         {
-            const int nxt = it + NB - 1;
-            issue(cb + (nxt < ntile ? nxt : 0) * BN, nxt < ntile ? nxt % NB : (it + NB - 1) % NB);
+            const int nxs = sidx + NB - 1;
+            issue(nxs < nstage ? nxs : 0, nxs < nstage ? nxs % NB : nxs % NB);
         }
         const char *sp = sring + st * STAGE;
-        floatx4 acc[RT][CT];
+        if (ch == 0) {
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+                for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
+        for (int kk = 0; kk < KCS; ++kk) {
+            const int ks = ch * KCS + kk;
             mt::bf16x8 b[CT], bl[NSPLIT == 3 ? CT : 1];
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
-                const int off = ((ct * 16 + r16) * SPR + ks * 4 + (lane >> 4)) * 16;
+                const int off = ((ct * 16 + r16) * SPR + kk * 4 + (lane >> 4)) * 16;
                 b[ct] = *reinterpret_cast<const mt::bf16x8 *>(sp + off);
                 if (NSPLIT == 3) bl[ct] = *reinterpret_cast<const mt::bf16x8 *>(sp + PART + off);
             }
@@ -302,6 +311,7 @@ k_range_reg(const uint16_t *Qh, const uint16_t *Ql, int32_t nq, const uint16_t *
                     }
                 }
         }
+        if (ch < NCH - 1) continue;
         const int32_t c0 = cb + it * BN;
         const float *snc = reinterpret_cast<const float *>(sp + TERMS * PART + w * 256);
         // columns past the split's end (rows past nx load row nx - 1) occur
@@ -391,6 +401,7 @@ k_range_reg(const uint16_t *Qh, const uint16_t *Ql, int32_t nq, const uint16_t *
             }
         }
     }
+    }
     if (nbuf > 0) flush();
     ring::wait_barrier<0>();
 }
@@ -421,7 +432,8 @@ bool launch_range_reg_t(const TileRows &tq, const TileRows &tx, int64_t nq, int6
     }
 }
 
-// the register-row tiles for row widths up to 256, else false
+// the register-row tiles for the listed row widths (up to 1,024; wider rows
+// staged in chunks), else false
 bool launch_range_reg(int nsplit, int Kp, const TileRows &tq, const TileRows &tx, int64_t nq,
                       int64_t nx, const float *thr, int metric, int32_t *cq, int32_t *cx,
                       int64_t cap, unsigned long long *count, hipStream_t s) {
@@ -432,7 +444,8 @@ bool launch_range_reg(int nsplit, int Kp, const TileRows &tq, const TileRows &tx
                            : launch_range_reg_t<1, kp>(tq, tx, nq, nx, thr, metric, cq, cx, cap, count, s);
     switch (Kp) {
         VJ_RANGE_CASE(32) VJ_RANGE_CASE(64) VJ_RANGE_CASE(96) VJ_RANGE_CASE(128)
-        VJ_RANGE_CASE(192) VJ_RANGE_CASE(256)
+        VJ_RANGE_CASE(192) VJ_RANGE_CASE(256) VJ_RANGE_CASE(384) VJ_RANGE_CASE(512)
+        VJ_RANGE_CASE(768) VJ_RANGE_CASE(960) VJ_RANGE_CASE(1024)
     default: return false;
     }
 #undef VJ_RANGE_CASE

@@ -108,12 +108,13 @@ def test_nonpositive_eps_and_errors():
                               float("inf"))
 
 
-@pytest.mark.parametrize("d", [96, 128, 250])
+@pytest.mark.parametrize("d", [96, 128, 250, 384, 500, 768, 960, 1000])
 @pytest.mark.parametrize("metric", ["l2", "ip"])
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_register_row_widths_and_splits(d, metric, precision):
     # 37 query rows (one row block) against 16,411 data rows: 513 tiles of
-    # 32, split 32 ways, so the last split of the sweep is empty
+    # 32 over column splits with a ragged last tile; rows wider than 256
+    # are staged in chunks of 128 (960: 192) dimensions
     r = np.random.default_rng(d)
     Q = r.standard_normal((37, d)).astype(np.float32)
     X = r.standard_normal((16_411, d)).astype(np.float32)
