@@ -795,7 +795,7 @@ def stream_insert(args, torch, vj, Q, X, starts, counts, eps, nq, workload, reca
                 log(f"  batch {b + 1}: insert {sum(ins_ms):.0f} ms, join {sum(join_ms):.0f} ms so far")
         return res, np.array(ins_ms), np.array(join_ms)
 
-    for _ in range(max(1, args.warmup)):
+    for _ in range(args.warmup):  # a warm-up pass is a whole stream (0 allowed)
         one_pass(idx)
         idx = None
         idx = fresh()

@@ -281,7 +281,7 @@ k_range_reg(const uint16_t *Qh, const uint16_t *Ql, int32_t nq, const uint16_t *
         ring::wait_barrier<(NB - 2) * LPT>();
         {
             const int nxs = sidx + NB - 1;
-            issue(nxs < nstage ? nxs : 0, nxs < nstage ? nxs % NB : nxs % NB);
+            issue(nxs < nstage ? nxs : 0, nxs % NB);
         }
         const char *sp = sring + st * STAGE;
         if (ch == 0) {
