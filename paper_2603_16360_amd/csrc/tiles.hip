@@ -374,10 +374,11 @@ k_range_reg(const uint16_t *Qh, const uint16_t *Ql, int32_t nq, const uint16_t *
             const int total =
                 __builtin_amdgcn_readfirstlane(mt::wave_scan(__popc(hits), lane, excl));
             if (nbuf + total > kRangeBuf) flush();
+            // a lane walks only its set hit bits (usually one or two)
             if (total <= kRangeBuf) {
                 int o = nbuf + excl;
-                for (int bt = 0; bt < RT * CT * 4; ++bt) {
-                    if (!(hits & (1u << bt))) continue;
+                for (uint32_t hm = hits; hm; hm &= hm - 1) {
+                    const int bt = __builtin_ctz(hm);
                     const int rt = bt / (CT * 4), ct = (bt / 4) % CT, i = bt & 3;
                     wbuf[o++] = make_int2(prow0 + rt * 16 + rq + i, c0 + ct * 16 + r16);
                 }
@@ -389,8 +390,8 @@ k_range_reg(const uint16_t *Qh, const uint16_t *Ql, int32_t nq, const uint16_t *
                 if (lane == 0) base = atomicAdd(count, (unsigned long long)total);
                 base = __shfl(base, 0);
                 int o = 0;
-                for (int bt = 0; bt < RT * CT * 4; ++bt) {
-                    if (!(hits & (1u << bt))) continue;
+                for (uint32_t hm = hits; hm; hm &= hm - 1) {
+                    const int bt = __builtin_ctz(hm);
                     const int rt = bt / (CT * 4), ct = (bt / 4) % CT, i = bt & 3;
                     const unsigned long long at = base + excl + o++;
                     if (at < (unsigned long long)cap) {
