@@ -608,6 +608,18 @@ __global__ void k_list_tau(const float *bkey, const int32_t *bid, const int32_t 
     tau[pos] = t;
 }
 
+// an insertion's changing rows: every old node that receives an offer and
+// every new node (flag), then their ids at the flags' scan positions
+__global__ void k_changed_flags(const int32_t *indeg, int64_t n_old, int64_t N, int32_t *flag) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < N) flag[v] = v >= n_old || indeg[v] > 0;
+}
+__global__ void k_scatter_flagged(const int32_t *flag, const int64_t *pos, int64_t N,
+                                  int32_t *rows) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < N && flag[v]) rows[pos[v]] = (int32_t)v;
+}
+
 // reverse offers of the forward lists of rows [rb, rb + M) (fwd indexed from rb)
 __global__ void k_scatter_rev(int64_t M, int R, const int32_t *fwd, const float *fwd_d2,
                               const int64_t *roff, int32_t *rpos, int32_t *rid, float *rd2,
@@ -1274,16 +1286,15 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
     VJ_HIP(hipGetLastError());
     bidb.release();
 
-    // 3. reverse lists (CSR by target), then the final rows
-    std::vector<int32_t> indeg_h((size_t)N);
-    VJ_HIP(hipMemcpyAsync(indeg_h.data(), indeg.p, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    // 3. reverse lists (CSR by target, offsets scanned on the device), then
+    //    the final rows
+    DevBuf roff((size_t)(N + 1) * sizeof(int64_t)), rpos((size_t)N * sizeof(int32_t)), stmp;
+    exclusive_scan_i32_i64(indeg.as<int32_t>(), roff.as<int64_t>(), N, stmp, s);
+    int64_t nrev = 0;
+    VJ_HIP(hipMemcpyAsync(&nrev, roff.as<int64_t>() + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     VJ_HIP(hipStreamSynchronize(s));
-    std::vector<int64_t> roff_h((size_t)N + 1, 0);
-    for (int64_t v = 0; v < N; ++v) roff_h[v + 1] = roff_h[v] + indeg_h[v];
-    DevBuf roff((size_t)(N + 1) * sizeof(int64_t)), rpos((size_t)N * sizeof(int32_t));
-    DevBuf rid((size_t)std::max<int64_t>(roff_h[N], 1) * sizeof(int32_t));
-    DevBuf rd2((size_t)std::max<int64_t>(roff_h[N], 1) * sizeof(float));
-    VJ_HIP(hipMemcpyAsync(roff.p, roff_h.data(), (N + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DevBuf rid((size_t)std::max<int64_t>(nrev, 1) * sizeof(int32_t));
+    DevBuf rd2((size_t)std::max<int64_t>(nrev, 1) * sizeof(float));
     VJ_HIP(hipMemsetAsync(rpos.p, 0, rpos.bytes, s));
     hipLaunchKernelGGL(k_scatter_rev, dim3(g1b(N * R, 256)), dim3(256), 0, s, N, R,
                        fwd.as<int32_t>(), fwd_d2.as<float>(), roff.as<int64_t>(),
@@ -1346,28 +1357,29 @@ void insert_graph(Index &ix, int64_t n_old, int kc, hipStream_t s) {
                 fwd.as<int32_t>(), fwd_d2.as<float>(), fdeg.as<int32_t>(), indeg.as<int32_t>(),
                 n_old, M, s);
     VJ_HIP(hipGetLastError());
-    std::vector<int32_t> indeg_h((size_t)N);
-    VJ_HIP(hipMemcpyAsync(indeg_h.data(), indeg.p, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    VJ_HIP(hipStreamSynchronize(s));
     bidb.release();
     kid.release();
     kd2.release();
 
     // 2. offers (CSR by target) and the rows that change: every old row that
-    //    receives an offer, and every new row
-    std::vector<int64_t> roff_h((size_t)N + 1, 0);
-    for (int64_t v = 0; v < N; ++v) roff_h[v + 1] = roff_h[v] + indeg_h[v];
-    std::vector<int32_t> rows_h;
-    for (int64_t v = 0; v < n_old; ++v)
-        if (indeg_h[v] > 0) rows_h.push_back((int32_t)v);
-    for (int64_t v = n_old; v < N; ++v) rows_h.push_back((int32_t)v);
-    const int64_t L = (int64_t)rows_h.size();
-    DevBuf roff((size_t)(N + 1) * sizeof(int64_t)), rpos((size_t)N * sizeof(int32_t));
-    DevBuf rid((size_t)std::max<int64_t>(roff_h[N], 1) * sizeof(int32_t));
-    DevBuf rd2((size_t)std::max<int64_t>(roff_h[N], 1) * sizeof(float));
-    DevBuf rows((size_t)L * sizeof(int32_t));
-    VJ_HIP(hipMemcpyAsync(roff.p, roff_h.data(), (N + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    VJ_HIP(hipMemcpyAsync(rows.p, rows_h.data(), L * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    //    receives an offer, and every new row (offsets and the row list
+    //    scanned on the device; two totals come back)
+    DevBuf roff((size_t)(N + 1) * sizeof(int64_t)), rpos((size_t)N * sizeof(int32_t)),
+        flag((size_t)N * sizeof(int32_t)), fpos((size_t)(N + 1) * sizeof(int64_t)), stmp;
+    exclusive_scan_i32_i64(indeg.as<int32_t>(), roff.as<int64_t>(), N, stmp, s);
+    hipLaunchKernelGGL(k_changed_flags, dim3(g1b(N, 256)), dim3(256), 0, s, indeg.as<int32_t>(),
+                       n_old, N, flag.as<int32_t>());
+    exclusive_scan_i32_i64(flag.as<int32_t>(), fpos.as<int64_t>(), N, stmp, s);
+    int64_t tot[2] = {0, 0};
+    VJ_HIP(hipMemcpyAsync(&tot[0], roff.as<int64_t>() + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipMemcpyAsync(&tot[1], fpos.as<int64_t>() + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    const int64_t nrev = tot[0], L = tot[1];
+    DevBuf rid((size_t)std::max<int64_t>(nrev, 1) * sizeof(int32_t));
+    DevBuf rd2((size_t)std::max<int64_t>(nrev, 1) * sizeof(float));
+    DevBuf rows((size_t)std::max<int64_t>(L, 1) * sizeof(int32_t));
+    hipLaunchKernelGGL(k_scatter_flagged, dim3(g1b(N, 256)), dim3(256), 0, s, flag.as<int32_t>(),
+                       fpos.as<int64_t>(), N, rows.as<int32_t>());
     VJ_HIP(hipMemsetAsync(rpos.p, 0, rpos.bytes, s));
     hipLaunchKernelGGL(k_scatter_rev, dim3(g1b(M * R, 256)), dim3(256), 0, s, M, R,
                        fwd.as<int32_t>(), fwd_d2.as<float>(), roff.as<int64_t>(),
@@ -1385,15 +1397,22 @@ void insert_graph(Index &ix, int64_t n_old, int kc, hipStream_t s) {
     VJ_HIP(hipStreamSynchronize(s));
 
     // 4. connectivity repair from the (unchanged) entry, then the lengths of
-    //    every row that changed
-    repair_connectivity(ix, s, &rows_h);
-    if ((int64_t)rows_h.size() > L) {
-        rows.alloc(rows_h.size() * sizeof(int32_t));
-        VJ_HIP(hipMemcpyAsync(rows.p, rows_h.data(), rows_h.size() * sizeof(int32_t),
-                              hipMemcpyHostToDevice, s));
+    //    every row that changed (the listed rows and the repairs' sources)
+    std::vector<int32_t> touched;
+    repair_connectivity(ix, s, &touched);
+    int64_t nrows = L;
+    if (!touched.empty()) {
+        nrows = L + (int64_t)touched.size();
+        DevBuf grown((size_t)nrows * sizeof(int32_t));
+        if (L > 0)
+            VJ_HIP(hipMemcpyAsync(grown.p, rows.p, (size_t)L * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, s));
+        VJ_HIP(hipMemcpyAsync(grown.as<int32_t>() + L, touched.data(),
+                              touched.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        VJ_HIP(hipStreamSynchronize(s));  // touched is host memory
+        rows = std::move(grown);
     }
-    launch_edge_lengths_rows(vec, dp, adj, N, R, rows.as<int32_t>(), (int64_t)rows_h.size(),
-                             ix.elen.as<float>(), s);
+    launch_edge_lengths_rows(vec, dp, adj, N, R, rows.as<int32_t>(), nrows, ix.elen.as<float>(), s);
     VJ_HIP(hipGetLastError());
     VJ_HIP(hipStreamSynchronize(s));
 }

@@ -78,5 +78,9 @@ void sort_pairs_i32(const int32_t *keys_in, int32_t *keys_out, const int32_t *va
                     int32_t *vals_out, int64_t n, int end_bit, DevBuf &tmp, hipStream_t s);
 void order_by_depth(const int32_t *depth, int64_t nq, const int32_t *ids, int64_t n,
                     int32_t *qlist, int32_t *qpos, DevBuf &tmp, hipStream_t s);
+// out[i] = in[0] + ... + in[i - 1] for i = 0 .. n (n + 1 entries; out[n] is
+// the total); tmp is grown as needed
+void exclusive_scan_i32_i64(const int32_t *in, int64_t *out, int64_t n, DevBuf &tmp,
+                            hipStream_t s);
 
 }  // namespace vj

@@ -729,6 +729,23 @@ void sort_pairs_i32(const int32_t *keys_in, int32_t *keys_out, const int32_t *va
                                      (size_t)n, 0, end_bit, s));
 }
 
+__global__ void k_scan_tail(const int32_t *in, int64_t *out, int64_t n) {
+    out[n] = n > 0 ? out[n - 1] + in[n - 1] : 0;
+}
+
+void exclusive_scan_i32_i64(const int32_t *in, int64_t *out, int64_t n, DevBuf &tmp,
+                            hipStream_t s) {
+    if (n > 0) {
+        size_t bytes = 0;
+        VJ_HIP(rocprim::exclusive_scan(nullptr, bytes, in, out, (int64_t)0, (size_t)n,
+                                       rocprim::plus<int64_t>(), s));
+        tmp.reserve(bytes);
+        VJ_HIP(rocprim::exclusive_scan(tmp.p, bytes, in, out, (int64_t)0, (size_t)n,
+                                       rocprim::plus<int64_t>(), s));
+    }
+    hipLaunchKernelGGL(k_scan_tail, dim3(1), dim3(1), 0, s, in, out, n);
+}
+
 void order_by_depth(const int32_t *depth, int64_t nq, const int32_t *ids, int64_t n,
                     int32_t *qlist, int32_t *qpos, DevBuf &tmp, hipStream_t s) {
     if (n == 0) return;
