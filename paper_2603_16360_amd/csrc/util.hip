@@ -1,6 +1,8 @@
 // Small device helpers of the index and the result: padded copies, exact u8
 // and bf16 copies, edge lengths, id bookkeeping and the pair export.
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include <rocprim/rocprim.hpp>
 
@@ -727,6 +729,80 @@ void sort_pairs_i32(const int32_t *keys_in, int32_t *keys_out, const int32_t *va
     tmp.reserve(bytes);
     VJ_HIP(rocprim::radix_sort_pairs(tmp.p, bytes, keys_in, keys_out, vals_in, vals_out,
                                      (size_t)n, 0, end_bit, s));
+}
+
+namespace {
+struct CachedBlock {
+    void *p;
+    size_t n;
+};
+struct BlockCache {
+    std::mutex mu;
+    std::vector<CachedBlock> blocks[64];
+    size_t held[64] = {};
+};
+// never destroyed: no HIP call runs during static destruction
+BlockCache &block_cache() {
+    static BlockCache *c = new BlockCache;
+    return *c;
+}
+void drop_cached(BlockCache &c, int dev) {
+    for (const CachedBlock &b : c.blocks[dev]) (void)hipFree(b.p);
+    c.blocks[dev].clear();
+    c.held[dev] = 0;
+}
+}  // namespace
+
+void *dev_alloc(size_t n, int *dev) {
+    VJ_HIP(hipGetDevice(dev));
+    BlockCache &c = block_cache();
+    const int d = *dev;
+    if (n >= kBlockCacheMin && d >= 0 && d < 64) {
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto &v = c.blocks[d];
+        int best = -1;
+        for (int i = 0; i < (int)v.size(); ++i)
+            if (v[i].n >= n && v[i].n / 2 <= n && (best < 0 || v[i].n < v[best].n)) best = i;
+        if (best >= 0) {
+            void *p = v[best].p;
+            c.held[d] -= v[best].n;
+            v.erase(v.begin() + best);
+            return p;
+        }
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipErrorOutOfMemory && d >= 0 && d < 64) {
+        (void)hipGetLastError();
+        {
+            std::lock_guard<std::mutex> lk(c.mu);
+            drop_cached(c, d);
+        }
+        e = hipMalloc(&p, n);
+    }
+    VJ_HIP(e);
+    return p;
+}
+
+void dev_free(void *p, size_t n, int dev) {
+    // a freed buffer may still be read by work in flight on any stream, as
+    // with hipFree: wait for the device before the block can be reused
+    BlockCache &c = block_cache();
+    if (n >= kBlockCacheMin && dev >= 0 && dev < 64) {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && cur == dev && hipDeviceSynchronize() == hipSuccess) {
+            std::lock_guard<std::mutex> lk(c.mu);
+            c.blocks[dev].push_back({p, n});
+            c.held[dev] += n;
+            while (c.held[dev] > kBlockCacheMax && !c.blocks[dev].empty()) {
+                (void)hipFree(c.blocks[dev].front().p);
+                c.held[dev] -= c.blocks[dev].front().n;
+                c.blocks[dev].erase(c.blocks[dev].begin());
+            }
+            return;
+        }
+    }
+    (void)hipFree(p);
 }
 
 __global__ void k_scan_tail(const int32_t *in, int64_t *out, int64_t n) {

@@ -34,25 +34,39 @@ struct Error {
         if (!(cond)) throw ::vj::Error{status, msg};                                  \
     } while (0)
 
+// Device memory with reuse of large blocks: a block of kBlockCacheMin bytes
+// or more is not returned to the runtime when freed but kept per device (the
+// device is synchronised first, as hipFree would) and handed to a later
+// request of between half its size and its size; at most kBlockCacheMax
+// bytes are kept per device, and a failed hipMalloc empties the cache and
+// retries.  Large hipMalloc / hipFree pairs cost up to a second each when
+// a build or an insertion allocates gigabytes of temporaries again and again.
+constexpr size_t kBlockCacheMin = (size_t)16 << 20;
+constexpr size_t kBlockCacheMax = (size_t)32 << 30;
+void *dev_alloc(size_t n, int *dev);
+void dev_free(void *p, size_t n, int dev);
+
 // Device buffer that frees itself.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
     bool own = true;  // false: a view into another buffer (not freed here)
+    int dev = -1;     // device of the block
     DevBuf() = default;
     explicit DevBuf(size_t n) { alloc(n); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), own(o.own) {
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), own(o.own), dev(o.dev) {
         o.p = nullptr;
         o.bytes = 0;
         o.own = true;
+        o.dev = -1;
     }
     DevBuf &operator=(DevBuf &&o) noexcept {
         if (this != &o) {
             release();
-            p = o.p; bytes = o.bytes; own = o.own;
-            o.p = nullptr; o.bytes = 0; o.own = true;
+            p = o.p; bytes = o.bytes; own = o.own; dev = o.dev;
+            o.p = nullptr; o.bytes = 0; o.own = true; o.dev = -1;
         }
         return *this;
     }
@@ -67,16 +81,17 @@ struct DevBuf {
     void alloc(size_t n) {
         release();
         if (n == 0) n = 16;
-        VJ_HIP(hipMalloc(&p, n));
+        p = dev_alloc(n, &dev);
         bytes = n;
     }
     // grow (contents not kept)
     void reserve(size_t n) { if (n > bytes || !own) alloc(n); }
     void release() {
-        if (p && own) (void)hipFree(p);
+        if (p && own) dev_free(p, bytes, dev);
         p = nullptr;
         bytes = 0;
         own = true;
+        dev = -1;
     }
     template <typename T> T *as() const { return static_cast<T *>(p); }
 };
