@@ -538,6 +538,17 @@ vj_status vj_index_descend(vj_index *idx, const int32_t *query_ids, int64_t n, i
 const char *vj_last_error(void);
 
 /*
+ * Device memory kept by the library: a freed temporary of 16 MB or more is
+ * not returned to the runtime but kept for a later request of between half
+ * its size and its size (the device is synchronised first, as hipFree
+ * would), at most 32 GB per device; a failed allocation empties the device's
+ * cache and retries.  vj_trim_memory returns every kept block of the current
+ * device to the runtime.  bytes_freed (host, may be NULL): the bytes
+ * returned.
+ */
+vj_status vj_trim_memory(int64_t *bytes_freed);
+
+/*
  * Hardware-counter calibration (not part of the method): out[i] = the sum
  * of row ids[i] of rows, for i < n.  rows: [nrows][dp] fp32 on the device,
  * dp a positive multiple of 32; ids: [n] int32 (an id outside [0, nrows)

@@ -784,6 +784,17 @@ void *dev_alloc(size_t n, int *dev) {
     return p;
 }
 
+size_t trim_block_cache() {
+    int d = -1;
+    VJ_HIP(hipGetDevice(&d));
+    if (d < 0 || d >= 64) return 0;
+    BlockCache &c = block_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    const size_t n = c.held[d];
+    drop_cached(c, d);
+    return n;
+}
+
 void dev_free(void *p, size_t n, int dev) {
     // a freed buffer may still be read by work in flight on any stream, as
     // with hipFree: wait for the device before the block can be reused

@@ -1117,6 +1117,13 @@ void vj_default_join_params(vj_join_params *p) {
 
 const char *vj_last_error(void) { return vj::last_error(); }
 
+vj_status vj_trim_memory(int64_t *bytes_freed) {
+    API_BEGIN
+    const size_t n = vj::trim_block_cache();
+    if (bytes_freed) *bytes_freed = (int64_t)n;
+    API_END
+}
+
 vj_status vj_calib_gather(const float *rows, int64_t nrows, int32_t dp, const int32_t *ids,
                           int64_t n, float *out, void *stream) {
     API_BEGIN

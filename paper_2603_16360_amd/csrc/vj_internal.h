@@ -45,6 +45,8 @@ constexpr size_t kBlockCacheMin = (size_t)16 << 20;
 constexpr size_t kBlockCacheMax = (size_t)32 << 30;
 void *dev_alloc(size_t n, int *dev);
 void dev_free(void *p, size_t n, int dev);
+// return every kept block of the current device to the runtime; bytes freed
+size_t trim_block_cache();
 
 // Device buffer that frees itself.
 struct DevBuf {

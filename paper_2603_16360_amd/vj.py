@@ -112,6 +112,7 @@ _SIGS = {
     "vj_predictor_get_adam_state": (C.c_int, [_vp, _vp, _vp, C.POINTER(_i64), _vp]),
     "vj_index_attach_predictor": (C.c_int, [_vp, _vp, _f32, _vp]),
     "vj_last_error": (C.c_char_p, []),
+    "vj_trim_memory": (C.c_int, [C.POINTER(_i64)]),
     "vj_calib_gather": (C.c_int, [_vp, _i64, _i32, _vp, _i64, _vp, _vp]),
     "vj_index_build_layers": (C.c_int, [_vp, _i32, C.c_uint64, _i32, _vp]),
     "vj_index_layers_info": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -579,6 +580,14 @@ def vj_index_attach_predictor(index: Index, pred: Predictor | None, recall_targe
 
 def vj_last_error() -> str:
     return _lib.vj_last_error().decode()
+
+
+def vj_trim_memory() -> int:
+    """Return the library's kept device blocks of the current device to the
+    runtime (see include/vj.h); the bytes returned."""
+    n = _i64(0)
+    _check(_lib.vj_trim_memory(C.byref(n)))
+    return n.value
 
 
 def vj_index_build_layers(index: Index, R: int = 16, seed: int = 1, max_levels: int = 8):

@@ -125,3 +125,16 @@ def test_register_row_widths_and_splits(d, metric, precision):
     eps = float(np.quantile(D, 0.002))
     G, O = _check(Q, X, eps, metric, precision)
     assert len(O) > 500
+
+
+def test_kept_blocks_are_returned_by_trim():
+    # the all-pairs result (6M pairs, 72 MB) and the call's candidate arrays
+    # are kept for reuse when freed; trimming returns them, a second trim
+    # finds nothing
+    r = np.random.default_rng(5)
+    X = r.standard_normal((4000, 32)).astype(np.float32)
+    res = vj.vj_bruteforce_join(torch.from_numpy(X[:1500]).cuda(), torch.from_numpy(X).cuda(), 1e6)
+    assert res.count() == 1500 * 4000
+    del res
+    assert vj.vj_trim_memory() >= 72 << 20
+    assert vj.vj_trim_memory() == 0
