@@ -327,8 +327,9 @@ template <int NSPLIT, int KP>
 __global__ void __launch_bounds__(256, 2)
 k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_t M,
           const uint16_t *Bh, const uint16_t *Bl, const float *bn2, const int32_t *bid_of,
-          int32_t T, const int32_t *start_tile, int32_t j0, int32_t tiles_per_split,
-          int32_t split_base, const float *tau_in, int K, float *bkey,
+          const int64_t *__restrict__ run_off, const int32_t *__restrict__ run_tile,
+          const int32_t *__restrict__ run_pos, const int32_t *__restrict__ vtot,
+          int32_t split_base, const float *tau_in, const int32_t *cnt_in, int K, float *bkey,
           int32_t *bid, int32_t rb, int32_t blk0) {
     using S = ring::Shape<NSPLIT, KP>;
     constexpr int RT = S::RT, CT = S::CT, KS = S::KS, BN = S::BN, CPR = S::CPR, SPR = S::SPR;
@@ -343,19 +344,39 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
     const int32_t blk = blk0 + (int32_t)blockIdx.x;  // row block (launches may be chunked)
     const int32_t prow0 = blk * S::ROWS + w * RT * 16;  // wave's first row (order)
     const int64_t boff = (int64_t)(split_base + blockIdx.y) * M;  // this split's buffer rows
-    // this split's sweep positions [jb, je); position j is tile (t0 + j) % T
-    const int32_t jb = j0 + (int32_t)blockIdx.y * tiles_per_split;
-    const int32_t je = min(T, jb + tiles_per_split);
-    const int32_t t0 = start_tile[blk];
+    // the block's tiles are runs [run_off[blk], run_off[blk + 1]): run k
+    // covers positions [run_pos[k], next run's start or vtot[blk]) from tile
+    // run_tile[k] on; split y of gridDim.y sweeps positions [jb, je)
+    const int64_t k0 = run_off[blk], k1 = run_off[blk + 1];
+    const int32_t V = vtot[blk];
+    const int32_t tps = (V + (int32_t)gridDim.y - 1) / (int32_t)gridDim.y;
+    const int32_t jb = min(V, (int32_t)blockIdx.y * tps), je = min(V, jb + tps);
+    const int ntile = je - jb;
+    // the run holding position jb (the last one starting at or before it)
+    int64_t rk = k0;
+    if (ntile > 0) {
+        int64_t lo = k0, hi = k1 - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (run_pos[mid] <= jb) lo = mid; else hi = mid - 1;
+        }
+        rk = lo;
+    }
+    int32_t rdelta = ntile > 0 ? run_tile[rk] - run_pos[rk] : 0;  // tile - position in run rk
+    int32_t rend = ntile > 0 ? (rk + 1 < k1 ? run_pos[rk + 1] : V) : 0;
+    int32_t pnext = jb;  // the next position issued (positions are issued in order)
+    const int32_t first_col = ntile > 0 ? (jb + rdelta) * BN : 0;
     // a row is cut back to K once it holds more than merge_at entries: the
     // threshold then tightens early, which keeps the appends few
     const int merge_at = min(K + 96, kKnnCap - BN);
-    // entries held by the wave's row r: lane r of cnt
+    // entries held by the wave's row r: lane r of cnt (a later pass goes on
+    // with the lists an earlier one left: cnt_in entries, threshold tau_in)
     int cnt = 0;
     if (lane < RT * 16) {
         const int32_t node = prow0 + lane < M ? rowperm[prow0 + lane] : -1;
         s_node[w][lane] = node;
         s_tau[w][lane] = node < 0 ? -INFINITY : tau_in ? tau_in[prow0 + lane] : FLT_MAX;
+        if (cnt_in && node >= 0) cnt = cnt_in[prow0 + lane];
     }
 
     // the wave's rows: fragment (rt, ks) holds row rt*16 + (lane & 15),
@@ -400,7 +421,16 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
         ring::lds_dma4(bn2 + c0, soff4, sbase + TERMS * PART + w * 256);
         ring::lds_dma4(bid_of + c0, soff4, sbase + TERMS * PART + 1024 + w * 256);
     };
-    auto tile_col = [&](int32_t j) { return (int32_t)((int64_t)((t0 + j) % T) * BN); };
+    // column of the next position (in order; past the split's last one the
+    // first tile's column, loaded into a stage no tile reads)
+    auto next_col = [&]() -> int32_t {
+        while (pnext >= rend) {
+            ++rk;
+            rdelta = run_tile[rk] - run_pos[rk];
+            rend = rk + 1 < k1 ? run_pos[rk + 1] : V;
+        }
+        return (pnext++ + rdelta) * BN;
+    };
 
     float tau[RT][4];
     auto load_tau = [&]() {
@@ -417,13 +447,12 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
         if (lane == 0) s_tau[w][r] = fminf(s_tau[w][r], kth);
     };
 
-    const int ntile = je > jb ? je - jb : 0;
     // prologue: tiles 0 .. NB-2 in flight (every wave issues LPT loads per
     // tile slot, a slot past the last tile re-loads tile 0's stage 0 data
     // into the last stage, which no tile reads before it is re-issued)
 #pragma unroll
     for (int p = 0; p < NB - 1; ++p)
-        issue(tile_col(jb + (p < ntile ? p : 0)), p < ntile ? p : NB - 1);
+        issue(p < ntile ? next_col() : first_col, p < ntile ? p : NB - 1);
     for (int it = 0; it < ntile; ++it) {
         const int st = it % NB;
         // tile it has landed when at most (NB - 2) tiles' loads are in
@@ -434,7 +463,7 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
         if (it == 0) load_tau();
         {
             const int nx = it + NB - 1;  // into the stage read at it - 1
-            issue(tile_col(jb + (nx < ntile ? nx : 0)), nx < ntile ? nx % NB : (it + NB - 1) % NB);
+            issue(nx < ntile ? next_col() : first_col, nx < ntile ? nx % NB : (it + NB - 1) % NB);
         }
         const char *sp = sring + st * STAGE;
         floatx4 acc[RT][CT];
@@ -596,16 +625,23 @@ k_knn_merge_splits(float *bkey, int32_t *bid, int64_t M, int S, int K, int G, in
 
 // starting thresholds of a later pass: the K-th key of each row's list 0,
 // i.e. the largest of its K kept entries (kept unordered or sorted),
-// FLT_MAX while it holds fewer than K; by processing position
-// (rowperm[pos] is row rb + i of list 0)
+// FLT_MAX while it holds fewer than K, and the number of entries held (the
+// first cnt slots; the rest hold id -1); by processing position (rowperm[pos]
+// is row rb + i of list 0)
 __global__ void k_list_tau(const float *bkey, const int32_t *bid, const int32_t *rowperm,
-                           int64_t M, int64_t rb, int K, float *tau) {
+                           int64_t M, int64_t rb, int K, float *tau, int32_t *cnt) {
     const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (pos >= M) return;
     const int64_t o = ((int64_t)rowperm[pos] - rb) * kKnnCap;
     float t = -FLT_MAX;
-    for (int e = 0; e < K; ++e) t = bid[o + e] >= 0 ? fmaxf(t, bkey[o + e]) : FLT_MAX;
+    int c = 0;
+    for (int e = 0; e < K; ++e) {
+        const bool ok = bid[o + e] >= 0;
+        t = ok ? fmaxf(t, bkey[o + e]) : FLT_MAX;
+        c += ok;
+    }
     tau[pos] = t;
+    cnt[pos] = c;
 }
 
 // an insertion's changing rows: every old node that receives an offer and
@@ -889,54 +925,175 @@ void launch_gather(int dp, const float *vec, int R, const int32_t *adj, const in
     }
 }
 
-// ---- cluster order of the kNN sweep
-// nearest of P pivot rows (fp32 L2; the smaller pivot index on ties) for
-// every node; 32 pivot rows at a time in LDS (dp <= 256)
-__global__ void __launch_bounds__(256)
-k_assign_pivot(const float *vec, int dp, int64_t N, const float *piv, int P, int32_t *assign) {
-    __shared__ __attribute__((aligned(16))) float sp[32 * 256];
-    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const float *x = vec + (v < N ? v : 0) * dp;
-    float best = INFINITY;
-    int bi = 0;
-    for (int p0 = 0; p0 < P; p0 += 32) {
-        const int np = min(32, P - p0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < np * dp; e += 256) sp[e] = piv[(int64_t)p0 * dp + e];
-        __syncthreads();
-        float acc[32];
+// ---- group order of the kNN sweep
+// The nodes are grouped by their nearest of P centres (P <= kMaxGroups;
+// centres: every (N / P)-th node, moved to its group's mean kLloyd times),
+// rows and columns are sorted by group, and each group starts a tile.  The
+// sweep of a row block runs in two passes: its own groups first, whose
+// lists give every row a threshold tau (its K-th key), then only the groups
+// that a row of the block could still take a member from.  Group g has
+// centre m_g and radius rad_g (no member farther from m_g); by the triangle
+// inequality every member c has |r - c| >= |r - m_g| - rad_g, so when that
+// bound, less the tile key's error bound, puts every member's key above tau
+// for every row of the block, no member of g would enter a list: skipping g
+// leaves the lists exactly as the full sweep leaves them.
+constexpr int64_t kGroupRows = 256;  // nodes per group (on average, at most kMaxGroups)
+constexpr int kMaxGroups = 4096;
+constexpr int kLloyd = 1;            // mean steps of the centres before the last labelling
+
+// Distances of rows to centres, eight lanes per row: lane p8 of a row's
+// group holds float4 slices p8, p8 + 8, ... (NCHL = dp / 32 of them) of two
+// rows in registers; a chunk of 32 centres is staged in LDS.  Each lane
+// sums its slices for all 32 centres, then three exchange steps (xor 4, 2,
+// 1) leave lane p8 with the totals of centres 4 p8 .. 4 p8 + 3.
+template <int NCHL>
+struct RowPair {
+    float4 a[NCHL], b[NCHL];
+    __device__ void load(const float *xa, const float *xb, int p8) {
 #pragma unroll
-        for (int k = 0; k < 32; ++k) acc[k] = 0.f;
-        for (int c = 0; c < dp; c += 4) {
-            const float4 xv = *reinterpret_cast<const float4 *>(x + c);
-#pragma unroll
-            for (int k = 0; k < 32; ++k) {
-                if (k < np) {
-                    const float4 pv = *reinterpret_cast<const float4 *>(sp + k * dp + c);
-                    float t = xv.x - pv.x; acc[k] = fmaf(t, t, acc[k]);
-                    t = xv.y - pv.y; acc[k] = fmaf(t, t, acc[k]);
-                    t = xv.z - pv.z; acc[k] = fmaf(t, t, acc[k]);
-                    t = xv.w - pv.w; acc[k] = fmaf(t, t, acc[k]);
-                }
-            }
+        for (int j = 0; j < NCHL; ++j) {
+            a[j] = reinterpret_cast<const float4 *>(xa)[j * 8 + p8];
+            b[j] = reinterpret_cast<const float4 *>(xb)[j * 8 + p8];
         }
+    }
+    // totals of centres 4 p8 + i (i < 4) for both rows
+    __device__ void dist(const float *sp, int p8, float (&da)[4], float (&db)[4]) const {
+        constexpr int dp = NCHL * 32;
+        float pa[32], pb[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) { pa[k] = 0.f; pb[k] = 0.f; }
 #pragma unroll
         for (int k = 0; k < 32; ++k)
-            if (k < np && acc[k] < best) { best = acc[k]; bi = p0 + k; }
+#pragma unroll
+            for (int j = 0; j < NCHL; ++j) {
+                const float4 c = reinterpret_cast<const float4 *>(sp + k * dp)[j * 8 + p8];
+                float t = a[j].x - c.x; pa[k] = fmaf(t, t, pa[k]);
+                t = a[j].y - c.y; pa[k] = fmaf(t, t, pa[k]);
+                t = a[j].z - c.z; pa[k] = fmaf(t, t, pa[k]);
+                t = a[j].w - c.w; pa[k] = fmaf(t, t, pa[k]);
+                t = b[j].x - c.x; pb[k] = fmaf(t, t, pb[k]);
+                t = b[j].y - c.y; pb[k] = fmaf(t, t, pb[k]);
+                t = b[j].z - c.z; pb[k] = fmaf(t, t, pb[k]);
+                t = b[j].w - c.w; pb[k] = fmaf(t, t, pb[k]);
+            }
+        reduce_scatter(pa, p8);
+        reduce_scatter(pb, p8);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { da[i] = pa[i]; db[i] = pb[i]; }
     }
-    if (v < N) assign[v] = bi;
+    // step with mask m keeps the half of v[0 .. 2h) selected by lane bit m
+    // and adds the partner's copy of it
+    __device__ static void reduce_scatter(float (&v)[32], int p8) {
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int m = 4 >> s, h = 16 >> s;
+            const bool up = (p8 & m) != 0;
+#pragma unroll
+            for (int i = 0; i < h; ++i) {
+                const float send = up ? v[i] : v[i + h];
+                const float keep = up ? v[i + h] : v[i];
+                v[i] = keep + __shfl_xor(send, m);
+            }
+        }
+    }
+};
+
+// stage centres p0 .. p0 + np - 1 (np <= 32) into sp; past np, +inf rows
+__device__ __forceinline__ void stage_centres(const float *cen, int p0, int np, int dp, float *sp) {
+    for (int e = threadIdx.x; e < 32 * dp; e += blockDim.x)
+        sp[e] = e < np * dp ? cen[(int64_t)p0 * dp + e] : INFINITY;
 }
 
-// sweep-order copy of the tile rows: row j of the copy is node perm[j]
-// (j < N), a zero row with |x|^2 = +inf and id -1 past N (j < Np)
+// nearest of P centres (fp32 L2; the smaller index on ties) for every node,
+// 64 nodes per workgroup (dp = 32 NCHL <= 256).  With rad, the group's
+// radius grows to the node's distance (non-negative floats order as their
+// bits).
+template <int NCHL>
+__global__ void __launch_bounds__(256, 3)
+k_assign_pivot(const float *vec, int64_t N, const float *piv, int P, int32_t *assign, float *rad) {
+    constexpr int dp = NCHL * 32;
+    __shared__ __attribute__((aligned(16))) float sp[32 * dp];
+    const int p8 = threadIdx.x & 7, grp = threadIdx.x >> 3;
+    const int64_t va = (int64_t)blockIdx.x * 64 + grp, vb = va + 32;
+    RowPair<NCHL> rp;
+    rp.load(vec + (va < N ? va : 0) * dp, vec + (vb < N ? vb : 0) * dp, p8);
+    float ba = INFINITY, bb = INFINITY;
+    int ia = 0, ib = 0;
+    for (int p0 = 0; p0 < P; p0 += 32) {
+        __syncthreads();
+        stage_centres(piv, p0, min(32, P - p0), dp, sp);
+        __syncthreads();
+        float da[4], db[4];
+        rp.dist(sp, p8, da, db);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int g = p0 + 4 * p8 + i;  // staged +inf rows never win
+            if (da[i] < ba) { ba = da[i]; ia = g; }
+            if (db[i] < bb) { bb = db[i]; ib = g; }
+        }
+    }
+    // the smallest (d2, index) over the row's eight lanes
+#pragma unroll
+    for (int m = 4; m > 0; m >>= 1) {
+        const float oa = __shfl_xor(ba, m), ob = __shfl_xor(bb, m);
+        const int ja = __shfl_xor(ia, m), jb = __shfl_xor(ib, m);
+        if (oa < ba || (oa == ba && ja < ia)) { ba = oa; ia = ja; }
+        if (ob < bb || (ob == bb && jb < ib)) { bb = ob; ib = jb; }
+    }
+    if (p8 == 0) {
+        if (va < N) {
+            assign[va] = ia;
+            if (rad) atomicMax(reinterpret_cast<unsigned int *>(rad) + ia, __float_as_uint(sqrtf(ba)));
+        }
+        if (vb < N) {
+            assign[vb] = ib;
+            if (rad) atomicMax(reinterpret_cast<unsigned int *>(rad) + ib, __float_as_uint(sqrtf(bb)));
+        }
+    }
+}
+
+// centre of each non-empty group: the mean of its members (sweep positions
+// [gstart, gend) of perm); an empty group keeps its centre.  Lanes split
+// the float4 columns and the members; the parts meet in LDS.
+__global__ void __launch_bounds__(256)
+k_center_means(const float *vec, int dp, const int32_t *perm, const int32_t *gstart,
+               const int32_t *gend, float *cen) {
+    __shared__ float4 part[256];
+    const int g = blockIdx.x;
+    const int j0 = gstart[g], j1 = gend[g];
+    if (j0 < 0 || j1 <= j0) return;
+    const int nc4 = dp / 4, lanes = 256 / nc4;
+    const int c = threadIdx.x % nc4, m = threadIdx.x / nc4;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (m < lanes)
+        for (int j = j0 + m; j < j1; j += lanes) {
+            const float4 x = reinterpret_cast<const float4 *>(vec + (int64_t)perm[j] * dp)[c];
+            acc.x += x.x; acc.y += x.y; acc.z += x.z; acc.w += x.w;
+        }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < nc4) {
+        float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int k = 0; k < lanes; ++k) {
+            const float4 y = part[k * nc4 + threadIdx.x];
+            t.x += y.x; t.y += y.y; t.z += y.z; t.w += y.w;
+        }
+        const float inv = 1.f / (float)(j1 - j0);
+        reinterpret_cast<float4 *>(cen + (int64_t)g * dp)[threadIdx.x] =
+            make_float4(t.x * inv, t.y * inv, t.z * inv, t.w * inv);
+    }
+}
+
+// sweep-order copy of the tile rows: slot j of the copy is node slot[j], a
+// zero row with |x|^2 = +inf and id -1 where slot[j] < 0 (group padding)
 __global__ void k_sweep_copy(const uint16_t *hi, const uint16_t *lo, const float *n2, int Kp,
-                             const int32_t *perm, int64_t N, int64_t Np, uint16_t *bh,
-                             uint16_t *bl, float *bn2, int32_t *bid_of) {
+                             const int32_t *slot, int64_t Np, uint16_t *bh, uint16_t *bl,
+                             float *bn2, int32_t *bid_of) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int cpr = Kp / 8;
     if (e >= Np * cpr) return;
     const int64_t j = e / cpr, c = e - j * cpr;
-    const int32_t v = j < N ? perm[j] : -1;
+    const int32_t v = slot[j];
     const uint4 z = make_uint4(0, 0, 0, 0);
     reinterpret_cast<uint4 *>(bh + j * Kp)[c] = v >= 0 ? reinterpret_cast<const uint4 *>(hi + (int64_t)v * Kp)[c] : z;
     if (bl) reinterpret_cast<uint4 *>(bl + j * Kp)[c] = v >= 0 ? reinterpret_cast<const uint4 *>(lo + (int64_t)v * Kp)[c] : z;
@@ -946,7 +1103,7 @@ __global__ void k_sweep_copy(const uint16_t *hi, const uint16_t *lo, const float
     }
 }
 
-// first sweep position of each pivot group (keys: the sorted pivot ids)
+// first and last sweep position of each group (keys: the sorted group ids)
 __global__ void k_group_start(const int32_t *keys, int64_t N, int32_t *gstart, int32_t *gend) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
@@ -954,7 +1111,17 @@ __global__ void k_group_start(const int32_t *keys, int64_t N, int32_t *gstart, i
     if (j == N - 1 || keys[j] != keys[j + 1]) gend[keys[j]] = (int32_t)(j + 1);
 }
 
-// keys and values of the call's rows [rb, rb + M): their pivot, their id
+// the copy slot of sorted position j: its group's first tile, plus its rank
+// in the group
+__global__ void k_slot_map(const int32_t *keys, const int32_t *perm, int64_t N,
+                           const int32_t *gstart, const int32_t *gt_s, int bn, int32_t *slot) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const int32_t g = keys[j];
+    slot[(int64_t)gt_s[g] * bn + (j - gstart[g])] = perm[j];
+}
+
+// keys and values of the call's rows [rb, rb + M): their group, their id
 __global__ void k_row_keys(const int32_t *assign, int64_t rb, int64_t M, int32_t *keys,
                            int32_t *vals) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -963,27 +1130,176 @@ __global__ void k_row_keys(const int32_t *assign, int64_t rb, int64_t M, int32_t
     vals[i] = (int32_t)(rb + i);
 }
 
-// start tile of row block b: the tile holding the start of the pivot group
-// of the block's first row (rkeys: the rows' sorted pivot ids); span: the
-// tiles from there to the end of the group of the block's last row (every
-// row's own group holds at least the row itself)
-__global__ void k_start_tiles(const int32_t *rkeys, int64_t M, int rows, const int32_t *gstart,
-                              const int32_t *gend, int bn, int64_t nb, int32_t *start_tile,
-                              int32_t *span) {
+// first pass: one run per row block, the tiles of the groups from its first
+// row's to its last row's (rkeys: the rows' sorted group ids)
+__global__ void k_pass1_runs(const int32_t *rkeys, int64_t M, int rows, const int32_t *gt_s,
+                             const int32_t *gt_e, int64_t nb, int64_t *run_off,
+                             int32_t *run_tile, int32_t *run_pos, int32_t *vtot) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
-    const int32_t g = gstart[rkeys[b * rows]];
-    const int32_t t0 = g >= 0 ? g / bn : 0;
-    const int32_t e = gend[rkeys[min(M, (b + 1) * rows) - 1]];
-    start_tile[b] = t0;
-    span[b] = e > 0 ? (e + bn - 1) / bn - t0 : 0;
+    const int32_t t0 = gt_s[rkeys[b * rows]];
+    const int32_t t1 = gt_e[rkeys[min(M, (b + 1) * rows) - 1]];
+    run_off[b] = b;
+    if (b == nb - 1) run_off[nb] = nb;
+    run_tile[b] = t0;
+    run_pos[b] = 0;
+    vtot[b] = t1 - t0;
+}
+
+// the groups the second pass of row block b visits (bit g of words
+// need[b][0 .. W)): not one of the block's own groups, not empty, and not
+// ruled out for every row of the block by the bound above.  Row r takes a
+// key <= tau_r only from a member c with |r - c|^2 <= tau_r + |r|^2 + E_r,
+// E_r covering the tile key's error (ea: dot products, relative to
+// |r| |c|; eb: norms and the final adds) and the fp32 norm of r; the
+// distances here carry a relative margin of 1e-4 (fp32 sums of at most 256
+// squares are far closer).  Rows as in k_assign_pivot, 64 per pass over the
+// centres (rows / 64 passes).
+template <int NCHL>
+__global__ void __launch_bounds__(256, 3)
+k_visit_groups(const float *vec, const int32_t *rowperm, int64_t M, int rows, const int32_t *rkeys,
+               const float *cen, const float *rad, const int32_t *gt_s, const int32_t *gt_e,
+               int P, const float *tau, const float *n2, float ea, float eb, float maxn,
+               uint32_t *need, int32_t *nneed) {
+    constexpr int dp = NCHL * 32;
+    __shared__ __attribute__((aligned(16))) float sp[32 * dp];
+    __shared__ float srad[32];
+    __shared__ uint32_t sneed[kMaxGroups / 32];
+    __shared__ int scount[4];
+    const int64_t b = blockIdx.x;
+    const int i = threadIdx.x, p8 = i & 7, grp = i >> 3;
+    const int W = (P + 31) / 32;
+    for (int k = i; k < W; k += blockDim.x) sneed[k] = 0u;
+    // a row's bound: -1 past M (takes nothing), +inf while it holds < K
+    auto bound = [&](int64_t pos, int32_t node) {
+        const float t = tau[pos], nr2 = n2[node], nr = sqrtf(nr2);
+        const float E = 2.f * (ea * nr * maxn + eb * (maxn * maxn + nr * maxn + nr2));
+        return t >= FLT_MAX ? INFINITY : (t + nr2 + E) * (1.f + 1e-4f) + FLT_MIN;
+    };
+    const int64_t rend = min(M, (b + 1) * (int64_t)rows);
+    for (int64_t r0 = b * rows; r0 < rend; r0 += 64) {
+        const int64_t pa = r0 + grp, pb = pa + 32;
+        const int32_t na = pa < rend ? rowperm[pa] : 0, nb = pb < rend ? rowperm[pb] : 0;
+        const float ha = pa < rend ? bound(pa, na) : -1.f, hb = pb < rend ? bound(pb, nb) : -1.f;
+        RowPair<NCHL> rp;
+        rp.load(vec + (int64_t)na * dp, vec + (int64_t)nb * dp, p8);
+        for (int p0 = 0; p0 < P; p0 += 32) {
+            const int np = min(32, P - p0);
+            __syncthreads();
+            stage_centres(cen, p0, np, dp, sp);
+            if (i < 32) srad[i] = i < np ? rad[p0 + i] : 0.f;
+            __syncthreads();
+            float da[4], db[4];
+            rp.dist(sp, p8, da, db);
+            uint32_t m = 0u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = 4 * p8 + q;
+                const float rk = srad[k] * (1.f + 1e-4f);
+                const float la = sqrtf(da[q]) * (1.f - 1e-4f) - rk;
+                const float lb = sqrtf(db[q]) * (1.f - 1e-4f) - rk;
+                const bool fa = ha < 0.f || (la > 0.f && la * la > ha);
+                const bool fb = hb < 0.f || (lb > 0.f && lb * lb > hb);
+                if (k < np && (!fa || !fb)) m |= 1u << k;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) m |= __shfl_xor(m, off);
+            if ((i & 63) == 0 && m) atomicOr(&sneed[p0 / 32], m);
+        }
+    }
+    __syncthreads();
+    const int32_t gf = rkeys[b * rows], gl = rkeys[rend - 1];
+    int cnt = 0;
+    for (int k = i; k < W; k += blockDim.x) {
+        uint32_t word = sneed[k];
+        for (int bit = 0; bit < 32; ++bit) {
+            const int g = k * 32 + bit;
+            if (g >= P || (g >= gf && g <= gl) || gt_e[g] == gt_s[g]) word &= ~(1u << bit);
+        }
+        need[b * W + k] = word;
+        cnt += __popc(word);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((i & 63) == 0) scount[i >> 6] = cnt;
+    __syncthreads();
+    if (i == 0) nneed[b] = scount[0] + scount[1] + scount[2] + scount[3];
+}
+
+// the two kernels above for dp = 32 NCHL (dp <= 256, a multiple of 32)
+#define VJ_NCHL_SWITCH(dp, CALL)                                                        \
+    switch ((dp) / 32) {                                                                \
+    case 1: CALL(1); break;                                                             \
+    case 2: CALL(2); break;                                                             \
+    case 3: CALL(3); break;                                                             \
+    case 4: CALL(4); break;                                                             \
+    case 6: CALL(6); break;                                                             \
+    case 8: CALL(8); break;                                                             \
+    default: VJ_CHECK(false, VJ_ERR_UNSUPPORTED, "row width of the group order");     \
+    }
+void assign_groups(const float *vec, int dp, int64_t n, const float *cen, int P, int32_t *assign,
+                   float *rad, hipStream_t s) {
+    VJ_CHECK(dp % 32 == 0 && dp <= 256, VJ_ERR_UNSUPPORTED, "row width of the group order");
+#define VJ_CALL(c)                                                                              \
+    hipLaunchKernelGGL(k_assign_pivot<c>, dim3(g1b(n, 64)), dim3(256), 0, s, vec, n, cen, P, \
+                       assign, rad)
+    VJ_NCHL_SWITCH(dp, VJ_CALL)
+#undef VJ_CALL
+}
+void visit_groups(const float *vec, int dp, const int32_t *rowperm, int64_t M, int rows,
+                  const int32_t *rkeys, const float *cen, const float *rad, const int32_t *gt_s,
+                  const int32_t *gt_e, int P, const float *tau, const float *n2, float ea,
+                  float eb, float maxn, uint32_t *need, int32_t *nneed, hipStream_t s) {
+    const int64_t nb = (M + rows - 1) / rows;
+#define VJ_CALL(c)                                                                              \
+    hipLaunchKernelGGL(k_visit_groups<c>, dim3((unsigned)nb), dim3(256), 0, s, vec, rowperm, M, \
+                       rows, rkeys, cen, rad, gt_s, gt_e, P, tau, n2, ea, eb, maxn, need, nneed)
+    VJ_NCHL_SWITCH(dp, VJ_CALL)
+#undef VJ_CALL
+}
+#undef VJ_NCHL_SWITCH
+
+// runs of the second pass: one per visited group of row block b, in group
+// order, at run_off[b] on; positions counted from 0; vtot[b] the total.
+// 128 threads, thread k for word k (W <= 128).
+__global__ void __launch_bounds__(128)
+k_visit_runs(const uint32_t *need, int W, const int32_t *gt_s, const int32_t *gt_e,
+             const int64_t *run_off, int32_t *run_tile, int32_t *run_pos, int32_t *vtot) {
+    __shared__ int s_n[2], s_l[2];
+    const int64_t b = blockIdx.x;
+    const int k = threadIdx.x, lane = k & 63;
+    const uint32_t word = k < W ? need[b * W + k] : 0u;
+    int n = __popc(word), len = 0;
+    for (uint32_t m = word; m; m &= m - 1) {
+        const int g = k * 32 + __builtin_ctz(m);
+        len += gt_e[g] - gt_s[g];
+    }
+    // inclusive scans within the wave, then the first wave's totals
+    int ni = n, li = len;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int a = __shfl_up(ni, off), c = __shfl_up(li, off);
+        if (lane >= off) { ni += a; li += c; }
+    }
+    if (lane == 63) { s_n[k >> 6] = ni; s_l[k >> 6] = li; }
+    __syncthreads();
+    const int nb0 = k >= 64 ? s_n[0] : 0, lb0 = k >= 64 ? s_l[0] : 0;
+    int64_t at = run_off[b] + nb0 + ni - n;
+    int32_t p = lb0 + li - len;
+    for (uint32_t m = word; m; m &= m - 1) {
+        const int g = k * 32 + __builtin_ctz(m);
+        run_tile[at] = gt_s[g];
+        run_pos[at] = p;
+        p += gt_e[g] - gt_s[g];
+        ++at;
+    }
+    if (k == 127) vtot[b] = lb0 + li;
 }
 
 // the register-row kNN sweep for one (NSPLIT, Kp); false if that shape has
-// no instantiation.  Rows and columns are ordered by their nearest of up to
-// 1,024 pivot nodes (every (N / P)-th node), and each row block starts its
-// sweep at its own group.  Column splits keep >= 1,024 workgroups when M is
-// small (an insertion batch); their lists are merged into split 0.
+// no instantiation.  Rows and columns are in group order (above); a pass
+// over runs of tiles is split over columns (gridDim.y) when there are few
+// row blocks (an insertion batch), the splits' lists merged afterwards.
 template <int NSPLIT, int KP>
 bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, int64_t N, int K,
                       int64_t rb, int64_t M, DevBuf &bkey, DevBuf &bidb, hipStream_t s) {
@@ -993,82 +1309,119 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
     } else {
         constexpr int BN = S::BN;
         if (dp > 256) return false;
-        const int64_t T = (N + BN - 1) / BN, Np = T * BN;
-        // 1. the nearest pivot of every node: all nodes after a build's
-        //    choice of pivots; an insertion (rows [rb, N) appended to a graph
-        //    whose nodes [0, rb) are labelled) labels only its new nodes
+        DevBuf skeys((size_t)N * sizeof(int32_t)), iota((size_t)N * sizeof(int32_t)),
+            perm((size_t)N * sizeof(int32_t)), tmp;
+        int P = ix.piv_n;
+        int key_bits = 1;
+        DevBuf gstart, gend;
+        // nodes sorted by group (skeys, perm), each group's sweep positions
+        auto group_sort = [&]() {
+            iota_i32(iota.as<int32_t>(), N, s);
+            sort_pairs_i32(ix.piv_of.as<int32_t>(), skeys.as<int32_t>(), iota.as<int32_t>(),
+                           perm.as<int32_t>(), N, key_bits, tmp, s);
+            fill_i32(gstart.as<int32_t>(), P, -1, s);
+            fill_i32(gend.as<int32_t>(), P, 0, s);
+            hipLaunchKernelGGL(k_group_start, dim3(g1b(N, 256)), dim3(256), 0, s,
+                               skeys.as<int32_t>(), N, gstart.as<int32_t>(), gend.as<int32_t>());
+        };
+        // 1. groups: a build chooses the centres and labels every node; an
+        //    insertion (rows [rb, N) appended to a graph whose nodes [0, rb)
+        //    are labelled) labels its new nodes, the radii grow with them
         if (ix.piv_n == 0 || rb == 0 || ix.piv_cnt != rb) {
-            const int P = (int)std::min<int64_t>(1024, std::max<int64_t>(1, N / 512));
+            P = (int)std::min<int64_t>(kMaxGroups, std::max<int64_t>(1, N / kGroupRows));
+            while ((1 << key_bits) < P) ++key_bits;
+            gstart.alloc((size_t)P * sizeof(int32_t));
+            gend.alloc((size_t)P * sizeof(int32_t));
             std::vector<int32_t> ph((size_t)P);
             for (int k = 0; k < P; ++k) ph[(size_t)k] = (int32_t)((int64_t)k * (N / P));
             DevBuf pids((size_t)P * sizeof(int32_t));
             ix.piv_rows.alloc((size_t)P * dp * sizeof(float));
             ix.piv_of.alloc((size_t)N * sizeof(int32_t));
+            ix.piv_rad.alloc((size_t)P * sizeof(float));
             VJ_HIP(hipMemcpyAsync(pids.p, ph.data(), (size_t)P * sizeof(int32_t),
                                   hipMemcpyHostToDevice, s));
             gather_rows_f32(vec, dp, pids.as<int32_t>(), P, ix.piv_rows.as<float>(), s);
-            hipLaunchKernelGGL(k_assign_pivot, dim3(g1b(N, 256)), dim3(256), 0, s, vec, dp, N,
-                               ix.piv_rows.as<float>(), P, ix.piv_of.as<int32_t>());
+            for (int l = 0; l < kLloyd; ++l) {
+                assign_groups(vec, dp, N, ix.piv_rows.as<float>(), P, ix.piv_of.as<int32_t>(),
+                              nullptr, s);
+                group_sort();
+                hipLaunchKernelGGL(k_center_means, dim3(P), dim3(256), 0, s, vec, dp,
+                                   perm.as<int32_t>(), gstart.as<int32_t>(), gend.as<int32_t>(),
+                                   ix.piv_rows.as<float>());
+            }
+            VJ_HIP(hipMemsetAsync(ix.piv_rad.p, 0, ix.piv_rad.bytes, s));
+            assign_groups(vec, dp, N, ix.piv_rows.as<float>(), P, ix.piv_of.as<int32_t>(),
+                          ix.piv_rad.as<float>(), s);
             VJ_HIP(hipStreamSynchronize(s));  // pids is freed on return
             ix.piv_n = P;
         } else {
+            while ((1 << key_bits) < P) ++key_bits;
+            gstart.alloc((size_t)P * sizeof(int32_t));
+            gend.alloc((size_t)P * sizeof(int32_t));
             DevBuf grown((size_t)N * sizeof(int32_t));
             VJ_HIP(hipMemcpyAsync(grown.p, ix.piv_of.p, (size_t)rb * sizeof(int32_t),
                                   hipMemcpyDeviceToDevice, s));
-            hipLaunchKernelGGL(k_assign_pivot, dim3(g1b(N - rb, 256)), dim3(256), 0, s,
-                               vec + rb * dp, dp, N - rb, ix.piv_rows.as<float>(), ix.piv_n,
-                               grown.as<int32_t>() + rb);
+            assign_groups(vec + rb * dp, dp, N - rb, ix.piv_rows.as<float>(), P,
+                          grown.as<int32_t>() + rb, ix.piv_rad.as<float>(), s);
             ix.piv_of = std::move(grown);
         }
         ix.piv_cnt = N;
-        const int P = ix.piv_n;
-        DevBuf assign = DevBuf::view(ix.piv_of.p, (size_t)N * sizeof(int32_t));
-        // 2. columns in pivot order, as sweep-order copies padded to whole tiles
-        DevBuf skeys((size_t)N * sizeof(int32_t)), iota((size_t)N * sizeof(int32_t)),
-            perm((size_t)N * sizeof(int32_t)), tmp;
-        iota_i32(iota.as<int32_t>(), N, s);
-        sort_pairs_i32(assign.as<int32_t>(), skeys.as<int32_t>(), iota.as<int32_t>(),
-                       perm.as<int32_t>(), N, 11, tmp, s);
+        build_log(s, "kNN sweep: %d groups", P);
+        // 2. columns in group order, each group from a tile start (its last
+        //    tile padded with zero rows of id -1 and |x|^2 = +inf)
+        group_sort();
+        std::vector<int32_t> gs((size_t)P), ge((size_t)P), ts((size_t)P), te((size_t)P);
+        VJ_HIP(hipMemcpyAsync(gs.data(), gstart.p, (size_t)P * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipMemcpyAsync(ge.data(), gend.p, (size_t)P * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipStreamSynchronize(s));
+        int64_t T = 0;
+        for (int g = 0; g < P; ++g) {
+            const int64_t n = gs[(size_t)g] < 0 ? 0 : ge[(size_t)g] - gs[(size_t)g];
+            ts[(size_t)g] = (int32_t)T;
+            T += (n + BN - 1) / BN;
+            te[(size_t)g] = (int32_t)T;
+        }
+        const int64_t Np = T * BN;
+        VJ_CHECK(Np < ((int64_t)1 << 31), VJ_ERR_UNSUPPORTED, "kNN sweep columns");
+        DevBuf gt_s((size_t)P * sizeof(int32_t)), gt_e((size_t)P * sizeof(int32_t)),
+            slot((size_t)Np * sizeof(int32_t));
+        VJ_HIP(hipMemcpyAsync(gt_s.p, ts.data(), (size_t)P * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+        VJ_HIP(hipMemcpyAsync(gt_e.p, te.data(), (size_t)P * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+        fill_i32(slot.as<int32_t>(), Np, -1, s);
+        hipLaunchKernelGGL(k_slot_map, dim3(g1b(N, 256)), dim3(256), 0, s, skeys.as<int32_t>(),
+                           perm.as<int32_t>(), N, gstart.as<int32_t>(), gt_s.as<int32_t>(), BN,
+                           slot.as<int32_t>());
         DevBuf bh((size_t)Np * KP * sizeof(uint16_t)),
             bl(NSPLIT == 3 ? (size_t)Np * KP * sizeof(uint16_t) : 16), bn2((size_t)Np * sizeof(float)),
-            bid_of((size_t)Np * sizeof(int32_t)), gstart((size_t)P * sizeof(int32_t)),
-            gend((size_t)P * sizeof(int32_t));
+            bid_of((size_t)Np * sizeof(int32_t));
         hipLaunchKernelGGL(k_sweep_copy, dim3(g1b(Np * (KP / 8), 256)), dim3(256), 0, s,
                            t.hi.as<uint16_t>(), NSPLIT == 3 ? t.lo.as<uint16_t>() : nullptr,
-                           t.norm2.as<float>(), KP, perm.as<int32_t>(), N, Np, bh.as<uint16_t>(),
+                           t.norm2.as<float>(), KP, slot.as<int32_t>(), Np, bh.as<uint16_t>(),
                            NSPLIT == 3 ? bl.as<uint16_t>() : nullptr, bn2.as<float>(),
                            bid_of.as<int32_t>());
-        fill_i32(gstart.as<int32_t>(), P, -1, s);
-        fill_i32(gend.as<int32_t>(), P, 0, s);
-        hipLaunchKernelGGL(k_group_start, dim3(g1b(N, 256)), dim3(256), 0, s, skeys.as<int32_t>(),
-                           N, gstart.as<int32_t>(), gend.as<int32_t>());
-        // 3. the call's rows in pivot order, and each block's start tile
+        slot.release();
+        skeys.release();
+        perm.release();
+        iota.release();
+        // 3. the call's rows in group order
         const int64_t nb = (M + S::ROWS - 1) / S::ROWS;
         DevBuf rkeys((size_t)M * sizeof(int32_t)), rkeys2((size_t)M * sizeof(int32_t)),
-            rvals((size_t)M * sizeof(int32_t)), rowperm((size_t)M * sizeof(int32_t)),
-            start_tile((size_t)nb * sizeof(int32_t)), span((size_t)nb * sizeof(int32_t));
-        hipLaunchKernelGGL(k_row_keys, dim3(g1b(M, 256)), dim3(256), 0, s, assign.as<int32_t>(),
+            rvals((size_t)M * sizeof(int32_t)), rowperm((size_t)M * sizeof(int32_t));
+        hipLaunchKernelGGL(k_row_keys, dim3(g1b(M, 256)), dim3(256), 0, s, ix.piv_of.as<int32_t>(),
                            rb, M, rkeys.as<int32_t>(), rvals.as<int32_t>());
         sort_pairs_i32(rkeys.as<int32_t>(), rkeys2.as<int32_t>(), rvals.as<int32_t>(),
-                       rowperm.as<int32_t>(), M, 11, tmp, s);
-        hipLaunchKernelGGL(k_start_tiles, dim3(g1b(nb, 256)), dim3(256), 0, s,
-                           rkeys2.as<int32_t>(), M, S::ROWS, gstart.as<int32_t>(),
-                           gend.as<int32_t>(), BN, nb, start_tile.as<int32_t>(),
-                           span.as<int32_t>());
-        // 4. the sweep.  With enough row blocks, one pass over all tiles.
-        //    Otherwise (an insertion batch) two passes, each split over
-        //    columns so that the grid fills the chip: the first over the P1
-        //    tiles from each block's start, P1 covering the groups of all of
-        //    the block's rows (at least 64); its lists are merged and the
-        //    K-th key of each row is the starting threshold of every split of
-        //    the second pass over the remaining tiles (a true top-K entry is
-        //    at or below it, so it passes in its split and survives that
-        //    split's merges); then the lists are merged again.
+                       rowperm.as<int32_t>(), M, key_bits, tmp, s);
+        rkeys.release();
+        rvals.release();
         // launches of at most kKnnChunk row blocks (progress between them
         // when logging; no launch runs for minutes on the largest builds)
-        auto sweep = [&](int32_t j0, int32_t ntiles, int splits, int32_t split_base,
-                         const float *tau_in) {
-            const int64_t tps = (ntiles + splits - 1) / splits;
+        auto sweep = [&](const DevBuf &roff, const DevBuf &rtile, const DevBuf &rpos,
+                         const DevBuf &vt, int splits, int32_t split_base, const float *tau_in,
+                         const int32_t *cnt_in) {
             for (int64_t b0 = 0; b0 < nb; b0 += kKnnChunk) {
                 const int64_t nbc = std::min<int64_t>(kKnnChunk, nb - b0);
                 hipLaunchKernelGGL((k_knn_reg<NSPLIT, KP>), dim3((unsigned)nbc, (unsigned)splits),
@@ -1076,18 +1429,30 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
                                    NSPLIT == 3 ? t.lo.as<uint16_t>() : nullptr,
                                    rowperm.as<int32_t>(), (int32_t)M, bh.as<uint16_t>(),
                                    NSPLIT == 3 ? bl.as<uint16_t>() : nullptr, bn2.as<float>(),
-                                   bid_of.as<int32_t>(), (int32_t)T, start_tile.as<int32_t>(), j0,
-                                   (int32_t)tps, split_base, tau_in, K, bkey.as<float>(),
-                                   bidb.as<int32_t>(), (int32_t)rb, (int32_t)b0);
+                                   bid_of.as<int32_t>(), roff.as<int64_t>(), rtile.as<int32_t>(),
+                                   rpos.as<int32_t>(), vt.as<int32_t>(), split_base, tau_in,
+                                   cnt_in, K, bkey.as<float>(), bidb.as<int32_t>(), (int32_t)rb,
+                                   (int32_t)b0);
                 if (nb > kKnnChunk)
                     build_log(s, "kNN sweep: row blocks %lld of %lld", (long long)(b0 + nbc),
                               (long long)nb);
             }
         };
-        auto nsplits = [&](int64_t ntiles) {
+        // column splits of a pass whose blocks sweep vsum tiles in all
+        auto nsplits = [&](int64_t vsum) {
+            const int64_t mean = (vsum + nb - 1) / nb;
             int sp = 1;
-            while (nb * sp < 1024 && ntiles / (sp * 2) >= 8 && sp < 256) sp *= 2;
+            while (nb * sp < 1024 && mean / (sp * 2) >= 8 && sp < 256) sp *= 2;
             return sp;
+        };
+        auto total = [&](const DevBuf &vt) {
+            std::vector<int32_t> h((size_t)nb);
+            VJ_HIP(hipMemcpyAsync(h.data(), vt.p, (size_t)nb * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, s));
+            VJ_HIP(hipStreamSynchronize(s));
+            int64_t v = 0;
+            for (int32_t x : h) v += x;
+            return v;
         };
         // lists 0 .. S-1 of every row into list 0 (sorted), in rounds
         auto merge_lists = [&](int S) {
@@ -1098,38 +1463,69 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
                                    bkey.as<float>(), bidb.as<int32_t>(), M, S, K, G, (int)step);
             }
         };
-        if (nsplits(T) == 1) {
-            bkey.alloc((size_t)M * kKnnCap * sizeof(float));
-            bidb.alloc((size_t)M * kKnnCap * sizeof(int32_t));
-            sweep(0, (int32_t)T, 1, 0, nullptr);
-        } else {
-            std::vector<int32_t> span_h((size_t)nb);
-            VJ_HIP(hipMemcpyAsync(span_h.data(), span.p, (size_t)nb * sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, s));
-            VJ_HIP(hipStreamSynchronize(s));
-            int64_t P1 = 64;
-            for (int32_t v : span_h) P1 = std::max<int64_t>(P1, v);
-            P1 = std::min<int64_t>(T, P1);
-            // a split ends at its start + tiles_per_split (or T): P1 a
-            // multiple of the first pass's splits, so the passes do not
-            // overlap (a column seen twice would be kept twice)
-            const int s1 = nsplits(P1);
-            P1 = std::min<int64_t>(T, (P1 + s1 - 1) / s1 * s1);
-            const int s2 = T > P1 ? nsplits(T - P1) : 0;
-            const int nl = std::max(s1, 1 + s2);
-            bkey.alloc((size_t)nl * M * kKnnCap * sizeof(float));
-            bidb.alloc((size_t)nl * M * kKnnCap * sizeof(int32_t));
-            sweep(0, (int32_t)P1, s1, 0, nullptr);
-            merge_lists(s1);
-            if (s2 > 0) {
-                DevBuf tau((size_t)M * sizeof(float));
-                hipLaunchKernelGGL(k_list_tau, dim3(g1b(M, 256)), dim3(256), 0, s,
-                                   bkey.as<float>(), bidb.as<int32_t>(), rowperm.as<int32_t>(), M,
-                                   rb, K, tau.as<float>());
-                sweep((int32_t)P1, (int32_t)(T - P1), s2, 1, tau.as<float>());
+        // 4. first pass: each block's own groups
+        DevBuf roff1((size_t)(nb + 1) * sizeof(int64_t)), rtile1((size_t)nb * sizeof(int32_t)),
+            rpos1((size_t)nb * sizeof(int32_t)), vt1((size_t)nb * sizeof(int32_t));
+        hipLaunchKernelGGL(k_pass1_runs, dim3(g1b(nb, 256)), dim3(256), 0, s, rkeys2.as<int32_t>(),
+                           M, S::ROWS, gt_s.as<int32_t>(), gt_e.as<int32_t>(), nb,
+                           roff1.as<int64_t>(), rtile1.as<int32_t>(), rpos1.as<int32_t>(),
+                           vt1.as<int32_t>());
+        const int64_t v1 = total(vt1);
+        const int s1 = nsplits(v1);
+        bkey.alloc((size_t)s1 * M * kKnnCap * sizeof(float));
+        bidb.alloc((size_t)s1 * M * kKnnCap * sizeof(int32_t));
+        sweep(roff1, rtile1, rpos1, vt1, s1, 0, nullptr, nullptr);
+        merge_lists(s1);
+        // 5. thresholds, then the groups each block still needs
+        DevBuf tau((size_t)M * sizeof(float)), cnt((size_t)M * sizeof(int32_t));
+        hipLaunchKernelGGL(k_list_tau, dim3(g1b(M, 256)), dim3(256), 0, s, bkey.as<float>(),
+                           bidb.as<int32_t>(), rowperm.as<int32_t>(), M, rb, K, tau.as<float>(),
+                           cnt.as<int32_t>());
+        const int W = (P + 31) / 32;
+        double e_dot = 0.0, e_fin = 0.0;
+        tile_error_bounds(t, t, NSPLIT, e_dot, e_fin);
+        DevBuf need((size_t)nb * W * sizeof(uint32_t)), nneed((size_t)nb * sizeof(int32_t)),
+            roff2((size_t)(nb + 1) * sizeof(int64_t)), vt2((size_t)nb * sizeof(int32_t));
+        visit_groups(vec, dp, rowperm.as<int32_t>(), M, S::ROWS, rkeys2.as<int32_t>(),
+                     ix.piv_rows.as<float>(), ix.piv_rad.as<float>(), gt_s.as<int32_t>(),
+                     gt_e.as<int32_t>(), P, tau.as<float>(), t.norm2.as<float>(), (float)e_dot,
+                     (float)e_fin, t.maxnorm, need.as<uint32_t>(), nneed.as<int32_t>(), s);
+        exclusive_scan_i32_i64(nneed.as<int32_t>(), roff2.as<int64_t>(), nb, tmp, s);
+        int64_t nruns = 0;
+        VJ_HIP(hipMemcpyAsync(&nruns, roff2.as<int64_t>() + nb, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, s));
+        VJ_HIP(hipStreamSynchronize(s));
+        DevBuf rtile2((size_t)std::max<int64_t>(nruns, 1) * sizeof(int32_t)),
+            rpos2((size_t)std::max<int64_t>(nruns, 1) * sizeof(int32_t));
+        hipLaunchKernelGGL(k_visit_runs, dim3((unsigned)nb), dim3(128), 0, s, need.as<uint32_t>(),
+                           W, gt_s.as<int32_t>(), gt_e.as<int32_t>(), roff2.as<int64_t>(),
+                           rtile2.as<int32_t>(), rpos2.as<int32_t>(), vt2.as<int32_t>());
+        const int64_t v2 = total(vt2);
+        build_log(s, "kNN sweep: first pass %lld tiles, second pass %lld of %lld (%.3f)",
+                  (long long)v1, (long long)v2, (long long)(nb * T), (double)v2 / (double)(nb * T));
+        // 6. second pass: with one split the lists go on in list 0 (from
+        //    their counts and thresholds); with more, the splits start empty
+        //    lists 1 .. s2 from the thresholds (a true top-K entry is at or
+        //    below them, so it passes in its split and survives that split's
+        //    merges) and all are merged again
+        if (v2 > 0) {
+            const int s2 = nsplits(v2);
+            if (s2 == 1) {
+                sweep(roff2, rtile2, rpos2, vt2, 1, 0, tau.as<float>(), cnt.as<int32_t>());
+            } else {
+                if ((size_t)(1 + s2) > (size_t)s1) {
+                    // room for 1 + s2 lists, list 0 kept
+                    DevBuf k2((size_t)(1 + s2) * M * kKnnCap * sizeof(float)),
+                        i2((size_t)(1 + s2) * M * kKnnCap * sizeof(int32_t));
+                    VJ_HIP(hipMemcpyAsync(k2.p, bkey.p, (size_t)M * kKnnCap * sizeof(float),
+                                          hipMemcpyDeviceToDevice, s));
+                    VJ_HIP(hipMemcpyAsync(i2.p, bidb.p, (size_t)M * kKnnCap * sizeof(int32_t),
+                                          hipMemcpyDeviceToDevice, s));
+                    bkey = std::move(k2);
+                    bidb = std::move(i2);
+                }
+                sweep(roff2, rtile2, rpos2, vt2, s2, 1, tau.as<float>(), nullptr);
                 merge_lists(1 + s2);
-                VJ_HIP(hipGetLastError());
-                VJ_HIP(hipStreamSynchronize(s));  // tau is freed on return
             }
         }
         VJ_HIP(hipGetLastError());

@@ -1498,6 +1498,7 @@ vj_status vj_index_insert_queries(vj_index *idx, const float *Q, int64_t n, int3
     // error they are dropped, and the next insertion labels every node)
     b.piv_rows = std::move(ix.piv_rows);
     b.piv_of = std::move(ix.piv_of);
+    b.piv_rad = std::move(ix.piv_rad);
     b.piv_n = ix.piv_n;
     b.piv_cnt = ix.piv_cnt;
     ix.piv_n = 0;
@@ -1509,6 +1510,7 @@ vj_status vj_index_insert_queries(vj_index *idx, const float *Q, int64_t n, int3
     ix.elen = std::move(b.elen);
     ix.piv_rows = std::move(b.piv_rows);
     ix.piv_of = std::move(b.piv_of);
+    ix.piv_rad = std::move(b.piv_rad);
     ix.piv_n = b.piv_n;
     ix.piv_cnt = b.piv_cnt;
     ix.nq = b.nq;

@@ -185,10 +185,11 @@ struct Index {
     std::vector<int32_t> lay_entry;
     DevBuf lay_adj, lay_pos, lay_ids, lay_offd, lay_seed;
     int64_t repairs = 0;  // connectivity-repair edges added by the build
-    // pivot order of the kNN sweep, kept so that an insertion labels only
-    // its new nodes: pivot rows (fp32 [piv_n][dp]) and the nearest pivot of
-    // nodes [0, piv_cnt)
-    DevBuf piv_rows, piv_of;
+    // group order of the kNN sweep, kept so that an insertion labels only
+    // its new nodes: group centres (fp32 [piv_n][dp]), the nearest centre of
+    // nodes [0, piv_cnt) and each group's radius (fp32 [piv_n]: no member of
+    // group g is farther than piv_rad[g] from its centre)
+    DevBuf piv_rows, piv_of, piv_rad;
     int32_t piv_n = 0;
     int64_t piv_cnt = 0;
     // join state shared by calls on this index (calls on one index must not overlap)
