@@ -644,6 +644,26 @@ __global__ void k_list_tau(const float *bkey, const int32_t *bid, const int32_t 
     cnt[pos] = c;
 }
 
+// distance bound of each row's list (rows by processing position; cert
+// indexed by row - rb): every node outside the K kept entries has a key >=
+// the K-th key t, so its squared distance is >= t + |r|^2 less the key's
+// error bound (ea, eb, maxn as in k_visit_groups) and the rounding of that
+// sum; +inf while the row holds fewer than K (every node is in the list)
+__global__ void k_list_cert(const float *bkey, const int32_t *bid, const int32_t *rowperm,
+                            int64_t M, int64_t rb, int K, const float *n2, float ea, float eb,
+                            float maxn, float *cert) {
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= M) return;
+    const int32_t node = rowperm[pos];
+    const int64_t o = ((int64_t)node - rb) * kKnnCap;
+    float t = -FLT_MAX;
+    for (int e = 0; e < K; ++e) t = bid[o + e] >= 0 ? fmaxf(t, bkey[o + e]) : FLT_MAX;
+    const float nr2 = n2[node], nr = sqrtf(nr2);
+    const float E = 2.f * (ea * nr * maxn + eb * (maxn * maxn + nr * maxn + nr2)) +
+                    4.f * FLT_EPSILON * (fabsf(t) + nr2);
+    cert[node - rb] = t >= FLT_MAX ? INFINITY : fmaxf(0.f, (t + nr2 - E) * (1.f - 1e-4f));
+}
+
 // an insertion's changing rows: every old node that receives an offer and
 // every new node (flag), then their ids at the flags' scan positions
 __global__ void k_changed_flags(const int32_t *indeg, int64_t n_old, int64_t N, int32_t *flag) {
@@ -751,6 +771,8 @@ struct RepairCtl {
     int nnext;                     // BFS: size of the next front
     unsigned long long best_any;   // (d2 bits << 32 | id) of the nearest reached node
     unsigned long long best_free;  // the same among nodes with a free slot
+    int certified;                 // best_free came from first's own list (no scan)
+    int pad;
 };
 
 __global__ void k_repair_reset(RepairCtl *c) {
@@ -758,6 +780,38 @@ __global__ void k_repair_reset(RepairCtl *c) {
     c->nnext = 0;
     c->best_any = ~0ull;
     c->best_free = ~0ull;
+    c->certified = 0;
+}
+
+// the nearest free reached node to w = c->first from w's own sorted list
+// (kc entries by (d2, id), d2 in the scan's arithmetic): every node outside
+// the list is at squared distance >= cert[w] (the kNN sweep's K-th key
+// turned into a distance bound), so a first reached free entry closer than
+// that is the scan's answer.  Rows [rb, rb + n) have lists; one wave.
+__global__ void k_repair_from_list(const int32_t *kid, const float *kd2, int kc, const float *cert,
+                                   int64_t rb, int64_t n, const int *seen, const int32_t *adj,
+                                   int R, RepairCtl *c) {
+    const int32_t w = c->first;
+    if (w == 0x7fffffff || w < rb || w >= rb + n) return;
+    const int lane = threadIdx.x;
+    const int64_t row = w - rb;
+    for (int e0 = 0; e0 < kc; e0 += 64) {
+        const int e = e0 + lane;
+        const int32_t v = e < kc ? kid[row * kc + e] : -1;
+        const bool hit = v >= 0 && seen[v] && adj[(int64_t)v * R + R - 1] < 0;
+        const unsigned long long m = __ballot(hit);
+        if (m) {
+            const int f = __ffsll((unsigned long long)m) - 1;
+            if (lane == f) {
+                const float d = kd2[row * kc + e];
+                if (d < cert[row]) {
+                    c->best_free = ((unsigned long long)__float_as_uint(d) << 32) | (uint32_t)v;
+                    c->certified = 1;
+                }
+            }
+            return;
+        }
+    }
 }
 
 // BFS seed: start is seen, the front is {start}
@@ -798,14 +852,15 @@ __device__ __forceinline__ float sum8(float acc) {
 
 __global__ void __launch_bounds__(256)
 k_nearest_reached(const float *vec, int64_t N, int dp, const int *wp, const int *seen,
-                  const int32_t *adj, int R, unsigned long long *best_any,
+                  const int32_t *adj, int R, const int *skip, unsigned long long *best_any,
                   unsigned long long *best_free) {
     // 8 lanes per node, 32 nodes per workgroup step, grid-stride over the
     // nodes; one atomic per workgroup (the minimum of unique (d2, id) keys
-    // does not depend on the order).  w (*wp) INT_MAX: nothing to do.
+    // does not depend on the order).  w (*wp) INT_MAX or *skip (the answer
+    // is known): nothing to do.
     __shared__ unsigned long long s_a[4], s_f[4];
     const int32_t w = *wp;
-    if (w == 0x7fffffff) return;
+    if (w == 0x7fffffff || *skip) return;
     const int lane = threadIdx.x & 63;
     const int g = lane >> 3, p8 = lane & 7;
     const float4 *b = reinterpret_cast<const float4 *>(vec + (int64_t)w * dp);
@@ -1302,7 +1357,8 @@ k_visit_runs(const uint32_t *need, int W, const int32_t *gt_s, const int32_t *gt
 // row blocks (an insertion batch), the splits' lists merged afterwards.
 template <int NSPLIT, int KP>
 bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, int64_t N, int K,
-                      int64_t rb, int64_t M, DevBuf &bkey, DevBuf &bidb, hipStream_t s) {
+                      int64_t rb, int64_t M, DevBuf &bkey, DevBuf &bidb, float *cert,
+                      hipStream_t s) {
     using S = ring::Shape<NSPLIT, KP>;
     if constexpr (!S::OK || !S::WHOLE) {
         return false;
@@ -1528,6 +1584,10 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
                 merge_lists(1 + s2);
             }
         }
+        if (cert)
+            hipLaunchKernelGGL(k_list_cert, dim3(g1b(M, 256)), dim3(256), 0, s, bkey.as<float>(),
+                               bidb.as<int32_t>(), rowperm.as<int32_t>(), M, rb, K,
+                               t.norm2.as<float>(), (float)e_dot, (float)e_fin, t.maxnorm, cert);
         VJ_HIP(hipGetLastError());
         VJ_HIP(hipStreamSynchronize(s));  // the temporaries above are freed on return
         return true;
@@ -1536,12 +1596,12 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
 
 bool launch_knn_reg(Index &ix, int nsplit, int Kp, const TileRows &t, const float *vec, int dp,
                     int64_t N, int K, int64_t rb, int64_t M, DevBuf &bkey, DevBuf &bidb,
-                    hipStream_t s) {
+                    float *cert, hipStream_t s) {
     if (K > 128 || M <= 0) return false;
 #define VJ_KNN_CASE(kp)                                                                         \
     case kp:                                                                                    \
-        return nsplit == 3 ? launch_knn_reg_t<3, kp>(ix, t, vec, dp, N, K, rb, M, bkey, bidb, s) \
-                           : launch_knn_reg_t<1, kp>(ix, t, vec, dp, N, K, rb, M, bkey, bidb, s);
+        return nsplit == 3 ? launch_knn_reg_t<3, kp>(ix, t, vec, dp, N, K, rb, M, bkey, bidb, cert, s) \
+                           : launch_knn_reg_t<1, kp>(ix, t, vec, dp, N, K, rb, M, bkey, bidb, cert, s);
     switch (Kp) {
         VJ_KNN_CASE(32) VJ_KNN_CASE(64) VJ_KNN_CASE(96) VJ_KNN_CASE(128) VJ_KNN_CASE(192)
         VJ_KNN_CASE(256)
@@ -1551,8 +1611,10 @@ bool launch_knn_reg(Index &ix, int nsplit, int Kp, const TileRows &t, const floa
 }
 
 // exact top-K candidate lists (ids in bid [M][kKnnCap], K of them) of rows
-// [rb, rb + M) of ix.vec among all ix.N rows, on MFMA tiles
-void knn_candidates(Index &ix, int64_t rb, int64_t M, int K, DevBuf &bidb, hipStream_t s) {
+// [rb, rb + M) of ix.vec among all ix.N rows, on MFMA tiles; true if the
+// lists' distance bounds went to cert (M floats; the register-row sweep)
+bool knn_candidates(Index &ix, int64_t rb, int64_t M, int K, DevBuf &bidb, float *cert,
+                    hipStream_t s) {
     const int64_t N = ix.N;
     const int dp = ix.dp;
     const float *vec = ix.vec.as<float>();
@@ -1563,10 +1625,10 @@ void knn_candidates(Index &ix, int64_t rb, int64_t M, int K, DevBuf &bidb, hipSt
     tile_error_bounds(t, t, 1, e_dot, e_fin);
     const int nsplit = (e_dot == 0.0) ? 1 : 3;
     DevBuf bkey;
-    if (launch_knn_reg(ix, nsplit, Kp, t, vec, dp, N, K, rb, M, bkey, bidb, s)) {
+    if (launch_knn_reg(ix, nsplit, Kp, t, vec, dp, N, K, rb, M, bkey, bidb, cert, s)) {
         VJ_HIP(hipGetLastError());
         VJ_HIP(hipStreamSynchronize(s));
-        return;
+        return true;
     }
     bkey.alloc((size_t)M * kKnnCap * sizeof(float));
     bidb.alloc((size_t)M * kKnnCap * sizeof(int32_t));
@@ -1580,13 +1642,24 @@ void knn_candidates(Index &ix, int64_t rb, int64_t M, int K, DevBuf &bidb, hipSt
                            bidb.as<int32_t>(), rb, M);
     VJ_HIP(hipGetLastError());
     VJ_HIP(hipStreamSynchronize(s));
+    return false;
 }
 
 // connectivity repair from the entry: the smallest unreachable node gets an
 // edge from its nearest reached node with a free slot (else that node's
 // longest edge is replaced), until every node is reached.  The rows changed
 // are appended to `touched` (if given).
-void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched) {
+// sorted kNN lists of rows [rb, rb + n) and their distance bounds (see
+// k_repair_from_list); kid null: none
+struct RepairLists {
+    const int32_t *kid = nullptr;
+    const float *kd2 = nullptr, *cert = nullptr;
+    int kc = 0;
+    int64_t rb = 0, n = 0;
+};
+
+void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched,
+                         const RepairLists &L) {
     const int64_t N = ix.N;
     const int R = ix.R, dp = ix.dp;
     const float *vec = ix.vec.as<float>();
@@ -1621,6 +1694,7 @@ void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched
     };
     bfs_from(ix.entry, true);
     const int64_t max_iter = std::min<int64_t>(N, 200000);
+    int64_t ncert = 0;  // steps answered from the lists
     // while edges are only added, reachability only grows and the smallest
     // unseen node only moves up: each scan starts after the last one
     int64_t from = 0;
@@ -1630,10 +1704,14 @@ void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched
         hipLaunchKernelGGL(k_repair_reset, dim3(1), dim3(1), 0, s, ctl);
         hipLaunchKernelGGL(k_first_unseen, dim3(scan_grid), dim3(256), 0, s, seenp, from, N,
                            &ctl->first);
+        if (L.kid)
+            hipLaunchKernelGGL(k_repair_from_list, dim3(1), dim3(64), 0, s, L.kid, L.kd2, L.kc,
+                               L.cert, L.rb, L.n, seenp, ix.adj.as<int32_t>(), R, ctl);
         hipLaunchKernelGGL(k_nearest_reached, dim3(std::min<unsigned>(g1b(N, 32), 2048)), dim3(256),
                            0, s, vec, N, dp, &ctl->first, seenp, ix.adj.as<int32_t>(), R,
-                           &ctl->best_any, &ctl->best_free);
+                           &ctl->certified, &ctl->best_any, &ctl->best_free);
         readback();
+        ncert += h->certified;
         const int32_t first = h->first;
         if (first == 0x7fffffff) break;
         const bool has_free = h->best_free != ~0ull;
@@ -1653,6 +1731,7 @@ void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched
             from = 0;
         }
     }
+    build_log(s, "connectivity repair: %lld steps answered from the kNN lists", (long long)ncert);
 }
 
 }  // namespace
@@ -1667,9 +1746,9 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
     const float *vec = ix.vec.as<float>();
 
     // 1. kNN on MFMA tiles over all nodes, then exact re-rank
-    DevBuf bidb;
+    DevBuf bidb, cert((size_t)N * sizeof(float));
     build_log(s, "build over %lld nodes: start", (long long)N);
-    knn_candidates(ix, 0, N, K, bidb, s);
+    const bool have_cert = knn_candidates(ix, 0, N, K, bidb, cert.as<float>(), s);
     build_log(s, "kNN lists done");
 
     // 2. re-rank + forward prune
@@ -1721,8 +1800,18 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
         ix.entry = e;
     }
 
-    // 5. connectivity repair from the entry
-    repair_connectivity(ix, s, nullptr);
+    // 5. connectivity repair from the entry (with the sorted lists and their
+    //    distance bounds: a step whose answer is certified there skips the scan)
+    RepairLists lists;
+    if (have_cert) {
+        lists.kid = kid.as<int32_t>();
+        lists.kd2 = kd2.as<float>();
+        lists.cert = cert.as<float>();
+        lists.kc = kc;
+        lists.rb = 0;
+        lists.n = N;
+    }
+    repair_connectivity(ix, s, nullptr, lists);
     build_log(s, "connectivity repair done (%lld edges)", (long long)ix.repairs);
 
     // 6. edge lengths
@@ -1743,8 +1832,8 @@ void insert_graph(Index &ix, int64_t n_old, int kc, hipStream_t s) {
     int32_t *adj = ix.adj.as<int32_t>();
 
     // 1. candidates of the new rows among all rows, re-rank, forward prune
-    DevBuf bidb;
-    knn_candidates(ix, n_old, M, K, bidb, s);
+    DevBuf bidb, cert((size_t)M * sizeof(float));
+    const bool have_cert = knn_candidates(ix, n_old, M, K, bidb, cert.as<float>(), s);
     DevBuf kid((size_t)M * kc * sizeof(int32_t)), kd2((size_t)M * kc * sizeof(float));
     DevBuf fwd((size_t)M * R * sizeof(int32_t)), fwd_d2((size_t)M * R * sizeof(float));
     DevBuf fdeg((size_t)M * sizeof(int32_t)), indeg((size_t)N * sizeof(int32_t));
@@ -1754,8 +1843,6 @@ void insert_graph(Index &ix, int64_t n_old, int kc, hipStream_t s) {
                 n_old, M, s);
     VJ_HIP(hipGetLastError());
     bidb.release();
-    kid.release();
-    kd2.release();
 
     // 2. offers (CSR by target) and the rows that change: every old row that
     //    receives an offer, and every new row (offsets and the row list
@@ -1795,7 +1882,16 @@ void insert_graph(Index &ix, int64_t n_old, int kc, hipStream_t s) {
     // 4. connectivity repair from the (unchanged) entry, then the lengths of
     //    every row that changed (the listed rows and the repairs' sources)
     std::vector<int32_t> touched;
-    repair_connectivity(ix, s, &touched);
+    RepairLists lists;
+    if (have_cert) {
+        lists.kid = kid.as<int32_t>();
+        lists.kd2 = kd2.as<float>();
+        lists.cert = cert.as<float>();
+        lists.kc = kc;
+        lists.rb = n_old;
+        lists.n = M;
+    }
+    repair_connectivity(ix, s, &touched, lists);
     int64_t nrows = L;
     if (!touched.empty()) {
         nrows = L + (int64_t)touched.size();
