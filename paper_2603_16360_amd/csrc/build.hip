@@ -330,7 +330,7 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
           const int64_t *__restrict__ run_off, const int32_t *__restrict__ run_tile,
           const int32_t *__restrict__ run_pos, const int32_t *__restrict__ vtot,
           int32_t split_base, const float *tau_in, const int32_t *cnt_in, int K, float *bkey,
-          int32_t *bid, int32_t rb, int32_t blk0) {
+          int32_t *bid, int32_t rb, int32_t blk0, const int32_t *order) {
     using S = ring::Shape<NSPLIT, KP>;
     constexpr int RT = S::RT, CT = S::CT, KS = S::KS, BN = S::BN, CPR = S::CPR, SPR = S::SPR;
     constexpr int IPW = S::IPW, TERMS = S::TERMS, PART = S::PART, STAGE = S::STAGE, NB = S::NB;
@@ -341,7 +341,8 @@ k_knn_reg(const uint16_t *Ah, const uint16_t *Al, const int32_t *rowperm, int32_
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r16 = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4, grp = lane >> 4;
-    const int32_t blk = blk0 + (int32_t)blockIdx.x;  // row block (launches may be chunked)
+    // row block (launches may be chunked; order: the blocks in launch order)
+    const int32_t blk = order ? order[blk0 + (int32_t)blockIdx.x] : blk0 + (int32_t)blockIdx.x;
     const int32_t prow0 = blk * S::ROWS + w * RT * 16;  // wave's first row (order)
     const int64_t boff = (int64_t)(split_base + blockIdx.y) * M;  // this split's buffer rows
     // the block's tiles are runs [run_off[blk], run_off[blk + 1]): run k
@@ -982,7 +983,8 @@ void launch_gather(int dp, const float *vec, int R, const int32_t *adj, const in
 
 // ---- group order of the kNN sweep
 // The nodes are grouped by their nearest of P centres (P <= kMaxGroups;
-// centres: every (N / P)-th node, moved to its group's mean kLloyd times),
+// centres: every (N / P)-th node, moved to its group's mean lloyd_steps(N)
+// times),
 // rows and columns are sorted by group, and each group starts a tile.  The
 // sweep of a row block runs in two passes: its own groups first, whose
 // lists give every row a threshold tau (its K-th key), then only the groups
@@ -992,9 +994,11 @@ void launch_gather(int dp, const float *vec, int R, const int32_t *adj, const in
 // bound, less the tile key's error bound, puts every member's key above tau
 // for every row of the block, no member of g would enter a list: skipping g
 // leaves the lists exactly as the full sweep leaves them.
-constexpr int64_t kGroupRows = 256;  // nodes per group (on average, at most kMaxGroups)
+constexpr int64_t kGroupRows = 512;  // nodes per group (on average, at most kMaxGroups)
 constexpr int kMaxGroups = 4096;
-constexpr int kLloyd = 1;            // mean steps of the centres before the last labelling
+// mean steps of the centres before the last labelling: one, two from 4M
+// nodes on (where the tighter groups save more sweep than a step costs)
+inline int lloyd_steps(int64_t N) { return N >= 4000000 ? 2 : 1; }
 
 // Distances of rows to centres, eight lanes per row: lane p8 of a row's
 // group holds float4 slices p8, p8 + 8, ... (NCHL = dp / 32 of them) of two
@@ -1060,12 +1064,16 @@ __device__ __forceinline__ void stage_centres(const float *cen, int p0, int np, 
 }
 
 // nearest of P centres (fp32 L2; the smaller index on ties) for every node,
-// 64 nodes per workgroup (dp = 32 NCHL <= 256).  With rad, the group's
+// 64 nodes per workgroup (dp = 32 NCHL <= 256).  With one slice of centres
+// (gridDim.y = 1) the label goes to assign and, with rad, the group's
 // radius grows to the node's distance (non-negative floats order as their
-// bits).
+// bits).  With several, slice y covers centre words [y wps, (y + 1) wps) and
+// each node's best goes to best[v] as (d2 bits << 32 | index) by atomicMin,
+// for k_assign_finish.
 template <int NCHL>
 __global__ void __launch_bounds__(256, 3)
-k_assign_pivot(const float *vec, int64_t N, const float *piv, int P, int32_t *assign, float *rad) {
+k_assign_pivot(const float *vec, int64_t N, const float *piv, int P, int wps, int32_t *assign,
+               float *rad, unsigned long long *best) {
     constexpr int dp = NCHL * 32;
     __shared__ __attribute__((aligned(16))) float sp[32 * dp];
     const int p8 = threadIdx.x & 7, grp = threadIdx.x >> 3;
@@ -1074,9 +1082,10 @@ k_assign_pivot(const float *vec, int64_t N, const float *piv, int P, int32_t *as
     rp.load(vec + (va < N ? va : 0) * dp, vec + (vb < N ? vb : 0) * dp, p8);
     float ba = INFINITY, bb = INFINITY;
     int ia = 0, ib = 0;
-    for (int p0 = 0; p0 < P; p0 += 32) {
+    const int pe = min(P, (int)(blockIdx.y + 1) * wps * 32);
+    for (int p0 = blockIdx.y * wps * 32; p0 < pe; p0 += 32) {
         __syncthreads();
-        stage_centres(piv, p0, min(32, P - p0), dp, sp);
+        stage_centres(piv, p0, min(32, pe - p0), dp, sp);
         __syncthreads();
         float da[4], db[4];
         rp.dist(sp, p8, da, db);
@@ -1095,16 +1104,35 @@ k_assign_pivot(const float *vec, int64_t N, const float *piv, int P, int32_t *as
         if (oa < ba || (oa == ba && ja < ia)) { ba = oa; ia = ja; }
         if (ob < bb || (ob == bb && jb < ib)) { bb = ob; ib = jb; }
     }
-    if (p8 == 0) {
-        if (va < N) {
-            assign[va] = ia;
-            if (rad) atomicMax(reinterpret_cast<unsigned int *>(rad) + ia, __float_as_uint(sqrtf(ba)));
-        }
-        if (vb < N) {
-            assign[vb] = ib;
-            if (rad) atomicMax(reinterpret_cast<unsigned int *>(rad) + ib, __float_as_uint(sqrtf(bb)));
-        }
+    if (p8 != 0) return;
+    if (best) {
+        if (va < N && ba < INFINITY)
+            atomicMin(best + va, ((unsigned long long)__float_as_uint(ba) << 32) | (uint32_t)ia);
+        if (vb < N && bb < INFINITY)
+            atomicMin(best + vb, ((unsigned long long)__float_as_uint(bb) << 32) | (uint32_t)ib);
+        return;
     }
+    if (va < N) {
+        assign[va] = ia;
+        if (rad) atomicMax(reinterpret_cast<unsigned int *>(rad) + ia, __float_as_uint(sqrtf(ba)));
+    }
+    if (vb < N) {
+        assign[vb] = ib;
+        if (rad) atomicMax(reinterpret_cast<unsigned int *>(rad) + ib, __float_as_uint(sqrtf(bb)));
+    }
+}
+
+// labels (and radii) from the slices' packed minima
+__global__ void k_assign_finish(const unsigned long long *best, int64_t N, int32_t *assign,
+                                float *rad) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    const unsigned long long k = best[v];
+    const int32_t g = (int32_t)(uint32_t)k;
+    assign[v] = g;
+    if (rad)
+        atomicMax(reinterpret_cast<unsigned int *>(rad) + g,
+                  __float_as_uint(sqrtf(__uint_as_float((uint32_t)(k >> 32)))));
 }
 
 // centre of each non-empty group: the mean of its members (sweep positions
@@ -1185,6 +1213,12 @@ __global__ void k_row_keys(const int32_t *assign, int64_t rb, int64_t M, int32_t
     vals[i] = (int32_t)(rb + i);
 }
 
+// sort keys that put larger counts first
+__global__ void k_desc_keys(const int32_t *v, int32_t vmax, int64_t n, int32_t *keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) keys[i] = vmax - v[i];
+}
+
 // first pass: one run per row block, the tiles of the groups from its first
 // row's to its last row's (rkeys: the rows' sorted group ids)
 __global__ void k_pass1_runs(const int32_t *rkeys, int64_t M, int rows, const int32_t *gt_s,
@@ -1209,12 +1243,13 @@ __global__ void k_pass1_runs(const int32_t *rkeys, int64_t M, int rows, const in
 // |r| |c|; eb: norms and the final adds) and the fp32 norm of r; the
 // distances here carry a relative margin of 1e-4 (fp32 sums of at most 256
 // squares are far closer).  Rows as in k_assign_pivot, 64 per pass over the
-// centres (rows / 64 passes).
+// centres (rows / 64 passes); workgroup (b, y) takes centre words
+// [y wps, (y + 1) wps) and adds its count to nneed[b] (zeroed before).
 template <int NCHL>
 __global__ void __launch_bounds__(256, 3)
 k_visit_groups(const float *vec, const int32_t *rowperm, int64_t M, int rows, const int32_t *rkeys,
                const float *cen, const float *rad, const int32_t *gt_s, const int32_t *gt_e,
-               int P, const float *tau, const float *n2, float ea, float eb, float maxn,
+               int P, int wps, const float *tau, const float *n2, float ea, float eb, float maxn,
                uint32_t *need, int32_t *nneed) {
     constexpr int dp = NCHL * 32;
     __shared__ __attribute__((aligned(16))) float sp[32 * dp];
@@ -1224,7 +1259,8 @@ k_visit_groups(const float *vec, const int32_t *rowperm, int64_t M, int rows, co
     const int64_t b = blockIdx.x;
     const int i = threadIdx.x, p8 = i & 7, grp = i >> 3;
     const int W = (P + 31) / 32;
-    for (int k = i; k < W; k += blockDim.x) sneed[k] = 0u;
+    const int w0 = blockIdx.y * wps, w1 = min(W, w0 + wps);
+    for (int k = w0 + i; k < w1; k += blockDim.x) sneed[k] = 0u;
     // a row's bound: -1 past M (takes nothing), +inf while it holds < K
     auto bound = [&](int64_t pos, int32_t node) {
         const float t = tau[pos], nr2 = n2[node], nr = sqrtf(nr2);
@@ -1238,7 +1274,7 @@ k_visit_groups(const float *vec, const int32_t *rowperm, int64_t M, int rows, co
         const float ha = pa < rend ? bound(pa, na) : -1.f, hb = pb < rend ? bound(pb, nb) : -1.f;
         RowPair<NCHL> rp;
         rp.load(vec + (int64_t)na * dp, vec + (int64_t)nb * dp, p8);
-        for (int p0 = 0; p0 < P; p0 += 32) {
+        for (int p0 = w0 * 32; p0 < min(P, w1 * 32); p0 += 32) {
             const int np = min(32, P - p0);
             __syncthreads();
             stage_centres(cen, p0, np, dp, sp);
@@ -1265,7 +1301,7 @@ k_visit_groups(const float *vec, const int32_t *rowperm, int64_t M, int rows, co
     __syncthreads();
     const int32_t gf = rkeys[b * rows], gl = rkeys[rend - 1];
     int cnt = 0;
-    for (int k = i; k < W; k += blockDim.x) {
+    for (int k = w0 + i; k < w1; k += blockDim.x) {
         uint32_t word = sneed[k];
         for (int bit = 0; bit < 32; ++bit) {
             const int g = k * 32 + bit;
@@ -1278,7 +1314,7 @@ k_visit_groups(const float *vec, const int32_t *rowperm, int64_t M, int rows, co
     for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
     if ((i & 63) == 0) scount[i >> 6] = cnt;
     __syncthreads();
-    if (i == 0) nneed[b] = scount[0] + scount[1] + scount[2] + scount[3];
+    if (i == 0) atomicAdd(nneed + b, scount[0] + scount[1] + scount[2] + scount[3]);
 }
 
 // the two kernels above for dp = 32 NCHL (dp <= 256, a multiple of 32)
@@ -1292,23 +1328,45 @@ k_visit_groups(const float *vec, const int32_t *rowperm, int64_t M, int rows, co
     case 8: CALL(8); break;                                                             \
     default: VJ_CHECK(false, VJ_ERR_UNSUPPORTED, "row width of the group order");     \
     }
+// slices of the centre words so that a launch of nb row workgroups has
+// about 2,048 workgroups (few rows: an insertion batch)
+inline int centre_slices(int64_t nb, int W) {
+    return (int)std::min<int64_t>(W, std::max<int64_t>(1, (2048 + nb - 1) / nb));
+}
 void assign_groups(const float *vec, int dp, int64_t n, const float *cen, int P, int32_t *assign,
                    float *rad, hipStream_t s) {
     VJ_CHECK(dp % 32 == 0 && dp <= 256, VJ_ERR_UNSUPPORTED, "row width of the group order");
-#define VJ_CALL(c)                                                                              \
-    hipLaunchKernelGGL(k_assign_pivot<c>, dim3(g1b(n, 64)), dim3(256), 0, s, vec, n, cen, P, \
-                       assign, rad)
+    const int64_t nb = g1b(n, 64);
+    const int W = (P + 31) / 32, cs = centre_slices(nb, W), wps = (W + cs - 1) / cs;
+    const int ny = (W + wps - 1) / wps;
+    DevBuf best;
+    if (ny > 1) {
+        best.alloc((size_t)n * sizeof(unsigned long long));
+        VJ_HIP(hipMemsetAsync(best.p, 0xff, best.bytes, s));
+    }
+    unsigned long long *bp = ny > 1 ? best.as<unsigned long long>() : nullptr;
+#define VJ_CALL(c)                                                                                 \
+    hipLaunchKernelGGL(k_assign_pivot<c>, dim3((unsigned)nb, (unsigned)ny), dim3(256), 0, s, vec, n, \
+                       cen, P, wps, assign, rad, bp)
     VJ_NCHL_SWITCH(dp, VJ_CALL)
 #undef VJ_CALL
+    if (ny > 1) {
+        hipLaunchKernelGGL(k_assign_finish, dim3(g1b(n, 256)), dim3(256), 0, s, bp, n, assign, rad);
+        VJ_HIP(hipStreamSynchronize(s));  // best is freed on return
+    }
 }
 void visit_groups(const float *vec, int dp, const int32_t *rowperm, int64_t M, int rows,
                   const int32_t *rkeys, const float *cen, const float *rad, const int32_t *gt_s,
                   const int32_t *gt_e, int P, const float *tau, const float *n2, float ea,
                   float eb, float maxn, uint32_t *need, int32_t *nneed, hipStream_t s) {
     const int64_t nb = (M + rows - 1) / rows;
-#define VJ_CALL(c)                                                                              \
-    hipLaunchKernelGGL(k_visit_groups<c>, dim3((unsigned)nb), dim3(256), 0, s, vec, rowperm, M, \
-                       rows, rkeys, cen, rad, gt_s, gt_e, P, tau, n2, ea, eb, maxn, need, nneed)
+    const int W = (P + 31) / 32, cs = centre_slices(nb, W), wps = (W + cs - 1) / cs;
+    const int ny = (W + wps - 1) / wps;
+    fill_i32(nneed, nb, 0, s);
+#define VJ_CALL(c)                                                                                 \
+    hipLaunchKernelGGL(k_visit_groups<c>, dim3((unsigned)nb, (unsigned)ny), dim3(256), 0, s, vec,   \
+                       rowperm, M, rows, rkeys, cen, rad, gt_s, gt_e, P, wps, tau, n2, ea, eb, maxn, \
+                       need, nneed)
     VJ_NCHL_SWITCH(dp, VJ_CALL)
 #undef VJ_CALL
 }
@@ -1397,7 +1455,7 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
             VJ_HIP(hipMemcpyAsync(pids.p, ph.data(), (size_t)P * sizeof(int32_t),
                                   hipMemcpyHostToDevice, s));
             gather_rows_f32(vec, dp, pids.as<int32_t>(), P, ix.piv_rows.as<float>(), s);
-            for (int l = 0; l < kLloyd; ++l) {
+            for (int l = 0; l < lloyd_steps(N); ++l) {
                 assign_groups(vec, dp, N, ix.piv_rows.as<float>(), P, ix.piv_of.as<int32_t>(),
                               nullptr, s);
                 group_sort();
@@ -1477,7 +1535,7 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
         // when logging; no launch runs for minutes on the largest builds)
         auto sweep = [&](const DevBuf &roff, const DevBuf &rtile, const DevBuf &rpos,
                          const DevBuf &vt, int splits, int32_t split_base, const float *tau_in,
-                         const int32_t *cnt_in) {
+                         const int32_t *cnt_in, const int32_t *order) {
             for (int64_t b0 = 0; b0 < nb; b0 += kKnnChunk) {
                 const int64_t nbc = std::min<int64_t>(kKnnChunk, nb - b0);
                 hipLaunchKernelGGL((k_knn_reg<NSPLIT, KP>), dim3((unsigned)nbc, (unsigned)splits),
@@ -1488,7 +1546,7 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
                                    bid_of.as<int32_t>(), roff.as<int64_t>(), rtile.as<int32_t>(),
                                    rpos.as<int32_t>(), vt.as<int32_t>(), split_base, tau_in,
                                    cnt_in, K, bkey.as<float>(), bidb.as<int32_t>(), (int32_t)rb,
-                                   (int32_t)b0);
+                                   (int32_t)b0, order);
                 if (nb > kKnnChunk)
                     build_log(s, "kNN sweep: row blocks %lld of %lld", (long long)(b0 + nbc),
                               (long long)nb);
@@ -1501,13 +1559,18 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
             while (nb * sp < 1024 && mean / (sp * 2) >= 8 && sp < 256) sp *= 2;
             return sp;
         };
+        int64_t vmax = 0;  // the most tiles of one block in the last pass counted
         auto total = [&](const DevBuf &vt) {
             std::vector<int32_t> h((size_t)nb);
             VJ_HIP(hipMemcpyAsync(h.data(), vt.p, (size_t)nb * sizeof(int32_t),
                                   hipMemcpyDeviceToHost, s));
             VJ_HIP(hipStreamSynchronize(s));
             int64_t v = 0;
-            for (int32_t x : h) v += x;
+            vmax = 0;
+            for (int32_t x : h) {
+                v += x;
+                vmax = std::max<int64_t>(vmax, x);
+            }
             return v;
         };
         // lists 0 .. S-1 of every row into list 0 (sorted), in rounds
@@ -1530,7 +1593,7 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
         const int s1 = nsplits(v1);
         bkey.alloc((size_t)s1 * M * kKnnCap * sizeof(float));
         bidb.alloc((size_t)s1 * M * kKnnCap * sizeof(int32_t));
-        sweep(roff1, rtile1, rpos1, vt1, s1, 0, nullptr, nullptr);
+        sweep(roff1, rtile1, rpos1, vt1, s1, 0, nullptr, nullptr, nullptr);
         merge_lists(s1);
         // 5. thresholds, then the groups each block still needs
         DevBuf tau((size_t)M * sizeof(float)), cnt((size_t)M * sizeof(int32_t));
@@ -1557,8 +1620,10 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
                            W, gt_s.as<int32_t>(), gt_e.as<int32_t>(), roff2.as<int64_t>(),
                            rtile2.as<int32_t>(), rpos2.as<int32_t>(), vt2.as<int32_t>());
         const int64_t v2 = total(vt2);
-        build_log(s, "kNN sweep: first pass %lld tiles, second pass %lld of %lld (%.3f)",
-                  (long long)v1, (long long)v2, (long long)(nb * T), (double)v2 / (double)(nb * T));
+        build_log(s, "kNN sweep: first pass %lld tiles, second pass %lld of %lld (%.3f; %lld blocks, "
+                  "at most %lld of %lld tiles in one)", (long long)v1, (long long)v2,
+                  (long long)(nb * T), (double)v2 / (double)(nb * T), (long long)nb,
+                  (long long)vmax, (long long)T);
         // 6. second pass: with one split the lists go on in list 0 (from
         //    their counts and thresholds); with more, the splits start empty
         //    lists 1 .. s2 from the thresholds (a true top-K entry is at or
@@ -1567,7 +1632,21 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
         if (v2 > 0) {
             const int s2 = nsplits(v2);
             if (s2 == 1) {
-                sweep(roff2, rtile2, rpos2, vt2, 1, 0, tau.as<float>(), cnt.as<int32_t>());
+                // the blocks by falling tile count: a block whose rows got no
+                // threshold from their own groups sweeps nearly every tile,
+                // and runs beside the others instead of after them
+                DevBuf keys((size_t)nb * sizeof(int32_t)), keys2((size_t)nb * sizeof(int32_t)),
+                    iota2((size_t)nb * sizeof(int32_t)), order((size_t)nb * sizeof(int32_t));
+                int bits = 1;
+                while (((int64_t)1 << bits) <= vmax) ++bits;
+                hipLaunchKernelGGL(k_desc_keys, dim3(g1b(nb, 256)), dim3(256), 0, s,
+                                   vt2.as<int32_t>(), (int32_t)vmax, nb, keys.as<int32_t>());
+                iota_i32(iota2.as<int32_t>(), nb, s);
+                sort_pairs_i32(keys.as<int32_t>(), keys2.as<int32_t>(), iota2.as<int32_t>(),
+                               order.as<int32_t>(), nb, bits, tmp, s);
+                sweep(roff2, rtile2, rpos2, vt2, 1, 0, tau.as<float>(), cnt.as<int32_t>(),
+                      order.as<int32_t>());
+                VJ_HIP(hipStreamSynchronize(s));  // the order buffers are freed at the block's end
             } else {
                 if ((size_t)(1 + s2) > (size_t)s1) {
                     // room for 1 + s2 lists, list 0 kept
@@ -1580,7 +1659,7 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
                     bkey = std::move(k2);
                     bidb = std::move(i2);
                 }
-                sweep(roff2, rtile2, rpos2, vt2, s2, 1, tau.as<float>(), nullptr);
+                sweep(roff2, rtile2, rpos2, vt2, s2, 1, tau.as<float>(), nullptr, nullptr);
                 merge_lists(1 + s2);
             }
         }
