@@ -149,7 +149,7 @@ void vj_default_join_params(vj_join_params *p);
  * Limits: 1 <= d <= 1024, nq + nx < 2^30, 1 <= R <= 64 (VJ_ERR_UNSUPPORTED).
  * With the environment variable VJ_LOG set, the build (and an insertion's
  * kNN sweep) prints its progress on stderr, synchronising the stream at each
- * step; builds over millions of nodes take minutes.
+ * step; builds over millions of nodes take tens of seconds.
  */
 vj_status vj_build_merged_index(const float *Q, int64_t nq, const float *X, int64_t nx,
                                 int32_t d, vj_metric metric, const vj_build_params *p,
