@@ -254,6 +254,21 @@ vj_status vj_index_export_graph(const vj_index *idx, int32_t *adj, float *elen,
 vj_status vj_index_info(const vj_index *idx, int64_t *nq, int64_t *nx, int32_t *d,
                         int32_t *R, int32_t *entry, int32_t *metric);
 
+/*
+ * Work counters of the index's last build or insertion (any pointer may be
+ * NULL).  The kNN sweep (Section 4.3's graph, built here by exact kNN on
+ * MFMA tiles) groups the nodes around centres and sweeps, per block of rows,
+ * first the tiles of the block's own groups, then only the groups a
+ * triangle-inequality bound cannot rule out; tiles_first and tiles_second
+ * count those (row blocks x column tiles), tiles_all what a sweep of all
+ * pairs would take (all three 0 where the sweep for rows wider than 256
+ * floats ran).  repairs: connectivity-repair edges; repairs_listed: repair
+ * steps answered from the unreachable node's own kNN list, without a scan
+ * of all nodes.  Host pointers.
+ */
+vj_status vj_index_build_stats(const vj_index *idx, int64_t *tiles_first, int64_t *tiles_second,
+                               int64_t *tiles_all, int64_t *repairs, int64_t *repairs_listed);
+
 void vj_index_free(vj_index *idx);
 
 /*

@@ -1620,6 +1620,9 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
                            W, gt_s.as<int32_t>(), gt_e.as<int32_t>(), roff2.as<int64_t>(),
                            rtile2.as<int32_t>(), rpos2.as<int32_t>(), vt2.as<int32_t>());
         const int64_t v2 = total(vt2);
+        ix.knn_tiles[0] = v1;
+        ix.knn_tiles[1] = v2;
+        ix.knn_tiles[2] = nb * T;
         build_log(s, "kNN sweep: first pass %lld tiles, second pass %lld of %lld (%.3f; %lld blocks, "
                   "at most %lld of %lld tiles in one)", (long long)v1, (long long)v2,
                   (long long)(nb * T), (double)v2 / (double)(nb * T), (long long)nb,
@@ -1709,6 +1712,7 @@ bool knn_candidates(Index &ix, int64_t rb, int64_t M, int K, DevBuf &bidb, float
         VJ_HIP(hipStreamSynchronize(s));
         return true;
     }
+    ix.knn_tiles[0] = ix.knn_tiles[1] = ix.knn_tiles[2] = 0;
     bkey.alloc((size_t)M * kKnnCap * sizeof(float));
     bidb.alloc((size_t)M * kKnnCap * sizeof(int32_t));
     if (nsplit == 3)
@@ -1774,6 +1778,7 @@ void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched
     bfs_from(ix.entry, true);
     const int64_t max_iter = std::min<int64_t>(N, 200000);
     int64_t ncert = 0;  // steps answered from the lists
+    ix.last_repairs = 0;
     // while edges are only added, reachability only grows and the smallest
     // unseen node only moves up: each scan starts after the last one
     int64_t from = 0;
@@ -1799,6 +1804,7 @@ void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched
         hipLaunchKernelGGL(k_attach, dim3(1), dim3(64), 0, s, vec, dp, ix.adj.as<int32_t>(), R, p,
                            first);
         ix.repairs += 1;
+        ix.last_repairs = iter + 1;
         if ((iter + 1) % 1024 == 0) build_log(s, "connectivity repair: %lld edges", (long long)(iter + 1));
         if (touched) touched->push_back(p);
         // a new edge only adds reachability; an overwritten edge may remove some
@@ -1811,6 +1817,7 @@ void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched
         }
     }
     build_log(s, "connectivity repair: %lld steps answered from the kNN lists", (long long)ncert);
+    ix.last_listed = ncert;
 }
 
 }  // namespace

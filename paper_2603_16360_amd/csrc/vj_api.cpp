@@ -1516,6 +1516,9 @@ vj_status vj_index_insert_queries(vj_index *idx, const float *Q, int64_t n, int3
     ix.nq = b.nq;
     ix.N = N;
     ix.repairs += b.repairs;
+    for (int k = 0; k < 3; ++k) ix.knn_tiles[k] = b.knn_tiles[k];
+    ix.last_repairs = b.last_repairs;
+    ix.last_listed = b.last_listed;
     const bool had_bf16 = ix.vec_bf16.p != nullptr, had_f8 = ix.vec_f8.p != nullptr;
     ix.vec_bf16.release();
     ix.vec_f8.release();
@@ -1590,6 +1593,19 @@ vj_status vj_index_info(const vj_index *idx, int64_t *nq, int64_t *nx, int32_t *
     if (R) *R = ix.R;
     if (entry) *entry = ix.entry;
     if (metric) *metric = ix.metric;
+    API_END
+}
+
+vj_status vj_index_build_stats(const vj_index *idx, int64_t *tiles_first, int64_t *tiles_second,
+                               int64_t *tiles_all, int64_t *repairs, int64_t *repairs_listed) {
+    API_BEGIN
+    VJ_CHECK(idx != nullptr, VJ_ERR_INVALID_ARG, "null index");
+    const Index &ix = idx->impl;
+    if (tiles_first) *tiles_first = ix.knn_tiles[0];
+    if (tiles_second) *tiles_second = ix.knn_tiles[1];
+    if (tiles_all) *tiles_all = ix.knn_tiles[2];
+    if (repairs) *repairs = ix.last_repairs;
+    if (repairs_listed) *repairs_listed = ix.last_listed;
     API_END
 }
 

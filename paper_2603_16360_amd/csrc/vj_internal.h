@@ -185,6 +185,11 @@ struct Index {
     std::vector<int32_t> lay_entry;
     DevBuf lay_adj, lay_pos, lay_ids, lay_offd, lay_seed;
     int64_t repairs = 0;  // connectivity-repair edges added by the build
+    // work of the last build or insertion: the kNN sweep's tiles (first pass,
+    // second pass, all pairs; row blocks x column tiles, 0 on the wide-row
+    // sweep), its repair edges and the steps answered from the kNN lists
+    int64_t knn_tiles[3] = {0, 0, 0};
+    int64_t last_repairs = 0, last_listed = 0;
     // group order of the kNN sweep, kept so that an insertion labels only
     // its new nodes: group centres (fp32 [piv_n][dp]), the nearest centre of
     // nodes [0, piv_cnt) and each group's radius (fp32 [piv_n]: no member of

@@ -74,6 +74,7 @@ _SIGS = {
     "vj_index_export_nnmap": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vj_index_export_graph": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "vj_index_info": (C.c_int, [_vp] + [_vp] * 6),
+    "vj_index_build_stats": (C.c_int, [_vp] + [_vp] * 5),
     "vj_index_free": (None, [_vp]),
     "vj_index_save": (C.c_int, [_vp, C.c_char_p]),
     "vj_index_load": (C.c_int, [C.c_char_p, _vp, _PP]),
@@ -217,6 +218,13 @@ class Index:
                                   C.byref(e), C.byref(m)))
         return {"nq": nq.value, "nx": nx.value, "d": d.value, "R": R.value,
                 "entry": e.value, "metric": m.value}
+
+    def build_stats(self) -> dict:
+        """Work counters of the last build or insertion (vj_index_build_stats)."""
+        v = [C.c_int64() for _ in range(5)]
+        _check(_lib.vj_index_build_stats(self._h, *[C.byref(x) for x in v]))
+        return dict(zip(("tiles_first", "tiles_second", "tiles_all", "repairs",
+                         "repairs_listed"), (x.value for x in v)))
 
     def export_graph(self, with_parent: bool = True):
         """(adj int32 [N, R], elen float32 [N, R], parent int32 [nq] or None

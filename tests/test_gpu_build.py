@@ -62,9 +62,28 @@ def test_build_integer_data_identical():
     info = idx.info()
     assert info["entry"] == g.entry
     same = (adj == g.adj).all(axis=1)
-    print(f"[build] integer rows identical {same.mean():.5f}", flush=True)
+    print(f"[build] integer rows identical {same.mean():.5f}; {idx.build_stats()}", flush=True)
     assert same.all()
     _invariants(w, adj, elen, info["entry"], 32)
+
+
+def test_build_pruned_sweep_identical():
+    # well-separated integer clusters: the kNN sweep's second pass skips most
+    # groups of nodes (the triangle bound rules them out for every row of a
+    # block), and the graph must still be the oracle's, row for row
+    w = workloads.separated_integer_case()
+    idx, adj, elen, parent = _build(w, w.R)
+    st = idx.build_stats()
+    print(f"[build] separated clusters: {st}", flush=True)
+    assert st["tiles_all"] > 0 and st["tiles_first"] > 0
+    assert st["tiles_first"] + st["tiles_second"] < 0.5 * st["tiles_all"]
+    assert 0 <= st["repairs_listed"] <= st["repairs"]
+    g = oracle.build_merged(w.Q, w.X, w.R)
+    assert idx.info()["entry"] == g.entry
+    same = (adj == g.adj).all(axis=1)
+    print(f"[build] separated rows identical {same.mean():.5f}", flush=True)
+    assert same.all()
+    _invariants(w, adj, elen, g.entry, w.R)
 
 
 def test_build_hub_identical():

@@ -110,9 +110,9 @@ def test_insert_edge_cases():
                          ids=["two-passes", "first-pass-covers-all"])
 def test_large_batch_identical_to_oracle(nx, q0, n):
     # one batch large enough that the insertion's kNN sweep splits its first
-    # pass (the tiles of the pivot groups of each block's rows) over several
+    # pass (the tiles of the groups of each block's rows) over several
     # workgroups and merges them before the second pass; with 1,000 nodes or
-    # fewer there is one pivot group and the first pass covers every tile
+    # fewer there is one group and the first pass covers every tile
     w = workloads.width_case(128, nx, q0 + n, True, 77)
     X, Q = w.X, w.Q
     R = 32
@@ -122,6 +122,28 @@ def test_large_batch_identical_to_oracle(nx, q0, n):
                                  torch.from_numpy(g.adj).cuda(), g.entry)
     want = oracle.insert_batch(Q[:q0], X, g.adj, g.entry, Q[q0:])
     idx.insert_queries(torch.from_numpy(Q[q0:]).cuda())
+    a = idx.export_graph()[0].cpu().numpy()
+    bad = np.nonzero((a != want.adj).any(1))[0]
+    assert bad.size == 0, f"{bad.size} rows differ: {bad[:10].tolist()}"
+
+
+def test_insert_pruned_sweep_identical():
+    # well-separated integer clusters: the insertion's sweep (split over
+    # columns, few row blocks) skips most groups in its second pass, and the
+    # grown graph must be the oracle's, row for row
+    w = workloads.separated_integer_case()
+    X, Q, R, q0 = w.X, w.Q, w.R, 200
+    g = oracle.build_merged(Q[:q0], X, R)
+    print(f"[gpu-step] insert: separated clusters, index over {X.shape[0]} + {q0}, "
+          f"one batch of {Q.shape[0] - q0}", flush=True)
+    idx = vj.vj_index_from_graph(torch.from_numpy(Q[:q0]).cuda(), torch.from_numpy(X).cuda(),
+                                 torch.from_numpy(g.adj).cuda(), g.entry)
+    want = oracle.insert_batch(Q[:q0], X, g.adj, g.entry, Q[q0:])
+    idx.insert_queries(torch.from_numpy(Q[q0:]).cuda())
+    st = idx.build_stats()
+    print(f"[insert] separated clusters: {st}", flush=True)
+    assert st["tiles_all"] > 0
+    assert st["tiles_first"] + st["tiles_second"] < 0.5 * st["tiles_all"]
     a = idx.export_graph()[0].cpu().numpy()
     bad = np.nonzero((a != want.adj).any(1))[0]
     assert bad.size == 0, f"{bad.size} rows differ: {bad[:10].tolist()}"

@@ -37,6 +37,7 @@ __all__ = [
     "config_stream",
     "vmf_kappa_for_mean_cosine",
     "hub_chain",
+    "separated_integer_case",
 ]
 
 
@@ -339,6 +340,22 @@ def width_case(d: int, n_x: int, n_q: int, integer: bool, seed: int,
         Q = gaussian_mixture(n_q, means, 1.0, seed + 1)
     return Workload(f"width{d}", Q, X, "l2", 16, 10.0, seed + 3, n_q,
                     {"integer": integer, "value_max": vmax})
+
+
+def separated_integer_case(n_x: int = 12_000, n_q: int = 1_200, d: int = 64, k: int = 24,
+                           sigma: float = 4.0, seed: int = 610) -> Workload:
+    """Well-separated integer clusters (a build edge case: most groups of
+    nodes are far from most others).  k means uniform in [20, 235]^d
+    (seed), points round(mean + sigma N(0, I)) clipped to [0, 255], X with
+    seed + 1, Q with seed + 2, equal cluster weights; L2, R = 16.  Every
+    squared distance is an integer below 2^24."""
+    means = _rng(seed).uniform(20.0, 235.0, size=(k, d))
+    scales = np.full(d, 3.0 * sigma)  # integer_mixture draws (scale / 3) N(0, 1)
+    weights = np.full(k, 1.0 / k)
+    X = integer_mixture(n_x, means, scales, weights, seed + 1, vmax=255)
+    Q = integer_mixture(n_q, means, scales, weights, seed + 2, vmax=255)
+    return Workload("separated", Q, X, "l2", 16, 10.0, seed + 3, n_q,
+                    {"integer": True, "clusters": k, "sigma": sigma})
 
 
 def hub_chain(d: int = 1024, window: int = 60, n_queries: int = 8) -> Workload:
