@@ -86,6 +86,22 @@ def test_build_pruned_sweep_identical():
     _invariants(w, adj, elen, g.entry, w.R)
 
 
+def test_build_pruned_sweep_float():
+    # the same well-separated geometry in float32: the pruning bound then
+    # carries the three-term tile key's error bound; rows may differ from
+    # the fp64 oracle's only where fp32 and fp64 order near-equal distances
+    w = workloads.separated_float_case()
+    idx, adj, elen, parent = _build(w, w.R)
+    st = idx.build_stats()
+    print(f"[build] separated float clusters: {st}", flush=True)
+    assert st["tiles_first"] + st["tiles_second"] < 0.5 * st["tiles_all"]
+    g = oracle.build_merged(w.Q, w.X, w.R)
+    same = (adj == g.adj).all(axis=1)
+    print(f"[build] separated float rows identical {same.mean():.5f}", flush=True)
+    assert same.mean() >= 0.995
+    _invariants(w, adj, elen, idx.info()["entry"], w.R)
+
+
 def test_build_hub_identical():
     # one node with 1,024 reverse-edge candidates whose 768 nearest prune to
     # fewer than R edges: the build must prune the whole list, as the oracle

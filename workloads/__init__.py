@@ -38,6 +38,7 @@ __all__ = [
     "vmf_kappa_for_mean_cosine",
     "hub_chain",
     "separated_integer_case",
+    "separated_float_case",
 ]
 
 
@@ -356,6 +357,18 @@ def separated_integer_case(n_x: int = 12_000, n_q: int = 1_200, d: int = 64, k: 
     Q = integer_mixture(n_q, means, scales, weights, seed + 2, vmax=255)
     return Workload("separated", Q, X, "l2", 16, 10.0, seed + 3, n_q,
                     {"integer": True, "clusters": k, "sigma": sigma})
+
+
+def separated_float_case(n_x: int = 12_000, n_q: int = 1_200, d: int = 64, k: int = 24,
+                         sigma: float = 4.0, seed: int = 620) -> Workload:
+    """The same geometry with float32 values: k means uniform in
+    [20, 235]^d (seed), points mean + sigma N(0, I) (X seed + 1, Q seed + 2,
+    equal weights); L2, R = 16."""
+    means = _rng(seed).uniform(20.0, 235.0, size=(k, d))
+    X = gaussian_mixture(n_x, means, sigma, seed + 1)
+    Q = gaussian_mixture(n_q, means, sigma, seed + 2)
+    return Workload("separated_float", Q, X, "l2", 16, 10.0, seed + 3, n_q,
+                    {"integer": False, "clusters": k, "sigma": sigma})
 
 
 def hub_chain(d: int = 1024, window: int = 60, n_queries: int = 8) -> Workload:
