@@ -193,11 +193,11 @@ k_knn(const uint16_t *Ah, const uint16_t *Al, int64_t N, int Kp, const float *n2
 // A workgroup of 4 waves owns 4 * RT * 16 rows (RT row tiles of 16 per wave)
 // of the call's rows, taken in a given processing order (rowperm), and
 // sweeps the column tiles of its split (blockIdx.y) 32 columns at a time.
-// The columns come as a copy in sweep order (node ids bid_of, +inf norms
-// and id -1 past the last node, whole tiles); a row block starts at its own
-// start tile and wraps around.  When rows and columns are ordered by their
-// nearest pivot node, a block first meets the columns nearest to its rows,
-// so its thresholds tighten in the first tiles and few later columns pass.
+// The columns come as a copy in group order (node ids bid_of; each group
+// padded to whole tiles with id -1 and +inf norms).  A block sweeps the
+// tiles of its runs (run_off / run_tile / run_pos / vtot): in the first
+// pass the tiles of its own groups, so its thresholds tighten early and few
+// later columns pass, in the second only the groups a bound keeps.
 // Column tiles stream through a ring of NB LDS stages filled by direct
 // global-to-LDS loads (global_load_lds_dwordx4), NB - 1 tiles ahead of the
 // tile being multiplied, so the loads' latency hides behind NB - 2 tiles of

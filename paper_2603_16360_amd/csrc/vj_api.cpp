@@ -1494,8 +1494,9 @@ vj_status vj_index_insert_queries(vj_index *idx, const float *Q, int64_t n, int3
     b.elen.alloc((size_t)N * R * sizeof(float));
     VJ_HIP(hipMemcpyAsync(b.elen.p, ix.elen.p, (size_t)n_old * R * sizeof(float),
                           hipMemcpyDeviceToDevice, s));
-    // the kNN sweep's pivot labels of the old nodes go with the graph (on an
-    // error they are dropped, and the next insertion labels every node)
+    // the kNN sweep's group centres, labels of the old nodes and radii go
+    // with the graph (on an error they are dropped, and the next insertion
+    // labels every node)
     b.piv_rows = std::move(ix.piv_rows);
     b.piv_of = std::move(ix.piv_of);
     b.piv_rad = std::move(ix.piv_rad);
