@@ -263,8 +263,9 @@ vj_status vj_index_info(const vj_index *idx, int64_t *nq, int64_t *nx, int32_t *
  * count those (row blocks x column tiles), tiles_all what a sweep of all
  * pairs would take (all three 0 where the sweep for rows wider than 256
  * floats ran).  repairs: connectivity-repair edges; repairs_listed: repair
- * steps answered from the unreachable node's own kNN list, without a scan
- * of all nodes.  Host pointers.
+ * steps answered from the unreachable node's own kNN list (which the index
+ * keeps from its build and insertions), with at most a scan of the nodes
+ * added since that list was made instead of all nodes.  Host pointers.
  */
 vj_status vj_index_build_stats(const vj_index *idx, int64_t *tiles_first, int64_t *tiles_second,
                                int64_t *tiles_all, int64_t *repairs, int64_t *repairs_listed);

@@ -772,8 +772,9 @@ struct RepairCtl {
     int nnext;                     // BFS: size of the next front
     unsigned long long best_any;   // (d2 bits << 32 | id) of the nearest reached node
     unsigned long long best_free;  // the same among nodes with a free slot
-    int certified;                 // best_free came from first's own list (no scan)
+    int certified;                 // best_free is known: no scan
     int pad;
+    int64_t scan_from;             // else the nodes [scan_from, N) to scan
 };
 
 __global__ void k_repair_reset(RepairCtl *c) {
@@ -782,20 +783,26 @@ __global__ void k_repair_reset(RepairCtl *c) {
     c->best_any = ~0ull;
     c->best_free = ~0ull;
     c->certified = 0;
+    c->scan_from = 0;
 }
 
 // the nearest free reached node to w = c->first from w's own sorted list
-// (kc entries by (d2, id), d2 in the scan's arithmetic): every node outside
-// the list is at squared distance >= cert[w] (the kNN sweep's K-th key
-// turned into a distance bound), so a first reached free entry closer than
-// that is the scan's answer.  Rows [rb, rb + n) have lists; one wave.
+// (kc entries by (d2, id), d2 in the scan's arithmetic) among the nodes
+// [0, from[w]) that existed when the list was made: every one of those
+// outside the list is at squared distance >= cert[w] (the kNN sweep's K-th
+// key turned into a distance bound; -inf: w has no list), so a first reached
+// free entry closer than that is the answer among them.  Nodes added since
+// (from[w] < N) are left to a scan of [from[w], N).  Rows [0, n) have
+// lists; one wave.
 __global__ void k_repair_from_list(const int32_t *kid, const float *kd2, int kc, const float *cert,
-                                   int64_t rb, int64_t n, const int *seen, const int32_t *adj,
-                                   int R, RepairCtl *c) {
+                                   const int32_t *from, int64_t n, int64_t N, const int *seen,
+                                   const int32_t *adj, int R, RepairCtl *c) {
     const int32_t w = c->first;
-    if (w == 0x7fffffff || w < rb || w >= rb + n) return;
+    if (w == 0x7fffffff || w >= n) return;
     const int lane = threadIdx.x;
-    const int64_t row = w - rb;
+    const int64_t row = w;
+    const float bound = cert[row];
+    if (!(bound > -INFINITY)) return;
     for (int e0 = 0; e0 < kc; e0 += 64) {
         const int e = e0 + lane;
         const int32_t v = e < kc ? kid[row * kc + e] : -1;
@@ -805,9 +812,10 @@ __global__ void k_repair_from_list(const int32_t *kid, const float *kd2, int kc,
             const int f = __ffsll((unsigned long long)m) - 1;
             if (lane == f) {
                 const float d = kd2[row * kc + e];
-                if (d < cert[row]) {
+                if (d < bound) {
                     c->best_free = ((unsigned long long)__float_as_uint(d) << 32) | (uint32_t)v;
-                    c->certified = 1;
+                    if (from[row] >= N) c->certified = 1;
+                    else c->scan_from = from[row];
                 }
             }
             return;
@@ -853,12 +861,12 @@ __device__ __forceinline__ float sum8(float acc) {
 
 __global__ void __launch_bounds__(256)
 k_nearest_reached(const float *vec, int64_t N, int dp, const int *wp, const int *seen,
-                  const int32_t *adj, int R, const int *skip, unsigned long long *best_any,
-                  unsigned long long *best_free) {
+                  const int32_t *adj, int R, const int *skip, const int64_t *from,
+                  unsigned long long *best_any, unsigned long long *best_free) {
     // 8 lanes per node, 32 nodes per workgroup step, grid-stride over the
-    // nodes; one atomic per workgroup (the minimum of unique (d2, id) keys
-    // does not depend on the order).  w (*wp) INT_MAX or *skip (the answer
-    // is known): nothing to do.
+    // nodes [*from, N); one atomic per workgroup (the minimum of unique
+    // (d2, id) keys does not depend on the order).  w (*wp) INT_MAX or *skip
+    // (the answer is known): nothing to do.
     __shared__ unsigned long long s_a[4], s_f[4];
     const int32_t w = *wp;
     if (w == 0x7fffffff || *skip) return;
@@ -867,7 +875,8 @@ k_nearest_reached(const float *vec, int64_t N, int dp, const int *wp, const int 
     const float4 *b = reinterpret_cast<const float4 *>(vec + (int64_t)w * dp);
     unsigned long long ka = ~0ull, kf = ~0ull;
     const int64_t stride = (int64_t)gridDim.x * 32;
-    for (int64_t base = (int64_t)blockIdx.x * 32; base < N; base += stride) {
+    const int64_t p0 = *from;
+    for (int64_t base = p0 + (int64_t)blockIdx.x * 32; base < N; base += stride) {
         const int64_t p = base + (threadIdx.x >> 6) * 8 + g;
         const bool ok = p < N && seen[p];
         float acc = 0.f;
@@ -1735,10 +1744,10 @@ bool knn_candidates(Index &ix, int64_t rb, int64_t M, int K, DevBuf &bidb, float
 // sorted kNN lists of rows [rb, rb + n) and their distance bounds (see
 // k_repair_from_list); kid null: none
 struct RepairLists {
-    const int32_t *kid = nullptr;
+    const int32_t *kid = nullptr, *from = nullptr;
     const float *kd2 = nullptr, *cert = nullptr;
     int kc = 0;
-    int64_t rb = 0, n = 0;
+    int64_t n = 0;  // rows [0, n)
 };
 
 void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched,
@@ -1777,7 +1786,7 @@ void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched
     };
     bfs_from(ix.entry, true);
     const int64_t max_iter = std::min<int64_t>(N, 200000);
-    int64_t ncert = 0;  // steps answered from the lists
+    int64_t ncert = 0, nrange = 0;  // steps answered from the lists; with a scan of newer nodes
     ix.last_repairs = 0;
     // while edges are only added, reachability only grows and the smallest
     // unseen node only moves up: each scan starts after the last one
@@ -1790,12 +1799,13 @@ void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched
                            &ctl->first);
         if (L.kid)
             hipLaunchKernelGGL(k_repair_from_list, dim3(1), dim3(64), 0, s, L.kid, L.kd2, L.kc,
-                               L.cert, L.rb, L.n, seenp, ix.adj.as<int32_t>(), R, ctl);
+                               L.cert, L.from, L.n, N, seenp, ix.adj.as<int32_t>(), R, ctl);
         hipLaunchKernelGGL(k_nearest_reached, dim3(std::min<unsigned>(g1b(N, 32), 2048)), dim3(256),
                            0, s, vec, N, dp, &ctl->first, seenp, ix.adj.as<int32_t>(), R,
-                           &ctl->certified, &ctl->best_any, &ctl->best_free);
+                           &ctl->certified, &ctl->scan_from, &ctl->best_any, &ctl->best_free);
         readback();
         ncert += h->certified;
+        nrange += h->scan_from > 0;
         const int32_t first = h->first;
         if (first == 0x7fffffff) break;
         const bool has_free = h->best_free != ~0ull;
@@ -1816,8 +1826,9 @@ void repair_connectivity(Index &ix, hipStream_t s, std::vector<int32_t> *touched
             from = 0;
         }
     }
-    build_log(s, "connectivity repair: %lld steps answered from the kNN lists", (long long)ncert);
-    ix.last_listed = ncert;
+    build_log(s, "connectivity repair: %lld steps answered from the kNN lists, %lld from a list "
+              "and the nodes added since", (long long)ncert, (long long)nrange);
+    ix.last_listed = ncert + nrange;
 }
 
 }  // namespace
@@ -1888,13 +1899,26 @@ void build_graph(Index &ix, int kc, hipStream_t s) {
 
     // 5. connectivity repair from the entry (with the sorted lists and their
     //    distance bounds: a step whose answer is certified there skips the scan)
+    //    The lists stay with the index for the repairs of later insertions.
     RepairLists lists;
+    ix.knn_id.release();
+    ix.knn_d2.release();
+    ix.knn_cert.release();
+    ix.knn_from.release();
+    ix.knn_rows = ix.knn_cap = 0;
     if (have_cert) {
-        lists.kid = kid.as<int32_t>();
-        lists.kd2 = kd2.as<float>();
-        lists.cert = cert.as<float>();
+        ix.knn_from.alloc((size_t)N * sizeof(int32_t));
+        fill_i32(ix.knn_from.as<int32_t>(), N, (int32_t)N, s);
+        ix.knn_id = std::move(kid);
+        ix.knn_d2 = std::move(kd2);
+        ix.knn_cert = std::move(cert);
+        ix.knn_kc = kc;
+        ix.knn_rows = ix.knn_cap = N;
+        lists.kid = ix.knn_id.as<int32_t>();
+        lists.from = ix.knn_from.as<int32_t>();
+        lists.kd2 = ix.knn_d2.as<float>();
+        lists.cert = ix.knn_cert.as<float>();
         lists.kc = kc;
-        lists.rb = 0;
         lists.n = N;
     }
     repair_connectivity(ix, s, nullptr, lists);
@@ -1968,14 +1992,52 @@ void insert_graph(Index &ix, int64_t n_old, int kc, hipStream_t s) {
     // 4. connectivity repair from the (unchanged) entry, then the lengths of
     //    every row that changed (the listed rows and the repairs' sources)
     std::vector<int32_t> touched;
+    //    The new rows' lists join those the index kept for its old rows (from
+    //    the build and earlier insertions; an old row without one gets the
+    //    bound -inf), in arrays grown by half when full.
     RepairLists lists;
     if (have_cert) {
-        lists.kid = kid.as<int32_t>();
-        lists.kd2 = kd2.as<float>();
-        lists.cert = cert.as<float>();
+        const bool keep_old = ix.knn_rows == n_old && ix.knn_kc == kc;
+        if (!keep_old || ix.knn_cap < N) {
+            const int64_t cap = keep_old ? std::max<int64_t>(N, ix.knn_cap + ix.knn_cap / 2) : N;
+            DevBuf nid((size_t)cap * kc * sizeof(int32_t)), nd2((size_t)cap * kc * sizeof(float)),
+                ncert((size_t)cap * sizeof(float)), nfrom((size_t)cap * sizeof(int32_t));
+            if (keep_old) {
+                VJ_HIP(hipMemcpyAsync(nid.p, ix.knn_id.p, (size_t)n_old * kc * sizeof(int32_t),
+                                      hipMemcpyDeviceToDevice, s));
+                VJ_HIP(hipMemcpyAsync(nd2.p, ix.knn_d2.p, (size_t)n_old * kc * sizeof(float),
+                                      hipMemcpyDeviceToDevice, s));
+                VJ_HIP(hipMemcpyAsync(ncert.p, ix.knn_cert.p, (size_t)n_old * sizeof(float),
+                                      hipMemcpyDeviceToDevice, s));
+                VJ_HIP(hipMemcpyAsync(nfrom.p, ix.knn_from.p, (size_t)n_old * sizeof(int32_t),
+                                      hipMemcpyDeviceToDevice, s));
+            } else {
+                fill_i32(ncert.as<int32_t>(), n_old, (int32_t)0xff800000u, s);  // -inf
+                fill_i32(nfrom.as<int32_t>(), n_old, 0, s);
+            }
+            ix.knn_id = std::move(nid);
+            ix.knn_d2 = std::move(nd2);
+            ix.knn_cert = std::move(ncert);
+            ix.knn_from = std::move(nfrom);
+            ix.knn_cap = cap;
+            ix.knn_kc = kc;
+        }
+        VJ_HIP(hipMemcpyAsync(ix.knn_id.as<int32_t>() + n_old * kc, kid.p,
+                              (size_t)M * kc * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        VJ_HIP(hipMemcpyAsync(ix.knn_d2.as<float>() + n_old * kc, kd2.p,
+                              (size_t)M * kc * sizeof(float), hipMemcpyDeviceToDevice, s));
+        VJ_HIP(hipMemcpyAsync(ix.knn_cert.as<float>() + n_old, cert.p, (size_t)M * sizeof(float),
+                              hipMemcpyDeviceToDevice, s));
+        fill_i32(ix.knn_from.as<int32_t>() + n_old, M, (int32_t)N, s);
+        ix.knn_rows = N;
+        lists.kid = ix.knn_id.as<int32_t>();
+        lists.from = ix.knn_from.as<int32_t>();
+        lists.kd2 = ix.knn_d2.as<float>();
+        lists.cert = ix.knn_cert.as<float>();
         lists.kc = kc;
-        lists.rb = n_old;
-        lists.n = M;
+        lists.n = N;
+    } else {
+        ix.knn_rows = 0;  // the old rows' lists no longer line up
     }
     repair_connectivity(ix, s, &touched, lists);
     int64_t nrows = L;

@@ -1504,6 +1504,15 @@ vj_status vj_index_insert_queries(vj_index *idx, const float *Q, int64_t n, int3
     b.piv_cnt = ix.piv_cnt;
     ix.piv_n = 0;
     ix.piv_cnt = 0;
+    // so do the kNN lists kept for the repair
+    b.knn_id = std::move(ix.knn_id);
+    b.knn_d2 = std::move(ix.knn_d2);
+    b.knn_cert = std::move(ix.knn_cert);
+    b.knn_from = std::move(ix.knn_from);
+    b.knn_kc = ix.knn_kc;
+    b.knn_rows = ix.knn_rows;
+    b.knn_cap = ix.knn_cap;
+    ix.knn_rows = ix.knn_cap = 0;
     insert_graph(b, n_old, kc, s);
     // swap in, then the derived state
     ix.vec = std::move(b.vec);
@@ -1514,6 +1523,13 @@ vj_status vj_index_insert_queries(vj_index *idx, const float *Q, int64_t n, int3
     ix.piv_rad = std::move(b.piv_rad);
     ix.piv_n = b.piv_n;
     ix.piv_cnt = b.piv_cnt;
+    ix.knn_id = std::move(b.knn_id);
+    ix.knn_d2 = std::move(b.knn_d2);
+    ix.knn_cert = std::move(b.knn_cert);
+    ix.knn_from = std::move(b.knn_from);
+    ix.knn_kc = b.knn_kc;
+    ix.knn_rows = b.knn_rows;
+    ix.knn_cap = b.knn_cap;
     ix.nq = b.nq;
     ix.N = N;
     ix.repairs += b.repairs;

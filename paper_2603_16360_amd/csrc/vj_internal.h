@@ -195,6 +195,15 @@ struct Index {
     // nodes [0, piv_cnt) and each group's radius (fp32 [piv_n]: no member of
     // group g is farther than piv_rad[g] from its centre)
     DevBuf piv_rows, piv_of, piv_rad;
+    // kNN lists kept for the connectivity repair of later insertions (rows
+    // [0, knn_rows), room for knn_cap): node v's knn_kc nearest among the
+    // nodes [0, knn_from[v]) that existed when its list was made (int32
+    // ids, fp32 squared distances in the repair's arithmetic, sorted by
+    // (d2, id)), and knn_cert[v], a squared distance below which no other
+    // of those nodes lies (-inf: no list)
+    DevBuf knn_id, knn_d2, knn_cert, knn_from;
+    int32_t knn_kc = 0;
+    int64_t knn_rows = 0, knn_cap = 0;
     int32_t piv_n = 0;
     int64_t piv_cnt = 0;
     // join state shared by calls on this index (calls on one index must not overlap)

@@ -147,3 +147,36 @@ def test_insert_pruned_sweep_identical():
     a = idx.export_graph()[0].cpu().numpy()
     bad = np.nonzero((a != want.adj).any(1))[0]
     assert bad.size == 0, f"{bad.size} rows differ: {bad[:10].tolist()}"
+
+
+@pytest.mark.parametrize("case", ["mid", "separated"])
+def test_insert_after_gpu_build_identical(case):
+    # an index built on the GPU keeps its kNN lists, so an insertion's repair
+    # can answer an orphaned old node's step from that node's list and a scan
+    # of only the nodes added since; on integer data the GPU build is the
+    # oracle's graph, and the grown graph must stay the oracle's after each
+    # of two batches
+    if case == "mid":
+        w = workloads.config_mid(scale=0.01)  # 10,000 data + 1,000 queries, d=128 integer
+        R, q0, q1 = 32, 600, 800
+    else:
+        w = workloads.separated_integer_case()
+        R, q0, q1 = w.R, 400, 800
+    X, Q = w.X, w.Q
+    print(f"[gpu-step] insert after a GPU build: {case}, index over {X.shape[0]} + {q0}", flush=True)
+    idx = vj.vj_build_merged_index(torch.from_numpy(Q[:q0]).cuda(), torch.from_numpy(X).cuda(),
+                                   metric="l2", R=R)
+    g = oracle.build_merged(Q[:q0], X, R)
+    assert idx.info()["entry"] == g.entry
+    assert (idx.export_graph()[0].cpu().numpy() == g.adj).all()
+    adj = g.adj
+    for lo, hi in ((q0, q1), (q1, Q.shape[0])):
+        want = oracle.insert_batch(Q[:lo], X, adj, g.entry, Q[lo:hi])
+        idx.insert_queries(torch.from_numpy(Q[lo:hi]).cuda())
+        st = idx.build_stats()
+        print(f"[insert] {case} batch {lo}..{hi}: {st}", flush=True)
+        assert 0 <= st["repairs_listed"] <= st["repairs"]
+        a = idx.export_graph()[0].cpu().numpy()
+        bad = np.nonzero((a != want.adj).any(1))[0]
+        assert bad.size == 0, f"{bad.size} rows differ: {bad[:10].tolist()}"
+        adj = want.adj
