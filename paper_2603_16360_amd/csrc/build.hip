@@ -1326,6 +1326,58 @@ k_visit_groups(const float *vec, const int32_t *rowperm, int64_t M, int rows, co
     if (i == 0) atomicAdd(nneed + b, scount[0] + scount[1] + scount[2] + scount[3]);
 }
 
+// squared fp32 distances between all pairs of the P centres (out [P][P])
+__global__ void k_centre_d2(const float *c, int P, int dp, float *out) {
+    const int i = blockIdx.x;
+    const int j = blockIdx.y * blockDim.x + threadIdx.x;
+    if (j >= P) return;
+    const float *a = c + (int64_t)i * dp, *b = c + (int64_t)j * dp;
+    float acc = 0.f;
+    for (int k = 0; k < dp; ++k) {
+        const float t = a[k] - b[k];
+        acc = fmaf(t, t, acc);
+    }
+    out[(int64_t)i * P + j] = acc;
+}
+
+// renumber the P centres along a nearest-neighbour chain: centre 0 first,
+// then always the nearest centre not yet taken (the smaller index on
+// ties).  Groups with nearby numbers then lie near each other, so a block
+// whose few rows come from several consecutive groups (an insertion batch)
+// needs fewer other groups.  The order changes no list, only the work.
+void order_centres(DevBuf &cen, int P, int dp, hipStream_t s) {
+    if (P <= 2) return;
+    DevBuf d2((size_t)P * P * sizeof(float));
+    hipLaunchKernelGGL(k_centre_d2, dim3((unsigned)P, (unsigned)g1b(P, 256)), dim3(256), 0, s,
+                       cen.as<float>(), P, dp, d2.as<float>());
+    std::vector<float> h((size_t)P * P);
+    VJ_HIP(hipMemcpyAsync(h.data(), d2.p, h.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    VJ_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> order((size_t)P);
+    std::vector<char> taken((size_t)P, 0);
+    int cur = 0;
+    taken[0] = 1;
+    order[0] = 0;
+    for (int k = 1; k < P; ++k) {
+        const float *row = h.data() + (size_t)cur * P;
+        int best = -1;
+        float bd = INFINITY;
+        for (int j = 0; j < P; ++j)
+            if (!taken[(size_t)j] && (best < 0 || row[j] < bd)) {
+                best = j;
+                bd = row[j];
+            }
+        taken[(size_t)best] = 1;
+        order[(size_t)k] = best;
+        cur = best;
+    }
+    DevBuf ids((size_t)P * sizeof(int32_t)), out((size_t)P * dp * sizeof(float));
+    VJ_HIP(hipMemcpyAsync(ids.p, order.data(), (size_t)P * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    gather_rows_f32(cen.as<float>(), dp, ids.as<int32_t>(), P, out.as<float>(), s);
+    VJ_HIP(hipStreamSynchronize(s));  // ids and the old rows are freed on return
+    cen = std::move(out);
+}
+
 // the two kernels above for dp = 32 NCHL (dp <= 256, a multiple of 32)
 #define VJ_NCHL_SWITCH(dp, CALL)                                                        \
     switch ((dp) / 32) {                                                                \
@@ -1472,6 +1524,7 @@ bool launch_knn_reg_t(Index &ix, const TileRows &t, const float *vec, int dp, in
                                    perm.as<int32_t>(), gstart.as<int32_t>(), gend.as<int32_t>(),
                                    ix.piv_rows.as<float>());
             }
+            order_centres(ix.piv_rows, P, dp, s);
             VJ_HIP(hipMemsetAsync(ix.piv_rad.p, 0, ix.piv_rad.bytes, s));
             assign_groups(vec, dp, N, ix.piv_rows.as<float>(), P, ix.piv_of.as<int32_t>(),
                           ix.piv_rad.as<float>(), s);

@@ -753,10 +753,11 @@ void drop_cached(BlockCache &c, int dev) {
 }
 }  // namespace
 
-void *dev_alloc(size_t n, int *dev) {
+void *dev_alloc(size_t n, int *dev, size_t *cap) {
     VJ_HIP(hipGetDevice(dev));
     BlockCache &c = block_cache();
     const int d = *dev;
+    *cap = n;
     if (n >= kBlockCacheMin && d >= 0 && d < 64) {
         std::lock_guard<std::mutex> lk(c.mu);
         auto &v = c.blocks[d];
@@ -765,20 +766,26 @@ void *dev_alloc(size_t n, int *dev) {
             if (v[i].n >= n && v[i].n / 2 <= n && (best < 0 || v[i].n < v[best].n)) best = i;
         if (best >= 0) {
             void *p = v[best].p;
+            *cap = v[best].n;
             c.held[d] -= v[best].n;
             v.erase(v.begin() + best);
             return p;
         }
+        // a new block: rounded up to an eighth of the request's power of two
+        size_t g = (size_t)1 << 63;
+        while (g > n) g >>= 1;
+        g >>= 3;
+        *cap = (n + g - 1) / g * g;
     }
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, n);
+    hipError_t e = hipMalloc(&p, *cap);
     if (e == hipErrorOutOfMemory && d >= 0 && d < 64) {
         (void)hipGetLastError();
         {
             std::lock_guard<std::mutex> lk(c.mu);
             drop_cached(c, d);
         }
-        e = hipMalloc(&p, n);
+        e = hipMalloc(&p, *cap);
     }
     VJ_HIP(e);
     return p;

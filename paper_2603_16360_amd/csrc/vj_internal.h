@@ -39,11 +39,15 @@ struct Error {
 // device is synchronised first, as hipFree would) and handed to a later
 // request of between half its size and its size; at most kBlockCacheMax
 // bytes are kept per device, and a failed hipMalloc empties the cache and
-// retries.  Large hipMalloc / hipFree pairs cost up to a second each when
-// a build or an insertion allocates gigabytes of temporaries again and again.
+// retries.  Such blocks are allocated rounded up to an eighth of their
+// power of two (at most 12.5 % more), so that a later request a little
+// larger (an insertion's buffers grow with the index) still finds them.
+// Large hipMalloc / hipFree pairs cost up to a second each when a build or
+// an insertion allocates gigabytes of temporaries again and again.  *cap:
+// the bytes allocated, which dev_free takes.
 constexpr size_t kBlockCacheMin = (size_t)16 << 20;
 constexpr size_t kBlockCacheMax = (size_t)32 << 30;
-void *dev_alloc(size_t n, int *dev);
+void *dev_alloc(size_t n, int *dev, size_t *cap);
 void dev_free(void *p, size_t n, int dev);
 // return every kept block of the current device to the runtime; bytes freed
 size_t trim_block_cache();
@@ -52,23 +56,24 @@ size_t trim_block_cache();
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    size_t cap = 0;   // bytes allocated (>= bytes)
     bool own = true;  // false: a view into another buffer (not freed here)
     int dev = -1;     // device of the block
     DevBuf() = default;
     explicit DevBuf(size_t n) { alloc(n); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), own(o.own), dev(o.dev) {
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), cap(o.cap), own(o.own), dev(o.dev) {
         o.p = nullptr;
-        o.bytes = 0;
+        o.bytes = o.cap = 0;
         o.own = true;
         o.dev = -1;
     }
     DevBuf &operator=(DevBuf &&o) noexcept {
         if (this != &o) {
             release();
-            p = o.p; bytes = o.bytes; own = o.own; dev = o.dev;
-            o.p = nullptr; o.bytes = 0; o.own = true; o.dev = -1;
+            p = o.p; bytes = o.bytes; cap = o.cap; own = o.own; dev = o.dev;
+            o.p = nullptr; o.bytes = o.cap = 0; o.own = true; o.dev = -1;
         }
         return *this;
     }
@@ -83,15 +88,15 @@ struct DevBuf {
     void alloc(size_t n) {
         release();
         if (n == 0) n = 16;
-        p = dev_alloc(n, &dev);
+        p = dev_alloc(n, &dev, &cap);
         bytes = n;
     }
     // grow (contents not kept)
     void reserve(size_t n) { if (n > bytes || !own) alloc(n); }
     void release() {
-        if (p && own) dev_free(p, bytes, dev);
+        if (p && own) dev_free(p, cap, dev);
         p = nullptr;
-        bytes = 0;
+        bytes = cap = 0;
         own = true;
         dev = -1;
     }
