@@ -557,8 +557,9 @@ const char *vj_last_error(void);
  * Device memory kept by the library: a freed temporary of 16 MB or more is
  * not returned to the runtime but kept for a later request of between half
  * its size and its size (the device is synchronised first, as hipFree
- * would), at most 32 GB per device; a failed allocation empties the device's
- * cache and retries.  vj_trim_memory returns every kept block of the current
+ * would), at most 32 GB per device; such blocks are allocated rounded up to
+ * an eighth of their power of two (at most 12.5 % more), and a failed
+ * allocation empties the device's cache and retries.  vj_trim_memory returns every kept block of the current
  * device to the runtime.  bytes_freed (host, may be NULL): the bytes
  * returned.
  */
