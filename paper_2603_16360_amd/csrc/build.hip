@@ -731,13 +731,17 @@ __global__ void k_argmin_id(const double *dist, int64_t N, const unsigned long l
 
 // ------------------------------------------------------ connectivity --
 // one BFS level: every edge of the front; a node seen first here goes to the
-// next front (one counter atomic per wave)
+// next front (one counter atomic per wave).  A plain read skips the nodes
+// already seen (seen only goes from 0 to 1 within a BFS, so a stale 0 only
+// leads to the exchange, which decides), and the exchange claims each new
+// node for exactly one edge.
 __global__ void k_bfs_step(const int32_t *adj, int R, const int32_t *front, int nf, int *seen,
                            int32_t *next, int *nnext) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int32_t v = -1;
     if (t < (int64_t)nf * R) v = adj[(int64_t)front[t / R] * R + t % R];
-    const bool fresh = v >= 0 && atomicExch(&seen[v], 1) == 0;
+    const bool fresh = v >= 0 && __atomic_load_n(&seen[v], __ATOMIC_RELAXED) == 0 &&
+                       atomicExch(&seen[v], 1) == 0;
     const unsigned long long m = __ballot(fresh);
     if (m == 0) return;
     const int lane = threadIdx.x & 63;
